@@ -1,0 +1,87 @@
+"""Planted mistakes in the CPU oracle must be caught by its pins.
+
+Each mutant is a copy of the oracle source with one plausible slip (a
+flipped comparison, a dropped term, a transposed operand, an off-by-one),
+compiled on the CPU. The pin tests of ``test_oracle_pins`` -- excluding the
+cross-check against the second transcription -- run against it, and at least
+one must fail. This shows the pins constrain every step of the oracle.
+"""
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+from oracle import oracle as O
+from tests import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(O.__file__), "jet_oracle.c")
+
+# (name, exact source text, replacement)
+MUTANTS = [
+    ("argmax tie to larger part", "(conn[p] == bestc && p < best)) { best = p; bestc = conn[p]; }\n        }\n        conn_s",
+     "(conn[p] == bestc && p > best)) { best = p; bestc = conn[p]; }\n        }\n        conn_s"),
+    ("filter not strict", "-F[v] < thr", "-F[v] <= thr"),
+    ("filter ratio transposed", "((int64_t)cn * conn[ps]) / cd", "((int64_t)cd * conn[ps]) / cn"),
+    ("ord by smaller gain", "(F[u] > F[v] || (F[u] == F[v] && u < v))", "(F[u] < F[v] || (F[u] == F[v] && u < v))"),
+    ("ord tie by larger id", "(F[u] > F[v] || (F[u] == F[v] && u < v))", "(F[u] > F[v] || (F[u] == F[v] && u > v))"),
+    ("afterburner sign", "else if (q == P[v]) f2 -= g->adjwgt[e];", "else if (q == P[v]) f2 += g->adjwgt[e];"),
+    ("afterburner drops zero gain", "if (f2 >= 0) { move[v] = 1; nM++; }", "if (f2 > 0) { move[v] = 1; nM++; }"),
+    ("afterburner ignores ord", "q = pd[u];\n", ";\n"),
+    ("slot off by one", "return 2 + fl;", "return 1 + fl;"),
+    ("inclusive eviction test", "if (s >= need) break;", "if (s + g->vwgt[L[i].v] >= need) break;"),
+    ("eligibility factor", "3 * ((int64_t)k * w[ps] - W)", "2 * ((int64_t)k * w[ps] - W)"),
+    ("strong loss uses sum", "int64_t mean = cnt ? sum / cnt : 0;", "int64_t mean = sum;"),
+    ("weak loss sign", "loss[v] = conn[ps] - conn[best];", "loss[v] = conn[best] - conn[ps];"),
+    ("cut double counted", "if (u > v && P[u] != P[v]) c += g->adjwgt[e];", "if (P[u] != P[v]) c += g->adjwgt[e];"),
+    ("locks ignored", "if (locked[v]) continue;", ""),
+    ("limit lambda sign", "(1000000 + (__int128)lambda_ppm)", "(1000000 - (__int128)lambda_ppm)"),
+    ("no deadzone", "if (slack < div) return o - 1;\n    return o - slack / div;", "return o;"),
+    ("cookie interval closed", "pos < start[i] + (sigma - w[Blist[i]])", "pos <= start[i] + (sigma - w[Blist[i]])"),
+    ("phi operands transposed", "if (pdn * cut < pn * cut_best) stall = 0;", "if (pn * cut < pdn * cut_best) stall = 0;"),
+    ("balanced best never taken", "bal_best = 1; cut_best = cut; maxw_best = maxw; stall = 0;",
+     "bal_best = 1; cut_best = cut; maxw_best = maxw;"),
+    ("contraction keeps self loops", "if (cu == c) continue;", ""),
+    ("rebalance from B side", "if (!inB[p] || conn[p] <= 0) continue;", "if (conn[p] <= 0) continue;"),
+]
+
+PIN_TESTS = [
+    pins.test_golden_path4_refine,
+    lambda O: pins.test_golden_rebalance(O, "path4_k2_jetrw.json", 2),
+    lambda O: pins.test_golden_rebalance(O, "path6_k3_jetrs.json", 3),
+    pins.test_slot_matches_bit_length,
+    pins.test_gain_destination_against_sparse_product,
+    pins.test_afterburner_equals_gain_under_expected_partition,
+    pins.test_afterburner_independent_set_reduces_to_plain_gain,
+    pins.test_c_filter_floor_boundaries,
+    pins.test_rebalance_rules,
+    pins.test_theorem1_bucket_prefix_loss_bound,
+    pins.test_jetrw_balances_within_k_iterations_unit_weights,
+    pins.test_jetrs_balances_in_one_iteration_unit_weights,
+    pins.test_loop_invariants_and_brute_force,
+    pins.test_stall_counter_follows_algorithm3,
+    pins.test_exhaustive_optimum_bounds_result,
+    pins.test_hem_is_a_matching_and_contraction_preserves_cut,
+]
+
+
+def _caught(libpath):
+    with O.use_library(libpath):
+        for t in PIN_TESTS:
+            try:
+                t(O)
+            except (AssertionError, ValueError):
+                return True
+    return False
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(name, old, new, tmp_path):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation site missing: {name}"
+    mutated = src.replace(old, new, 1)
+    cfile = tmp_path / "mut.c"
+    cfile.write_text(mutated)
+    so = tmp_path / "libmut.so"
+    subprocess.check_call(["gcc", "-O1", "-std=gnu11", "-shared", "-fPIC", "-o", str(so), str(cfile)])
+    assert _caught(str(so)), f"no pin caught the planted mistake: {name}"
