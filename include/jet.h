@@ -1,0 +1,214 @@
+/*
+ * jet.h -- C ABI of the MI355X (gfx950) Jet graph-partition refinement library.
+ *
+ * Implements the refinement pass of Jet (Gilbert, Madduri, Boman,
+ * Rajamanickam, "Jet: Multilevel Graph Partitioning on Graphics Processing
+ * Units"): part connectivity and gain, the Jetlp candidate filter and the
+ * afterburner (Section 4.1, Algorithm 4), synchronous move application with
+ * cut and part-weight updates, the refinement loop with best tracking
+ * (Algorithm 3) and weak / strong rebalancing through loss slots
+ * (Section 4.2, Algorithm 5); and, as the surrounding multilevel scaffold,
+ * heavy-edge matching, contraction (Algorithm 2) and projection
+ * (Algorithm 1).
+ *
+ * Conventions
+ *  - Every pointer inside jet_csr, and `part`, are DEVICE pointers unless a
+ *    comment says (host). The caller owns them; the library never frees them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). All
+ *    device work is enqueued on it; calls return after the stream has
+ *    finished the call's work (they synchronise it).
+ *  - Status codes are returned as int; no exception crosses the ABI. On an
+ *    error detected before any device work, `part` is untouched; after device
+ *    work has started, `part` is unspecified.
+ *  - Graph (Section 2.1): undirected, no self-loops, no parallel edges; each
+ *    edge is stored in both rows. Vertex and edge weights are positive
+ *    integers. Arithmetic is integer only: int32 weights, int64 cuts, gains
+ *    and part weights. Results are deterministic and independent of thread
+ *    scheduling: ties break by part id or vertex id, never by atomic order.
+ *  - Limits: n < 2^31; the total vertex weight and the total edge weight
+ *    (summed over both directions) must be below 2^31 (else JET_EOVERFLOW);
+ *    1 <= k <= 16384.
+ *  - One context per host thread, or external locking.
+ */
+#ifndef JET_H
+#define JET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define JET_OK         0
+#define JET_EINVAL    (-1) /* bad parameter (k < 1, lambda < 0, c_den < 0, NULL pointer, ...) */
+#define JET_EGRAPH    (-2) /* malformed CSR (checked cheaply always, fully with JET_F_VALIDATE) */
+#define JET_EPART     (-3) /* a part id outside [0, k) */
+#define JET_EOVERFLOW (-4) /* total vertex or edge weight >= 2^31 */
+#define JET_ENOMEM    (-5) /* device or host allocation failed */
+#define JET_EHIP      (-6) /* HIP runtime error; jet_last_hip_error() has the code */
+#define JET_EAGAIN    (-7) /* reserved: try again later */
+#define JET_ELIMIT    (-8) /* outside a documented size limit (e.g. k > 16384) */
+
+/* ---- flags ------------------------------------------------------------- */
+#define JET_F_VALIDATE    0x1u  /* full CSR check: range, self-loops, symmetry, duplicates */
+#define JET_F_RETURN_ITER 0x2u  /* return P_iter (state after the last iteration) instead of P_best */
+
+typedef struct jet_context jet_context;
+typedef struct jet_hierarchy jet_hierarchy;
+
+/* Graph in CSR form (Section 2.1). Device pointers. */
+typedef struct {
+    int32_t n;              /* number of vertices */
+    int32_t reserved;
+    int64_t nnz;            /* = xadj[n] = 2m (every edge stored in both rows) */
+    const int64_t *xadj;    /* [n+1], xadj[0] = 0, non-decreasing */
+    const int32_t *adjncy;  /* [nnz], neighbour ids in [0, n) */
+    const int32_t *vwgt;    /* [n] >= 1, or NULL for unit vertex weights */
+    const int32_t *adjwgt;  /* [nnz] >= 1, symmetric, or NULL for unit edge weights */
+} jet_csr;
+
+/* Refinement parameters. Zero-initialise, set k and lambda_ppm, keep the
+ * defaults by leaving the rest 0. */
+typedef struct {
+    int32_t k;                    /* number of parts, >= 1 */
+    int32_t lambda_ppm;           /* imbalance lambda * 1e6 (3% = 30000); balance limit
+                                     o = floor(W (1e6 + lambda_ppm) / (k 1e6)) */
+    int32_t c_num, c_den;         /* first-filter ratio c of eq. gainconn_filter; c_den = 0 ->
+                                     1/4 at level 0 and 3/4 at coarser levels (Section 4.1.2) */
+    int32_t phi_num, phi_den;     /* loop tolerance phi of Algorithm 3; 0 -> 999/1000 */
+    int32_t stall_limit;          /* iterations without a new best before stopping; 0 -> 12 */
+    int32_t weak_rebalance_iters; /* Jetrw iterations before Jetrs (b_max); -1 -> 0, 0 -> 2 */
+    int32_t deadzone_div;         /* sigma rule divisor; 0 -> 10 (see jet_refine) */
+    int32_t level;                /* hierarchy level of the graph (0 = finest): selects the
+                                     default c and seeds the random destination hash */
+    int32_t max_iters;            /* safety cap on iterations, 0 = none */
+    uint32_t flags;               /* JET_F_* */
+    uint64_t seed;                /* seed of every random choice (SplitMix64) */
+} jet_params;
+
+/* Results of a call (host). */
+typedef struct {
+    int64_t cut;             /* cut of the returned partition */
+    int64_t max_part_weight; /* max part weight of the returned partition */
+    int64_t o;               /* balance limit */
+    int64_t sigma;           /* deadzone bound */
+    int64_t total_weight;    /* W */
+    int32_t balanced;        /* returned partition satisfies max part weight <= o */
+    int32_t iters;           /* refinement iterations (summed over levels for jet_partition) */
+    int32_t lp_iters, rw_iters, rs_iters;
+    int32_t levels;          /* hierarchy levels (jet_partition), 1 for jet_refine */
+    float ms_total;          /* device time of the call (hipEvents) */
+    float ms_refine;         /* device time spent in refinement iterations */
+    float ms_coarsen;        /* device time spent coarsening (jet_partition) */
+    float ms_init;           /* device time of per-level set-up (binning, cut, weights) */
+} jet_stats;
+
+/* One record per refinement iteration (written when a trace is passed). */
+typedef struct {
+    int32_t level, t, kind;  /* kind: 1 Jetlp, 2 Jetrw, 3 Jetrs */
+    int32_t nX;              /* Jetlp: |X|; rebalancing: number of eligible vertices */
+    int32_t nM;              /* moves applied */
+    int32_t stall, wcount, balanced;
+    int64_t moved_w;         /* total weight of the moved vertices */
+    int64_t cut, maxw;       /* of P_iter after the iteration */
+    int64_t best_cut;        /* cut of P_best after the iteration */
+    uint64_t digest;         /* sum over v of mix64((v << 32) | P_iter[v]) mod 2^64 */
+} jet_trace_rec;
+
+typedef struct {
+    jet_trace_rec *recs;     /* (host) capacity `cap`; NULL = no trace */
+    int32_t cap;
+    int32_t count;           /* out: records written (<= cap) */
+    int32_t total;           /* out: iterations run (may exceed cap) */
+    int32_t reserved;
+} jet_trace;
+
+/* ---- context ----------------------------------------------------------- */
+/* Creates a context bound to HIP device `device`. It owns the workspace pool
+ * (grown on demand, reused across calls) and small pinned host buffers. */
+int  jet_context_create(jet_context **ctx, int device);
+void jet_context_destroy(jet_context *ctx);
+const char *jet_strerror(int status);
+int  jet_last_hip_error(const jet_context *ctx);
+
+/* ---- refinement (Algorithm 3 with Algorithms 4 and 5) -------------------
+ * Refines `part` (int32[n], device, in: P_0, out: P_best) of graph `g` into
+ * k parts under balance lambda:
+ *   - while balanced (max part weight <= o): a Jetlp iteration. For each
+ *     unlocked v with another adjacent part: P_d = most connected other part
+ *     (ties -> smallest id), F = conn(P_d) - conn(P_s); X = {F >= 0 or
+ *     -F < floor(c conn(P_s))}; afterburner gain F2 over the ord-merged
+ *     neighbourhood; M = {v in X : F2 >= 0}; the vertices of M are locked
+ *     for the next Jetlp (Section 4.1.3).
+ *   - else weak (Jetrw, first b_max iterations after a Jetlp) or strong
+ *     (Jetrs) rebalancing: oversized parts A = {w > o}, valid destinations
+ *     B = {w <= sigma}, sigma = o if slack = o - ceil(W/k) <= 0, o - 1 if
+ *     slack < deadzone_div, else o - floor(slack / deadzone_div); eligible
+ *     vertices 2k vw <= 3(k w(p) - W); loss slot 0 / 1 / 2 + floor(log2);
+ *     per part, evict in (slot, vertex id) order while the weight already
+ *     evicted is below w(p) - o. Jetrw sends each evicted vertex to its best
+ *     connected B part (or B[floor(h * |B| / 2^64)] with
+ *     h = mix64(mix64(seed ^ (level 2^32 + t)) ^ v) when it touches none);
+ *     Jetrs overlays the evicted vertices, in id order, onto B's capacities
+ *     sigma - w(b) in id order.
+ *   - moves are applied simultaneously; the best balanced partition (or,
+ *     while none is balanced, the least oversized) is kept; the loop stops
+ *     after stall_limit iterations without a new best, where a new balanced
+ *     best only restarts the count if cut < phi * best cut.
+ * part_weights_out: optional device int64[k], weights of the returned
+ * partition. stats (host, optional), trace (host, optional).
+ * Errors: JET_EINVAL, JET_EGRAPH, JET_EPART, JET_EOVERFLOW, JET_ELIMIT,
+ * JET_ENOMEM, JET_EHIP. */
+int jet_refine(jet_context *ctx, const jet_csr *g, const jet_params *params, int32_t *part,
+               int64_t *part_weights_out, jet_stats *stats, jet_trace *trace, void *stream);
+
+/* ---- single-step entry points (for step-level checks) --------------------
+ * One Jetlp step (Algorithm 4) against `part` with lock flags `locked`
+ * (device u8[n], nonzero = locked). Outputs (device, [n] each): pd (P_d, or
+ * P_s when v has no other adjacent part or is locked), F (int64, INT64_MIN
+ * when undefined), conn_s (int64, 0 when locked), inX (u8), F2 (int64, 0
+ * outside X), move (u8). */
+int jet_lp_step(jet_context *ctx, const jet_csr *g, const jet_params *params, const int32_t *part,
+                const uint8_t *locked, int32_t *pd, int64_t *F, int64_t *conn_s, uint8_t *inX,
+                int64_t *F2, uint8_t *move, void *stream);
+
+/* One rebalancing step (kind 2 = Jetrw, 3 = Jetrs) at iteration index t.
+ * Outputs (device, [n]): dest (destination or -1), loss (int64, INT64_MIN
+ * when not eligible), slot (int32, -1 when not eligible). */
+int jet_rebalance_step(jet_context *ctx, const jet_csr *g, const jet_params *params,
+                       const int32_t *part, int32_t kind, int32_t t, int32_t *dest, int64_t *loss,
+                       int32_t *slot, void *stream);
+
+/* ---- multilevel scaffold (Algorithms 1 and 2) ---------------------------
+ * jet_coarsen builds the hierarchy G_0 = g, G_1, ... by heavy-edge matching
+ * (rounds of mutual proposals: heaviest edge to an unmatched neighbour, ties
+ * to the smaller mix64(stream(seed, level) ^ (min << 32 | max)), then the
+ * smaller id; at most 16 rounds, stopping when a round matches < 1% of the
+ * vertices) and contraction (coarse ids = matched pairs and singletons
+ * numbered by their smaller member; coarse edge weights summed; no
+ * self-loops). Coarsening stops when n <= 8k, when a level keeps more than
+ * 90% of its vertices, or at 64 levels. The hierarchy lives in device memory
+ * owned by the library until jet_hierarchy_free. Rows of coarse graphs are
+ * not sorted. */
+int jet_coarsen(jet_context *ctx, const jet_csr *g, const jet_params *params, jet_hierarchy **h,
+                void *stream);
+int jet_hierarchy_levels(const jet_hierarchy *h);
+/* view: device CSR of level `level` (level 0 = the input graph); map: device
+ * int32[n_level] mapping level -> level+1 vertex (NULL for the coarsest). */
+int jet_hierarchy_level(const jet_hierarchy *h, int level, jet_csr *view, const int32_t **map);
+void jet_hierarchy_free(jet_hierarchy *h);
+
+/* Full multilevel partition (Algorithm 1): coarsen, seeded uniform random
+ * partition of the coarsest graph P[v] = floor(stream(mix64(seed ^ 1), v) k
+ * / 2^64), refine it, then project and refine every finer level (c = 3/4
+ * above level 0, 1/4 at level 0 unless params sets c). part_out: device
+ * int32[n]. The trace, if given, concatenates the levels' records. */
+int jet_partition(jet_context *ctx, const jet_csr *g, const jet_params *params, int32_t *part_out,
+                  jet_stats *stats, jet_trace *trace, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JET_H */

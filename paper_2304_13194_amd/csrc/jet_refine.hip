@@ -1,0 +1,1633 @@
+// Jet refinement on gfx950: Jetlp with the afterburner (Algorithm 4), weak and
+// strong rebalancing (Algorithm 5 and the strong variant of Section 4.2.2),
+// synchronous move application, and the refinement loop of Algorithm 3 run by
+// a device-side controller.
+//
+// Design (one MI355X):
+//  * Connectivity conn(v, .) is rebuilt per pass in LDS. Vertices are binned
+//    by degree: <= 32 -> 8-lane groups (32 groups per 256-thread block),
+//    <= 1024 -> one wave, larger -> one block. Each group owns a dense int32
+//    table of k entries; neighbours add their edge weight with LDS atomics,
+//    then read-and-clear the entry of their own part with an atomic exchange,
+//    so every adjacent part is seen exactly once and the table is left zero.
+//    Integer sums are exact in any order; argmax ties break by part id, so the
+//    result does not depend on scheduling.
+//  * Per-vertex Jetlp state is one 8-byte record (P_s, P_d + in-X flag, F), so
+//    the afterburner's neighbour gather is a single load.
+//  * Rebalancing orders evictions by (loss slot, vertex id): a per-(part, slot)
+//    weight histogram fixes the cut-off slot of every oversized part; inside
+//    that slot, vertex-ordered prefix sums per part come from per-tile sums,
+//    a per-part scan over tiles, and a wave-level ballot/scan inside each tile.
+//  * A single-block controller kernel decides each iteration's kind from
+//    device state; every other kernel exits at once when its kind is not
+//    selected, so iterations are enqueued in chunks with one host sync each.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "jet_device.h"
+#include "jet_internal.h"
+
+namespace jet {
+
+// ------------------------------------------------------------------ set-up --
+
+// Copies P_0, clears per-vertex state, sums vertex and part weights, counts
+// degree classes and checks part ids / vertex weights / xadj monotonicity.
+__global__ __launch_bounds__(BLOCK) void k_init_vertices(KArgs a, const int32_t *part_in)
+{
+    extern __shared__ int32_t s_w[];  // [k] block-partial part weights
+    __shared__ int64_t s_red[BLOCK / 64];
+    __shared__ uint64_t s_redu[BLOCK / 64];
+    __shared__ int32_t s_cls[NCLS];
+    for (int p = threadIdx.x; p < a.k; p += BLOCK) s_w[p] = 0;
+    if (threadIdx.x < NCLS) s_cls[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t wsum = 0;
+    uint64_t dig = 0;
+    int bad_part = 0, bad_graph = 0;
+    const int stride = gridDim.x * BLOCK;
+    for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += stride) {
+        int p = part_in[v];
+        if (p < 0 || p >= a.k) { bad_part = 1; p = 0; }
+        a.P[v] = p;
+        a.dest[v] = -1;
+        a.lock[v] = -1;
+        int vwv = a.vw ? a.vw[v] : 1;
+        if (vwv < 1) bad_graph = 1;
+        int64_t d = a.xadj[v + 1] - a.xadj[v];
+        if (d < 0) { bad_graph = 1; d = 0; }
+        int c = d == 0 ? CLS_Z : (d <= S_MAXDEG ? CLS_S : (d <= M_MAXDEG ? CLS_M : CLS_L));
+        atomicAdd(&s_cls[c], 1);
+        atomicAdd(&s_w[p], vwv);
+        wsum += vwv;
+        dig += mix64(((uint64_t)(uint32_t)v << 32) | (uint32_t)p);
+    }
+    wsum = block_sum<BLOCK>(wsum, s_red);
+    dig = block_sum<BLOCK>(dig, s_redu);
+    if (bad_part) a.ctl->bad_part = 1;
+    if (bad_graph) a.ctl->bad_graph = 1;
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long *)&a.ctl->wsum, (unsigned long long)wsum);
+        atomicAdd((unsigned long long *)&a.ctl->digest, (unsigned long long)dig);
+    }
+    if (threadIdx.x < NCLS && s_cls[threadIdx.x]) atomicAdd(&a.ctl->bincnt[threadIdx.x], s_cls[threadIdx.x]);
+    for (int p = threadIdx.x; p < a.k; p += BLOCK)
+        if (s_w[p]) atomicAdd((unsigned long long *)&a.w[p], (unsigned long long)(int64_t)s_w[p]);
+}
+
+// Edge pass: cut of P_0, total edge weight, neighbour-range / self-loop /
+// weight checks. Each thread walks a run of 16 consecutive CSR entries.
+__global__ __launch_bounds__(BLOCK) void k_init_edges(KArgs a, int64_t nnz)
+{
+    __shared__ int64_t s_red[BLOCK / 64];
+    constexpr int RUN = 16;
+    int64_t cut = 0, ews = 0;
+    int bad = 0;
+    const int64_t nruns = (nnz + RUN - 1) / RUN;
+    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < nruns; r += (int64_t)gridDim.x * BLOCK) {
+        int64_t e0 = r * RUN, e1 = e0 + RUN < nnz ? e0 + RUN : nnz;
+        // row containing e0: last v with xadj[v] <= e0
+        int lo = 0, hi = a.n;  // invariant xadj[lo] <= e0 < xadj[hi] (xadj[n] = nnz > e0)
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (a.xadj[mid] <= e0) lo = mid; else hi = mid;
+        }
+        int v = lo;
+        int64_t vend = a.xadj[v + 1];
+        int pv = a.P[v];
+        for (int64_t e = e0; e < e1; e++) {
+            while (e >= vend && v < a.n - 1) { v++; vend = a.xadj[v + 1]; pv = a.P[v]; }
+            int u = a.adj[e];
+            int wt = a.ew ? a.ew[e] : 1;
+            if (u < 0 || u >= a.n || u == v || wt < 1) { bad = 1; continue; }
+            ews += wt;
+            if (u > v && a.P[u] != pv) cut += wt;
+        }
+    }
+    cut = block_sum<BLOCK>(cut, s_red);
+    ews = block_sum<BLOCK>(ews, s_red);
+    if (bad) a.ctl->bad_graph = 1;
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long *)&a.ctl->cut, (unsigned long long)cut);
+        atomicAdd((unsigned long long *)&a.ctl->ewsum, (unsigned long long)ews);
+    }
+}
+
+// Fill the degree-class vertex lists.
+__global__ __launch_bounds__(BLOCK) void k_fill_bins(KArgs a, int32_t *bins, int32_t *fill)
+{
+    const int stride = gridDim.x * BLOCK;
+    const int nloop = (a.n + stride - 1) / stride;
+    for (int it = 0; it < nloop; it++) {
+        int v = it * stride + blockIdx.x * BLOCK + threadIdx.x;
+        bool ok = v < a.n;
+        int c = -1;
+        if (ok) {
+            int64_t d = a.xadj[v + 1] - a.xadj[v];
+            c = d == 0 ? CLS_Z : (d <= S_MAXDEG ? CLS_S : (d <= M_MAXDEG ? CLS_M : CLS_L));
+        }
+#pragma unroll
+        for (int cc = 0; cc < NCLS; cc++) wave_append(c == cc, &fill[cc], bins + a.binoff[cc], v);
+    }
+}
+
+// Derived loop state after the set-up passes.
+__global__ __launch_bounds__(BLOCK) void k_ctl_setup(KArgs a, int64_t W, int64_t o, int64_t sigma)
+{
+    __shared__ uint64_t s_red[BLOCK / 64];
+    Ctl *c = a.ctl;
+    uint64_t m = 0;
+    for (int p = threadIdx.x; p < a.k; p += BLOCK) {
+        uint64_t x = (uint64_t)a.w[p];
+        m = x > m ? x : m;
+        a.wbest[p] = a.w[p];
+    }
+    m = block_max_u64<BLOCK>(m, s_red);
+    if (threadIdx.x == 0) {
+        c->W = W; c->o = o; c->sigma = sigma;
+        c->maxw = (int64_t)m;
+        c->balanced = (int64_t)m <= o;
+        c->bal_best = c->balanced;
+        c->cut_best = c->cut;
+        c->maxw_best = c->maxw;
+    }
+}
+
+// -------------------------------------------------------------- controller --
+
+// Oversized parts A = {w > o}, valid destinations B = {w <= sigma} listed in
+// ascending id, and a cleared (part, slot) histogram. Whole block calls.
+__device__ void rb_prepare(const KArgs &a)
+{
+    __shared__ int32_t s_scan[BLOCK / 64];
+    Ctl *c = a.ctl;
+    const int64_t o = c->o, sigma = c->sigma;
+    int32_t carry = 0, nA = 0;
+    for (int base = 0; base < a.k; base += BLOCK) {
+        int p = base + threadIdx.x;
+        int inA = 0, inB = 0;
+        if (p < a.k) {
+            int64_t wp = a.w[p];
+            inA = wp > o;
+            inB = wp <= sigma;
+            a.isA[p] = (uint8_t)inA;
+            a.isB[p] = (uint8_t)inB;
+        }
+        int32_t tot;
+        int32_t pos = block_excl_scan<BLOCK>((int32_t)inB, s_scan, tot);
+        if (inB) a.Blist[carry + pos] = p;
+        carry += tot;
+        int32_t ta;
+        block_excl_scan<BLOCK>((int32_t)inA, s_scan, ta);
+        nA += ta;
+    }
+    for (int i = threadIdx.x; i < a.k * NSLOT; i += BLOCK) a.hist[i] = 0;
+    if (threadIdx.x == 0) { c->nB = carry; c->nA = nA; }
+}
+
+__device__ __forceinline__ void clear_accumulators(Ctl *c)
+{
+    c->ncand = 0;
+    for (int i = 0; i < NCLS; i++) { c->xcnt[i] = 0; c->mcnt[i] = 0; }
+    c->dcut = 0; c->moved_w = 0; c->ddigest = 0;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_ctl_begin(KArgs a)
+{
+    __shared__ int s_kind;
+    Ctl *c = a.ctl;
+    if (threadIdx.x == 0) {
+        int kind;
+        if (c->done || c->stall >= c->stall_limit || (c->max_iters > 0 && c->t >= c->max_iters)) {
+            c->done = 1;
+            kind = KIND_DONE;
+        } else {
+            c->stall++;
+            if (c->balanced) { kind = KIND_LP; c->lp_id++; c->wcount = 0; c->n_lp++; }
+            else if (c->wcount < c->bmax) { kind = KIND_RW; c->wcount++; c->n_rw++; }
+            else { kind = KIND_RS; c->wcount++; c->n_rs++; }
+        }
+        c->kind = kind;
+        clear_accumulators(c);
+        s_kind = kind;
+    }
+    __syncthreads();
+    const int kind = s_kind;
+    if (kind == KIND_RW || kind == KIND_RS) rb_prepare(a);
+}
+
+// Single-step entry points: force one iteration of `kind` at index t. For
+// Jetlp, lock flags become stamps of the previous Jetlp (id 0).
+__global__ __launch_bounds__(BLOCK) void k_force_step(KArgs a, int kind, int t, const uint8_t *locked)
+{
+    Ctl *c = a.ctl;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c->kind = kind;
+        c->t = t;
+        c->lp_id = 1;
+        clear_accumulators(c);
+    }
+    if (locked)
+        for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) a.lock[v] = locked[v] ? 0 : -1;
+    if (blockIdx.x == 0) {
+        __syncthreads();
+        if (kind == KIND_RW || kind == KIND_RS) rb_prepare(a);
+    }
+}
+
+// Defaults of the step outputs for vertices no row kernel visits (isolated).
+__global__ __launch_bounds__(BLOCK) void k_step_defaults(KArgs a, const int32_t *part)
+{
+    for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) {
+        if (a.dbg_F) { a.dbg_F[v] = INT64_MIN; a.dbg_cs[v] = 0; a.dbg_F2[v] = 0; a.dbg_pd[v] = part[v]; }
+        if (a.dbg_loss) { a.dbg_loss[v] = INT64_MIN; a.dbg_slot[v] = -1; }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_lp_outputs(KArgs a, uint8_t *inX, uint8_t *move)
+{
+    for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) {
+        const bool iso = a.xadj[v + 1] == a.xadj[v];
+        inX[v] = iso ? 0 : (uint8_t)((a.rec[v].x & 0xFFFF) != 0);
+        move[v] = a.dest[v] >= 0;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_ctl_end(KArgs a)
+{
+    __shared__ uint64_t s_red[BLOCK / 64];
+    __shared__ int s_improved;
+    Ctl *c = a.ctl;
+    if (c->kind == KIND_DONE) return;
+    uint64_t m = 0;
+    for (int p = threadIdx.x; p < a.k; p += BLOCK) {
+        uint64_t x = (uint64_t)a.w[p];
+        m = x > m ? x : m;
+    }
+    m = block_max_u64<BLOCK>(m, s_red);
+    if (threadIdx.x == 0) {
+        const int64_t maxw = (int64_t)m;
+        int nM = 0, nXl = 0;
+        for (int i = 0; i < NCLS; i++) { nM += c->mcnt[i]; nXl += c->xcnt[i]; }
+        c->cut += c->dcut;
+        c->digest += c->ddigest;
+        c->maxw = maxw;
+        const int bal = maxw <= c->o;
+        c->balanced = bal;
+        int improved = 0;
+        if (bal) {
+            if (!c->bal_best) {
+                // a balanced partition always replaces an imbalanced best
+                improved = 1; c->bal_best = 1; c->cut_best = c->cut; c->maxw_best = maxw; c->stall = 0;
+            } else if (c->cut < c->cut_best) {
+                // only a gain beyond the tolerance phi restarts the count
+                if ((int64_t)c->phi_den * c->cut < (int64_t)c->phi_num * c->cut_best) c->stall = 0;
+                improved = 1; c->cut_best = c->cut; c->maxw_best = maxw;
+            }
+        } else if (!c->bal_best && maxw < c->maxw_best) {
+            improved = 1; c->maxw_best = maxw; c->cut_best = c->cut; c->stall = 0;
+        }
+        c->copy_best = improved;
+        if (a.trace && c->t < c->trace_cap) {
+            jet_trace_rec r;
+            r.level = c->level; r.t = c->t; r.kind = c->kind;
+            r.nX = c->kind == KIND_LP ? nXl : c->ncand;
+            r.nM = nM; r.stall = c->stall; r.wcount = c->wcount; r.balanced = bal;
+            r.moved_w = c->moved_w; r.cut = c->cut; r.maxw = maxw; r.best_cut = c->cut_best;
+            r.digest = c->digest;
+            a.trace[c->t] = r;
+        }
+        c->t++;
+        s_improved = improved;
+    }
+    __syncthreads();
+    if (s_improved)
+        for (int p = threadIdx.x; p < a.k; p += BLOCK) a.wbest[p] = a.w[p];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_copy_best(KArgs a)
+{
+    if (!a.ctl->copy_best) return;
+    const int stride = gridDim.x * BLOCK;
+    if ((((uintptr_t)a.best | (uintptr_t)a.P) & 15) == 0) {
+        const int n4 = a.n >> 2;
+        const int4 *src = (const int4 *)a.P;
+        int4 *dst = (int4 *)a.best;
+        for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n4; i += stride) dst[i] = src[i];
+        for (int v = (n4 << 2) + blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += stride) a.best[v] = a.P[v];
+    } else {
+        for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += stride) a.best[v] = a.P[v];
+    }
+}
+
+// ------------------------------------------------------ connectivity core --
+
+// Group of G lanes gathers the neighbours of v (deg <= G*R) into table `tab`
+// and reads every adjacent part's total back exactly once: on return pu[r] is
+// the part of neighbour slot r (-1 if none) and cu[r] its connectivity for the
+// first lane that claimed it, else 0. The table is left all-zero.
+template <int G, int R>
+__device__ __forceinline__ void group_conn(const KArgs &a, int v, int gl, int32_t *tab, int (&pu)[R],
+                                           int (&cu)[R])
+{
+    const int64_t s = a.xadj[v];
+    const int deg = (int)(a.xadj[v + 1] - s);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int idx = gl + r * G;
+        pu[r] = -1;
+        if (idx < deg) {
+            const int u = a.adj[s + idx];
+            const int wt = a.ew ? a.ew[s + idx] : 1;
+            pu[r] = a.P[u];
+            atomicAdd(&tab[pu[r]], wt);
+        }
+    }
+    lds_fence_wave();
+#pragma unroll
+    for (int r = 0; r < R; r++) cu[r] = pu[r] >= 0 ? atomicExch(&tab[pu[r]], 0) : 0;
+    lds_fence_wave();
+}
+
+// Whole block gathers the neighbours of v into `tab` (k entries).
+__device__ __forceinline__ void block_fill(const KArgs &a, int v, int32_t *tab)
+{
+    const int64_t s = a.xadj[v], e = a.xadj[v + 1];
+    for (int64_t i = s + threadIdx.x; i < e; i += BLOCK) {
+        const int u = a.adj[i];
+        atomicAdd(&tab[a.P[u]], a.ew ? a.ew[i] : 1);
+    }
+    __syncthreads();
+}
+
+// Largest-connectivity key: connectivity in the high word, ~part in the low
+// word, so ties go to the smaller part id.
+__device__ __forceinline__ uint64_t conn_key(int c, int p)
+{
+    return ((uint64_t)(uint32_t)c << 32) | (uint32_t)(~p);
+}
+
+// -------------------------------------------------------------- Jetlp gain --
+
+// Writes rec[v] and appends v to its class's X list when it passes the
+// first filter (eq. gainconn_filter).
+__device__ __forceinline__ bool gain_finish(const KArgs &a, int v, int ps, uint64_t best, int cs)
+{
+    int2 r;
+    r.x = ps << 16;
+    r.y = 0;
+    bool inx = false;
+    int pd = ps;
+    int64_t F = INT64_MIN;
+    if (best) {
+        pd = (int)(~(uint32_t)best);
+        const int f = (int)(best >> 32) - cs;
+        const int64_t thr = ((int64_t)a.ctl->c_num * cs) / a.ctl->c_den;
+        inx = f >= 0 || -(int64_t)f < thr;
+        r.y = f;
+        F = f;
+        if (inx) r.x |= pd + 1;
+    }
+    a.rec[v] = r;
+    if (a.dbg_F) {
+        a.dbg_F[v] = F;
+        a.dbg_cs[v] = cs;
+        a.dbg_pd[v] = pd;
+    }
+    return inx;
+}
+
+__device__ __forceinline__ void gain_locked(const KArgs &a, int v, int ps)
+{
+    a.rec[v] = make_int2(ps << 16, 0);
+    if (a.dbg_F) { a.dbg_F[v] = INT64_MIN; a.dbg_cs[v] = 0; a.dbg_pd[v] = ps; }
+}
+
+template <int G, int R>
+__device__ void gain_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ngroups, int lp_prev)
+{
+    const int gl = threadIdx.x & (G - 1);
+    const int32_t *list = a.bins + a.binoff[cls];
+    const int cnt = a.binoff[cls + 1] - a.binoff[cls];
+    const int nloop = (cnt + ngroups - 1) / ngroups;
+    for (int it = 0; it < nloop; it++) {
+        const int i = it * ngroups + gid;
+        bool inx = false;
+        int v = -1;
+        if (i < cnt) {
+            v = list[i];
+            const int ps = a.P[v];
+            if (a.lock[v] == lp_prev) {
+                if (gl == 0) gain_locked(a, v, ps);
+            } else {
+                int pu[R], cu[R];
+                group_conn<G, R>(a, v, gl, tab, pu, cu);
+                uint64_t best = 0;
+                int cs = 0;
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    if (cu[r] > 0) {
+                        if (pu[r] == ps) cs += cu[r];
+                        else { uint64_t k2 = conn_key(cu[r], pu[r]); best = k2 > best ? k2 : best; }
+                    }
+                }
+                best = gmax_u64<G>(best);
+                cs = gsum<G>(cs);
+                if (gl == 0) inx = gain_finish(a, v, ps, best, cs);
+            }
+        }
+        // wave-uniform loop: every lane reaches the append
+        wave_append(inx, &a.ctl->xcnt[cls], a.xl + a.binoff[cls], v);
+    }
+}
+
+__device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nblocks, int lp_prev)
+{
+    __shared__ uint64_t s_red[BLOCK / 64];
+    __shared__ int32_t s_red32[BLOCK / 64];
+    const int32_t *list = a.bins + a.binoff[cls];
+    const int cnt = a.binoff[cls + 1] - a.binoff[cls];
+    for (int i = bid; i < cnt; i += nblocks) {
+        const int v = list[i];
+        const int ps = a.P[v];
+        if (a.lock[v] == lp_prev) {
+            if (threadIdx.x == 0) gain_locked(a, v, ps);
+            continue;
+        }
+        block_fill(a, v, tab);
+        uint64_t best = 0;
+        int cs = 0;
+        for (int p = threadIdx.x; p < a.k; p += BLOCK) {
+            const int c = tab[p];
+            if (c) {
+                tab[p] = 0;
+                if (p == ps) cs = c;
+                else { uint64_t k2 = conn_key(c, p); best = k2 > best ? k2 : best; }
+            }
+        }
+        best = block_max_u64<BLOCK>(best, s_red);
+        cs = block_sum<BLOCK>(cs, s_red32);
+        if (threadIdx.x == 0 && gain_finish(a, v, ps, best, cs)) {
+            int pos = atomicAdd(&a.ctl->xcnt[cls], 1);
+            a.xl[a.binoff[cls] + pos] = v;
+        }
+    }
+}
+
+// Role layout of the LDS-table kernels: blocks [0, gS) serve the classes
+// mapped to the 8-lane role, the next gM blocks the wave role, the next gL
+// blocks the block role, and (rebalancing only) the last gZ blocks isolated
+// vertices.
+__global__ __launch_bounds__(BLOCK) void k_gain(KArgs a)
+{
+    if (a.ctl->kind != KIND_LP) return;
+    extern __shared__ int32_t lds[];
+    const int lp_prev = a.ctl->lp_id - 1;
+    int b = blockIdx.x;
+    if (b < a.gS) {
+        const int ng = BLOCK / 8;
+        for (int i = threadIdx.x; i < ng * a.k; i += BLOCK) lds[i] = 0;
+        __syncthreads();
+        int32_t *tab = lds + (threadIdx.x >> 3) * a.k;
+        for (int c = 1; c < NCLS; c++)
+            if (a.tmap[c] == 1) gain_groups<8, 4>(a, c, tab, b * ng + (threadIdx.x >> 3), a.gS * ng, lp_prev);
+        return;
+    }
+    b -= a.gS;
+    if (b < a.gM) {
+        const int ng = BLOCK / 64;
+        for (int i = threadIdx.x; i < ng * a.k; i += BLOCK) lds[i] = 0;
+        __syncthreads();
+        int32_t *tab = lds + (threadIdx.x >> 6) * a.k;
+        for (int c = 1; c < NCLS; c++)
+            if (a.tmap[c] == 2) gain_groups<64, 16>(a, c, tab, b * ng + (threadIdx.x >> 6), a.gM * ng, lp_prev);
+        return;
+    }
+    b -= a.gM;
+    if (b < a.gL) {
+        for (int i = threadIdx.x; i < a.k; i += BLOCK) lds[i] = 0;
+        __syncthreads();
+        for (int c = 1; c < NCLS; c++)
+            if (a.tmap[c] == 3) gain_blocks(a, c, lds, b, a.gL, lp_prev);
+    }
+}
+
+// -------------------------------------------------------------- afterburner --
+
+// F2(v) = sum over neighbours u of w * ([q_u = P_d(v)] - [q_u = P_s(v)]) with
+// q_u = P_d(u) when u is in X and precedes v (larger F, or equal F and smaller
+// id), else P_s(u). Moves with F2 >= 0 form M.
+template <int G>
+__device__ __forceinline__ int after_sum(const KArgs &a, int v, int ps, int pd, int Fv, int gl, int stride)
+{
+    const int64_t s = a.xadj[v];
+    const int deg = (int)(a.xadj[v + 1] - s);
+    int sum = 0;
+    for (int idx = gl; idx < deg; idx += stride) {
+        const int u = a.adj[s + idx];
+        const int wt = a.ew ? a.ew[s + idx] : 1;
+        const int2 ru = a.rec[u];
+        int q = ru.x >> 16;
+        const int pdu = (ru.x & 0xFFFF) - 1;
+        if (pdu >= 0 && (ru.y > Fv || (ru.y == Fv && u < v))) q = pdu;
+        sum += q == pd ? wt : (q == ps ? -wt : 0);
+    }
+    return sum;
+}
+
+template <int G>
+__device__ void after_groups(const KArgs &a, int cls, int gid, int ngroups)
+{
+    const int gl = threadIdx.x & (G - 1);
+    const int32_t *list = a.xl + a.binoff[cls];
+    const int cnt = a.ctl->xcnt[cls];
+    const int nloop = (cnt + ngroups - 1) / ngroups;
+    for (int it = 0; it < nloop; it++) {
+        const int i = it * ngroups + gid;
+        bool mv = false;
+        int v = -1;
+        if (i < cnt) {
+            v = list[i];
+            const int2 r = a.rec[v];
+            const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
+            int sum = after_sum<G>(a, v, ps, pd, r.y, gl, G);
+            sum = gsum<G>(sum);
+            if (gl == 0) {
+                if (a.dbg_F2) a.dbg_F2[v] = sum;
+                if (sum >= 0) { mv = true; a.dest[v] = pd; }
+            }
+        }
+        wave_append(mv, &a.ctl->mcnt[cls], a.ml + a.binoff[cls], v);
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_afterburner(KArgs a)
+{
+    __shared__ int32_t s_red[BLOCK / 64];
+    if (a.ctl->kind != KIND_LP) return;
+    int b = blockIdx.x;
+    if (b < a.gS) { after_groups<8>(a, CLS_S, b * (BLOCK / 8) + (threadIdx.x >> 3), a.gS * (BLOCK / 8)); return; }
+    b -= a.gS;
+    if (b < a.gM) { after_groups<64>(a, CLS_M, b * (BLOCK / 64) + (threadIdx.x >> 6), a.gM * (BLOCK / 64)); return; }
+    b -= a.gM;
+    if (b >= a.gL) return;
+    const int32_t *list = a.xl + a.binoff[CLS_L];
+    const int cnt = a.ctl->xcnt[CLS_L];
+    for (int i = b; i < cnt; i += a.gL) {
+        const int v = list[i];
+        const int2 r = a.rec[v];
+        const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
+        int sum = after_sum<BLOCK>(a, v, ps, pd, r.y, threadIdx.x, BLOCK);
+        sum = block_sum<BLOCK>(sum, s_red);
+        if (threadIdx.x == 0) {
+            if (a.dbg_F2) a.dbg_F2[v] = sum;
+            if (sum >= 0) {
+                a.dest[v] = pd;
+                int pos = atomicAdd(&a.ctl->mcnt[CLS_L], 1);
+                a.ml[a.binoff[CLS_L] + pos] = v;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------- cut change of the moves --
+
+// Delta of the cut over the edges of moved vertices: an edge whose two ends
+// both move is counted from its smaller end. Also moved weight and digest.
+__device__ __forceinline__ int dcut_sum(const KArgs &a, int v, int ps, int pn, int gl, int stride)
+{
+    const int64_t s = a.xadj[v];
+    const int deg = (int)(a.xadj[v + 1] - s);
+    int delta = 0;
+    for (int idx = gl; idx < deg; idx += stride) {
+        const int u = a.adj[s + idx];
+        const int du = a.dest[u];
+        if (du >= 0 && u < v) continue;
+        const int wt = a.ew ? a.ew[s + idx] : 1;
+        const int pu = a.P[u];
+        const int pun = du >= 0 ? du : pu;
+        delta += wt * ((int)(pn != pun) - (int)(ps != pu));
+    }
+    return delta;
+}
+
+__device__ __forceinline__ void move_meta(const KArgs &a, int v, int ps, int pn, int64_t &mw, uint64_t &dg)
+{
+    mw += a.vw ? a.vw[v] : 1;
+    dg += mix64(((uint64_t)(uint32_t)v << 32) | (uint32_t)pn) - mix64(((uint64_t)(uint32_t)v << 32) | (uint32_t)ps);
+}
+
+template <int G>
+__device__ void dcut_groups(const KArgs &a, int cls, int gid, int ngroups, int64_t &dc, int64_t &mw, uint64_t &dg)
+{
+    const int gl = threadIdx.x & (G - 1);
+    const int32_t *list = a.ml + a.binoff[cls];
+    const int cnt = a.ctl->mcnt[cls];
+    for (int i = gid; i < cnt; i += ngroups) {
+        const int v = list[i];
+        const int ps = a.P[v], pn = a.dest[v];
+        int d = dcut_sum(a, v, ps, pn, gl, G);
+        d = gsum<G>(d);
+        if (gl == 0) {
+            dc += d;
+            move_meta(a, v, ps, pn, mw, dg);
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
+{
+    __shared__ int64_t s_red[BLOCK / 64];
+    __shared__ uint64_t s_redu[BLOCK / 64];
+    __shared__ int32_t s_red32[BLOCK / 64];
+    if (a.ctl->kind == KIND_DONE) return;
+    int64_t dc = 0, mw = 0;
+    uint64_t dg = 0;
+    int b = blockIdx.x;
+    if (b < a.gS) {
+        dcut_groups<8>(a, CLS_S, b * (BLOCK / 8) + (threadIdx.x >> 3), a.gS * (BLOCK / 8), dc, mw, dg);
+    } else if ((b -= a.gS) < a.gM) {
+        dcut_groups<64>(a, CLS_M, b * (BLOCK / 64) + (threadIdx.x >> 6), a.gM * (BLOCK / 64), dc, mw, dg);
+    } else if ((b -= a.gM) < a.gL) {
+        const int32_t *list = a.ml + a.binoff[CLS_L];
+        const int cnt = a.ctl->mcnt[CLS_L];
+        for (int i = b; i < cnt; i += a.gL) {
+            const int v = list[i];
+            const int ps = a.P[v], pn = a.dest[v];
+            int d = dcut_sum(a, v, ps, pn, threadIdx.x, BLOCK);
+            d = block_sum<BLOCK>(d, s_red32);
+            if (threadIdx.x == 0) { dc += d; move_meta(a, v, ps, pn, mw, dg); }
+        }
+    } else if ((b -= a.gL) < a.gZ) {
+        const int32_t *list = a.ml + a.binoff[CLS_Z];
+        const int cnt = a.ctl->mcnt[CLS_Z];
+        for (int i = b * BLOCK + threadIdx.x; i < cnt; i += a.gZ * BLOCK) {
+            const int v = list[i];
+            move_meta(a, v, a.P[v], a.dest[v], mw, dg);
+        }
+    }
+    dc = block_sum<BLOCK>(dc, s_red);
+    mw = block_sum<BLOCK>(mw, s_red);
+    dg = block_sum<BLOCK>(dg, s_redu);
+    if (threadIdx.x == 0 && (dc | mw | (int64_t)dg)) {
+        atomicAdd((unsigned long long *)&a.ctl->dcut, (unsigned long long)dc);
+        atomicAdd((unsigned long long *)&a.ctl->moved_w, (unsigned long long)mw);
+        atomicAdd((unsigned long long *)&a.ctl->ddigest, (unsigned long long)dg);
+    }
+}
+
+// ------------------------------------------------------------ apply moves --
+
+__global__ __launch_bounds__(BLOCK) void k_apply(KArgs a)
+{
+    extern __shared__ int32_t s_dw[];  // [k] block-partial weight change
+    const int kind = a.ctl->kind;
+    if (kind == KIND_DONE) return;
+    int off[NCLS + 1];
+    off[0] = 0;
+    for (int c = 0; c < NCLS; c++) off[c + 1] = off[c] + a.ctl->mcnt[c];
+    const int total = off[NCLS];
+    if (total == 0) return;
+    for (int p = threadIdx.x; p < a.k; p += BLOCK) s_dw[p] = 0;
+    __syncthreads();
+    const int lp_id = a.ctl->lp_id;
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < total; i += gridDim.x * BLOCK) {
+        int c = 0;
+        while (i >= off[c + 1]) c++;
+        const int v = a.ml[a.binoff[c] + (i - off[c])];
+        const int ps = a.P[v], pn = a.dest[v];
+        const int vwv = a.vw ? a.vw[v] : 1;
+        a.P[v] = pn;
+        a.dest[v] = -1;
+        if (kind == KIND_LP) a.lock[v] = lp_id;
+        atomicSub(&s_dw[ps], vwv);
+        atomicAdd(&s_dw[pn], vwv);
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < a.k; p += BLOCK)
+        if (s_dw[p]) atomicAdd((unsigned long long *)&a.w[p], (unsigned long long)(int64_t)s_dw[p]);
+}
+
+// -------------------------------------------------------------- rebalance --
+
+// Loss of an eligible vertex of an oversized part (Jetrw: own connectivity
+// minus that of the best connected valid destination, ties -> smaller id, or
+// a random valid destination when none is adjacent; Jetrs: own connectivity
+// minus the floor mean over adjacent valid destinations), its slot, and the
+// per-(part, slot) weight histogram.
+__device__ __forceinline__ void rb_finish(const KArgs &a, int v, int ps, int vwv, int kind, uint64_t best, int cs,
+                                          int sumB, int cntB, uint64_t hseed, int &ncand)
+{
+    int loss, d = -1;
+    if (kind == KIND_RW) {
+        if (best) {
+            d = (int)(~(uint32_t)best);
+            loss = cs - (int)(best >> 32);
+        } else if (a.ctl->nB > 0) {
+            const uint64_t h = mix64(hseed ^ (uint64_t)(uint32_t)v);
+            d = a.Blist[__umul64hi(h, (uint64_t)a.ctl->nB)];
+            loss = cs;
+        } else {
+            d = ps;  // unreachable: the lightest part is always a valid destination
+            loss = cs;
+        }
+        a.rbd[v] = d;
+    } else {
+        loss = cs - (cntB ? sumB / cntB : 0);
+    }
+    const int s = loss_slot(loss);
+    a.slot[v] = (uint8_t)s;
+    atomicAdd((unsigned long long *)&a.hist[ps * NSLOT + s], (unsigned long long)(int64_t)vwv);
+    ncand++;
+    if (a.dbg_loss) { a.dbg_loss[v] = loss; a.dbg_slot[v] = s; a.dbg_pd[v] = d; }
+}
+
+__device__ __forceinline__ bool rb_eligible(const KArgs &a, int ps, int vwv)
+{
+    const int64_t k = a.k;
+    return 2 * k * vwv <= 3 * (k * a.w[ps] - a.ctl->W);
+}
+
+template <int G, int R>
+__device__ void rb_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ngroups, int kind, uint64_t hseed,
+                          int &ncand)
+{
+    const int gl = threadIdx.x & (G - 1);
+    const int32_t *list = a.bins + a.binoff[cls];
+    const int cnt = a.binoff[cls + 1] - a.binoff[cls];
+    for (int i = gid; i < cnt; i += ngroups) {
+        const int v = list[i];
+        const int ps = a.P[v];
+        const int vwv = a.vw ? a.vw[v] : 1;
+        if (!a.isA[ps] || !rb_eligible(a, ps, vwv)) {
+            if (gl == 0) { a.slot[v] = 255; if (a.dbg_loss) { a.dbg_loss[v] = INT64_MIN; a.dbg_slot[v] = -1; a.dbg_pd[v] = -1; } }
+            continue;
+        }
+        int pu[R], cu[R];
+        group_conn<G, R>(a, v, gl, tab, pu, cu);
+        uint64_t best = 0;
+        int cs = 0, sumB = 0, cntB = 0;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            if (cu[r] > 0) {
+                if (pu[r] == ps) cs += cu[r];
+                else if (a.isB[pu[r]]) {
+                    uint64_t k2 = conn_key(cu[r], pu[r]);
+                    best = k2 > best ? k2 : best;
+                    sumB += cu[r];
+                    cntB++;
+                }
+            }
+        }
+        best = gmax_u64<G>(best);
+        cs = gsum<G>(cs);
+        sumB = gsum<G>(sumB);
+        cntB = gsum<G>(cntB);
+        if (gl == 0) rb_finish(a, v, ps, vwv, kind, best, cs, sumB, cntB, hseed, ncand);
+    }
+}
+
+__device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nblocks, int kind, uint64_t hseed,
+                          int &ncand)
+{
+    __shared__ uint64_t s_red[BLOCK / 64];
+    __shared__ int32_t s_red32[BLOCK / 64];
+    const int32_t *list = a.bins + a.binoff[cls];
+    const int cnt = a.binoff[cls + 1] - a.binoff[cls];
+    for (int i = bid; i < cnt; i += nblocks) {
+        const int v = list[i];
+        const int ps = a.P[v];
+        const int vwv = a.vw ? a.vw[v] : 1;
+        if (!a.isA[ps] || !rb_eligible(a, ps, vwv)) {
+            if (threadIdx.x == 0) { a.slot[v] = 255; if (a.dbg_loss) { a.dbg_loss[v] = INT64_MIN; a.dbg_slot[v] = -1; a.dbg_pd[v] = -1; } }
+            continue;
+        }
+        block_fill(a, v, tab);
+        uint64_t best = 0;
+        int cs = 0, sumB = 0, cntB = 0;
+        for (int p = threadIdx.x; p < a.k; p += BLOCK) {
+            const int c = tab[p];
+            if (c) {
+                tab[p] = 0;
+                if (p == ps) cs = c;
+                else if (a.isB[p]) {
+                    uint64_t k2 = conn_key(c, p);
+                    best = k2 > best ? k2 : best;
+                    sumB += c;
+                    cntB++;
+                }
+            }
+        }
+        best = block_max_u64<BLOCK>(best, s_red);
+        cs = block_sum<BLOCK>(cs, s_red32);
+        sumB = block_sum<BLOCK>(sumB, s_red32);
+        cntB = block_sum<BLOCK>(cntB, s_red32);
+        if (threadIdx.x == 0) rb_finish(a, v, ps, vwv, kind, best, cs, sumB, cntB, hseed, ncand);
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a)
+{
+    extern __shared__ int32_t lds[];
+    __shared__ int32_t s_red32[BLOCK / 64];
+    const int kind = a.ctl->kind;
+    if (kind != KIND_RW && kind != KIND_RS) return;
+    const uint64_t hseed = mix64(a.ctl->seed ^ (((uint64_t)(uint32_t)a.ctl->level << 32) + (uint64_t)(uint32_t)a.ctl->t));
+    int ncand = 0;
+    int b = blockIdx.x;
+    if (b < a.gS) {
+        const int ng = BLOCK / 8;
+        for (int i = threadIdx.x; i < ng * a.k; i += BLOCK) lds[i] = 0;
+        __syncthreads();
+        int32_t *tab = lds + (threadIdx.x >> 3) * a.k;
+        for (int c = 1; c < NCLS; c++)
+            if (a.tmap[c] == 1) rb_groups<8, 4>(a, c, tab, b * ng + (threadIdx.x >> 3), a.gS * ng, kind, hseed, ncand);
+    } else if ((b -= a.gS) < a.gM) {
+        const int ng = BLOCK / 64;
+        for (int i = threadIdx.x; i < ng * a.k; i += BLOCK) lds[i] = 0;
+        __syncthreads();
+        int32_t *tab = lds + (threadIdx.x >> 6) * a.k;
+        for (int c = 1; c < NCLS; c++)
+            if (a.tmap[c] == 2) rb_groups<64, 16>(a, c, tab, b * ng + (threadIdx.x >> 6), a.gM * ng, kind, hseed, ncand);
+    } else if ((b -= a.gM) < a.gL) {
+        for (int i = threadIdx.x; i < a.k; i += BLOCK) lds[i] = 0;
+        __syncthreads();
+        for (int c = 1; c < NCLS; c++)
+            if (a.tmap[c] == 3) rb_blocks(a, c, lds, b, a.gL, kind, hseed, ncand);
+    } else if ((b -= a.gL) < a.gZ) {
+        // isolated vertices: no connectivity, loss 0, random destination (Jetrw)
+        const int32_t *list = a.bins + a.binoff[CLS_Z];
+        const int cnt = a.binoff[CLS_Z + 1] - a.binoff[CLS_Z];
+        for (int i = b * BLOCK + threadIdx.x; i < cnt; i += a.gZ * BLOCK) {
+            const int v = list[i];
+            const int ps = a.P[v];
+            const int vwv = a.vw ? a.vw[v] : 1;
+            if (!a.isA[ps] || !rb_eligible(a, ps, vwv)) {
+                a.slot[v] = 255;
+                if (a.dbg_loss) { a.dbg_loss[v] = INT64_MIN; a.dbg_slot[v] = -1; a.dbg_pd[v] = -1; }
+                continue;
+            }
+            rb_finish(a, v, ps, vwv, kind, 0, 0, 0, 0, hseed, ncand);
+        }
+    } else {
+        return;
+    }
+    ncand = block_sum<BLOCK>(ncand, s_red32);
+    if (threadIdx.x == 0 && ncand) atomicAdd(&a.ctl->ncand, ncand);
+}
+
+// Per oversized part: cut-off slot s* (slots below it are evicted whole) and
+// the residual weight still needed inside s*; the compact list of parts whose
+// cut-off lies inside the histogram; Jetrs capacities over B.
+__global__ __launch_bounds__(BLOCK) void k_rb_cutoff(KArgs a)
+{
+    __shared__ int32_t s_scan[BLOCK / 64];
+    __shared__ int64_t s_scan64[BLOCK / 64];
+    Ctl *c = a.ctl;
+    const int kind = c->kind;
+    if (kind != KIND_RW && kind != KIND_RS) return;
+    const int64_t o = c->o;
+    int32_t carry = 0;
+    for (int base = 0; base < a.k; base += BLOCK) {
+        const int p = base + threadIdx.x;
+        int split = 0;
+        if (p < a.k) {
+            int ss = -1;
+            int64_t res = 0;
+            if (a.isA[p]) {
+                const int64_t need = a.w[p] - o;
+                int64_t cum = 0;
+                ss = NSLOT;
+                for (int s = 0; s < NSLOT; s++) {
+                    const int64_t h = a.hist[p * NSLOT + s];
+                    if (cum + h >= need) { ss = s; res = need - cum; break; }
+                    cum += h;
+                }
+            }
+            a.sstar[p] = ss;
+            a.resid[p] = res;
+            split = ss >= 0 && ss < NSLOT;
+        }
+        int32_t tot;
+        const int32_t pos = block_excl_scan<BLOCK>((int32_t)split, s_scan, tot);
+        if (p < a.k) a.splitidx[p] = split ? carry + pos : -1;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) c->nsplit = carry;
+    if (kind == KIND_RS) {
+        const int nB = c->nB;
+        const int64_t sigma = c->sigma;
+        int64_t acc = 0;
+        for (int base = 0; base < nB; base += BLOCK) {
+            const int i = base + threadIdx.x;
+            const int64_t cap = i < nB ? sigma - a.w[a.Blist[i]] : 0;
+            int64_t tot;
+            const int64_t pos = block_excl_scan<BLOCK>(cap, s_scan64, tot);
+            if (i < nB) a.capstart[i] = acc + pos;
+            acc += tot;
+        }
+        if (threadIdx.x == 0) { a.capstart[nB] = acc; c->total_cap = acc; }
+    }
+}
+
+// Per tile (one wave) and split part: weight of the tile's vertices that sit
+// in the part's cut-off slot. Stored as tsum[j * ntile + tile].
+__global__ __launch_bounds__(64) void k_rb_tilesum(KArgs a)
+{
+    extern __shared__ int32_t acc[];
+    const int kind = a.ctl->kind;
+    if (kind != KIND_RW && kind != KIND_RS) return;
+    const int nsplit = a.ctl->nsplit;
+    if (nsplit == 0) return;
+    for (int tile = blockIdx.x; tile < a.ntile; tile += gridDim.x) {
+        for (int j = threadIdx.x; j < nsplit; j += 64) acc[j] = 0;
+        lds_fence_wave();
+        const int v0 = tile * TILE;
+        for (int ch = 0; ch < TILE; ch += 64) {
+            const int v = v0 + ch + threadIdx.x;
+            if (v < a.n) {
+                const int sl = a.slot[v];
+                if (sl != 255) {
+                    const int p = a.P[v];
+                    if (sl == a.sstar[p]) atomicAdd(&acc[a.splitidx[p]], a.vw ? a.vw[v] : 1);
+                }
+            }
+        }
+        lds_fence_wave();
+        for (int j = threadIdx.x; j < nsplit; j += 64) a.tsum[(int64_t)j * a.ntile + tile] = acc[j];
+        lds_fence_wave();
+    }
+}
+
+// Exclusive scan over tiles of one split part per block.
+__global__ __launch_bounds__(BLOCK) void k_rb_tilescan(KArgs a)
+{
+    __shared__ int32_t s_scan[BLOCK / 64];
+    const int kind = a.ctl->kind;
+    if (kind != KIND_RW && kind != KIND_RS) return;
+    const int nsplit = a.ctl->nsplit;
+    for (int j = blockIdx.x; j < nsplit; j += gridDim.x) {
+        int32_t *row = a.tsum + (int64_t)j * a.ntile;
+        int32_t carry = 0;
+        for (int base = 0; base < a.ntile; base += BLOCK) {
+            const int i = base + threadIdx.x;
+            const int32_t x = i < a.ntile ? row[i] : 0;
+            int32_t tot;
+            const int32_t ex = block_excl_scan<BLOCK>(x, s_scan, tot);
+            if (i < a.ntile) row[i] = carry + ex;
+            carry += tot;
+        }
+    }
+}
+
+__device__ __forceinline__ int degree_class(const KArgs &a, int v)
+{
+    const int64_t d = a.xadj[v + 1] - a.xadj[v];
+    return d == 0 ? CLS_Z : (d <= S_MAXDEG ? CLS_S : (d <= M_MAXDEG ? CLS_M : CLS_L));
+}
+
+// Ordered eviction inside each tile (one wave): a candidate in a slot below
+// its part's cut-off is evicted; one in the cut-off slot is evicted when the
+// weight of earlier (smaller id) cut-off-slot vertices of its part is below
+// the residual. Jetrw emits the move; Jetrs marks the vertex and sums the
+// tile's evicted weight.
+__global__ __launch_bounds__(64) void k_rb_select(KArgs a)
+{
+    extern __shared__ int32_t run[];
+    const int kind = a.ctl->kind;
+    if (kind != KIND_RW && kind != KIND_RS) return;
+    const int nsplit = a.ctl->nsplit;
+    const int l = threadIdx.x;
+    for (int tile = blockIdx.x; tile < a.ntile; tile += gridDim.x) {
+        for (int j = l; j < nsplit; j += 64) run[j] = a.tsum[(int64_t)j * a.ntile + tile];
+        lds_fence_wave();
+        int64_t esum = 0;
+        const int v0 = tile * TILE;
+        for (int ch = 0; ch < TILE; ch += 64) {
+            const int v = v0 + ch + l;
+            const bool valid = v < a.n;
+            int sl = 255, p = 0, vwv = 0;
+            if (valid) {
+                sl = a.slot[v];
+                if (sl != 255) { p = a.P[v]; vwv = a.vw ? a.vw[v] : 1; }
+            }
+            const bool cand = sl != 255;
+            const int ss = cand ? a.sstar[p] : -1;
+            bool ev = cand && sl < ss;
+            const bool split = cand && sl == ss;
+            uint64_t rem = __ballot(split);
+            while (rem) {
+                const int leader = __ffsll((unsigned long long)rem) - 1;
+                const int pl = __shfl(p, leader, 64);
+                const bool in = split && p == pl;
+                const uint64_t grp = __ballot(in);
+                const int x = in ? vwv : 0;
+                const int inc = wave_incl_scan(x);
+                const int j = a.splitidx[pl];
+                const int base = run[j];
+                if (in) ev = (int64_t)base + inc - x < a.resid[pl];
+                lds_fence_wave();
+                if (l == 63) run[j] = base + inc;
+                lds_fence_wave();
+                rem &= ~grp;
+            }
+            if (kind == KIND_RW) {
+                if (ev) a.dest[v] = a.rbd[v];
+                const int c = valid ? degree_class(a, v) : -1;
+#pragma unroll
+                for (int cc = 0; cc < NCLS; cc++) wave_append(ev && c == cc, &a.ctl->mcnt[cc], a.ml + a.binoff[cc], v);
+            } else {
+                if (valid) a.rsev[v] = ev;
+                if (ev) esum += vwv;
+            }
+        }
+        if (kind == KIND_RS) {
+            esum = gsum<64>(esum);
+            if (l == 0) a.esum[tile] = esum;
+        }
+        lds_fence_wave();
+    }
+}
+
+// Jetrs: exclusive scan of the evicted weight over tiles.
+__global__ __launch_bounds__(BLOCK) void k_rs_scan(KArgs a)
+{
+    __shared__ int64_t s_scan[BLOCK / 64];
+    if (a.ctl->kind != KIND_RS) return;
+    int64_t carry = 0;
+    for (int base = 0; base < a.ntile; base += BLOCK) {
+        const int i = base + threadIdx.x;
+        const int64_t x = i < a.ntile ? a.esum[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan<BLOCK>(x, s_scan, tot);
+        if (i < a.ntile) a.esum[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+// Jetrs cookie-cutter: evicted vertices in id order take consecutive
+// positions (exclusive prefix of their weights); position pos goes to the
+// valid destination whose capacity interval [capstart, capstart + cap) holds
+// it; positions beyond the total capacity stay.
+__global__ __launch_bounds__(64) void k_rs_assign(KArgs a)
+{
+    if (a.ctl->kind != KIND_RS) return;
+    const int nB = a.ctl->nB;
+    const int64_t total = a.ctl->total_cap;
+    const int l = threadIdx.x;
+    for (int tile = blockIdx.x; tile < a.ntile; tile += gridDim.x) {
+        int64_t runpos = a.esum[tile];
+        const int v0 = tile * TILE;
+        for (int ch = 0; ch < TILE; ch += 64) {
+            const int v = v0 + ch + l;
+            const bool valid = v < a.n;
+            const bool ev = valid && a.rsev[v];
+            const int64_t x = ev ? (a.vw ? a.vw[v] : 1) : 0;
+            const int64_t inc = wave_incl_scan(x);
+            const int64_t pos = runpos + inc - x;
+            runpos += __shfl(inc, 63, 64);
+            bool mv = false;
+            if (ev && pos < total) {
+                int lo = 0, hi = nB;  // largest i with capstart[i] <= pos (capstart[0] = 0 <= pos)
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (a.capstart[mid] <= pos) lo = mid; else hi = mid;
+                }
+                a.dest[v] = a.Blist[lo];
+                mv = true;
+            }
+            const int c = valid ? degree_class(a, v) : -1;
+#pragma unroll
+            for (int cc = 0; cc < NCLS; cc++) wave_append(mv && c == cc, &a.ctl->mcnt[cc], a.ml + a.binoff[cc], v);
+        }
+    }
+}
+
+// ------------------------------------------------------------- host side --
+
+int hip_status(jet_context *ctx, hipError_t e)
+{
+    if (e == hipSuccess) return JET_OK;
+    ctx->last_hip = (int)e;
+    if (e == hipErrorOutOfMemory) return JET_ENOMEM;
+    return JET_EHIP;
+}
+
+void *ws_get(jet_context *ctx, int slot, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    Buffer &b = ctx->bufs[slot];
+    if (b.bytes >= bytes) return b.ptr;
+    if (b.ptr) { (void)hipFree(b.ptr); b.ptr = nullptr; b.bytes = 0; }
+    size_t want = bytes + bytes / 8;  // headroom for the next, slightly larger level
+    if (hipMalloc(&b.ptr, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.ptr = nullptr;
+        return nullptr;
+    }
+    b.bytes = want;
+    return b.ptr;
+}
+
+static int64_t balance_limit(int64_t W, int k, int lambda_ppm)
+{
+    return (int64_t)(((__int128)W * (1000000 + (__int128)lambda_ppm)) / ((__int128)k * 1000000));
+}
+static int64_t deadzone_sigma(int64_t W, int k, int64_t o, int div)
+{
+    const int64_t ceil_avg = (W + k - 1) / k;
+    const int64_t slack = o - ceil_avg;
+    if (slack <= 0) return o;
+    if (slack < div) return o - 1;
+    return o - slack / div;
+}
+
+#define JET_TRY(expr)                                      \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return hip_status(ctx, e_);  \
+    } while (0)
+
+struct Plan {
+    KArgs tab;    // LDS-table kernels (gain, loss)
+    KArgs plain;  // afterburner, cut delta
+    int grid_tab, grid_plain, grid_rbtab;
+    size_t lds_tab;
+    int grid_flat;
+    int grid_tile;
+};
+
+static int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+static void plan_roles(const jet_context *ctx, KArgs &a, const int32_t *cnt, Plan &pl)
+{
+    const int maxb = ctx->num_cu * 8;
+    // LDS-table kernels: the 8-lane role keeps 32 tables of k ints, the wave
+    // role 4, the block role 1; larger k moves classes to roles with fewer
+    // tables so a block stays within 64 KiB of LDS.
+    KArgs t = a;
+    t.tmap[0] = 0;
+    const int k = a.k;
+    if (k <= 512) { t.tmap[1] = 1; t.tmap[2] = 2; t.tmap[3] = 3; }
+    else if (k <= 4096) { t.tmap[1] = 2; t.tmap[2] = 2; t.tmap[3] = 3; }
+    else { t.tmap[1] = 3; t.tmap[2] = 3; t.tmap[3] = 3; }
+    int64_t role_cnt[4] = {0, 0, 0, 0};
+    for (int c = 1; c < NCLS; c++) role_cnt[t.tmap[c]] += cnt[c];
+    t.gS = std::min(div_up(role_cnt[1], BLOCK / 8), maxb);
+    t.gM = std::min(div_up(role_cnt[2], BLOCK / 64), maxb);
+    t.gL = std::min((int)role_cnt[3], maxb);
+    t.gZ = std::min(div_up(cnt[0], BLOCK), maxb);
+    size_t lds = 0;
+    if (t.gS) lds = std::max(lds, (size_t)(BLOCK / 8) * k * 4);
+    if (t.gM) lds = std::max(lds, (size_t)(BLOCK / 64) * k * 4);
+    if (t.gL) lds = std::max(lds, (size_t)k * 4);
+    pl.lds_tab = lds;
+    pl.grid_tab = t.gS + t.gM + t.gL;       // gain: no isolated role
+    pl.grid_rbtab = t.gS + t.gM + t.gL + t.gZ;
+    // plain row kernels: roles follow the classes directly
+    KArgs p = a;
+    p.tmap[0] = 0; p.tmap[1] = 1; p.tmap[2] = 2; p.tmap[3] = 3;
+    p.gS = std::min(div_up(cnt[1], BLOCK / 8), maxb);
+    p.gM = std::min(div_up(cnt[2], BLOCK / 64), maxb);
+    p.gL = std::min(cnt[3], maxb);
+    p.gZ = std::min(div_up(cnt[0], BLOCK), maxb);
+    pl.grid_plain = p.gS + p.gM + p.gL + p.gZ;
+    pl.tab = t;
+    pl.plain = p;
+    pl.grid_flat = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
+    pl.grid_tile = std::max(1, std::min(a.ntile, ctx->num_cu * 8));
+}
+
+static void launch_iteration(const Plan &pl, hipStream_t s, bool lp_kernels, bool rb_kernels)
+{
+    const KArgs &t = pl.tab;
+    const KArgs &p = pl.plain;
+    k_ctl_begin<<<1, BLOCK, 0, s>>>(p);
+    if (lp_kernels) {
+        if (pl.grid_tab) k_gain<<<pl.grid_tab, BLOCK, pl.lds_tab, s>>>(t);
+        if (pl.grid_plain) k_afterburner<<<pl.grid_plain, BLOCK, 0, s>>>(p);
+    }
+    if (rb_kernels) {
+        if (pl.grid_rbtab) k_rb_loss<<<pl.grid_rbtab, BLOCK, pl.lds_tab, s>>>(t);
+        k_rb_cutoff<<<1, BLOCK, 0, s>>>(p);
+        k_rb_tilesum<<<pl.grid_tile, 64, (size_t)p.k * 4, s>>>(p);
+        k_rb_tilescan<<<std::min(p.k, 1024), BLOCK, 0, s>>>(p);
+        k_rb_select<<<pl.grid_tile, 64, (size_t)p.k * 4, s>>>(p);
+        k_rs_scan<<<1, BLOCK, 0, s>>>(p);
+        k_rs_assign<<<pl.grid_tile, 64, 0, s>>>(p);
+    }
+    if (pl.grid_plain) k_dcut<<<pl.grid_plain, BLOCK, 0, s>>>(p);
+    k_apply<<<pl.grid_flat, BLOCK, (size_t)p.k * 4, s>>>(p);
+    k_ctl_end<<<1, BLOCK, 0, s>>>(p);
+    k_copy_best<<<pl.grid_flat, BLOCK, 0, s>>>(p);
+}
+
+static void set_lds_limits()
+{
+    static bool done = false;
+    if (done) return;
+    done = true;
+    (void)hipFuncSetAttribute((const void *)k_gain, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_apply, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_init_vertices, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_tilesum, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_select, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+}
+
+static int check_params(const jet_csr *g, const jet_params *prm)
+{
+    if (!g || !prm) return JET_EINVAL;
+    if (prm->k < 1 || prm->lambda_ppm < 0 || prm->c_den < 0 || prm->c_num < 0 || prm->phi_den < 0 ||
+        prm->phi_num < 0 || prm->stall_limit < 0 || prm->deadzone_div < 0 || prm->max_iters < 0 ||
+        prm->weak_rebalance_iters < -1 || prm->level < 0)
+        return JET_EINVAL;
+    if (prm->c_den > 0 && prm->c_num > prm->c_den * 64) return JET_EINVAL;
+    if (prm->k > KMAX) return JET_ELIMIT;
+    if (g->n < 0 || g->nnz < 0) return JET_EGRAPH;
+    if (g->n > 0 && (!g->xadj)) return JET_EINVAL;
+    if (g->nnz > 0 && !g->adjncy) return JET_EINVAL;
+    return JET_OK;
+}
+
+// Host-side full CSR check (JET_F_VALIDATE): symmetric with equal weights,
+// no duplicates, no self-loops, ids in range.
+static int validate_full(jet_context *ctx, const jet_csr *g, hipStream_t s)
+{
+    const int n = g->n;
+    const int64_t nnz = g->nnz;
+    std::vector<int64_t> xadj(n + 1);
+    std::vector<int32_t> adj(nnz), ew(nnz, 1);
+    JET_TRY(hipMemcpyAsync(xadj.data(), g->xadj, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+    if (nnz) JET_TRY(hipMemcpyAsync(adj.data(), g->adjncy, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
+    if (nnz && g->adjwgt) JET_TRY(hipMemcpyAsync(ew.data(), g->adjwgt, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
+    JET_TRY(hipStreamSynchronize(s));
+    if (xadj[0] != 0 || xadj[n] != nnz) return JET_EGRAPH;
+    std::vector<uint64_t> key(nnz), rkey(nnz);
+    std::vector<std::pair<uint64_t, int32_t>> kw(nnz), rkw(nnz);
+    for (int v = 0; v < n; v++) {
+        if (xadj[v + 1] < xadj[v]) return JET_EGRAPH;
+        for (int64_t e = xadj[v]; e < xadj[v + 1]; e++) {
+            const int u = adj[e];
+            if (u < 0 || u >= n || u == v || ew[e] < 1) return JET_EGRAPH;
+            kw[e] = {((uint64_t)(uint32_t)v << 32) | (uint32_t)u, ew[e]};
+            rkw[e] = {((uint64_t)(uint32_t)u << 32) | (uint32_t)v, ew[e]};
+        }
+    }
+    std::sort(kw.begin(), kw.end());
+    std::sort(rkw.begin(), rkw.end());
+    for (int64_t e = 0; e < nnz; e++) {
+        if (e > 0 && kw[e].first == kw[e - 1].first) return JET_EGRAPH;
+        if (kw[e] != rkw[e]) return JET_EGRAPH;
+    }
+    return JET_OK;
+}
+
+struct DebugOut {
+    int64_t *F = nullptr, *cs = nullptr, *F2 = nullptr, *loss = nullptr;
+    int32_t *pd = nullptr, *slot = nullptr;
+};
+
+// Shared set-up of a refinement call: validates, fills the workspace and the
+// controller, and returns the launch plan.
+static int setup(jet_context *ctx, const jet_csr *g, const jet_params *prm, int32_t *part, Plan &pl,
+                 Ctl &hc, hipStream_t s, jet_trace_rec *trace_dev, int32_t trace_cap, const DebugOut *dbg)
+{
+    const int n = g->n, k = prm->k;
+    set_lds_limits();
+    if (prm->flags & JET_F_VALIDATE) {
+        int st = validate_full(ctx, g, s);
+        if (st) return st;
+    }
+    KArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = n; a.k = k;
+    a.xadj = g->xadj; a.adj = g->adjncy; a.vw = g->vwgt; a.ew = g->adjwgt;
+    const size_t nn = (size_t)std::max(n, 1);
+    a.P = (int32_t *)ws_get(ctx, WS_P, nn * 4);
+    a.rec = (int2 *)ws_get(ctx, WS_REC, nn * 8);
+    a.dest = (int32_t *)ws_get(ctx, WS_DEST, nn * 4);
+    a.lock = (int32_t *)ws_get(ctx, WS_LOCK, nn * 4);
+    a.slot = (uint8_t *)ws_get(ctx, WS_SLOT, nn);
+    a.rbd = (int32_t *)ws_get(ctx, WS_RBD, nn * 4);
+    a.rsev = (uint8_t *)ws_get(ctx, WS_RSEV, nn);
+    int32_t *bins = (int32_t *)ws_get(ctx, WS_BIN, nn * 4);
+    a.bins = bins;
+    a.xl = (int32_t *)ws_get(ctx, WS_XL, nn * 4);
+    a.ml = (int32_t *)ws_get(ctx, WS_ML, nn * 4);
+    a.ctl = (Ctl *)ws_get(ctx, WS_CTL, sizeof(Ctl) + 64);
+    int64_t *p64 = (int64_t *)ws_get(ctx, WS_PART64, sizeof(int64_t) * (4 * (size_t)k + 8));
+    int32_t *p32 = (int32_t *)ws_get(ctx, WS_PART32, sizeof(int32_t) * (3 * (size_t)k + 8));
+    uint8_t *p8 = (uint8_t *)ws_get(ctx, WS_PART8, 2 * (size_t)k + 16);
+    a.hist = (int64_t *)ws_get(ctx, WS_HIST, sizeof(int64_t) * (size_t)k * NSLOT);
+    a.ntile = std::max(1, div_up(n, TILE));
+    a.tsum = (int32_t *)ws_get(ctx, WS_TSUM, sizeof(int32_t) * (size_t)a.ntile * k);
+    a.esum = (int64_t *)ws_get(ctx, WS_ESUM, sizeof(int64_t) * (size_t)a.ntile);
+    if (!a.P || !a.rec || !a.dest || !a.lock || !a.slot || !a.rbd || !a.rsev || !bins || !a.xl || !a.ml ||
+        !a.ctl || !p64 || !p32 || !p8 || !a.hist || !a.tsum || !a.esum)
+        return JET_ENOMEM;
+    a.w = p64; a.wbest = p64 + k; a.resid = p64 + 2 * k; a.capstart = p64 + 3 * k;
+    a.Blist = p32; a.sstar = p32 + k; a.splitidx = p32 + 2 * k;
+    a.isA = p8; a.isB = p8 + k;
+    a.best = part;
+    a.trace = trace_dev;
+    if (dbg) {
+        a.dbg_F = dbg->F; a.dbg_cs = dbg->cs; a.dbg_F2 = dbg->F2; a.dbg_loss = dbg->loss;
+        a.dbg_pd = dbg->pd; a.dbg_slot = dbg->slot;
+    }
+    // controller configuration; state starts at zero
+    memset(&hc, 0, sizeof(hc));
+    hc.n = n; hc.k = k;
+    hc.stall_limit = prm->stall_limit > 0 ? prm->stall_limit : 12;
+    hc.bmax = prm->weak_rebalance_iters == 0 ? 2 : (prm->weak_rebalance_iters < 0 ? 0 : prm->weak_rebalance_iters);
+    hc.max_iters = prm->max_iters;
+    if (prm->c_den > 0) { hc.c_num = prm->c_num; hc.c_den = prm->c_den; }
+    else { hc.c_num = prm->level == 0 ? 1 : 3; hc.c_den = 4; }
+    hc.phi_num = prm->phi_num > 0 ? prm->phi_num : 999;
+    hc.phi_den = prm->phi_den > 0 ? prm->phi_den : 1000;
+    hc.level = prm->level;
+    hc.trace_cap = trace_dev ? trace_cap : 0;
+    hc.seed = prm->seed;
+    Ctl *pin = (Ctl *)ctx->pinned;
+    *pin = hc;
+    JET_TRY(hipMemcpyAsync(a.ctl, pin, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    JET_TRY(hipMemsetAsync(a.w, 0, sizeof(int64_t) * k, s));
+    const int grid_v = std::max(1, std::min(div_up(n, BLOCK), ctx->num_cu * 4));
+    if (n > 0) k_init_vertices<<<grid_v, BLOCK, (size_t)k * 4, s>>>(a, part);
+    if (g->nnz > 0) {
+        const int grid_e = std::max(1, std::min(div_up(div_up(g->nnz, 16), BLOCK), ctx->num_cu * 8));
+        k_init_edges<<<grid_e, BLOCK, 0, s>>>(a, g->nnz);
+    }
+    JET_TRY(hipGetLastError());
+    JET_TRY(hipMemcpyAsync(pin, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    int64_t *xends = (int64_t *)((char *)ctx->pinned + 2048);
+    JET_TRY(hipMemcpyAsync(xends, g->xadj, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    JET_TRY(hipMemcpyAsync(xends + 1, g->xadj + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    JET_TRY(hipStreamSynchronize(s));
+    hc = *pin;
+    if (xends[0] != 0 || xends[1] != g->nnz) return JET_EGRAPH;
+    if (hc.bad_graph) return JET_EGRAPH;
+    if (hc.bad_part) return JET_EPART;
+    if (hc.wsum >= ((int64_t)1 << 31) || hc.ewsum >= ((int64_t)1 << 31)) return JET_EOVERFLOW;
+    a.binoff[0] = 0;
+    for (int c = 0; c < NCLS; c++) a.binoff[c + 1] = a.binoff[c] + hc.bincnt[c];
+    int32_t *fill = a.xl;  // scratch counters before the X lists are used
+    JET_TRY(hipMemsetAsync(fill, 0, sizeof(int32_t) * NCLS, s));
+    if (n > 0) k_fill_bins<<<grid_v, BLOCK, 0, s>>>(a, bins, fill);
+    const int64_t W = hc.wsum;
+    const int64_t o = balance_limit(W, k, prm->lambda_ppm);
+    const int64_t sigma = deadzone_sigma(W, k, o, prm->deadzone_div > 0 ? prm->deadzone_div : 10);
+    k_ctl_setup<<<1, BLOCK, 0, s>>>(a, W, o, sigma);
+    JET_TRY(hipGetLastError());
+    hc.W = W; hc.o = o; hc.sigma = sigma;
+    plan_roles(ctx, a, hc.bincnt, pl);
+    return JET_OK;
+}
+
+int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int32_t *part,
+                 int64_t *part_weights_out, jet_stats *stats, jet_trace_rec *trace_host, int32_t trace_cap,
+                 int32_t *trace_count, int32_t *trace_total, hipStream_t s)
+{
+    int st = check_params(g, prm);
+    if (st) return st;
+    const int n = g->n, k = prm->k;
+    if (trace_count) *trace_count = 0;
+    if (trace_total) *trace_total = 0;
+    JET_TRY(hipEventRecord(ctx->ev[0], s));
+    if (k == 1 || n == 0) {
+        // a single part: every vertex in part 0, nothing to refine
+        if (n > 0) JET_TRY(hipMemsetAsync(part, 0, sizeof(int32_t) * n, s));
+        int64_t W = n;
+        if (n > 0 && g->vwgt) {
+            std::vector<int32_t> vw(n);
+            JET_TRY(hipMemcpyAsync(vw.data(), g->vwgt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+            JET_TRY(hipStreamSynchronize(s));
+            W = 0;
+            for (int32_t x : vw) W += x;
+        }
+        if (part_weights_out) {
+            std::vector<int64_t> pw(k, 0);
+            pw[0] = W;
+            JET_TRY(hipMemcpyAsync(part_weights_out, pw.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, s));
+        }
+        JET_TRY(hipStreamSynchronize(s));
+        if (stats) {
+            memset(stats, 0, sizeof(*stats));
+            stats->max_part_weight = W;
+            stats->o = balance_limit(W, k, prm->lambda_ppm);
+            stats->sigma = stats->o;
+            stats->total_weight = W;
+            stats->balanced = W <= stats->o;
+            stats->levels = 1;
+        }
+        return JET_OK;
+    }
+    jet_trace_rec *trace_dev = nullptr;
+    if (trace_host && trace_cap > 0) {
+        trace_dev = (jet_trace_rec *)ws_get(ctx, WS_TRACE, sizeof(jet_trace_rec) * (size_t)trace_cap);
+        if (!trace_dev) return JET_ENOMEM;
+    }
+    Plan pl;
+    Ctl hc;
+    st = setup(ctx, g, prm, part, pl, hc, s, trace_dev, trace_cap, nullptr);
+    if (st) return st;
+    JET_TRY(hipEventRecord(ctx->ev[1], s));
+    Ctl *pin = (Ctl *)ctx->pinned;
+    int chunk = 4;
+    for (;;) {
+        for (int i = 0; i < chunk; i++) launch_iteration(pl, s, true, true);
+        JET_TRY(hipGetLastError());
+        JET_TRY(hipMemcpyAsync(pin, pl.plain.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        JET_TRY(hipStreamSynchronize(s));
+        if (pin->done) break;
+        chunk = std::min(chunk * 2, 32);
+    }
+    hc = *pin;
+    JET_TRY(hipEventRecord(ctx->ev[2], s));
+    if (prm->flags & JET_F_RETURN_ITER)
+        JET_TRY(hipMemcpyAsync(part, pl.plain.P, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    if (part_weights_out)
+        JET_TRY(hipMemcpyAsync(part_weights_out, (prm->flags & JET_F_RETURN_ITER) ? pl.plain.w : pl.plain.wbest,
+                               sizeof(int64_t) * k, hipMemcpyDeviceToDevice, s));
+    const int ntr = std::min(hc.t, hc.trace_cap);
+    if (trace_dev && ntr > 0)
+        JET_TRY(hipMemcpyAsync(trace_host, trace_dev, sizeof(jet_trace_rec) * ntr, hipMemcpyDeviceToHost, s));
+    JET_TRY(hipEventRecord(ctx->ev[3], s));
+    JET_TRY(hipStreamSynchronize(s));
+    if (trace_count) *trace_count = ntr;
+    if (trace_total) *trace_total = hc.t;
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        const bool it = prm->flags & JET_F_RETURN_ITER;
+        stats->cut = it ? hc.cut : hc.cut_best;
+        stats->max_part_weight = it ? hc.maxw : hc.maxw_best;
+        stats->o = hc.o;
+        stats->sigma = hc.sigma;
+        stats->total_weight = hc.W;
+        stats->balanced = stats->max_part_weight <= hc.o;
+        stats->iters = hc.t;
+        stats->lp_iters = hc.n_lp;
+        stats->rw_iters = hc.n_rw;
+        stats->rs_iters = hc.n_rs;
+        stats->levels = 1;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]);
+        stats->ms_total = ms;
+        (void)hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]);
+        stats->ms_refine = ms;
+        (void)hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]);
+        stats->ms_init = ms;
+    }
+    return JET_OK;
+}
+
+}  // namespace jet
+
+using namespace jet;
+
+// --------------------------------------------------------------- C ABI ------
+
+extern "C" int jet_context_create(jet_context **out, int device)
+{
+    if (!out) return JET_EINVAL;
+    *out = nullptr;
+    jet_context *ctx = new (std::nothrow) jet_context();
+    if (!ctx) return JET_ENOMEM;
+    ctx->device = device;
+    ctx->bufs.resize(WS_COUNT);
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) { int st = hip_status(ctx, e); delete ctx; return st; }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        ctx->num_cu = prop.multiProcessorCount;
+    ctx->pinned_bytes = 4096;
+    e = hipHostMalloc(&ctx->pinned, ctx->pinned_bytes, hipHostMallocDefault);
+    if (e != hipSuccess) { int st = hip_status(ctx, e); delete ctx; return st; }
+    for (auto &ev : ctx->ev) {
+        e = hipEventCreate(&ev);
+        if (e != hipSuccess) { int st = hip_status(ctx, e); jet_context_destroy(ctx); return st; }
+    }
+    *out = ctx;
+    return JET_OK;
+}
+
+extern "C" void jet_context_destroy(jet_context *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    for (auto &b : ctx->bufs)
+        if (b.ptr) (void)hipFree(b.ptr);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (auto &ev : ctx->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    delete ctx;
+}
+
+extern "C" int jet_last_hip_error(const jet_context *ctx) { return ctx ? ctx->last_hip : 0; }
+
+extern "C" const char *jet_strerror(int status)
+{
+    switch (status) {
+    case JET_OK: return "ok";
+    case JET_EINVAL: return "invalid parameter";
+    case JET_EGRAPH: return "malformed CSR graph";
+    case JET_EPART: return "part id out of range";
+    case JET_EOVERFLOW: return "total vertex or edge weight too large (>= 2^31)";
+    case JET_ENOMEM: return "out of memory";
+    case JET_EHIP: return "HIP runtime error";
+    case JET_EAGAIN: return "try again";
+    case JET_ELIMIT: return "size limit exceeded";
+    default: return "unknown status";
+    }
+}
+
+extern "C" int jet_refine(jet_context *ctx, const jet_csr *g, const jet_params *params, int32_t *part,
+                          int64_t *part_weights_out, jet_stats *stats, jet_trace *trace, void *stream)
+{
+    if (!ctx || !g || !params || (!part && g->n > 0)) return JET_EINVAL;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_status(ctx, e);
+    int32_t cnt = 0, tot = 0;
+    int st = refine_level(ctx, g, params, part, part_weights_out, stats, trace ? trace->recs : nullptr,
+                          trace ? trace->cap : 0, &cnt, &tot, (hipStream_t)stream);
+    if (trace) { trace->count = cnt; trace->total = tot; }
+    return st;
+}
+
+extern "C" int jet_lp_step(jet_context *ctx, const jet_csr *g, const jet_params *params, const int32_t *part,
+                           const uint8_t *locked, int32_t *pd, int64_t *F, int64_t *conn_s, uint8_t *inX,
+                           int64_t *F2, uint8_t *move, void *stream)
+{
+    if (!ctx || !g || !params) return JET_EINVAL;
+    int st = check_params(g, params);
+    if (st) return st;
+    const int n = g->n;
+    if (n > 0 && (!part || !locked || !pd || !F || !conn_s || !inX || !F2 || !move)) return JET_EINVAL;
+    if (params->k < 2) return JET_EINVAL;
+    if (n == 0) return JET_OK;
+    hipStream_t s = (hipStream_t)stream;
+    JET_TRY(hipSetDevice(ctx->device));
+    // private copy of the partition: the step leaves `part` untouched
+    int32_t *p0 = (int32_t *)ws_get(ctx, WS_H0, sizeof(int32_t) * n);
+    if (!p0) return JET_ENOMEM;
+    JET_TRY(hipMemcpyAsync(p0, part, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    DebugOut dbg;
+    dbg.F = F; dbg.cs = conn_s; dbg.F2 = F2; dbg.pd = pd;
+    Plan pl;
+    Ctl hc;
+    st = setup(ctx, g, params, p0, pl, hc, s, nullptr, 0, &dbg);
+    if (st) return st;
+    k_step_defaults<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, part);
+    k_force_step<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, KIND_LP, 0, locked);
+    if (pl.grid_tab) k_gain<<<pl.grid_tab, BLOCK, pl.lds_tab, s>>>(pl.tab);
+    if (pl.grid_plain) k_afterburner<<<pl.grid_plain, BLOCK, 0, s>>>(pl.plain);
+    k_lp_outputs<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, inX, move);
+    JET_TRY(hipGetLastError());
+    JET_TRY(hipStreamSynchronize(s));
+    return JET_OK;
+}
+
+extern "C" int jet_rebalance_step(jet_context *ctx, const jet_csr *g, const jet_params *params,
+                                  const int32_t *part, int32_t kind, int32_t t, int32_t *dest, int64_t *loss,
+                                  int32_t *slot, void *stream)
+{
+    if (!ctx || !g || !params) return JET_EINVAL;
+    int st = check_params(g, params);
+    if (st) return st;
+    if (kind != KIND_RW && kind != KIND_RS) return JET_EINVAL;
+    const int n = g->n;
+    if (n > 0 && (!part || !dest || !loss || !slot)) return JET_EINVAL;
+    if (params->k < 2 || t < 0) return JET_EINVAL;
+    if (n == 0) return JET_OK;
+    hipStream_t s = (hipStream_t)stream;
+    JET_TRY(hipSetDevice(ctx->device));
+    int32_t *p0 = (int32_t *)ws_get(ctx, WS_H0, sizeof(int32_t) * n);
+    int32_t *pdv = (int32_t *)ws_get(ctx, WS_DBG_LOCK, sizeof(int32_t) * n);
+    if (!p0 || !pdv) return JET_ENOMEM;
+    JET_TRY(hipMemcpyAsync(p0, part, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    DebugOut dbg;
+    dbg.loss = loss; dbg.slot = slot; dbg.pd = pdv;
+    Plan pl;
+    Ctl hc;
+    st = setup(ctx, g, params, p0, pl, hc, s, nullptr, 0, &dbg);
+    if (st) return st;
+    const KArgs &p = pl.plain;
+    k_step_defaults<<<pl.grid_flat, BLOCK, 0, s>>>(p, part);
+    k_force_step<<<1, BLOCK, 0, s>>>(p, kind, t, nullptr);
+    if (pl.grid_rbtab) k_rb_loss<<<pl.grid_rbtab, BLOCK, pl.lds_tab, s>>>(pl.tab);
+    k_rb_cutoff<<<1, BLOCK, 0, s>>>(p);
+    k_rb_tilesum<<<pl.grid_tile, 64, (size_t)p.k * 4, s>>>(p);
+    k_rb_tilescan<<<std::min(p.k, 1024), BLOCK, 0, s>>>(p);
+    k_rb_select<<<pl.grid_tile, 64, (size_t)p.k * 4, s>>>(p);
+    k_rs_scan<<<1, BLOCK, 0, s>>>(p);
+    k_rs_assign<<<pl.grid_tile, 64, 0, s>>>(p);
+    JET_TRY(hipGetLastError());
+    JET_TRY(hipMemcpyAsync(dest, p.dest, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    JET_TRY(hipStreamSynchronize(s));
+    return JET_OK;
+}

@@ -1,0 +1,322 @@
+"""Python binding of libjet.so: argument marshalling only.
+
+Every computation runs in the library's HIP kernels; this module converts
+torch CUDA tensors into the C ABI's device pointers and structs and passes
+torch's current HIP stream. It raises if libjet.so is missing or if a
+tensor is not on the GPU; there is no fallback path.
+
+Names follow the C ABI (include/jet.h): ``refine``, ``lp_step``,
+``rebalance_step``, ``coarsen``, ``partition``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libjet.so")
+
+JET_OK, JET_EINVAL, JET_EGRAPH, JET_EPART, JET_EOVERFLOW, JET_ENOMEM, JET_EHIP, JET_EAGAIN, JET_ELIMIT = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+JET_F_VALIDATE = 0x1
+JET_F_RETURN_ITER = 0x2
+KIND_LP, KIND_RW, KIND_RS = 1, 2, 3
+
+# Every function declared in include/jet.h.
+EXPORTS = [
+    "jet_context_create", "jet_context_destroy", "jet_strerror", "jet_last_hip_error",
+    "jet_refine", "jet_lp_step", "jet_rebalance_step", "jet_coarsen", "jet_hierarchy_levels",
+    "jet_hierarchy_level", "jet_hierarchy_free", "jet_partition",
+]
+
+
+class JetError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("reserved", C.c_int32), ("nnz", C.c_int64),
+                ("xadj", C.c_void_p), ("adjncy", C.c_void_p), ("vwgt", C.c_void_p),
+                ("adjwgt", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("k", C.c_int32), ("lambda_ppm", C.c_int32), ("c_num", C.c_int32),
+                ("c_den", C.c_int32), ("phi_num", C.c_int32), ("phi_den", C.c_int32),
+                ("stall_limit", C.c_int32), ("weak_rebalance_iters", C.c_int32),
+                ("deadzone_div", C.c_int32), ("level", C.c_int32), ("max_iters", C.c_int32),
+                ("flags", C.c_uint32), ("seed", C.c_uint64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("cut", C.c_int64), ("max_part_weight", C.c_int64), ("o", C.c_int64),
+                ("sigma", C.c_int64), ("total_weight", C.c_int64), ("balanced", C.c_int32),
+                ("iters", C.c_int32), ("lp_iters", C.c_int32), ("rw_iters", C.c_int32),
+                ("rs_iters", C.c_int32), ("levels", C.c_int32), ("ms_total", C.c_float),
+                ("ms_refine", C.c_float), ("ms_coarsen", C.c_float), ("ms_init", C.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TraceRec(C.Structure):
+    _fields_ = [("level", C.c_int32), ("t", C.c_int32), ("kind", C.c_int32), ("nX", C.c_int32),
+                ("nM", C.c_int32), ("stall", C.c_int32), ("wcount", C.c_int32),
+                ("balanced", C.c_int32), ("moved_w", C.c_int64), ("cut", C.c_int64),
+                ("maxw", C.c_int64), ("best_cut", C.c_int64), ("digest", C.c_uint64)]
+
+
+class Trace(C.Structure):
+    _fields_ = [("recs", C.c_void_p), ("cap", C.c_int32), ("count", C.c_int32),
+                ("total", C.c_int32), ("reserved", C.c_int32)]
+
+
+TRACE_FIELDS = [f for f, _ in TraceRec._fields_]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libjet.so not built ({LIB_PATH}); run python -m paper_2304_13194_amd.build")
+        L = C.CDLL(LIB_PATH)
+        L.jet_strerror.restype = C.c_char_p
+        L.jet_hierarchy_level.argtypes = [C.c_void_p, C.c_int, C.POINTER(Csr), C.POINTER(C.c_void_p)]
+        L.jet_hierarchy_levels.argtypes = [C.c_void_p]
+        L.jet_hierarchy_free.argtypes = [C.c_void_p]
+        L.jet_context_destroy.argtypes = [C.c_void_p]
+        L.jet_last_hip_error.argtypes = [C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _check(st, what):
+    if st != JET_OK:
+        raise JetError(st, f"{what}: {lib().jet_strerror(st).decode()}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class DeviceGraph:
+    """Device CSR; vwgt / adjwgt may be None (unit weights)."""
+    xadj: torch.Tensor
+    adjncy: torch.Tensor
+    vwgt: torch.Tensor | None
+    adjwgt: torch.Tensor | None
+
+    @property
+    def n(self):
+        return int(self.xadj.shape[0] - 1)
+
+    @property
+    def nnz(self):
+        return int(self.adjncy.shape[0])
+
+    def csr(self) -> Csr:
+        return Csr(self.n, 0, self.nnz, _ptr(self.xadj), _ptr(self.adjncy), _ptr(self.vwgt),
+                   _ptr(self.adjwgt))
+
+
+def to_device(g, unit_vwgt=False, unit_adjwgt=False, device="cuda") -> DeviceGraph:
+    """Copy a host graph (``inputs.Graph``) to the GPU."""
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+    return DeviceGraph(t(g.xadj, np.int64), t(g.adjncy, np.int32),
+                       None if unit_vwgt else t(g.vwgt, np.int32),
+                       None if unit_adjwgt else t(g.adjwgt, np.int32))
+
+
+def make_params(k, lambda_ppm=30000, c=None, phi=None, stall_limit=0, weak_rebalance_iters=0,
+                deadzone_div=0, level=0, max_iters=0, flags=0, seed=0) -> Params:
+    cn, cd = (0, 0) if c is None else c
+    pn, pd = (0, 0) if phi is None else phi
+    return Params(k, lambda_ppm, cn, cd, pn, pd, stall_limit, weak_rebalance_iters, deadzone_div,
+                  level, max_iters, flags, seed & ((1 << 64) - 1))
+
+
+class Context:
+    def __init__(self, device=None):
+        dev = torch.cuda.current_device() if device is None else device
+        self.h = C.c_void_p()
+        _check(lib().jet_context_create(C.byref(self.h), C.c_int(dev)), "jet_context_create")
+
+    def close(self):
+        if self.h:
+            lib().jet_context_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = None
+
+
+def default_context() -> Context:
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context()
+    return _default_ctx
+
+
+def _trace_buf(cap):
+    if cap <= 0:
+        return None, None
+    arr = (TraceRec * cap)()
+    return arr, Trace(C.cast(arr, C.c_void_p), cap, 0, 0, 0)
+
+
+def _trace_list(arr, tr):
+    if tr is None:
+        return None
+    return [{f: getattr(arr[i], f) for f in TRACE_FIELDS} for i in range(tr.count)]
+
+
+def refine(g: DeviceGraph, part: torch.Tensor, k: int, trace_cap=0, ctx=None, part_weights=False,
+           **kw):
+    """jet_refine: refines ``part`` (int32 device tensor) in place to P_best.
+
+    Returns (stats dict, trace list or None, part weights tensor or None)."""
+    ctx = ctx or default_context()
+    prm = make_params(k, **kw)
+    st = Stats()
+    arr, tr = _trace_buf(trace_cap)
+    pw = torch.empty(k, dtype=torch.int64, device=part.device) if part_weights else None
+    csr = g.csr()
+    s = lib().jet_refine(ctx.h, C.byref(csr), C.byref(prm), _ptr(part), _ptr(pw), C.byref(st),
+                         C.byref(tr) if tr is not None else None, _stream())
+    _check(s, "jet_refine")
+    out = st.as_dict()
+    if tr is not None:
+        out["trace_total"] = tr.total
+    return out, _trace_list(arr, tr), pw
+
+
+def lp_step(g: DeviceGraph, part: torch.Tensor, locked: torch.Tensor, k: int, ctx=None, **kw):
+    """jet_lp_step: one Jetlp step. Returns dict of device tensors."""
+    ctx = ctx or default_context()
+    prm = make_params(k, **kw)
+    n = g.n
+    dev = part.device
+    out = dict(pd=torch.empty(n, dtype=torch.int32, device=dev),
+               F=torch.empty(n, dtype=torch.int64, device=dev),
+               conn_s=torch.empty(n, dtype=torch.int64, device=dev),
+               inX=torch.empty(n, dtype=torch.uint8, device=dev),
+               F2=torch.empty(n, dtype=torch.int64, device=dev),
+               move=torch.empty(n, dtype=torch.uint8, device=dev))
+    csr = g.csr()
+    s = lib().jet_lp_step(ctx.h, C.byref(csr), C.byref(prm), _ptr(part), _ptr(locked), _ptr(out["pd"]),
+                          _ptr(out["F"]), _ptr(out["conn_s"]), _ptr(out["inX"]), _ptr(out["F2"]),
+                          _ptr(out["move"]), _stream())
+    _check(s, "jet_lp_step")
+    return out
+
+
+def rebalance_step(g: DeviceGraph, part: torch.Tensor, kind: int, t: int, k: int, ctx=None, **kw):
+    """jet_rebalance_step: one Jetrw (kind 2) / Jetrs (kind 3) step."""
+    ctx = ctx or default_context()
+    prm = make_params(k, **kw)
+    n = g.n
+    dev = part.device
+    out = dict(dest=torch.empty(n, dtype=torch.int32, device=dev),
+               loss=torch.empty(n, dtype=torch.int64, device=dev),
+               slot=torch.empty(n, dtype=torch.int32, device=dev))
+    csr = g.csr()
+    s = lib().jet_rebalance_step(ctx.h, C.byref(csr), C.byref(prm), _ptr(part), C.c_int32(kind),
+                                 C.c_int32(t), _ptr(out["dest"]), _ptr(out["loss"]), _ptr(out["slot"]),
+                                 _stream())
+    _check(s, "jet_rebalance_step")
+    return out
+
+
+def partition(g: DeviceGraph, k: int, trace_cap=0, ctx=None, **kw):
+    """jet_partition: full multilevel partition. Returns (part tensor, stats, trace)."""
+    ctx = ctx or default_context()
+    prm = make_params(k, **kw)
+    st = Stats()
+    arr, tr = _trace_buf(trace_cap)
+    part = torch.empty(g.n, dtype=torch.int32, device=g.xadj.device)
+    csr = g.csr()
+    s = lib().jet_partition(ctx.h, C.byref(csr), C.byref(prm), _ptr(part), C.byref(st),
+                            C.byref(tr) if tr is not None else None, _stream())
+    _check(s, "jet_partition")
+    out = st.as_dict()
+    if tr is not None:
+        out["trace_total"] = tr.total
+    return part, out, _trace_list(arr, tr)
+
+
+class Hierarchy:
+    """jet_coarsen result; levels are views into library-owned device memory."""
+
+    def __init__(self, h):
+        self.h = h
+
+    @property
+    def levels(self):
+        return lib().jet_hierarchy_levels(self.h)
+
+    def level(self, i):
+        """(n, xadj, adjncy, vwgt, adjwgt, map) of level i as host numpy arrays."""
+        view = Csr()
+        mp = C.c_void_p()
+        _check(lib().jet_hierarchy_level(self.h, i, C.byref(view), C.byref(mp)), "jet_hierarchy_level")
+        n, nnz = view.n, view.nnz
+
+        def fetch(ptr, count, dt):
+            if not ptr or count == 0:
+                return None if not ptr else np.zeros(0, dt)
+            out = np.empty(count, dt)
+            torch.cuda.synchronize()
+            C.memmove  # keep ctypes import used
+            import ctypes
+            hip = ctypes.CDLL("libamdhip64.so")
+            hip.hipMemcpy(C.c_void_p(out.ctypes.data), C.c_void_p(ptr), C.c_size_t(out.nbytes), C.c_int(2))
+            return out
+
+        return dict(n=n, xadj=fetch(view.xadj, n + 1, np.int64), adjncy=fetch(view.adjncy, nnz, np.int32),
+                    vwgt=fetch(view.vwgt, n, np.int32), adjwgt=fetch(view.adjwgt, nnz, np.int32),
+                    map=fetch(mp.value, n, np.int32))
+
+    def close(self):
+        if self.h:
+            lib().jet_hierarchy_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def coarsen(g: DeviceGraph, k: int, ctx=None, **kw) -> Hierarchy:
+    ctx = ctx or default_context()
+    prm = make_params(k, **kw)
+    h = C.c_void_p()
+    csr = g.csr()
+    _check(lib().jet_coarsen(ctx.h, C.byref(csr), C.byref(prm), C.byref(h), _stream()), "jet_coarsen")
+    return Hierarchy(h)
