@@ -54,6 +54,7 @@ extern "C" {
 /* ---- flags ------------------------------------------------------------- */
 #define JET_F_VALIDATE    0x1u  /* full CSR check: range, self-loops, symmetry, duplicates */
 #define JET_F_RETURN_ITER 0x2u  /* return P_iter (state after the last iteration) instead of P_best */
+#define JET_F_PROFILE     0x4u  /* time the connectivity/gain passes (see jet_stats.ms_gain) */
 
 typedef struct jet_context jet_context;
 typedef struct jet_hierarchy jet_hierarchy;
@@ -103,6 +104,13 @@ typedef struct {
     float ms_refine;         /* device time spent in refinement iterations */
     float ms_coarsen;        /* device time spent coarsening (jet_partition) */
     float ms_init;           /* device time of per-level set-up (binning, cut, weights) */
+    /* With JET_F_PROFILE, for the Jetlp iterations of the finest level (level
+     * 0): summed device time of the connectivity/gain passes (hipEvents on
+     * the call's stream around each pass), their count, the CSR entries and
+     * unlocked rows they read and the vertices they visited. */
+    float ms_gain;
+    int32_t gain_passes;
+    int64_t gain_entries, gain_rows, gain_vertices;
 } jet_stats;
 
 /* One record per refinement iteration (written when a trace is passed). */

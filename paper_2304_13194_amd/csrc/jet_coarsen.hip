@@ -1,15 +1,730 @@
-// Multilevel scaffold (placeholder until the coarsening kernels land).
+// Multilevel scaffold on gfx950 (Algorithms 1 and 2): heavy-edge matching,
+// hashed contraction, projection, a seeded random coarsest partition, and the
+// driver that refines every level on the way back up.
+//
+// Heavy-edge matching runs in rounds of mutual proposals: every unmatched
+// vertex proposes to the unmatched neighbour across its heaviest edge (ties
+// to the smaller edge hash mix64(hseed ^ (min << 32 | max)), then to the
+// smaller id) and mutual proposals match. A device-side check stops the
+// rounds once a round matches fewer than 1% of the vertices, so the 16
+// rounds are enqueued without host synchronisation. Pairs and singletons
+// are numbered by their smaller member (exclusive scan over leader flags).
+// Contraction follows Algorithm 2: an upper bound of each coarse row's length
+// (sum of member degrees), an exclusive scan of the bounds, open-addressed
+// per-row hash tables (twice the bound) filled with atomic CAS + add, and a
+// compaction of the occupied slots. Coarse rows come out unsorted; nothing
+// downstream depends on row order.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "jet_device.h"
 #include "jet_internal.h"
 
-extern "C" int jet_coarsen(jet_context *, const jet_csr *, const jet_params *, jet_hierarchy **, void *)
-{
-    return JET_ELIMIT;
+namespace jet {
+int validate_full_csr(jet_context *ctx, const jet_csr *g, hipStream_t s);
 }
-extern "C" int jet_hierarchy_levels(const jet_hierarchy *) { return 0; }
-extern "C" int jet_hierarchy_level(const jet_hierarchy *, int, jet_csr *, const int32_t **) { return JET_EINVAL; }
-extern "C" void jet_hierarchy_free(jet_hierarchy *) {}
-extern "C" int jet_partition(jet_context *, const jet_csr *, const jet_params *, int32_t *, jet_stats *, jet_trace *,
-                             void *)
+
+struct jet_hierarchy {
+    int device = 0;
+    int nlevels = 0;
+    std::vector<jet_csr> lv;        // level views (level 0 = caller's graph)
+    std::vector<int32_t *> maps;    // maps[l]: level l -> level l+1 (owned)
+    std::vector<void *> owned;      // device buffers owned by the hierarchy
+    float ms_coarsen = 0.f;
+};
+
+namespace jet {
+
+constexpr int CB = 256;   // block size of the coarsening kernels
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = CB * SCAN_ITEMS;
+
+struct CState {
+    int32_t stop;
+    int32_t newly;
+    int32_t bad;
+    int32_t pad;
+    int64_t wsum, ewsum;
+};
+
+// --------------------------------------------------------- input checks ---
+
+__global__ __launch_bounds__(CB) void k_chk_vertices(int n, const int64_t *xadj, const int32_t *vw, CState *st)
 {
-    return JET_ELIMIT;
+    __shared__ int64_t s_red[CB / 64];
+    int64_t ws = 0;
+    int bad = 0;
+    for (int v = blockIdx.x * CB + threadIdx.x; v < n; v += gridDim.x * CB) {
+        const int x = vw ? vw[v] : 1;
+        if (x < 1) bad = 1;
+        if (xadj[v + 1] < xadj[v]) bad = 1;
+        ws += x;
+    }
+    ws = block_sum<CB>(ws, s_red);
+    if (bad) st->bad = 1;
+    if (threadIdx.x == 0) atomicAdd((unsigned long long *)&st->wsum, (unsigned long long)ws);
+}
+
+__global__ __launch_bounds__(CB) void k_chk_edges(int n, int64_t nnz, const int64_t *xadj, const int32_t *adj,
+                                                  const int32_t *ew, CState *st)
+{
+    __shared__ int64_t s_red[CB / 64];
+    constexpr int RUN = 16;
+    int64_t ews = 0;
+    int bad = 0;
+    const int64_t nruns = (nnz + RUN - 1) / RUN;
+    for (int64_t r = (int64_t)blockIdx.x * CB + threadIdx.x; r < nruns; r += (int64_t)gridDim.x * CB) {
+        const int64_t e0 = r * RUN, e1 = e0 + RUN < nnz ? e0 + RUN : nnz;
+        int lo = 0, hi = n;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (xadj[mid] <= e0) lo = mid; else hi = mid;
+        }
+        int v = lo;
+        int64_t vend = xadj[v + 1];
+        for (int64_t e = e0; e < e1; e++) {
+            while (e >= vend && v < n - 1) { v++; vend = xadj[v + 1]; }
+            const int u = adj[e];
+            const int w = ew ? ew[e] : 1;
+            if (u < 0 || u >= n || u == v || w < 1) { bad = 1; continue; }
+            ews += w;
+        }
+    }
+    ews = block_sum<CB>(ews, s_red);
+    if (bad) st->bad = 1;
+    if (threadIdx.x == 0) atomicAdd((unsigned long long *)&st->ewsum, (unsigned long long)ews);
+}
+
+// ---------------------------------------------------------------- scans ---
+
+// Exclusive scan of int32 `in[0..n)` into int64 `out[0..n]` (out[n] = total).
+__global__ __launch_bounds__(CB) void k_scan_tiles(const int32_t *in, int n, int64_t *tsum)
+{
+    __shared__ int64_t s_red[CB / 64];
+    const int base = blockIdx.x * SCAN_TILE;
+    int64_t acc = 0;
+    for (int i = threadIdx.x; i < SCAN_TILE; i += CB) {
+        const int j = base + i;
+        if (j < n) acc += in[j];
+    }
+    acc = block_sum<CB>(acc, s_red);
+    if (threadIdx.x == 0) tsum[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(CB) void k_scan_top(int64_t *tsum, int ntiles)
+{
+    __shared__ int64_t s_scan[CB / 64];
+    int64_t carry = 0;
+    for (int base = 0; base < ntiles; base += CB) {
+        const int i = base + threadIdx.x;
+        const int64_t x = i < ntiles ? tsum[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan<CB>(x, s_scan, tot);
+        if (i < ntiles) tsum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) tsum[ntiles] = carry;
+}
+
+__global__ __launch_bounds__(CB) void k_scan_apply(const int32_t *in, int n, const int64_t *tsum, int64_t *out)
+{
+    __shared__ int64_t s_scan[CB / 64];
+    const int base = blockIdx.x * SCAN_TILE;
+    int64_t carry = tsum[blockIdx.x];
+    for (int c = 0; c < SCAN_ITEMS; c++) {
+        const int j = base + c * CB + threadIdx.x;
+        const int64_t x = j < n ? in[j] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan<CB>(x, s_scan, tot);
+        if (j < n) out[j] = carry + ex;
+        carry += tot;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = tsum[gridDim.x];
+}
+
+static void scan_excl(const int32_t *in, int n, int64_t *out, int64_t *tsum, hipStream_t s)
+{
+    const int ntiles = std::max(1, (n + SCAN_TILE - 1) / SCAN_TILE);
+    k_scan_tiles<<<ntiles, CB, 0, s>>>(in, n, tsum);
+    k_scan_top<<<1, CB, 0, s>>>(tsum, ntiles);
+    k_scan_apply<<<ntiles, CB, 0, s>>>(in, n, tsum, out);
+}
+
+// ------------------------------------------------------ heavy-edge match ---
+
+// Larger is better: heavier edge, then smaller hash, then smaller id.
+struct Prop {
+    int32_t w;
+    int32_t u;
+    uint64_t h;
+};
+__device__ __forceinline__ bool prop_better(const Prop &a, const Prop &b)
+{
+    if (a.u < 0) return false;
+    if (b.u < 0) return true;
+    if (a.w != b.w) return a.w > b.w;
+    if (a.h != b.h) return a.h < b.h;
+    return a.u < b.u;
+}
+
+__device__ __forceinline__ Prop prop_shfl_xor(const Prop &p, int o, int width)
+{
+    Prop q;
+    q.w = __shfl_xor(p.w, o, width);
+    q.u = __shfl_xor(p.u, o, width);
+    q.h = __shfl_xor(p.h, o, width);
+    return q;
+}
+
+__device__ __forceinline__ Prop prop_scan_row(int v, int64_t s, int64_t e, int lane, int stride, const int32_t *adj,
+                                               const int32_t *ew, const int32_t *match, uint64_t hseed)
+{
+    Prop best{0, -1, 0};
+    for (int64_t i = s + lane; i < e; i += stride) {
+        const int u = adj[i];
+        if (match[u] >= 0) continue;
+        const uint32_t lo = (uint32_t)(u < v ? u : v), hi = (uint32_t)(u < v ? v : u);
+        Prop c{ew ? ew[i] : 1, u, mix64(hseed ^ (((uint64_t)lo << 32) | hi))};
+        if (prop_better(c, best)) best = c;
+    }
+    return best;
+}
+
+// Proposals. Vertices of degree <= 64 use 8-lane groups; heavier rows are
+// left to k_hem_propose_big (one block per row) through the `big` list.
+__global__ __launch_bounds__(CB) void k_hem_propose(int n, const int64_t *xadj, const int32_t *adj, const int32_t *ew,
+                                                    const int32_t *match, int32_t *prop, uint64_t hseed,
+                                                    const CState *st)
+{
+    if (st->stop) return;
+    constexpr int G = 8;
+    const int gl = threadIdx.x & (G - 1);
+    const int ngroups = gridDim.x * (CB / G);
+    for (int v = blockIdx.x * (CB / G) + (threadIdx.x >> 3); v < n; v += ngroups) {
+        const int64_t s = xadj[v], e = xadj[v + 1];
+        if (e - s > 64) continue;  // heavy row: handled by the block kernel
+        if (match[v] >= 0) { if (gl == 0) prop[v] = -1; continue; }
+        Prop b = prop_scan_row(v, s, e, gl, G, adj, ew, match, hseed);
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) {
+            Prop q = prop_shfl_xor(b, o, G);
+            if (prop_better(q, b)) b = q;
+        }
+        if (gl == 0) prop[v] = b.u;
+    }
+}
+
+__global__ __launch_bounds__(CB) void k_hem_propose_big(const int32_t *big, int nbig, const int64_t *xadj,
+                                                        const int32_t *adj, const int32_t *ew, const int32_t *match,
+                                                        int32_t *prop, uint64_t hseed, const CState *st)
+{
+    __shared__ Prop s_p[CB / 64];
+    if (st->stop) return;
+    for (int i = blockIdx.x; i < nbig; i += gridDim.x) {
+        const int v = big[i];
+        if (match[v] >= 0) { if (threadIdx.x == 0) prop[v] = -1; continue; }
+        Prop b = prop_scan_row(v, xadj[v], xadj[v + 1], threadIdx.x, CB, adj, ew, match, hseed);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            Prop q = prop_shfl_xor(b, o, 64);
+            if (prop_better(q, b)) b = q;
+        }
+        if ((threadIdx.x & 63) == 0) s_p[threadIdx.x >> 6] = b;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            Prop r = s_p[0];
+            for (int w = 1; w < CB / 64; w++)
+                if (prop_better(s_p[w], r)) r = s_p[w];
+            prop[v] = r.u;
+        }
+        __syncthreads();
+    }
+}
+
+// Mutual proposals match; the smaller id of each pair writes both entries.
+__global__ __launch_bounds__(CB) void k_hem_match(int n, int32_t *match, const int32_t *prop, CState *st)
+{
+    __shared__ int32_t s_red[CB / 64];
+    if (st->stop) return;
+    int cnt = 0;
+    for (int v = blockIdx.x * CB + threadIdx.x; v < n; v += gridDim.x * CB) {
+        if (match[v] >= 0) continue;
+        const int u = prop[v];
+        if (u > v && prop[u] == v) {
+            match[v] = u;
+            match[u] = v;
+            cnt += 2;
+        }
+    }
+    cnt = block_sum<CB>(cnt, s_red);
+    if (threadIdx.x == 0 && cnt) atomicAdd(&st->newly, cnt);
+}
+
+__global__ void k_hem_round_end(int n, CState *st)
+{
+    if (st->stop) return;
+    const int64_t newly = st->newly;
+    if (newly == 0 || newly * 100 < (int64_t)n) st->stop = 1;
+    st->newly = 0;
+}
+
+__global__ __launch_bounds__(CB) void k_big_list(int n, const int64_t *xadj, int32_t *big, int32_t *nbig)
+{
+    const int stride = gridDim.x * CB;
+    const int nloop = (n + stride - 1) / stride;
+    for (int it = 0; it < nloop; it++) {
+        const int v = it * stride + blockIdx.x * CB + threadIdx.x;
+        const bool heavy = v < n && xadj[v + 1] - xadj[v] > 64;
+        wave_append(heavy, nbig, big, v);
+    }
+}
+
+__global__ __launch_bounds__(CB) void k_leader_flags(int n, const int32_t *match, int32_t *flag)
+{
+    for (int v = blockIdx.x * CB + threadIdx.x; v < n; v += gridDim.x * CB) {
+        const int m = match[v];
+        flag[v] = (m < 0 || v < m) ? 1 : 0;
+    }
+}
+
+// map[v] = coarse id of v's leader; coarse vertex weight and row-length bound
+// are written by the leader.
+__global__ __launch_bounds__(CB) void k_coarse_map(int n, const int32_t *match, const int64_t *cid,
+                                                   const int64_t *xadj, const int32_t *vw, int32_t *map,
+                                                   int32_t *cvw, int32_t *bound)
+{
+    for (int v = blockIdx.x * CB + threadIdx.x; v < n; v += gridDim.x * CB) {
+        const int m = match[v];
+        const bool leader = m < 0 || v < m;
+        const int lead = leader ? v : m;
+        const int c = (int)cid[lead];
+        map[v] = c;
+        if (leader) {
+            int w = vw ? vw[v] : 1;
+            int64_t b = xadj[v + 1] - xadj[v];
+            if (m >= 0) {
+                w += vw ? vw[m] : 1;
+                b += xadj[m + 1] - xadj[m];
+            }
+            cvw[c] = w;
+            bound[c] = (int32_t)b;
+        }
+    }
+}
+
+// Algorithm 2's insertOrLookup: every fine edge (v, u, w) with distinct coarse
+// ends adds w to key map[u] in the table of row map[v]. Tables are open
+// addressed over [toff[c], toff[c] + 2 * bound[c]) with linear probing.
+__global__ __launch_bounds__(CB) void k_contract_insert(int n, int64_t nnz, const int64_t *xadj, const int32_t *adj,
+                                                        const int32_t *ew, const int32_t *map, const int64_t *toff,
+                                                        int32_t *tkey, int32_t *tval, int32_t *ccount)
+{
+    constexpr int RUN = 16;
+    const int64_t nruns = (nnz + RUN - 1) / RUN;
+    for (int64_t r = (int64_t)blockIdx.x * CB + threadIdx.x; r < nruns; r += (int64_t)gridDim.x * CB) {
+        const int64_t e0 = r * RUN, e1 = e0 + RUN < nnz ? e0 + RUN : nnz;
+        int lo = 0, hi = n;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (xadj[mid] <= e0) lo = mid; else hi = mid;
+        }
+        int v = lo;
+        int64_t vend = xadj[v + 1];
+        int cv = map[v];
+        for (int64_t e = e0; e < e1; e++) {
+            while (e >= vend) { v++; vend = xadj[v + 1]; cv = map[v]; }
+            const int cu = map[adj[e]];
+            if (cu == cv) continue;
+            const int w = ew ? ew[e] : 1;
+            const int64_t base = toff[cv];
+            const uint32_t T = (uint32_t)(toff[cv + 1] - base);
+            uint32_t h = ((uint32_t)cu * 2654435761u) % T;
+            for (;;) {
+                const int32_t old = atomicCAS(&tkey[base + h], -1, cu);
+                if (old == -1) { atomicAdd(&ccount[cv], 1); atomicAdd(&tval[base + h], w); break; }
+                if (old == cu) { atomicAdd(&tval[base + h], w); break; }
+                h = h + 1 == T ? 0 : h + 1;
+            }
+        }
+    }
+}
+
+// Compaction of each coarse row's occupied slots (8 lanes per row).
+__global__ __launch_bounds__(CB) void k_contract_extract(int nc, const int64_t *toff, const int32_t *tkey,
+                                                         const int32_t *tval, const int64_t *cxadj, int32_t *cadj,
+                                                         int32_t *cew)
+{
+    constexpr int G = 8;
+    const int gl = threadIdx.x & (G - 1);
+    const int gshift = (threadIdx.x & 63) & ~(G - 1);
+    const int ngroups = gridDim.x * (CB / G);
+    const int nloop_rows = (nc + ngroups - 1) / ngroups;
+    for (int it = 0; it < nloop_rows; it++) {
+        const int c = it * ngroups + blockIdx.x * (CB / G) + (threadIdx.x >> 3);
+        const bool rowok = c < nc;
+        int64_t s = 0, e = 0, out = 0;
+        if (rowok) { s = toff[c]; e = toff[c + 1]; out = cxadj[c]; }
+        // lanes of a wave walk their rows in lockstep chunks of G slots
+        int64_t len = e - s;
+        int64_t maxlen = len;
+        for (int o = 32; o > 0; o >>= 1) {
+            int64_t y = __shfl_xor(maxlen, o, 64);
+            maxlen = y > maxlen ? y : maxlen;
+        }
+        for (int64_t i = 0; i < maxlen; i += G) {
+            const int64_t j = s + i + gl;
+            const bool occ = rowok && i + gl < len && tkey[j] >= 0;
+            const uint64_t m = __ballot(occ);
+            const uint32_t gm = (uint32_t)((m >> gshift) & 0xFFu);
+            if (occ) {
+                const int pos = __popc(gm & ((1u << gl) - 1u));
+                cadj[out + pos] = tkey[j];
+                cew[out + pos] = tval[j];
+            }
+            out += __popc(gm);
+        }
+    }
+}
+
+__global__ __launch_bounds__(CB) void k_double(const int32_t *b, int32_t *b2, int m)
+{
+    for (int i = blockIdx.x * CB + threadIdx.x; i < m; i += gridDim.x * CB) b2[i] = 2 * b[i];
+}
+
+__global__ __launch_bounds__(CB) void k_project(int n, const int32_t *map, const int32_t *pc, int32_t *pf)
+{
+    for (int v = blockIdx.x * CB + threadIdx.x; v < n; v += gridDim.x * CB) pf[v] = pc[map[v]];
+}
+
+// Seeded uniform random part per vertex: floor(stream(seed, v) * k / 2^64).
+__global__ __launch_bounds__(CB) void k_random_part(int n, int k, uint64_t seed, int32_t *p)
+{
+    for (int v = blockIdx.x * CB + threadIdx.x; v < n; v += gridDim.x * CB)
+        p[v] = (int32_t)__umul64hi(stream64(seed, (uint64_t)v), (uint64_t)k);
+}
+
+// ----------------------------------------------------------------- host ---
+
+#define JET_TRY(expr)                                      \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return hip_status(ctx, e_);  \
+    } while (0)
+
+static int grid_for(const jet_context *ctx, int64_t items, int per_block, int cap_mult = 8)
+{
+    int64_t b = (items + per_block - 1) / per_block;
+    b = std::max<int64_t>(1, std::min<int64_t>(b, (int64_t)ctx->num_cu * cap_mult));
+    return (int)b;
+}
+
+// Cheap checks every entry point runs before kernels index through the graph.
+int check_graph(jet_context *ctx, const jet_csr *g, uint32_t flags, hipStream_t s)
+{
+    if (g->n < 0 || g->nnz < 0) return JET_EGRAPH;
+    if (g->n == 0) return JET_OK;
+    if (!g->xadj || (g->nnz > 0 && !g->adjncy)) return JET_EINVAL;
+    if (flags & JET_F_VALIDATE) {
+        int st = validate_full_csr(ctx, g, s);
+        if (st) return st;
+    }
+    CState *st = (CState *)ws_get(ctx, WS_H1, sizeof(CState));
+    if (!st) return JET_ENOMEM;
+    JET_TRY(hipMemsetAsync(st, 0, sizeof(CState), s));
+    int64_t *ends = (int64_t *)((char *)ctx->pinned + 2048);
+    JET_TRY(hipMemcpyAsync(ends, g->xadj, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    JET_TRY(hipMemcpyAsync(ends + 1, g->xadj + g->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    JET_TRY(hipStreamSynchronize(s));
+    if (ends[0] != 0 || ends[1] != g->nnz) return JET_EGRAPH;
+    k_chk_vertices<<<grid_for(ctx, g->n, CB, 4), CB, 0, s>>>(g->n, g->xadj, g->vwgt, st);
+    if (g->nnz > 0)
+        k_chk_edges<<<grid_for(ctx, (g->nnz + 15) / 16, CB), CB, 0, s>>>(g->n, g->nnz, g->xadj, g->adjncy, g->adjwgt, st);
+    JET_TRY(hipGetLastError());
+    CState *h = (CState *)((char *)ctx->pinned + 2304);
+    JET_TRY(hipMemcpyAsync(h, st, sizeof(CState), hipMemcpyDeviceToHost, s));
+    JET_TRY(hipStreamSynchronize(s));
+    if (h->bad) return JET_EGRAPH;
+    if (h->wsum >= ((int64_t)1 << 31) || h->ewsum >= ((int64_t)1 << 31)) return JET_EOVERFLOW;
+    return JET_OK;
+}
+
+static void *hier_alloc(jet_hierarchy *h, size_t bytes)
+{
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    h->owned.push_back(p);
+    return p;
+}
+
+static void hier_release(jet_hierarchy *h)
+{
+    for (void *p : h->owned) (void)hipFree(p);
+    h->owned.clear();
+}
+
+// One coarsening step of level graph f into c (device buffers owned by h).
+// Returns the coarse vertex count in *nc_out (== f->n when nothing matched).
+static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, int level, uint64_t seed,
+                         jet_csr *c, int32_t **map_out, int *nc_out, hipStream_t s)
+{
+    const int n = f->n;
+    const int64_t nnz = f->nnz;
+    const size_t nn = (size_t)std::max(n, 1);
+    int32_t *match = (int32_t *)ws_get(ctx, WS_C0, nn * 4);
+    int32_t *prop = (int32_t *)ws_get(ctx, WS_C1, nn * 4);
+    int32_t *big = (int32_t *)ws_get(ctx, WS_C2, nn * 4);
+    int64_t *cid = (int64_t *)ws_get(ctx, WS_C3, (nn + 1) * 8);
+    int64_t *tsum = (int64_t *)ws_get(ctx, WS_C4, ((nn + SCAN_TILE - 1) / SCAN_TILE + 2) * 8);
+    CState *st = (CState *)ws_get(ctx, WS_H1, sizeof(CState) + 16);
+    int32_t *nbig = (int32_t *)(st + 1);
+    if (!match || !prop || !big || !cid || !tsum || !st) return JET_ENOMEM;
+    JET_TRY(hipMemsetAsync(match, 0xFF, nn * 4, s));
+    JET_TRY(hipMemsetAsync(st, 0, sizeof(CState) + 16, s));
+    const int gv = grid_for(ctx, n, CB, 4);
+    k_big_list<<<gv, CB, 0, s>>>(n, f->xadj, big, nbig);
+    int32_t *hbig = (int32_t *)((char *)ctx->pinned + 2400);
+    JET_TRY(hipMemcpyAsync(hbig, nbig, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    JET_TRY(hipStreamSynchronize(s));
+    const int nb = *hbig;
+    const uint64_t hseed = stream64(seed, (uint64_t)(uint32_t)level);
+    const int gp = grid_for(ctx, n, CB / 8);
+    for (int round = 0; round < 16; round++) {
+        k_hem_propose<<<gp, CB, 0, s>>>(n, f->xadj, f->adjncy, f->adjwgt, match, prop, hseed, st);
+        if (nb > 0)
+            k_hem_propose_big<<<std::min(nb, ctx->num_cu * 8), CB, 0, s>>>(big, nb, f->xadj, f->adjncy, f->adjwgt,
+                                                                           match, prop, hseed, st);
+        k_hem_match<<<gv, CB, 0, s>>>(n, match, prop, st);
+        k_hem_round_end<<<1, 1, 0, s>>>(n, st);
+    }
+    // coarse ids: leaders numbered in vertex order
+    int32_t *flag = prop;  // proposals are no longer needed
+    k_leader_flags<<<gv, CB, 0, s>>>(n, match, flag);
+    scan_excl(flag, n, cid, tsum, s);
+    int64_t *hn = (int64_t *)((char *)ctx->pinned + 2432);
+    JET_TRY(hipMemcpyAsync(hn, cid + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    JET_TRY(hipStreamSynchronize(s));
+    const int nc = (int)*hn;
+    *nc_out = nc;
+    if (nc == n) return JET_OK;
+    const size_t ncc = (size_t)std::max(nc, 1);
+    int32_t *map = (int32_t *)hier_alloc(h, nn * 4);
+    int32_t *cvw = (int32_t *)hier_alloc(h, ncc * 4);
+    int32_t *bound = (int32_t *)ws_get(ctx, WS_C5, ncc * 4);
+    int64_t *toff = (int64_t *)ws_get(ctx, WS_C6, (ncc + 1) * 8);
+    int32_t *ccount = (int32_t *)ws_get(ctx, WS_C7, ncc * 4);
+    int64_t *cxadj = (int64_t *)hier_alloc(h, (ncc + 1) * 8);
+    if (!map || !cvw || !bound || !toff || !ccount || !cxadj) return JET_ENOMEM;
+    k_coarse_map<<<gv, CB, 0, s>>>(n, match, cid, f->xadj, f->vwgt, map, cvw, bound);
+    // table offsets: exclusive scan of 2 * bound (bounds summed <= nnz)
+    int32_t *bound2 = ccount;
+    k_double<<<grid_for(ctx, nc, CB, 4), CB, 0, s>>>(bound, bound2, nc);
+    scan_excl(bound2, nc, toff, tsum, s);
+    const size_t tsize = (size_t)std::max<int64_t>(2 * nnz, 1);
+    int32_t *tkey = (int32_t *)ws_get(ctx, WS_C8, tsize * 4);
+    int32_t *tval = (int32_t *)ws_get(ctx, WS_C9, tsize * 4);
+    if (!tkey || !tval) return JET_ENOMEM;
+    JET_TRY(hipMemsetAsync(tkey, 0xFF, tsize * 4, s));
+    JET_TRY(hipMemsetAsync(tval, 0, tsize * 4, s));
+    JET_TRY(hipMemsetAsync(ccount, 0, ncc * 4, s));
+    if (nnz > 0)
+        k_contract_insert<<<grid_for(ctx, (nnz + 15) / 16, CB), CB, 0, s>>>(n, nnz, f->xadj, f->adjncy, f->adjwgt, map,
+                                                                          toff, tkey, tval, ccount);
+    scan_excl(ccount, nc, cxadj, tsum, s);
+    JET_TRY(hipMemcpyAsync(hn, cxadj + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    JET_TRY(hipStreamSynchronize(s));
+    const int64_t cnnz = *hn;
+    int32_t *cadj = (int32_t *)hier_alloc(h, (size_t)std::max<int64_t>(cnnz, 1) * 4);
+    int32_t *cew = (int32_t *)hier_alloc(h, (size_t)std::max<int64_t>(cnnz, 1) * 4);
+    if (!cadj || !cew) return JET_ENOMEM;
+    k_contract_extract<<<grid_for(ctx, nc, CB / 8), CB, 0, s>>>(nc, toff, tkey, tval, cxadj, cadj, cew);
+    JET_TRY(hipGetLastError());
+    c->n = nc;
+    c->reserved = 0;
+    c->nnz = cnnz;
+    c->xadj = cxadj;
+    c->adjncy = cadj;
+    c->vwgt = cvw;
+    c->adjwgt = cew;
+    *map_out = map;
+    return JET_OK;
+}
+
+static int build_hierarchy(jet_context *ctx, const jet_csr *g, const jet_params *prm, jet_hierarchy *h,
+                           hipStream_t s)
+{
+    h->device = ctx->device;
+    h->lv.clear();
+    h->maps.clear();
+    h->lv.push_back(*g);
+    const int64_t target = 8 * (int64_t)prm->k;
+    while ((int)h->lv.size() < 64 && h->lv.back().n > target) {
+        jet_csr f = h->lv.back();
+        jet_csr c;
+        int32_t *map = nullptr;
+        int nc = 0;
+        int st = coarsen_level(ctx, h, &f, (int)h->lv.size() - 1, prm->seed, &c, &map, &nc, s);
+        if (st) return st;
+        if (nc == f.n) break;
+        h->maps.push_back(map);
+        h->lv.push_back(c);
+        if (10 * (int64_t)nc > 9 * (int64_t)f.n) break;
+    }
+    h->maps.push_back(nullptr);
+    h->nlevels = (int)h->lv.size();
+    return JET_OK;
+}
+
+}  // namespace jet
+
+using namespace jet;
+
+extern "C" int jet_coarsen(jet_context *ctx, const jet_csr *g, const jet_params *params, jet_hierarchy **out,
+                           void *stream)
+{
+    if (!ctx || !g || !params || !out) return JET_EINVAL;
+    *out = nullptr;
+    if (params->k < 1) return JET_EINVAL;
+    if (params->k > KMAX) return JET_ELIMIT;
+    hipStream_t s = (hipStream_t)stream;
+    JET_TRY(hipSetDevice(ctx->device));
+    int st = check_graph(ctx, g, params->flags, s);
+    if (st) return st;
+    jet_hierarchy *h = new (std::nothrow) jet_hierarchy();
+    if (!h) return JET_ENOMEM;
+    JET_TRY(hipEventRecord(ctx->ev[0], s));
+    st = build_hierarchy(ctx, g, params, h, s);
+    if (st) { hier_release(h); delete h; return st; }
+    JET_TRY(hipEventRecord(ctx->ev[1], s));
+    JET_TRY(hipStreamSynchronize(s));
+    (void)hipEventElapsedTime(&h->ms_coarsen, ctx->ev[0], ctx->ev[1]);
+    *out = h;
+    return JET_OK;
+}
+
+extern "C" int jet_hierarchy_levels(const jet_hierarchy *h) { return h ? h->nlevels : 0; }
+
+extern "C" int jet_hierarchy_level(const jet_hierarchy *h, int level, jet_csr *view, const int32_t **map)
+{
+    if (!h || !view || level < 0 || level >= h->nlevels) return JET_EINVAL;
+    *view = h->lv[level];
+    if (map) *map = h->maps[level];
+    return JET_OK;
+}
+
+extern "C" void jet_hierarchy_free(jet_hierarchy *h)
+{
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    hier_release(h);
+    delete h;
+}
+
+extern "C" int jet_partition(jet_context *ctx, const jet_csr *g, const jet_params *params, int32_t *part_out,
+                             jet_stats *stats, jet_trace *trace, void *stream)
+{
+    if (!ctx || !g || !params || (!part_out && g->n > 0)) return JET_EINVAL;
+    if (params->k < 1 || params->lambda_ppm < 0) return JET_EINVAL;
+    if (params->k > KMAX) return JET_ELIMIT;
+    hipStream_t s = (hipStream_t)stream;
+    JET_TRY(hipSetDevice(ctx->device));
+    int st = check_graph(ctx, g, params->flags, s);
+    if (st) return st;
+    if (trace) { trace->count = 0; trace->total = 0; }
+    hipEvent_t e0, e1, e2;
+    JET_TRY(hipEventCreate(&e0));
+    JET_TRY(hipEventCreate(&e1));
+    JET_TRY(hipEventCreate(&e2));
+    JET_TRY(hipEventRecord(e0, s));
+    jet_hierarchy h;
+    st = build_hierarchy(ctx, g, params, &h, s);
+    JET_TRY(hipEventRecord(e1, s));
+    int levels = h.nlevels;
+    jet_stats agg;
+    memset(&agg, 0, sizeof(agg));
+    if (st == JET_OK && g->n > 0) {
+        // seeded random partition of the coarsest graph, then refine upward
+        const int l = levels - 1;
+        const int nmax = g->n;
+        int32_t *pa = (int32_t *)ws_get(ctx, WS_C10, (size_t)nmax * 4);
+        int32_t *pb = (int32_t *)ws_get(ctx, WS_C11, (size_t)nmax * 4);
+        if (!pa || !pb) st = JET_ENOMEM;
+        if (st == JET_OK) {
+            k_random_part<<<grid_for(ctx, h.lv[l].n, CB, 4), CB, 0, s>>>(h.lv[l].n, params->k,
+                                                                         mix64(params->seed ^ 1ULL), pa);
+            int32_t *cur = pa, *other = pb;
+            for (int i = l; i >= 0 && st == JET_OK; i--) {
+                if (i < l) {
+                    int32_t *dst = i == 0 ? part_out : other;
+                    k_project<<<grid_for(ctx, h.lv[i].n, CB, 4), CB, 0, s>>>(h.lv[i].n, h.maps[i], cur, dst);
+                    other = cur;
+                    cur = dst;
+                } else if (i == 0) {
+                    JET_TRY(hipMemcpyAsync(part_out, cur, sizeof(int32_t) * g->n, hipMemcpyDeviceToDevice, s));
+                    cur = part_out;
+                }
+                jet_params q = *params;
+                q.level = i;
+                q.flags &= ~(uint32_t)JET_F_VALIDATE;
+                jet_stats ls;
+                int32_t cnt = 0, tot = 0;
+                jet_trace_rec *recs = nullptr;
+                int32_t cap = 0;
+                if (trace && trace->recs && trace->count < trace->cap) {
+                    recs = trace->recs + trace->count;
+                    cap = trace->cap - trace->count;
+                }
+                st = refine_level(ctx, &h.lv[i], &q, cur, nullptr, &ls, recs, cap, &cnt, &tot, s);
+                if (st) break;
+                if (trace) { trace->count += cnt; trace->total += tot; }
+                agg.iters += ls.iters;
+                agg.lp_iters += ls.lp_iters;
+                agg.rw_iters += ls.rw_iters;
+                agg.rs_iters += ls.rs_iters;
+                agg.ms_refine += ls.ms_refine;
+                agg.ms_init += ls.ms_init;
+                if (i == 0) {
+                    agg.ms_gain = ls.ms_gain;
+                    agg.gain_passes = ls.gain_passes;
+                    agg.gain_entries = ls.gain_entries;
+                    agg.gain_rows = ls.gain_rows;
+                    agg.gain_vertices = ls.gain_vertices;
+                    agg.cut = ls.cut;
+                    agg.max_part_weight = ls.max_part_weight;
+                    agg.o = ls.o;
+                    agg.sigma = ls.sigma;
+                    agg.total_weight = ls.total_weight;
+                    agg.balanced = ls.balanced;
+                }
+            }
+        }
+    }
+    if (st == JET_OK) {
+        JET_TRY(hipEventRecord(e2, s));
+        JET_TRY(hipStreamSynchronize(s));
+    }
+    float ms_c = 0, ms_t = 0;
+    if (st == JET_OK) {
+        (void)hipEventElapsedTime(&ms_c, e0, e1);
+        (void)hipEventElapsedTime(&ms_t, e0, e2);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    hier_release(&h);
+    if (st) return st;
+    if (stats) {
+        *stats = agg;
+        stats->levels = levels;
+        stats->ms_coarsen = ms_c;
+        stats->ms_total = ms_t;
+    }
+    return JET_OK;
 }

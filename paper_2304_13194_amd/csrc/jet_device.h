@@ -18,12 +18,16 @@ __host__ __device__ __forceinline__ uint64_t stream64(uint64_t seed, uint64_t i)
     return mix64(seed + (i + 1) * 0x9E3779B97F4A7C15ULL);
 }
 
-// Order LDS traffic of this wave: earlier LDS ops complete before later ones
-// are issued, and the compiler may not move LDS ops across this point.
+// Order this wave's LDS traffic across lanes. The LDS executes a wave's DS
+// instructions in issue order, so it is enough to keep the compiler from
+// moving LDS operations across this point and to let earlier LDS operations
+// retire (lgkmcnt(0)); outstanding global loads are not waited for.
 __device__ __forceinline__ void lds_fence_wave()
 {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __asm__ __volatile__("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt(63) expcnt(7) lgkmcnt(0)
     __builtin_amdgcn_wave_barrier();
+    __asm__ __volatile__("" ::: "memory");
 }
 
 template <int G>

@@ -14,6 +14,13 @@ constexpr int NSLOT = 33;   // loss slots 0..32: losses are int32 (|loss| <= wei
 constexpr int KMAX = 16384; // part-count limit (dense LDS tables of int32)
 constexpr int BLOCK = 256;  // threads per block of the row kernels
 constexpr int TILE = 2048;  // vertices per tile of the ordered-selection kernels (one wave each)
+// Per-block partial counters: slot 0 |X| (Jetlp) or eligible count (rebalancing),
+// 1 |M|, 2 cut change, 3 moved weight, 4 digest change.
+// Profiling counters of the gain pass: 5 CSR entries of unlocked rows, 6 unlocked
+// rows, 7 visited vertices.
+enum Stat { ST_X = 0, ST_M = 1, ST_DCUT = 2, ST_MW = 3, ST_DIG = 4, ST_E = 5, ST_R = 6, ST_V = 7, NSTAT = 8 };
+constexpr int KIND_LOG = 1 << 16;  // iterations whose kind is logged
+constexpr int BSTAT_STRIDE = 16384;  // >= any row-kernel grid
 
 enum Kind { KIND_DONE = 0, KIND_LP = 1, KIND_RW = 2, KIND_RS = 3 };
 // Degree classes: 0 isolated, 1 small (<= 32), 2 medium (<= 1024), 3 large.
@@ -36,14 +43,14 @@ struct Ctl {
     int32_t n_rw, n_rs, err, pad0;
     int64_t cut, cut_best, maxw, maxw_best;
     uint64_t digest;
-    // per-iteration accumulators (cleared at the start of each iteration)
-    int32_t ncand, pad1;
-    int32_t xcnt[NCLS], mcnt[NCLS];
+    // per-iteration results (reduced from per-block partials)
+    int32_t nX, nM;
     int64_t dcut, moved_w;
     uint64_t ddigest;
     int64_t total_cap;
     // set-up accumulators
     int64_t wsum, ewsum;
+    int64_t prof_e, prof_r, prof_v;  // gain-pass counters summed over Jetlp iterations
     int32_t bincnt[NCLS];
     int32_t bad_graph, bad_part;
 };
@@ -63,10 +70,10 @@ struct KArgs {
     uint8_t *slot;   // rebalancing loss slot, 255 = not a candidate
     int32_t *rbd;    // Jetrw destination of each candidate
     uint8_t *rsev;   // Jetrs: evicted flag
-    const int32_t *bins;
-    int32_t *xl;     // X lists, per class region
-    int32_t *ml;     // move lists, per class region
+    const int32_t *bins;   // vertex ids grouped by degree class
     int32_t binoff[NCLS + 1];
+    int64_t *bstat;  // per-block partial counters [NSTAT][BSTAT_STRIDE], summed by the controller
+    int32_t grid_tab, grid_rbtab, grid_plain;
     Ctl *ctl;
     int64_t *w, *wbest, *resid, *capstart, *hist;
     int32_t *Blist, *sstar, *splitidx;
@@ -75,6 +82,7 @@ struct KArgs {
     int64_t *esum;
     int32_t ntile;
     jet_trace_rec *trace;
+    int8_t *kinds;   // kind of iteration t (t < KIND_LOG)
     // block counts per role of the row kernels
     int32_t gS, gM, gL, gZ;
     // which role (1 S, 2 M, 3 L) serves each class in the LDS-table kernels
@@ -101,14 +109,16 @@ struct jet_context {
     void *pinned = nullptr;  // host staging for small read-backs
     size_t pinned_bytes = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> prof_ev;  // pairs around gain passes (JET_F_PROFILE)
 };
 
 namespace jet {
 
 enum WsSlot {
-    WS_P, WS_REC, WS_DEST, WS_LOCK, WS_SLOT, WS_RBD, WS_RSEV, WS_BIN, WS_XL, WS_ML,
+    WS_P, WS_REC, WS_DEST, WS_LOCK, WS_SLOT, WS_RBD, WS_RSEV, WS_BIN, WS_BSTAT, WS_FILL,
     WS_CTL, WS_PART64, WS_PART32, WS_PART8, WS_HIST, WS_TSUM, WS_ESUM, WS_TRACE,
-    WS_DBG_LOCK, WS_H0, WS_COUNT = 64
+    WS_DBG_LOCK, WS_H0, WS_H1, WS_C0, WS_C1, WS_C2, WS_C3, WS_C4, WS_C5, WS_C6, WS_C7, WS_C8,
+    WS_C9, WS_C10, WS_C11, WS_KINDS, WS_COUNT = 64
 };
 
 // Grow-only workspace slot; returns nullptr on allocation failure.

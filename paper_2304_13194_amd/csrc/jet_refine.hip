@@ -192,8 +192,7 @@ __device__ void rb_prepare(const KArgs &a)
 
 __device__ __forceinline__ void clear_accumulators(Ctl *c)
 {
-    c->ncand = 0;
-    for (int i = 0; i < NCLS; i++) { c->xcnt[i] = 0; c->mcnt[i] = 0; }
+    c->nX = 0; c->nM = 0;
     c->dcut = 0; c->moved_w = 0; c->ddigest = 0;
 }
 
@@ -261,19 +260,50 @@ __global__ __launch_bounds__(BLOCK) void k_lp_outputs(KArgs a, uint8_t *inX, uin
 __global__ __launch_bounds__(BLOCK) void k_ctl_end(KArgs a)
 {
     __shared__ uint64_t s_red[BLOCK / 64];
+    __shared__ int64_t s_red64[BLOCK / 64];
     __shared__ int s_improved;
     Ctl *c = a.ctl;
-    if (c->kind == KIND_DONE) return;
+    const int kind = c->kind;
+    if (kind == KIND_DONE) return;
     uint64_t m = 0;
     for (int p = threadIdx.x; p < a.k; p += BLOCK) {
         uint64_t x = (uint64_t)a.w[p];
         m = x > m ? x : m;
     }
     m = block_max_u64<BLOCK>(m, s_red);
+    // per-block partials of this iteration's kernels
+    int64_t px = 0, pm = 0, pdc = 0, pmw = 0;
+    uint64_t pdg = 0;
+    const int gx = kind == KIND_LP ? a.grid_tab : a.grid_rbtab;
+    for (int i = threadIdx.x; i < gx; i += BLOCK) px += a.bstat[ST_X * BSTAT_STRIDE + i];
+    for (int i = threadIdx.x; i < a.grid_plain; i += BLOCK) {
+        pm += a.bstat[ST_M * BSTAT_STRIDE + i];
+        pdc += a.bstat[ST_DCUT * BSTAT_STRIDE + i];
+        pmw += a.bstat[ST_MW * BSTAT_STRIDE + i];
+        pdg += (uint64_t)a.bstat[ST_DIG * BSTAT_STRIDE + i];
+    }
+    int64_t pe = 0, pr = 0, pv = 0;
+    if (kind == KIND_LP)
+        for (int i = threadIdx.x; i < a.grid_tab; i += BLOCK) {
+            pe += a.bstat[ST_E * BSTAT_STRIDE + i];
+            pr += a.bstat[ST_R * BSTAT_STRIDE + i];
+            pv += a.bstat[ST_V * BSTAT_STRIDE + i];
+        }
+    pe = block_sum<BLOCK>(pe, s_red64);
+    pr = block_sum<BLOCK>(pr, s_red64);
+    pv = block_sum<BLOCK>(pv, s_red64);
+    px = block_sum<BLOCK>(px, s_red64);
+    pm = block_sum<BLOCK>(pm, s_red64);
+    pdc = block_sum<BLOCK>(pdc, s_red64);
+    pmw = block_sum<BLOCK>(pmw, s_red64);
+    pdg = block_sum<BLOCK>(pdg, s_red);
     if (threadIdx.x == 0) {
         const int64_t maxw = (int64_t)m;
-        int nM = 0, nXl = 0;
-        for (int i = 0; i < NCLS; i++) { nM += c->mcnt[i]; nXl += c->xcnt[i]; }
+        const int nM = (int)pm, nXl = (int)px;
+        c->nX = nXl; c->nM = nM;
+        c->dcut = pdc; c->moved_w = pmw; c->ddigest = pdg;
+        c->prof_e += pe; c->prof_r += pr; c->prof_v += pv;
+        if (a.kinds && c->t < KIND_LOG) a.kinds[c->t] = (int8_t)kind;
         c->cut += c->dcut;
         c->digest += c->ddigest;
         c->maxw = maxw;
@@ -296,7 +326,7 @@ __global__ __launch_bounds__(BLOCK) void k_ctl_end(KArgs a)
         if (a.trace && c->t < c->trace_cap) {
             jet_trace_rec r;
             r.level = c->level; r.t = c->t; r.kind = c->kind;
-            r.nX = c->kind == KIND_LP ? nXl : c->ncand;
+            r.nX = nXl;
             r.nM = nM; r.stall = c->stall; r.wcount = c->wcount; r.balanced = bal;
             r.moved_w = c->moved_w; r.cut = c->cut; r.maxw = maxw; r.best_cut = c->cut_best;
             r.digest = c->digest;
@@ -376,7 +406,7 @@ __device__ __forceinline__ uint64_t conn_key(int c, int p)
 
 // Writes rec[v] and appends v to its class's X list when it passes the
 // first filter (eq. gainconn_filter).
-__device__ __forceinline__ bool gain_finish(const KArgs &a, int v, int ps, uint64_t best, int cs)
+__device__ __forceinline__ bool gain_finish(const KArgs &a, int v, int ps, uint64_t best, int cs, int cn, int cd)
 {
     int2 r;
     r.x = ps << 16;
@@ -387,7 +417,7 @@ __device__ __forceinline__ bool gain_finish(const KArgs &a, int v, int ps, uint6
     if (best) {
         pd = (int)(~(uint32_t)best);
         const int f = (int)(best >> 32) - cs;
-        const int64_t thr = ((int64_t)a.ctl->c_num * cs) / a.ctl->c_den;
+        const int64_t thr = ((int64_t)cn * cs) / cd;
         inx = f >= 0 || -(int64_t)f < thr;
         r.y = f;
         F = f;
@@ -408,45 +438,46 @@ __device__ __forceinline__ void gain_locked(const KArgs &a, int v, int ps)
     if (a.dbg_F) { a.dbg_F[v] = INT64_MIN; a.dbg_cs[v] = 0; a.dbg_pd[v] = ps; }
 }
 
+struct GainCount {
+    int nx = 0;
+    int64_t e = 0, r = 0, v = 0;
+};
+
 template <int G, int R>
-__device__ void gain_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ngroups, int lp_prev)
+__device__ void gain_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ngroups, int lp_prev, int cn, int cd,
+                            GainCount &gc)
 {
     const int gl = threadIdx.x & (G - 1);
     const int32_t *list = a.bins + a.binoff[cls];
     const int cnt = a.binoff[cls + 1] - a.binoff[cls];
-    const int nloop = (cnt + ngroups - 1) / ngroups;
-    for (int it = 0; it < nloop; it++) {
-        const int i = it * ngroups + gid;
-        bool inx = false;
-        int v = -1;
-        if (i < cnt) {
-            v = list[i];
-            const int ps = a.P[v];
-            if (a.lock[v] == lp_prev) {
-                if (gl == 0) gain_locked(a, v, ps);
-            } else {
-                int pu[R], cu[R];
-                group_conn<G, R>(a, v, gl, tab, pu, cu);
-                uint64_t best = 0;
-                int cs = 0;
+    for (int i = gid; i < cnt; i += ngroups) {
+        const int v = list[i];
+        const int ps = a.P[v];
+        if (gl == 0) gc.v++;
+        if (a.lock[v] == lp_prev) {
+            if (gl == 0) gain_locked(a, v, ps);
+            continue;
+        }
+        if (gl == 0) { gc.r++; gc.e += a.xadj[v + 1] - a.xadj[v]; }
+        int pu[R], cu[R];
+        group_conn<G, R>(a, v, gl, tab, pu, cu);
+        uint64_t best = 0;
+        int cs = 0;
 #pragma unroll
-                for (int r = 0; r < R; r++) {
-                    if (cu[r] > 0) {
-                        if (pu[r] == ps) cs += cu[r];
-                        else { uint64_t k2 = conn_key(cu[r], pu[r]); best = k2 > best ? k2 : best; }
-                    }
-                }
-                best = gmax_u64<G>(best);
-                cs = gsum<G>(cs);
-                if (gl == 0) inx = gain_finish(a, v, ps, best, cs);
+        for (int r = 0; r < R; r++) {
+            if (cu[r] > 0) {
+                if (pu[r] == ps) cs += cu[r];
+                else { uint64_t k2 = conn_key(cu[r], pu[r]); best = k2 > best ? k2 : best; }
             }
         }
-        // wave-uniform loop: every lane reaches the append
-        wave_append(inx, &a.ctl->xcnt[cls], a.xl + a.binoff[cls], v);
+        best = gmax_u64<G>(best);
+        cs = gsum<G>(cs);
+        if (gl == 0) gc.nx += gain_finish(a, v, ps, best, cs, cn, cd);
     }
 }
 
-__device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nblocks, int lp_prev)
+__device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nblocks, int lp_prev, int cn, int cd,
+                            GainCount &gc)
 {
     __shared__ uint64_t s_red[BLOCK / 64];
     __shared__ int32_t s_red32[BLOCK / 64];
@@ -455,10 +486,12 @@ __device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int 
     for (int i = bid; i < cnt; i += nblocks) {
         const int v = list[i];
         const int ps = a.P[v];
+        if (threadIdx.x == 0) gc.v++;
         if (a.lock[v] == lp_prev) {
             if (threadIdx.x == 0) gain_locked(a, v, ps);
             continue;
         }
+        if (threadIdx.x == 0) { gc.r++; gc.e += a.xadj[v + 1] - a.xadj[v]; }
         block_fill(a, v, tab);
         uint64_t best = 0;
         int cs = 0;
@@ -472,10 +505,7 @@ __device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int 
         }
         best = block_max_u64<BLOCK>(best, s_red);
         cs = block_sum<BLOCK>(cs, s_red32);
-        if (threadIdx.x == 0 && gain_finish(a, v, ps, best, cs)) {
-            int pos = atomicAdd(&a.ctl->xcnt[cls], 1);
-            a.xl[a.binoff[cls] + pos] = v;
-        }
+        if (threadIdx.x == 0) gc.nx += gain_finish(a, v, ps, best, cs, cn, cd);
     }
 }
 
@@ -483,37 +513,53 @@ __device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int 
 // mapped to the 8-lane role, the next gM blocks the wave role, the next gL
 // blocks the block role, and (rebalancing only) the last gZ blocks isolated
 // vertices.
-__global__ __launch_bounds__(BLOCK) void k_gain(KArgs a)
+// One kernel per role (8-lane groups, waves, blocks), so each keeps its own
+// register budget. Group tables are padded to k + 1 ints so the tables of
+// neighbouring groups start in different LDS banks. Block partials of |X|
+// land at offset `boff` of the counter row.
+template <int ROLE>
+__global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk, int boff)
 {
     if (a.ctl->kind != KIND_LP) return;
     extern __shared__ int32_t lds[];
+    __shared__ int32_t s_red32[BLOCK / 64];
     const int lp_prev = a.ctl->lp_id - 1;
-    int b = blockIdx.x;
-    if (b < a.gS) {
+    const int cn = a.ctl->c_num, cd = a.ctl->c_den;
+    const int stride = a.k + 1;
+    GainCount gc;
+    if (ROLE == 1) {
         const int ng = BLOCK / 8;
-        for (int i = threadIdx.x; i < ng * a.k; i += BLOCK) lds[i] = 0;
+        for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         __syncthreads();
-        int32_t *tab = lds + (threadIdx.x >> 3) * a.k;
+        int32_t *tab = lds + (threadIdx.x >> 3) * stride;
         for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 1) gain_groups<8, 4>(a, c, tab, b * ng + (threadIdx.x >> 3), a.gS * ng, lp_prev);
-        return;
-    }
-    b -= a.gS;
-    if (b < a.gM) {
+            if (a.tmap[c] == 1)
+                gain_groups<8, 4>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 3), nblk * ng, lp_prev, cn, cd, gc);
+    } else if (ROLE == 2) {
         const int ng = BLOCK / 64;
-        for (int i = threadIdx.x; i < ng * a.k; i += BLOCK) lds[i] = 0;
+        for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         __syncthreads();
-        int32_t *tab = lds + (threadIdx.x >> 6) * a.k;
+        int32_t *tab = lds + (threadIdx.x >> 6) * stride;
         for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 2) gain_groups<64, 16>(a, c, tab, b * ng + (threadIdx.x >> 6), a.gM * ng, lp_prev);
-        return;
-    }
-    b -= a.gM;
-    if (b < a.gL) {
+            if (a.tmap[c] == 2)
+                gain_groups<64, 16>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 6), nblk * ng, lp_prev, cn, cd, gc);
+    } else {
         for (int i = threadIdx.x; i < a.k; i += BLOCK) lds[i] = 0;
         __syncthreads();
         for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 3) gain_blocks(a, c, lds, b, a.gL, lp_prev);
+            if (a.tmap[c] == 3) gain_blocks(a, c, lds, blockIdx.x, nblk, lp_prev, cn, cd, gc);
+    }
+    __shared__ int64_t s_red64[BLOCK / 64];
+    const int nx = block_sum<BLOCK>(gc.nx, s_red32);
+    const int64_t e = block_sum<BLOCK>(gc.e, s_red64);
+    const int64_t r = block_sum<BLOCK>(gc.r, s_red64);
+    const int64_t v = block_sum<BLOCK>(gc.v, s_red64);
+    if (threadIdx.x == 0) {
+        const int j = boff + blockIdx.x;
+        a.bstat[ST_X * BSTAT_STRIDE + j] = nx;
+        a.bstat[ST_E * BSTAT_STRIDE + j] = e;
+        a.bstat[ST_R * BSTAT_STRIDE + j] = r;
+        a.bstat[ST_V * BSTAT_STRIDE + j] = v;
     }
 }
 
@@ -544,25 +590,19 @@ template <int G>
 __device__ void after_groups(const KArgs &a, int cls, int gid, int ngroups)
 {
     const int gl = threadIdx.x & (G - 1);
-    const int32_t *list = a.xl + a.binoff[cls];
-    const int cnt = a.ctl->xcnt[cls];
-    const int nloop = (cnt + ngroups - 1) / ngroups;
-    for (int it = 0; it < nloop; it++) {
-        const int i = it * ngroups + gid;
-        bool mv = false;
-        int v = -1;
-        if (i < cnt) {
-            v = list[i];
-            const int2 r = a.rec[v];
-            const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
-            int sum = after_sum<G>(a, v, ps, pd, r.y, gl, G);
-            sum = gsum<G>(sum);
-            if (gl == 0) {
-                if (a.dbg_F2) a.dbg_F2[v] = sum;
-                if (sum >= 0) { mv = true; a.dest[v] = pd; }
-            }
+    const int32_t *list = a.bins + a.binoff[cls];
+    const int cnt = a.binoff[cls + 1] - a.binoff[cls];
+    for (int i = gid; i < cnt; i += ngroups) {
+        const int v = list[i];
+        const int2 r = a.rec[v];
+        if ((r.x & 0xFFFF) == 0) continue;  // not in X
+        const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
+        int sum = after_sum<G>(a, v, ps, pd, r.y, gl, G);
+        sum = gsum<G>(sum);
+        if (gl == 0) {
+            if (a.dbg_F2) a.dbg_F2[v] = sum;
+            if (sum >= 0) a.dest[v] = pd;
         }
-        wave_append(mv, &a.ctl->mcnt[cls], a.ml + a.binoff[cls], v);
     }
 }
 
@@ -576,21 +616,18 @@ __global__ __launch_bounds__(BLOCK) void k_afterburner(KArgs a)
     if (b < a.gM) { after_groups<64>(a, CLS_M, b * (BLOCK / 64) + (threadIdx.x >> 6), a.gM * (BLOCK / 64)); return; }
     b -= a.gM;
     if (b >= a.gL) return;
-    const int32_t *list = a.xl + a.binoff[CLS_L];
-    const int cnt = a.ctl->xcnt[CLS_L];
+    const int32_t *list = a.bins + a.binoff[CLS_L];
+    const int cnt = a.binoff[CLS_L + 1] - a.binoff[CLS_L];
     for (int i = b; i < cnt; i += a.gL) {
         const int v = list[i];
         const int2 r = a.rec[v];
+        if ((r.x & 0xFFFF) == 0) continue;
         const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
         int sum = after_sum<BLOCK>(a, v, ps, pd, r.y, threadIdx.x, BLOCK);
         sum = block_sum<BLOCK>(sum, s_red);
         if (threadIdx.x == 0) {
             if (a.dbg_F2) a.dbg_F2[v] = sum;
-            if (sum >= 0) {
-                a.dest[v] = pd;
-                int pos = atomicAdd(&a.ctl->mcnt[CLS_L], 1);
-                a.ml[a.binoff[CLS_L] + pos] = v;
-            }
+            if (sum >= 0) a.dest[v] = pd;
         }
     }
 }
@@ -623,18 +660,22 @@ __device__ __forceinline__ void move_meta(const KArgs &a, int v, int ps, int pn,
 }
 
 template <int G>
-__device__ void dcut_groups(const KArgs &a, int cls, int gid, int ngroups, int64_t &dc, int64_t &mw, uint64_t &dg)
+__device__ void dcut_groups(const KArgs &a, int cls, int gid, int ngroups, int64_t &dc, int64_t &mw, uint64_t &dg,
+                            int64_t &nm)
 {
     const int gl = threadIdx.x & (G - 1);
-    const int32_t *list = a.ml + a.binoff[cls];
-    const int cnt = a.ctl->mcnt[cls];
+    const int32_t *list = a.bins + a.binoff[cls];
+    const int cnt = a.binoff[cls + 1] - a.binoff[cls];
     for (int i = gid; i < cnt; i += ngroups) {
         const int v = list[i];
-        const int ps = a.P[v], pn = a.dest[v];
+        const int pn = a.dest[v];
+        if (pn < 0) continue;
+        const int ps = a.P[v];
         int d = dcut_sum(a, v, ps, pn, gl, G);
         d = gsum<G>(d);
         if (gl == 0) {
             dc += d;
+            nm++;
             move_meta(a, v, ps, pn, mw, dg);
         }
     }
@@ -646,38 +687,45 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
     __shared__ uint64_t s_redu[BLOCK / 64];
     __shared__ int32_t s_red32[BLOCK / 64];
     if (a.ctl->kind == KIND_DONE) return;
-    int64_t dc = 0, mw = 0;
+    int64_t dc = 0, mw = 0, nm = 0;
     uint64_t dg = 0;
     int b = blockIdx.x;
     if (b < a.gS) {
-        dcut_groups<8>(a, CLS_S, b * (BLOCK / 8) + (threadIdx.x >> 3), a.gS * (BLOCK / 8), dc, mw, dg);
+        dcut_groups<8>(a, CLS_S, b * (BLOCK / 8) + (threadIdx.x >> 3), a.gS * (BLOCK / 8), dc, mw, dg, nm);
     } else if ((b -= a.gS) < a.gM) {
-        dcut_groups<64>(a, CLS_M, b * (BLOCK / 64) + (threadIdx.x >> 6), a.gM * (BLOCK / 64), dc, mw, dg);
+        dcut_groups<64>(a, CLS_M, b * (BLOCK / 64) + (threadIdx.x >> 6), a.gM * (BLOCK / 64), dc, mw, dg, nm);
     } else if ((b -= a.gM) < a.gL) {
-        const int32_t *list = a.ml + a.binoff[CLS_L];
-        const int cnt = a.ctl->mcnt[CLS_L];
+        const int32_t *list = a.bins + a.binoff[CLS_L];
+        const int cnt = a.binoff[CLS_L + 1] - a.binoff[CLS_L];
         for (int i = b; i < cnt; i += a.gL) {
             const int v = list[i];
-            const int ps = a.P[v], pn = a.dest[v];
+            const int pn = a.dest[v];
+            if (pn < 0) continue;
+            const int ps = a.P[v];
             int d = dcut_sum(a, v, ps, pn, threadIdx.x, BLOCK);
             d = block_sum<BLOCK>(d, s_red32);
-            if (threadIdx.x == 0) { dc += d; move_meta(a, v, ps, pn, mw, dg); }
+            if (threadIdx.x == 0) { dc += d; nm++; move_meta(a, v, ps, pn, mw, dg); }
         }
     } else if ((b -= a.gL) < a.gZ) {
-        const int32_t *list = a.ml + a.binoff[CLS_Z];
-        const int cnt = a.ctl->mcnt[CLS_Z];
+        const int32_t *list = a.bins + a.binoff[CLS_Z];
+        const int cnt = a.binoff[CLS_Z + 1] - a.binoff[CLS_Z];
         for (int i = b * BLOCK + threadIdx.x; i < cnt; i += a.gZ * BLOCK) {
             const int v = list[i];
-            move_meta(a, v, a.P[v], a.dest[v], mw, dg);
+            const int pn = a.dest[v];
+            if (pn < 0) continue;
+            nm++;
+            move_meta(a, v, a.P[v], pn, mw, dg);
         }
     }
     dc = block_sum<BLOCK>(dc, s_red);
     mw = block_sum<BLOCK>(mw, s_red);
+    nm = block_sum<BLOCK>(nm, s_red);
     dg = block_sum<BLOCK>(dg, s_redu);
-    if (threadIdx.x == 0 && (dc | mw | (int64_t)dg)) {
-        atomicAdd((unsigned long long *)&a.ctl->dcut, (unsigned long long)dc);
-        atomicAdd((unsigned long long *)&a.ctl->moved_w, (unsigned long long)mw);
-        atomicAdd((unsigned long long *)&a.ctl->ddigest, (unsigned long long)dg);
+    if (threadIdx.x == 0) {
+        a.bstat[ST_DCUT * BSTAT_STRIDE + blockIdx.x] = dc;
+        a.bstat[ST_MW * BSTAT_STRIDE + blockIdx.x] = mw;
+        a.bstat[ST_M * BSTAT_STRIDE + blockIdx.x] = nm;
+        a.bstat[ST_DIG * BSTAT_STRIDE + blockIdx.x] = (int64_t)dg;
     }
 }
 
@@ -688,19 +736,13 @@ __global__ __launch_bounds__(BLOCK) void k_apply(KArgs a)
     extern __shared__ int32_t s_dw[];  // [k] block-partial weight change
     const int kind = a.ctl->kind;
     if (kind == KIND_DONE) return;
-    int off[NCLS + 1];
-    off[0] = 0;
-    for (int c = 0; c < NCLS; c++) off[c + 1] = off[c] + a.ctl->mcnt[c];
-    const int total = off[NCLS];
-    if (total == 0) return;
     for (int p = threadIdx.x; p < a.k; p += BLOCK) s_dw[p] = 0;
     __syncthreads();
     const int lp_id = a.ctl->lp_id;
-    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < total; i += gridDim.x * BLOCK) {
-        int c = 0;
-        while (i >= off[c + 1]) c++;
-        const int v = a.ml[a.binoff[c] + (i - off[c])];
-        const int ps = a.P[v], pn = a.dest[v];
+    for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) {
+        const int pn = a.dest[v];
+        if (pn < 0) continue;
+        const int ps = a.P[v];
         const int vwv = a.vw ? a.vw[v] : 1;
         a.P[v] = pn;
         a.dest[v] = -1;
@@ -742,7 +784,6 @@ __device__ __forceinline__ void rb_finish(const KArgs &a, int v, int ps, int vwv
     }
     const int s = loss_slot(loss);
     a.slot[v] = (uint8_t)s;
-    atomicAdd((unsigned long long *)&a.hist[ps * NSLOT + s], (unsigned long long)(int64_t)vwv);
     ncand++;
     if (a.dbg_loss) { a.dbg_loss[v] = loss; a.dbg_slot[v] = s; a.dbg_pd[v] = d; }
 }
@@ -831,39 +872,42 @@ __device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nb
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a)
+template <int ROLE>
+__global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int boff)
 {
     extern __shared__ int32_t lds[];
     __shared__ int32_t s_red32[BLOCK / 64];
     const int kind = a.ctl->kind;
     if (kind != KIND_RW && kind != KIND_RS) return;
     const uint64_t hseed = mix64(a.ctl->seed ^ (((uint64_t)(uint32_t)a.ctl->level << 32) + (uint64_t)(uint32_t)a.ctl->t));
+    const int stride = a.k + 1;
     int ncand = 0;
-    int b = blockIdx.x;
-    if (b < a.gS) {
+    if (ROLE == 1) {
         const int ng = BLOCK / 8;
-        for (int i = threadIdx.x; i < ng * a.k; i += BLOCK) lds[i] = 0;
+        for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         __syncthreads();
-        int32_t *tab = lds + (threadIdx.x >> 3) * a.k;
+        int32_t *tab = lds + (threadIdx.x >> 3) * stride;
         for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 1) rb_groups<8, 4>(a, c, tab, b * ng + (threadIdx.x >> 3), a.gS * ng, kind, hseed, ncand);
-    } else if ((b -= a.gS) < a.gM) {
+            if (a.tmap[c] == 1)
+                rb_groups<8, 4>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 3), nblk * ng, kind, hseed, ncand);
+    } else if (ROLE == 2) {
         const int ng = BLOCK / 64;
-        for (int i = threadIdx.x; i < ng * a.k; i += BLOCK) lds[i] = 0;
+        for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         __syncthreads();
-        int32_t *tab = lds + (threadIdx.x >> 6) * a.k;
+        int32_t *tab = lds + (threadIdx.x >> 6) * stride;
         for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 2) rb_groups<64, 16>(a, c, tab, b * ng + (threadIdx.x >> 6), a.gM * ng, kind, hseed, ncand);
-    } else if ((b -= a.gM) < a.gL) {
+            if (a.tmap[c] == 2)
+                rb_groups<64, 16>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 6), nblk * ng, kind, hseed, ncand);
+    } else if (ROLE == 3) {
         for (int i = threadIdx.x; i < a.k; i += BLOCK) lds[i] = 0;
         __syncthreads();
         for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 3) rb_blocks(a, c, lds, b, a.gL, kind, hseed, ncand);
-    } else if ((b -= a.gL) < a.gZ) {
+            if (a.tmap[c] == 3) rb_blocks(a, c, lds, blockIdx.x, nblk, kind, hseed, ncand);
+    } else {
         // isolated vertices: no connectivity, loss 0, random destination (Jetrw)
         const int32_t *list = a.bins + a.binoff[CLS_Z];
         const int cnt = a.binoff[CLS_Z + 1] - a.binoff[CLS_Z];
-        for (int i = b * BLOCK + threadIdx.x; i < cnt; i += a.gZ * BLOCK) {
+        for (int i = blockIdx.x * BLOCK + threadIdx.x; i < cnt; i += nblk * BLOCK) {
             const int v = list[i];
             const int ps = a.P[v];
             const int vwv = a.vw ? a.vw[v] : 1;
@@ -874,11 +918,41 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a)
             }
             rb_finish(a, v, ps, vwv, kind, 0, 0, 0, 0, hseed, ncand);
         }
-    } else {
-        return;
     }
     ncand = block_sum<BLOCK>(ncand, s_red32);
-    if (threadIdx.x == 0 && ncand) atomicAdd(&a.ctl->ncand, ncand);
+    if (threadIdx.x == 0) a.bstat[ST_X * BSTAT_STRIDE + boff + blockIdx.x] = ncand;
+}
+
+// Per-(part, slot) weight histogram of the eligible vertices; one wave per
+// tile, accumulated in LDS when k * NSLOT int32 counters fit.
+__global__ __launch_bounds__(64) void k_rb_hist(KArgs a, int use_lds)
+{
+    extern __shared__ int32_t h[];
+    const int kind = a.ctl->kind;
+    if (kind != KIND_RW && kind != KIND_RS) return;
+    const int nh = a.k * NSLOT;
+    if (use_lds) {
+        for (int i = threadIdx.x; i < nh; i += 64) h[i] = 0;
+        lds_fence_wave();
+    }
+    for (int tile = blockIdx.x; tile < a.ntile; tile += gridDim.x) {
+        const int v0 = tile * TILE;
+        for (int ch = 0; ch < TILE; ch += 64) {
+            const int v = v0 + ch + threadIdx.x;
+            if (v >= a.n) break;
+            const int sl = a.slot[v];
+            if (sl == 255) continue;
+            const int idx = a.P[v] * NSLOT + sl;
+            const int vwv = a.vw ? a.vw[v] : 1;
+            if (use_lds) atomicAdd(&h[idx], vwv);
+            else atomicAdd((unsigned long long *)&a.hist[idx], (unsigned long long)(int64_t)vwv);
+        }
+    }
+    if (use_lds) {
+        lds_fence_wave();
+        for (int i = threadIdx.x; i < nh; i += 64)
+            if (h[i]) atomicAdd((unsigned long long *)&a.hist[i], (unsigned long long)(int64_t)h[i]);
+    }
 }
 
 // Per oversized part: cut-off slot s* (slots below it are evicted whole) and
@@ -985,12 +1059,6 @@ __global__ __launch_bounds__(BLOCK) void k_rb_tilescan(KArgs a)
     }
 }
 
-__device__ __forceinline__ int degree_class(const KArgs &a, int v)
-{
-    const int64_t d = a.xadj[v + 1] - a.xadj[v];
-    return d == 0 ? CLS_Z : (d <= S_MAXDEG ? CLS_S : (d <= M_MAXDEG ? CLS_M : CLS_L));
-}
-
 // Ordered eviction inside each tile (one wave): a candidate in a slot below
 // its part's cut-off is evicted; one in the cut-off slot is evicted when the
 // weight of earlier (smaller id) cut-off-slot vertices of its part is below
@@ -1038,9 +1106,6 @@ __global__ __launch_bounds__(64) void k_rb_select(KArgs a)
             }
             if (kind == KIND_RW) {
                 if (ev) a.dest[v] = a.rbd[v];
-                const int c = valid ? degree_class(a, v) : -1;
-#pragma unroll
-                for (int cc = 0; cc < NCLS; cc++) wave_append(ev && c == cc, &a.ctl->mcnt[cc], a.ml + a.binoff[cc], v);
             } else {
                 if (valid) a.rsev[v] = ev;
                 if (ev) esum += vwv;
@@ -1091,7 +1156,6 @@ __global__ __launch_bounds__(64) void k_rs_assign(KArgs a)
             const int64_t inc = wave_incl_scan(x);
             const int64_t pos = runpos + inc - x;
             runpos += __shfl(inc, 63, 64);
-            bool mv = false;
             if (ev && pos < total) {
                 int lo = 0, hi = nB;  // largest i with capstart[i] <= pos (capstart[0] = 0 <= pos)
                 while (hi - lo > 1) {
@@ -1099,11 +1163,7 @@ __global__ __launch_bounds__(64) void k_rs_assign(KArgs a)
                     if (a.capstart[mid] <= pos) lo = mid; else hi = mid;
                 }
                 a.dest[v] = a.Blist[lo];
-                mv = true;
             }
-            const int c = valid ? degree_class(a, v) : -1;
-#pragma unroll
-            for (int cc = 0; cc < NCLS; cc++) wave_append(mv && c == cc, &a.ctl->mcnt[cc], a.ml + a.binoff[cc], v);
         }
     }
 }
@@ -1160,6 +1220,8 @@ struct Plan {
     size_t lds_tab;
     int grid_flat;
     int grid_tile;
+    int grid_hist;
+    bool hist_lds;
 };
 
 static int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -1173,8 +1235,8 @@ static void plan_roles(const jet_context *ctx, KArgs &a, const int32_t *cnt, Pla
     KArgs t = a;
     t.tmap[0] = 0;
     const int k = a.k;
-    if (k <= 512) { t.tmap[1] = 1; t.tmap[2] = 2; t.tmap[3] = 3; }
-    else if (k <= 4096) { t.tmap[1] = 2; t.tmap[2] = 2; t.tmap[3] = 3; }
+    if (k <= 511) { t.tmap[1] = 1; t.tmap[2] = 2; t.tmap[3] = 3; }
+    else if (k <= 4095) { t.tmap[1] = 2; t.tmap[2] = 2; t.tmap[3] = 3; }
     else { t.tmap[1] = 3; t.tmap[2] = 3; t.tmap[3] = 3; }
     int64_t role_cnt[4] = {0, 0, 0, 0};
     for (int c = 1; c < NCLS; c++) role_cnt[t.tmap[c]] += cnt[c];
@@ -1197,23 +1259,53 @@ static void plan_roles(const jet_context *ctx, KArgs &a, const int32_t *cnt, Pla
     p.gL = std::min(cnt[3], maxb);
     p.gZ = std::min(div_up(cnt[0], BLOCK), maxb);
     pl.grid_plain = p.gS + p.gM + p.gL + p.gZ;
+    for (KArgs *x : {&t, &p}) {
+        x->grid_tab = pl.grid_tab;
+        x->grid_rbtab = pl.grid_rbtab;
+        x->grid_plain = pl.grid_plain;
+    }
     pl.tab = t;
     pl.plain = p;
+    pl.hist_lds = (size_t)a.k * NSLOT * 4 <= 65536;
+    pl.grid_hist = std::max(1, std::min(a.ntile, ctx->num_cu * 2));
     pl.grid_flat = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_tile = std::max(1, std::min(a.ntile, ctx->num_cu * 8));
 }
 
-static void launch_iteration(const Plan &pl, hipStream_t s, bool lp_kernels, bool rb_kernels)
+static void launch_gain(const Plan &pl, hipStream_t s)
+{
+    const KArgs &t = pl.tab;
+    const size_t st = (size_t)(t.k + 1) * 4;
+    if (t.gS) k_gain<1><<<t.gS, BLOCK, (BLOCK / 8) * st, s>>>(t, t.gS, 0);
+    if (t.gM) k_gain<2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM, t.gS);
+    if (t.gL) k_gain<3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL, t.gS + t.gM);
+}
+
+static void launch_rb_loss(const Plan &pl, hipStream_t s)
+{
+    const KArgs &t = pl.tab;
+    const size_t st = (size_t)(t.k + 1) * 4;
+    if (t.gS) k_rb_loss<1><<<t.gS, BLOCK, (BLOCK / 8) * st, s>>>(t, t.gS, 0);
+    if (t.gM) k_rb_loss<2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM, t.gS);
+    if (t.gL) k_rb_loss<3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL, t.gS + t.gM);
+    if (t.gZ) k_rb_loss<4><<<t.gZ, BLOCK, 0, s>>>(t, t.gZ, t.gS + t.gM + t.gL);
+}
+
+static void launch_iteration(const Plan &pl, hipStream_t s, bool lp_kernels, bool rb_kernels,
+                             hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr)
 {
     const KArgs &t = pl.tab;
     const KArgs &p = pl.plain;
     k_ctl_begin<<<1, BLOCK, 0, s>>>(p);
     if (lp_kernels) {
-        if (pl.grid_tab) k_gain<<<pl.grid_tab, BLOCK, pl.lds_tab, s>>>(t);
+        if (ev_a) (void)hipEventRecord(ev_a, s);
+        launch_gain(pl, s);
+        if (ev_b) (void)hipEventRecord(ev_b, s);
         if (pl.grid_plain) k_afterburner<<<pl.grid_plain, BLOCK, 0, s>>>(p);
     }
     if (rb_kernels) {
-        if (pl.grid_rbtab) k_rb_loss<<<pl.grid_rbtab, BLOCK, pl.lds_tab, s>>>(t);
+        launch_rb_loss(pl, s);
+        k_rb_hist<<<pl.grid_hist, 64, pl.hist_lds ? (size_t)p.k * NSLOT * 4 : 0, s>>>(p, pl.hist_lds);
         k_rb_cutoff<<<1, BLOCK, 0, s>>>(p);
         k_rb_tilesum<<<pl.grid_tile, 64, (size_t)p.k * 4, s>>>(p);
         k_rb_tilescan<<<std::min(p.k, 1024), BLOCK, 0, s>>>(p);
@@ -1232,12 +1324,17 @@ static void set_lds_limits()
     static bool done = false;
     if (done) return;
     done = true;
-    (void)hipFuncSetAttribute((const void *)k_gain, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-    (void)hipFuncSetAttribute((const void *)k_rb_loss, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_gain<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_gain<2>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_gain<3>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<2>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<3>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_apply, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_init_vertices, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_tilesum, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_select, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_hist, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
 }
 
 static int check_params(const jet_csr *g, const jet_params *prm)
@@ -1257,7 +1354,7 @@ static int check_params(const jet_csr *g, const jet_params *prm)
 
 // Host-side full CSR check (JET_F_VALIDATE): symmetric with equal weights,
 // no duplicates, no self-loops, ids in range.
-static int validate_full(jet_context *ctx, const jet_csr *g, hipStream_t s)
+int validate_full_csr(jet_context *ctx, const jet_csr *g, hipStream_t s)
 {
     const int n = g->n;
     const int64_t nnz = g->nnz;
@@ -1301,7 +1398,7 @@ static int setup(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     const int n = g->n, k = prm->k;
     set_lds_limits();
     if (prm->flags & JET_F_VALIDATE) {
-        int st = validate_full(ctx, g, s);
+        int st = validate_full_csr(ctx, g, s);
         if (st) return st;
     }
     KArgs a;
@@ -1318,8 +1415,8 @@ static int setup(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     a.rsev = (uint8_t *)ws_get(ctx, WS_RSEV, nn);
     int32_t *bins = (int32_t *)ws_get(ctx, WS_BIN, nn * 4);
     a.bins = bins;
-    a.xl = (int32_t *)ws_get(ctx, WS_XL, nn * 4);
-    a.ml = (int32_t *)ws_get(ctx, WS_ML, nn * 4);
+    a.bstat = (int64_t *)ws_get(ctx, WS_BSTAT, sizeof(int64_t) * NSTAT * BSTAT_STRIDE);
+    int32_t *fill = (int32_t *)ws_get(ctx, WS_FILL, sizeof(int32_t) * NCLS);
     a.ctl = (Ctl *)ws_get(ctx, WS_CTL, sizeof(Ctl) + 64);
     int64_t *p64 = (int64_t *)ws_get(ctx, WS_PART64, sizeof(int64_t) * (4 * (size_t)k + 8));
     int32_t *p32 = (int32_t *)ws_get(ctx, WS_PART32, sizeof(int32_t) * (3 * (size_t)k + 8));
@@ -1328,8 +1425,9 @@ static int setup(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     a.ntile = std::max(1, div_up(n, TILE));
     a.tsum = (int32_t *)ws_get(ctx, WS_TSUM, sizeof(int32_t) * (size_t)a.ntile * k);
     a.esum = (int64_t *)ws_get(ctx, WS_ESUM, sizeof(int64_t) * (size_t)a.ntile);
-    if (!a.P || !a.rec || !a.dest || !a.lock || !a.slot || !a.rbd || !a.rsev || !bins || !a.xl || !a.ml ||
-        !a.ctl || !p64 || !p32 || !p8 || !a.hist || !a.tsum || !a.esum)
+    a.kinds = (int8_t *)ws_get(ctx, WS_KINDS, KIND_LOG);
+    if (!a.P || !a.rec || !a.dest || !a.lock || !a.slot || !a.rbd || !a.rsev || !bins || !a.bstat || !fill ||
+        !a.ctl || !p64 || !p32 || !p8 || !a.hist || !a.tsum || !a.esum || !a.kinds)
         return JET_ENOMEM;
     a.w = p64; a.wbest = p64 + k; a.resid = p64 + 2 * k; a.capstart = p64 + 3 * k;
     a.Blist = p32; a.sstar = p32 + k; a.splitidx = p32 + 2 * k;
@@ -1376,7 +1474,6 @@ static int setup(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     if (hc.wsum >= ((int64_t)1 << 31) || hc.ewsum >= ((int64_t)1 << 31)) return JET_EOVERFLOW;
     a.binoff[0] = 0;
     for (int c = 0; c < NCLS; c++) a.binoff[c + 1] = a.binoff[c] + hc.bincnt[c];
-    int32_t *fill = a.xl;  // scratch counters before the X lists are used
     JET_TRY(hipMemsetAsync(fill, 0, sizeof(int32_t) * NCLS, s));
     if (n > 0) k_fill_bins<<<grid_v, BLOCK, 0, s>>>(a, bins, fill);
     const int64_t W = hc.wsum;
@@ -1438,9 +1535,23 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     if (st) return st;
     JET_TRY(hipEventRecord(ctx->ev[1], s));
     Ctl *pin = (Ctl *)ctx->pinned;
-    int chunk = 4;
+    const bool prof = prm->flags & JET_F_PROFILE;
+    int chunk = 4, launched = 0;
     for (;;) {
-        for (int i = 0; i < chunk; i++) launch_iteration(pl, s, true, true);
+        for (int i = 0; i < chunk; i++) {
+            hipEvent_t ea = nullptr, eb = nullptr;
+            if (prof && launched < KIND_LOG) {
+                while ((int)ctx->prof_ev.size() < 2 * (launched + 1)) {
+                    hipEvent_t e;
+                    JET_TRY(hipEventCreate(&e));
+                    ctx->prof_ev.push_back(e);
+                }
+                ea = ctx->prof_ev[2 * launched];
+                eb = ctx->prof_ev[2 * launched + 1];
+            }
+            launch_iteration(pl, s, true, true, ea, eb);
+            launched++;
+        }
         JET_TRY(hipGetLastError());
         JET_TRY(hipMemcpyAsync(pin, pl.plain.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         JET_TRY(hipStreamSynchronize(s));
@@ -1461,6 +1572,24 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     JET_TRY(hipStreamSynchronize(s));
     if (trace_count) *trace_count = ntr;
     if (trace_total) *trace_total = hc.t;
+    float ms_gain = 0.f;
+    int gain_passes = 0;
+    if (prof) {
+        const int nk = std::min(hc.t, KIND_LOG);
+        std::vector<int8_t> kinds(std::max(nk, 1));
+        if (nk > 0) {
+            JET_TRY(hipMemcpyAsync(kinds.data(), pl.plain.kinds, nk, hipMemcpyDeviceToHost, s));
+            JET_TRY(hipStreamSynchronize(s));
+        }
+        for (int i = 0; i < nk; i++) {
+            if (kinds[i] != KIND_LP) continue;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ctx->prof_ev[2 * i], ctx->prof_ev[2 * i + 1]) == hipSuccess) {
+                ms_gain += ms;
+                gain_passes++;
+            }
+        }
+    }
     if (stats) {
         memset(stats, 0, sizeof(*stats));
         const bool it = prm->flags & JET_F_RETURN_ITER;
@@ -1482,6 +1611,13 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
         stats->ms_refine = ms;
         (void)hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]);
         stats->ms_init = ms;
+        if (prof) {
+            stats->ms_gain = ms_gain;
+            stats->gain_passes = gain_passes;
+            stats->gain_entries = hc.prof_e;
+            stats->gain_rows = hc.prof_r;
+            stats->gain_vertices = hc.prof_v;
+        }
     }
     return JET_OK;
 }
@@ -1525,6 +1661,7 @@ extern "C" void jet_context_destroy(jet_context *ctx)
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     for (auto &ev : ctx->ev)
         if (ev) (void)hipEventDestroy(ev);
+    for (auto ev : ctx->prof_ev) (void)hipEventDestroy(ev);
     delete ctx;
 }
 
@@ -1584,7 +1721,7 @@ extern "C" int jet_lp_step(jet_context *ctx, const jet_csr *g, const jet_params 
     if (st) return st;
     k_step_defaults<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, part);
     k_force_step<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, KIND_LP, 0, locked);
-    if (pl.grid_tab) k_gain<<<pl.grid_tab, BLOCK, pl.lds_tab, s>>>(pl.tab);
+    launch_gain(pl, s);
     if (pl.grid_plain) k_afterburner<<<pl.grid_plain, BLOCK, 0, s>>>(pl.plain);
     k_lp_outputs<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, inX, move);
     JET_TRY(hipGetLastError());
@@ -1619,7 +1756,8 @@ extern "C" int jet_rebalance_step(jet_context *ctx, const jet_csr *g, const jet_
     const KArgs &p = pl.plain;
     k_step_defaults<<<pl.grid_flat, BLOCK, 0, s>>>(p, part);
     k_force_step<<<1, BLOCK, 0, s>>>(p, kind, t, nullptr);
-    if (pl.grid_rbtab) k_rb_loss<<<pl.grid_rbtab, BLOCK, pl.lds_tab, s>>>(pl.tab);
+    launch_rb_loss(pl, s);
+    k_rb_hist<<<pl.grid_hist, 64, pl.hist_lds ? (size_t)p.k * NSLOT * 4 : 0, s>>>(p, pl.hist_lds);
     k_rb_cutoff<<<1, BLOCK, 0, s>>>(p);
     k_rb_tilesum<<<pl.grid_tile, 64, (size_t)p.k * 4, s>>>(p);
     k_rb_tilescan<<<std::min(p.k, 1024), BLOCK, 0, s>>>(p);

@@ -24,6 +24,7 @@ JET_OK, JET_EINVAL, JET_EGRAPH, JET_EPART, JET_EOVERFLOW, JET_ENOMEM, JET_EHIP, 
     0, -1, -2, -3, -4, -5, -6, -7, -8
 JET_F_VALIDATE = 0x1
 JET_F_RETURN_ITER = 0x2
+JET_F_PROFILE = 0x4
 KIND_LP, KIND_RW, KIND_RS = 1, 2, 3
 
 # Every function declared in include/jet.h.
@@ -59,7 +60,9 @@ class Stats(C.Structure):
                 ("sigma", C.c_int64), ("total_weight", C.c_int64), ("balanced", C.c_int32),
                 ("iters", C.c_int32), ("lp_iters", C.c_int32), ("rw_iters", C.c_int32),
                 ("rs_iters", C.c_int32), ("levels", C.c_int32), ("ms_total", C.c_float),
-                ("ms_refine", C.c_float), ("ms_coarsen", C.c_float), ("ms_init", C.c_float)]
+                ("ms_refine", C.c_float), ("ms_coarsen", C.c_float), ("ms_init", C.c_float),
+                ("ms_gain", C.c_float), ("gain_passes", C.c_int32), ("gain_entries", C.c_int64),
+                ("gain_rows", C.c_int64), ("gain_vertices", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -80,6 +83,15 @@ class Trace(C.Structure):
 TRACE_FIELDS = [f for f, _ in TraceRec._fields_]
 
 _lib = None
+_hiplib = None
+
+
+def _hip():
+    """The HIP runtime, for copying library-owned hierarchy levels to the host."""
+    global _hiplib
+    if _hiplib is None:
+        _hiplib = C.CDLL("libamdhip64.so")
+    return _hiplib
 
 
 def lib():
@@ -287,14 +299,15 @@ class Hierarchy:
         n, nnz = view.n, view.nnz
 
         def fetch(ptr, count, dt):
-            if not ptr or count == 0:
-                return None if not ptr else np.zeros(0, dt)
+            if not ptr:
+                return None
             out = np.empty(count, dt)
-            torch.cuda.synchronize()
-            C.memmove  # keep ctypes import used
-            import ctypes
-            hip = ctypes.CDLL("libamdhip64.so")
-            hip.hipMemcpy(C.c_void_p(out.ctypes.data), C.c_void_p(ptr), C.c_size_t(out.nbytes), C.c_int(2))
+            if count:
+                torch.cuda.synchronize()
+                st = _hip().hipMemcpy(C.c_void_p(out.ctypes.data), C.c_void_p(ptr), C.c_size_t(out.nbytes),
+                                      C.c_int(2))  # hipMemcpyDeviceToHost
+                if st != 0:
+                    raise RuntimeError(f"hipMemcpy failed ({st})")
             return out
 
         return dict(n=n, xadj=fetch(view.xadj, n + 1, np.int64), adjncy=fetch(view.adjncy, nnz, np.int32),

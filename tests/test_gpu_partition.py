@@ -1,0 +1,113 @@
+"""GPU parity of the multilevel scaffold and the full partition (Algorithm 1)
+against the CPU oracle: every coarse level (vertex weights, map, rows as
+neighbour sets with summed weights) and the concatenated per-iteration trace
+of all levels plus the final partition must match exactly."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2304_13194_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def J():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_13194_amd import jet
+    jet.lib()
+    return jet
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def rows_as_sets(xadj, adj, ew):
+    out = []
+    for v in range(len(xadj) - 1):
+        s, e = int(xadj[v]), int(xadj[v + 1])
+        out.append(sorted(zip(adj[s:e].tolist(), ew[s:e].tolist())))
+    return out
+
+
+CASES = [
+    ("grid40_k4", I.grid2d(40, 40), 4, 3),
+    ("stencil16_k8", I.stencil27(16, 16, 16), 8, 5),
+    ("rmat13_k16", I.rmat(13, 8, 4), 16, 6),
+    ("rgg20000_k32", I.rgg(20000, 3), 32, 7),
+    ("er200_k2", I.small_random_graph(200, 0.05, 9, wmax=5, vwmax=3), 2, 8),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_hierarchy_matches_oracle(J, O, case):
+    name, g, k, seed = case
+    _say(f"coarsen {name} n={g.n} k={k}")
+    h = J.coarsen(J.to_device(g), k, seed=seed)
+    cur = g
+    for lvl in range(h.levels):
+        L = h.level(lvl)
+        assert L["n"] == cur.n
+        if lvl == h.levels - 1:
+            assert L["map"] is None
+            break
+        nc, cmap = O.hem_map(cur, lvl, seed)
+        np.testing.assert_array_equal(L["map"], cmap, err_msg=f"{name} map level {lvl}")
+        nxt = O.contract(cur, cmap, nc)
+        Ln = h.level(lvl + 1)
+        assert Ln["n"] == nc
+        np.testing.assert_array_equal(Ln["vwgt"], nxt.vwgt)
+        assert rows_as_sets(Ln["xadj"], Ln["adjncy"], Ln["adjwgt"]) == \
+            rows_as_sets(nxt.xadj, nxt.adjncy, nxt.adjwgt), f"{name} rows level {lvl + 1}"
+        cur = nxt
+    h.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_partition_matches_oracle(J, O, case):
+    name, g, k, seed = case
+    _say(f"partition {name} n={g.n} k={k}")
+    exp = O.partition(g, k, seed=seed)
+    part, st, tr = J.partition(J.to_device(g), k, seed=seed, trace_cap=100000)
+    assert st["levels"] == len(exp["level_sizes"])
+    assert len(tr) == len(exp["trace"])
+    for a, b in zip(tr, exp["trace"]):
+        assert a == b, f"{name}: gpu {a} != oracle {b}"
+    np.testing.assert_array_equal(part.cpu().numpy(), exp["part"])
+    assert st["cut"] == exp["cut"] and bool(st["balanced"]) == exp["balanced"]
+
+
+def test_partition_unit_weight_pointers(J, O):
+    g = I.stencil27(12, 12, 12)
+    exp = O.partition(g, 8, seed=2)
+    part, st, _ = J.partition(J.to_device(g, unit_vwgt=True, unit_adjwgt=True), 8, seed=2)
+    np.testing.assert_array_equal(part.cpu().numpy(), exp["part"])
+
+
+def test_partition_errors(J):
+    import torch
+    g = I.grid2d(10, 10)
+    dg = J.to_device(g)
+    adj = dg.adjncy.clone()
+    adj[3] = 500  # out of range: caught before any kernel indexes with it
+    with pytest.raises(J.JetError) as e:
+        J.partition(J.DeviceGraph(dg.xadj, adj, None, None), 4)
+    assert e.value.status == J.JET_EGRAPH
+    with pytest.raises(J.JetError) as e:
+        J.partition(dg, 0)
+    assert e.value.status == J.JET_EINVAL
+    big = torch.full((g.nnz,), 2 ** 30, dtype=torch.int32, device="cuda")
+    with pytest.raises(J.JetError) as e:
+        J.partition(J.DeviceGraph(dg.xadj, dg.adjncy, None, big), 4)
+    assert e.value.status == J.JET_EOVERFLOW
