@@ -362,11 +362,9 @@ __global__ __launch_bounds__(BLOCK) void k_copy_best(KArgs a)
 // the part of neighbour slot r (-1 if none) and cu[r] its connectivity for the
 // first lane that claimed it, else 0. The table is left all-zero.
 template <int G, int R>
-__device__ __forceinline__ void group_conn(const KArgs &a, int v, int gl, int32_t *tab, int (&pu)[R],
-                                           int (&cu)[R])
+__device__ __forceinline__ void group_conn_row(const KArgs &a, int64_t s, int deg, int gl, int32_t *tab, int (&pu)[R],
+                                               int (&cu)[R])
 {
-    const int64_t s = a.xadj[v];
-    const int deg = (int)(a.xadj[v + 1] - s);
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int idx = gl + r * G;
@@ -382,6 +380,57 @@ __device__ __forceinline__ void group_conn(const KArgs &a, int v, int gl, int32_
 #pragma unroll
     for (int r = 0; r < R; r++) cu[r] = pu[r] >= 0 ? atomicExch(&tab[pu[r]], 0) : 0;
     lds_fence_wave();
+}
+
+template <int G, int R>
+__device__ __forceinline__ void group_conn(const KArgs &a, int v, int gl, int32_t *tab, int (&pu)[R], int (&cu)[R])
+{
+    const int64_t s = a.xadj[v];
+    group_conn_row<G, R>(a, s, (int)(a.xadj[v + 1] - s), gl, tab, pu, cu);
+}
+
+// Wave-batched driver of the 8-lane role. Lanes first inspect 64 list
+// entries at once (coalesced loads of the id, row offsets and per-vertex
+// state); the entries that need row work are queued in LDS and handed to the
+// wave's eight 8-lane groups, eight at a time. Metadata round trips are paid
+// once per 64 vertices instead of once per vertex, and skipped vertices cost
+// no group time.
+struct Meta {
+    int v, ps, deg, aux;
+    int64_t s;
+};
+
+template <class Pre, class Row>
+__device__ __forceinline__ void wave_batched8(const int32_t *list, int cnt, int32_t *q, int wid, int nwaves, Pre pre,
+                                              Row row)
+{
+    const int lane = threadIdx.x & 63, g = lane >> 3, gl = lane & 7;
+    for (int base = wid * 64; base < cnt; base += nwaves * 64) {
+        const int i = base + lane;
+        Meta m{0, 0, 0, 0, 0};
+        bool act = false;
+        if (i < cnt) {
+            m.v = list[i];
+            act = pre(m);
+        }
+        const uint64_t mask = __ballot(act);
+        if (act) q[__popcll(mask & ((1ull << lane) - 1ull))] = lane;
+        lds_fence_wave();
+        const int nact = __popcll(mask);
+        for (int sb = 0; sb < nact; sb += 8) {
+            const int slot = sb + g;
+            const bool has = slot < nact;
+            const int src = q[has ? slot : 0];
+            Meta t;
+            t.v = __shfl(m.v, src, 64);
+            t.ps = __shfl(m.ps, src, 64);
+            t.deg = __shfl(m.deg, src, 64);
+            t.aux = __shfl(m.aux, src, 64);
+            t.s = __shfl(m.s, src, 64);
+            if (has) row(t, gl);
+        }
+        lds_fence_wave();
+    }
 }
 
 // Whole block gathers the neighbours of v into `tab` (k entries).
@@ -532,9 +581,42 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk, int boff)
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         __syncthreads();
         int32_t *tab = lds + (threadIdx.x >> 3) * stride;
-        for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 1)
-                gain_groups<8, 4>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 3), nblk * ng, lp_prev, cn, cd, gc);
+        int32_t *q = lds + ng * stride + (threadIdx.x >> 6) * 64;
+        const int wid = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nblk * (BLOCK / 64);
+        for (int c = 1; c < NCLS; c++) {
+            if (a.tmap[c] != 1) continue;
+            wave_batched8(
+                a.bins + a.binoff[c], a.binoff[c + 1] - a.binoff[c], q, wid, nwaves,
+                [&](Meta &m) -> bool {
+                    m.ps = a.P[m.v];
+                    gc.v++;
+                    if (a.lock[m.v] == lp_prev) {
+                        gain_locked(a, m.v, m.ps);
+                        return false;
+                    }
+                    m.s = a.xadj[m.v];
+                    m.deg = (int)(a.xadj[m.v + 1] - m.s);
+                    gc.r++;
+                    gc.e += m.deg;
+                    return true;
+                },
+                [&](const Meta &t, int gl) {
+                    int pu[4], cu[4];
+                    group_conn_row<8, 4>(a, t.s, t.deg, gl, tab, pu, cu);
+                    uint64_t best = 0;
+                    int cs = 0;
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        if (cu[r] > 0) {
+                            if (pu[r] == t.ps) cs += cu[r];
+                            else { uint64_t k2 = conn_key(cu[r], pu[r]); best = k2 > best ? k2 : best; }
+                        }
+                    }
+                    best = gmax_u64<8>(best);
+                    cs = gsum<8>(cs);
+                    if (gl == 0) gc.nx += gain_finish(a, t.v, t.ps, best, cs, cn, cd);
+                });
+        }
     } else if (ROLE == 2) {
         const int ng = BLOCK / 64;
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
@@ -568,11 +650,9 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk, int boff)
 // F2(v) = sum over neighbours u of w * ([q_u = P_d(v)] - [q_u = P_s(v)]) with
 // q_u = P_d(u) when u is in X and precedes v (larger F, or equal F and smaller
 // id), else P_s(u). Moves with F2 >= 0 form M.
-template <int G>
-__device__ __forceinline__ int after_sum(const KArgs &a, int v, int ps, int pd, int Fv, int gl, int stride)
+__device__ __forceinline__ int after_sum_row(const KArgs &a, int v, int64_t s, int deg, int ps, int pd, int Fv, int gl,
+                                             int stride)
 {
-    const int64_t s = a.xadj[v];
-    const int deg = (int)(a.xadj[v + 1] - s);
     int sum = 0;
     for (int idx = gl; idx < deg; idx += stride) {
         const int u = a.adj[s + idx];
@@ -584,6 +664,13 @@ __device__ __forceinline__ int after_sum(const KArgs &a, int v, int ps, int pd, 
         sum += q == pd ? wt : (q == ps ? -wt : 0);
     }
     return sum;
+}
+
+template <int G>
+__device__ __forceinline__ int after_sum(const KArgs &a, int v, int ps, int pd, int Fv, int gl, int stride)
+{
+    const int64_t s = a.xadj[v];
+    return after_sum_row(a, v, s, (int)(a.xadj[v + 1] - s), ps, pd, Fv, gl, stride);
 }
 
 template <int G>
@@ -609,9 +696,34 @@ __device__ void after_groups(const KArgs &a, int cls, int gid, int ngroups)
 __global__ __launch_bounds__(BLOCK) void k_afterburner(KArgs a)
 {
     __shared__ int32_t s_red[BLOCK / 64];
+    __shared__ int32_t s_q[BLOCK];
     if (a.ctl->kind != KIND_LP) return;
     int b = blockIdx.x;
-    if (b < a.gS) { after_groups<8>(a, CLS_S, b * (BLOCK / 8) + (threadIdx.x >> 3), a.gS * (BLOCK / 8)); return; }
+    if (b < a.gS) {
+        int32_t *q = s_q + (threadIdx.x >> 6) * 64;
+        wave_batched8(
+            a.bins + a.binoff[CLS_S], a.binoff[CLS_S + 1] - a.binoff[CLS_S], q, b * (BLOCK / 64) + (threadIdx.x >> 6),
+            a.gS * (BLOCK / 64),
+            [&](Meta &m) -> bool {
+                const int2 r = a.rec[m.v];
+                if ((r.x & 0xFFFF) == 0) return false;  // not in X
+                m.ps = r.x;
+                m.aux = r.y;
+                m.s = a.xadj[m.v];
+                m.deg = (int)(a.xadj[m.v + 1] - m.s);
+                return true;
+            },
+            [&](const Meta &t, int gl) {
+                const int ps = t.ps >> 16, pd = (t.ps & 0xFFFF) - 1;
+                int sum = after_sum_row(a, t.v, t.s, t.deg, ps, pd, t.aux, gl, 8);
+                sum = gsum<8>(sum);
+                if (gl == 0) {
+                    if (a.dbg_F2) a.dbg_F2[t.v] = sum;
+                    if (sum >= 0) a.dest[t.v] = pd;
+                }
+            });
+        return;
+    }
     b -= a.gS;
     if (b < a.gM) { after_groups<64>(a, CLS_M, b * (BLOCK / 64) + (threadIdx.x >> 6), a.gM * (BLOCK / 64)); return; }
     b -= a.gM;
@@ -636,10 +748,9 @@ __global__ __launch_bounds__(BLOCK) void k_afterburner(KArgs a)
 
 // Delta of the cut over the edges of moved vertices: an edge whose two ends
 // both move is counted from its smaller end. Also moved weight and digest.
-__device__ __forceinline__ int dcut_sum(const KArgs &a, int v, int ps, int pn, int gl, int stride)
+__device__ __forceinline__ int dcut_sum_row(const KArgs &a, int v, int64_t s, int deg, int ps, int pn, int gl,
+                                            int stride)
 {
-    const int64_t s = a.xadj[v];
-    const int deg = (int)(a.xadj[v + 1] - s);
     int delta = 0;
     for (int idx = gl; idx < deg; idx += stride) {
         const int u = a.adj[s + idx];
@@ -651,6 +762,12 @@ __device__ __forceinline__ int dcut_sum(const KArgs &a, int v, int ps, int pn, i
         delta += wt * ((int)(pn != pun) - (int)(ps != pu));
     }
     return delta;
+}
+
+__device__ __forceinline__ int dcut_sum(const KArgs &a, int v, int ps, int pn, int gl, int stride)
+{
+    const int64_t s = a.xadj[v];
+    return dcut_sum_row(a, v, s, (int)(a.xadj[v + 1] - s), ps, pn, gl, stride);
 }
 
 __device__ __forceinline__ void move_meta(const KArgs &a, int v, int ps, int pn, int64_t &mw, uint64_t &dg)
@@ -686,12 +803,34 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
     __shared__ int64_t s_red[BLOCK / 64];
     __shared__ uint64_t s_redu[BLOCK / 64];
     __shared__ int32_t s_red32[BLOCK / 64];
+    __shared__ int32_t s_q[BLOCK];
     if (a.ctl->kind == KIND_DONE) return;
     int64_t dc = 0, mw = 0, nm = 0;
     uint64_t dg = 0;
     int b = blockIdx.x;
     if (b < a.gS) {
-        dcut_groups<8>(a, CLS_S, b * (BLOCK / 8) + (threadIdx.x >> 3), a.gS * (BLOCK / 8), dc, mw, dg, nm);
+        int32_t *q = s_q + (threadIdx.x >> 6) * 64;
+        wave_batched8(
+            a.bins + a.binoff[CLS_S], a.binoff[CLS_S + 1] - a.binoff[CLS_S], q, b * (BLOCK / 64) + (threadIdx.x >> 6),
+            a.gS * (BLOCK / 64),
+            [&](Meta &m) -> bool {
+                const int pn = a.dest[m.v];
+                if (pn < 0) return false;
+                m.aux = pn;
+                m.ps = a.P[m.v];
+                m.s = a.xadj[m.v];
+                m.deg = (int)(a.xadj[m.v + 1] - m.s);
+                return true;
+            },
+            [&](const Meta &t, int gl) {
+                int d = dcut_sum_row(a, t.v, t.s, t.deg, t.ps, t.aux, gl, 8);
+                d = gsum<8>(d);
+                if (gl == 0) {
+                    dc += d;
+                    nm++;
+                    move_meta(a, t.v, t.ps, t.aux, mw, dg);
+                }
+            });
     } else if ((b -= a.gS) < a.gM) {
         dcut_groups<64>(a, CLS_M, b * (BLOCK / 64) + (threadIdx.x >> 6), a.gM * (BLOCK / 64), dc, mw, dg, nm);
     } else if ((b -= a.gM) < a.gL) {
@@ -887,9 +1026,48 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int boff)
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         __syncthreads();
         int32_t *tab = lds + (threadIdx.x >> 3) * stride;
-        for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 1)
-                rb_groups<8, 4>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 3), nblk * ng, kind, hseed, ncand);
+        int32_t *q = lds + ng * stride + (threadIdx.x >> 6) * 64;
+        const int wid = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nblk * (BLOCK / 64);
+        for (int c = 1; c < NCLS; c++) {
+            if (a.tmap[c] != 1) continue;
+            wave_batched8(
+                a.bins + a.binoff[c], a.binoff[c + 1] - a.binoff[c], q, wid, nwaves,
+                [&](Meta &m) -> bool {
+                    m.ps = a.P[m.v];
+                    m.aux = a.vw ? a.vw[m.v] : 1;
+                    if (!a.isA[m.ps] || !rb_eligible(a, m.ps, m.aux)) {
+                        a.slot[m.v] = 255;
+                        if (a.dbg_loss) { a.dbg_loss[m.v] = INT64_MIN; a.dbg_slot[m.v] = -1; a.dbg_pd[m.v] = -1; }
+                        return false;
+                    }
+                    m.s = a.xadj[m.v];
+                    m.deg = (int)(a.xadj[m.v + 1] - m.s);
+                    return true;
+                },
+                [&](const Meta &t, int gl) {
+                    int pu[4], cu[4];
+                    group_conn_row<8, 4>(a, t.s, t.deg, gl, tab, pu, cu);
+                    uint64_t best = 0;
+                    int cs = 0, sumB = 0, cntB = 0;
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        if (cu[r] > 0) {
+                            if (pu[r] == t.ps) cs += cu[r];
+                            else if (a.isB[pu[r]]) {
+                                uint64_t k2 = conn_key(cu[r], pu[r]);
+                                best = k2 > best ? k2 : best;
+                                sumB += cu[r];
+                                cntB++;
+                            }
+                        }
+                    }
+                    best = gmax_u64<8>(best);
+                    cs = gsum<8>(cs);
+                    sumB = gsum<8>(sumB);
+                    cntB = gsum<8>(cntB);
+                    if (gl == 0) rb_finish(a, t.v, t.ps, t.aux, kind, best, cs, sumB, cntB, hseed, ncand);
+                });
+        }
     } else if (ROLE == 2) {
         const int ng = BLOCK / 64;
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
@@ -1235,7 +1413,7 @@ static void plan_roles(const jet_context *ctx, KArgs &a, const int32_t *cnt, Pla
     KArgs t = a;
     t.tmap[0] = 0;
     const int k = a.k;
-    if (k <= 511) { t.tmap[1] = 1; t.tmap[2] = 2; t.tmap[3] = 3; }
+    if (k <= 495) { t.tmap[1] = 1; t.tmap[2] = 2; t.tmap[3] = 3; }
     else if (k <= 4095) { t.tmap[1] = 2; t.tmap[2] = 2; t.tmap[3] = 3; }
     else { t.tmap[1] = 3; t.tmap[2] = 3; t.tmap[3] = 3; }
     int64_t role_cnt[4] = {0, 0, 0, 0};
@@ -1276,7 +1454,7 @@ static void launch_gain(const Plan &pl, hipStream_t s)
 {
     const KArgs &t = pl.tab;
     const size_t st = (size_t)(t.k + 1) * 4;
-    if (t.gS) k_gain<1><<<t.gS, BLOCK, (BLOCK / 8) * st, s>>>(t, t.gS, 0);
+    if (t.gS) k_gain<1><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS, 0);
     if (t.gM) k_gain<2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM, t.gS);
     if (t.gL) k_gain<3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL, t.gS + t.gM);
 }
@@ -1285,7 +1463,7 @@ static void launch_rb_loss(const Plan &pl, hipStream_t s)
 {
     const KArgs &t = pl.tab;
     const size_t st = (size_t)(t.k + 1) * 4;
-    if (t.gS) k_rb_loss<1><<<t.gS, BLOCK, (BLOCK / 8) * st, s>>>(t, t.gS, 0);
+    if (t.gS) k_rb_loss<1><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS, 0);
     if (t.gM) k_rb_loss<2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM, t.gS);
     if (t.gL) k_rb_loss<3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL, t.gS + t.gM);
     if (t.gZ) k_rb_loss<4><<<t.gZ, BLOCK, 0, s>>>(t, t.gZ, t.gS + t.gM + t.gL);
