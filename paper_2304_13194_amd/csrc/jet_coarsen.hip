@@ -296,7 +296,7 @@ __global__ __launch_bounds__(CB) void k_leader_flags(int n, const int32_t *match
 // are written by the leader.
 __global__ __launch_bounds__(CB) void k_coarse_map(int n, const int32_t *match, const int64_t *cid,
                                                    const int64_t *xadj, const int32_t *vw, int32_t *map,
-                                                   int32_t *cvw, int32_t *bound)
+                                                   int32_t *cvw, int32_t *bound, int32_t *mem0, int32_t *mem1)
 {
     for (int v = blockIdx.x * CB + threadIdx.x; v < n; v += gridDim.x * CB) {
         const int m = match[v];
@@ -313,6 +313,8 @@ __global__ __launch_bounds__(CB) void k_coarse_map(int n, const int32_t *match, 
             }
             cvw[c] = w;
             bound[c] = (int32_t)b;
+            mem0[c] = v;
+            mem1[c] = m;
         }
     }
 }
@@ -387,6 +389,247 @@ __global__ __launch_bounds__(CB) void k_contract_extract(int nc, const int64_t *
                 cew[out + pos] = tval[j];
             }
             out += __popc(gm);
+        }
+    }
+}
+
+
+// ---------------------------------------------------- LDS contraction ---
+// Each coarse row is deduplicated in an LDS hash table (key = coarse
+// neighbour, value = summed edge weight) built from its members' fine rows.
+// A count pass sizes the rows, an exclusive scan places them, a fill pass
+// writes them. Rows of bound <= 64 use 8-lane groups with 128 slots; rows of
+// bound <= 2048 one block with 4096 slots; larger rows a global table.
+constexpr int CS_MAX = 64, CS_T = 128;
+constexpr int CM_MAX = 2048, CM_T = 4096;
+
+__device__ __forceinline__ uint32_t chash(int key, int bits)
+{
+    return ((uint32_t)key * 2654435761u) >> (32 - bits);
+}
+
+// Fine entry idx (0 <= idx < d0 + d1) of the two member rows.
+__device__ __forceinline__ int64_t member_entry(int64_t s0, int d0, int64_t s1, int idx)
+{
+    return idx < d0 ? s0 + idx : s1 + (idx - d0);
+}
+
+__global__ __launch_bounds__(CB) void k_cclass(int nc, const int32_t *bound, int32_t *listM, int32_t *listL,
+                                               int32_t *cnt, int64_t *ltot)
+{
+    const int stride = gridDim.x * CB;
+    const int nloop = (nc + stride - 1) / stride;
+    for (int it = 0; it < nloop; it++) {
+        const int c = it * stride + blockIdx.x * CB + threadIdx.x;
+        const int b = c < nc ? bound[c] : 0;
+        wave_append(c < nc && b > CS_MAX && b <= CM_MAX, &cnt[0], listM, c);
+        const bool isL = c < nc && b > CM_MAX;
+        wave_append(isL, &cnt[1], listL, c);
+        if (isL) atomicAdd((unsigned long long *)ltot, (unsigned long long)(2 * (int64_t)b));
+    }
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(CB) void k_crow_small(int nc, const int32_t *bound, const int32_t *mem0,
+                                                   const int32_t *mem1, const int64_t *xadj, const int32_t *adj,
+                                                   const int32_t *ew, const int32_t *map, int32_t *ccount,
+                                                   const int64_t *cxadj, int32_t *cadj, int32_t *cew,
+                                                   int32_t *overflow)
+{
+    __shared__ int32_t keys[(CB / 8) * CS_T];
+    __shared__ int32_t vals[(CB / 8) * CS_T];
+    for (int i = threadIdx.x; i < (CB / 8) * CS_T; i += CB) { keys[i] = -1; vals[i] = 0; }
+    __syncthreads();
+    const int gl = threadIdx.x & 7;
+    const int gshift = (threadIdx.x & 63) & ~7;
+    int32_t *K = keys + (threadIdx.x >> 3) * CS_T;
+    int32_t *V = vals + (threadIdx.x >> 3) * CS_T;
+    const int ngroups = gridDim.x * (CB / 8);
+    for (int c = blockIdx.x * (CB / 8) + (threadIdx.x >> 3); c < nc; c += ngroups) {
+        if (bound[c] > CS_MAX) continue;
+        const int m0 = mem0[c], m1 = mem1[c];
+        const int64_t s0 = xadj[m0];
+        const int d0 = (int)(xadj[m0 + 1] - s0);
+        int64_t s1 = 0;
+        int d1 = 0;
+        if (m1 >= 0) { s1 = xadj[m1]; d1 = (int)(xadj[m1 + 1] - s1); }
+        for (int idx = gl; idx < d0 + d1; idx += 8) {
+            const int64_t e = member_entry(s0, d0, s1, idx);
+            const int cu = map[adj[e]];
+            if (cu == c) continue;
+            const int w = ew ? ew[e] : 1;
+            uint32_t h = chash(cu, 7);
+            for (int probe = 0;; probe++) {
+                if (probe == CS_T) { *overflow = 1; break; }  // cannot happen: <= 64 keys in 128 slots
+                const int old = atomicCAS(&K[h], -1, cu);
+                if (old == -1 || old == cu) { if (FILL) atomicAdd(&V[h], w); break; }
+                h = (h + 1) & (CS_T - 1);
+            }
+        }
+        lds_fence_wave();
+        if (!FILL) {
+            int cnt = 0;
+            for (int j = gl; j < CS_T; j += 8) {
+                if (K[j] >= 0) { cnt++; K[j] = -1; }
+            }
+            cnt = gsum<8>(cnt);
+            if (gl == 0) ccount[c] = cnt;
+        } else {
+            int64_t out = cxadj[c];
+            for (int j0 = 0; j0 < CS_T; j0 += 8) {
+                const int j = j0 + gl;
+                const int key = K[j];
+                const bool occ = key >= 0;
+                const uint32_t gm = (uint32_t)((__ballot(occ) >> gshift) & 0xFFu);
+                if (occ) {
+                    const int pos = __popc(gm & ((1u << gl) - 1u));
+                    cadj[out + pos] = key;
+                    cew[out + pos] = V[j];
+                    K[j] = -1;
+                    V[j] = 0;
+                }
+                out += __popc(gm);
+            }
+        }
+        lds_fence_wave();
+    }
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(CB) void k_crow_medium(const int32_t *list, int cntM, const int32_t *mem0,
+                                                    const int32_t *mem1, const int64_t *xadj, const int32_t *adj,
+                                                    const int32_t *ew, const int32_t *map, int32_t *ccount,
+                                                    const int64_t *cxadj, int32_t *cadj, int32_t *cew,
+                                                    int32_t *overflow)
+{
+    extern __shared__ int32_t lds[];
+    __shared__ int32_t s_red[CB / 64];
+    constexpr int PER = CM_T / CB;
+    int32_t *K = lds, *V = lds + CM_T;
+    for (int i = threadIdx.x; i < CM_T; i += CB) { K[i] = -1; V[i] = 0; }
+    __syncthreads();
+    for (int r = blockIdx.x; r < cntM; r += gridDim.x) {
+        const int c = list[r];
+        const int m0 = mem0[c], m1 = mem1[c];
+        const int64_t s0 = xadj[m0];
+        const int d0 = (int)(xadj[m0 + 1] - s0);
+        int64_t s1 = 0;
+        int d1 = 0;
+        if (m1 >= 0) { s1 = xadj[m1]; d1 = (int)(xadj[m1 + 1] - s1); }
+        for (int idx = threadIdx.x; idx < d0 + d1; idx += CB) {
+            const int64_t e = member_entry(s0, d0, s1, idx);
+            const int cu = map[adj[e]];
+            if (cu == c) continue;
+            const int w = ew ? ew[e] : 1;
+            uint32_t h = chash(cu, 12);
+            for (int probe = 0;; probe++) {
+                if (probe == CM_T) { *overflow = 1; break; }  // cannot happen: <= 2048 keys in 4096 slots
+                const int old = atomicCAS(&K[h], -1, cu);
+                if (old == -1 || old == cu) { if (FILL) atomicAdd(&V[h], w); break; }
+                h = (h + 1) & (CM_T - 1);
+            }
+        }
+        __syncthreads();
+        int mine = 0;
+        const int j0 = threadIdx.x * PER;
+        for (int q = 0; q < PER; q++) mine += K[j0 + q] >= 0;
+        if (!FILL) {
+            const int tot = block_sum<CB>(mine, s_red);
+            if (threadIdx.x == 0) ccount[c] = tot;
+            for (int q = 0; q < PER; q++) K[j0 + q] = -1;
+        } else {
+            int tot;
+            int64_t out = cxadj[c] + block_excl_scan<CB>(mine, s_red, tot);
+            for (int q = 0; q < PER; q++) {
+                const int key = K[j0 + q];
+                if (key >= 0) {
+                    cadj[out] = key;
+                    cew[out] = V[j0 + q];
+                    out++;
+                    K[j0 + q] = -1;
+                    V[j0 + q] = 0;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Exclusive scan of 2 * bound over the large rows (single block).
+__global__ __launch_bounds__(CB) void k_cl_offsets(const int32_t *listL, int cntL, const int32_t *bound, int64_t *toffL)
+{
+    __shared__ int64_t s_scan[CB / 64];
+    int64_t carry = 0;
+    for (int base = 0; base < cntL; base += CB) {
+        const int i = base + threadIdx.x;
+        const int64_t x = i < cntL ? 2 * (int64_t)bound[listL[i]] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan<CB>(x, s_scan, tot);
+        if (i < cntL) toffL[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) toffL[cntL] = carry;
+}
+
+// Large rows: one block per row inserts into a global open-addressed table of
+// 2 * bound slots and counts the distinct keys.
+__global__ __launch_bounds__(CB) void k_crow_large_insert(const int32_t *listL, int cntL, const int64_t *toffL,
+                                                          const int32_t *mem0, const int32_t *mem1,
+                                                          const int64_t *xadj, const int32_t *adj, const int32_t *ew,
+                                                          const int32_t *map, int32_t *tkey, int32_t *tval,
+                                                          int32_t *ccount, int32_t *overflow)
+{
+    __shared__ int32_t s_red[CB / 64];
+    for (int r = blockIdx.x; r < cntL; r += gridDim.x) {
+        const int c = listL[r];
+        const int m0 = mem0[c], m1 = mem1[c];
+        const int64_t base = toffL[r];
+        const uint32_t T = (uint32_t)(toffL[r + 1] - base);
+        const int64_t s0 = xadj[m0];
+        const int d0 = (int)(xadj[m0 + 1] - s0);
+        int64_t s1 = 0;
+        int d1 = 0;
+        if (m1 >= 0) { s1 = xadj[m1]; d1 = (int)(xadj[m1 + 1] - s1); }
+        int claimed = 0;
+        for (int idx = threadIdx.x; idx < d0 + d1; idx += CB) {
+            const int64_t e = member_entry(s0, d0, s1, idx);
+            const int cu = map[adj[e]];
+            if (cu == c) continue;
+            const int w = ew ? ew[e] : 1;
+            if (T == 0) { *overflow = 1; break; }
+            uint32_t h = ((uint32_t)cu * 2654435761u) % T;
+            for (uint32_t probe = 0;; probe++) {
+                if (probe == T) { *overflow = 1; break; }  // cannot happen: <= bound keys in 2 * bound slots
+                const int32_t old = atomicCAS(&tkey[base + h], -1, cu);
+                if (old == -1) { claimed++; atomicAdd(&tval[base + h], w); break; }
+                if (old == cu) { atomicAdd(&tval[base + h], w); break; }
+                h = h + 1 == T ? 0 : h + 1;
+            }
+        }
+        const int tot = block_sum<CB>(claimed, s_red);
+        if (threadIdx.x == 0) ccount[c] = tot;
+    }
+}
+
+__global__ __launch_bounds__(CB) void k_crow_large_extract(const int32_t *listL, int cntL, const int64_t *toffL,
+                                                           const int32_t *tkey, const int32_t *tval,
+                                                           const int64_t *cxadj, int32_t *cadj, int32_t *cew)
+{
+    __shared__ int64_t s_scan[CB / 64];
+    for (int r = blockIdx.x; r < cntL; r += gridDim.x) {
+        const int c = listL[r];
+        const int64_t base = toffL[r], T = toffL[r + 1] - base;
+        int64_t out = cxadj[c];
+        for (int64_t j0 = 0; j0 < T; j0 += CB) {
+            const int64_t j = j0 + threadIdx.x;
+            const int occ = j < T && tkey[base + j] >= 0;
+            int64_t tot;
+            const int64_t pos = block_excl_scan<CB>((int64_t)occ, s_scan, tot);
+            if (occ) {
+                cadj[out + pos] = tkey[base + j];
+                cew[out + pos] = tval[base + j];
+            }
+            out += tot;
         }
     }
 }
@@ -476,7 +719,6 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
                          jet_csr *c, int32_t **map_out, int *nc_out, hipStream_t s)
 {
     const int n = f->n;
-    const int64_t nnz = f->nnz;
     const size_t nn = (size_t)std::max(n, 1);
     int32_t *match = (int32_t *)ws_get(ctx, WS_C0, nn * 4);
     int32_t *prop = (int32_t *)ws_get(ctx, WS_C1, nn * 4);
@@ -518,33 +760,61 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     int32_t *map = (int32_t *)hier_alloc(h, nn * 4);
     int32_t *cvw = (int32_t *)hier_alloc(h, ncc * 4);
     int32_t *bound = (int32_t *)ws_get(ctx, WS_C5, ncc * 4);
-    int64_t *toff = (int64_t *)ws_get(ctx, WS_C6, (ncc + 1) * 8);
     int32_t *ccount = (int32_t *)ws_get(ctx, WS_C7, ncc * 4);
+    int32_t *mem0 = (int32_t *)ws_get(ctx, WS_C8, ncc * 4);
+    int32_t *mem1 = (int32_t *)ws_get(ctx, WS_C9, ncc * 4);
+    int32_t *lists = (int32_t *)ws_get(ctx, WS_C12, 2 * ncc * 4 + 64);
     int64_t *cxadj = (int64_t *)hier_alloc(h, (ncc + 1) * 8);
-    if (!map || !cvw || !bound || !toff || !ccount || !cxadj) return JET_ENOMEM;
-    k_coarse_map<<<gv, CB, 0, s>>>(n, match, cid, f->xadj, f->vwgt, map, cvw, bound);
-    // table offsets: exclusive scan of 2 * bound (bounds summed <= nnz)
-    int32_t *bound2 = ccount;
-    k_double<<<grid_for(ctx, nc, CB, 4), CB, 0, s>>>(bound, bound2, nc);
-    scan_excl(bound2, nc, toff, tsum, s);
-    const size_t tsize = (size_t)std::max<int64_t>(2 * nnz, 1);
-    int32_t *tkey = (int32_t *)ws_get(ctx, WS_C8, tsize * 4);
-    int32_t *tval = (int32_t *)ws_get(ctx, WS_C9, tsize * 4);
-    if (!tkey || !tval) return JET_ENOMEM;
-    JET_TRY(hipMemsetAsync(tkey, 0xFF, tsize * 4, s));
-    JET_TRY(hipMemsetAsync(tval, 0, tsize * 4, s));
-    JET_TRY(hipMemsetAsync(ccount, 0, ncc * 4, s));
-    if (nnz > 0)
-        k_contract_insert<<<grid_for(ctx, (nnz + 15) / 16, CB), CB, 0, s>>>(n, nnz, f->xadj, f->adjncy, f->adjwgt, map,
-                                                                          toff, tkey, tval, ccount);
+    if (!map || !cvw || !bound || !ccount || !mem0 || !mem1 || !lists || !cxadj) return JET_ENOMEM;
+    int32_t *listM = lists, *listL = lists + ncc;
+    int32_t *ccnt = lists + 2 * ncc;          // [0] medium rows, [1] large rows, [2] probe overflow
+    int64_t *ltot = (int64_t *)(ccnt + 4);    // table slots of the large rows (bytes 16..23)
+    k_coarse_map<<<gv, CB, 0, s>>>(n, match, cid, f->xadj, f->vwgt, map, cvw, bound, mem0, mem1);
+    JET_TRY(hipMemsetAsync(ccnt, 0, 64, s));
+    k_cclass<<<grid_for(ctx, nc, CB, 4), CB, 0, s>>>(nc, bound, listM, listL, ccnt, ltot);
+    int32_t *hc = (int32_t *)((char *)ctx->pinned + 2448);
+    JET_TRY(hipMemcpyAsync(hc, ccnt, 24, hipMemcpyDeviceToHost, s));
+    JET_TRY(hipStreamSynchronize(s));
+    const int nM = hc[0], nL = hc[1];
+    const int64_t lslots = *(int64_t *)(hc + 4);
+    int64_t *toffL = nullptr;
+    int32_t *tkey = nullptr, *tval = nullptr;
+    if (nL > 0) {
+        toffL = (int64_t *)ws_get(ctx, WS_C6, ((size_t)nL + 1) * 8);
+        tkey = (int32_t *)ws_get(ctx, WS_C10, (size_t)lslots * 4);
+        tval = (int32_t *)ws_get(ctx, WS_C11, (size_t)lslots * 4);
+        if (!toffL || !tkey || !tval) return JET_ENOMEM;
+        JET_TRY(hipMemsetAsync(tkey, 0xFF, (size_t)lslots * 4, s));
+        JET_TRY(hipMemsetAsync(tval, 0, (size_t)lslots * 4, s));
+        k_cl_offsets<<<1, CB, 0, s>>>(listL, nL, bound, toffL);
+        k_crow_large_insert<<<std::min(nL, ctx->num_cu * 4), CB, 0, s>>>(listL, nL, toffL, mem0, mem1, f->xadj,
+                                                                         f->adjncy, f->adjwgt, map, tkey, tval, ccount,
+                                                                         ccnt + 2);
+    }
+    const int gsmall = grid_for(ctx, nc, CB / 8);
+    const size_t lds_m = 2 * CM_T * sizeof(int32_t);
+    k_crow_small<false><<<gsmall, CB, 0, s>>>(nc, bound, mem0, mem1, f->xadj, f->adjncy, f->adjwgt, map, ccount,
+                                               nullptr, nullptr, nullptr, ccnt + 2);
+    if (nM > 0)
+        k_crow_medium<false><<<std::min(nM, ctx->num_cu * 4), CB, lds_m, s>>>(
+            listM, nM, mem0, mem1, f->xadj, f->adjncy, f->adjwgt, map, ccount, nullptr, nullptr, nullptr, ccnt + 2);
     scan_excl(ccount, nc, cxadj, tsum, s);
     JET_TRY(hipMemcpyAsync(hn, cxadj + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    JET_TRY(hipMemcpyAsync(hc, ccnt, 24, hipMemcpyDeviceToHost, s));
     JET_TRY(hipStreamSynchronize(s));
+    if (hc[2]) return JET_EHIP;  // a probe ran past its table: internal error
     const int64_t cnnz = *hn;
     int32_t *cadj = (int32_t *)hier_alloc(h, (size_t)std::max<int64_t>(cnnz, 1) * 4);
     int32_t *cew = (int32_t *)hier_alloc(h, (size_t)std::max<int64_t>(cnnz, 1) * 4);
     if (!cadj || !cew) return JET_ENOMEM;
-    k_contract_extract<<<grid_for(ctx, nc, CB / 8), CB, 0, s>>>(nc, toff, tkey, tval, cxadj, cadj, cew);
+    k_crow_small<true><<<gsmall, CB, 0, s>>>(nc, bound, mem0, mem1, f->xadj, f->adjncy, f->adjwgt, map, ccount,
+                                              cxadj, cadj, cew, ccnt + 2);
+    if (nM > 0)
+        k_crow_medium<true><<<std::min(nM, ctx->num_cu * 4), CB, lds_m, s>>>(
+            listM, nM, mem0, mem1, f->xadj, f->adjncy, f->adjwgt, map, ccount, cxadj, cadj, cew, ccnt + 2);
+    if (nL > 0)
+        k_crow_large_extract<<<std::min(nL, ctx->num_cu * 4), CB, 0, s>>>(listL, nL, toffL, tkey, tval, cxadj, cadj,
+                                                                          cew);
     JET_TRY(hipGetLastError());
     c->n = nc;
     c->reserved = 0;
@@ -560,6 +830,14 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
 static int build_hierarchy(jet_context *ctx, const jet_csr *g, const jet_params *prm, jet_hierarchy *h,
                            hipStream_t s)
 {
+    static bool attr = false;
+    if (!attr) {
+        attr = true;
+        (void)hipFuncSetAttribute((const void *)k_crow_medium<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  65536);
+        (void)hipFuncSetAttribute((const void *)k_crow_medium<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  65536);
+    }
     h->device = ctx->device;
     h->lv.clear();
     h->maps.clear();

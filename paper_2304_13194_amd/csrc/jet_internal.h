@@ -76,7 +76,9 @@ struct KArgs {
     int32_t grid_tab, grid_rbtab, grid_plain;
     Ctl *ctl;
     int64_t *w, *wbest, *resid, *capstart, *hist;
+    int64_t *xbase;   // per split index: cut-off-slot weight before its crossing tile
     int32_t *Blist, *sstar, *splitidx;
+    int32_t *splitpart, *xtile, *vthr;  // split index -> part, crossing tile; per part threshold id
     uint8_t *isA, *isB;
     int32_t *tsum;
     int64_t *esum;
@@ -118,7 +120,7 @@ enum WsSlot {
     WS_P, WS_REC, WS_DEST, WS_LOCK, WS_SLOT, WS_RBD, WS_RSEV, WS_BIN, WS_BSTAT, WS_FILL,
     WS_CTL, WS_PART64, WS_PART32, WS_PART8, WS_HIST, WS_TSUM, WS_ESUM, WS_TRACE,
     WS_DBG_LOCK, WS_H0, WS_H1, WS_C0, WS_C1, WS_C2, WS_C3, WS_C4, WS_C5, WS_C6, WS_C7, WS_C8,
-    WS_C9, WS_C10, WS_C11, WS_KINDS, WS_COUNT = 64
+    WS_C9, WS_C10, WS_C11, WS_KINDS, WS_C12, WS_COUNT = 64
 };
 
 // Grow-only workspace slot; returns nullptr on allocation failure.

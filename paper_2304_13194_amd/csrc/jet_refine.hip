@@ -201,18 +201,20 @@ __global__ __launch_bounds__(BLOCK) void k_ctl_begin(KArgs a)
     __shared__ int s_kind;
     Ctl *c = a.ctl;
     if (threadIdx.x == 0) {
+        Ctl cc = *c;
         int kind;
-        if (c->done || c->stall >= c->stall_limit || (c->max_iters > 0 && c->t >= c->max_iters)) {
-            c->done = 1;
+        if (cc.done || cc.stall >= cc.stall_limit || (cc.max_iters > 0 && cc.t >= cc.max_iters)) {
+            cc.done = 1;
             kind = KIND_DONE;
         } else {
-            c->stall++;
-            if (c->balanced) { kind = KIND_LP; c->lp_id++; c->wcount = 0; c->n_lp++; }
-            else if (c->wcount < c->bmax) { kind = KIND_RW; c->wcount++; c->n_rw++; }
-            else { kind = KIND_RS; c->wcount++; c->n_rs++; }
+            cc.stall++;
+            if (cc.balanced) { kind = KIND_LP; cc.lp_id++; cc.wcount = 0; cc.n_lp++; }
+            else if (cc.wcount < cc.bmax) { kind = KIND_RW; cc.wcount++; cc.n_rw++; }
+            else { kind = KIND_RS; cc.wcount++; cc.n_rs++; }
         }
-        c->kind = kind;
-        clear_accumulators(c);
+        cc.kind = kind;
+        clear_accumulators(&cc);
+        *c = cc;
         s_kind = kind;
     }
     __syncthreads();
@@ -257,26 +259,28 @@ __global__ __launch_bounds__(BLOCK) void k_lp_outputs(KArgs a, uint8_t *inX, uin
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_ctl_end(KArgs a)
+constexpr int CTL_NT = BLOCK;  // threads of the end-of-iteration controller
+
+__global__ __launch_bounds__(CTL_NT) void k_ctl_end(KArgs a)
 {
-    __shared__ uint64_t s_red[BLOCK / 64];
-    __shared__ int64_t s_red64[BLOCK / 64];
+    __shared__ uint64_t s_red[CTL_NT / 64];
+    __shared__ int64_t s_red64[CTL_NT / 64];
     __shared__ int s_improved;
     Ctl *c = a.ctl;
     const int kind = c->kind;
     if (kind == KIND_DONE) return;
     uint64_t m = 0;
-    for (int p = threadIdx.x; p < a.k; p += BLOCK) {
+    for (int p = threadIdx.x; p < a.k; p += CTL_NT) {
         uint64_t x = (uint64_t)a.w[p];
         m = x > m ? x : m;
     }
-    m = block_max_u64<BLOCK>(m, s_red);
+    m = block_max_u64<CTL_NT>(m, s_red);
     // per-block partials of this iteration's kernels
     int64_t px = 0, pm = 0, pdc = 0, pmw = 0;
     uint64_t pdg = 0;
     const int gx = kind == KIND_LP ? a.grid_tab : a.grid_rbtab;
-    for (int i = threadIdx.x; i < gx; i += BLOCK) px += a.bstat[ST_X * BSTAT_STRIDE + i];
-    for (int i = threadIdx.x; i < a.grid_plain; i += BLOCK) {
+    for (int i = threadIdx.x; i < gx; i += CTL_NT) px += a.bstat[ST_X * BSTAT_STRIDE + i];
+    for (int i = threadIdx.x; i < a.grid_plain; i += CTL_NT) {
         pm += a.bstat[ST_M * BSTAT_STRIDE + i];
         pdc += a.bstat[ST_DCUT * BSTAT_STRIDE + i];
         pmw += a.bstat[ST_MW * BSTAT_STRIDE + i];
@@ -284,60 +288,63 @@ __global__ __launch_bounds__(BLOCK) void k_ctl_end(KArgs a)
     }
     int64_t pe = 0, pr = 0, pv = 0;
     if (kind == KIND_LP)
-        for (int i = threadIdx.x; i < a.grid_tab; i += BLOCK) {
+        for (int i = threadIdx.x; i < a.grid_tab; i += CTL_NT) {
             pe += a.bstat[ST_E * BSTAT_STRIDE + i];
             pr += a.bstat[ST_R * BSTAT_STRIDE + i];
             pv += a.bstat[ST_V * BSTAT_STRIDE + i];
         }
-    pe = block_sum<BLOCK>(pe, s_red64);
-    pr = block_sum<BLOCK>(pr, s_red64);
-    pv = block_sum<BLOCK>(pv, s_red64);
-    px = block_sum<BLOCK>(px, s_red64);
-    pm = block_sum<BLOCK>(pm, s_red64);
-    pdc = block_sum<BLOCK>(pdc, s_red64);
-    pmw = block_sum<BLOCK>(pmw, s_red64);
-    pdg = block_sum<BLOCK>(pdg, s_red);
+    pe = block_sum<CTL_NT>(pe, s_red64);
+    pr = block_sum<CTL_NT>(pr, s_red64);
+    pv = block_sum<CTL_NT>(pv, s_red64);
+    px = block_sum<CTL_NT>(px, s_red64);
+    pm = block_sum<CTL_NT>(pm, s_red64);
+    pdc = block_sum<CTL_NT>(pdc, s_red64);
+    pmw = block_sum<CTL_NT>(pmw, s_red64);
+    pdg = block_sum<CTL_NT>(pdg, s_red);
     if (threadIdx.x == 0) {
+        // one load of the whole state, one store: no dependent global round trips
+        Ctl cc = *c;
         const int64_t maxw = (int64_t)m;
         const int nM = (int)pm, nXl = (int)px;
-        c->nX = nXl; c->nM = nM;
-        c->dcut = pdc; c->moved_w = pmw; c->ddigest = pdg;
-        c->prof_e += pe; c->prof_r += pr; c->prof_v += pv;
-        if (a.kinds && c->t < KIND_LOG) a.kinds[c->t] = (int8_t)kind;
-        c->cut += c->dcut;
-        c->digest += c->ddigest;
-        c->maxw = maxw;
-        const int bal = maxw <= c->o;
-        c->balanced = bal;
+        cc.nX = nXl; cc.nM = nM;
+        cc.dcut = pdc; cc.moved_w = pmw; cc.ddigest = pdg;
+        cc.prof_e += pe; cc.prof_r += pr; cc.prof_v += pv;
+        cc.cut += cc.dcut;
+        cc.digest += cc.ddigest;
+        cc.maxw = maxw;
+        const int bal = maxw <= cc.o;
+        cc.balanced = bal;
         int improved = 0;
         if (bal) {
-            if (!c->bal_best) {
+            if (!cc.bal_best) {
                 // a balanced partition always replaces an imbalanced best
-                improved = 1; c->bal_best = 1; c->cut_best = c->cut; c->maxw_best = maxw; c->stall = 0;
-            } else if (c->cut < c->cut_best) {
+                improved = 1; cc.bal_best = 1; cc.cut_best = cc.cut; cc.maxw_best = maxw; cc.stall = 0;
+            } else if (cc.cut < cc.cut_best) {
                 // only a gain beyond the tolerance phi restarts the count
-                if ((int64_t)c->phi_den * c->cut < (int64_t)c->phi_num * c->cut_best) c->stall = 0;
-                improved = 1; c->cut_best = c->cut; c->maxw_best = maxw;
+                if ((int64_t)cc.phi_den * cc.cut < (int64_t)cc.phi_num * cc.cut_best) cc.stall = 0;
+                improved = 1; cc.cut_best = cc.cut; cc.maxw_best = maxw;
             }
-        } else if (!c->bal_best && maxw < c->maxw_best) {
-            improved = 1; c->maxw_best = maxw; c->cut_best = c->cut; c->stall = 0;
+        } else if (!cc.bal_best && maxw < cc.maxw_best) {
+            improved = 1; cc.maxw_best = maxw; cc.cut_best = cc.cut; cc.stall = 0;
         }
-        c->copy_best = improved;
-        if (a.trace && c->t < c->trace_cap) {
+        cc.copy_best = improved;
+        if (a.kinds && cc.t < KIND_LOG) a.kinds[cc.t] = (int8_t)kind;
+        if (a.trace && cc.t < cc.trace_cap) {
             jet_trace_rec r;
-            r.level = c->level; r.t = c->t; r.kind = c->kind;
+            r.level = cc.level; r.t = cc.t; r.kind = kind;
             r.nX = nXl;
-            r.nM = nM; r.stall = c->stall; r.wcount = c->wcount; r.balanced = bal;
-            r.moved_w = c->moved_w; r.cut = c->cut; r.maxw = maxw; r.best_cut = c->cut_best;
-            r.digest = c->digest;
-            a.trace[c->t] = r;
+            r.nM = nM; r.stall = cc.stall; r.wcount = cc.wcount; r.balanced = bal;
+            r.moved_w = cc.moved_w; r.cut = cc.cut; r.maxw = maxw; r.best_cut = cc.cut_best;
+            r.digest = cc.digest;
+            a.trace[cc.t] = r;
         }
-        c->t++;
+        cc.t++;
+        *c = cc;
         s_improved = improved;
     }
     __syncthreads();
     if (s_improved)
-        for (int p = threadIdx.x; p < a.k; p += BLOCK) a.wbest[p] = a.w[p];
+        for (int p = threadIdx.x; p < a.k; p += CTL_NT) a.wbest[p] = a.w[p];
 }
 
 __global__ __launch_bounds__(BLOCK) void k_copy_best(KArgs a)
@@ -400,11 +407,11 @@ struct Meta {
     int64_t s;
 };
 
-template <class Pre, class Row>
-__device__ __forceinline__ void wave_batched8(const int32_t *list, int cnt, int32_t *q, int wid, int nwaves, Pre pre,
-                                              Row row)
+template <int G, class Pre, class Row>
+__device__ __forceinline__ void wave_batched(const int32_t *list, int cnt, int32_t *q, int wid, int nwaves, Pre pre,
+                                             Row row)
 {
-    const int lane = threadIdx.x & 63, g = lane >> 3, gl = lane & 7;
+    const int lane = threadIdx.x & 63, g = lane / G, gl = lane & (G - 1);
     for (int base = wid * 64; base < cnt; base += nwaves * 64) {
         const int i = base + lane;
         Meta m{0, 0, 0, 0, 0};
@@ -417,7 +424,7 @@ __device__ __forceinline__ void wave_batched8(const int32_t *list, int cnt, int3
         if (act) q[__popcll(mask & ((1ull << lane) - 1ull))] = lane;
         lds_fence_wave();
         const int nact = __popcll(mask);
-        for (int sb = 0; sb < nact; sb += 8) {
+        for (int sb = 0; sb < nact; sb += 64 / G) {
             const int slot = sb + g;
             const bool has = slot < nact;
             const int src = q[has ? slot : 0];
@@ -431,6 +438,13 @@ __device__ __forceinline__ void wave_batched8(const int32_t *list, int cnt, int3
         }
         lds_fence_wave();
     }
+}
+
+template <class Pre, class Row>
+__device__ __forceinline__ void wave_batched8(const int32_t *list, int cnt, int32_t *q, int wid, int nwaves, Pre pre,
+                                              Row row)
+{
+    wave_batched<8>(list, cnt, q, wid, nwaves, pre, row);
 }
 
 // Whole block gathers the neighbours of v into `tab` (k entries).
@@ -566,7 +580,7 @@ __device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int 
 // register budget. Group tables are padded to k + 1 ints so the tables of
 // neighbouring groups start in different LDS banks. Block partials of |X|
 // land at offset `boff` of the counter row.
-template <int ROLE>
+template <int ROLE, int GS = 8>
 __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk, int boff)
 {
     if (a.ctl->kind != KIND_LP) return;
@@ -577,15 +591,16 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk, int boff)
     const int stride = a.k + 1;
     GainCount gc;
     if (ROLE == 1) {
-        const int ng = BLOCK / 8;
+        constexpr int RS_ = 32 / GS;
+        const int ng = BLOCK / GS;
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         __syncthreads();
-        int32_t *tab = lds + (threadIdx.x >> 3) * stride;
+        int32_t *tab = lds + (threadIdx.x / GS) * stride;
         int32_t *q = lds + ng * stride + (threadIdx.x >> 6) * 64;
         const int wid = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nblk * (BLOCK / 64);
         for (int c = 1; c < NCLS; c++) {
             if (a.tmap[c] != 1) continue;
-            wave_batched8(
+            wave_batched<GS>(
                 a.bins + a.binoff[c], a.binoff[c + 1] - a.binoff[c], q, wid, nwaves,
                 [&](Meta &m) -> bool {
                     m.ps = a.P[m.v];
@@ -601,19 +616,19 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk, int boff)
                     return true;
                 },
                 [&](const Meta &t, int gl) {
-                    int pu[4], cu[4];
-                    group_conn_row<8, 4>(a, t.s, t.deg, gl, tab, pu, cu);
+                    int pu[RS_], cu[RS_];
+                    group_conn_row<GS, RS_>(a, t.s, t.deg, gl, tab, pu, cu);
                     uint64_t best = 0;
                     int cs = 0;
 #pragma unroll
-                    for (int r = 0; r < 4; r++) {
+                    for (int r = 0; r < RS_; r++) {
                         if (cu[r] > 0) {
                             if (pu[r] == t.ps) cs += cu[r];
                             else { uint64_t k2 = conn_key(cu[r], pu[r]); best = k2 > best ? k2 : best; }
                         }
                     }
-                    best = gmax_u64<8>(best);
-                    cs = gsum<8>(cs);
+                    best = gmax_u64<GS>(best);
+                    cs = gsum<GS>(cs);
                     if (gl == 0) gc.nx += gain_finish(a, t.v, t.ps, best, cs, cn, cd);
                 });
         }
@@ -1011,7 +1026,7 @@ __device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nb
     }
 }
 
-template <int ROLE>
+template <int ROLE, int GS = 8>
 __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int boff)
 {
     extern __shared__ int32_t lds[];
@@ -1022,15 +1037,16 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int boff)
     const int stride = a.k + 1;
     int ncand = 0;
     if (ROLE == 1) {
-        const int ng = BLOCK / 8;
+        constexpr int RS_ = 32 / GS;
+        const int ng = BLOCK / GS;
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         __syncthreads();
-        int32_t *tab = lds + (threadIdx.x >> 3) * stride;
+        int32_t *tab = lds + (threadIdx.x / GS) * stride;
         int32_t *q = lds + ng * stride + (threadIdx.x >> 6) * 64;
         const int wid = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nblk * (BLOCK / 64);
         for (int c = 1; c < NCLS; c++) {
             if (a.tmap[c] != 1) continue;
-            wave_batched8(
+            wave_batched<GS>(
                 a.bins + a.binoff[c], a.binoff[c + 1] - a.binoff[c], q, wid, nwaves,
                 [&](Meta &m) -> bool {
                     m.ps = a.P[m.v];
@@ -1045,12 +1061,12 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int boff)
                     return true;
                 },
                 [&](const Meta &t, int gl) {
-                    int pu[4], cu[4];
-                    group_conn_row<8, 4>(a, t.s, t.deg, gl, tab, pu, cu);
+                    int pu[RS_], cu[RS_];
+                    group_conn_row<GS, RS_>(a, t.s, t.deg, gl, tab, pu, cu);
                     uint64_t best = 0;
                     int cs = 0, sumB = 0, cntB = 0;
 #pragma unroll
-                    for (int r = 0; r < 4; r++) {
+                    for (int r = 0; r < RS_; r++) {
                         if (cu[r] > 0) {
                             if (pu[r] == t.ps) cs += cu[r];
                             else if (a.isB[pu[r]]) {
@@ -1061,10 +1077,10 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int boff)
                             }
                         }
                     }
-                    best = gmax_u64<8>(best);
-                    cs = gsum<8>(cs);
-                    sumB = gsum<8>(sumB);
-                    cntB = gsum<8>(cntB);
+                    best = gmax_u64<GS>(best);
+                    cs = gsum<GS>(cs);
+                    sumB = gsum<GS>(sumB);
+                    cntB = gsum<GS>(cntB);
                     if (gl == 0) rb_finish(a, t.v, t.ps, t.aux, kind, best, cs, sumB, cntB, hseed, ncand);
                 });
         }
@@ -1101,34 +1117,30 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int boff)
     if (threadIdx.x == 0) a.bstat[ST_X * BSTAT_STRIDE + boff + blockIdx.x] = ncand;
 }
 
-// Per-(part, slot) weight histogram of the eligible vertices; one wave per
-// tile, accumulated in LDS when k * NSLOT int32 counters fit.
-__global__ __launch_bounds__(64) void k_rb_hist(KArgs a, int use_lds)
+// Per-(part, slot) weight histogram of the eligible vertices. Each block
+// accumulates its grid-stride share in LDS when k * NSLOT int32 counters fit,
+// then adds its nonzero counters to the global histogram.
+__global__ __launch_bounds__(BLOCK) void k_rb_hist(KArgs a, int use_lds)
 {
     extern __shared__ int32_t h[];
     const int kind = a.ctl->kind;
     if (kind != KIND_RW && kind != KIND_RS) return;
     const int nh = a.k * NSLOT;
     if (use_lds) {
-        for (int i = threadIdx.x; i < nh; i += 64) h[i] = 0;
-        lds_fence_wave();
+        for (int i = threadIdx.x; i < nh; i += BLOCK) h[i] = 0;
+        __syncthreads();
     }
-    for (int tile = blockIdx.x; tile < a.ntile; tile += gridDim.x) {
-        const int v0 = tile * TILE;
-        for (int ch = 0; ch < TILE; ch += 64) {
-            const int v = v0 + ch + threadIdx.x;
-            if (v >= a.n) break;
-            const int sl = a.slot[v];
-            if (sl == 255) continue;
-            const int idx = a.P[v] * NSLOT + sl;
-            const int vwv = a.vw ? a.vw[v] : 1;
-            if (use_lds) atomicAdd(&h[idx], vwv);
-            else atomicAdd((unsigned long long *)&a.hist[idx], (unsigned long long)(int64_t)vwv);
-        }
+    for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) {
+        const int sl = a.slot[v];
+        if (sl == 255) continue;
+        const int idx = a.P[v] * NSLOT + sl;
+        const int vwv = a.vw ? a.vw[v] : 1;
+        if (use_lds) atomicAdd(&h[idx], vwv);
+        else atomicAdd((unsigned long long *)&a.hist[idx], (unsigned long long)(int64_t)vwv);
     }
     if (use_lds) {
-        lds_fence_wave();
-        for (int i = threadIdx.x; i < nh; i += 64)
+        __syncthreads();
+        for (int i = threadIdx.x; i < nh; i += BLOCK)
             if (h[i]) atomicAdd((unsigned long long *)&a.hist[i], (unsigned long long)(int64_t)h[i]);
     }
 }
@@ -1167,7 +1179,10 @@ __global__ __launch_bounds__(BLOCK) void k_rb_cutoff(KArgs a)
         }
         int32_t tot;
         const int32_t pos = block_excl_scan<BLOCK>((int32_t)split, s_scan, tot);
-        if (p < a.k) a.splitidx[p] = split ? carry + pos : -1;
+        if (p < a.k) {
+            a.splitidx[p] = split ? carry + pos : -1;
+            if (split) a.splitpart[carry + pos] = p;
+        }
         carry += tot;
     }
     if (threadIdx.x == 0) c->nsplit = carry;
@@ -1187,9 +1202,10 @@ __global__ __launch_bounds__(BLOCK) void k_rb_cutoff(KArgs a)
     }
 }
 
-// Per tile (one wave) and split part: weight of the tile's vertices that sit
-// in the part's cut-off slot. Stored as tsum[j * ntile + tile].
-__global__ __launch_bounds__(64) void k_rb_tilesum(KArgs a)
+// Per tile of TILE vertices (one block) and split part j: weight of the
+// tile's eligible vertices that sit in the part's cut-off slot, stored as
+// tsum[j * ntile + tile].
+__global__ __launch_bounds__(BLOCK) void k_rb_tilesum(KArgs a)
 {
     extern __shared__ int32_t acc[];
     const int kind = a.ctl->kind;
@@ -1197,103 +1213,122 @@ __global__ __launch_bounds__(64) void k_rb_tilesum(KArgs a)
     const int nsplit = a.ctl->nsplit;
     if (nsplit == 0) return;
     for (int tile = blockIdx.x; tile < a.ntile; tile += gridDim.x) {
-        for (int j = threadIdx.x; j < nsplit; j += 64) acc[j] = 0;
-        lds_fence_wave();
+        for (int j = threadIdx.x; j < nsplit; j += BLOCK) acc[j] = 0;
+        __syncthreads();
         const int v0 = tile * TILE;
-        for (int ch = 0; ch < TILE; ch += 64) {
-            const int v = v0 + ch + threadIdx.x;
-            if (v < a.n) {
-                const int sl = a.slot[v];
-                if (sl != 255) {
-                    const int p = a.P[v];
-                    if (sl == a.sstar[p]) atomicAdd(&acc[a.splitidx[p]], a.vw ? a.vw[v] : 1);
-                }
-            }
+        for (int i = threadIdx.x; i < TILE; i += BLOCK) {
+            const int v = v0 + i;
+            if (v >= a.n) break;
+            const int sl = a.slot[v];
+            if (sl == 255) continue;
+            const int p = a.P[v];
+            if (sl == a.sstar[p]) atomicAdd(&acc[a.splitidx[p]], a.vw ? a.vw[v] : 1);
         }
-        lds_fence_wave();
-        for (int j = threadIdx.x; j < nsplit; j += 64) a.tsum[(int64_t)j * a.ntile + tile] = acc[j];
-        lds_fence_wave();
+        __syncthreads();
+        for (int j = threadIdx.x; j < nsplit; j += BLOCK) a.tsum[(int64_t)j * a.ntile + tile] = acc[j];
+        __syncthreads();
     }
 }
 
-// Exclusive scan over tiles of one split part per block.
+// Per split part (one block): exclusive scan of its tile sums; the tile in
+// which the running weight first reaches the residual is the only one that
+// needs an ordered look (every cut-off-slot vertex of an earlier tile is
+// evicted, none of a later one). Stores that tile and the weight before it.
 __global__ __launch_bounds__(BLOCK) void k_rb_tilescan(KArgs a)
 {
-    __shared__ int32_t s_scan[BLOCK / 64];
+    __shared__ int64_t s_scan[BLOCK / 64];
     const int kind = a.ctl->kind;
     if (kind != KIND_RW && kind != KIND_RS) return;
     const int nsplit = a.ctl->nsplit;
     for (int j = blockIdx.x; j < nsplit; j += gridDim.x) {
-        int32_t *row = a.tsum + (int64_t)j * a.ntile;
-        int32_t carry = 0;
+        const int32_t *row = a.tsum + (int64_t)j * a.ntile;
+        const int64_t resid = a.resid[a.splitpart[j]];
+        int64_t carry = 0;
         for (int base = 0; base < a.ntile; base += BLOCK) {
             const int i = base + threadIdx.x;
-            const int32_t x = i < a.ntile ? row[i] : 0;
-            int32_t tot;
-            const int32_t ex = block_excl_scan<BLOCK>(x, s_scan, tot);
-            if (i < a.ntile) row[i] = carry + ex;
+            const int64_t x = i < a.ntile ? row[i] : 0;
+            int64_t tot;
+            const int64_t before = carry + block_excl_scan<BLOCK>(x, s_scan, tot);
+            if (x > 0 && before < resid && resid <= before + x) {
+                a.xtile[j] = i;
+                a.xbase[j] = before;
+            }
             carry += tot;
         }
     }
 }
 
-// Ordered eviction inside each tile (one wave): a candidate in a slot below
-// its part's cut-off is evicted; one in the cut-off slot is evicted when the
-// weight of earlier (smaller id) cut-off-slot vertices of its part is below
-// the residual. Jetrw emits the move; Jetrs marks the vertex and sums the
-// tile's evicted weight.
-__global__ __launch_bounds__(64) void k_rb_select(KArgs a)
+// Per split part (one block): inside its crossing tile, the cut-off-slot
+// vertices in id order are evicted while the weight before them is below the
+// residual; the last evicted id is the part's threshold.
+__global__ __launch_bounds__(BLOCK) void k_rb_threshold(KArgs a)
 {
-    extern __shared__ int32_t run[];
+    __shared__ int64_t s_scan[BLOCK / 64];
+    __shared__ uint64_t s_red[BLOCK / 64];
+    constexpr int PER = TILE / BLOCK;
     const int kind = a.ctl->kind;
     if (kind != KIND_RW && kind != KIND_RS) return;
     const int nsplit = a.ctl->nsplit;
-    const int l = threadIdx.x;
+    for (int j = blockIdx.x; j < nsplit; j += gridDim.x) {
+        const int p = a.splitpart[j];
+        const int ss = a.sstar[p];
+        const int64_t resid = a.resid[p], base = a.xbase[j];
+        const int v0 = a.xtile[j] * TILE + threadIdx.x * PER;
+        int wv[PER];
+        int64_t mine = 0;
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int v = v0 + q;
+            wv[q] = 0;
+            if (v < a.n && a.slot[v] == ss && a.P[v] == p) wv[q] = a.vw ? a.vw[v] : 1;
+            mine += wv[q];
+        }
+        int64_t tot;
+        int64_t before = base + block_excl_scan<BLOCK>(mine, s_scan, tot);
+        uint64_t last = 0;  // (last evicted id + 1), 0 = none
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            if (wv[q] > 0 && before < resid) last = (uint64_t)(v0 + q) + 1;
+            before += wv[q];
+        }
+        last = block_max_u64<BLOCK>(last, s_red);
+        if (threadIdx.x == 0) a.vthr[p] = (int32_t)last - 1;
+    }
+}
+
+// Eviction decision for every eligible vertex (one block per tile): evicted
+// when its slot is below the part's cut-off, or equal with an id no larger
+// than the part's threshold. Jetrw moves it to its chosen destination; Jetrs
+// marks it and sums the tile's evicted weight.
+__global__ __launch_bounds__(BLOCK) void k_rb_mark(KArgs a)
+{
+    __shared__ int64_t s_red[BLOCK / 64];
+    const int kind = a.ctl->kind;
+    if (kind != KIND_RW && kind != KIND_RS) return;
     for (int tile = blockIdx.x; tile < a.ntile; tile += gridDim.x) {
-        for (int j = l; j < nsplit; j += 64) run[j] = a.tsum[(int64_t)j * a.ntile + tile];
-        lds_fence_wave();
         int64_t esum = 0;
         const int v0 = tile * TILE;
-        for (int ch = 0; ch < TILE; ch += 64) {
-            const int v = v0 + ch + l;
-            const bool valid = v < a.n;
-            int sl = 255, p = 0, vwv = 0;
-            if (valid) {
-                sl = a.slot[v];
-                if (sl != 255) { p = a.P[v]; vwv = a.vw ? a.vw[v] : 1; }
-            }
-            const bool cand = sl != 255;
-            const int ss = cand ? a.sstar[p] : -1;
-            bool ev = cand && sl < ss;
-            const bool split = cand && sl == ss;
-            uint64_t rem = __ballot(split);
-            while (rem) {
-                const int leader = __ffsll((unsigned long long)rem) - 1;
-                const int pl = __shfl(p, leader, 64);
-                const bool in = split && p == pl;
-                const uint64_t grp = __ballot(in);
-                const int x = in ? vwv : 0;
-                const int inc = wave_incl_scan(x);
-                const int j = a.splitidx[pl];
-                const int base = run[j];
-                if (in) ev = (int64_t)base + inc - x < a.resid[pl];
-                lds_fence_wave();
-                if (l == 63) run[j] = base + inc;
-                lds_fence_wave();
-                rem &= ~grp;
+        for (int i = threadIdx.x; i < TILE; i += BLOCK) {
+            const int v = v0 + i;
+            if (v >= a.n) break;
+            const int sl = a.slot[v];
+            bool ev = false;
+            if (sl != 255) {
+                const int p = a.P[v];
+                const int ss = a.sstar[p];
+                ev = sl < ss || (sl == ss && v <= a.vthr[p]);
             }
             if (kind == KIND_RW) {
                 if (ev) a.dest[v] = a.rbd[v];
             } else {
-                if (valid) a.rsev[v] = ev;
-                if (ev) esum += vwv;
+                a.rsev[v] = ev;
+                if (ev) esum += a.vw ? a.vw[v] : 1;
             }
         }
         if (kind == KIND_RS) {
-            esum = gsum<64>(esum);
-            if (l == 0) a.esum[tile] = esum;
+            esum = block_sum<BLOCK>(esum, s_red);
+            if (threadIdx.x == 0) a.esum[tile] = esum;
         }
-        lds_fence_wave();
     }
 }
 
@@ -1313,35 +1348,41 @@ __global__ __launch_bounds__(BLOCK) void k_rs_scan(KArgs a)
     }
 }
 
-// Jetrs cookie-cutter: evicted vertices in id order take consecutive
-// positions (exclusive prefix of their weights); position pos goes to the
-// valid destination whose capacity interval [capstart, capstart + cap) holds
-// it; positions beyond the total capacity stay.
-__global__ __launch_bounds__(64) void k_rs_assign(KArgs a)
+// Jetrs cookie-cutter (one block per tile, PER consecutive vertices per
+// thread): evicted vertices in id order take consecutive positions (exclusive
+// prefix of their weights); position pos goes to the valid destination whose
+// capacity interval [capstart, capstart + cap) holds it; positions beyond the
+// total capacity stay.
+__global__ __launch_bounds__(BLOCK) void k_rs_assign(KArgs a)
 {
+    __shared__ int64_t s_scan[BLOCK / 64];
+    constexpr int PER = TILE / BLOCK;
     if (a.ctl->kind != KIND_RS) return;
     const int nB = a.ctl->nB;
     const int64_t total = a.ctl->total_cap;
-    const int l = threadIdx.x;
     for (int tile = blockIdx.x; tile < a.ntile; tile += gridDim.x) {
-        int64_t runpos = a.esum[tile];
-        const int v0 = tile * TILE;
-        for (int ch = 0; ch < TILE; ch += 64) {
-            const int v = v0 + ch + l;
-            const bool valid = v < a.n;
-            const bool ev = valid && a.rsev[v];
-            const int64_t x = ev ? (a.vw ? a.vw[v] : 1) : 0;
-            const int64_t inc = wave_incl_scan(x);
-            const int64_t pos = runpos + inc - x;
-            runpos += __shfl(inc, 63, 64);
-            if (ev && pos < total) {
+        const int v0 = tile * TILE + threadIdx.x * PER;
+        int wv[PER];
+        int64_t mine = 0;
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int v = v0 + q;
+            wv[q] = (v < a.n && a.rsev[v]) ? (a.vw ? a.vw[v] : 1) : 0;
+            mine += wv[q];
+        }
+        int64_t tot;
+        int64_t pos = a.esum[tile] + block_excl_scan<BLOCK>(mine, s_scan, tot);
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            if (wv[q] > 0 && pos < total) {
                 int lo = 0, hi = nB;  // largest i with capstart[i] <= pos (capstart[0] = 0 <= pos)
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
                     if (a.capstart[mid] <= pos) lo = mid; else hi = mid;
                 }
-                a.dest[v] = a.Blist[lo];
+                a.dest[v0 + q] = a.Blist[lo];
             }
+            pos += wv[q];
         }
     }
 }
@@ -1450,11 +1491,18 @@ static void plan_roles(const jet_context *ctx, KArgs &a, const int32_t *cnt, Pla
     pl.grid_tile = std::max(1, std::min(a.ntile, ctx->num_cu * 8));
 }
 
+// Up to this k the 8-lane role runs with 4 lanes per vertex (64 tables of
+// k + 1 ints per block fit in 32 KiB): twice the vertices in flight per wave.
+constexpr int K_G4 = 120;
+
 static void launch_gain(const Plan &pl, hipStream_t s)
 {
     const KArgs &t = pl.tab;
     const size_t st = (size_t)(t.k + 1) * 4;
-    if (t.gS) k_gain<1><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS, 0);
+    if (t.gS) {
+        if (t.k <= K_G4) k_gain<1, 4><<<t.gS, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, t.gS, 0);
+        else k_gain<1, 8><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS, 0);
+    }
     if (t.gM) k_gain<2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM, t.gS);
     if (t.gL) k_gain<3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL, t.gS + t.gM);
 }
@@ -1463,16 +1511,32 @@ static void launch_rb_loss(const Plan &pl, hipStream_t s)
 {
     const KArgs &t = pl.tab;
     const size_t st = (size_t)(t.k + 1) * 4;
-    if (t.gS) k_rb_loss<1><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS, 0);
+    if (t.gS) {
+        if (t.k <= K_G4) k_rb_loss<1, 4><<<t.gS, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, t.gS, 0);
+        else k_rb_loss<1, 8><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS, 0);
+    }
     if (t.gM) k_rb_loss<2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM, t.gS);
     if (t.gL) k_rb_loss<3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL, t.gS + t.gM);
     if (t.gZ) k_rb_loss<4><<<t.gZ, BLOCK, 0, s>>>(t, t.gZ, t.gS + t.gM + t.gL);
 }
 
+// Histogram, cut-off slots, ordered selection and (Jetrs) the cookie-cutter.
+static void launch_rb_select(const Plan &pl, hipStream_t s)
+{
+    const KArgs &p = pl.plain;
+    k_rb_hist<<<pl.grid_hist, BLOCK, pl.hist_lds ? (size_t)p.k * NSLOT * 4 : 0, s>>>(p, pl.hist_lds);
+    k_rb_cutoff<<<1, BLOCK, 0, s>>>(p);
+    k_rb_tilesum<<<pl.grid_tile, BLOCK, (size_t)p.k * 4, s>>>(p);
+    k_rb_tilescan<<<std::min(p.k, 1024), BLOCK, 0, s>>>(p);
+    k_rb_threshold<<<std::min(p.k, 1024), BLOCK, 0, s>>>(p);
+    k_rb_mark<<<pl.grid_tile, BLOCK, 0, s>>>(p);
+    k_rs_scan<<<1, BLOCK, 0, s>>>(p);
+    k_rs_assign<<<pl.grid_tile, BLOCK, 0, s>>>(p);
+}
+
 static void launch_iteration(const Plan &pl, hipStream_t s, bool lp_kernels, bool rb_kernels,
                              hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr)
 {
-    const KArgs &t = pl.tab;
     const KArgs &p = pl.plain;
     k_ctl_begin<<<1, BLOCK, 0, s>>>(p);
     if (lp_kernels) {
@@ -1483,17 +1547,11 @@ static void launch_iteration(const Plan &pl, hipStream_t s, bool lp_kernels, boo
     }
     if (rb_kernels) {
         launch_rb_loss(pl, s);
-        k_rb_hist<<<pl.grid_hist, 64, pl.hist_lds ? (size_t)p.k * NSLOT * 4 : 0, s>>>(p, pl.hist_lds);
-        k_rb_cutoff<<<1, BLOCK, 0, s>>>(p);
-        k_rb_tilesum<<<pl.grid_tile, 64, (size_t)p.k * 4, s>>>(p);
-        k_rb_tilescan<<<std::min(p.k, 1024), BLOCK, 0, s>>>(p);
-        k_rb_select<<<pl.grid_tile, 64, (size_t)p.k * 4, s>>>(p);
-        k_rs_scan<<<1, BLOCK, 0, s>>>(p);
-        k_rs_assign<<<pl.grid_tile, 64, 0, s>>>(p);
+        launch_rb_select(pl, s);
     }
     if (pl.grid_plain) k_dcut<<<pl.grid_plain, BLOCK, 0, s>>>(p);
     k_apply<<<pl.grid_flat, BLOCK, (size_t)p.k * 4, s>>>(p);
-    k_ctl_end<<<1, BLOCK, 0, s>>>(p);
+    k_ctl_end<<<1, CTL_NT, 0, s>>>(p);
     k_copy_best<<<pl.grid_flat, BLOCK, 0, s>>>(p);
 }
 
@@ -1502,16 +1560,17 @@ static void set_lds_limits()
     static bool done = false;
     if (done) return;
     done = true;
-    (void)hipFuncSetAttribute((const void *)k_gain<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_gain<1, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_gain<1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_gain<2>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_gain<3>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-    (void)hipFuncSetAttribute((const void *)k_rb_loss<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<1, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_loss<2>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_loss<3>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_apply, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_init_vertices, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_tilesum, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-    (void)hipFuncSetAttribute((const void *)k_rb_select, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_hist, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
 }
 
@@ -1596,8 +1655,8 @@ static int setup(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     a.bstat = (int64_t *)ws_get(ctx, WS_BSTAT, sizeof(int64_t) * NSTAT * BSTAT_STRIDE);
     int32_t *fill = (int32_t *)ws_get(ctx, WS_FILL, sizeof(int32_t) * NCLS);
     a.ctl = (Ctl *)ws_get(ctx, WS_CTL, sizeof(Ctl) + 64);
-    int64_t *p64 = (int64_t *)ws_get(ctx, WS_PART64, sizeof(int64_t) * (4 * (size_t)k + 8));
-    int32_t *p32 = (int32_t *)ws_get(ctx, WS_PART32, sizeof(int32_t) * (3 * (size_t)k + 8));
+    int64_t *p64 = (int64_t *)ws_get(ctx, WS_PART64, sizeof(int64_t) * (5 * (size_t)k + 8));
+    int32_t *p32 = (int32_t *)ws_get(ctx, WS_PART32, sizeof(int32_t) * (6 * (size_t)k + 8));
     uint8_t *p8 = (uint8_t *)ws_get(ctx, WS_PART8, 2 * (size_t)k + 16);
     a.hist = (int64_t *)ws_get(ctx, WS_HIST, sizeof(int64_t) * (size_t)k * NSLOT);
     a.ntile = std::max(1, div_up(n, TILE));
@@ -1607,8 +1666,9 @@ static int setup(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     if (!a.P || !a.rec || !a.dest || !a.lock || !a.slot || !a.rbd || !a.rsev || !bins || !a.bstat || !fill ||
         !a.ctl || !p64 || !p32 || !p8 || !a.hist || !a.tsum || !a.esum || !a.kinds)
         return JET_ENOMEM;
-    a.w = p64; a.wbest = p64 + k; a.resid = p64 + 2 * k; a.capstart = p64 + 3 * k;
-    a.Blist = p32; a.sstar = p32 + k; a.splitidx = p32 + 2 * k;
+    a.w = p64; a.wbest = p64 + k; a.resid = p64 + 2 * k; a.xbase = p64 + 3 * k; a.capstart = p64 + 4 * k;
+    a.Blist = p32; a.sstar = p32 + k; a.splitidx = p32 + 2 * k; a.splitpart = p32 + 3 * k; a.xtile = p32 + 4 * k;
+    a.vthr = p32 + 5 * k;
     a.isA = p8; a.isB = p8 + k;
     a.best = part;
     a.trace = trace_dev;
@@ -1935,13 +1995,7 @@ extern "C" int jet_rebalance_step(jet_context *ctx, const jet_csr *g, const jet_
     k_step_defaults<<<pl.grid_flat, BLOCK, 0, s>>>(p, part);
     k_force_step<<<1, BLOCK, 0, s>>>(p, kind, t, nullptr);
     launch_rb_loss(pl, s);
-    k_rb_hist<<<pl.grid_hist, 64, pl.hist_lds ? (size_t)p.k * NSLOT * 4 : 0, s>>>(p, pl.hist_lds);
-    k_rb_cutoff<<<1, BLOCK, 0, s>>>(p);
-    k_rb_tilesum<<<pl.grid_tile, 64, (size_t)p.k * 4, s>>>(p);
-    k_rb_tilescan<<<std::min(p.k, 1024), BLOCK, 0, s>>>(p);
-    k_rb_select<<<pl.grid_tile, 64, (size_t)p.k * 4, s>>>(p);
-    k_rs_scan<<<1, BLOCK, 0, s>>>(p);
-    k_rs_assign<<<pl.grid_tile, 64, 0, s>>>(p);
+    launch_rb_select(pl, s);
     JET_TRY(hipGetLastError());
     JET_TRY(hipMemcpyAsync(dest, p.dest, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
     JET_TRY(hipStreamSynchronize(s));

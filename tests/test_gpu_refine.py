@@ -50,6 +50,7 @@ def cases():
         ("stencil12_k8_l2", I.stencil27(12, 12, 12), 8, 2),
         ("rmat12_k32_w", I.rmat(12, 8, 5), 32, 0),
         ("rmat14_k64_hubs", I.rmat(14, 16, 6), 64, 1),
+        ("rmat12_k200", I.rmat(12, 8, 9), 200, 0),
         ("rmat12_k600", I.rmat(12, 8, 7), 600, 0),
         ("rmat12_k5000", I.rmat(12, 8, 8), 5000, 0),
         ("star3000_k3", star(3000), 3, 0),
