@@ -20,7 +20,7 @@ constexpr int TILE = 2048;  // vertices per tile of the ordered-selection kernel
 // rows, 7 visited vertices.
 enum Stat { ST_X = 0, ST_M = 1, ST_DCUT = 2, ST_MW = 3, ST_DIG = 4, ST_E = 5, ST_R = 6, ST_V = 7, NSTAT = 8 };
 constexpr int KIND_LOG = 1 << 16;  // iterations whose kind is logged
-constexpr int BSTAT_STRIDE = 16384;  // >= any row-kernel grid
+constexpr int NSHARD = 64;  // shards per counter row
 
 enum Kind { KIND_DONE = 0, KIND_LP = 1, KIND_RW = 2, KIND_RS = 3 };
 // Degree classes: 0 isolated, 1 small (<= 32), 2 medium (<= 1024), 3 large.
@@ -72,7 +72,7 @@ struct KArgs {
     uint8_t *rsev;   // Jetrs: evicted flag
     const int32_t *bins;   // vertex ids grouped by degree class
     int32_t binoff[NCLS + 1];
-    int64_t *bstat;  // per-block partial counters [NSTAT][BSTAT_STRIDE], summed by the controller
+    int64_t *bstat;  // iteration counters [NSTAT][NSHARD], summed by the controller
     int32_t grid_tab, grid_rbtab, grid_plain;
     Ctl *ctl;
     int64_t *w, *wbest, *resid, *capstart, *hist;

@@ -136,28 +136,6 @@ __global__ __launch_bounds__(BLOCK) void k_fill_bins(KArgs a, int32_t *bins, int
     }
 }
 
-// Derived loop state after the set-up passes.
-__global__ __launch_bounds__(BLOCK) void k_ctl_setup(KArgs a, int64_t W, int64_t o, int64_t sigma)
-{
-    __shared__ uint64_t s_red[BLOCK / 64];
-    Ctl *c = a.ctl;
-    uint64_t m = 0;
-    for (int p = threadIdx.x; p < a.k; p += BLOCK) {
-        uint64_t x = (uint64_t)a.w[p];
-        m = x > m ? x : m;
-        a.wbest[p] = a.w[p];
-    }
-    m = block_max_u64<BLOCK>(m, s_red);
-    if (threadIdx.x == 0) {
-        c->W = W; c->o = o; c->sigma = sigma;
-        c->maxw = (int64_t)m;
-        c->balanced = (int64_t)m <= o;
-        c->bal_best = c->balanced;
-        c->cut_best = c->cut;
-        c->maxw_best = c->maxw;
-    }
-}
-
 // -------------------------------------------------------------- controller --
 
 // Oversized parts A = {w > o}, valid destinations B = {w <= sigma} listed in
@@ -196,30 +174,69 @@ __device__ __forceinline__ void clear_accumulators(Ctl *c)
     c->dcut = 0; c->moved_w = 0; c->ddigest = 0;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_ctl_begin(KArgs a)
+// Decides the kind of the next iteration from the loop state (thread 0):
+// stop after stall_limit iterations without a new best (or at max_iters);
+// Jetlp while balanced, else Jetrw for b_max iterations, then Jetrs. The
+// stall counter rises here, at the start of every iteration.
+__device__ __forceinline__ int ctl_next(Ctl &cc)
 {
-    __shared__ int s_kind;
+    int kind;
+    if (cc.done || cc.stall >= cc.stall_limit || (cc.max_iters > 0 && cc.t >= cc.max_iters)) {
+        cc.done = 1;
+        kind = KIND_DONE;
+    } else {
+        cc.stall++;
+        if (cc.balanced) { kind = KIND_LP; cc.lp_id++; cc.wcount = 0; cc.n_lp++; }
+        else if (cc.wcount < cc.bmax) { kind = KIND_RW; cc.wcount++; cc.n_rw++; }
+        else { kind = KIND_RS; cc.wcount++; cc.n_rs++; }
+    }
+    cc.kind = kind;
+    clear_accumulators(&cc);
+    return kind;
+}
+
+// Whole-block part of starting an iteration: clear the counter shards and,
+// for rebalancing, build A, B and clear the histogram.
+__device__ __forceinline__ void begin_iteration(const KArgs &a, int kind)
+{
+    for (int i = threadIdx.x; i < NSTAT * NSHARD; i += blockDim.x) a.bstat[i] = 0;
+    if (kind == KIND_RW || kind == KIND_RS) rb_prepare(a);
+}
+
+// Derived loop state after the set-up passes.
+__global__ __launch_bounds__(BLOCK) void k_ctl_setup(KArgs a, int64_t W, int64_t o, int64_t sigma)
+{
+    __shared__ uint64_t s_red[BLOCK / 64];
     Ctl *c = a.ctl;
+    uint64_t m = 0;
+    for (int p = threadIdx.x; p < a.k; p += BLOCK) {
+        uint64_t x = (uint64_t)a.w[p];
+        m = x > m ? x : m;
+        a.wbest[p] = a.w[p];
+    }
+    m = block_max_u64<BLOCK>(m, s_red);
+    __shared__ int s_next;
     if (threadIdx.x == 0) {
         Ctl cc = *c;
-        int kind;
-        if (cc.done || cc.stall >= cc.stall_limit || (cc.max_iters > 0 && cc.t >= cc.max_iters)) {
-            cc.done = 1;
-            kind = KIND_DONE;
-        } else {
-            cc.stall++;
-            if (cc.balanced) { kind = KIND_LP; cc.lp_id++; cc.wcount = 0; cc.n_lp++; }
-            else if (cc.wcount < cc.bmax) { kind = KIND_RW; cc.wcount++; cc.n_rw++; }
-            else { kind = KIND_RS; cc.wcount++; cc.n_rs++; }
-        }
-        cc.kind = kind;
-        clear_accumulators(&cc);
+        cc.W = W; cc.o = o; cc.sigma = sigma;
+        cc.maxw = (int64_t)m;
+        cc.balanced = (int64_t)m <= o;
+        cc.bal_best = cc.balanced;
+        cc.cut_best = cc.cut;
+        cc.maxw_best = cc.maxw;
+        s_next = ctl_next(cc);  // iteration 0
         *c = cc;
-        s_kind = kind;
     }
     __syncthreads();
-    const int kind = s_kind;
-    if (kind == KIND_RW || kind == KIND_RS) rb_prepare(a);
+    begin_iteration(a, s_next);
+}
+
+// Adds a block's partial counter into one of NSHARD shards of its stat row
+// (shards spread the atomics; the controller sums NSHARD values per row).
+__device__ __forceinline__ void shard_add(const KArgs &a, int row, int64_t val)
+{
+    if (val) atomicAdd((unsigned long long *)&a.bstat[row * NSHARD + (blockIdx.x & (NSHARD - 1))],
+                       (unsigned long long)val);
 }
 
 // Single-step entry points: force one iteration of `kind` at index t. For
@@ -237,7 +254,7 @@ __global__ __launch_bounds__(BLOCK) void k_force_step(KArgs a, int kind, int t, 
         for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) a.lock[v] = locked[v] ? 0 : -1;
     if (blockIdx.x == 0) {
         __syncthreads();
-        if (kind == KIND_RW || kind == KIND_RS) rb_prepare(a);
+        begin_iteration(a, kind);
     }
 }
 
@@ -265,7 +282,7 @@ __global__ __launch_bounds__(CTL_NT) void k_ctl_end(KArgs a)
 {
     __shared__ uint64_t s_red[CTL_NT / 64];
     __shared__ int64_t s_red64[CTL_NT / 64];
-    __shared__ int s_improved;
+    __shared__ int s_improved, s_next;
     Ctl *c = a.ctl;
     const int kind = c->kind;
     if (kind == KIND_DONE) return;
@@ -275,24 +292,23 @@ __global__ __launch_bounds__(CTL_NT) void k_ctl_end(KArgs a)
         m = x > m ? x : m;
     }
     m = block_max_u64<CTL_NT>(m, s_red);
-    // per-block partials of this iteration's kernels
+    // this iteration's counters (NSHARD shards per row)
     int64_t px = 0, pm = 0, pdc = 0, pmw = 0;
     uint64_t pdg = 0;
-    const int gx = kind == KIND_LP ? a.grid_tab : a.grid_rbtab;
-    for (int i = threadIdx.x; i < gx; i += CTL_NT) px += a.bstat[ST_X * BSTAT_STRIDE + i];
-    for (int i = threadIdx.x; i < a.grid_plain; i += CTL_NT) {
-        pm += a.bstat[ST_M * BSTAT_STRIDE + i];
-        pdc += a.bstat[ST_DCUT * BSTAT_STRIDE + i];
-        pmw += a.bstat[ST_MW * BSTAT_STRIDE + i];
-        pdg += (uint64_t)a.bstat[ST_DIG * BSTAT_STRIDE + i];
-    }
     int64_t pe = 0, pr = 0, pv = 0;
-    if (kind == KIND_LP)
-        for (int i = threadIdx.x; i < a.grid_tab; i += CTL_NT) {
-            pe += a.bstat[ST_E * BSTAT_STRIDE + i];
-            pr += a.bstat[ST_R * BSTAT_STRIDE + i];
-            pv += a.bstat[ST_V * BSTAT_STRIDE + i];
+    if (threadIdx.x < NSHARD) {
+        const int i = threadIdx.x;
+        px = a.bstat[ST_X * NSHARD + i];
+        pm = a.bstat[ST_M * NSHARD + i];
+        pdc = a.bstat[ST_DCUT * NSHARD + i];
+        pmw = a.bstat[ST_MW * NSHARD + i];
+        pdg = (uint64_t)a.bstat[ST_DIG * NSHARD + i];
+        if (kind == KIND_LP) {
+            pe = a.bstat[ST_E * NSHARD + i];
+            pr = a.bstat[ST_R * NSHARD + i];
+            pv = a.bstat[ST_V * NSHARD + i];
         }
+    }
     pe = block_sum<CTL_NT>(pe, s_red64);
     pr = block_sum<CTL_NT>(pr, s_red64);
     pv = block_sum<CTL_NT>(pv, s_red64);
@@ -339,12 +355,14 @@ __global__ __launch_bounds__(CTL_NT) void k_ctl_end(KArgs a)
             a.trace[cc.t] = r;
         }
         cc.t++;
+        s_next = ctl_next(cc);
         *c = cc;
         s_improved = improved;
     }
     __syncthreads();
     if (s_improved)
         for (int p = threadIdx.x; p < a.k; p += CTL_NT) a.wbest[p] = a.w[p];
+    begin_iteration(a, s_next);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_copy_best(KArgs a)
@@ -652,11 +670,10 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk, int boff)
     const int64_t r = block_sum<BLOCK>(gc.r, s_red64);
     const int64_t v = block_sum<BLOCK>(gc.v, s_red64);
     if (threadIdx.x == 0) {
-        const int j = boff + blockIdx.x;
-        a.bstat[ST_X * BSTAT_STRIDE + j] = nx;
-        a.bstat[ST_E * BSTAT_STRIDE + j] = e;
-        a.bstat[ST_R * BSTAT_STRIDE + j] = r;
-        a.bstat[ST_V * BSTAT_STRIDE + j] = v;
+        shard_add(a, ST_X, nx);
+        shard_add(a, ST_E, e);
+        shard_add(a, ST_R, r);
+        shard_add(a, ST_V, v);
     }
 }
 
@@ -820,6 +837,10 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
     __shared__ int32_t s_red32[BLOCK / 64];
     __shared__ int32_t s_q[BLOCK];
     if (a.ctl->kind == KIND_DONE) return;
+    // the previous iteration improved the best partition: copy P_iter before
+    // this iteration's moves are applied
+    if (a.ctl->copy_best)
+        for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) a.best[v] = a.P[v];
     int64_t dc = 0, mw = 0, nm = 0;
     uint64_t dg = 0;
     int b = blockIdx.x;
@@ -876,10 +897,10 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
     nm = block_sum<BLOCK>(nm, s_red);
     dg = block_sum<BLOCK>(dg, s_redu);
     if (threadIdx.x == 0) {
-        a.bstat[ST_DCUT * BSTAT_STRIDE + blockIdx.x] = dc;
-        a.bstat[ST_MW * BSTAT_STRIDE + blockIdx.x] = mw;
-        a.bstat[ST_M * BSTAT_STRIDE + blockIdx.x] = nm;
-        a.bstat[ST_DIG * BSTAT_STRIDE + blockIdx.x] = (int64_t)dg;
+        shard_add(a, ST_DCUT, dc);
+        shard_add(a, ST_MW, mw);
+        shard_add(a, ST_M, nm);
+        shard_add(a, ST_DIG, (int64_t)dg);
     }
 }
 
@@ -1114,7 +1135,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int boff)
         }
     }
     ncand = block_sum<BLOCK>(ncand, s_red32);
-    if (threadIdx.x == 0) a.bstat[ST_X * BSTAT_STRIDE + boff + blockIdx.x] = ncand;
+    if (threadIdx.x == 0) shard_add(a, ST_X, ncand);
 }
 
 // Per-(part, slot) weight histogram of the eligible vertices. Each block
@@ -1230,50 +1251,37 @@ __global__ __launch_bounds__(BLOCK) void k_rb_tilesum(KArgs a)
     }
 }
 
-// Per split part (one block): exclusive scan of its tile sums; the tile in
-// which the running weight first reaches the residual is the only one that
-// needs an ordered look (every cut-off-slot vertex of an earlier tile is
-// evicted, none of a later one). Stores that tile and the weight before it.
-__global__ __launch_bounds__(BLOCK) void k_rb_tilescan(KArgs a)
-{
-    __shared__ int64_t s_scan[BLOCK / 64];
-    const int kind = a.ctl->kind;
-    if (kind != KIND_RW && kind != KIND_RS) return;
-    const int nsplit = a.ctl->nsplit;
-    for (int j = blockIdx.x; j < nsplit; j += gridDim.x) {
-        const int32_t *row = a.tsum + (int64_t)j * a.ntile;
-        const int64_t resid = a.resid[a.splitpart[j]];
-        int64_t carry = 0;
-        for (int base = 0; base < a.ntile; base += BLOCK) {
-            const int i = base + threadIdx.x;
-            const int64_t x = i < a.ntile ? row[i] : 0;
-            int64_t tot;
-            const int64_t before = carry + block_excl_scan<BLOCK>(x, s_scan, tot);
-            if (x > 0 && before < resid && resid <= before + x) {
-                a.xtile[j] = i;
-                a.xbase[j] = before;
-            }
-            carry += tot;
-        }
-    }
-}
-
-// Per split part (one block): inside its crossing tile, the cut-off-slot
-// vertices in id order are evicted while the weight before them is below the
-// residual; the last evicted id is the part's threshold.
-__global__ __launch_bounds__(BLOCK) void k_rb_threshold(KArgs a)
+// Per split part (one block): exclusive scan of its tile sums finds the one
+// tile in which the running cut-off-slot weight reaches the residual (every
+// cut-off-slot vertex of an earlier tile is evicted, none of a later one).
+// Inside that tile the vertices are taken in id order while the weight
+// before them is below the residual; the last evicted id is the threshold.
+__global__ __launch_bounds__(BLOCK) void k_rb_split(KArgs a)
 {
     __shared__ int64_t s_scan[BLOCK / 64];
     __shared__ uint64_t s_red[BLOCK / 64];
+    __shared__ int s_tile;
+    __shared__ int64_t s_base;
     constexpr int PER = TILE / BLOCK;
     const int kind = a.ctl->kind;
     if (kind != KIND_RW && kind != KIND_RS) return;
     const int nsplit = a.ctl->nsplit;
     for (int j = blockIdx.x; j < nsplit; j += gridDim.x) {
         const int p = a.splitpart[j];
+        const int32_t *row = a.tsum + (int64_t)j * a.ntile;
+        const int64_t resid = a.resid[p];
+        int64_t carry = 0;
+        for (int b0 = 0; b0 < a.ntile; b0 += BLOCK) {
+            const int i = b0 + threadIdx.x;
+            const int64_t x = i < a.ntile ? row[i] : 0;
+            int64_t tot;
+            const int64_t before = carry + block_excl_scan<BLOCK>(x, s_scan, tot);
+            if (x > 0 && before < resid && resid <= before + x) { s_tile = i; s_base = before; }
+            carry += tot;
+        }
+        __syncthreads();
         const int ss = a.sstar[p];
-        const int64_t resid = a.resid[p], base = a.xbase[j];
-        const int v0 = a.xtile[j] * TILE + threadIdx.x * PER;
+        const int v0 = s_tile * TILE + threadIdx.x * PER;
         int wv[PER];
         int64_t mine = 0;
 #pragma unroll
@@ -1284,7 +1292,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_threshold(KArgs a)
             mine += wv[q];
         }
         int64_t tot;
-        int64_t before = base + block_excl_scan<BLOCK>(mine, s_scan, tot);
+        int64_t before = s_base + block_excl_scan<BLOCK>(mine, s_scan, tot);
         uint64_t last = 0;  // (last evicted id + 1), 0 = none
 #pragma unroll
         for (int q = 0; q < PER; q++) {
@@ -1293,6 +1301,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_threshold(KArgs a)
         }
         last = block_max_u64<BLOCK>(last, s_red);
         if (threadIdx.x == 0) a.vthr[p] = (int32_t)last - 1;
+        __syncthreads();
     }
 }
 
@@ -1527,8 +1536,7 @@ static void launch_rb_select(const Plan &pl, hipStream_t s)
     k_rb_hist<<<pl.grid_hist, BLOCK, pl.hist_lds ? (size_t)p.k * NSLOT * 4 : 0, s>>>(p, pl.hist_lds);
     k_rb_cutoff<<<1, BLOCK, 0, s>>>(p);
     k_rb_tilesum<<<pl.grid_tile, BLOCK, (size_t)p.k * 4, s>>>(p);
-    k_rb_tilescan<<<std::min(p.k, 1024), BLOCK, 0, s>>>(p);
-    k_rb_threshold<<<std::min(p.k, 1024), BLOCK, 0, s>>>(p);
+    k_rb_split<<<std::min(p.k, 1024), BLOCK, 0, s>>>(p);
     k_rb_mark<<<pl.grid_tile, BLOCK, 0, s>>>(p);
     k_rs_scan<<<1, BLOCK, 0, s>>>(p);
     k_rs_assign<<<pl.grid_tile, BLOCK, 0, s>>>(p);
@@ -1538,7 +1546,6 @@ static void launch_iteration(const Plan &pl, hipStream_t s, bool lp_kernels, boo
                              hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr)
 {
     const KArgs &p = pl.plain;
-    k_ctl_begin<<<1, BLOCK, 0, s>>>(p);
     if (lp_kernels) {
         if (ev_a) (void)hipEventRecord(ev_a, s);
         launch_gain(pl, s);
@@ -1552,7 +1559,6 @@ static void launch_iteration(const Plan &pl, hipStream_t s, bool lp_kernels, boo
     if (pl.grid_plain) k_dcut<<<pl.grid_plain, BLOCK, 0, s>>>(p);
     k_apply<<<pl.grid_flat, BLOCK, (size_t)p.k * 4, s>>>(p);
     k_ctl_end<<<1, CTL_NT, 0, s>>>(p);
-    k_copy_best<<<pl.grid_flat, BLOCK, 0, s>>>(p);
 }
 
 static void set_lds_limits()
@@ -1652,7 +1658,7 @@ static int setup(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     a.rsev = (uint8_t *)ws_get(ctx, WS_RSEV, nn);
     int32_t *bins = (int32_t *)ws_get(ctx, WS_BIN, nn * 4);
     a.bins = bins;
-    a.bstat = (int64_t *)ws_get(ctx, WS_BSTAT, sizeof(int64_t) * NSTAT * BSTAT_STRIDE);
+    a.bstat = (int64_t *)ws_get(ctx, WS_BSTAT, sizeof(int64_t) * NSTAT * NSHARD);
     int32_t *fill = (int32_t *)ws_get(ctx, WS_FILL, sizeof(int32_t) * NCLS);
     a.ctl = (Ctl *)ws_get(ctx, WS_CTL, sizeof(Ctl) + 64);
     int64_t *p64 = (int64_t *)ws_get(ctx, WS_PART64, sizeof(int64_t) * (5 * (size_t)k + 8));
@@ -1797,6 +1803,7 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
         chunk = std::min(chunk * 2, 32);
     }
     hc = *pin;
+    k_copy_best<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain);
     JET_TRY(hipEventRecord(ctx->ev[2], s));
     if (prm->flags & JET_F_RETURN_ITER)
         JET_TRY(hipMemcpyAsync(part, pl.plain.P, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
