@@ -1,6 +1,7 @@
-"""Benchmark: Jet refinement throughput on one MI355X.
+"""Benchmark: Jet refinement on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload stencil128|rmat22|grid64]
+                    [--no-cpu-baseline] [--no-batch] [--no-serve]
 
 A step is one full multilevel partition (Algorithm 1: heavy-edge coarsening,
 seeded random coarsest partition, Jet refinement of every level, i.e. every
@@ -17,8 +18,14 @@ Prints one JSON line:
                iterations: algorithmic bytes per pass / average pass time
                (HIP events around each pass, on the library's stream),
                against 8 TB/s HBM
-  cpu_baseline the CPU oracle (single thread, this host), same unit, on a
-               bounded sample of the same workload
+  cpu_baseline the CPU oracle (single thread, this host), same unit, on the
+               same workload
+  batch        512 random geometric graphs refined in one jet_refine_batch
+               call vs one jet_refine call per graph (graphs/s, identical
+               partitions required)
+  serving      Poisson arrivals of partition jobs (grids and R-MAT graphs)
+               into jet_server: p50 / p99 latency and graphs/s per arrival
+               rate, vs partitioning the same jobs one at a time
 """
 from __future__ import annotations
 
@@ -27,6 +34,7 @@ import json
 import os
 import sys
 import time
+from concurrent.futures import ProcessPoolExecutor
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -34,11 +42,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
-    # configs[1]: full multilevel partition of the 128^3 27-point mesh, k = 64
+    # full multilevel partition of the 128^3 27-point mesh, k = 64
     "stencil128": dict(kind="stencil", side=128, k=64, unit=True),
-    # configs[2]: R-MAT scale 22, edge factor 16, weights in [1, 16], k = 256
+    # R-MAT scale 22, edge factor 16, weights in [1, 16], k = 256
     "rmat22": dict(kind="rmat", scale=22, ef=16, k=256, unit=False),
-    # configs[0]: 64 x 64 grid, k = 4 (single level in the config; here multilevel)
+    # 64 x 64 grid, k = 4
     "grid64": dict(kind="grid", side=64, k=4, unit=True),
 }
 
@@ -64,15 +72,167 @@ def gain_bytes(entries, rows, vertices, weighted):
     return entries * (8 if weighted else 4) + rows * 12 + vertices * 20
 
 
-def cpu_baseline(g, k, seed, budget_s=25.0):
+# ------------------------------------------------------------ input makers --
+# (module-level so a process pool can run them)
+
+def _gen_rgg(args):
+    from paper_2304_13194_amd import inputs as I
+    n, seed = args
+    return I.rgg(n, seed)
+
+
+def _gen_pool_graph(spec):
+    from paper_2304_13194_amd import inputs as I
+    if spec[0] == "grid":
+        return I.grid2d(spec[1], spec[1])
+    return I.rmat(spec[1], spec[2], spec[3])
+
+
+def rgg_batch_spec(count=512, nmin=1000, nmax=200000, seed=77):
+    """n log-uniform on [nmin, nmax], k uniform in {2, 4, ..., 128}, seeds."""
+    import numpy as np
+    from paper_2304_13194_amd import inputs as I
+    u = I.stream(seed, np.arange(2 * count, dtype=np.uint64))
+    frac = (u[:count] >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    ns = np.exp(np.log(nmin) + (np.log(nmax) - np.log(nmin)) * frac).astype(np.int64)
+    ks = np.array([2, 4, 8, 16, 32, 64, 128])[I.uniform_below(u[count:], 7)]
+    return [(int(ns[i]), int(ks[i]), seed * 100003 + i) for i in range(count)]
+
+
+SERVE_POOL = [("grid", 64), ("grid", 128), ("grid", 256), ("grid", 512), ("grid", 1024),
+              ("rmat", 12, 8, 41), ("rmat", 14, 16, 42), ("rmat", 16, 8, 43), ("rmat", 18, 16, 44),
+              ("rmat", 20, 16, 45)]
+
+
+def serve_jobs(count, seed=99):
+    """(pool index, k uniform in [2, 256], seed) per job."""
+    import numpy as np
+    from paper_2304_13194_amd import inputs as I
+    u = I.stream(seed, np.arange(2 * count, dtype=np.uint64))
+    gi = I.uniform_below(u[:count], len(SERVE_POOL))
+    ks = 2 + I.uniform_below(u[count:], 255)
+    return [(int(gi[i]), int(ks[i]), 1000 + i) for i in range(count)]
+
+
+def arrivals(rate, count, seed):
+    """Poisson process: exponential gaps of mean 1/rate (seeded)."""
+    import numpy as np
+    from paper_2304_13194_amd import inputs as I
+    u = (I.stream(seed, np.arange(count, dtype=np.uint64)) >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    gaps = -np.log1p(-u) / rate
+    return np.cumsum(gaps) - gaps[0]
+
+
+# -------------------------------------------------------------- sub-benches --
+
+def batch_bench(J, graphs, spec, reps=2):
+    """512 RGGs: one jet_refine_batch call vs one jet_refine per graph."""
+    import torch
+    from paper_2304_13194_amd import inputs as I
+    dgs = [J.to_device(g, unit_vwgt=True, unit_adjwgt=True) for g in graphs]
+    p0 = [torch.from_numpy(I.random_partition(g.n, k, s)).cuda() for g, (n, k, s) in zip(graphs, spec)]
+    params = [dict(k=k, seed=s) for (n, k, s) in spec]
+    torch.cuda.synchronize()
+    # batched: warm-up, then timed calls on fresh copies of P_0
+    parts = [p.clone() for p in p0]
+    J.refine_batch(dgs, parts, params)
+    times = []
+    for _ in range(reps):
+        parts = [p.clone() for p in p0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats, _ = J.refine_batch(dgs, parts, params)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t_batch = min(times)
+    # one call per graph
+    single = [p.clone() for p in p0]
+    for dg, p, prm in zip(dgs[:8], [q.clone() for q in p0[:8]], params[:8]):
+        J.refine(dg, p, **prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sstats = [J.refine(dg, p, **prm)[0] for dg, p, prm in zip(dgs, single, params)]
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    identical = all(torch.equal(a, b) for a, b in zip(parts, single))
+    cut_b = sum(s["cut"] for s in stats)
+    cut_s = sum(s["cut"] for s in sstats)
+    edges = sum(s["iters"] * g.nnz for s, g in zip(stats, graphs))
+    return {
+        "workload": f"{len(graphs)} RGGs (mean degree 10, n log-uniform in [1e3, 2e5], sum n = "
+                    f"{sum(g.n for g in graphs)}, sum 2m = {sum(g.nnz for g in graphs)}), k in {{2..128}}, "
+                    f"lambda 3%, seeded random P_0, single-level refinement",
+        "graphs_per_s_batched": len(graphs) / t_batch,
+        "graphs_per_s_one_per_launch": len(graphs) / t_single,
+        "speedup": t_single / t_batch,
+        "ms_batched": t_batch * 1e3,
+        "ms_one_per_launch": t_single * 1e3,
+        "refine_edges_per_s_batched": edges / t_batch,
+        "iters_max": max(s["iters"] for s in stats),
+        "iters_mean": sum(s["iters"] for s in stats) / len(stats),
+        "total_cut": cut_b,
+        "identical_partitions": bool(identical and cut_b == cut_s),
+    }
+
+
+def serve_bench(J, pool, jobs, rates=(50, 200, 1000, 2000)):
+    """Poisson arrivals into jet_server vs the same jobs one at a time."""
+    import numpy as np
+    import torch
+    dgs = [J.to_device(g, unit_vwgt=(s[0] == "grid"), unit_adjwgt=(s[0] == "grid")) for g, s in zip(pool, SERVE_POOL)]
+    # one at a time (jet_partition): reference results and sequential throughput
+    for gi, k, seed in jobs[:4]:
+        J.partition(dgs[gi], k, seed=seed)
+    torch.cuda.synchronize()
+    ref = []
+    t0 = time.perf_counter()
+    for gi, k, seed in jobs:
+        part, st, _ = J.partition(dgs[gi], k, seed=seed)
+        ref.append((part, st["cut"]))
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    out = {"workload": f"{len(jobs)} jobs per rate drawn from grids (side 64..1024) and R-MAT graphs "
+                       f"(scale 12..20, edge factor 8/16, weights 1..16), k uniform in [2, 256], lambda 3%",
+           "graphs_per_s_one_at_a_time": len(jobs) / t_seq, "rates": []}
+    identical = True
+    for ri, rate in enumerate(rates):
+        arr = arrivals(rate, len(jobs), 500 + ri)
+        outs = [torch.empty(dgs[gi].n, dtype=torch.int32, device="cuda") for gi, _, _ in jobs]
+        torch.cuda.synchronize()
+        sv = J.Server(hbm_budget_bytes=128 << 30, max_slots=64)
+        try:
+            tickets = []
+            t0 = time.perf_counter()
+            for (gi, k, seed), at, o in zip(jobs, arr, outs):
+                d = t0 + at - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets.append(sv.submit(dgs[gi], o, k, seed=seed))
+            res = [sv.wait(t, 600000) for t in tickets]
+            info = sv.info()
+        finally:
+            sv.close()
+        lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in res])
+        span = (max(r["t_done_ms"] for r in res) - min(r["t_submit_ms"] for r in res)) * 1e-3
+        ok = all(r["status"] == 0 and r["cut"] == c and torch.equal(o, p)
+                 for r, o, (p, c) in zip(res, outs, ref))
+        identical = identical and ok
+        out["rates"].append({"rate_jobs_per_s": rate, "p50_ms": float(np.percentile(lat, 50)),
+                             "p99_ms": float(np.percentile(lat, 99)), "graphs_per_s": len(jobs) / span,
+                             "mean_jobs_per_step": info["step_jobs"] / max(info["steps"], 1),
+                             "steps": info["steps"]})
+    out["identical_to_alone"] = bool(identical)
+    return out
+
+
+def cpu_baseline(g, k, seed):
     """The oracle's multilevel partition of the same graph, single thread."""
     from oracle import oracle as O
     O.lib()
     t0 = time.perf_counter()
     res = O.partition(g, k, seed=seed, trace_cap=1 << 20)
     dt = time.perf_counter() - t0
-    sizes = res["level_sizes"]
-    return res, dt, sizes
+    return res, dt, res["level_sizes"]
 
 
 def main():
@@ -82,6 +242,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="stencil128", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--seed", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -95,6 +257,18 @@ def main():
 
     w = WORKLOADS[args.workload]
     k = w["k"]
+    # inputs of the batch and serving runs are generated in worker processes
+    # while the main workload runs (none of it inside a timed region)
+    pool_ex = None
+    fut_rgg = fut_pool = None
+    spec = serve = None
+    if not (args.no_batch and args.no_serve):
+        pool_ex = ProcessPoolExecutor(max_workers=6)
+        if not args.no_batch:
+            spec = rgg_batch_spec()
+            fut_rgg = [pool_ex.submit(_gen_rgg, (n, s)) for n, _, s in spec]
+        if not args.no_serve:
+            fut_pool = [pool_ex.submit(_gen_pool_graph, s) for s in SERVE_POOL]
     t_gen = time.perf_counter()
     g = make_graph(w)
     t_gen = time.perf_counter() - t_gen
@@ -175,6 +349,21 @@ def main():
             "passes": passes,
         },
     }
+    if fut_rgg is not None:
+        try:
+            graphs = [f.result() for f in fut_rgg]
+            out["batch"] = batch_bench(J, graphs, spec)
+            del graphs
+        except Exception as e:  # reported, never hidden
+            out["batch"] = {"error": repr(e)}
+    if fut_pool is not None:
+        try:
+            pool = [f.result() for f in fut_pool]
+            out["serving"] = serve_bench(J, pool, serve_jobs(40))
+        except Exception as e:
+            out["serving"] = {"error": repr(e)}
+    if pool_ex is not None:
+        pool_ex.shutdown()
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         res, dt, sizes = cpu_baseline(g, k, args.seed)
         # the oracle coarsens with the same rule, so its levels have the same sizes

@@ -48,7 +48,7 @@ extern "C" {
 #define JET_EOVERFLOW (-4) /* total vertex or edge weight >= 2^31 */
 #define JET_ENOMEM    (-5) /* device or host allocation failed */
 #define JET_EHIP      (-6) /* HIP runtime error; jet_last_hip_error() has the code */
-#define JET_EAGAIN    (-7) /* reserved: try again later */
+#define JET_EAGAIN    (-7) /* serving: queue full, or the job is not done yet */
 #define JET_ELIMIT    (-8) /* outside a documented size limit (e.g. k > 16384) */
 
 /* ---- flags ------------------------------------------------------------- */
@@ -172,6 +172,30 @@ int  jet_last_hip_error(const jet_context *ctx);
 int jet_refine(jet_context *ctx, const jet_csr *g, const jet_params *params, int32_t *part,
                int64_t *part_weights_out, jet_stats *stats, jet_trace *trace, void *stream);
 
+/* ---- batched refinement ---------------------------------------------------
+ * Refines `count` independent graphs in one launch sequence: the graphs are
+ * laid out as one block-diagonal union (graph i's vertices, parts and
+ * selection tiles follow graph i-1's) and every iteration's kernels serve all
+ * graphs at once, each graph with its own controller, so each runs exactly
+ * the iterations it would run alone (Algorithm 3 applied per graph; no edge
+ * joins two graphs, so no connectivity, gain or loss mixes them). Graph i's
+ * result equals jet_refine(graphs[i], params[i], parts[i]) bit for bit,
+ * trace included.
+ *   graphs:  host array [count] of CSRs whose arrays are device pointers
+ *   params:  host array [count]; per graph k, lambda, c, phi, stall limit,
+ *            b_max, deadzone, level, seed, JET_F_VALIDATE, JET_F_RETURN_ITER
+ *            (JET_F_PROFILE is ignored)
+ *   parts:   host array [count] of device int32[n_i] (in: P_0, out: P_best)
+ *   stats:   host array [count] or NULL (ms_* fields are the whole batch's)
+ *   traces:  host array [count] or NULL; each with its own host buffer
+ * Graphs with k = 1 or n = 0 are answered directly (all vertices in part 0).
+ * Limits: the union must stay below 2^31 vertices and parts. Errors as for
+ * jet_refine; the first invalid graph stops the call before any refinement
+ * (parts are then unchanged, except that graphs answered directly may
+ * already be written). */
+int jet_refine_batch(jet_context *ctx, int32_t count, const jet_csr *graphs, const jet_params *params,
+                     int32_t *const *parts, jet_stats *stats, jet_trace *traces, void *stream);
+
 /* ---- single-step entry points (for step-level checks) --------------------
  * One Jetlp step (Algorithm 4) against `part` with lock flags `locked`
  * (device u8[n], nonzero = locked). Outputs (device, [n] each): pd (P_d, or
@@ -215,6 +239,73 @@ void jet_hierarchy_free(jet_hierarchy *h);
  * int32[n]. The trace, if given, concatenates the levels' records. */
 int jet_partition(jet_context *ctx, const jet_csr *g, const jet_params *params, int32_t *part_out,
                   jet_stats *stats, jet_trace *trace, void *stream);
+
+/* ---- serving loop ---------------------------------------------------------
+ * A server partitions submitted jobs (each one jet_partition call's worth of
+ * work) with continuous batching at level granularity. A worker thread owns
+ * the context and a stream of its own and repeats one step:
+ *   1. admit queued jobs in submission order while fewer than max_slots are
+ *      active and the job's HBM footprint fits in what the budget has left;
+ *      an admitted job is checked, coarsened (its hierarchy stays in device
+ *      memory until the job ends) and gets its seeded coarsest partition;
+ *   2. refine the current level of every active job in one jet_refine_batch
+ *      launch sequence;
+ *   3. project every job one level finer; a job whose finest level was
+ *      refined is done: its hierarchy is freed and its budget returned.
+ * Jobs therefore join and leave the device-wide batch between steps, and a
+ * job's result does not depend on what else is in the batch: it equals
+ * jet_partition(graph, params) bit for bit.
+ * Footprint of a job (bytes): 3 (8 (n+1) + 4 nnz (1 + [adjwgt]) + 4 n [vwgt])
+ * + 48 n: its level graphs, its share of the batch's union copies and
+ * per-vertex state, and two partition buffers.
+ * The context belongs to the server until jet_server_destroy; the caller
+ * must not use it meanwhile. Submit, poll and wait are thread-safe. */
+typedef struct jet_server jet_server;
+
+typedef struct {
+    jet_csr graph;          /* device CSR, valid and unchanged until the job is done */
+    jet_params params;      /* as for jet_partition (JET_F_PROFILE ignored) */
+    int32_t *part_out;      /* device int32[n]; holds the partition once the job is done */
+} jet_job;
+
+typedef struct {
+    int32_t status;         /* JET_OK, or the error that ended the job */
+    int32_t levels;         /* hierarchy levels */
+    int32_t iters;          /* refinement iterations over all levels */
+    int32_t balanced;
+    int64_t cut, max_part_weight;
+    double t_submit_ms;     /* host steady clock, ms since the server was created */
+    double t_admit_ms;
+    double t_done_ms;
+    int32_t steps;          /* batch steps the job took part in */
+    int32_t reserved;
+} jet_result;
+
+typedef struct {
+    int64_t submitted, completed, steps;
+    int64_t step_jobs;      /* sum over steps of the number of jobs refined together */
+    int32_t active, queued;
+    int64_t hbm_in_use;     /* footprint of the active jobs (bytes) */
+    double busy_ms;         /* host time the worker spent in steps */
+} jet_server_info;
+
+/* hbm_budget_bytes: total footprint of the jobs active at once (0 = no
+ * limit); max_slots: jobs active at once (>= 1). The queue holds at most
+ * 65536 jobs. */
+int jet_server_create(jet_server **server, jet_context *ctx, size_t hbm_budget_bytes, int32_t max_slots);
+/* Queues a job; *ticket identifies it. JET_EAGAIN: queue full; JET_ELIMIT:
+ * the job's footprint exceeds the whole budget; JET_EINVAL / JET_ELIMIT for
+ * parameters jet_partition would reject up front. */
+int jet_server_submit(jet_server *server, const jet_job *job, uint64_t *ticket);
+/* JET_OK and *result once the job is done (the ticket is then released),
+ * JET_EAGAIN while it is not, JET_EINVAL for an unknown ticket. */
+int jet_server_poll(jet_server *server, uint64_t ticket, jet_result *result);
+/* As poll, but waits up to timeout_ms (< 0: no limit) for the job to end. */
+int jet_server_wait(jet_server *server, uint64_t ticket, int32_t timeout_ms, jet_result *result);
+int jet_server_info_get(jet_server *server, jet_server_info *info);
+/* Finishes every submitted job, then stops the worker and frees the server
+ * (results not yet polled are dropped). */
+void jet_server_destroy(jet_server *server);
 
 #ifdef __cplusplus
 }

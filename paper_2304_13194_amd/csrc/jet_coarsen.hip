@@ -26,19 +26,6 @@
 #include "jet_internal.h"
 
 namespace jet {
-int validate_full_csr(jet_context *ctx, const jet_csr *g, hipStream_t s);
-}
-
-struct jet_hierarchy {
-    int device = 0;
-    int nlevels = 0;
-    std::vector<jet_csr> lv;        // level views (level 0 = caller's graph)
-    std::vector<int32_t *> maps;    // maps[l]: level l -> level l+1 (owned)
-    std::vector<void *> owned;      // device buffers owned by the hierarchy
-    float ms_coarsen = 0.f;
-};
-
-namespace jet {
 
 constexpr int CB = 256;   // block size of the coarsening kernels
 constexpr int SCAN_ITEMS = 8;
@@ -858,6 +845,25 @@ static int build_hierarchy(jet_context *ctx, const jet_csr *g, const jet_params 
     h->maps.push_back(nullptr);
     h->nlevels = (int)h->lv.size();
     return JET_OK;
+}
+
+int hierarchy_build(jet_context *ctx, const jet_csr *g, const jet_params *prm, jet_hierarchy *h, hipStream_t s)
+{
+    return build_hierarchy(ctx, g, prm, h, s);
+}
+
+void hierarchy_release(jet_hierarchy *h) { hier_release(h); }
+
+int random_partition(jet_context *ctx, int n, int k, uint64_t seed, int32_t *part, hipStream_t s)
+{
+    if (n > 0) k_random_part<<<grid_for(ctx, n, CB, 4), CB, 0, s>>>(n, k, mix64(seed ^ 1ULL), part);
+    return hip_status(ctx, hipGetLastError());
+}
+
+int project_partition(jet_context *ctx, int n, const int32_t *map, const int32_t *coarse, int32_t *fine, hipStream_t s)
+{
+    if (n > 0) k_project<<<grid_for(ctx, n, CB, 4), CB, 0, s>>>(n, map, coarse, fine);
+    return hip_status(ctx, hipGetLastError());
 }
 
 }  // namespace jet

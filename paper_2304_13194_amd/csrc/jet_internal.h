@@ -10,17 +10,17 @@
 
 namespace jet {
 
-constexpr int NSLOT = 33;   // loss slots 0..32: losses are int32 (|loss| <= weighted degree < 2^31)
-constexpr int KMAX = 16384; // part-count limit (dense LDS tables of int32)
-constexpr int BLOCK = 256;  // threads per block of the row kernels
-constexpr int TILE = 2048;  // vertices per tile of the ordered-selection kernels (one wave each)
-// Per-block partial counters: slot 0 |X| (Jetlp) or eligible count (rebalancing),
-// 1 |M|, 2 cut change, 3 moved weight, 4 digest change.
-// Profiling counters of the gain pass: 5 CSR entries of unlocked rows, 6 unlocked
-// rows, 7 visited vertices.
+constexpr int NSLOT = 33;    // loss slots 0..32: losses are int32 (|loss| <= weighted degree < 2^31)
+constexpr int KMAX = 16384;  // part-count limit per graph (dense LDS tables of int32)
+constexpr int BLOCK = 256;   // threads per block of the row kernels
+constexpr int TILE = 2048;   // vertices per tile of the ordered-selection kernels
+constexpr int PER = TILE / BLOCK;
+// Iteration counters: 0 |X| (Jetlp) or eligible count (rebalancing), 1 |M|,
+// 2 cut change, 3 moved weight, 4 digest change; profiling of the gain pass:
+// 5 CSR entries of unlocked rows, 6 unlocked rows, 7 visited vertices.
 enum Stat { ST_X = 0, ST_M = 1, ST_DCUT = 2, ST_MW = 3, ST_DIG = 4, ST_E = 5, ST_R = 6, ST_V = 7, NSTAT = 8 };
-constexpr int KIND_LOG = 1 << 16;  // iterations whose kind is logged
-constexpr int NSHARD = 64;  // shards per counter row
+constexpr int NSHARD = 64;         // shards per counter row and graph
+constexpr int KIND_LOG = 1 << 16;  // iterations whose kind is logged (graph 0)
 
 enum Kind { KIND_DONE = 0, KIND_LP = 1, KIND_RW = 2, KIND_RS = 3 };
 // Degree classes: 0 isolated, 1 small (<= 32), 2 medium (<= 1024), 3 large.
@@ -28,68 +28,76 @@ enum Cls { CLS_Z = 0, CLS_S = 1, CLS_M = 2, CLS_L = 3, NCLS = 4 };
 constexpr int S_MAXDEG = 32;
 constexpr int M_MAXDEG = 1024;
 
-// Device-resident loop state of one refinement call.
+// Launch-wide counts: CNT_DONE graphs finished; then two rows (selected by
+// the parity of the iteration's launch index) of [graphs whose previous
+// iteration improved the best and that go on, graphs in Jetlp, Jetrw, Jetrs].
+enum Cnt { CNT_DONE = 0, CNT_ROW = 2, CNT_N = 10 };
+
+// Device-resident state of one graph's refinement (one per graph of a batch).
 struct Ctl {
-    // configuration (written by the host before the first iteration)
+    // configuration
     int32_t n, k, stall_limit, bmax;
     int32_t max_iters, c_num, c_den, phi_num;
     int32_t phi_den, level, trace_cap, nB;
+    int32_t voff, poff, t0, ntiles;      // first vertex, first global part, first tile, tiles
+    int32_t trace_off, flags, lambda_ppm, deadzone_div;
     int64_t W, o, sigma;
+    int64_t rowbase;                     // first tile-sum entry of the graph
     uint64_t seed;
     // loop state
     int32_t kind, t, stall, wcount;
     int32_t lp_id, done, balanced, bal_best;
-    int32_t copy_best, nA, nsplit, n_lp;
-    int32_t n_rw, n_rs, err, pad0;
+    int32_t copy_best, nA, n_lp, n_rw;
+    int32_t n_rs, bad_part, nX, nM;
     int64_t cut, cut_best, maxw, maxw_best;
     uint64_t digest;
-    // per-iteration results (reduced from per-block partials)
-    int32_t nX, nM;
+    // per-iteration results
     int64_t dcut, moved_w;
     uint64_t ddigest;
     int64_t total_cap;
-    // set-up accumulators
+    // set-up accumulators and profiling
     int64_t wsum, ewsum;
-    int64_t prof_e, prof_r, prof_v;  // gain-pass counters summed over Jetlp iterations
-    int32_t bincnt[NCLS];
-    int32_t bad_graph, bad_part;
+    int64_t prof_e, prof_r, prof_v;
 };
 
 // Everything a kernel needs, passed by value.
 struct KArgs {
-    int32_t n, k;
+    int32_t n, k;          // union vertices; largest k of the batch (LDS table size)
+    int32_t ngraph, ktot;  // graphs; total parts (global part id = poff + local part)
     const int64_t *xadj;
     const int32_t *adj;
     const int32_t *vw;
     const int32_t *ew;
-    int32_t *P;      // P_iter
-    int32_t *best;   // P_best (the caller's array)
-    int2 *rec;       // per-vertex Jetlp record: x = (P_s << 16) | (in X ? P_d + 1 : 0), y = F
-    int32_t *dest;   // move destination or -1 (kept -1 outside moves)
-    int32_t *lock;   // Jetlp id of the last move of each vertex
-    uint8_t *slot;   // rebalancing loss slot, 255 = not a candidate
-    int32_t *rbd;    // Jetrw destination of each candidate
-    uint8_t *rsev;   // Jetrs: evicted flag
-    const int32_t *bins;   // vertex ids grouped by degree class
+    const int32_t *vg;     // graph of each vertex (NULL: one graph)
+    const int32_t *pg;     // graph of each global part (NULL: one graph)
+    const int32_t *tg;     // graph of each tile (NULL: one graph)
+    int32_t *P;            // P_iter (local part ids)
+    int32_t *best;         // P_best
+    int2 *rec;             // Jetlp record: x = (P_s << 16) | (in X ? P_d + 1 : 0), y = F
+    int32_t *dest;         // move destination or -1 (kept -1 outside moves)
+    int32_t *lock;         // Jetlp id of the last move of each vertex
+    uint8_t *slot;         // rebalancing loss slot, 255 = not a candidate
+    int32_t *rbd;          // Jetrw destination of each candidate
+    uint8_t *rsev;         // Jetrs: evicted flag
+    const int32_t *bins;   // vertex ids grouped by degree class, ascending within a class
     int32_t binoff[NCLS + 1];
-    int64_t *bstat;  // iteration counters [NSTAT][NSHARD], summed by the controller
-    int32_t grid_tab, grid_rbtab, grid_plain;
-    Ctl *ctl;
-    int64_t *w, *wbest, *resid, *capstart, *hist;
-    int64_t *xbase;   // per split index: cut-off-slot weight before its crossing tile
-    int32_t *Blist, *sstar, *splitidx;
-    int32_t *splitpart, *xtile, *vthr;  // split index -> part, crossing tile; per part threshold id
+    int64_t *bstat;        // iteration counters [graph][NSTAT][NSHARD]
+    Ctl *ctl;              // [ngraph]
+    int32_t *cnt;          // [CNT_N] launch-wide counts
+    int32_t it;            // launch index of the current iteration (its parity picks the count row)
+    // per global part
+    int64_t *w, *wbest, *resid, *hist;
+    int64_t *capstart;     // Jetrs capacity starts: graph g's nB + 1 entries at poff + g
+    int32_t *Blist, *sstar, *vthr;
     uint8_t *isA, *isB;
-    int32_t *tsum;
-    int64_t *esum;
-    int32_t ntile;
+    int32_t *tsum;         // per graph: [k][ntiles] cut-off-slot weight per (part, tile)
+    int64_t *esum;         // per tile: Jetrs evicted weight, then its exclusive prefix in the graph
+    int32_t ntile;         // tiles (each inside one graph)
     jet_trace_rec *trace;
-    int8_t *kinds;   // kind of iteration t (t < KIND_LOG)
+    int8_t *kinds;         // kind of iteration t of graph 0 (t < KIND_LOG)
     // block counts per role of the row kernels
     int32_t gS, gM, gL, gZ;
-    // which role (1 S, 2 M, 3 L) serves each class in the LDS-table kernels
-    int32_t tmap[NCLS];
-    int32_t ngroups_tab_S; // groups per block of the S role in table kernels
+    int32_t tmap[NCLS];    // which role (1 S, 2 M, 3 L) serves each class in the LDS-table kernels
     // optional step outputs
     int64_t *dbg_F, *dbg_cs, *dbg_F2, *dbg_loss;
     int32_t *dbg_pd;
@@ -103,12 +111,21 @@ struct Buffer {
 
 }  // namespace jet
 
+struct jet_hierarchy {
+    int device = 0;
+    int nlevels = 0;
+    std::vector<jet_csr> lv;        // level views (level 0 = caller's graph)
+    std::vector<int32_t *> maps;    // maps[l]: level l -> level l+1 (owned)
+    std::vector<void *> owned;      // device buffers owned by the hierarchy
+    float ms_coarsen = 0.f;
+};
+
 struct jet_context {
     int device = 0;
     int num_cu = 256;
     int last_hip = 0;
     std::vector<jet::Buffer> bufs;
-    void *pinned = nullptr;  // host staging for small read-backs
+    void *pinned = nullptr;  // host staging for read-backs and controller uploads
     size_t pinned_bytes = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> prof_ev;  // pairs around gain passes (JET_F_PROFILE)
@@ -117,21 +134,40 @@ struct jet_context {
 namespace jet {
 
 enum WsSlot {
-    WS_P, WS_REC, WS_DEST, WS_LOCK, WS_SLOT, WS_RBD, WS_RSEV, WS_BIN, WS_BSTAT, WS_FILL,
+    WS_P, WS_REC, WS_DEST, WS_LOCK, WS_SLOT, WS_RBD, WS_RSEV, WS_BIN, WS_BSTAT, WS_CNT,
     WS_CTL, WS_PART64, WS_PART32, WS_PART8, WS_HIST, WS_TSUM, WS_ESUM, WS_TRACE,
     WS_DBG_LOCK, WS_H0, WS_H1, WS_C0, WS_C1, WS_C2, WS_C3, WS_C4, WS_C5, WS_C6, WS_C7, WS_C8,
-    WS_C9, WS_C10, WS_C11, WS_KINDS, WS_C12, WS_COUNT = 64
+    WS_C9, WS_C10, WS_C11, WS_KINDS, WS_C12, WS_BLKCNT, WS_TG,
+    WS_U_XADJ, WS_U_ADJ, WS_U_VW, WS_U_EW, WS_U_VG, WS_U_P0, WS_U_BEST, WS_U_DESC,
+    WS_COUNT = 64
 };
 
 // Grow-only workspace slot; returns nullptr on allocation failure.
 void *ws_get(jet_context *ctx, int slot, size_t bytes);
+// Grow-only pinned host staging; returns nullptr on allocation failure.
+void *pinned_get(jet_context *ctx, size_t bytes);
 
 // Refinement of one level; `part` holds P_0 on entry and P_best on exit.
-// `trace_dev`/`trace_cap` optional. stats filled (host). Stream already set.
 int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int32_t *part,
                  int64_t *part_weights_out, jet_stats *stats, jet_trace_rec *trace_host,
                  int32_t trace_cap, int32_t *trace_count, int32_t *trace_total, hipStream_t s);
 
+// Refinement of `count` independent graphs in one launch sequence; parts[i]
+// holds graph i's P_0 on entry and its P_best on exit.
+int refine_batch(jet_context *ctx, int count, const jet_csr *graphs, const jet_params *params,
+                 int32_t *const *parts, jet_stats *stats, jet_trace *traces, hipStream_t s);
+
 int hip_status(jet_context *ctx, hipError_t e);
+int validate_full_csr(jet_context *ctx, const jet_csr *g, hipStream_t s);
+// Cheap O(n + m) input checks (and the full check under JET_F_VALIDATE).
+int check_graph(jet_context *ctx, const jet_csr *g, uint32_t flags, hipStream_t s);
+
+// Multilevel scaffold: the hierarchy of g (levels owned by h until
+// hierarchy_release), the seeded coarsest partition P[v] =
+// floor(stream(mix64(seed ^ 1), v) k / 2^64), and projection to a finer level.
+int hierarchy_build(jet_context *ctx, const jet_csr *g, const jet_params *prm, jet_hierarchy *h, hipStream_t s);
+void hierarchy_release(jet_hierarchy *h);
+int random_partition(jet_context *ctx, int n, int k, uint64_t seed, int32_t *part, hipStream_t s);
+int project_partition(jet_context *ctx, int n, const int32_t *map, const int32_t *coarse, int32_t *fine, hipStream_t s);
 
 }  // namespace jet

@@ -1,27 +1,35 @@
 // Jet refinement on gfx950: Jetlp with the afterburner (Algorithm 4), weak and
 // strong rebalancing (Algorithm 5 and the strong variant of Section 4.2.2),
 // synchronous move application, and the refinement loop of Algorithm 3 run by
-// a device-side controller.
+// device-side controllers -- for one graph or for a batch of graphs.
 //
 // Design (one MI355X):
+//  * A batch is one block-diagonal union graph: graph g owns the vertices
+//    [voff_g, voff_g + n_g), the global parts [poff_g, poff_g + k_g) and the
+//    tiles [t0_g, t0_g + ntiles_g). No edge joins two graphs, so every
+//    connectivity, gain and loss is the graph's own, and each graph keeps its
+//    own controller, counters and iteration kind. One launch sequence per
+//    iteration serves every graph; a single graph is a batch of one.
 //  * Connectivity conn(v, .) is rebuilt per pass in LDS. Vertices are binned
-//    by degree: <= 32 -> 8-lane groups (32 groups per 256-thread block),
-//    <= 1024 -> one wave, larger -> one block. Each group owns a dense int32
-//    table of k entries; neighbours add their edge weight with LDS atomics,
-//    then read-and-clear the entry of their own part with an atomic exchange,
-//    so every adjacent part is seen exactly once and the table is left zero.
-//    Integer sums are exact in any order; argmax ties break by part id, so the
-//    result does not depend on scheduling.
+//    by degree: <= 32 -> 4- or 8-lane groups, <= 1024 -> one wave, larger ->
+//    one block. Each group owns a dense int32 table of k + 1 entries;
+//    neighbours add their edge weight with LDS atomics, then read-and-clear
+//    the entry of their own part with an atomic exchange, so every adjacent
+//    part is seen exactly once and the table is left zero. Integer sums are
+//    exact in any order; argmax ties break by part id, so no result depends
+//    on scheduling.
 //  * Per-vertex Jetlp state is one 8-byte record (P_s, P_d + in-X flag, F), so
 //    the afterburner's neighbour gather is a single load.
-//  * Rebalancing orders evictions by (loss slot, vertex id): a per-(part, slot)
-//    weight histogram fixes the cut-off slot of every oversized part; inside
-//    that slot, vertex-ordered prefix sums per part come from per-tile sums,
-//    a per-part scan over tiles, and a wave-level ballot/scan inside each tile.
-//  * A single-block controller kernel decides each iteration's kind from
-//    device state; every other kernel exits at once when its kind is not
-//    selected, so iterations are enqueued in chunks with one host sync each.
+//  * Rebalancing orders evictions by (loss slot, vertex id): a per-(part,
+//    slot) weight histogram fixes each oversized part's cut-off slot; inside
+//    it, per-(part, tile) weight sums locate the one tile where the residual
+//    is reached, and an ordered scan of that tile fixes the last evicted id.
+//  * A controller block per graph ends each iteration (best tracking, trace,
+//    the next kind) and counts the graphs of each kind; the other kernels
+//    exit at once when no graph needs them, so iterations are enqueued in
+//    chunks with one host sync per chunk.
 #include <hip/hip_runtime.h>
+#include <limits.h>
 #include <stdint.h>
 #include <string.h>
 
@@ -34,144 +42,372 @@
 
 namespace jet {
 
+// ------------------------------------------------------------- graph views --
+
+__device__ __forceinline__ int graph_of(const KArgs &a, int v) { return a.vg ? a.vg[v] : 0; }
+
+// Count row of the current iteration: [improved-and-going-on, Jetlp, Jetrw, Jetrs].
+__device__ __forceinline__ const int32_t *count_row(const KArgs &a) { return a.cnt + CNT_ROW + (a.it & 1) * 4; }
+__device__ __forceinline__ bool any_kind(const KArgs &a, int kind) { return count_row(a)[kind] > 0; }
+__device__ __forceinline__ bool any_rb(const KArgs &a)
+{
+    const int32_t *r = count_row(a);
+    return r[KIND_RW] + r[KIND_RS] > 0;
+}
+__device__ __forceinline__ bool any_active(const KArgs &a)
+{
+    const int32_t *r = count_row(a);
+    return r[KIND_LP] + r[KIND_RW] + r[KIND_RS] > 0;
+}
+__device__ __forceinline__ bool is_rb(int kind) { return kind == KIND_RW || kind == KIND_RS; }
+
+// Per-lane copy of the fields of a vertex's graph that a kernel reads. A lane
+// reloads it only when it reaches a vertex of another graph: lanes walk
+// contiguous stretches of a batch, and a single graph loads it once. Fields a
+// kernel does not use are never loaded.
+struct GV {
+    int g = -1;
+    int kind = 0, lp_id = 0, cn = 0, cd = 1, k = 0, poff = 0, voff = 0, nB = 0, copy = 0;
+    int64_t W = 0;
+    uint64_t hs = 0;  // Jetrw hash seed of the iteration: mix64(seed ^ (level * 2^32 + t))
+    __device__ __forceinline__ void at(const KArgs &a, int gg)
+    {
+        if (gg == g) return;
+        g = gg;
+        const Ctl *c = a.ctl + gg;
+        kind = c->kind;
+        lp_id = c->lp_id;
+        cn = c->c_num;
+        cd = c->c_den;
+        k = c->k;
+        poff = c->poff;
+        voff = c->voff;
+        nB = c->nB;
+        copy = c->copy_best;
+        W = c->W;
+        hs = mix64(c->seed ^ (((uint64_t)(uint32_t)c->level << 32) + (uint64_t)(uint32_t)c->t));
+    }
+};
+
+// Counters are summed modulo 2^64 (signed values and the digest alike).
+__device__ __forceinline__ void stat_add(const KArgs &a, int g, int row, uint64_t val)
+{
+    if (val)
+        atomicAdd((unsigned long long *)&a.bstat[((int64_t)g * NSTAT + row) * NSHARD + (blockIdx.x & (NSHARD - 1))],
+                  (unsigned long long)val);
+}
+
+// Up to three iteration counters of the graph a lane is visiting; reaching
+// another graph adds the previous graph's counts to its shards.
+template <int R0, int R1 = -1, int R2 = -1>
+struct GAcc {
+    static constexpr int r1 = R1, r2 = R2;
+    int g = -1;
+    uint64_t c0 = 0, c1 = 0, c2 = 0;
+    __device__ __forceinline__ void flush(const KArgs &a)
+    {
+        if (g >= 0) {
+            stat_add(a, g, R0, c0);
+            if (R1 >= 0) stat_add(a, g, R1, c1);
+            if (R2 >= 0) stat_add(a, g, R2, c2);
+        }
+        c0 = 0;
+        c1 = 0;
+        c2 = 0;
+    }
+    __device__ __forceinline__ void to(const KArgs &a, int gg)
+    {
+        if (gg != g) {
+            flush(a);
+            g = gg;
+        }
+    }
+};
+
+// End of a kernel (whole block): when every counting lane is in the same
+// graph (always for one graph) the counts are summed over the block and added
+// once per row; otherwise every lane adds its own.
+template <class Acc>
+__device__ void acc_finish(const KArgs &a, Acc &acc)
+{
+    __shared__ int s_lo, s_hi;
+    __shared__ uint64_t s_red[BLOCK / 64];
+    if (threadIdx.x == 0) {
+        s_lo = INT_MAX;
+        s_hi = -1;
+    }
+    __syncthreads();
+    if (acc.g >= 0) {
+        atomicMin(&s_lo, acc.g);
+        atomicMax(&s_hi, acc.g);
+    }
+    __syncthreads();
+    const int lo = s_lo, hi = s_hi;
+    __syncthreads();
+    if (hi < 0) return;
+    if (lo == hi) {
+        const uint64_t t0 = block_sum<BLOCK>(acc.c0, s_red);
+        uint64_t t1 = 0, t2 = 0;
+        if (Acc::r1 >= 0) t1 = block_sum<BLOCK>(acc.c1, s_red);
+        if (Acc::r2 >= 0) t2 = block_sum<BLOCK>(acc.c2, s_red);
+        acc.c0 = t0;
+        acc.c1 = t1;
+        acc.c2 = t2;
+        acc.g = threadIdx.x == 0 ? lo : -1;
+    }
+    acc.flush(a);
+}
+
+// List entries a worker visits, in steps of `unit` (64 for the wave-batched
+// role, else 1): one graph interleaves the workers; a batch gives each worker
+// one contiguous stretch, so its vertices fall in few graphs.
+struct Walk {
+    int first, end, step;
+};
+__device__ __forceinline__ Walk walk(const KArgs &a, int cnt, int worker, int nworkers, int unit)
+{
+    Walk w;
+    if (!a.vg) {
+        w.first = worker * unit;
+        w.end = cnt;
+        w.step = nworkers * unit;
+    } else {
+        int64_t chunk = ((int64_t)cnt + nworkers - 1) / nworkers;
+        chunk = (chunk + unit - 1) / unit * unit;
+        int64_t lo = (int64_t)worker * chunk;
+        lo = lo < cnt ? lo : cnt;
+        const int64_t hi = lo + chunk < cnt ? lo + chunk : cnt;
+        w.first = (int)lo;
+        w.end = (int)hi;
+        w.step = unit;
+    }
+    return w;
+}
+
+// Contiguous range [lo, hi) of `cnt` items for block `b` of `nb`.
+__device__ __forceinline__ void block_chunk(int cnt, int b, int nb, int &lo, int &hi)
+{
+    int64_t chunk = ((int64_t)cnt + nb - 1) / nb;
+    chunk = (chunk + BLOCK - 1) / BLOCK * BLOCK;
+    int64_t l = (int64_t)b * chunk;
+    l = l < cnt ? l : cnt;
+    lo = (int)l;
+    hi = (int)(l + chunk < cnt ? l + chunk : cnt);
+}
+
+__device__ __forceinline__ int degree_class(int64_t d)
+{
+    return d == 0 ? CLS_Z : (d <= S_MAXDEG ? CLS_S : (d <= M_MAXDEG ? CLS_M : CLS_L));
+}
+
 // ------------------------------------------------------------------ set-up --
 
-// Copies P_0, clears per-vertex state, sums vertex and part weights, counts
-// degree classes and checks part ids / vertex weights / xadj monotonicity.
-__global__ __launch_bounds__(BLOCK) void k_init_vertices(KArgs a, const int32_t *part_in)
+// Copies P_0, clears per-vertex state, sums vertex weights and part weights,
+// counts degree classes per block (for the ordered bins) and checks part ids,
+// vertex weights and row offsets. Vertex weights and the digest go to
+// counter rows 0 and 1 of the graph. Blocks own contiguous ranges.
+__global__ __launch_bounds__(BLOCK) void k_init_vertices(KArgs a, const int32_t *part_in, int32_t *blkcnt)
 {
-    extern __shared__ int32_t s_w[];  // [k] block-partial part weights
-    __shared__ int64_t s_red[BLOCK / 64];
-    __shared__ uint64_t s_redu[BLOCK / 64];
+    extern __shared__ int32_t s_w[];  // [k] block-partial part weights (one graph)
     __shared__ int32_t s_cls[NCLS];
-    for (int p = threadIdx.x; p < a.k; p += BLOCK) s_w[p] = 0;
+    const bool single = a.vg == nullptr;
+    if (single)
+        for (int p = threadIdx.x; p < a.k; p += BLOCK) s_w[p] = 0;
     if (threadIdx.x < NCLS) s_cls[threadIdx.x] = 0;
     __syncthreads();
-    int64_t wsum = 0;
-    uint64_t dig = 0;
-    int bad_part = 0, bad_graph = 0;
-    const int stride = gridDim.x * BLOCK;
-    for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += stride) {
+    int lo, hi;
+    block_chunk(a.n, blockIdx.x, gridDim.x, lo, hi);
+    GV gv;
+    GAcc<0, 1> acc;
+    int bad = 0;
+    for (int v = lo + threadIdx.x; v < hi; v += BLOCK) {
+        const int g = graph_of(a, v);
+        gv.at(a, g);
+        acc.to(a, g);
         int p = part_in[v];
-        if (p < 0 || p >= a.k) { bad_part = 1; p = 0; }
+        if (p < 0 || p >= gv.k) {
+            a.ctl[g].bad_part = 1;
+            p = 0;
+        } else if (a.best != part_in) {
+            a.best[v] = p;
+        }
         a.P[v] = p;
         a.dest[v] = -1;
         a.lock[v] = -1;
-        int vwv = a.vw ? a.vw[v] : 1;
-        if (vwv < 1) bad_graph = 1;
+        a.slot[v] = 255;
+        const int vwv = a.vw ? a.vw[v] : 1;
+        if (vwv < 1) bad = 1;
         int64_t d = a.xadj[v + 1] - a.xadj[v];
-        if (d < 0) { bad_graph = 1; d = 0; }
-        int c = d == 0 ? CLS_Z : (d <= S_MAXDEG ? CLS_S : (d <= M_MAXDEG ? CLS_M : CLS_L));
-        atomicAdd(&s_cls[c], 1);
-        atomicAdd(&s_w[p], vwv);
-        wsum += vwv;
-        dig += mix64(((uint64_t)(uint32_t)v << 32) | (uint32_t)p);
+        if (d < 0) {
+            bad = 1;
+            d = 0;
+        }
+        atomicAdd(&s_cls[degree_class(d)], 1);
+        if (single) atomicAdd(&s_w[p], vwv);
+        else atomicAdd((unsigned long long *)&a.w[gv.poff + p], (unsigned long long)(int64_t)vwv);
+        acc.c0 += vwv;
+        acc.c1 += mix64(((uint64_t)(uint32_t)(v - gv.voff) << 32) | (uint32_t)p);
     }
-    wsum = block_sum<BLOCK>(wsum, s_red);
-    dig = block_sum<BLOCK>(dig, s_redu);
-    if (bad_part) a.ctl->bad_part = 1;
-    if (bad_graph) a.ctl->bad_graph = 1;
-    if (threadIdx.x == 0) {
-        atomicAdd((unsigned long long *)&a.ctl->wsum, (unsigned long long)wsum);
-        atomicAdd((unsigned long long *)&a.ctl->digest, (unsigned long long)dig);
-    }
-    if (threadIdx.x < NCLS && s_cls[threadIdx.x]) atomicAdd(&a.ctl->bincnt[threadIdx.x], s_cls[threadIdx.x]);
-    for (int p = threadIdx.x; p < a.k; p += BLOCK)
-        if (s_w[p]) atomicAdd((unsigned long long *)&a.w[p], (unsigned long long)(int64_t)s_w[p]);
+    if (bad) a.cnt[1] = 1;
+    acc_finish(a, acc);
+    __syncthreads();
+    if (threadIdx.x < NCLS) blkcnt[blockIdx.x * NCLS + threadIdx.x] = s_cls[threadIdx.x];
+    if (single)
+        for (int p = threadIdx.x; p < a.k; p += BLOCK)
+            if (s_w[p]) atomicAdd((unsigned long long *)&a.w[p], (unsigned long long)(int64_t)s_w[p]);
 }
 
-// Edge pass: cut of P_0, total edge weight, neighbour-range / self-loop /
-// weight checks. Each thread walks a run of 16 consecutive CSR entries.
+// Edge pass: cut of P_0 and total edge weight (counter rows 2 and 3),
+// neighbour-range / self-loop / weight checks. Blocks own contiguous ranges
+// of runs of 16 consecutive CSR entries.
 __global__ __launch_bounds__(BLOCK) void k_init_edges(KArgs a, int64_t nnz)
 {
-    __shared__ int64_t s_red[BLOCK / 64];
     constexpr int RUN = 16;
-    int64_t cut = 0, ews = 0;
-    int bad = 0;
     const int64_t nruns = (nnz + RUN - 1) / RUN;
-    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < nruns; r += (int64_t)gridDim.x * BLOCK) {
-        int64_t e0 = r * RUN, e1 = e0 + RUN < nnz ? e0 + RUN : nnz;
-        // row containing e0: last v with xadj[v] <= e0
+    const int64_t per = (nruns + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = r0 + per < nruns ? r0 + per : nruns;
+    GAcc<2, 3> acc;
+    int bad = 0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += BLOCK) {
+        const int64_t e0 = r * RUN, e1 = e0 + RUN < nnz ? e0 + RUN : nnz;
         int lo = 0, hi = a.n;  // invariant xadj[lo] <= e0 < xadj[hi] (xadj[n] = nnz > e0)
         while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (a.xadj[mid] <= e0) lo = mid; else hi = mid;
+            const int mid = (lo + hi) >> 1;
+            if (a.xadj[mid] <= e0) lo = mid;
+            else hi = mid;
         }
         int v = lo;
         int64_t vend = a.xadj[v + 1];
         int pv = a.P[v];
+        acc.to(a, graph_of(a, v));
         for (int64_t e = e0; e < e1; e++) {
-            while (e >= vend && v < a.n - 1) { v++; vend = a.xadj[v + 1]; pv = a.P[v]; }
-            int u = a.adj[e];
-            int wt = a.ew ? a.ew[e] : 1;
-            if (u < 0 || u >= a.n || u == v || wt < 1) { bad = 1; continue; }
-            ews += wt;
-            if (u > v && a.P[u] != pv) cut += wt;
+            while (e >= vend && v < a.n - 1) {
+                v++;
+                vend = a.xadj[v + 1];
+                pv = a.P[v];
+                acc.to(a, graph_of(a, v));
+            }
+            const int u = a.adj[e];
+            const int wt = a.ew ? a.ew[e] : 1;
+            if (u < 0 || u >= a.n || u == v || wt < 1) {
+                bad = 1;
+                continue;
+            }
+            acc.c1 += wt;
+            if (u > v && a.P[u] != pv) acc.c0 += wt;
         }
     }
-    cut = block_sum<BLOCK>(cut, s_red);
-    ews = block_sum<BLOCK>(ews, s_red);
-    if (bad) a.ctl->bad_graph = 1;
+    if (bad) a.cnt[1] = 1;
+    acc_finish(a, acc);
+}
+
+// Per graph (one wave each): totals of the set-up counters into the controller.
+__global__ __launch_bounds__(64) void k_init_reduce(KArgs a)
+{
+    const int g = blockIdx.x;
+    const int64_t *b = a.bstat + (int64_t)g * NSTAT * NSHARD + threadIdx.x;
+    const int64_t ws = gsum<64>(b[0 * NSHARD]);
+    const uint64_t dg = gsum<64>((uint64_t)b[1 * NSHARD]);
+    const int64_t cut = gsum<64>(b[2 * NSHARD]);
+    const int64_t ews = gsum<64>(b[3 * NSHARD]);
     if (threadIdx.x == 0) {
-        atomicAdd((unsigned long long *)&a.ctl->cut, (unsigned long long)cut);
-        atomicAdd((unsigned long long *)&a.ctl->ewsum, (unsigned long long)ews);
+        Ctl *c = a.ctl + g;
+        c->wsum = ws;
+        c->digest = dg;
+        c->cut = cut;
+        c->ewsum = ews;
     }
 }
 
-// Fill the degree-class vertex lists.
-__global__ __launch_bounds__(BLOCK) void k_fill_bins(KArgs a, int32_t *bins, int32_t *fill)
+// Block offsets per degree class: exclusive scan over blocks, class-major, so
+// every class lists its vertices in ascending id. Totals land after the
+// nblk * NCLS offsets.
+__global__ __launch_bounds__(BLOCK) void k_bin_scan(int32_t *blkcnt, int nblk)
 {
-    const int stride = gridDim.x * BLOCK;
-    const int nloop = (a.n + stride - 1) / stride;
-    for (int it = 0; it < nloop; it++) {
-        int v = it * stride + blockIdx.x * BLOCK + threadIdx.x;
-        bool ok = v < a.n;
-        int c = -1;
-        if (ok) {
-            int64_t d = a.xadj[v + 1] - a.xadj[v];
-            c = d == 0 ? CLS_Z : (d <= S_MAXDEG ? CLS_S : (d <= M_MAXDEG ? CLS_M : CLS_L));
+    __shared__ int32_t s_scan[BLOCK / 64];
+    int32_t base = 0;
+    for (int c = 0; c < NCLS; c++) {
+        int32_t carry = 0;
+        for (int b0 = 0; b0 < nblk; b0 += BLOCK) {
+            const int b = b0 + threadIdx.x;
+            const int32_t x = b < nblk ? blkcnt[b * NCLS + c] : 0;
+            int32_t tot;
+            const int32_t ex = block_excl_scan<BLOCK>(x, s_scan, tot);
+            if (b < nblk) blkcnt[b * NCLS + c] = base + carry + ex;
+            carry += tot;
         }
+        if (threadIdx.x == 0) blkcnt[nblk * NCLS + c] = carry;
+        base += carry;
+    }
+}
+
+// Ordered fill of the class lists; same grid and ranges as k_init_vertices.
+__global__ __launch_bounds__(BLOCK) void k_fill_bins(KArgs a, const int32_t *blkoff, int32_t *bins)
+{
+    __shared__ int32_t s_scan[BLOCK / 64];
+    int lo, hi;
+    block_chunk(a.n, blockIdx.x, gridDim.x, lo, hi);
+    int32_t run[NCLS];
 #pragma unroll
-        for (int cc = 0; cc < NCLS; cc++) wave_append(c == cc, &fill[cc], bins + a.binoff[cc], v);
+    for (int c = 0; c < NCLS; c++) run[c] = blkoff[blockIdx.x * NCLS + c];
+    for (int base = lo; base < hi; base += BLOCK) {
+        const int v = base + threadIdx.x;
+        int cls = -1;
+        if (v < hi) cls = degree_class(a.xadj[v + 1] - a.xadj[v]);
+#pragma unroll
+        for (int c = 0; c < NCLS; c++) {
+            int32_t tot;
+            const int32_t pos = block_excl_scan<BLOCK>((int32_t)(cls == c), s_scan, tot);
+            if (cls == c) bins[run[c] + pos] = v;
+            run[c] += tot;
+        }
     }
 }
 
 // -------------------------------------------------------------- controller --
 
 // Oversized parts A = {w > o}, valid destinations B = {w <= sigma} listed in
-// ascending id, and a cleared (part, slot) histogram. Whole block calls.
-__device__ void rb_prepare(const KArgs &a)
+// ascending id, and a cleared (part, slot) histogram, for graph g. Whole
+// block calls.
+__device__ void rb_prepare(const KArgs &a, int g)
 {
     __shared__ int32_t s_scan[BLOCK / 64];
-    Ctl *c = a.ctl;
+    Ctl *c = a.ctl + g;
     const int64_t o = c->o, sigma = c->sigma;
+    const int k = c->k, poff = c->poff;
     int32_t carry = 0, nA = 0;
-    for (int base = 0; base < a.k; base += BLOCK) {
-        int p = base + threadIdx.x;
+    for (int base = 0; base < k; base += BLOCK) {
+        const int p = base + threadIdx.x;
         int inA = 0, inB = 0;
-        if (p < a.k) {
-            int64_t wp = a.w[p];
+        if (p < k) {
+            const int64_t wp = a.w[poff + p];
             inA = wp > o;
             inB = wp <= sigma;
-            a.isA[p] = (uint8_t)inA;
-            a.isB[p] = (uint8_t)inB;
+            a.isA[poff + p] = (uint8_t)inA;
+            a.isB[poff + p] = (uint8_t)inB;
         }
         int32_t tot;
-        int32_t pos = block_excl_scan<BLOCK>((int32_t)inB, s_scan, tot);
-        if (inB) a.Blist[carry + pos] = p;
+        const int32_t pos = block_excl_scan<BLOCK>((int32_t)inB, s_scan, tot);
+        if (inB) a.Blist[poff + carry + pos] = p;
         carry += tot;
         int32_t ta;
         block_excl_scan<BLOCK>((int32_t)inA, s_scan, ta);
         nA += ta;
     }
-    for (int i = threadIdx.x; i < a.k * NSLOT; i += BLOCK) a.hist[i] = 0;
-    if (threadIdx.x == 0) { c->nB = carry; c->nA = nA; }
+    for (int i = threadIdx.x; i < k * NSLOT; i += BLOCK) a.hist[(int64_t)poff * NSLOT + i] = 0;
+    if (threadIdx.x == 0) {
+        c->nB = carry;
+        c->nA = nA;
+    }
 }
 
 __device__ __forceinline__ void clear_accumulators(Ctl *c)
 {
-    c->nX = 0; c->nM = 0;
-    c->dcut = 0; c->moved_w = 0; c->ddigest = 0;
+    c->nX = 0;
+    c->nM = 0;
+    c->dcut = 0;
+    c->moved_w = 0;
+    c->ddigest = 0;
 }
 
 // Decides the kind of the next iteration from the loop state (thread 0):
@@ -186,61 +422,211 @@ __device__ __forceinline__ int ctl_next(Ctl &cc)
         kind = KIND_DONE;
     } else {
         cc.stall++;
-        if (cc.balanced) { kind = KIND_LP; cc.lp_id++; cc.wcount = 0; cc.n_lp++; }
-        else if (cc.wcount < cc.bmax) { kind = KIND_RW; cc.wcount++; cc.n_rw++; }
-        else { kind = KIND_RS; cc.wcount++; cc.n_rs++; }
+        if (cc.balanced) {
+            kind = KIND_LP;
+            cc.lp_id++;
+            cc.wcount = 0;
+            cc.n_lp++;
+        } else if (cc.wcount < cc.bmax) {
+            kind = KIND_RW;
+            cc.wcount++;
+            cc.n_rw++;
+        } else {
+            kind = KIND_RS;
+            cc.wcount++;
+            cc.n_rs++;
+        }
     }
     cc.kind = kind;
     clear_accumulators(&cc);
     return kind;
 }
 
-// Whole-block part of starting an iteration: clear the counter shards and,
-// for rebalancing, build A, B and clear the histogram.
-__device__ __forceinline__ void begin_iteration(const KArgs &a, int kind)
+// Whole-block part of starting graph g's next iteration: clear its counter
+// shards and, for rebalancing, build A, B and clear its histogram.
+__device__ __forceinline__ void begin_iteration(const KArgs &a, int g, int kind)
 {
-    for (int i = threadIdx.x; i < NSTAT * NSHARD; i += blockDim.x) a.bstat[i] = 0;
-    if (kind == KIND_RW || kind == KIND_RS) rb_prepare(a);
+    for (int i = threadIdx.x; i < NSTAT * NSHARD; i += BLOCK) a.bstat[(int64_t)g * NSTAT * NSHARD + i] = 0;
+    if (is_rb(kind)) rb_prepare(a, g);
 }
 
-// Derived loop state after the set-up passes.
-__global__ __launch_bounds__(BLOCK) void k_ctl_setup(KArgs a, int64_t W, int64_t o, int64_t sigma)
+// Adds graph g's next kind (and whether its best must be copied) to the
+// count row of launch `it`.
+__device__ __forceinline__ void count_next(const KArgs &a, int it, int next, int copy)
+{
+    if (next == KIND_DONE) {
+        atomicAdd(&a.cnt[CNT_DONE], 1);
+        return;
+    }
+    int32_t *row = a.cnt + CNT_ROW + (it & 1) * 4;
+    atomicAdd(&row[next], 1);
+    if (copy) atomicAdd(&row[0], 1);
+}
+
+// Per graph (one block each): loop state after the set-up passes (W, o and
+// sigma are already set), then the first iteration's kind.
+__global__ __launch_bounds__(BLOCK) void k_ctl_setup(KArgs a)
 {
     __shared__ uint64_t s_red[BLOCK / 64];
-    Ctl *c = a.ctl;
+    __shared__ int s_next;
+    const int g = blockIdx.x;
+    Ctl *c = a.ctl + g;
+    const int k = c->k, poff = c->poff;
     uint64_t m = 0;
-    for (int p = threadIdx.x; p < a.k; p += BLOCK) {
-        uint64_t x = (uint64_t)a.w[p];
+    for (int p = threadIdx.x; p < k; p += BLOCK) {
+        const uint64_t x = (uint64_t)a.w[poff + p];
         m = x > m ? x : m;
-        a.wbest[p] = a.w[p];
+        a.wbest[poff + p] = a.w[poff + p];
     }
     m = block_max_u64<BLOCK>(m, s_red);
-    __shared__ int s_next;
     if (threadIdx.x == 0) {
         Ctl cc = *c;
-        cc.W = W; cc.o = o; cc.sigma = sigma;
         cc.maxw = (int64_t)m;
-        cc.balanced = (int64_t)m <= o;
+        cc.balanced = (int64_t)m <= cc.o;
         cc.bal_best = cc.balanced;
         cc.cut_best = cc.cut;
         cc.maxw_best = cc.maxw;
-        s_next = ctl_next(cc);  // iteration 0
+        const int next = ctl_next(cc);  // iteration 0
         *c = cc;
+        s_next = next;
+        count_next(a, a.it, next, 0);
     }
     __syncthreads();
-    begin_iteration(a, s_next);
+    begin_iteration(a, g, s_next);
 }
 
-// Adds a block's partial counter into one of NSHARD shards of its stat row
-// (shards spread the atomics; the controller sums NSHARD values per row).
-__device__ __forceinline__ void shard_add(const KArgs &a, int row, int64_t val)
+// Per graph (one block each): end of an iteration. Sums the counter shards,
+// applies Algorithm 3's best / stall rules, writes the trace record, decides
+// the next iteration and starts it.
+__global__ __launch_bounds__(BLOCK) void k_ctl_end(KArgs a)
 {
-    if (val) atomicAdd((unsigned long long *)&a.bstat[row * NSHARD + (blockIdx.x & (NSHARD - 1))],
-                       (unsigned long long)val);
+    __shared__ uint64_t s_red[BLOCK / 64];
+    __shared__ int64_t s_red64[BLOCK / 64];
+    __shared__ int s_improved, s_next;
+    // this launch's count row has been read by every kernel of the iteration:
+    // clear it for the iteration after next
+    if (blockIdx.x == 0 && threadIdx.x < 4) a.cnt[CNT_ROW + (a.it & 1) * 4 + threadIdx.x] = 0;
+    const int g = blockIdx.x;
+    Ctl *c = a.ctl + g;
+    const int kind = c->kind;
+    if (kind == KIND_DONE) return;
+    const int k = c->k, poff = c->poff;
+    uint64_t m = 0;
+    for (int p = threadIdx.x; p < k; p += BLOCK) {
+        const uint64_t x = (uint64_t)a.w[poff + p];
+        m = x > m ? x : m;
+    }
+    m = block_max_u64<BLOCK>(m, s_red);
+    int64_t px = 0, pm = 0, pdc = 0, pmw = 0, pe = 0, pr = 0, pv = 0;
+    uint64_t pdg = 0;
+    if (threadIdx.x < NSHARD) {
+        const int64_t *b = a.bstat + (int64_t)g * NSTAT * NSHARD + threadIdx.x;
+        px = b[ST_X * NSHARD];
+        pm = b[ST_M * NSHARD];
+        pdc = b[ST_DCUT * NSHARD];
+        pmw = b[ST_MW * NSHARD];
+        pdg = (uint64_t)b[ST_DIG * NSHARD];
+        if (kind == KIND_LP) {
+            pe = b[ST_E * NSHARD];
+            pr = b[ST_R * NSHARD];
+            pv = b[ST_V * NSHARD];
+        }
+    }
+    px = block_sum<BLOCK>(px, s_red64);
+    pm = block_sum<BLOCK>(pm, s_red64);
+    pdc = block_sum<BLOCK>(pdc, s_red64);
+    pmw = block_sum<BLOCK>(pmw, s_red64);
+    pe = block_sum<BLOCK>(pe, s_red64);
+    pr = block_sum<BLOCK>(pr, s_red64);
+    pv = block_sum<BLOCK>(pv, s_red64);
+    pdg = block_sum<BLOCK>(pdg, s_red);
+    if (threadIdx.x == 0) {
+        // one load of the whole state, one store: no dependent global round trips
+        Ctl cc = *c;
+        const int64_t maxw = (int64_t)m;
+        cc.nX = (int)px;
+        cc.nM = (int)pm;
+        cc.dcut = pdc;
+        cc.moved_w = pmw;
+        cc.ddigest = pdg;
+        cc.prof_e += pe;
+        cc.prof_r += pr;
+        cc.prof_v += pv;
+        cc.cut += cc.dcut;
+        cc.digest += cc.ddigest;
+        cc.maxw = maxw;
+        const int bal = maxw <= cc.o;
+        cc.balanced = bal;
+        int improved = 0;
+        if (bal) {
+            if (!cc.bal_best) {
+                // a balanced partition always replaces an imbalanced best
+                improved = 1;
+                cc.bal_best = 1;
+                cc.cut_best = cc.cut;
+                cc.maxw_best = maxw;
+                cc.stall = 0;
+            } else if (cc.cut < cc.cut_best) {
+                // only a gain beyond the tolerance phi restarts the count
+                if ((int64_t)cc.phi_den * cc.cut < (int64_t)cc.phi_num * cc.cut_best) cc.stall = 0;
+                improved = 1;
+                cc.cut_best = cc.cut;
+                cc.maxw_best = maxw;
+            }
+        } else if (!cc.bal_best && maxw < cc.maxw_best) {
+            improved = 1;
+            cc.maxw_best = maxw;
+            cc.cut_best = cc.cut;
+            cc.stall = 0;
+        }
+        cc.copy_best = improved;
+        if (g == 0 && a.kinds && cc.t < KIND_LOG) a.kinds[cc.t] = (int8_t)kind;
+        if (a.trace && cc.t < cc.trace_cap) {
+            jet_trace_rec r;
+            r.level = cc.level;
+            r.t = cc.t;
+            r.kind = kind;
+            r.nX = cc.nX;
+            r.nM = cc.nM;
+            r.stall = cc.stall;
+            r.wcount = cc.wcount;
+            r.balanced = bal;
+            r.moved_w = cc.moved_w;
+            r.cut = cc.cut;
+            r.maxw = maxw;
+            r.best_cut = cc.cut_best;
+            r.digest = cc.digest;
+            a.trace[(int64_t)cc.trace_off + cc.t] = r;
+        }
+        cc.t++;
+        const int next = ctl_next(cc);
+        *c = cc;
+        s_improved = improved;
+        s_next = next;
+        count_next(a, a.it + 1, next, improved);
+    }
+    __syncthreads();
+    if (s_improved)
+        for (int p = threadIdx.x; p < k; p += BLOCK) a.wbest[poff + p] = a.w[poff + p];
+    begin_iteration(a, g, s_next);
 }
 
-// Single-step entry points: force one iteration of `kind` at index t. For
-// Jetlp, lock flags become stamps of the previous Jetlp (id 0).
+// After the loop: P_iter into P_best for graphs whose last iteration improved
+// the best (earlier improvements were copied by the next cut-delta pass).
+__global__ __launch_bounds__(BLOCK) void k_copy_best(KArgs a)
+{
+    if (!a.vg && !a.ctl->copy_best) return;
+    GV gv;
+    int lo, hi;
+    block_chunk(a.n, blockIdx.x, gridDim.x, lo, hi);
+    for (int v = lo + threadIdx.x; v < hi; v += BLOCK) {
+        gv.at(a, graph_of(a, v));
+        if (gv.copy) a.best[v] = a.P[v];
+    }
+}
+
+// Single-step entry points (one graph): force one iteration of `kind` at
+// index t. For Jetlp, lock flags become stamps of the previous Jetlp (id 0).
 __global__ __launch_bounds__(BLOCK) void k_force_step(KArgs a, int kind, int t, const uint8_t *locked)
 {
     Ctl *c = a.ctl;
@@ -249,12 +635,14 @@ __global__ __launch_bounds__(BLOCK) void k_force_step(KArgs a, int kind, int t, 
         c->t = t;
         c->lp_id = 1;
         clear_accumulators(c);
+        for (int i = 0; i < 8; i++) a.cnt[CNT_ROW + i] = 0;
+        a.cnt[CNT_ROW + (a.it & 1) * 4 + kind] = 1;
     }
     if (locked)
         for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) a.lock[v] = locked[v] ? 0 : -1;
     if (blockIdx.x == 0) {
         __syncthreads();
-        begin_iteration(a, kind);
+        begin_iteration(a, 0, kind);
     }
 }
 
@@ -262,8 +650,16 @@ __global__ __launch_bounds__(BLOCK) void k_force_step(KArgs a, int kind, int t, 
 __global__ __launch_bounds__(BLOCK) void k_step_defaults(KArgs a, const int32_t *part)
 {
     for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) {
-        if (a.dbg_F) { a.dbg_F[v] = INT64_MIN; a.dbg_cs[v] = 0; a.dbg_F2[v] = 0; a.dbg_pd[v] = part[v]; }
-        if (a.dbg_loss) { a.dbg_loss[v] = INT64_MIN; a.dbg_slot[v] = -1; }
+        if (a.dbg_F) {
+            a.dbg_F[v] = INT64_MIN;
+            a.dbg_cs[v] = 0;
+            a.dbg_F2[v] = 0;
+            a.dbg_pd[v] = part[v];
+        }
+        if (a.dbg_loss) {
+            a.dbg_loss[v] = INT64_MIN;
+            a.dbg_slot[v] = -1;
+        }
     }
 }
 
@@ -276,116 +672,13 @@ __global__ __launch_bounds__(BLOCK) void k_lp_outputs(KArgs a, uint8_t *inX, uin
     }
 }
 
-constexpr int CTL_NT = BLOCK;  // threads of the end-of-iteration controller
-
-__global__ __launch_bounds__(CTL_NT) void k_ctl_end(KArgs a)
-{
-    __shared__ uint64_t s_red[CTL_NT / 64];
-    __shared__ int64_t s_red64[CTL_NT / 64];
-    __shared__ int s_improved, s_next;
-    Ctl *c = a.ctl;
-    const int kind = c->kind;
-    if (kind == KIND_DONE) return;
-    uint64_t m = 0;
-    for (int p = threadIdx.x; p < a.k; p += CTL_NT) {
-        uint64_t x = (uint64_t)a.w[p];
-        m = x > m ? x : m;
-    }
-    m = block_max_u64<CTL_NT>(m, s_red);
-    // this iteration's counters (NSHARD shards per row)
-    int64_t px = 0, pm = 0, pdc = 0, pmw = 0;
-    uint64_t pdg = 0;
-    int64_t pe = 0, pr = 0, pv = 0;
-    if (threadIdx.x < NSHARD) {
-        const int i = threadIdx.x;
-        px = a.bstat[ST_X * NSHARD + i];
-        pm = a.bstat[ST_M * NSHARD + i];
-        pdc = a.bstat[ST_DCUT * NSHARD + i];
-        pmw = a.bstat[ST_MW * NSHARD + i];
-        pdg = (uint64_t)a.bstat[ST_DIG * NSHARD + i];
-        if (kind == KIND_LP) {
-            pe = a.bstat[ST_E * NSHARD + i];
-            pr = a.bstat[ST_R * NSHARD + i];
-            pv = a.bstat[ST_V * NSHARD + i];
-        }
-    }
-    pe = block_sum<CTL_NT>(pe, s_red64);
-    pr = block_sum<CTL_NT>(pr, s_red64);
-    pv = block_sum<CTL_NT>(pv, s_red64);
-    px = block_sum<CTL_NT>(px, s_red64);
-    pm = block_sum<CTL_NT>(pm, s_red64);
-    pdc = block_sum<CTL_NT>(pdc, s_red64);
-    pmw = block_sum<CTL_NT>(pmw, s_red64);
-    pdg = block_sum<CTL_NT>(pdg, s_red);
-    if (threadIdx.x == 0) {
-        // one load of the whole state, one store: no dependent global round trips
-        Ctl cc = *c;
-        const int64_t maxw = (int64_t)m;
-        const int nM = (int)pm, nXl = (int)px;
-        cc.nX = nXl; cc.nM = nM;
-        cc.dcut = pdc; cc.moved_w = pmw; cc.ddigest = pdg;
-        cc.prof_e += pe; cc.prof_r += pr; cc.prof_v += pv;
-        cc.cut += cc.dcut;
-        cc.digest += cc.ddigest;
-        cc.maxw = maxw;
-        const int bal = maxw <= cc.o;
-        cc.balanced = bal;
-        int improved = 0;
-        if (bal) {
-            if (!cc.bal_best) {
-                // a balanced partition always replaces an imbalanced best
-                improved = 1; cc.bal_best = 1; cc.cut_best = cc.cut; cc.maxw_best = maxw; cc.stall = 0;
-            } else if (cc.cut < cc.cut_best) {
-                // only a gain beyond the tolerance phi restarts the count
-                if ((int64_t)cc.phi_den * cc.cut < (int64_t)cc.phi_num * cc.cut_best) cc.stall = 0;
-                improved = 1; cc.cut_best = cc.cut; cc.maxw_best = maxw;
-            }
-        } else if (!cc.bal_best && maxw < cc.maxw_best) {
-            improved = 1; cc.maxw_best = maxw; cc.cut_best = cc.cut; cc.stall = 0;
-        }
-        cc.copy_best = improved;
-        if (a.kinds && cc.t < KIND_LOG) a.kinds[cc.t] = (int8_t)kind;
-        if (a.trace && cc.t < cc.trace_cap) {
-            jet_trace_rec r;
-            r.level = cc.level; r.t = cc.t; r.kind = kind;
-            r.nX = nXl;
-            r.nM = nM; r.stall = cc.stall; r.wcount = cc.wcount; r.balanced = bal;
-            r.moved_w = cc.moved_w; r.cut = cc.cut; r.maxw = maxw; r.best_cut = cc.cut_best;
-            r.digest = cc.digest;
-            a.trace[cc.t] = r;
-        }
-        cc.t++;
-        s_next = ctl_next(cc);
-        *c = cc;
-        s_improved = improved;
-    }
-    __syncthreads();
-    if (s_improved)
-        for (int p = threadIdx.x; p < a.k; p += CTL_NT) a.wbest[p] = a.w[p];
-    begin_iteration(a, s_next);
-}
-
-__global__ __launch_bounds__(BLOCK) void k_copy_best(KArgs a)
-{
-    if (!a.ctl->copy_best) return;
-    const int stride = gridDim.x * BLOCK;
-    if ((((uintptr_t)a.best | (uintptr_t)a.P) & 15) == 0) {
-        const int n4 = a.n >> 2;
-        const int4 *src = (const int4 *)a.P;
-        int4 *dst = (int4 *)a.best;
-        for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n4; i += stride) dst[i] = src[i];
-        for (int v = (n4 << 2) + blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += stride) a.best[v] = a.P[v];
-    } else {
-        for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += stride) a.best[v] = a.P[v];
-    }
-}
-
 // ------------------------------------------------------ connectivity core --
 
-// Group of G lanes gathers the neighbours of v (deg <= G*R) into table `tab`
-// and reads every adjacent part's total back exactly once: on return pu[r] is
-// the part of neighbour slot r (-1 if none) and cu[r] its connectivity for the
-// first lane that claimed it, else 0. The table is left all-zero.
+// Group of G lanes gathers the neighbours of a row (deg <= G*R) into table
+// `tab` and reads every adjacent part's total back exactly once: on return
+// pu[r] is the part of neighbour slot r (-1 if none) and cu[r] its
+// connectivity for the first lane that claimed it, else 0. The table is left
+// all-zero.
 template <int G, int R>
 __device__ __forceinline__ void group_conn_row(const KArgs &a, int64_t s, int deg, int gl, int32_t *tab, int (&pu)[R],
                                                int (&cu)[R])
@@ -407,34 +700,26 @@ __device__ __forceinline__ void group_conn_row(const KArgs &a, int64_t s, int de
     lds_fence_wave();
 }
 
-template <int G, int R>
-__device__ __forceinline__ void group_conn(const KArgs &a, int v, int gl, int32_t *tab, int (&pu)[R], int (&cu)[R])
-{
-    const int64_t s = a.xadj[v];
-    group_conn_row<G, R>(a, s, (int)(a.xadj[v + 1] - s), gl, tab, pu, cu);
-}
-
-// Wave-batched driver of the 8-lane role. Lanes first inspect 64 list
+// Wave-batched driver of the small-row role. Lanes first inspect 64 list
 // entries at once (coalesced loads of the id, row offsets and per-vertex
 // state); the entries that need row work are queued in LDS and handed to the
-// wave's eight 8-lane groups, eight at a time. Metadata round trips are paid
-// once per 64 vertices instead of once per vertex, and skipped vertices cost
-// no group time.
+// wave's groups of G lanes. Metadata round trips are paid once per 64
+// vertices instead of once per vertex, and skipped vertices cost no group
+// time.
 struct Meta {
-    int v, ps, deg, aux;
+    int v, ps, deg, aux, g;
     int64_t s;
 };
 
 template <int G, class Pre, class Row>
-__device__ __forceinline__ void wave_batched(const int32_t *list, int cnt, int32_t *q, int wid, int nwaves, Pre pre,
-                                             Row row)
+__device__ __forceinline__ void wave_batched(const int32_t *list, Walk w, int32_t *q, Pre pre, Row row)
 {
-    const int lane = threadIdx.x & 63, g = lane / G, gl = lane & (G - 1);
-    for (int base = wid * 64; base < cnt; base += nwaves * 64) {
+    const int lane = threadIdx.x & 63, grp = lane / G, gl = lane & (G - 1);
+    for (int base = w.first; base < w.end; base += w.step) {
         const int i = base + lane;
-        Meta m{0, 0, 0, 0, 0};
+        Meta m{0, 0, 0, 0, 0, 0};
         bool act = false;
-        if (i < cnt) {
+        if (i < w.end) {
             m.v = list[i];
             act = pre(m);
         }
@@ -443,7 +728,7 @@ __device__ __forceinline__ void wave_batched(const int32_t *list, int cnt, int32
         lds_fence_wave();
         const int nact = __popcll(mask);
         for (int sb = 0; sb < nact; sb += 64 / G) {
-            const int slot = sb + g;
+            const int slot = sb + grp;
             const bool has = slot < nact;
             const int src = q[has ? slot : 0];
             Meta t;
@@ -451,6 +736,7 @@ __device__ __forceinline__ void wave_batched(const int32_t *list, int cnt, int32
             t.ps = __shfl(m.ps, src, 64);
             t.deg = __shfl(m.deg, src, 64);
             t.aux = __shfl(m.aux, src, 64);
+            t.g = __shfl(m.g, src, 64);
             t.s = __shfl(m.s, src, 64);
             if (has) row(t, gl);
         }
@@ -458,14 +744,7 @@ __device__ __forceinline__ void wave_batched(const int32_t *list, int cnt, int32
     }
 }
 
-template <class Pre, class Row>
-__device__ __forceinline__ void wave_batched8(const int32_t *list, int cnt, int32_t *q, int wid, int nwaves, Pre pre,
-                                              Row row)
-{
-    wave_batched<8>(list, cnt, q, wid, nwaves, pre, row);
-}
-
-// Whole block gathers the neighbours of v into `tab` (k entries).
+// Whole block gathers the neighbours of v into `tab`.
 __device__ __forceinline__ void block_fill(const KArgs &a, int v, int32_t *tab)
 {
     const int64_t s = a.xadj[v], e = a.xadj[v + 1];
@@ -478,15 +757,12 @@ __device__ __forceinline__ void block_fill(const KArgs &a, int v, int32_t *tab)
 
 // Largest-connectivity key: connectivity in the high word, ~part in the low
 // word, so ties go to the smaller part id.
-__device__ __forceinline__ uint64_t conn_key(int c, int p)
-{
-    return ((uint64_t)(uint32_t)c << 32) | (uint32_t)(~p);
-}
+__device__ __forceinline__ uint64_t conn_key(int c, int p) { return ((uint64_t)(uint32_t)c << 32) | (uint32_t)(~p); }
 
 // -------------------------------------------------------------- Jetlp gain --
 
-// Writes rec[v] and appends v to its class's X list when it passes the
-// first filter (eq. gainconn_filter).
+// Writes rec[v]; returns whether v passes the first filter (a destination
+// exists and F >= 0 or -F < floor(c * conn(v, P_s))).
 __device__ __forceinline__ bool gain_finish(const KArgs &a, int v, int ps, uint64_t best, int cs, int cn, int cd)
 {
     int2 r;
@@ -516,98 +792,127 @@ __device__ __forceinline__ bool gain_finish(const KArgs &a, int v, int ps, uint6
 __device__ __forceinline__ void gain_locked(const KArgs &a, int v, int ps)
 {
     a.rec[v] = make_int2(ps << 16, 0);
-    if (a.dbg_F) { a.dbg_F[v] = INT64_MIN; a.dbg_cs[v] = 0; a.dbg_pd[v] = ps; }
+    if (a.dbg_F) {
+        a.dbg_F[v] = INT64_MIN;
+        a.dbg_cs[v] = 0;
+        a.dbg_pd[v] = ps;
+    }
 }
 
-struct GainCount {
-    int nx = 0;
-    int64_t e = 0, r = 0, v = 0;
-};
+typedef GAcc<ST_V, ST_R, ST_E> GainPre;  // visited vertices, unlocked rows, their CSR entries
+typedef GAcc<ST_X> CountX;
 
 template <int G, int R>
-__device__ void gain_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ngroups, int lp_prev, int cn, int cd,
-                            GainCount &gc)
+__device__ void gain_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ngroups, GV &gv, GainPre &pacc,
+                            CountX &racc)
 {
     const int gl = threadIdx.x & (G - 1);
     const int32_t *list = a.bins + a.binoff[cls];
-    const int cnt = a.binoff[cls + 1] - a.binoff[cls];
-    for (int i = gid; i < cnt; i += ngroups) {
+    const Walk w = walk(a, a.binoff[cls + 1] - a.binoff[cls], gid, ngroups, 1);
+    for (int i = w.first; i < w.end; i += w.step) {
         const int v = list[i];
+        const int g = graph_of(a, v);
+        gv.at(a, g);
+        if (gv.kind != KIND_LP) continue;
         const int ps = a.P[v];
-        if (gl == 0) gc.v++;
-        if (a.lock[v] == lp_prev) {
+        if (gl == 0) {
+            pacc.to(a, g);
+            pacc.c0++;
+        }
+        if (a.lock[v] == gv.lp_id - 1) {
             if (gl == 0) gain_locked(a, v, ps);
             continue;
         }
-        if (gl == 0) { gc.r++; gc.e += a.xadj[v + 1] - a.xadj[v]; }
+        const int64_t s = a.xadj[v];
+        const int deg = (int)(a.xadj[v + 1] - s);
+        if (gl == 0) {
+            pacc.c1++;
+            pacc.c2 += deg;
+        }
         int pu[R], cu[R];
-        group_conn<G, R>(a, v, gl, tab, pu, cu);
+        group_conn_row<G, R>(a, s, deg, gl, tab, pu, cu);
         uint64_t best = 0;
         int cs = 0;
 #pragma unroll
         for (int r = 0; r < R; r++) {
             if (cu[r] > 0) {
                 if (pu[r] == ps) cs += cu[r];
-                else { uint64_t k2 = conn_key(cu[r], pu[r]); best = k2 > best ? k2 : best; }
+                else {
+                    const uint64_t k2 = conn_key(cu[r], pu[r]);
+                    best = k2 > best ? k2 : best;
+                }
             }
         }
         best = gmax_u64<G>(best);
         cs = gsum<G>(cs);
-        if (gl == 0) gc.nx += gain_finish(a, v, ps, best, cs, cn, cd);
+        if (gl == 0) {
+            racc.to(a, g);
+            racc.c0 += gain_finish(a, v, ps, best, cs, gv.cn, gv.cd);
+        }
     }
 }
 
-__device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nblocks, int lp_prev, int cn, int cd,
-                            GainCount &gc)
+__device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nblocks, GV &gv, GainPre &pacc,
+                            CountX &racc)
 {
     __shared__ uint64_t s_red[BLOCK / 64];
     __shared__ int32_t s_red32[BLOCK / 64];
     const int32_t *list = a.bins + a.binoff[cls];
-    const int cnt = a.binoff[cls + 1] - a.binoff[cls];
-    for (int i = bid; i < cnt; i += nblocks) {
+    const Walk w = walk(a, a.binoff[cls + 1] - a.binoff[cls], bid, nblocks, 1);
+    for (int i = w.first; i < w.end; i += w.step) {
         const int v = list[i];
+        const int g = graph_of(a, v);
+        gv.at(a, g);
+        if (gv.kind != KIND_LP) continue;
         const int ps = a.P[v];
-        if (threadIdx.x == 0) gc.v++;
-        if (a.lock[v] == lp_prev) {
+        if (threadIdx.x == 0) {
+            pacc.to(a, g);
+            pacc.c0++;
+        }
+        if (a.lock[v] == gv.lp_id - 1) {
             if (threadIdx.x == 0) gain_locked(a, v, ps);
             continue;
         }
-        if (threadIdx.x == 0) { gc.r++; gc.e += a.xadj[v + 1] - a.xadj[v]; }
+        if (threadIdx.x == 0) {
+            pacc.c1++;
+            pacc.c2 += a.xadj[v + 1] - a.xadj[v];
+        }
         block_fill(a, v, tab);
         uint64_t best = 0;
         int cs = 0;
-        for (int p = threadIdx.x; p < a.k; p += BLOCK) {
+        for (int p = threadIdx.x; p < gv.k; p += BLOCK) {
             const int c = tab[p];
             if (c) {
                 tab[p] = 0;
                 if (p == ps) cs = c;
-                else { uint64_t k2 = conn_key(c, p); best = k2 > best ? k2 : best; }
+                else {
+                    const uint64_t k2 = conn_key(c, p);
+                    best = k2 > best ? k2 : best;
+                }
             }
         }
         best = block_max_u64<BLOCK>(best, s_red);
         cs = block_sum<BLOCK>(cs, s_red32);
-        if (threadIdx.x == 0) gc.nx += gain_finish(a, v, ps, best, cs, cn, cd);
+        if (threadIdx.x == 0) {
+            racc.to(a, g);
+            racc.c0 += gain_finish(a, v, ps, best, cs, gv.cn, gv.cd);
+        }
     }
 }
 
-// Role layout of the LDS-table kernels: blocks [0, gS) serve the classes
-// mapped to the 8-lane role, the next gM blocks the wave role, the next gL
-// blocks the block role, and (rebalancing only) the last gZ blocks isolated
-// vertices.
-// One kernel per role (8-lane groups, waves, blocks), so each keeps its own
-// register budget. Group tables are padded to k + 1 ints so the tables of
-// neighbouring groups start in different LDS banks. Block partials of |X|
-// land at offset `boff` of the counter row.
+// Role layout of the LDS-table kernels: one kernel per role (small-row
+// groups, waves, blocks), so each keeps its own register budget; a.tmap says
+// which classes a role serves. Group tables are padded to k + 1 ints so the
+// tables of neighbouring groups start in different LDS banks.
 template <int ROLE, int GS = 8>
-__global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk, int boff)
+__global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
 {
-    if (a.ctl->kind != KIND_LP) return;
+    if (!any_kind(a, KIND_LP)) return;
     extern __shared__ int32_t lds[];
-    __shared__ int32_t s_red32[BLOCK / 64];
-    const int lp_prev = a.ctl->lp_id - 1;
-    const int cn = a.ctl->c_num, cd = a.ctl->c_den;
     const int stride = a.k + 1;
-    GainCount gc;
+    GV pv, rv;
+    GainPre pacc;
+    CountX racc;
     if (ROLE == 1) {
         constexpr int RS_ = 32 / GS;
         const int ng = BLOCK / GS;
@@ -619,18 +924,22 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk, int boff)
         for (int c = 1; c < NCLS; c++) {
             if (a.tmap[c] != 1) continue;
             wave_batched<GS>(
-                a.bins + a.binoff[c], a.binoff[c + 1] - a.binoff[c], q, wid, nwaves,
+                a.bins + a.binoff[c], walk(a, a.binoff[c + 1] - a.binoff[c], wid, nwaves, 64), q,
                 [&](Meta &m) -> bool {
+                    m.g = graph_of(a, m.v);
+                    pv.at(a, m.g);
+                    if (pv.kind != KIND_LP) return false;
                     m.ps = a.P[m.v];
-                    gc.v++;
-                    if (a.lock[m.v] == lp_prev) {
+                    pacc.to(a, m.g);
+                    pacc.c0++;
+                    if (a.lock[m.v] == pv.lp_id - 1) {
                         gain_locked(a, m.v, m.ps);
                         return false;
                     }
                     m.s = a.xadj[m.v];
                     m.deg = (int)(a.xadj[m.v + 1] - m.s);
-                    gc.r++;
-                    gc.e += m.deg;
+                    pacc.c1++;
+                    pacc.c2 += m.deg;
                     return true;
                 },
                 [&](const Meta &t, int gl) {
@@ -642,12 +951,19 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk, int boff)
                     for (int r = 0; r < RS_; r++) {
                         if (cu[r] > 0) {
                             if (pu[r] == t.ps) cs += cu[r];
-                            else { uint64_t k2 = conn_key(cu[r], pu[r]); best = k2 > best ? k2 : best; }
+                            else {
+                                const uint64_t k2 = conn_key(cu[r], pu[r]);
+                                best = k2 > best ? k2 : best;
+                            }
                         }
                     }
                     best = gmax_u64<GS>(best);
                     cs = gsum<GS>(cs);
-                    if (gl == 0) gc.nx += gain_finish(a, t.v, t.ps, best, cs, cn, cd);
+                    if (gl == 0) {
+                        rv.at(a, t.g);
+                        racc.to(a, t.g);
+                        racc.c0 += gain_finish(a, t.v, t.ps, best, cs, rv.cn, rv.cd);
+                    }
                 });
         }
     } else if (ROLE == 2) {
@@ -657,24 +973,15 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk, int boff)
         int32_t *tab = lds + (threadIdx.x >> 6) * stride;
         for (int c = 1; c < NCLS; c++)
             if (a.tmap[c] == 2)
-                gain_groups<64, 16>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 6), nblk * ng, lp_prev, cn, cd, gc);
+                gain_groups<64, 16>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 6), nblk * ng, pv, pacc, racc);
     } else {
         for (int i = threadIdx.x; i < a.k; i += BLOCK) lds[i] = 0;
         __syncthreads();
         for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 3) gain_blocks(a, c, lds, blockIdx.x, nblk, lp_prev, cn, cd, gc);
+            if (a.tmap[c] == 3) gain_blocks(a, c, lds, blockIdx.x, nblk, pv, pacc, racc);
     }
-    __shared__ int64_t s_red64[BLOCK / 64];
-    const int nx = block_sum<BLOCK>(gc.nx, s_red32);
-    const int64_t e = block_sum<BLOCK>(gc.e, s_red64);
-    const int64_t r = block_sum<BLOCK>(gc.r, s_red64);
-    const int64_t v = block_sum<BLOCK>(gc.v, s_red64);
-    if (threadIdx.x == 0) {
-        shard_add(a, ST_X, nx);
-        shard_add(a, ST_E, e);
-        shard_add(a, ST_R, r);
-        shard_add(a, ST_V, v);
-    }
+    acc_finish(a, pacc);
+    acc_finish(a, racc);
 }
 
 // -------------------------------------------------------------- afterburner --
@@ -698,45 +1005,29 @@ __device__ __forceinline__ int after_sum_row(const KArgs &a, int v, int64_t s, i
     return sum;
 }
 
-template <int G>
-__device__ __forceinline__ int after_sum(const KArgs &a, int v, int ps, int pd, int Fv, int gl, int stride)
+__device__ __forceinline__ void after_store(const KArgs &a, int v, int pd, int sum)
 {
-    const int64_t s = a.xadj[v];
-    return after_sum_row(a, v, s, (int)(a.xadj[v + 1] - s), ps, pd, Fv, gl, stride);
-}
-
-template <int G>
-__device__ void after_groups(const KArgs &a, int cls, int gid, int ngroups)
-{
-    const int gl = threadIdx.x & (G - 1);
-    const int32_t *list = a.bins + a.binoff[cls];
-    const int cnt = a.binoff[cls + 1] - a.binoff[cls];
-    for (int i = gid; i < cnt; i += ngroups) {
-        const int v = list[i];
-        const int2 r = a.rec[v];
-        if ((r.x & 0xFFFF) == 0) continue;  // not in X
-        const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
-        int sum = after_sum<G>(a, v, ps, pd, r.y, gl, G);
-        sum = gsum<G>(sum);
-        if (gl == 0) {
-            if (a.dbg_F2) a.dbg_F2[v] = sum;
-            if (sum >= 0) a.dest[v] = pd;
-        }
-    }
+    if (a.dbg_F2) a.dbg_F2[v] = sum;
+    if (sum >= 0) a.dest[v] = pd;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_afterburner(KArgs a)
 {
     __shared__ int32_t s_red[BLOCK / 64];
     __shared__ int32_t s_q[BLOCK];
-    if (a.ctl->kind != KIND_LP) return;
+    if (!any_kind(a, KIND_LP)) return;
+    GV pv;
     int b = blockIdx.x;
     if (b < a.gS) {
         int32_t *q = s_q + (threadIdx.x >> 6) * 64;
-        wave_batched8(
-            a.bins + a.binoff[CLS_S], a.binoff[CLS_S + 1] - a.binoff[CLS_S], q, b * (BLOCK / 64) + (threadIdx.x >> 6),
-            a.gS * (BLOCK / 64),
+        wave_batched<8>(
+            a.bins + a.binoff[CLS_S],
+            walk(a, a.binoff[CLS_S + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6), a.gS * (BLOCK / 64),
+                 64),
+            q,
             [&](Meta &m) -> bool {
+                pv.at(a, graph_of(a, m.v));
+                if (pv.kind != KIND_LP) return false;
                 const int2 r = a.rec[m.v];
                 if ((r.x & 0xFFFF) == 0) return false;  // not in X
                 m.ps = r.x;
@@ -749,37 +1040,53 @@ __global__ __launch_bounds__(BLOCK) void k_afterburner(KArgs a)
                 const int ps = t.ps >> 16, pd = (t.ps & 0xFFFF) - 1;
                 int sum = after_sum_row(a, t.v, t.s, t.deg, ps, pd, t.aux, gl, 8);
                 sum = gsum<8>(sum);
-                if (gl == 0) {
-                    if (a.dbg_F2) a.dbg_F2[t.v] = sum;
-                    if (sum >= 0) a.dest[t.v] = pd;
-                }
+                if (gl == 0) after_store(a, t.v, pd, sum);
             });
         return;
     }
     b -= a.gS;
-    if (b < a.gM) { after_groups<64>(a, CLS_M, b * (BLOCK / 64) + (threadIdx.x >> 6), a.gM * (BLOCK / 64)); return; }
+    if (b < a.gM) {
+        const int gl = threadIdx.x & 63;
+        const int32_t *list = a.bins + a.binoff[CLS_M];
+        const Walk w = walk(a, a.binoff[CLS_M + 1] - a.binoff[CLS_M], b * (BLOCK / 64) + (threadIdx.x >> 6),
+                            a.gM * (BLOCK / 64), 1);
+        for (int i = w.first; i < w.end; i += w.step) {
+            const int v = list[i];
+            pv.at(a, graph_of(a, v));
+            if (pv.kind != KIND_LP) continue;
+            const int2 r = a.rec[v];
+            if ((r.x & 0xFFFF) == 0) continue;
+            const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
+            const int64_t s = a.xadj[v];
+            int sum = after_sum_row(a, v, s, (int)(a.xadj[v + 1] - s), ps, pd, r.y, gl, 64);
+            sum = gsum<64>(sum);
+            if (gl == 0) after_store(a, v, pd, sum);
+        }
+        return;
+    }
     b -= a.gM;
     if (b >= a.gL) return;
     const int32_t *list = a.bins + a.binoff[CLS_L];
-    const int cnt = a.binoff[CLS_L + 1] - a.binoff[CLS_L];
-    for (int i = b; i < cnt; i += a.gL) {
+    const Walk w = walk(a, a.binoff[CLS_L + 1] - a.binoff[CLS_L], b, a.gL, 1);
+    for (int i = w.first; i < w.end; i += w.step) {
         const int v = list[i];
+        pv.at(a, graph_of(a, v));
+        if (pv.kind != KIND_LP) continue;
         const int2 r = a.rec[v];
         if ((r.x & 0xFFFF) == 0) continue;
         const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
-        int sum = after_sum<BLOCK>(a, v, ps, pd, r.y, threadIdx.x, BLOCK);
+        const int64_t s = a.xadj[v];
+        int sum = after_sum_row(a, v, s, (int)(a.xadj[v + 1] - s), ps, pd, r.y, threadIdx.x, BLOCK);
         sum = block_sum<BLOCK>(sum, s_red);
-        if (threadIdx.x == 0) {
-            if (a.dbg_F2) a.dbg_F2[v] = sum;
-            if (sum >= 0) a.dest[v] = pd;
-        }
+        if (threadIdx.x == 0) after_store(a, v, pd, sum);
     }
 }
 
 // ------------------------------------------------- cut change of the moves --
 
 // Delta of the cut over the edges of moved vertices: an edge whose two ends
-// both move is counted from its smaller end. Also moved weight and digest.
+// both move is counted from its smaller end. Moved count, weight and digest
+// change are counted by the lane that finds the move.
 __device__ __forceinline__ int dcut_sum_row(const KArgs &a, int v, int64_t s, int deg, int ps, int pn, int gl,
                                             int stride)
 {
@@ -796,64 +1103,51 @@ __device__ __forceinline__ int dcut_sum_row(const KArgs &a, int v, int64_t s, in
     return delta;
 }
 
-__device__ __forceinline__ int dcut_sum(const KArgs &a, int v, int ps, int pn, int gl, int stride)
-{
-    const int64_t s = a.xadj[v];
-    return dcut_sum_row(a, v, s, (int)(a.xadj[v + 1] - s), ps, pn, gl, stride);
-}
+typedef GAcc<ST_M, ST_MW, ST_DIG> MoveAcc;
+typedef GAcc<ST_DCUT> CutAcc;
 
-__device__ __forceinline__ void move_meta(const KArgs &a, int v, int ps, int pn, int64_t &mw, uint64_t &dg)
+__device__ __forceinline__ void move_meta(const KArgs &a, int v, int lv, int ps, int pn, MoveAcc &acc)
 {
-    mw += a.vw ? a.vw[v] : 1;
-    dg += mix64(((uint64_t)(uint32_t)v << 32) | (uint32_t)pn) - mix64(((uint64_t)(uint32_t)v << 32) | (uint32_t)ps);
-}
-
-template <int G>
-__device__ void dcut_groups(const KArgs &a, int cls, int gid, int ngroups, int64_t &dc, int64_t &mw, uint64_t &dg,
-                            int64_t &nm)
-{
-    const int gl = threadIdx.x & (G - 1);
-    const int32_t *list = a.bins + a.binoff[cls];
-    const int cnt = a.binoff[cls + 1] - a.binoff[cls];
-    for (int i = gid; i < cnt; i += ngroups) {
-        const int v = list[i];
-        const int pn = a.dest[v];
-        if (pn < 0) continue;
-        const int ps = a.P[v];
-        int d = dcut_sum(a, v, ps, pn, gl, G);
-        d = gsum<G>(d);
-        if (gl == 0) {
-            dc += d;
-            nm++;
-            move_meta(a, v, ps, pn, mw, dg);
-        }
-    }
+    acc.c0++;
+    acc.c1 += a.vw ? a.vw[v] : 1;
+    acc.c2 += mix64(((uint64_t)(uint32_t)lv << 32) | (uint32_t)pn) - mix64(((uint64_t)(uint32_t)lv << 32) | (uint32_t)ps);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
 {
-    __shared__ int64_t s_red[BLOCK / 64];
-    __shared__ uint64_t s_redu[BLOCK / 64];
     __shared__ int32_t s_red32[BLOCK / 64];
     __shared__ int32_t s_q[BLOCK];
-    if (a.ctl->kind == KIND_DONE) return;
-    // the previous iteration improved the best partition: copy P_iter before
-    // this iteration's moves are applied
-    if (a.ctl->copy_best)
-        for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) a.best[v] = a.P[v];
-    int64_t dc = 0, mw = 0, nm = 0;
-    uint64_t dg = 0;
+    if (!any_active(a)) return;
+    GV pv;
+    if (count_row(a)[0] > 0) {
+        // graphs whose previous iteration improved the best partition: copy
+        // P_iter before this iteration's moves are applied
+        int lo, hi;
+        block_chunk(a.n, blockIdx.x, gridDim.x, lo, hi);
+        for (int v = lo + threadIdx.x; v < hi; v += BLOCK) {
+            pv.at(a, graph_of(a, v));
+            if (pv.copy && pv.kind != KIND_DONE) a.best[v] = a.P[v];
+        }
+    }
+    MoveAcc macc;
+    CutAcc cacc;
     int b = blockIdx.x;
     if (b < a.gS) {
         int32_t *q = s_q + (threadIdx.x >> 6) * 64;
-        wave_batched8(
-            a.bins + a.binoff[CLS_S], a.binoff[CLS_S + 1] - a.binoff[CLS_S], q, b * (BLOCK / 64) + (threadIdx.x >> 6),
-            a.gS * (BLOCK / 64),
+        wave_batched<8>(
+            a.bins + a.binoff[CLS_S],
+            walk(a, a.binoff[CLS_S + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6), a.gS * (BLOCK / 64),
+                 64),
+            q,
             [&](Meta &m) -> bool {
                 const int pn = a.dest[m.v];
                 if (pn < 0) return false;
                 m.aux = pn;
                 m.ps = a.P[m.v];
+                m.g = graph_of(a, m.v);
+                pv.at(a, m.g);
+                macc.to(a, m.g);
+                move_meta(a, m.v, m.v - pv.voff, m.ps, pn, macc);
                 m.s = a.xadj[m.v];
                 m.deg = (int)(a.xadj[m.v + 1] - m.s);
                 return true;
@@ -862,72 +1156,107 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
                 int d = dcut_sum_row(a, t.v, t.s, t.deg, t.ps, t.aux, gl, 8);
                 d = gsum<8>(d);
                 if (gl == 0) {
-                    dc += d;
-                    nm++;
-                    move_meta(a, t.v, t.ps, t.aux, mw, dg);
+                    cacc.to(a, t.g);
+                    cacc.c0 += (uint64_t)(int64_t)d;
                 }
             });
     } else if ((b -= a.gS) < a.gM) {
-        dcut_groups<64>(a, CLS_M, b * (BLOCK / 64) + (threadIdx.x >> 6), a.gM * (BLOCK / 64), dc, mw, dg, nm);
-    } else if ((b -= a.gM) < a.gL) {
-        const int32_t *list = a.bins + a.binoff[CLS_L];
-        const int cnt = a.binoff[CLS_L + 1] - a.binoff[CLS_L];
-        for (int i = b; i < cnt; i += a.gL) {
+        const int gl = threadIdx.x & 63;
+        const int32_t *list = a.bins + a.binoff[CLS_M];
+        const Walk w = walk(a, a.binoff[CLS_M + 1] - a.binoff[CLS_M], b * (BLOCK / 64) + (threadIdx.x >> 6),
+                            a.gM * (BLOCK / 64), 1);
+        for (int i = w.first; i < w.end; i += w.step) {
             const int v = list[i];
             const int pn = a.dest[v];
             if (pn < 0) continue;
             const int ps = a.P[v];
-            int d = dcut_sum(a, v, ps, pn, threadIdx.x, BLOCK);
+            const int g = graph_of(a, v);
+            const int64_t s = a.xadj[v];
+            int d = dcut_sum_row(a, v, s, (int)(a.xadj[v + 1] - s), ps, pn, gl, 64);
+            d = gsum<64>(d);
+            if (gl == 0) {
+                pv.at(a, g);
+                macc.to(a, g);
+                move_meta(a, v, v - pv.voff, ps, pn, macc);
+                cacc.to(a, g);
+                cacc.c0 += (uint64_t)(int64_t)d;
+            }
+        }
+    } else if ((b -= a.gM) < a.gL) {
+        const int32_t *list = a.bins + a.binoff[CLS_L];
+        const Walk w = walk(a, a.binoff[CLS_L + 1] - a.binoff[CLS_L], b, a.gL, 1);
+        for (int i = w.first; i < w.end; i += w.step) {
+            const int v = list[i];
+            const int pn = a.dest[v];
+            if (pn < 0) continue;
+            const int ps = a.P[v];
+            const int g = graph_of(a, v);
+            const int64_t s = a.xadj[v];
+            int d = dcut_sum_row(a, v, s, (int)(a.xadj[v + 1] - s), ps, pn, threadIdx.x, BLOCK);
             d = block_sum<BLOCK>(d, s_red32);
-            if (threadIdx.x == 0) { dc += d; nm++; move_meta(a, v, ps, pn, mw, dg); }
+            if (threadIdx.x == 0) {
+                pv.at(a, g);
+                macc.to(a, g);
+                move_meta(a, v, v - pv.voff, ps, pn, macc);
+                cacc.to(a, g);
+                cacc.c0 += (uint64_t)(int64_t)d;
+            }
         }
     } else if ((b -= a.gL) < a.gZ) {
         const int32_t *list = a.bins + a.binoff[CLS_Z];
         const int cnt = a.binoff[CLS_Z + 1] - a.binoff[CLS_Z];
-        for (int i = b * BLOCK + threadIdx.x; i < cnt; i += a.gZ * BLOCK) {
+        int lo, hi;
+        block_chunk(cnt, b, a.gZ, lo, hi);
+        for (int i = lo + threadIdx.x; i < hi; i += BLOCK) {
             const int v = list[i];
             const int pn = a.dest[v];
             if (pn < 0) continue;
-            nm++;
-            move_meta(a, v, a.P[v], pn, mw, dg);
+            const int g = graph_of(a, v);
+            pv.at(a, g);
+            macc.to(a, g);
+            move_meta(a, v, v - pv.voff, a.P[v], pn, macc);
         }
     }
-    dc = block_sum<BLOCK>(dc, s_red);
-    mw = block_sum<BLOCK>(mw, s_red);
-    nm = block_sum<BLOCK>(nm, s_red);
-    dg = block_sum<BLOCK>(dg, s_redu);
-    if (threadIdx.x == 0) {
-        shard_add(a, ST_DCUT, dc);
-        shard_add(a, ST_MW, mw);
-        shard_add(a, ST_M, nm);
-        shard_add(a, ST_DIG, (int64_t)dg);
-    }
+    acc_finish(a, macc);
+    acc_finish(a, cacc);
 }
 
 // ------------------------------------------------------------ apply moves --
 
 __global__ __launch_bounds__(BLOCK) void k_apply(KArgs a)
 {
-    extern __shared__ int32_t s_dw[];  // [k] block-partial weight change
-    const int kind = a.ctl->kind;
-    if (kind == KIND_DONE) return;
-    for (int p = threadIdx.x; p < a.k; p += BLOCK) s_dw[p] = 0;
-    __syncthreads();
-    const int lp_id = a.ctl->lp_id;
-    for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) {
+    extern __shared__ int32_t s_dw[];  // [k] block-partial weight change (one graph)
+    if (!any_active(a)) return;
+    const bool single = a.vg == nullptr;
+    if (single) {
+        for (int p = threadIdx.x; p < a.k; p += BLOCK) s_dw[p] = 0;
+        __syncthreads();
+    }
+    GV pv;
+    int lo, hi;
+    block_chunk(a.n, blockIdx.x, gridDim.x, lo, hi);
+    for (int v = lo + threadIdx.x; v < hi; v += BLOCK) {
         const int pn = a.dest[v];
         if (pn < 0) continue;
+        pv.at(a, graph_of(a, v));
         const int ps = a.P[v];
         const int vwv = a.vw ? a.vw[v] : 1;
         a.P[v] = pn;
         a.dest[v] = -1;
-        if (kind == KIND_LP) a.lock[v] = lp_id;
-        atomicSub(&s_dw[ps], vwv);
-        atomicAdd(&s_dw[pn], vwv);
+        if (pv.kind == KIND_LP) a.lock[v] = pv.lp_id;
+        if (single) {
+            atomicSub(&s_dw[ps], vwv);
+            atomicAdd(&s_dw[pn], vwv);
+        } else {
+            atomicAdd((unsigned long long *)&a.w[pv.poff + ps], (unsigned long long)(-(int64_t)vwv));
+            atomicAdd((unsigned long long *)&a.w[pv.poff + pn], (unsigned long long)(int64_t)vwv);
+        }
     }
-    __syncthreads();
-    for (int p = threadIdx.x; p < a.k; p += BLOCK)
-        if (s_dw[p]) atomicAdd((unsigned long long *)&a.w[p], (unsigned long long)(int64_t)s_dw[p]);
+    if (single) {
+        __syncthreads();
+        for (int p = threadIdx.x; p < a.k; p += BLOCK)
+            if (s_dw[p]) atomicAdd((unsigned long long *)&a.w[p], (unsigned long long)(int64_t)s_dw[p]);
+    }
 }
 
 // -------------------------------------------------------------- rebalance --
@@ -935,19 +1264,18 @@ __global__ __launch_bounds__(BLOCK) void k_apply(KArgs a)
 // Loss of an eligible vertex of an oversized part (Jetrw: own connectivity
 // minus that of the best connected valid destination, ties -> smaller id, or
 // a random valid destination when none is adjacent; Jetrs: own connectivity
-// minus the floor mean over adjacent valid destinations), its slot, and the
-// per-(part, slot) weight histogram.
-__device__ __forceinline__ void rb_finish(const KArgs &a, int v, int ps, int vwv, int kind, uint64_t best, int cs,
-                                          int sumB, int cntB, uint64_t hseed, int &ncand)
+// minus the floor mean over adjacent valid destinations) and its slot.
+__device__ __forceinline__ void rb_finish(const KArgs &a, int v, int ps, const GV &gv, uint64_t best, int cs, int sumB,
+                                          int cntB)
 {
     int loss, d = -1;
-    if (kind == KIND_RW) {
+    if (gv.kind == KIND_RW) {
         if (best) {
             d = (int)(~(uint32_t)best);
             loss = cs - (int)(best >> 32);
-        } else if (a.ctl->nB > 0) {
-            const uint64_t h = mix64(hseed ^ (uint64_t)(uint32_t)v);
-            d = a.Blist[__umul64hi(h, (uint64_t)a.ctl->nB)];
+        } else if (gv.nB > 0) {
+            const uint64_t h = mix64(gv.hs ^ (uint64_t)(uint32_t)(v - gv.voff));
+            d = a.Blist[gv.poff + (int)__umul64hi(h, (uint64_t)gv.nB)];
             loss = cs;
         } else {
             d = ps;  // unreachable: the lightest part is always a valid destination
@@ -959,41 +1287,54 @@ __device__ __forceinline__ void rb_finish(const KArgs &a, int v, int ps, int vwv
     }
     const int s = loss_slot(loss);
     a.slot[v] = (uint8_t)s;
-    ncand++;
-    if (a.dbg_loss) { a.dbg_loss[v] = loss; a.dbg_slot[v] = s; a.dbg_pd[v] = d; }
+    if (a.dbg_loss) {
+        a.dbg_loss[v] = loss;
+        a.dbg_slot[v] = s;
+        a.dbg_pd[v] = d;
+    }
 }
 
-__device__ __forceinline__ bool rb_eligible(const KArgs &a, int ps, int vwv)
+// Candidate test: the vertex's part is oversized and its weight is small
+// enough (2k * vw <= 3 (k * w(P_s) - W)). Writes the "no candidate" outputs.
+__device__ __forceinline__ bool rb_candidate(const KArgs &a, int v, int ps, int vwv, const GV &gv)
 {
-    const int64_t k = a.k;
-    return 2 * k * vwv <= 3 * (k * a.w[ps] - a.ctl->W);
+    const int gp = gv.poff + ps;
+    const int64_t k = gv.k;
+    if (a.isA[gp] && 2 * k * vwv <= 3 * (k * a.w[gp] - gv.W)) return true;
+    a.slot[v] = 255;
+    if (a.dbg_loss) {
+        a.dbg_loss[v] = INT64_MIN;
+        a.dbg_slot[v] = -1;
+        a.dbg_pd[v] = -1;
+    }
+    return false;
 }
 
 template <int G, int R>
-__device__ void rb_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ngroups, int kind, uint64_t hseed,
-                          int &ncand)
+__device__ void rb_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ngroups, GV &gv, CountX &racc)
 {
     const int gl = threadIdx.x & (G - 1);
     const int32_t *list = a.bins + a.binoff[cls];
-    const int cnt = a.binoff[cls + 1] - a.binoff[cls];
-    for (int i = gid; i < cnt; i += ngroups) {
+    const Walk w = walk(a, a.binoff[cls + 1] - a.binoff[cls], gid, ngroups, 1);
+    for (int i = w.first; i < w.end; i += w.step) {
         const int v = list[i];
+        const int g = graph_of(a, v);
+        gv.at(a, g);
+        if (!is_rb(gv.kind)) continue;
         const int ps = a.P[v];
         const int vwv = a.vw ? a.vw[v] : 1;
-        if (!a.isA[ps] || !rb_eligible(a, ps, vwv)) {
-            if (gl == 0) { a.slot[v] = 255; if (a.dbg_loss) { a.dbg_loss[v] = INT64_MIN; a.dbg_slot[v] = -1; a.dbg_pd[v] = -1; } }
-            continue;
-        }
+        if (!rb_candidate(a, v, ps, vwv, gv)) continue;  // same outcome and stores in every lane
+        const int64_t s = a.xadj[v];
         int pu[R], cu[R];
-        group_conn<G, R>(a, v, gl, tab, pu, cu);
+        group_conn_row<G, R>(a, s, (int)(a.xadj[v + 1] - s), gl, tab, pu, cu);
         uint64_t best = 0;
         int cs = 0, sumB = 0, cntB = 0;
 #pragma unroll
         for (int r = 0; r < R; r++) {
             if (cu[r] > 0) {
                 if (pu[r] == ps) cs += cu[r];
-                else if (a.isB[pu[r]]) {
-                    uint64_t k2 = conn_key(cu[r], pu[r]);
+                else if (a.isB[gv.poff + pu[r]]) {
+                    const uint64_t k2 = conn_key(cu[r], pu[r]);
                     best = k2 > best ? k2 : best;
                     sumB += cu[r];
                     cntB++;
@@ -1004,35 +1345,38 @@ __device__ void rb_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ng
         cs = gsum<G>(cs);
         sumB = gsum<G>(sumB);
         cntB = gsum<G>(cntB);
-        if (gl == 0) rb_finish(a, v, ps, vwv, kind, best, cs, sumB, cntB, hseed, ncand);
+        if (gl == 0) {
+            rb_finish(a, v, ps, gv, best, cs, sumB, cntB);
+            racc.to(a, g);
+            racc.c0++;
+        }
     }
 }
 
-__device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nblocks, int kind, uint64_t hseed,
-                          int &ncand)
+__device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nblocks, GV &gv, CountX &racc)
 {
     __shared__ uint64_t s_red[BLOCK / 64];
     __shared__ int32_t s_red32[BLOCK / 64];
     const int32_t *list = a.bins + a.binoff[cls];
-    const int cnt = a.binoff[cls + 1] - a.binoff[cls];
-    for (int i = bid; i < cnt; i += nblocks) {
+    const Walk w = walk(a, a.binoff[cls + 1] - a.binoff[cls], bid, nblocks, 1);
+    for (int i = w.first; i < w.end; i += w.step) {
         const int v = list[i];
+        const int g = graph_of(a, v);
+        gv.at(a, g);
+        if (!is_rb(gv.kind)) continue;
         const int ps = a.P[v];
         const int vwv = a.vw ? a.vw[v] : 1;
-        if (!a.isA[ps] || !rb_eligible(a, ps, vwv)) {
-            if (threadIdx.x == 0) { a.slot[v] = 255; if (a.dbg_loss) { a.dbg_loss[v] = INT64_MIN; a.dbg_slot[v] = -1; a.dbg_pd[v] = -1; } }
-            continue;
-        }
+        if (!rb_candidate(a, v, ps, vwv, gv)) continue;
         block_fill(a, v, tab);
         uint64_t best = 0;
         int cs = 0, sumB = 0, cntB = 0;
-        for (int p = threadIdx.x; p < a.k; p += BLOCK) {
+        for (int p = threadIdx.x; p < gv.k; p += BLOCK) {
             const int c = tab[p];
             if (c) {
                 tab[p] = 0;
                 if (p == ps) cs = c;
-                else if (a.isB[p]) {
-                    uint64_t k2 = conn_key(c, p);
+                else if (a.isB[gv.poff + p]) {
+                    const uint64_t k2 = conn_key(c, p);
                     best = k2 > best ? k2 : best;
                     sumB += c;
                     cntB++;
@@ -1043,20 +1387,22 @@ __device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nb
         cs = block_sum<BLOCK>(cs, s_red32);
         sumB = block_sum<BLOCK>(sumB, s_red32);
         cntB = block_sum<BLOCK>(cntB, s_red32);
-        if (threadIdx.x == 0) rb_finish(a, v, ps, vwv, kind, best, cs, sumB, cntB, hseed, ncand);
+        if (threadIdx.x == 0) {
+            rb_finish(a, v, ps, gv, best, cs, sumB, cntB);
+            racc.to(a, g);
+            racc.c0++;
+        }
     }
 }
 
 template <int ROLE, int GS = 8>
-__global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int boff)
+__global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
 {
     extern __shared__ int32_t lds[];
-    __shared__ int32_t s_red32[BLOCK / 64];
-    const int kind = a.ctl->kind;
-    if (kind != KIND_RW && kind != KIND_RS) return;
-    const uint64_t hseed = mix64(a.ctl->seed ^ (((uint64_t)(uint32_t)a.ctl->level << 32) + (uint64_t)(uint32_t)a.ctl->t));
+    if (!any_rb(a)) return;
     const int stride = a.k + 1;
-    int ncand = 0;
+    GV pv, rv;
+    CountX racc;
     if (ROLE == 1) {
         constexpr int RS_ = 32 / GS;
         const int ng = BLOCK / GS;
@@ -1068,20 +1414,20 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int boff)
         for (int c = 1; c < NCLS; c++) {
             if (a.tmap[c] != 1) continue;
             wave_batched<GS>(
-                a.bins + a.binoff[c], a.binoff[c + 1] - a.binoff[c], q, wid, nwaves,
+                a.bins + a.binoff[c], walk(a, a.binoff[c + 1] - a.binoff[c], wid, nwaves, 64), q,
                 [&](Meta &m) -> bool {
+                    m.g = graph_of(a, m.v);
+                    pv.at(a, m.g);
+                    if (!is_rb(pv.kind)) return false;
                     m.ps = a.P[m.v];
                     m.aux = a.vw ? a.vw[m.v] : 1;
-                    if (!a.isA[m.ps] || !rb_eligible(a, m.ps, m.aux)) {
-                        a.slot[m.v] = 255;
-                        if (a.dbg_loss) { a.dbg_loss[m.v] = INT64_MIN; a.dbg_slot[m.v] = -1; a.dbg_pd[m.v] = -1; }
-                        return false;
-                    }
+                    if (!rb_candidate(a, m.v, m.ps, m.aux, pv)) return false;
                     m.s = a.xadj[m.v];
                     m.deg = (int)(a.xadj[m.v + 1] - m.s);
                     return true;
                 },
                 [&](const Meta &t, int gl) {
+                    rv.at(a, t.g);
                     int pu[RS_], cu[RS_];
                     group_conn_row<GS, RS_>(a, t.s, t.deg, gl, tab, pu, cu);
                     uint64_t best = 0;
@@ -1090,8 +1436,8 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int boff)
                     for (int r = 0; r < RS_; r++) {
                         if (cu[r] > 0) {
                             if (pu[r] == t.ps) cs += cu[r];
-                            else if (a.isB[pu[r]]) {
-                                uint64_t k2 = conn_key(cu[r], pu[r]);
+                            else if (a.isB[rv.poff + pu[r]]) {
+                                const uint64_t k2 = conn_key(cu[r], pu[r]);
                                 best = k2 > best ? k2 : best;
                                 sumB += cu[r];
                                 cntB++;
@@ -1102,7 +1448,11 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int boff)
                     cs = gsum<GS>(cs);
                     sumB = gsum<GS>(sumB);
                     cntB = gsum<GS>(cntB);
-                    if (gl == 0) rb_finish(a, t.v, t.ps, t.aux, kind, best, cs, sumB, cntB, hseed, ncand);
+                    if (gl == 0) {
+                        rb_finish(a, t.v, t.ps, rv, best, cs, sumB, cntB);
+                        racc.to(a, t.g);
+                        racc.c0++;
+                    }
                 });
         }
     } else if (ROLE == 2) {
@@ -1111,50 +1461,54 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int boff)
         __syncthreads();
         int32_t *tab = lds + (threadIdx.x >> 6) * stride;
         for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 2)
-                rb_groups<64, 16>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 6), nblk * ng, kind, hseed, ncand);
+            if (a.tmap[c] == 2) rb_groups<64, 16>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 6), nblk * ng, pv, racc);
     } else if (ROLE == 3) {
         for (int i = threadIdx.x; i < a.k; i += BLOCK) lds[i] = 0;
         __syncthreads();
         for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 3) rb_blocks(a, c, lds, blockIdx.x, nblk, kind, hseed, ncand);
+            if (a.tmap[c] == 3) rb_blocks(a, c, lds, blockIdx.x, nblk, pv, racc);
     } else {
         // isolated vertices: no connectivity, loss 0, random destination (Jetrw)
         const int32_t *list = a.bins + a.binoff[CLS_Z];
         const int cnt = a.binoff[CLS_Z + 1] - a.binoff[CLS_Z];
-        for (int i = blockIdx.x * BLOCK + threadIdx.x; i < cnt; i += nblk * BLOCK) {
+        int lo, hi;
+        block_chunk(cnt, blockIdx.x, nblk, lo, hi);
+        for (int i = lo + threadIdx.x; i < hi; i += BLOCK) {
             const int v = list[i];
+            const int g = graph_of(a, v);
+            pv.at(a, g);
+            if (!is_rb(pv.kind)) continue;
             const int ps = a.P[v];
-            const int vwv = a.vw ? a.vw[v] : 1;
-            if (!a.isA[ps] || !rb_eligible(a, ps, vwv)) {
-                a.slot[v] = 255;
-                if (a.dbg_loss) { a.dbg_loss[v] = INT64_MIN; a.dbg_slot[v] = -1; a.dbg_pd[v] = -1; }
-                continue;
-            }
-            rb_finish(a, v, ps, vwv, kind, 0, 0, 0, 0, hseed, ncand);
+            if (!rb_candidate(a, v, ps, a.vw ? a.vw[v] : 1, pv)) continue;
+            rb_finish(a, v, ps, pv, 0, 0, 0, 0);
+            racc.to(a, g);
+            racc.c0++;
         }
     }
-    ncand = block_sum<BLOCK>(ncand, s_red32);
-    if (threadIdx.x == 0) shard_add(a, ST_X, ncand);
+    acc_finish(a, racc);
 }
 
-// Per-(part, slot) weight histogram of the eligible vertices. Each block
-// accumulates its grid-stride share in LDS when k * NSLOT int32 counters fit,
-// then adds its nonzero counters to the global histogram.
+// Per-(part, slot) weight histogram of the candidates. With one graph whose
+// k * NSLOT int32 counters fit, each block accumulates its range in LDS and
+// adds its nonzero counters once.
 __global__ __launch_bounds__(BLOCK) void k_rb_hist(KArgs a, int use_lds)
 {
     extern __shared__ int32_t h[];
-    const int kind = a.ctl->kind;
-    if (kind != KIND_RW && kind != KIND_RS) return;
+    if (!any_rb(a)) return;
     const int nh = a.k * NSLOT;
     if (use_lds) {
         for (int i = threadIdx.x; i < nh; i += BLOCK) h[i] = 0;
         __syncthreads();
     }
-    for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) {
+    GV pv;
+    int lo, hi;
+    block_chunk(a.n, blockIdx.x, gridDim.x, lo, hi);
+    for (int v = lo + threadIdx.x; v < hi; v += BLOCK) {
         const int sl = a.slot[v];
         if (sl == 255) continue;
-        const int idx = a.P[v] * NSLOT + sl;
+        pv.at(a, graph_of(a, v));
+        if (!is_rb(pv.kind)) continue;  // a slot left from an earlier iteration
+        const int idx = (pv.poff + a.P[v]) * NSLOT + sl;
         const int vwv = a.vw ? a.vw[v] : 1;
         if (use_lds) atomicAdd(&h[idx], vwv);
         else atomicAdd((unsigned long long *)&a.hist[idx], (unsigned long long)(int64_t)vwv);
@@ -1166,193 +1520,220 @@ __global__ __launch_bounds__(BLOCK) void k_rb_hist(KArgs a, int use_lds)
     }
 }
 
-// Per oversized part: cut-off slot s* (slots below it are evicted whole) and
-// the residual weight still needed inside s*; the compact list of parts whose
-// cut-off lies inside the histogram; Jetrs capacities over B.
+// Per graph (one block each): cut-off slot s* of every oversized part (slots
+// below it are evicted whole) and the residual weight still needed inside
+// s*; Jetrs capacities over B.
 __global__ __launch_bounds__(BLOCK) void k_rb_cutoff(KArgs a)
 {
-    __shared__ int32_t s_scan[BLOCK / 64];
     __shared__ int64_t s_scan64[BLOCK / 64];
-    Ctl *c = a.ctl;
+    const int g = blockIdx.x;
+    Ctl *c = a.ctl + g;
     const int kind = c->kind;
-    if (kind != KIND_RW && kind != KIND_RS) return;
+    if (!is_rb(kind)) return;
     const int64_t o = c->o;
-    int32_t carry = 0;
-    for (int base = 0; base < a.k; base += BLOCK) {
-        const int p = base + threadIdx.x;
-        int split = 0;
-        if (p < a.k) {
-            int ss = -1;
-            int64_t res = 0;
-            if (a.isA[p]) {
-                const int64_t need = a.w[p] - o;
-                int64_t cum = 0;
-                ss = NSLOT;
-                for (int s = 0; s < NSLOT; s++) {
-                    const int64_t h = a.hist[p * NSLOT + s];
-                    if (cum + h >= need) { ss = s; res = need - cum; break; }
-                    cum += h;
+    const int k = c->k, poff = c->poff;
+    for (int p = threadIdx.x; p < k; p += BLOCK) {
+        const int gp = poff + p;
+        int ss = -1;
+        int64_t res = 0;
+        if (a.isA[gp]) {
+            const int64_t need = a.w[gp] - o;
+            int64_t cum = 0;
+            ss = NSLOT;
+            for (int s = 0; s < NSLOT; s++) {
+                const int64_t hv = a.hist[(int64_t)gp * NSLOT + s];
+                if (cum + hv >= need) {
+                    ss = s;
+                    res = need - cum;
+                    break;
                 }
+                cum += hv;
             }
-            a.sstar[p] = ss;
-            a.resid[p] = res;
-            split = ss >= 0 && ss < NSLOT;
         }
-        int32_t tot;
-        const int32_t pos = block_excl_scan<BLOCK>((int32_t)split, s_scan, tot);
-        if (p < a.k) {
-            a.splitidx[p] = split ? carry + pos : -1;
-            if (split) a.splitpart[carry + pos] = p;
-        }
-        carry += tot;
+        a.sstar[gp] = ss;
+        a.resid[gp] = res;
     }
-    if (threadIdx.x == 0) c->nsplit = carry;
     if (kind == KIND_RS) {
         const int nB = c->nB;
         const int64_t sigma = c->sigma;
+        int64_t *cap = a.capstart + poff + g;
         int64_t acc = 0;
         for (int base = 0; base < nB; base += BLOCK) {
             const int i = base + threadIdx.x;
-            const int64_t cap = i < nB ? sigma - a.w[a.Blist[i]] : 0;
+            const int64_t cv = i < nB ? sigma - a.w[poff + a.Blist[poff + i]] : 0;
             int64_t tot;
-            const int64_t pos = block_excl_scan<BLOCK>(cap, s_scan64, tot);
-            if (i < nB) a.capstart[i] = acc + pos;
+            const int64_t pos = block_excl_scan<BLOCK>(cv, s_scan64, tot);
+            if (i < nB) cap[i] = acc + pos;
             acc += tot;
         }
-        if (threadIdx.x == 0) { a.capstart[nB] = acc; c->total_cap = acc; }
+        if (threadIdx.x == 0) {
+            cap[nB] = acc;
+            c->total_cap = acc;
+        }
     }
 }
 
-// Per tile of TILE vertices (one block) and split part j: weight of the
-// tile's eligible vertices that sit in the part's cut-off slot, stored as
-// tsum[j * ntile + tile].
+// Vertex range [v0, v1) of tile `tile` and its graph's controller.
+__device__ __forceinline__ const Ctl *tile_range(const KArgs &a, int tile, int &lt, int &v0, int &v1)
+{
+    const int g = a.tg ? a.tg[tile] : 0;
+    const Ctl *c = a.ctl + g;
+    lt = tile - c->t0;
+    v0 = c->voff + lt * TILE;
+    const int vend = c->voff + c->n;
+    v1 = v0 + TILE < vend ? v0 + TILE : vend;
+    return c;
+}
+
+// Per tile (one block) and part whose cut-off lies inside the histogram:
+// weight of the tile's candidates that sit in the part's cut-off slot,
+// stored at tsum[rowbase + part * ntiles + tile].
 __global__ __launch_bounds__(BLOCK) void k_rb_tilesum(KArgs a)
 {
     extern __shared__ int32_t acc[];
-    const int kind = a.ctl->kind;
-    if (kind != KIND_RW && kind != KIND_RS) return;
-    const int nsplit = a.ctl->nsplit;
-    if (nsplit == 0) return;
+    if (!any_rb(a)) return;
     for (int tile = blockIdx.x; tile < a.ntile; tile += gridDim.x) {
-        for (int j = threadIdx.x; j < nsplit; j += BLOCK) acc[j] = 0;
+        int lt, v0, v1;
+        const Ctl *c = tile_range(a, tile, lt, v0, v1);
+        if (!is_rb(c->kind)) continue;
+        const int k = c->k, poff = c->poff, ntl = c->ntiles;
+        for (int p = threadIdx.x; p < k; p += BLOCK) acc[p] = 0;
         __syncthreads();
-        const int v0 = tile * TILE;
-        for (int i = threadIdx.x; i < TILE; i += BLOCK) {
-            const int v = v0 + i;
-            if (v >= a.n) break;
+        for (int v = v0 + threadIdx.x; v < v1; v += BLOCK) {
             const int sl = a.slot[v];
             if (sl == 255) continue;
             const int p = a.P[v];
-            if (sl == a.sstar[p]) atomicAdd(&acc[a.splitidx[p]], a.vw ? a.vw[v] : 1);
+            if (sl == a.sstar[poff + p]) atomicAdd(&acc[p], a.vw ? a.vw[v] : 1);
         }
         __syncthreads();
-        for (int j = threadIdx.x; j < nsplit; j += BLOCK) a.tsum[(int64_t)j * a.ntile + tile] = acc[j];
+        int32_t *row = a.tsum + c->rowbase + lt;
+        for (int p = threadIdx.x; p < k; p += BLOCK) {
+            const int ss = a.sstar[poff + p];
+            if (ss >= 0 && ss < NSLOT) row[(int64_t)p * ntl] = acc[p];
+        }
         __syncthreads();
     }
 }
 
-// Per split part (one block): exclusive scan of its tile sums finds the one
-// tile in which the running cut-off-slot weight reaches the residual (every
-// cut-off-slot vertex of an earlier tile is evicted, none of a later one).
-// Inside that tile the vertices are taken in id order while the weight
-// before them is below the residual; the last evicted id is the threshold.
+// Per part whose cut-off lies inside the histogram (one block): an exclusive
+// scan of its tile sums finds the one tile in which the running cut-off-slot
+// weight reaches the residual (every cut-off-slot vertex of an earlier tile
+// is evicted, none of a later one). Inside that tile the vertices are taken
+// in id order while the weight before them is below the residual; the last
+// evicted id is the part's threshold.
 __global__ __launch_bounds__(BLOCK) void k_rb_split(KArgs a)
 {
     __shared__ int64_t s_scan[BLOCK / 64];
     __shared__ uint64_t s_red[BLOCK / 64];
     __shared__ int s_tile;
     __shared__ int64_t s_base;
-    constexpr int PER = TILE / BLOCK;
-    const int kind = a.ctl->kind;
-    if (kind != KIND_RW && kind != KIND_RS) return;
-    const int nsplit = a.ctl->nsplit;
-    for (int j = blockIdx.x; j < nsplit; j += gridDim.x) {
-        const int p = a.splitpart[j];
-        const int32_t *row = a.tsum + (int64_t)j * a.ntile;
-        const int64_t resid = a.resid[p];
+    if (!any_rb(a)) return;
+    for (int gp = blockIdx.x; gp < a.ktot; gp += gridDim.x) {
+        const int g = a.pg ? a.pg[gp] : 0;
+        const Ctl *c = a.ctl + g;
+        if (!is_rb(c->kind)) continue;
+        const int ss = a.sstar[gp];
+        if (ss < 0 || ss >= NSLOT) continue;
+        const int p = gp - c->poff, ntl = c->ntiles;
+        const int32_t *row = a.tsum + c->rowbase + (int64_t)p * ntl;
+        const int64_t resid = a.resid[gp];
+        if (threadIdx.x == 0) s_tile = -1;
+        __syncthreads();
         int64_t carry = 0;
-        for (int b0 = 0; b0 < a.ntile; b0 += BLOCK) {
+        for (int b0 = 0; b0 < ntl; b0 += BLOCK) {
             const int i = b0 + threadIdx.x;
-            const int64_t x = i < a.ntile ? row[i] : 0;
+            const int64_t x = i < ntl ? row[i] : 0;
             int64_t tot;
             const int64_t before = carry + block_excl_scan<BLOCK>(x, s_scan, tot);
-            if (x > 0 && before < resid && resid <= before + x) { s_tile = i; s_base = before; }
+            if (x > 0 && before < resid && resid <= before + x) {
+                s_tile = i;
+                s_base = before;
+            }
             carry += tot;
         }
         __syncthreads();
-        const int ss = a.sstar[p];
-        const int v0 = s_tile * TILE + threadIdx.x * PER;
-        int wv[PER];
-        int64_t mine = 0;
-#pragma unroll
-        for (int q = 0; q < PER; q++) {
-            const int v = v0 + q;
-            wv[q] = 0;
-            if (v < a.n && a.slot[v] == ss && a.P[v] == p) wv[q] = a.vw ? a.vw[v] : 1;
-            mine += wv[q];
-        }
-        int64_t tot;
-        int64_t before = s_base + block_excl_scan<BLOCK>(mine, s_scan, tot);
+        const int lt = s_tile;
         uint64_t last = 0;  // (last evicted id + 1), 0 = none
+        if (lt >= 0) {
+            const int vbeg = c->voff + lt * TILE, vend0 = c->voff + c->n;
+            const int vend = vbeg + TILE < vend0 ? vbeg + TILE : vend0;
+            const int v0 = vbeg + threadIdx.x * PER;
+            int wv[PER];
+            int64_t mine = 0;
 #pragma unroll
-        for (int q = 0; q < PER; q++) {
-            if (wv[q] > 0 && before < resid) last = (uint64_t)(v0 + q) + 1;
-            before += wv[q];
+            for (int q = 0; q < PER; q++) {
+                const int v = v0 + q;
+                wv[q] = 0;
+                if (v < vend && a.slot[v] == ss && a.P[v] == p) wv[q] = a.vw ? a.vw[v] : 1;
+                mine += wv[q];
+            }
+            int64_t tot;
+            int64_t before = s_base + block_excl_scan<BLOCK>(mine, s_scan, tot);
+#pragma unroll
+            for (int q = 0; q < PER; q++) {
+                if (wv[q] > 0 && before < resid) last = (uint64_t)(v0 + q) + 1;
+                before += wv[q];
+            }
         }
         last = block_max_u64<BLOCK>(last, s_red);
-        if (threadIdx.x == 0) a.vthr[p] = (int32_t)last - 1;
+        if (threadIdx.x == 0) a.vthr[gp] = (int32_t)last - 1;
         __syncthreads();
     }
 }
 
-// Eviction decision for every eligible vertex (one block per tile): evicted
-// when its slot is below the part's cut-off, or equal with an id no larger
-// than the part's threshold. Jetrw moves it to its chosen destination; Jetrs
-// marks it and sums the tile's evicted weight.
+// Eviction decision for every candidate (one block per tile): evicted when
+// its slot is below the part's cut-off, or equal with an id no larger than
+// the part's threshold. Jetrw moves it to its chosen destination; Jetrs marks
+// it and sums the tile's evicted weight.
 __global__ __launch_bounds__(BLOCK) void k_rb_mark(KArgs a)
 {
     __shared__ int64_t s_red[BLOCK / 64];
-    const int kind = a.ctl->kind;
-    if (kind != KIND_RW && kind != KIND_RS) return;
+    if (!any_rb(a)) return;
     for (int tile = blockIdx.x; tile < a.ntile; tile += gridDim.x) {
-        int64_t esum = 0;
-        const int v0 = tile * TILE;
-        for (int i = threadIdx.x; i < TILE; i += BLOCK) {
-            const int v = v0 + i;
-            if (v >= a.n) break;
+        int lt, v0, v1;
+        const Ctl *c = tile_range(a, tile, lt, v0, v1);
+        const int kind = c->kind;
+        if (!is_rb(kind)) continue;
+        const int poff = c->poff;
+        int64_t es = 0;
+        for (int v = v0 + threadIdx.x; v < v1; v += BLOCK) {
             const int sl = a.slot[v];
             bool ev = false;
             if (sl != 255) {
-                const int p = a.P[v];
-                const int ss = a.sstar[p];
-                ev = sl < ss || (sl == ss && v <= a.vthr[p]);
+                const int gp = poff + a.P[v];
+                const int ss = a.sstar[gp];
+                ev = sl < ss || (sl == ss && v <= a.vthr[gp]);
             }
             if (kind == KIND_RW) {
                 if (ev) a.dest[v] = a.rbd[v];
             } else {
                 a.rsev[v] = ev;
-                if (ev) esum += a.vw ? a.vw[v] : 1;
+                if (ev) es += a.vw ? a.vw[v] : 1;
             }
         }
         if (kind == KIND_RS) {
-            esum = block_sum<BLOCK>(esum, s_red);
-            if (threadIdx.x == 0) a.esum[tile] = esum;
+            es = block_sum<BLOCK>(es, s_red);
+            if (threadIdx.x == 0) a.esum[tile] = es;
         }
     }
 }
 
-// Jetrs: exclusive scan of the evicted weight over tiles.
+// Jetrs, per graph (one block each): exclusive scan of the evicted weight
+// over the graph's tiles.
 __global__ __launch_bounds__(BLOCK) void k_rs_scan(KArgs a)
 {
     __shared__ int64_t s_scan[BLOCK / 64];
-    if (a.ctl->kind != KIND_RS) return;
+    const Ctl *c = a.ctl + blockIdx.x;
+    if (c->kind != KIND_RS) return;
+    int64_t *e = a.esum + c->t0;
+    const int ntl = c->ntiles;
     int64_t carry = 0;
-    for (int base = 0; base < a.ntile; base += BLOCK) {
+    for (int base = 0; base < ntl; base += BLOCK) {
         const int i = base + threadIdx.x;
-        const int64_t x = i < a.ntile ? a.esum[i] : 0;
+        const int64_t x = i < ntl ? e[i] : 0;
         int64_t tot;
         const int64_t ex = block_excl_scan<BLOCK>(x, s_scan, tot);
-        if (i < a.ntile) a.esum[i] = carry + ex;
+        if (i < ntl) e[i] = carry + ex;
         carry += tot;
     }
 }
@@ -1365,18 +1746,22 @@ __global__ __launch_bounds__(BLOCK) void k_rs_scan(KArgs a)
 __global__ __launch_bounds__(BLOCK) void k_rs_assign(KArgs a)
 {
     __shared__ int64_t s_scan[BLOCK / 64];
-    constexpr int PER = TILE / BLOCK;
-    if (a.ctl->kind != KIND_RS) return;
-    const int nB = a.ctl->nB;
-    const int64_t total = a.ctl->total_cap;
+    if (!any_kind(a, KIND_RS)) return;
     for (int tile = blockIdx.x; tile < a.ntile; tile += gridDim.x) {
-        const int v0 = tile * TILE + threadIdx.x * PER;
+        int lt, v0, v1;
+        const Ctl *c = tile_range(a, tile, lt, v0, v1);
+        if (c->kind != KIND_RS) continue;
+        const int g = a.tg ? a.tg[tile] : 0;
+        const int nB = c->nB, poff = c->poff;
+        const int64_t total = c->total_cap;
+        const int64_t *cap = a.capstart + poff + g;
+        const int vb = v0 + threadIdx.x * PER;
         int wv[PER];
         int64_t mine = 0;
 #pragma unroll
         for (int q = 0; q < PER; q++) {
-            const int v = v0 + q;
-            wv[q] = (v < a.n && a.rsev[v]) ? (a.vw ? a.vw[v] : 1) : 0;
+            const int v = vb + q;
+            wv[q] = (v < v1 && a.rsev[v]) ? (a.vw ? a.vw[v] : 1) : 0;
             mine += wv[q];
         }
         int64_t tot;
@@ -1384,15 +1769,103 @@ __global__ __launch_bounds__(BLOCK) void k_rs_assign(KArgs a)
 #pragma unroll
         for (int q = 0; q < PER; q++) {
             if (wv[q] > 0 && pos < total) {
-                int lo = 0, hi = nB;  // largest i with capstart[i] <= pos (capstart[0] = 0 <= pos)
+                int lo = 0, hi = nB;  // largest i with cap[i] <= pos (cap[0] = 0 <= pos)
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
-                    if (a.capstart[mid] <= pos) lo = mid; else hi = mid;
+                    if (cap[mid] <= pos) lo = mid;
+                    else hi = mid;
                 }
-                a.dest[v0 + q] = a.Blist[lo];
+                a.dest[vb + q] = a.Blist[poff + lo];
             }
             pos += wv[q];
         }
+    }
+}
+
+// ------------------------------------------------------- batch union graph --
+
+// One graph of a batch as the union sees it.
+struct UDesc {
+    const int64_t *xadj;
+    const int32_t *adj, *vw, *ew;
+    int32_t *part;
+    int64_t eoff, nnz;
+    int32_t voff, n, ret_iter, pad;
+};
+
+// Graph whose range [off(g), off(g + 1)) holds x (binary search over G).
+template <class Off>
+__device__ __forceinline__ int find_graph(int G, int64_t x, Off off)
+{
+    int lo = 0, hi = G;  // off(lo) <= x < off(hi)
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off(mid) <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Union vertex arrays: row offsets shifted by the graph's first CSR entry,
+// vertex weights, graph ids and P_0 (also the start of P_best). Checks each
+// graph's first and last row offset. Blocks own contiguous ranges.
+__global__ __launch_bounds__(BLOCK) void k_union_vertices(const UDesc *d, int G, int N, int64_t NNZ, int64_t *xadj,
+                                                          int32_t *vw, int32_t *vg, int32_t *p0, int32_t *bad)
+{
+    int lo, hi;
+    block_chunk(N, blockIdx.x, gridDim.x, lo, hi);
+    if (lo >= hi) return;
+    int g = find_graph(G, lo + threadIdx.x, [&](int i) { return (int64_t)d[i].voff; });
+    for (int v = lo + threadIdx.x; v < hi; v += BLOCK) {
+        while (g + 1 < G && v >= d[g + 1].voff) g++;
+        const UDesc &u = d[g];
+        const int i = v - u.voff;
+        const int64_t x = u.xadj[i];
+        xadj[v] = x + u.eoff;
+        if (vw) vw[v] = u.vw ? u.vw[i] : 1;
+        vg[v] = g;
+        p0[v] = u.part[i];
+        if (i == 0 && (x != 0 || u.xadj[u.n] != u.nnz)) *bad = 1;
+        if (v == N - 1) xadj[N] = NNZ;
+    }
+}
+
+// Union edge arrays: neighbour ids shifted by the graph's first vertex (each
+// checked against the graph's own range) and edge weights.
+__global__ __launch_bounds__(BLOCK) void k_union_edges(const UDesc *d, int G, int64_t NNZ, int32_t *adj, int32_t *ew,
+                                                       int32_t *bad)
+{
+    const int64_t per = ((NNZ + gridDim.x - 1) / gridDim.x + BLOCK - 1) / BLOCK * BLOCK;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < NNZ ? lo + per : NNZ;
+    if (lo >= hi) return;
+    int g = find_graph(G, lo + threadIdx.x, [&](int i) { return d[i].eoff; });
+    int badl = 0;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += BLOCK) {
+        while (g + 1 < G && e >= d[g + 1].eoff) g++;
+        const UDesc &u = d[g];
+        const int64_t i = e - u.eoff;
+        const int x = u.adj[i];
+        if (x < 0 || x >= u.n) badl = 1;
+        adj[e] = x + u.voff;
+        if (ew) ew[e] = u.ew ? u.ew[i] : 1;
+    }
+    if (badl) *bad = 1;
+}
+
+// Result of each graph back into the caller's array: P_best, or P_iter for
+// graphs that asked for it.
+__global__ __launch_bounds__(BLOCK) void k_union_scatter(const UDesc *d, int G, int N, const int32_t *P,
+                                                         const int32_t *best)
+{
+    int lo, hi;
+    block_chunk(N, blockIdx.x, gridDim.x, lo, hi);
+    if (lo >= hi) return;
+    int g = find_graph(G, lo + threadIdx.x, [&](int i) { return (int64_t)d[i].voff; });
+    for (int v = lo + threadIdx.x; v < hi; v += BLOCK) {
+        while (g + 1 < G && v >= d[g + 1].voff) g++;
+        const UDesc &u = d[g];
+        u.part[v - u.voff] = u.ret_iter ? P[v] : best[v];
     }
 }
 
@@ -1411,7 +1884,11 @@ void *ws_get(jet_context *ctx, int slot, size_t bytes)
     if (bytes == 0) bytes = 16;
     Buffer &b = ctx->bufs[slot];
     if (b.bytes >= bytes) return b.ptr;
-    if (b.ptr) { (void)hipFree(b.ptr); b.ptr = nullptr; b.bytes = 0; }
+    if (b.ptr) {
+        (void)hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
     size_t want = bytes + bytes / 8;  // headroom for the next, slightly larger level
     if (hipMalloc(&b.ptr, want) != hipSuccess) {
         (void)hipGetLastError();
@@ -1420,6 +1897,21 @@ void *ws_get(jet_context *ctx, int slot, size_t bytes)
     }
     b.bytes = want;
     return b.ptr;
+}
+
+void *pinned_get(jet_context *ctx, size_t bytes)
+{
+    if (ctx->pinned && ctx->pinned_bytes >= bytes) return ctx->pinned;
+    void *p = nullptr;
+    const size_t want = std::max(bytes + bytes / 4, (size_t)4096);
+    if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    ctx->pinned = p;
+    ctx->pinned_bytes = want;
+    return p;
 }
 
 static int64_t balance_limit(int64_t W, int k, int lambda_ppm)
@@ -1443,23 +1935,22 @@ static int64_t deadzone_sigma(int64_t W, int k, int64_t o, int div)
 
 struct Plan {
     KArgs tab;    // LDS-table kernels (gain, loss)
-    KArgs plain;  // afterburner, cut delta
+    KArgs plain;  // afterburner, cut delta and the flat kernels
+    int G;
     int grid_tab, grid_plain, grid_rbtab;
     size_t lds_tab;
-    int grid_flat;
-    int grid_tile;
-    int grid_hist;
+    int grid_flat, grid_tile, grid_hist;
     bool hist_lds;
 };
 
 static int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
-static void plan_roles(const jet_context *ctx, KArgs &a, const int32_t *cnt, Plan &pl)
+static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cnt, Plan &pl)
 {
     const int maxb = ctx->num_cu * 8;
-    // LDS-table kernels: the 8-lane role keeps 32 tables of k ints, the wave
-    // role 4, the block role 1; larger k moves classes to roles with fewer
-    // tables so a block stays within 64 KiB of LDS.
+    // LDS-table kernels: the small-row role keeps 32 or 64 tables of k ints,
+    // the wave role 4, the block role 1; larger k moves classes to roles with
+    // fewer tables so a block stays within 64 KiB of LDS.
     KArgs t = a;
     t.tmap[0] = 0;
     const int k = a.k;
@@ -1477,7 +1968,7 @@ static void plan_roles(const jet_context *ctx, KArgs &a, const int32_t *cnt, Pla
     if (t.gM) lds = std::max(lds, (size_t)(BLOCK / 64) * k * 4);
     if (t.gL) lds = std::max(lds, (size_t)k * 4);
     pl.lds_tab = lds;
-    pl.grid_tab = t.gS + t.gM + t.gL;       // gain: no isolated role
+    pl.grid_tab = t.gS + t.gM + t.gL;
     pl.grid_rbtab = t.gS + t.gM + t.gL + t.gZ;
     // plain row kernels: roles follow the classes directly
     KArgs p = a;
@@ -1487,20 +1978,15 @@ static void plan_roles(const jet_context *ctx, KArgs &a, const int32_t *cnt, Pla
     p.gL = std::min(cnt[3], maxb);
     p.gZ = std::min(div_up(cnt[0], BLOCK), maxb);
     pl.grid_plain = p.gS + p.gM + p.gL + p.gZ;
-    for (KArgs *x : {&t, &p}) {
-        x->grid_tab = pl.grid_tab;
-        x->grid_rbtab = pl.grid_rbtab;
-        x->grid_plain = pl.grid_plain;
-    }
     pl.tab = t;
     pl.plain = p;
-    pl.hist_lds = (size_t)a.k * NSLOT * 4 <= 65536;
-    pl.grid_hist = std::max(1, std::min(a.ntile, ctx->num_cu * 2));
+    pl.hist_lds = a.vg == nullptr && (size_t)a.k * NSLOT * 4 <= 65536;
+    pl.grid_hist = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_flat = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_tile = std::max(1, std::min(a.ntile, ctx->num_cu * 8));
 }
 
-// Up to this k the 8-lane role runs with 4 lanes per vertex (64 tables of
+// Up to this k the small-row role runs with 4 lanes per vertex (64 tables of
 // k + 1 ints per block fit in 32 KiB): twice the vertices in flight per wave.
 constexpr int K_G4 = 120;
 
@@ -1509,11 +1995,11 @@ static void launch_gain(const Plan &pl, hipStream_t s)
     const KArgs &t = pl.tab;
     const size_t st = (size_t)(t.k + 1) * 4;
     if (t.gS) {
-        if (t.k <= K_G4) k_gain<1, 4><<<t.gS, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, t.gS, 0);
-        else k_gain<1, 8><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS, 0);
+        if (t.k <= K_G4) k_gain<1, 4><<<t.gS, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, t.gS);
+        else k_gain<1, 8><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS);
     }
-    if (t.gM) k_gain<2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM, t.gS);
-    if (t.gL) k_gain<3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL, t.gS + t.gM);
+    if (t.gM) k_gain<2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM);
+    if (t.gL) k_gain<3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL);
 }
 
 static void launch_rb_loss(const Plan &pl, hipStream_t s)
@@ -1521,12 +2007,12 @@ static void launch_rb_loss(const Plan &pl, hipStream_t s)
     const KArgs &t = pl.tab;
     const size_t st = (size_t)(t.k + 1) * 4;
     if (t.gS) {
-        if (t.k <= K_G4) k_rb_loss<1, 4><<<t.gS, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, t.gS, 0);
-        else k_rb_loss<1, 8><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS, 0);
+        if (t.k <= K_G4) k_rb_loss<1, 4><<<t.gS, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, t.gS);
+        else k_rb_loss<1, 8><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS);
     }
-    if (t.gM) k_rb_loss<2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM, t.gS);
-    if (t.gL) k_rb_loss<3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL, t.gS + t.gM);
-    if (t.gZ) k_rb_loss<4><<<t.gZ, BLOCK, 0, s>>>(t, t.gZ, t.gS + t.gM + t.gL);
+    if (t.gM) k_rb_loss<2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM);
+    if (t.gL) k_rb_loss<3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL);
+    if (t.gZ) k_rb_loss<4><<<t.gZ, BLOCK, 0, s>>>(t, t.gZ);
 }
 
 // Histogram, cut-off slots, ordered selection and (Jetrs) the cookie-cutter.
@@ -1534,31 +2020,32 @@ static void launch_rb_select(const Plan &pl, hipStream_t s)
 {
     const KArgs &p = pl.plain;
     k_rb_hist<<<pl.grid_hist, BLOCK, pl.hist_lds ? (size_t)p.k * NSLOT * 4 : 0, s>>>(p, pl.hist_lds);
-    k_rb_cutoff<<<1, BLOCK, 0, s>>>(p);
+    k_rb_cutoff<<<pl.G, BLOCK, 0, s>>>(p);
     k_rb_tilesum<<<pl.grid_tile, BLOCK, (size_t)p.k * 4, s>>>(p);
-    k_rb_split<<<std::min(p.k, 1024), BLOCK, 0, s>>>(p);
+    k_rb_split<<<std::min(p.ktot, 1024), BLOCK, 0, s>>>(p);
     k_rb_mark<<<pl.grid_tile, BLOCK, 0, s>>>(p);
-    k_rs_scan<<<1, BLOCK, 0, s>>>(p);
+    k_rs_scan<<<pl.G, BLOCK, 0, s>>>(p);
     k_rs_assign<<<pl.grid_tile, BLOCK, 0, s>>>(p);
 }
 
-static void launch_iteration(const Plan &pl, hipStream_t s, bool lp_kernels, bool rb_kernels,
-                             hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr)
+static void launch_iteration(const Plan &pl, hipStream_t s, hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr)
 {
     const KArgs &p = pl.plain;
-    if (lp_kernels) {
-        if (ev_a) (void)hipEventRecord(ev_a, s);
-        launch_gain(pl, s);
-        if (ev_b) (void)hipEventRecord(ev_b, s);
-        if (pl.grid_plain) k_afterburner<<<pl.grid_plain, BLOCK, 0, s>>>(p);
-    }
-    if (rb_kernels) {
-        launch_rb_loss(pl, s);
-        launch_rb_select(pl, s);
-    }
+    if (ev_a) (void)hipEventRecord(ev_a, s);
+    launch_gain(pl, s);
+    if (ev_b) (void)hipEventRecord(ev_b, s);
+    if (pl.grid_plain) k_afterburner<<<pl.grid_plain, BLOCK, 0, s>>>(p);
+    launch_rb_loss(pl, s);
+    launch_rb_select(pl, s);
     if (pl.grid_plain) k_dcut<<<pl.grid_plain, BLOCK, 0, s>>>(p);
-    k_apply<<<pl.grid_flat, BLOCK, (size_t)p.k * 4, s>>>(p);
-    k_ctl_end<<<1, CTL_NT, 0, s>>>(p);
+    k_apply<<<pl.grid_flat, BLOCK, p.vg ? 0 : (size_t)p.k * 4, s>>>(p);
+    k_ctl_end<<<pl.G, BLOCK, 0, s>>>(p);
+}
+
+static void set_it(Plan &pl, int it)
+{
+    pl.tab.it = it;
+    pl.plain.it = it;
 }
 
 static void set_lds_limits()
@@ -1608,7 +2095,6 @@ int validate_full_csr(jet_context *ctx, const jet_csr *g, hipStream_t s)
     if (nnz && g->adjwgt) JET_TRY(hipMemcpyAsync(ew.data(), g->adjwgt, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
     JET_TRY(hipStreamSynchronize(s));
     if (xadj[0] != 0 || xadj[n] != nnz) return JET_EGRAPH;
-    std::vector<uint64_t> key(nnz), rkey(nnz);
     std::vector<std::pair<uint64_t, int32_t>> kw(nnz), rkw(nnz);
     for (int v = 0; v < n; v++) {
         if (xadj[v + 1] < xadj[v]) return JET_EGRAPH;
@@ -1633,22 +2119,70 @@ struct DebugOut {
     int32_t *pd = nullptr, *slot = nullptr;
 };
 
-// Shared set-up of a refinement call: validates, fills the workspace and the
-// controller, and returns the launch plan.
-static int setup(jet_context *ctx, const jet_csr *g, const jet_params *prm, int32_t *part, Plan &pl,
-                 Ctl &hc, hipStream_t s, jet_trace_rec *trace_dev, int32_t trace_cap, const DebugOut *dbg)
+// Controller configuration of one graph from its parameters.
+static Ctl make_ctl(const jet_params *prm, int n)
 {
-    const int n = g->n, k = prm->k;
-    set_lds_limits();
-    if (prm->flags & JET_F_VALIDATE) {
-        int st = validate_full_csr(ctx, g, s);
-        if (st) return st;
+    Ctl hc;
+    memset(&hc, 0, sizeof(hc));
+    hc.n = n;
+    hc.k = prm->k;
+    hc.stall_limit = prm->stall_limit > 0 ? prm->stall_limit : 12;
+    hc.bmax = prm->weak_rebalance_iters == 0 ? 2 : (prm->weak_rebalance_iters < 0 ? 0 : prm->weak_rebalance_iters);
+    hc.max_iters = prm->max_iters;
+    if (prm->c_den > 0) {
+        hc.c_num = prm->c_num;
+        hc.c_den = prm->c_den;
+    } else {
+        hc.c_num = prm->level == 0 ? 1 : 3;
+        hc.c_den = 4;
     }
+    hc.phi_num = prm->phi_num > 0 ? prm->phi_num : 999;
+    hc.phi_den = prm->phi_den > 0 ? prm->phi_den : 1000;
+    hc.level = prm->level;
+    hc.seed = prm->seed;
+    hc.lambda_ppm = prm->lambda_ppm;
+    hc.deadzone_div = prm->deadzone_div > 0 ? prm->deadzone_div : 10;
+    hc.flags = (int32_t)prm->flags;
+    return hc;
+}
+
+// One refinement launch over G graphs laid out as a union (for G = 1 the
+// caller's own graph and arrays).
+struct Launch {
+    int G = 1;
+    jet_csr u;                                               // union CSR
+    const int32_t *vg = nullptr, *pg = nullptr, *tg = nullptr;  // device maps (NULL for one graph)
+    const int32_t *part_in = nullptr;                        // P_0
+    int32_t *best = nullptr;                                 // P_best (may be part_in)
+    std::vector<Ctl> hc;                                     // per graph: configuration in, final state out
+    int ktot = 0, kmax = 0, ntile = 0;
+    int64_t tsum_cap = 0;
+    jet_trace_rec *trace_dev = nullptr;
+};
+
+// Fills the workspace and the controllers, runs the set-up passes and
+// returns the launch plan. Per-graph offsets (voff, poff, t0, ntiles,
+// rowbase, trace_off, trace_cap) must already be in L.hc.
+static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const DebugOut *dbg)
+{
+    set_lds_limits();
+    const int G = L.G;
+    const int n = L.u.n;
     KArgs a;
     memset(&a, 0, sizeof(a));
-    a.n = n; a.k = k;
-    a.xadj = g->xadj; a.adj = g->adjncy; a.vw = g->vwgt; a.ew = g->adjwgt;
+    a.n = n;
+    a.k = L.kmax;
+    a.ngraph = G;
+    a.ktot = L.ktot;
+    a.xadj = L.u.xadj;
+    a.adj = L.u.adjncy;
+    a.vw = L.u.vwgt;
+    a.ew = L.u.adjwgt;
+    a.vg = L.vg;
+    a.pg = L.pg;
+    a.tg = L.tg;
     const size_t nn = (size_t)std::max(n, 1);
+    const size_t kt = (size_t)L.ktot;
     a.P = (int32_t *)ws_get(ctx, WS_P, nn * 4);
     a.rec = (int2 *)ws_get(ctx, WS_REC, nn * 8);
     a.dest = (int32_t *)ws_get(ctx, WS_DEST, nn * 4);
@@ -1658,129 +2192,101 @@ static int setup(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     a.rsev = (uint8_t *)ws_get(ctx, WS_RSEV, nn);
     int32_t *bins = (int32_t *)ws_get(ctx, WS_BIN, nn * 4);
     a.bins = bins;
-    a.bstat = (int64_t *)ws_get(ctx, WS_BSTAT, sizeof(int64_t) * NSTAT * NSHARD);
-    int32_t *fill = (int32_t *)ws_get(ctx, WS_FILL, sizeof(int32_t) * NCLS);
-    a.ctl = (Ctl *)ws_get(ctx, WS_CTL, sizeof(Ctl) + 64);
-    int64_t *p64 = (int64_t *)ws_get(ctx, WS_PART64, sizeof(int64_t) * (5 * (size_t)k + 8));
-    int32_t *p32 = (int32_t *)ws_get(ctx, WS_PART32, sizeof(int32_t) * (6 * (size_t)k + 8));
-    uint8_t *p8 = (uint8_t *)ws_get(ctx, WS_PART8, 2 * (size_t)k + 16);
-    a.hist = (int64_t *)ws_get(ctx, WS_HIST, sizeof(int64_t) * (size_t)k * NSLOT);
-    a.ntile = std::max(1, div_up(n, TILE));
-    a.tsum = (int32_t *)ws_get(ctx, WS_TSUM, sizeof(int32_t) * (size_t)a.ntile * k);
-    a.esum = (int64_t *)ws_get(ctx, WS_ESUM, sizeof(int64_t) * (size_t)a.ntile);
+    a.bstat = (int64_t *)ws_get(ctx, WS_BSTAT, sizeof(int64_t) * NSTAT * NSHARD * (size_t)G);
+    a.cnt = (int32_t *)ws_get(ctx, WS_CNT, sizeof(int32_t) * CNT_N);
+    a.ctl = (Ctl *)ws_get(ctx, WS_CTL, sizeof(Ctl) * (size_t)G);
+    int64_t *p64 = (int64_t *)ws_get(ctx, WS_PART64, sizeof(int64_t) * (4 * kt + G + 8));
+    int32_t *p32 = (int32_t *)ws_get(ctx, WS_PART32, sizeof(int32_t) * (3 * kt + 8));
+    uint8_t *p8 = (uint8_t *)ws_get(ctx, WS_PART8, 2 * kt + 16);
+    a.hist = (int64_t *)ws_get(ctx, WS_HIST, sizeof(int64_t) * kt * NSLOT);
+    a.ntile = L.ntile;
+    a.tsum = (int32_t *)ws_get(ctx, WS_TSUM, sizeof(int32_t) * (size_t)std::max<int64_t>(L.tsum_cap, 1));
+    a.esum = (int64_t *)ws_get(ctx, WS_ESUM, sizeof(int64_t) * (size_t)std::max(L.ntile, 1));
     a.kinds = (int8_t *)ws_get(ctx, WS_KINDS, KIND_LOG);
-    if (!a.P || !a.rec || !a.dest || !a.lock || !a.slot || !a.rbd || !a.rsev || !bins || !a.bstat || !fill ||
-        !a.ctl || !p64 || !p32 || !p8 || !a.hist || !a.tsum || !a.esum || !a.kinds)
-        return JET_ENOMEM;
-    a.w = p64; a.wbest = p64 + k; a.resid = p64 + 2 * k; a.xbase = p64 + 3 * k; a.capstart = p64 + 4 * k;
-    a.Blist = p32; a.sstar = p32 + k; a.splitidx = p32 + 2 * k; a.splitpart = p32 + 3 * k; a.xtile = p32 + 4 * k;
-    a.vthr = p32 + 5 * k;
-    a.isA = p8; a.isB = p8 + k;
-    a.best = part;
-    a.trace = trace_dev;
-    if (dbg) {
-        a.dbg_F = dbg->F; a.dbg_cs = dbg->cs; a.dbg_F2 = dbg->F2; a.dbg_loss = dbg->loss;
-        a.dbg_pd = dbg->pd; a.dbg_slot = dbg->slot;
-    }
-    // controller configuration; state starts at zero
-    memset(&hc, 0, sizeof(hc));
-    hc.n = n; hc.k = k;
-    hc.stall_limit = prm->stall_limit > 0 ? prm->stall_limit : 12;
-    hc.bmax = prm->weak_rebalance_iters == 0 ? 2 : (prm->weak_rebalance_iters < 0 ? 0 : prm->weak_rebalance_iters);
-    hc.max_iters = prm->max_iters;
-    if (prm->c_den > 0) { hc.c_num = prm->c_num; hc.c_den = prm->c_den; }
-    else { hc.c_num = prm->level == 0 ? 1 : 3; hc.c_den = 4; }
-    hc.phi_num = prm->phi_num > 0 ? prm->phi_num : 999;
-    hc.phi_den = prm->phi_den > 0 ? prm->phi_den : 1000;
-    hc.level = prm->level;
-    hc.trace_cap = trace_dev ? trace_cap : 0;
-    hc.seed = prm->seed;
-    Ctl *pin = (Ctl *)ctx->pinned;
-    *pin = hc;
-    JET_TRY(hipMemcpyAsync(a.ctl, pin, sizeof(Ctl), hipMemcpyHostToDevice, s));
-    JET_TRY(hipMemsetAsync(a.w, 0, sizeof(int64_t) * k, s));
     const int grid_v = std::max(1, std::min(div_up(n, BLOCK), ctx->num_cu * 4));
-    if (n > 0) k_init_vertices<<<grid_v, BLOCK, (size_t)k * 4, s>>>(a, part);
-    if (g->nnz > 0) {
-        const int grid_e = std::max(1, std::min(div_up(div_up(g->nnz, 16), BLOCK), ctx->num_cu * 8));
-        k_init_edges<<<grid_e, BLOCK, 0, s>>>(a, g->nnz);
+    int32_t *blkcnt = (int32_t *)ws_get(ctx, WS_BLKCNT, sizeof(int32_t) * ((size_t)grid_v + 1) * NCLS);
+    char *pin = (char *)pinned_get(ctx, 4096 + sizeof(Ctl) * (size_t)G);
+    if (!a.P || !a.rec || !a.dest || !a.lock || !a.slot || !a.rbd || !a.rsev || !bins || !a.bstat || !a.cnt ||
+        !a.ctl || !p64 || !p32 || !p8 || !a.hist || !a.tsum || !a.esum || !a.kinds || !blkcnt || !pin)
+        return JET_ENOMEM;
+    a.w = p64;
+    a.wbest = p64 + kt;
+    a.resid = p64 + 2 * kt;
+    a.capstart = p64 + 3 * kt;
+    a.Blist = p32;
+    a.sstar = p32 + kt;
+    a.vthr = p32 + 2 * kt;
+    a.isA = p8;
+    a.isB = p8 + kt;
+    a.best = L.best;
+    a.trace = L.trace_dev;
+    if (dbg) {
+        a.dbg_F = dbg->F;
+        a.dbg_cs = dbg->cs;
+        a.dbg_F2 = dbg->F2;
+        a.dbg_loss = dbg->loss;
+        a.dbg_pd = dbg->pd;
+        a.dbg_slot = dbg->slot;
     }
+    Ctl *hcs = (Ctl *)(pin + 4096);
+    memcpy(hcs, L.hc.data(), sizeof(Ctl) * G);
+    JET_TRY(hipMemcpyAsync(a.ctl, hcs, sizeof(Ctl) * G, hipMemcpyHostToDevice, s));
+    JET_TRY(hipMemsetAsync(a.w, 0, sizeof(int64_t) * kt, s));
+    JET_TRY(hipMemsetAsync(a.bstat, 0, sizeof(int64_t) * NSTAT * NSHARD * (size_t)G, s));
+    JET_TRY(hipMemsetAsync(a.cnt, 0, sizeof(int32_t) * CNT_N, s));
+    if (n > 0) k_init_vertices<<<grid_v, BLOCK, a.vg ? 0 : (size_t)a.k * 4, s>>>(a, L.part_in, blkcnt);
+    if (L.u.nnz > 0) {
+        const int grid_e = std::max(1, std::min(div_up(div_up(L.u.nnz, 16), BLOCK), ctx->num_cu * 8));
+        k_init_edges<<<grid_e, BLOCK, 0, s>>>(a, L.u.nnz);
+    }
+    k_bin_scan<<<1, BLOCK, 0, s>>>(blkcnt, grid_v);
+    k_init_reduce<<<G, 64, 0, s>>>(a);
     JET_TRY(hipGetLastError());
-    JET_TRY(hipMemcpyAsync(pin, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    int64_t *xends = (int64_t *)((char *)ctx->pinned + 2048);
-    JET_TRY(hipMemcpyAsync(xends, g->xadj, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    JET_TRY(hipMemcpyAsync(xends + 1, g->xadj + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    int32_t *hcnt = (int32_t *)pin;             // CNT_N counts
+    int32_t *htot = (int32_t *)(pin + 64);      // class totals
+    int64_t *xends = (int64_t *)(pin + 128);    // first and last row offset (one graph)
+    JET_TRY(hipMemcpyAsync(hcs, a.ctl, sizeof(Ctl) * G, hipMemcpyDeviceToHost, s));
+    JET_TRY(hipMemcpyAsync(hcnt, a.cnt, sizeof(int32_t) * CNT_N, hipMemcpyDeviceToHost, s));
+    JET_TRY(hipMemcpyAsync(htot, blkcnt + (size_t)grid_v * NCLS, sizeof(int32_t) * NCLS, hipMemcpyDeviceToHost, s));
+    JET_TRY(hipMemcpyAsync(xends, L.u.xadj, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    JET_TRY(hipMemcpyAsync(xends + 1, L.u.xadj + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     JET_TRY(hipStreamSynchronize(s));
-    hc = *pin;
-    if (xends[0] != 0 || xends[1] != g->nnz) return JET_EGRAPH;
-    if (hc.bad_graph) return JET_EGRAPH;
-    if (hc.bad_part) return JET_EPART;
-    if (hc.wsum >= ((int64_t)1 << 31) || hc.ewsum >= ((int64_t)1 << 31)) return JET_EOVERFLOW;
+    if (xends[0] != 0 || xends[1] != L.u.nnz || hcnt[1]) return JET_EGRAPH;
+    for (int g = 0; g < G; g++)
+        if (hcs[g].bad_part) return JET_EPART;
+    for (int g = 0; g < G; g++)
+        if (hcs[g].wsum >= ((int64_t)1 << 31) || hcs[g].ewsum >= ((int64_t)1 << 31)) return JET_EOVERFLOW;
+    for (int g = 0; g < G; g++) {
+        Ctl &c = hcs[g];
+        c.W = c.wsum;
+        c.o = balance_limit(c.W, c.k, c.lambda_ppm);
+        c.sigma = deadzone_sigma(c.W, c.k, c.o, c.deadzone_div);
+    }
+    JET_TRY(hipMemcpyAsync(a.ctl, hcs, sizeof(Ctl) * G, hipMemcpyHostToDevice, s));
     a.binoff[0] = 0;
-    for (int c = 0; c < NCLS; c++) a.binoff[c + 1] = a.binoff[c] + hc.bincnt[c];
-    JET_TRY(hipMemsetAsync(fill, 0, sizeof(int32_t) * NCLS, s));
-    if (n > 0) k_fill_bins<<<grid_v, BLOCK, 0, s>>>(a, bins, fill);
-    const int64_t W = hc.wsum;
-    const int64_t o = balance_limit(W, k, prm->lambda_ppm);
-    const int64_t sigma = deadzone_sigma(W, k, o, prm->deadzone_div > 0 ? prm->deadzone_div : 10);
-    k_ctl_setup<<<1, BLOCK, 0, s>>>(a, W, o, sigma);
+    int32_t tot[NCLS];
+    for (int c = 0; c < NCLS; c++) {
+        tot[c] = htot[c];
+        a.binoff[c + 1] = a.binoff[c] + tot[c];
+    }
+    if (n > 0) k_fill_bins<<<grid_v, BLOCK, 0, s>>>(a, blkcnt, bins);
+    a.it = 0;
+    k_ctl_setup<<<G, BLOCK, 0, s>>>(a);
     JET_TRY(hipGetLastError());
-    hc.W = W; hc.o = o; hc.sigma = sigma;
-    plan_roles(ctx, a, hc.bincnt, pl);
+    // the host copy must outlive the upload: wait before the staging is reused
+    JET_TRY(hipStreamSynchronize(s));
+    pl.G = G;
+    plan_roles(ctx, a, tot, pl);
     return JET_OK;
 }
 
-int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int32_t *part,
-                 int64_t *part_weights_out, jet_stats *stats, jet_trace_rec *trace_host, int32_t trace_cap,
-                 int32_t *trace_count, int32_t *trace_total, hipStream_t s)
+// Iterates until every graph is done: chunks of iterations, one sync each.
+static int run_loop(jet_context *ctx, Plan &pl, bool prof, hipStream_t s, int &launched)
 {
-    int st = check_params(g, prm);
-    if (st) return st;
-    const int n = g->n, k = prm->k;
-    if (trace_count) *trace_count = 0;
-    if (trace_total) *trace_total = 0;
-    JET_TRY(hipEventRecord(ctx->ev[0], s));
-    if (k == 1 || n == 0) {
-        // a single part: every vertex in part 0, nothing to refine
-        if (n > 0) JET_TRY(hipMemsetAsync(part, 0, sizeof(int32_t) * n, s));
-        int64_t W = n;
-        if (n > 0 && g->vwgt) {
-            std::vector<int32_t> vw(n);
-            JET_TRY(hipMemcpyAsync(vw.data(), g->vwgt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-            JET_TRY(hipStreamSynchronize(s));
-            W = 0;
-            for (int32_t x : vw) W += x;
-        }
-        if (part_weights_out) {
-            std::vector<int64_t> pw(k, 0);
-            pw[0] = W;
-            JET_TRY(hipMemcpyAsync(part_weights_out, pw.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, s));
-        }
-        JET_TRY(hipStreamSynchronize(s));
-        if (stats) {
-            memset(stats, 0, sizeof(*stats));
-            stats->max_part_weight = W;
-            stats->o = balance_limit(W, k, prm->lambda_ppm);
-            stats->sigma = stats->o;
-            stats->total_weight = W;
-            stats->balanced = W <= stats->o;
-            stats->levels = 1;
-        }
-        return JET_OK;
-    }
-    jet_trace_rec *trace_dev = nullptr;
-    if (trace_host && trace_cap > 0) {
-        trace_dev = (jet_trace_rec *)ws_get(ctx, WS_TRACE, sizeof(jet_trace_rec) * (size_t)trace_cap);
-        if (!trace_dev) return JET_ENOMEM;
-    }
-    Plan pl;
-    Ctl hc;
-    st = setup(ctx, g, prm, part, pl, hc, s, trace_dev, trace_cap, nullptr);
-    if (st) return st;
-    JET_TRY(hipEventRecord(ctx->ev[1], s));
-    Ctl *pin = (Ctl *)ctx->pinned;
-    const bool prof = prm->flags & JET_F_PROFILE;
-    int chunk = 4, launched = 0;
+    int32_t *pin = (int32_t *)pinned_get(ctx, 4096);
+    if (!pin) return JET_ENOMEM;
+    int chunk = 4;
+    launched = 0;
     for (;;) {
         for (int i = 0; i < chunk; i++) {
             hipEvent_t ea = nullptr, eb = nullptr;
@@ -1793,16 +2299,129 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
                 ea = ctx->prof_ev[2 * launched];
                 eb = ctx->prof_ev[2 * launched + 1];
             }
-            launch_iteration(pl, s, true, true, ea, eb);
+            set_it(pl, launched);
+            launch_iteration(pl, s, ea, eb);
             launched++;
         }
         JET_TRY(hipGetLastError());
-        JET_TRY(hipMemcpyAsync(pin, pl.plain.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        JET_TRY(hipMemcpyAsync(pin, pl.plain.cnt + CNT_DONE, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         JET_TRY(hipStreamSynchronize(s));
-        if (pin->done) break;
+        if (pin[0] >= pl.G) break;
         chunk = std::min(chunk * 2, 32);
     }
-    hc = *pin;
+    return JET_OK;
+}
+
+// Final controller states into L.hc (after the loop).
+static int read_state(jet_context *ctx, Launch &L, const Plan &pl, hipStream_t s)
+{
+    Ctl *hcs = (Ctl *)((char *)pinned_get(ctx, 4096 + sizeof(Ctl) * (size_t)L.G) + 4096);
+    JET_TRY(hipMemcpyAsync(hcs, pl.plain.ctl, sizeof(Ctl) * L.G, hipMemcpyDeviceToHost, s));
+    JET_TRY(hipStreamSynchronize(s));
+    memcpy(L.hc.data(), hcs, sizeof(Ctl) * L.G);
+    return JET_OK;
+}
+
+static void fill_stats(jet_stats *st, const Ctl &c, bool ret_iter)
+{
+    memset(st, 0, sizeof(*st));
+    st->cut = ret_iter ? c.cut : c.cut_best;
+    st->max_part_weight = ret_iter ? c.maxw : c.maxw_best;
+    st->o = c.o;
+    st->sigma = c.sigma;
+    st->total_weight = c.W;
+    st->balanced = st->max_part_weight <= c.o;
+    st->iters = c.t;
+    st->lp_iters = c.n_lp;
+    st->rw_iters = c.n_rw;
+    st->rs_iters = c.n_rs;
+    st->levels = 1;
+}
+
+// One graph with k = 1 or n = 0: every vertex in part 0, nothing to refine.
+static int refine_trivial(jet_context *ctx, const jet_csr *g, const jet_params *prm, int32_t *part,
+                          int64_t *part_weights_out, jet_stats *stats, hipStream_t s)
+{
+    const int n = g->n, k = prm->k;
+    if (n > 0) JET_TRY(hipMemsetAsync(part, 0, sizeof(int32_t) * n, s));
+    int64_t W = n;
+    if (n > 0 && g->vwgt) {
+        std::vector<int32_t> vw(n);
+        JET_TRY(hipMemcpyAsync(vw.data(), g->vwgt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+        JET_TRY(hipStreamSynchronize(s));
+        W = 0;
+        for (int32_t x : vw) W += x;
+    }
+    if (part_weights_out) {
+        std::vector<int64_t> pw(k, 0);
+        pw[0] = W;
+        JET_TRY(hipMemcpyAsync(part_weights_out, pw.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, s));
+    }
+    JET_TRY(hipStreamSynchronize(s));
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->max_part_weight = W;
+        stats->o = balance_limit(W, k, prm->lambda_ppm);
+        stats->sigma = stats->o;
+        stats->total_weight = W;
+        stats->balanced = W <= stats->o;
+        stats->levels = 1;
+    }
+    return JET_OK;
+}
+
+// Launch description of one graph refined on its own.
+static void single_launch(Launch &L, const jet_csr *g, const jet_params *prm, int32_t *part,
+                          jet_trace_rec *trace_dev, int32_t trace_cap)
+{
+    L.G = 1;
+    L.u = *g;
+    L.part_in = part;
+    L.best = part;
+    L.ktot = prm->k;
+    L.kmax = prm->k;
+    L.ntile = std::max(1, div_up(g->n, TILE));
+    L.tsum_cap = (int64_t)L.ntile * prm->k;
+    L.trace_dev = trace_dev;
+    L.hc.assign(1, make_ctl(prm, g->n));
+    Ctl &c = L.hc[0];
+    c.t0 = 0;
+    c.ntiles = L.ntile;
+    c.rowbase = 0;
+    c.trace_off = 0;
+    c.trace_cap = trace_dev ? trace_cap : 0;
+}
+
+int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int32_t *part,
+                 int64_t *part_weights_out, jet_stats *stats, jet_trace_rec *trace_host, int32_t trace_cap,
+                 int32_t *trace_count, int32_t *trace_total, hipStream_t s)
+{
+    int st = check_params(g, prm);
+    if (st) return st;
+    const int n = g->n, k = prm->k;
+    if (trace_count) *trace_count = 0;
+    if (trace_total) *trace_total = 0;
+    if (k == 1 || n == 0) return refine_trivial(ctx, g, prm, part, part_weights_out, stats, s);
+    if (prm->flags & JET_F_VALIDATE) {
+        st = validate_full_csr(ctx, g, s);
+        if (st) return st;
+    }
+    JET_TRY(hipEventRecord(ctx->ev[0], s));
+    jet_trace_rec *trace_dev = nullptr;
+    if (trace_host && trace_cap > 0) {
+        trace_dev = (jet_trace_rec *)ws_get(ctx, WS_TRACE, sizeof(jet_trace_rec) * (size_t)trace_cap);
+        if (!trace_dev) return JET_ENOMEM;
+    }
+    Launch L;
+    single_launch(L, g, prm, part, trace_dev, trace_cap);
+    Plan pl;
+    st = setup(ctx, L, pl, s, nullptr);
+    if (st) return st;
+    JET_TRY(hipEventRecord(ctx->ev[1], s));
+    const bool prof = prm->flags & JET_F_PROFILE;
+    int launched = 0;
+    st = run_loop(ctx, pl, prof, s, launched);
+    if (st) return st;
     k_copy_best<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain);
     JET_TRY(hipEventRecord(ctx->ev[2], s));
     if (prm->flags & JET_F_RETURN_ITER)
@@ -1810,6 +2429,9 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     if (part_weights_out)
         JET_TRY(hipMemcpyAsync(part_weights_out, (prm->flags & JET_F_RETURN_ITER) ? pl.plain.w : pl.plain.wbest,
                                sizeof(int64_t) * k, hipMemcpyDeviceToDevice, s));
+    st = read_state(ctx, L, pl, s);
+    if (st) return st;
+    const Ctl &hc = L.hc[0];
     const int ntr = std::min(hc.t, hc.trace_cap);
     if (trace_dev && ntr > 0)
         JET_TRY(hipMemcpyAsync(trace_host, trace_dev, sizeof(jet_trace_rec) * ntr, hipMemcpyDeviceToHost, s));
@@ -1826,6 +2448,7 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
             JET_TRY(hipMemcpyAsync(kinds.data(), pl.plain.kinds, nk, hipMemcpyDeviceToHost, s));
             JET_TRY(hipStreamSynchronize(s));
         }
+        // launch i ran iteration i (the kind log is written before t advances)
         for (int i = 0; i < nk; i++) {
             if (kinds[i] != KIND_LP) continue;
             float ms = 0.f;
@@ -1836,19 +2459,7 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
         }
     }
     if (stats) {
-        memset(stats, 0, sizeof(*stats));
-        const bool it = prm->flags & JET_F_RETURN_ITER;
-        stats->cut = it ? hc.cut : hc.cut_best;
-        stats->max_part_weight = it ? hc.maxw : hc.maxw_best;
-        stats->o = hc.o;
-        stats->sigma = hc.sigma;
-        stats->total_weight = hc.W;
-        stats->balanced = stats->max_part_weight <= hc.o;
-        stats->iters = hc.t;
-        stats->lp_iters = hc.n_lp;
-        stats->rw_iters = hc.n_rw;
-        stats->rs_iters = hc.n_rs;
-        stats->levels = 1;
+        fill_stats(stats, hc, prm->flags & JET_F_RETURN_ITER);
         float ms = 0;
         (void)hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]);
         stats->ms_total = ms;
@@ -1862,6 +2473,174 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
             stats->gain_entries = hc.prof_e;
             stats->gain_rows = hc.prof_r;
             stats->gain_vertices = hc.prof_v;
+        }
+    }
+    return JET_OK;
+}
+
+int refine_batch(jet_context *ctx, int count, const jet_csr *graphs, const jet_params *params, int32_t *const *parts,
+                 jet_stats *stats, jet_trace *traces, hipStream_t s)
+{
+    if (count < 0 || (count > 0 && (!graphs || !params || !parts))) return JET_EINVAL;
+    for (int i = 0; i < count; i++) {
+        const int st = check_params(&graphs[i], &params[i]);
+        if (st) return st;
+        if (graphs[i].n > 0 && !parts[i]) return JET_EINVAL;
+        if (traces && traces[i].cap > 0 && !traces[i].recs) return JET_EINVAL;
+    }
+    for (int i = 0; i < count; i++)
+        if (params[i].flags & JET_F_VALIDATE) {
+            const int st = validate_full_csr(ctx, &graphs[i], s);
+            if (st) return st;
+        }
+    // graphs with one part or no vertex need no refinement
+    std::vector<int> act;
+    for (int i = 0; i < count; i++) {
+        if (traces) {
+            traces[i].count = 0;
+            traces[i].total = 0;
+        }
+        if (params[i].k == 1 || graphs[i].n == 0) {
+            const int st = refine_trivial(ctx, &graphs[i], &params[i], parts[i], nullptr, stats ? &stats[i] : nullptr, s);
+            if (st) return st;
+        } else {
+            act.push_back(i);
+        }
+    }
+    const int G = (int)act.size();
+    if (G == 0) return JET_OK;
+    JET_TRY(hipEventRecord(ctx->ev[0], s));
+    // union layout
+    Launch L;
+    L.G = G;
+    L.hc.resize(G);
+    std::vector<UDesc> hd(G);
+    int64_t N = 0, NNZ = 0, tsum = 0, trace_total = 0;
+    int64_t ktot = 0, ntile = 0;
+    int kmax = 0;
+    bool any_vw = false, any_ew = false;
+    for (int j = 0; j < G; j++) {
+        const int i = act[j];
+        const jet_csr &g = graphs[i];
+        const jet_params &p = params[i];
+        Ctl c = make_ctl(&p, g.n);
+        c.voff = (int32_t)N;
+        c.poff = (int32_t)ktot;
+        c.t0 = (int32_t)ntile;
+        c.ntiles = div_up(g.n, TILE);
+        c.rowbase = tsum;
+        c.trace_off = (int32_t)trace_total;
+        c.trace_cap = traces ? std::max(traces[i].cap, 0) : 0;
+        L.hc[j] = c;
+        UDesc &d = hd[j];
+        d.xadj = g.xadj;
+        d.adj = g.adjncy;
+        d.vw = g.vwgt;
+        d.ew = g.adjwgt;
+        d.part = parts[i];
+        d.eoff = NNZ;
+        d.nnz = g.nnz;
+        d.voff = (int32_t)N;
+        d.n = g.n;
+        d.ret_iter = (p.flags & JET_F_RETURN_ITER) ? 1 : 0;
+        d.pad = 0;
+        N += g.n;
+        NNZ += g.nnz;
+        ktot += p.k;
+        ntile += c.ntiles;
+        tsum += (int64_t)c.ntiles * p.k;
+        trace_total += c.trace_cap;
+        kmax = std::max(kmax, p.k);
+        any_vw = any_vw || g.vwgt;
+        any_ew = any_ew || g.adjwgt;
+        if (N >= INT32_MAX || ktot >= INT32_MAX || ntile >= INT32_MAX || trace_total >= INT32_MAX) return JET_ELIMIT;
+    }
+    L.ktot = (int)ktot;
+    L.kmax = kmax;
+    L.ntile = (int)ntile;
+    L.tsum_cap = tsum;
+    std::vector<int32_t> maps(ntile + ktot);  // graph of each tile, then of each global part
+    for (int j = 0; j < G; j++) {
+        for (int t = 0; t < L.hc[j].ntiles; t++) maps[L.hc[j].t0 + t] = j;
+        for (int p = 0; p < L.hc[j].k; p++) maps[ntile + L.hc[j].poff + p] = j;
+    }
+    int64_t *uxadj = (int64_t *)ws_get(ctx, WS_U_XADJ, sizeof(int64_t) * (size_t)(N + 1));
+    int32_t *uadj = (int32_t *)ws_get(ctx, WS_U_ADJ, sizeof(int32_t) * (size_t)std::max<int64_t>(NNZ, 1));
+    int32_t *uvw = any_vw ? (int32_t *)ws_get(ctx, WS_U_VW, sizeof(int32_t) * (size_t)N) : nullptr;
+    int32_t *uew = any_ew ? (int32_t *)ws_get(ctx, WS_U_EW, sizeof(int32_t) * (size_t)std::max<int64_t>(NNZ, 1)) : nullptr;
+    int32_t *uvg = (int32_t *)ws_get(ctx, WS_U_VG, sizeof(int32_t) * (size_t)N);
+    int32_t *up0 = (int32_t *)ws_get(ctx, WS_U_P0, sizeof(int32_t) * (size_t)N);
+    int32_t *ubest = (int32_t *)ws_get(ctx, WS_U_BEST, sizeof(int32_t) * (size_t)N);
+    UDesc *udesc = (UDesc *)ws_get(ctx, WS_U_DESC, sizeof(UDesc) * (size_t)G + 64);
+    int32_t *umaps = (int32_t *)ws_get(ctx, WS_TG, sizeof(int32_t) * (size_t)(ntile + ktot));
+    jet_trace_rec *trace_dev = nullptr;
+    if (trace_total > 0) trace_dev = (jet_trace_rec *)ws_get(ctx, WS_TRACE, sizeof(jet_trace_rec) * (size_t)trace_total);
+    if (!uxadj || !uadj || (any_vw && !uvw) || (any_ew && !uew) || !uvg || !up0 || !ubest || !udesc || !umaps ||
+        (trace_total > 0 && !trace_dev))
+        return JET_ENOMEM;
+    int32_t *ubad = (int32_t *)((char *)udesc + sizeof(UDesc) * (size_t)G);
+    JET_TRY(hipMemcpyAsync(udesc, hd.data(), sizeof(UDesc) * G, hipMemcpyHostToDevice, s));
+    JET_TRY(hipMemcpyAsync(umaps, maps.data(), sizeof(int32_t) * maps.size(), hipMemcpyHostToDevice, s));
+    JET_TRY(hipMemsetAsync(ubad, 0, sizeof(int32_t), s));
+    const int grid_v = std::max(1, std::min(div_up(N, BLOCK), ctx->num_cu * 8));
+    const int grid_e = std::max(1, std::min(div_up(NNZ, BLOCK), ctx->num_cu * 16));
+    k_union_vertices<<<grid_v, BLOCK, 0, s>>>(udesc, G, (int)N, NNZ, uxadj, uvw, uvg, up0, ubad);
+    if (NNZ > 0) k_union_edges<<<grid_e, BLOCK, 0, s>>>(udesc, G, NNZ, uadj, uew, ubad);
+    JET_TRY(hipGetLastError());
+    int32_t *hbad = (int32_t *)pinned_get(ctx, 4096);
+    if (!hbad) return JET_ENOMEM;
+    JET_TRY(hipMemcpyAsync(hbad, ubad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    JET_TRY(hipStreamSynchronize(s));
+    if (hbad[0]) return JET_EGRAPH;
+    L.u.n = (int32_t)N;
+    L.u.nnz = NNZ;
+    L.u.xadj = uxadj;
+    L.u.adjncy = uadj;
+    L.u.vwgt = uvw;
+    L.u.adjwgt = uew;
+    L.vg = uvg;
+    L.tg = umaps;
+    L.pg = umaps + ntile;
+    L.part_in = up0;
+    L.best = ubest;
+    L.trace_dev = trace_dev;
+    Plan pl;
+    int st = setup(ctx, L, pl, s, nullptr);
+    if (st) return st;
+    JET_TRY(hipEventRecord(ctx->ev[1], s));
+    int launched = 0;
+    st = run_loop(ctx, pl, false, s, launched);
+    if (st) return st;
+    k_copy_best<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain);
+    JET_TRY(hipEventRecord(ctx->ev[2], s));
+    k_union_scatter<<<grid_v, BLOCK, 0, s>>>(udesc, G, (int)N, pl.plain.P, ubest);
+    JET_TRY(hipGetLastError());
+    st = read_state(ctx, L, pl, s);
+    if (st) return st;
+    if (traces)
+        for (int j = 0; j < G; j++) {
+            jet_trace &tr = traces[act[j]];
+            const Ctl &c = L.hc[j];
+            const int ntr = std::min(c.t, c.trace_cap);
+            if (ntr > 0)
+                JET_TRY(hipMemcpyAsync(tr.recs, trace_dev + c.trace_off, sizeof(jet_trace_rec) * ntr,
+                                       hipMemcpyDeviceToHost, s));
+            tr.count = ntr;
+            tr.total = c.t;
+        }
+    JET_TRY(hipEventRecord(ctx->ev[3], s));
+    JET_TRY(hipStreamSynchronize(s));
+    if (stats) {
+        float ms_total = 0, ms_refine = 0, ms_init = 0;
+        (void)hipEventElapsedTime(&ms_total, ctx->ev[0], ctx->ev[3]);
+        (void)hipEventElapsedTime(&ms_refine, ctx->ev[1], ctx->ev[2]);
+        (void)hipEventElapsedTime(&ms_init, ctx->ev[0], ctx->ev[1]);
+        for (int j = 0; j < G; j++) {
+            jet_stats &sj = stats[act[j]];
+            fill_stats(&sj, L.hc[j], params[act[j]].flags & JET_F_RETURN_ITER);
+            sj.ms_total = ms_total;
+            sj.ms_refine = ms_refine;
+            sj.ms_init = ms_init;
         }
     }
     return JET_OK;
@@ -1882,16 +2661,25 @@ extern "C" int jet_context_create(jet_context **out, int device)
     ctx->device = device;
     ctx->bufs.resize(WS_COUNT);
     hipError_t e = hipSetDevice(device);
-    if (e != hipSuccess) { int st = hip_status(ctx, e); delete ctx; return st; }
+    if (e != hipSuccess) {
+        int st = hip_status(ctx, e);
+        delete ctx;
+        return st;
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         ctx->num_cu = prop.multiProcessorCount;
-    ctx->pinned_bytes = 4096;
-    e = hipHostMalloc(&ctx->pinned, ctx->pinned_bytes, hipHostMallocDefault);
-    if (e != hipSuccess) { int st = hip_status(ctx, e); delete ctx; return st; }
+    if (!pinned_get(ctx, 4096)) {
+        delete ctx;
+        return JET_ENOMEM;
+    }
     for (auto &ev : ctx->ev) {
         e = hipEventCreate(&ev);
-        if (e != hipSuccess) { int st = hip_status(ctx, e); jet_context_destroy(ctx); return st; }
+        if (e != hipSuccess) {
+            int st = hip_status(ctx, e);
+            jet_context_destroy(ctx);
+            return st;
+        }
     }
     *out = ctx;
     return JET_OK;
@@ -1937,8 +2725,37 @@ extern "C" int jet_refine(jet_context *ctx, const jet_csr *g, const jet_params *
     int32_t cnt = 0, tot = 0;
     int st = refine_level(ctx, g, params, part, part_weights_out, stats, trace ? trace->recs : nullptr,
                           trace ? trace->cap : 0, &cnt, &tot, (hipStream_t)stream);
-    if (trace) { trace->count = cnt; trace->total = tot; }
+    if (trace) {
+        trace->count = cnt;
+        trace->total = tot;
+    }
     return st;
+}
+
+extern "C" int jet_refine_batch(jet_context *ctx, int32_t count, const jet_csr *graphs, const jet_params *params,
+                                int32_t *const *parts, jet_stats *stats, jet_trace *traces, void *stream)
+{
+    if (!ctx) return JET_EINVAL;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_status(ctx, e);
+    return refine_batch(ctx, count, graphs, params, parts, stats, traces, (hipStream_t)stream);
+}
+
+// Shared set-up of the single-step entry points: one graph, a private copy of
+// the partition, the step outputs wired in.
+static int step_setup(jet_context *ctx, const jet_csr *g, const jet_params *params, const int32_t *part,
+                      const DebugOut &dbg, Launch &L, Plan &pl, hipStream_t s)
+{
+    const int n = g->n;
+    int32_t *p0 = (int32_t *)ws_get(ctx, WS_H0, sizeof(int32_t) * n);
+    if (!p0) return JET_ENOMEM;
+    JET_TRY(hipMemcpyAsync(p0, part, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    if (params->flags & JET_F_VALIDATE) {
+        const int st = validate_full_csr(ctx, g, s);
+        if (st) return st;
+    }
+    single_launch(L, g, params, p0, nullptr, 0);
+    return setup(ctx, L, pl, s, &dbg);
 }
 
 extern "C" int jet_lp_step(jet_context *ctx, const jet_csr *g, const jet_params *params, const int32_t *part,
@@ -1954,16 +2771,16 @@ extern "C" int jet_lp_step(jet_context *ctx, const jet_csr *g, const jet_params 
     if (n == 0) return JET_OK;
     hipStream_t s = (hipStream_t)stream;
     JET_TRY(hipSetDevice(ctx->device));
-    // private copy of the partition: the step leaves `part` untouched
-    int32_t *p0 = (int32_t *)ws_get(ctx, WS_H0, sizeof(int32_t) * n);
-    if (!p0) return JET_ENOMEM;
-    JET_TRY(hipMemcpyAsync(p0, part, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
     DebugOut dbg;
-    dbg.F = F; dbg.cs = conn_s; dbg.F2 = F2; dbg.pd = pd;
+    dbg.F = F;
+    dbg.cs = conn_s;
+    dbg.F2 = F2;
+    dbg.pd = pd;
+    Launch L;
     Plan pl;
-    Ctl hc;
-    st = setup(ctx, g, params, p0, pl, hc, s, nullptr, 0, &dbg);
+    st = step_setup(ctx, g, params, part, dbg, L, pl, s);
     if (st) return st;
+    set_it(pl, 0);
     k_step_defaults<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, part);
     k_force_step<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, KIND_LP, 0, locked);
     launch_gain(pl, s);
@@ -1988,16 +2805,17 @@ extern "C" int jet_rebalance_step(jet_context *ctx, const jet_csr *g, const jet_
     if (n == 0) return JET_OK;
     hipStream_t s = (hipStream_t)stream;
     JET_TRY(hipSetDevice(ctx->device));
-    int32_t *p0 = (int32_t *)ws_get(ctx, WS_H0, sizeof(int32_t) * n);
     int32_t *pdv = (int32_t *)ws_get(ctx, WS_DBG_LOCK, sizeof(int32_t) * n);
-    if (!p0 || !pdv) return JET_ENOMEM;
-    JET_TRY(hipMemcpyAsync(p0, part, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    if (!pdv) return JET_ENOMEM;
     DebugOut dbg;
-    dbg.loss = loss; dbg.slot = slot; dbg.pd = pdv;
+    dbg.loss = loss;
+    dbg.slot = slot;
+    dbg.pd = pdv;
+    Launch L;
     Plan pl;
-    Ctl hc;
-    st = setup(ctx, g, params, p0, pl, hc, s, nullptr, 0, &dbg);
+    st = step_setup(ctx, g, params, part, dbg, L, pl, s);
     if (st) return st;
+    set_it(pl, 0);
     const KArgs &p = pl.plain;
     k_step_defaults<<<pl.grid_flat, BLOCK, 0, s>>>(p, part);
     k_force_step<<<1, BLOCK, 0, s>>>(p, kind, t, nullptr);

@@ -5,8 +5,9 @@ torch CUDA tensors into the C ABI's device pointers and structs and passes
 torch's current HIP stream. It raises if libjet.so is missing or if a
 tensor is not on the GPU; there is no fallback path.
 
-Names follow the C ABI (include/jet.h): ``refine``, ``lp_step``,
-``rebalance_step``, ``coarsen``, ``partition``.
+Names follow the C ABI (include/jet.h): ``refine``, ``refine_batch``,
+``lp_step``, ``rebalance_step``, ``coarsen``, ``partition`` and ``Server``
+(``jet_server_*``).
 """
 from __future__ import annotations
 
@@ -30,8 +31,10 @@ KIND_LP, KIND_RW, KIND_RS = 1, 2, 3
 # Every function declared in include/jet.h.
 EXPORTS = [
     "jet_context_create", "jet_context_destroy", "jet_strerror", "jet_last_hip_error",
-    "jet_refine", "jet_lp_step", "jet_rebalance_step", "jet_coarsen", "jet_hierarchy_levels",
-    "jet_hierarchy_level", "jet_hierarchy_free", "jet_partition",
+    "jet_refine", "jet_refine_batch", "jet_lp_step", "jet_rebalance_step", "jet_coarsen",
+    "jet_hierarchy_levels", "jet_hierarchy_level", "jet_hierarchy_free", "jet_partition",
+    "jet_server_create", "jet_server_submit", "jet_server_poll", "jet_server_wait",
+    "jet_server_info_get", "jet_server_destroy",
 ]
 
 
@@ -80,6 +83,29 @@ class Trace(C.Structure):
                 ("total", C.c_int32), ("reserved", C.c_int32)]
 
 
+class Job(C.Structure):
+    _fields_ = [("graph", Csr), ("params", Params), ("part_out", C.c_void_p)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("levels", C.c_int32), ("iters", C.c_int32),
+                ("balanced", C.c_int32), ("cut", C.c_int64), ("max_part_weight", C.c_int64),
+                ("t_submit_ms", C.c_double), ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double),
+                ("steps", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("steps", C.c_int64),
+                ("step_jobs", C.c_int64), ("active", C.c_int32), ("queued", C.c_int32),
+                ("hbm_in_use", C.c_int64), ("busy_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 TRACE_FIELDS = [f for f, _ in TraceRec._fields_]
 
 _lib = None
@@ -106,6 +132,12 @@ def lib():
         L.jet_hierarchy_free.argtypes = [C.c_void_p]
         L.jet_context_destroy.argtypes = [C.c_void_p]
         L.jet_last_hip_error.argtypes = [C.c_void_p]
+        L.jet_server_create.argtypes = [C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t, C.c_int32]
+        L.jet_server_submit.argtypes = [C.c_void_p, C.POINTER(Job), C.POINTER(C.c_uint64)]
+        L.jet_server_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(Result)]
+        L.jet_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(Result)]
+        L.jet_server_info_get.argtypes = [C.c_void_p, C.POINTER(ServerInfo)]
+        L.jet_server_destroy.argtypes = [C.c_void_p]
         _lib = L
     return _lib
 
@@ -227,6 +259,39 @@ def refine(g: DeviceGraph, part: torch.Tensor, k: int, trace_cap=0, ctx=None, pa
     return out, _trace_list(arr, tr), pw
 
 
+def refine_batch(graphs, parts, params, trace_cap=0, ctx=None):
+    """jet_refine_batch: refines ``parts[i]`` of ``graphs[i]`` in place, all in
+    one launch sequence. ``params`` is a list of keyword dicts for
+    ``make_params`` (``k`` included). Returns (list of stats dicts, list of
+    traces or None)."""
+    ctx = ctx or default_context()
+    m = len(graphs)
+    if len(parts) != m or len(params) != m:
+        raise ValueError("graphs, parts and params must have the same length")
+    csrs = (Csr * max(m, 1))(*[g.csr() for g in graphs])
+    prms = (Params * max(m, 1))(*[make_params(**p) for p in params])
+    ptrs = (C.c_void_p * max(m, 1))(*[_ptr(p) for p in parts])
+    stats = (Stats * max(m, 1))()
+    bufs, trs = [], None
+    if trace_cap > 0:
+        trs = (Trace * max(m, 1))()
+        for i in range(m):
+            arr, tr = _trace_buf(trace_cap)
+            bufs.append(arr)
+            trs[i] = tr
+    s = lib().jet_refine_batch(ctx.h, C.c_int32(m), csrs, prms, ptrs, stats,
+                               trs if trs is not None else None, _stream())
+    _check(s, "jet_refine_batch")
+    out = [stats[i].as_dict() for i in range(m)]
+    traces = None
+    if trs is not None:
+        traces = []
+        for i in range(m):
+            out[i]["trace_total"] = trs[i].total
+            traces.append(_trace_list(bufs[i], trs[i]))
+    return out, traces
+
+
 def lp_step(g: DeviceGraph, part: torch.Tensor, locked: torch.Tensor, k: int, ctx=None, **kw):
     """jet_lp_step: one Jetlp step. Returns dict of device tensors."""
     ctx = ctx or default_context()
@@ -333,3 +398,60 @@ def coarsen(g: DeviceGraph, k: int, ctx=None, **kw) -> Hierarchy:
     csr = g.csr()
     _check(lib().jet_coarsen(ctx.h, C.byref(csr), C.byref(prm), C.byref(h), _stream()), "jet_coarsen")
     return Hierarchy(h)
+
+
+class Server:
+    """jet_server_*: continuous-batching partition server on its own context.
+
+    Graphs and output tensors passed to ``submit`` must stay alive (and the
+    graph unchanged) until the job is done; ``submit`` keeps references to
+    them until its result is taken."""
+
+    def __init__(self, hbm_budget_bytes=0, max_slots=64, device=None):
+        self.ctx = Context(device)
+        self.h = C.c_void_p()
+        _check(lib().jet_server_create(C.byref(self.h), self.ctx.h, C.c_size_t(hbm_budget_bytes),
+                                       C.c_int32(max_slots)), "jet_server_create")
+        self._keep = {}
+
+    def submit(self, g: DeviceGraph, part_out: torch.Tensor, k: int, **kw) -> int:
+        job = Job(g.csr(), make_params(k, **kw), _ptr(part_out))
+        t = C.c_uint64()
+        _check(lib().jet_server_submit(self.h, C.byref(job), C.byref(t)), "jet_server_submit")
+        self._keep[t.value] = (g, part_out)
+        return t.value
+
+    def _take(self, st, ticket, r):
+        if st == JET_EAGAIN:
+            return None
+        _check(st, "jet_server result")
+        self._keep.pop(ticket, None)
+        return r.as_dict()
+
+    def poll(self, ticket: int):
+        """Result dict once the job is done, else None."""
+        r = Result()
+        return self._take(lib().jet_server_poll(self.h, C.c_uint64(ticket), C.byref(r)), ticket, r)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        r = Result()
+        return self._take(lib().jet_server_wait(self.h, C.c_uint64(ticket), C.c_int32(timeout_ms), C.byref(r)),
+                          ticket, r)
+
+    def info(self):
+        i = ServerInfo()
+        _check(lib().jet_server_info_get(self.h, C.byref(i)), "jet_server_info_get")
+        return i.as_dict()
+
+    def close(self):
+        if self.h:
+            lib().jet_server_destroy(self.h)
+            self.h = C.c_void_p()
+            self._keep.clear()
+        self.ctx.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
