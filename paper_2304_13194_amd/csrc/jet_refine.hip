@@ -46,6 +46,15 @@ namespace jet {
 
 __device__ __forceinline__ int graph_of(const KArgs &a, int v) { return a.vg ? a.vg[v] : 0; }
 
+// Kernels on the hot path are built twice: B = false for one graph (graph 0
+// everywhere, its fields loaded once per lane at kernel start), B = true for
+// a batch (graph looked up per vertex).
+template <bool B>
+__device__ __forceinline__ int gof(const KArgs &a, int v)
+{
+    return B ? a.vg[v] : 0;
+}
+
 // Count row of the current iteration: [improved-and-going-on, Jetlp, Jetrw, Jetrs].
 __device__ __forceinline__ const int32_t *count_row(const KArgs &a) { return a.cnt + CNT_ROW + (a.it & 1) * 4; }
 __device__ __forceinline__ bool any_kind(const KArgs &a, int kind) { return count_row(a)[kind] > 0; }
@@ -87,6 +96,11 @@ struct GV {
         W = c->W;
         hs = mix64(c->seed ^ (((uint64_t)(uint32_t)c->level << 32) + (uint64_t)(uint32_t)c->t));
     }
+    template <bool B>
+    __device__ __forceinline__ void sel(const KArgs &a, int gg)
+    {
+        if (B) at(a, gg);
+    }
 };
 
 // Counters are summed modulo 2^64 (signed values and the digest alike).
@@ -121,6 +135,11 @@ struct GAcc {
             flush(a);
             g = gg;
         }
+    }
+    template <bool B>
+    __device__ __forceinline__ void sel(const KArgs &a, int gg)
+    {
+        if (B) to(a, gg);
     }
 };
 
@@ -164,10 +183,11 @@ __device__ void acc_finish(const KArgs &a, Acc &acc)
 struct Walk {
     int first, end, step;
 };
-__device__ __forceinline__ Walk walk(const KArgs &a, int cnt, int worker, int nworkers, int unit)
+template <bool B>
+__device__ __forceinline__ Walk walk(int cnt, int worker, int nworkers, int unit)
 {
     Walk w;
-    if (!a.vg) {
+    if (!B) {
         w.first = worker * unit;
         w.end = cnt;
         w.step = nworkers * unit;
@@ -802,21 +822,21 @@ __device__ __forceinline__ void gain_locked(const KArgs &a, int v, int ps)
 typedef GAcc<ST_V, ST_R, ST_E> GainPre;  // visited vertices, unlocked rows, their CSR entries
 typedef GAcc<ST_X> CountX;
 
-template <int G, int R>
+template <bool B, int G, int R>
 __device__ void gain_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ngroups, GV &gv, GainPre &pacc,
                             CountX &racc)
 {
     const int gl = threadIdx.x & (G - 1);
     const int32_t *list = a.bins + a.binoff[cls];
-    const Walk w = walk(a, a.binoff[cls + 1] - a.binoff[cls], gid, ngroups, 1);
+    const Walk w = walk<B>(a.binoff[cls + 1] - a.binoff[cls], gid, ngroups, 1);
     for (int i = w.first; i < w.end; i += w.step) {
         const int v = list[i];
-        const int g = graph_of(a, v);
-        gv.at(a, g);
+        const int g = gof<B>(a, v);
+        gv.sel<B>(a, g);
         if (gv.kind != KIND_LP) continue;
         const int ps = a.P[v];
         if (gl == 0) {
-            pacc.to(a, g);
+            pacc.sel<B>(a, g);
             pacc.c0++;
         }
         if (a.lock[v] == gv.lp_id - 1) {
@@ -846,27 +866,28 @@ __device__ void gain_groups(const KArgs &a, int cls, int32_t *tab, int gid, int 
         best = gmax_u64<G>(best);
         cs = gsum<G>(cs);
         if (gl == 0) {
-            racc.to(a, g);
+            racc.sel<B>(a, g);
             racc.c0 += gain_finish(a, v, ps, best, cs, gv.cn, gv.cd);
         }
     }
 }
 
+template <bool B>
 __device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nblocks, GV &gv, GainPre &pacc,
                             CountX &racc)
 {
     __shared__ uint64_t s_red[BLOCK / 64];
     __shared__ int32_t s_red32[BLOCK / 64];
     const int32_t *list = a.bins + a.binoff[cls];
-    const Walk w = walk(a, a.binoff[cls + 1] - a.binoff[cls], bid, nblocks, 1);
+    const Walk w = walk<B>(a.binoff[cls + 1] - a.binoff[cls], bid, nblocks, 1);
     for (int i = w.first; i < w.end; i += w.step) {
         const int v = list[i];
-        const int g = graph_of(a, v);
-        gv.at(a, g);
+        const int g = gof<B>(a, v);
+        gv.sel<B>(a, g);
         if (gv.kind != KIND_LP) continue;
         const int ps = a.P[v];
         if (threadIdx.x == 0) {
-            pacc.to(a, g);
+            pacc.sel<B>(a, g);
             pacc.c0++;
         }
         if (a.lock[v] == gv.lp_id - 1) {
@@ -894,7 +915,7 @@ __device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int 
         best = block_max_u64<BLOCK>(best, s_red);
         cs = block_sum<BLOCK>(cs, s_red32);
         if (threadIdx.x == 0) {
-            racc.to(a, g);
+            racc.sel<B>(a, g);
             racc.c0 += gain_finish(a, v, ps, best, cs, gv.cn, gv.cd);
         }
     }
@@ -904,7 +925,7 @@ __device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int 
 // groups, waves, blocks), so each keeps its own register budget; a.tmap says
 // which classes a role serves. Group tables are padded to k + 1 ints so the
 // tables of neighbouring groups start in different LDS banks.
-template <int ROLE, int GS = 8>
+template <bool B, int ROLE, int GS = 8>
 __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
 {
     if (!any_kind(a, KIND_LP)) return;
@@ -913,6 +934,12 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
     GV pv, rv;
     GainPre pacc;
     CountX racc;
+    if (!B) {
+        pv.at(a, 0);
+        rv.at(a, 0);
+        pacc.to(a, 0);
+        racc.to(a, 0);
+    }
     if (ROLE == 1) {
         constexpr int RS_ = 32 / GS;
         const int ng = BLOCK / GS;
@@ -924,13 +951,13 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
         for (int c = 1; c < NCLS; c++) {
             if (a.tmap[c] != 1) continue;
             wave_batched<GS>(
-                a.bins + a.binoff[c], walk(a, a.binoff[c + 1] - a.binoff[c], wid, nwaves, 64), q,
+                a.bins + a.binoff[c], walk<B>(a.binoff[c + 1] - a.binoff[c], wid, nwaves, 64), q,
                 [&](Meta &m) -> bool {
-                    m.g = graph_of(a, m.v);
-                    pv.at(a, m.g);
+                    m.g = gof<B>(a, m.v);
+                    pv.sel<B>(a, m.g);
                     if (pv.kind != KIND_LP) return false;
                     m.ps = a.P[m.v];
-                    pacc.to(a, m.g);
+                    pacc.sel<B>(a, m.g);
                     pacc.c0++;
                     if (a.lock[m.v] == pv.lp_id - 1) {
                         gain_locked(a, m.v, m.ps);
@@ -960,8 +987,8 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
                     best = gmax_u64<GS>(best);
                     cs = gsum<GS>(cs);
                     if (gl == 0) {
-                        rv.at(a, t.g);
-                        racc.to(a, t.g);
+                        rv.sel<B>(a, t.g);
+                        racc.sel<B>(a, t.g);
                         racc.c0 += gain_finish(a, t.v, t.ps, best, cs, rv.cn, rv.cd);
                     }
                 });
@@ -973,12 +1000,12 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
         int32_t *tab = lds + (threadIdx.x >> 6) * stride;
         for (int c = 1; c < NCLS; c++)
             if (a.tmap[c] == 2)
-                gain_groups<64, 16>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 6), nblk * ng, pv, pacc, racc);
+                gain_groups<B, 64, 16>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 6), nblk * ng, pv, pacc, racc);
     } else {
         for (int i = threadIdx.x; i < a.k; i += BLOCK) lds[i] = 0;
         __syncthreads();
         for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 3) gain_blocks(a, c, lds, blockIdx.x, nblk, pv, pacc, racc);
+            if (a.tmap[c] == 3) gain_blocks<B>(a, c, lds, blockIdx.x, nblk, pv, pacc, racc);
     }
     acc_finish(a, pacc);
     acc_finish(a, racc);
@@ -1011,22 +1038,24 @@ __device__ __forceinline__ void after_store(const KArgs &a, int v, int pd, int s
     if (sum >= 0) a.dest[v] = pd;
 }
 
+template <bool B>
 __global__ __launch_bounds__(BLOCK) void k_afterburner(KArgs a)
 {
     __shared__ int32_t s_red[BLOCK / 64];
     __shared__ int32_t s_q[BLOCK];
     if (!any_kind(a, KIND_LP)) return;
     GV pv;
+    if (!B) pv.at(a, 0);
     int b = blockIdx.x;
     if (b < a.gS) {
         int32_t *q = s_q + (threadIdx.x >> 6) * 64;
         wave_batched<8>(
             a.bins + a.binoff[CLS_S],
-            walk(a, a.binoff[CLS_S + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6), a.gS * (BLOCK / 64),
+            walk<B>(a.binoff[CLS_S + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6), a.gS * (BLOCK / 64),
                  64),
             q,
             [&](Meta &m) -> bool {
-                pv.at(a, graph_of(a, m.v));
+                pv.sel<B>(a, gof<B>(a, m.v));
                 if (pv.kind != KIND_LP) return false;
                 const int2 r = a.rec[m.v];
                 if ((r.x & 0xFFFF) == 0) return false;  // not in X
@@ -1048,11 +1077,11 @@ __global__ __launch_bounds__(BLOCK) void k_afterburner(KArgs a)
     if (b < a.gM) {
         const int gl = threadIdx.x & 63;
         const int32_t *list = a.bins + a.binoff[CLS_M];
-        const Walk w = walk(a, a.binoff[CLS_M + 1] - a.binoff[CLS_M], b * (BLOCK / 64) + (threadIdx.x >> 6),
+        const Walk w = walk<B>(a.binoff[CLS_M + 1] - a.binoff[CLS_M], b * (BLOCK / 64) + (threadIdx.x >> 6),
                             a.gM * (BLOCK / 64), 1);
         for (int i = w.first; i < w.end; i += w.step) {
             const int v = list[i];
-            pv.at(a, graph_of(a, v));
+            pv.sel<B>(a, gof<B>(a, v));
             if (pv.kind != KIND_LP) continue;
             const int2 r = a.rec[v];
             if ((r.x & 0xFFFF) == 0) continue;
@@ -1067,10 +1096,10 @@ __global__ __launch_bounds__(BLOCK) void k_afterburner(KArgs a)
     b -= a.gM;
     if (b >= a.gL) return;
     const int32_t *list = a.bins + a.binoff[CLS_L];
-    const Walk w = walk(a, a.binoff[CLS_L + 1] - a.binoff[CLS_L], b, a.gL, 1);
+    const Walk w = walk<B>(a.binoff[CLS_L + 1] - a.binoff[CLS_L], b, a.gL, 1);
     for (int i = w.first; i < w.end; i += w.step) {
         const int v = list[i];
-        pv.at(a, graph_of(a, v));
+        pv.sel<B>(a, gof<B>(a, v));
         if (pv.kind != KIND_LP) continue;
         const int2 r = a.rec[v];
         if ((r.x & 0xFFFF) == 0) continue;
@@ -1113,30 +1142,36 @@ __device__ __forceinline__ void move_meta(const KArgs &a, int v, int lv, int ps,
     acc.c2 += mix64(((uint64_t)(uint32_t)lv << 32) | (uint32_t)pn) - mix64(((uint64_t)(uint32_t)lv << 32) | (uint32_t)ps);
 }
 
+template <bool B>
 __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
 {
     __shared__ int32_t s_red32[BLOCK / 64];
     __shared__ int32_t s_q[BLOCK];
     if (!any_active(a)) return;
     GV pv;
+    if (!B) pv.at(a, 0);
     if (count_row(a)[0] > 0) {
         // graphs whose previous iteration improved the best partition: copy
         // P_iter before this iteration's moves are applied
         int lo, hi;
         block_chunk(a.n, blockIdx.x, gridDim.x, lo, hi);
         for (int v = lo + threadIdx.x; v < hi; v += BLOCK) {
-            pv.at(a, graph_of(a, v));
+            pv.sel<B>(a, gof<B>(a, v));
             if (pv.copy && pv.kind != KIND_DONE) a.best[v] = a.P[v];
         }
     }
     MoveAcc macc;
     CutAcc cacc;
+    if (!B) {
+        macc.to(a, 0);
+        cacc.to(a, 0);
+    }
     int b = blockIdx.x;
     if (b < a.gS) {
         int32_t *q = s_q + (threadIdx.x >> 6) * 64;
         wave_batched<8>(
             a.bins + a.binoff[CLS_S],
-            walk(a, a.binoff[CLS_S + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6), a.gS * (BLOCK / 64),
+            walk<B>(a.binoff[CLS_S + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6), a.gS * (BLOCK / 64),
                  64),
             q,
             [&](Meta &m) -> bool {
@@ -1144,9 +1179,9 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
                 if (pn < 0) return false;
                 m.aux = pn;
                 m.ps = a.P[m.v];
-                m.g = graph_of(a, m.v);
-                pv.at(a, m.g);
-                macc.to(a, m.g);
+                m.g = gof<B>(a, m.v);
+                pv.sel<B>(a, m.g);
+                macc.sel<B>(a, m.g);
                 move_meta(a, m.v, m.v - pv.voff, m.ps, pn, macc);
                 m.s = a.xadj[m.v];
                 m.deg = (int)(a.xadj[m.v + 1] - m.s);
@@ -1156,49 +1191,49 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
                 int d = dcut_sum_row(a, t.v, t.s, t.deg, t.ps, t.aux, gl, 8);
                 d = gsum<8>(d);
                 if (gl == 0) {
-                    cacc.to(a, t.g);
+                    cacc.sel<B>(a, t.g);
                     cacc.c0 += (uint64_t)(int64_t)d;
                 }
             });
     } else if ((b -= a.gS) < a.gM) {
         const int gl = threadIdx.x & 63;
         const int32_t *list = a.bins + a.binoff[CLS_M];
-        const Walk w = walk(a, a.binoff[CLS_M + 1] - a.binoff[CLS_M], b * (BLOCK / 64) + (threadIdx.x >> 6),
+        const Walk w = walk<B>(a.binoff[CLS_M + 1] - a.binoff[CLS_M], b * (BLOCK / 64) + (threadIdx.x >> 6),
                             a.gM * (BLOCK / 64), 1);
         for (int i = w.first; i < w.end; i += w.step) {
             const int v = list[i];
             const int pn = a.dest[v];
             if (pn < 0) continue;
             const int ps = a.P[v];
-            const int g = graph_of(a, v);
+            const int g = gof<B>(a, v);
             const int64_t s = a.xadj[v];
             int d = dcut_sum_row(a, v, s, (int)(a.xadj[v + 1] - s), ps, pn, gl, 64);
             d = gsum<64>(d);
             if (gl == 0) {
-                pv.at(a, g);
-                macc.to(a, g);
+                pv.sel<B>(a, g);
+                macc.sel<B>(a, g);
                 move_meta(a, v, v - pv.voff, ps, pn, macc);
-                cacc.to(a, g);
+                cacc.sel<B>(a, g);
                 cacc.c0 += (uint64_t)(int64_t)d;
             }
         }
     } else if ((b -= a.gM) < a.gL) {
         const int32_t *list = a.bins + a.binoff[CLS_L];
-        const Walk w = walk(a, a.binoff[CLS_L + 1] - a.binoff[CLS_L], b, a.gL, 1);
+        const Walk w = walk<B>(a.binoff[CLS_L + 1] - a.binoff[CLS_L], b, a.gL, 1);
         for (int i = w.first; i < w.end; i += w.step) {
             const int v = list[i];
             const int pn = a.dest[v];
             if (pn < 0) continue;
             const int ps = a.P[v];
-            const int g = graph_of(a, v);
+            const int g = gof<B>(a, v);
             const int64_t s = a.xadj[v];
             int d = dcut_sum_row(a, v, s, (int)(a.xadj[v + 1] - s), ps, pn, threadIdx.x, BLOCK);
             d = block_sum<BLOCK>(d, s_red32);
             if (threadIdx.x == 0) {
-                pv.at(a, g);
-                macc.to(a, g);
+                pv.sel<B>(a, g);
+                macc.sel<B>(a, g);
                 move_meta(a, v, v - pv.voff, ps, pn, macc);
-                cacc.to(a, g);
+                cacc.sel<B>(a, g);
                 cacc.c0 += (uint64_t)(int64_t)d;
             }
         }
@@ -1211,9 +1246,9 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
             const int v = list[i];
             const int pn = a.dest[v];
             if (pn < 0) continue;
-            const int g = graph_of(a, v);
-            pv.at(a, g);
-            macc.to(a, g);
+            const int g = gof<B>(a, v);
+            pv.sel<B>(a, g);
+            macc.sel<B>(a, g);
             move_meta(a, v, v - pv.voff, a.P[v], pn, macc);
         }
     }
@@ -1223,22 +1258,24 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
 
 // ------------------------------------------------------------ apply moves --
 
+template <bool B>
 __global__ __launch_bounds__(BLOCK) void k_apply(KArgs a)
 {
     extern __shared__ int32_t s_dw[];  // [k] block-partial weight change (one graph)
     if (!any_active(a)) return;
-    const bool single = a.vg == nullptr;
+    constexpr bool single = !B;
     if (single) {
         for (int p = threadIdx.x; p < a.k; p += BLOCK) s_dw[p] = 0;
         __syncthreads();
     }
     GV pv;
+    if (!B) pv.at(a, 0);
     int lo, hi;
     block_chunk(a.n, blockIdx.x, gridDim.x, lo, hi);
     for (int v = lo + threadIdx.x; v < hi; v += BLOCK) {
         const int pn = a.dest[v];
         if (pn < 0) continue;
-        pv.at(a, graph_of(a, v));
+        pv.sel<B>(a, gof<B>(a, v));
         const int ps = a.P[v];
         const int vwv = a.vw ? a.vw[v] : 1;
         a.P[v] = pn;
@@ -1310,16 +1347,16 @@ __device__ __forceinline__ bool rb_candidate(const KArgs &a, int v, int ps, int 
     return false;
 }
 
-template <int G, int R>
+template <bool B, int G, int R>
 __device__ void rb_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ngroups, GV &gv, CountX &racc)
 {
     const int gl = threadIdx.x & (G - 1);
     const int32_t *list = a.bins + a.binoff[cls];
-    const Walk w = walk(a, a.binoff[cls + 1] - a.binoff[cls], gid, ngroups, 1);
+    const Walk w = walk<B>(a.binoff[cls + 1] - a.binoff[cls], gid, ngroups, 1);
     for (int i = w.first; i < w.end; i += w.step) {
         const int v = list[i];
-        const int g = graph_of(a, v);
-        gv.at(a, g);
+        const int g = gof<B>(a, v);
+        gv.sel<B>(a, g);
         if (!is_rb(gv.kind)) continue;
         const int ps = a.P[v];
         const int vwv = a.vw ? a.vw[v] : 1;
@@ -1347,22 +1384,23 @@ __device__ void rb_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ng
         cntB = gsum<G>(cntB);
         if (gl == 0) {
             rb_finish(a, v, ps, gv, best, cs, sumB, cntB);
-            racc.to(a, g);
+            racc.sel<B>(a, g);
             racc.c0++;
         }
     }
 }
 
+template <bool B>
 __device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nblocks, GV &gv, CountX &racc)
 {
     __shared__ uint64_t s_red[BLOCK / 64];
     __shared__ int32_t s_red32[BLOCK / 64];
     const int32_t *list = a.bins + a.binoff[cls];
-    const Walk w = walk(a, a.binoff[cls + 1] - a.binoff[cls], bid, nblocks, 1);
+    const Walk w = walk<B>(a.binoff[cls + 1] - a.binoff[cls], bid, nblocks, 1);
     for (int i = w.first; i < w.end; i += w.step) {
         const int v = list[i];
-        const int g = graph_of(a, v);
-        gv.at(a, g);
+        const int g = gof<B>(a, v);
+        gv.sel<B>(a, g);
         if (!is_rb(gv.kind)) continue;
         const int ps = a.P[v];
         const int vwv = a.vw ? a.vw[v] : 1;
@@ -1389,13 +1427,13 @@ __device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nb
         cntB = block_sum<BLOCK>(cntB, s_red32);
         if (threadIdx.x == 0) {
             rb_finish(a, v, ps, gv, best, cs, sumB, cntB);
-            racc.to(a, g);
+            racc.sel<B>(a, g);
             racc.c0++;
         }
     }
 }
 
-template <int ROLE, int GS = 8>
+template <bool B, int ROLE, int GS = 8>
 __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
 {
     extern __shared__ int32_t lds[];
@@ -1403,6 +1441,11 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
     const int stride = a.k + 1;
     GV pv, rv;
     CountX racc;
+    if (!B) {
+        pv.at(a, 0);
+        rv.at(a, 0);
+        racc.to(a, 0);
+    }
     if (ROLE == 1) {
         constexpr int RS_ = 32 / GS;
         const int ng = BLOCK / GS;
@@ -1414,10 +1457,10 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
         for (int c = 1; c < NCLS; c++) {
             if (a.tmap[c] != 1) continue;
             wave_batched<GS>(
-                a.bins + a.binoff[c], walk(a, a.binoff[c + 1] - a.binoff[c], wid, nwaves, 64), q,
+                a.bins + a.binoff[c], walk<B>(a.binoff[c + 1] - a.binoff[c], wid, nwaves, 64), q,
                 [&](Meta &m) -> bool {
-                    m.g = graph_of(a, m.v);
-                    pv.at(a, m.g);
+                    m.g = gof<B>(a, m.v);
+                    pv.sel<B>(a, m.g);
                     if (!is_rb(pv.kind)) return false;
                     m.ps = a.P[m.v];
                     m.aux = a.vw ? a.vw[m.v] : 1;
@@ -1427,7 +1470,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
                     return true;
                 },
                 [&](const Meta &t, int gl) {
-                    rv.at(a, t.g);
+                    rv.sel<B>(a, t.g);
                     int pu[RS_], cu[RS_];
                     group_conn_row<GS, RS_>(a, t.s, t.deg, gl, tab, pu, cu);
                     uint64_t best = 0;
@@ -1450,7 +1493,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
                     cntB = gsum<GS>(cntB);
                     if (gl == 0) {
                         rb_finish(a, t.v, t.ps, rv, best, cs, sumB, cntB);
-                        racc.to(a, t.g);
+                        racc.sel<B>(a, t.g);
                         racc.c0++;
                     }
                 });
@@ -1461,12 +1504,12 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
         __syncthreads();
         int32_t *tab = lds + (threadIdx.x >> 6) * stride;
         for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 2) rb_groups<64, 16>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 6), nblk * ng, pv, racc);
+            if (a.tmap[c] == 2) rb_groups<B, 64, 16>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 6), nblk * ng, pv, racc);
     } else if (ROLE == 3) {
         for (int i = threadIdx.x; i < a.k; i += BLOCK) lds[i] = 0;
         __syncthreads();
         for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 3) rb_blocks(a, c, lds, blockIdx.x, nblk, pv, racc);
+            if (a.tmap[c] == 3) rb_blocks<B>(a, c, lds, blockIdx.x, nblk, pv, racc);
     } else {
         // isolated vertices: no connectivity, loss 0, random destination (Jetrw)
         const int32_t *list = a.bins + a.binoff[CLS_Z];
@@ -1475,13 +1518,13 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
         block_chunk(cnt, blockIdx.x, nblk, lo, hi);
         for (int i = lo + threadIdx.x; i < hi; i += BLOCK) {
             const int v = list[i];
-            const int g = graph_of(a, v);
-            pv.at(a, g);
+            const int g = gof<B>(a, v);
+            pv.sel<B>(a, g);
             if (!is_rb(pv.kind)) continue;
             const int ps = a.P[v];
             if (!rb_candidate(a, v, ps, a.vw ? a.vw[v] : 1, pv)) continue;
             rb_finish(a, v, ps, pv, 0, 0, 0, 0);
-            racc.to(a, g);
+            racc.sel<B>(a, g);
             racc.c0++;
         }
     }
@@ -1491,6 +1534,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
 // Per-(part, slot) weight histogram of the candidates. With one graph whose
 // k * NSLOT int32 counters fit, each block accumulates its range in LDS and
 // adds its nonzero counters once.
+template <bool B>
 __global__ __launch_bounds__(BLOCK) void k_rb_hist(KArgs a, int use_lds)
 {
     extern __shared__ int32_t h[];
@@ -1501,12 +1545,13 @@ __global__ __launch_bounds__(BLOCK) void k_rb_hist(KArgs a, int use_lds)
         __syncthreads();
     }
     GV pv;
+    if (!B) pv.at(a, 0);
     int lo, hi;
     block_chunk(a.n, blockIdx.x, gridDim.x, lo, hi);
     for (int v = lo + threadIdx.x; v < hi; v += BLOCK) {
         const int sl = a.slot[v];
         if (sl == 255) continue;
-        pv.at(a, graph_of(a, v));
+        pv.sel<B>(a, gof<B>(a, v));
         if (!is_rb(pv.kind)) continue;  // a slot left from an earlier iteration
         const int idx = (pv.poff + a.P[v]) * NSLOT + sl;
         const int vwv = a.vw ? a.vw[v] : 1;
@@ -1990,36 +2035,39 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
 // k + 1 ints per block fit in 32 KiB): twice the vertices in flight per wave.
 constexpr int K_G4 = 120;
 
-static void launch_gain(const Plan &pl, hipStream_t s)
+template <bool B>
+static void launch_gain_t(const Plan &pl, hipStream_t s)
 {
     const KArgs &t = pl.tab;
     const size_t st = (size_t)(t.k + 1) * 4;
     if (t.gS) {
-        if (t.k <= K_G4) k_gain<1, 4><<<t.gS, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, t.gS);
-        else k_gain<1, 8><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS);
+        if (t.k <= K_G4) k_gain<B, 1, 4><<<t.gS, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, t.gS);
+        else k_gain<B, 1, 8><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS);
     }
-    if (t.gM) k_gain<2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM);
-    if (t.gL) k_gain<3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL);
+    if (t.gM) k_gain<B, 2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM);
+    if (t.gL) k_gain<B, 3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL);
 }
 
-static void launch_rb_loss(const Plan &pl, hipStream_t s)
+template <bool B>
+static void launch_rb_loss_t(const Plan &pl, hipStream_t s)
 {
     const KArgs &t = pl.tab;
     const size_t st = (size_t)(t.k + 1) * 4;
     if (t.gS) {
-        if (t.k <= K_G4) k_rb_loss<1, 4><<<t.gS, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, t.gS);
-        else k_rb_loss<1, 8><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS);
+        if (t.k <= K_G4) k_rb_loss<B, 1, 4><<<t.gS, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, t.gS);
+        else k_rb_loss<B, 1, 8><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS);
     }
-    if (t.gM) k_rb_loss<2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM);
-    if (t.gL) k_rb_loss<3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL);
-    if (t.gZ) k_rb_loss<4><<<t.gZ, BLOCK, 0, s>>>(t, t.gZ);
+    if (t.gM) k_rb_loss<B, 2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM);
+    if (t.gL) k_rb_loss<B, 3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL);
+    if (t.gZ) k_rb_loss<B, 4><<<t.gZ, BLOCK, 0, s>>>(t, t.gZ);
 }
 
 // Histogram, cut-off slots, ordered selection and (Jetrs) the cookie-cutter.
-static void launch_rb_select(const Plan &pl, hipStream_t s)
+template <bool B>
+static void launch_rb_select_t(const Plan &pl, hipStream_t s)
 {
     const KArgs &p = pl.plain;
-    k_rb_hist<<<pl.grid_hist, BLOCK, pl.hist_lds ? (size_t)p.k * NSLOT * 4 : 0, s>>>(p, pl.hist_lds);
+    k_rb_hist<B><<<pl.grid_hist, BLOCK, pl.hist_lds ? (size_t)p.k * NSLOT * 4 : 0, s>>>(p, pl.hist_lds);
     k_rb_cutoff<<<pl.G, BLOCK, 0, s>>>(p);
     k_rb_tilesum<<<pl.grid_tile, BLOCK, (size_t)p.k * 4, s>>>(p);
     k_rb_split<<<std::min(p.ktot, 1024), BLOCK, 0, s>>>(p);
@@ -2028,18 +2076,42 @@ static void launch_rb_select(const Plan &pl, hipStream_t s)
     k_rs_assign<<<pl.grid_tile, BLOCK, 0, s>>>(p);
 }
 
-static void launch_iteration(const Plan &pl, hipStream_t s, hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr)
+template <bool B>
+static void launch_iteration_t(const Plan &pl, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b)
 {
     const KArgs &p = pl.plain;
     if (ev_a) (void)hipEventRecord(ev_a, s);
-    launch_gain(pl, s);
+    launch_gain_t<B>(pl, s);
     if (ev_b) (void)hipEventRecord(ev_b, s);
-    if (pl.grid_plain) k_afterburner<<<pl.grid_plain, BLOCK, 0, s>>>(p);
-    launch_rb_loss(pl, s);
-    launch_rb_select(pl, s);
-    if (pl.grid_plain) k_dcut<<<pl.grid_plain, BLOCK, 0, s>>>(p);
-    k_apply<<<pl.grid_flat, BLOCK, p.vg ? 0 : (size_t)p.k * 4, s>>>(p);
+    if (pl.grid_plain) k_afterburner<B><<<pl.grid_plain, BLOCK, 0, s>>>(p);
+    launch_rb_loss_t<B>(pl, s);
+    launch_rb_select_t<B>(pl, s);
+    if (pl.grid_plain) k_dcut<B><<<pl.grid_plain, BLOCK, 0, s>>>(p);
+    k_apply<B><<<pl.grid_flat, BLOCK, B ? 0 : (size_t)p.k * 4, s>>>(p);
     k_ctl_end<<<pl.G, BLOCK, 0, s>>>(p);
+}
+
+static bool batched(const Plan &pl) { return pl.plain.vg != nullptr; }
+
+static void launch_gain(const Plan &pl, hipStream_t s)
+{
+    if (batched(pl)) launch_gain_t<true>(pl, s);
+    else launch_gain_t<false>(pl, s);
+}
+static void launch_rb_loss(const Plan &pl, hipStream_t s)
+{
+    if (batched(pl)) launch_rb_loss_t<true>(pl, s);
+    else launch_rb_loss_t<false>(pl, s);
+}
+static void launch_rb_select(const Plan &pl, hipStream_t s)
+{
+    if (batched(pl)) launch_rb_select_t<true>(pl, s);
+    else launch_rb_select_t<false>(pl, s);
+}
+static void launch_iteration(const Plan &pl, hipStream_t s, hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr)
+{
+    if (batched(pl)) launch_iteration_t<true>(pl, s, ev_a, ev_b);
+    else launch_iteration_t<false>(pl, s, ev_a, ev_b);
 }
 
 static void set_it(Plan &pl, int it)
@@ -2048,23 +2120,30 @@ static void set_it(Plan &pl, int it)
     pl.plain.it = it;
 }
 
+template <bool B>
+static void set_lds_limits_t()
+{
+    (void)hipFuncSetAttribute((const void *)k_gain<B, 1, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_gain<B, 1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_gain<B, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_gain<B, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 1, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_apply<B>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_hist<B>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+}
+
 static void set_lds_limits()
 {
     static bool done = false;
     if (done) return;
     done = true;
-    (void)hipFuncSetAttribute((const void *)k_gain<1, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-    (void)hipFuncSetAttribute((const void *)k_gain<1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-    (void)hipFuncSetAttribute((const void *)k_gain<2>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-    (void)hipFuncSetAttribute((const void *)k_gain<3>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-    (void)hipFuncSetAttribute((const void *)k_rb_loss<1, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-    (void)hipFuncSetAttribute((const void *)k_rb_loss<1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-    (void)hipFuncSetAttribute((const void *)k_rb_loss<2>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-    (void)hipFuncSetAttribute((const void *)k_rb_loss<3>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-    (void)hipFuncSetAttribute((const void *)k_apply, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    set_lds_limits_t<false>();
+    set_lds_limits_t<true>();
     (void)hipFuncSetAttribute((const void *)k_init_vertices, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_tilesum, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-    (void)hipFuncSetAttribute((const void *)k_rb_hist, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
 }
 
 static int check_params(const jet_csr *g, const jet_params *prm)
@@ -2784,7 +2863,7 @@ extern "C" int jet_lp_step(jet_context *ctx, const jet_csr *g, const jet_params 
     k_step_defaults<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, part);
     k_force_step<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, KIND_LP, 0, locked);
     launch_gain(pl, s);
-    if (pl.grid_plain) k_afterburner<<<pl.grid_plain, BLOCK, 0, s>>>(pl.plain);
+    if (pl.grid_plain) k_afterburner<false><<<pl.grid_plain, BLOCK, 0, s>>>(pl.plain);
     k_lp_outputs<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, inX, move);
     JET_TRY(hipGetLastError());
     JET_TRY(hipStreamSynchronize(s));
