@@ -71,7 +71,7 @@ struct KArgs {
     const int32_t *vg;     // graph of each vertex (NULL: one graph)
     const int32_t *pg;     // graph of each global part (NULL: one graph)
     const int32_t *tg;     // graph of each tile (NULL: one graph)
-    int32_t *P;            // P_iter (local part ids)
+    uint16_t *P;           // P_iter (local part ids; k <= KMAX fits 16 bits, halving the gathered bytes)
     int32_t *best;         // P_best
     int2 *rec;             // Jetlp record: x = (P_s << 16) | (in X ? P_d + 1 : 0), y = F
     int32_t *dest;         // move destination or -1 (kept -1 outside moves)
@@ -98,6 +98,13 @@ struct KArgs {
     // block counts per role of the row kernels
     int32_t gS, gM, gL, gZ;
     int32_t tmap[NCLS];    // which role (1 S, 2 M, 3 L) serves each class in the LDS-table kernels
+    // long rows of the L class cut into chunks (see LCHUNK); nlch = 0: L rows use the block role
+    const int2 *lch;       // (index in the L list, chunk index) per chunk
+    int32_t nlch;
+    int32_t lstride;       // row length of gconn (largest k)
+    int32_t *gconn;        // [L list][lstride] connectivity summed over a vertex's chunks
+    int32_t *ldone;        // [L list] chunks of the vertex completed in this pass
+    int32_t *gf2;          // [L list] afterburner sum over a vertex's chunks
     // optional step outputs
     int64_t *dbg_F, *dbg_cs, *dbg_F2, *dbg_loss;
     int32_t *dbg_pd;
@@ -139,6 +146,7 @@ enum WsSlot {
     WS_DBG_LOCK, WS_H0, WS_H1, WS_C0, WS_C1, WS_C2, WS_C3, WS_C4, WS_C5, WS_C6, WS_C7, WS_C8,
     WS_C9, WS_C10, WS_C11, WS_KINDS, WS_C12, WS_BLKCNT, WS_TG,
     WS_U_XADJ, WS_U_ADJ, WS_U_VW, WS_U_EW, WS_U_VG, WS_U_P0, WS_U_BEST, WS_U_DESC,
+    WS_LCNT, WS_LCH, WS_GCONN, WS_LDONE,
     WS_COUNT = 64
 };
 

@@ -251,7 +251,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_vertices(KArgs a, const int32_t 
         } else if (a.best != part_in) {
             a.best[v] = p;
         }
-        a.P[v] = p;
+        a.P[v] = (uint16_t)p;
         a.dest[v] = -1;
         a.lock[v] = -1;
         a.slot[v] = 255;
@@ -645,6 +645,12 @@ __global__ __launch_bounds__(BLOCK) void k_copy_best(KArgs a)
     }
 }
 
+// P_iter widened into a caller's int32 array (JET_F_RETURN_ITER).
+__global__ __launch_bounds__(BLOCK) void k_copy_iter(KArgs a, int32_t *out)
+{
+    for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) out[v] = a.P[v];
+}
+
 // Single-step entry points (one graph): force one iteration of `kind` at
 // index t. For Jetlp, lock flags become stamps of the previous Jetlp (id 0).
 __global__ __launch_bounds__(BLOCK) void k_force_step(KArgs a, int kind, int t, const uint8_t *locked)
@@ -764,13 +770,28 @@ __device__ __forceinline__ void wave_batched(const int32_t *list, Walk w, int32_
     }
 }
 
+// Rows longer than a group walk their entries in rounds of U per lane: all
+// U neighbour ids (and weights) are loaded, then all U dependent gathers are
+// issued, so a lane has U loads in flight instead of one.
+constexpr int UROW = 8;
+
 // Whole block gathers the neighbours of v into `tab`.
 __device__ __forceinline__ void block_fill(const KArgs &a, int v, int32_t *tab)
 {
     const int64_t s = a.xadj[v], e = a.xadj[v + 1];
-    for (int64_t i = s + threadIdx.x; i < e; i += BLOCK) {
-        const int u = a.adj[i];
-        atomicAdd(&tab[a.P[u]], a.ew ? a.ew[i] : 1);
+    for (int64_t base = s + threadIdx.x; base < e; base += (int64_t)BLOCK * UROW) {
+        int u[UROW], w[UROW], p[UROW];
+#pragma unroll
+        for (int j = 0; j < UROW; j++) {
+            const int64_t i = base + (int64_t)j * BLOCK;
+            u[j] = i < e ? a.adj[i] : -1;
+            w[j] = i < e ? (a.ew ? a.ew[i] : 1) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < UROW; j++) p[j] = u[j] >= 0 ? a.P[u[j]] : -1;
+#pragma unroll
+        for (int j = 0; j < UROW; j++)
+            if (p[j] >= 0) atomicAdd(&tab[p[j]], w[j]);
     }
     __syncthreads();
 }
@@ -925,7 +946,7 @@ __device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int 
 // groups, waves, blocks), so each keeps its own register budget; a.tmap says
 // which classes a role serves. Group tables are padded to k + 1 ints so the
 // tables of neighbouring groups start in different LDS banks.
-template <bool B, int ROLE, int GS = 8>
+template <bool B, int ROLE, int GS = 8, int RS = 32 / GS>
 __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
 {
     if (!any_kind(a, KIND_LP)) return;
@@ -941,7 +962,8 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
         racc.to(a, 0);
     }
     if (ROLE == 1) {
-        constexpr int RS_ = 32 / GS;
+        // groups of GS lanes (rows of up to GS * RS entries), wave-batched
+        constexpr int RS_ = RS;
         const int ng = BLOCK / GS;
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         __syncthreads();
@@ -949,7 +971,7 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
         int32_t *q = lds + ng * stride + (threadIdx.x >> 6) * 64;
         const int wid = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nblk * (BLOCK / 64);
         for (int c = 1; c < NCLS; c++) {
-            if (a.tmap[c] != 1) continue;
+            if (a.tmap[c] != ROLE) continue;
             wave_batched<GS>(
                 a.bins + a.binoff[c], walk<B>(a.binoff[c + 1] - a.binoff[c], wid, nwaves, 64), q,
                 [&](Meta &m) -> bool {
@@ -994,6 +1016,7 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
                 });
         }
     } else if (ROLE == 2) {
+        // one wave per vertex, walking its list interleaved with the other waves
         const int ng = BLOCK / 64;
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         __syncthreads();
@@ -1016,18 +1039,30 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
 // F2(v) = sum over neighbours u of w * ([q_u = P_d(v)] - [q_u = P_s(v)]) with
 // q_u = P_d(u) when u is in X and precedes v (larger F, or equal F and smaller
 // id), else P_s(u). Moves with F2 >= 0 form M.
+template <int U>
 __device__ __forceinline__ int after_sum_row(const KArgs &a, int v, int64_t s, int deg, int ps, int pd, int Fv, int gl,
                                              int stride)
 {
     int sum = 0;
-    for (int idx = gl; idx < deg; idx += stride) {
-        const int u = a.adj[s + idx];
-        const int wt = a.ew ? a.ew[s + idx] : 1;
-        const int2 ru = a.rec[u];
-        int q = ru.x >> 16;
-        const int pdu = (ru.x & 0xFFFF) - 1;
-        if (pdu >= 0 && (ru.y > Fv || (ru.y == Fv && u < v))) q = pdu;
-        sum += q == pd ? wt : (q == ps ? -wt : 0);
+    for (int base = gl; base < deg; base += stride * U) {
+        int u[U], wt[U];
+        int2 ru[U];
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            const int idx = base + j * stride;
+            u[j] = idx < deg ? a.adj[s + idx] : -1;
+            wt[j] = idx < deg ? (a.ew ? a.ew[s + idx] : 1) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < U; j++) ru[j] = u[j] >= 0 ? a.rec[u[j]] : make_int2(0, 0);
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            if (u[j] < 0) continue;
+            int q = ru[j].x >> 16;
+            const int pdu = (ru[j].x & 0xFFFF) - 1;
+            if (pdu >= 0 && (ru[j].y > Fv || (ru[j].y == Fv && u[j] < v))) q = pdu;
+            sum += q == pd ? wt[j] : (q == ps ? -wt[j] : 0);
+        }
     }
     return sum;
 }
@@ -1067,7 +1102,7 @@ __global__ __launch_bounds__(BLOCK) void k_afterburner(KArgs a)
             },
             [&](const Meta &t, int gl) {
                 const int ps = t.ps >> 16, pd = (t.ps & 0xFFFF) - 1;
-                int sum = after_sum_row(a, t.v, t.s, t.deg, ps, pd, t.aux, gl, 8);
+                int sum = after_sum_row<1>(a, t.v, t.s, t.deg, ps, pd, t.aux, gl, 8);
                 sum = gsum<8>(sum);
                 if (gl == 0) after_store(a, t.v, pd, sum);
             });
@@ -1087,7 +1122,7 @@ __global__ __launch_bounds__(BLOCK) void k_afterburner(KArgs a)
             if ((r.x & 0xFFFF) == 0) continue;
             const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
             const int64_t s = a.xadj[v];
-            int sum = after_sum_row(a, v, s, (int)(a.xadj[v + 1] - s), ps, pd, r.y, gl, 64);
+            int sum = after_sum_row<4>(a, v, s, (int)(a.xadj[v + 1] - s), ps, pd, r.y, gl, 64);
             sum = gsum<64>(sum);
             if (gl == 0) after_store(a, v, pd, sum);
         }
@@ -1105,7 +1140,7 @@ __global__ __launch_bounds__(BLOCK) void k_afterburner(KArgs a)
         if ((r.x & 0xFFFF) == 0) continue;
         const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
         const int64_t s = a.xadj[v];
-        int sum = after_sum_row(a, v, s, (int)(a.xadj[v + 1] - s), ps, pd, r.y, threadIdx.x, BLOCK);
+        int sum = after_sum_row<UROW>(a, v, s, (int)(a.xadj[v + 1] - s), ps, pd, r.y, threadIdx.x, BLOCK);
         sum = block_sum<BLOCK>(sum, s_red);
         if (threadIdx.x == 0) after_store(a, v, pd, sum);
     }
@@ -1116,18 +1151,30 @@ __global__ __launch_bounds__(BLOCK) void k_afterburner(KArgs a)
 // Delta of the cut over the edges of moved vertices: an edge whose two ends
 // both move is counted from its smaller end. Moved count, weight and digest
 // change are counted by the lane that finds the move.
+template <int U>
 __device__ __forceinline__ int dcut_sum_row(const KArgs &a, int v, int64_t s, int deg, int ps, int pn, int gl,
                                             int stride)
 {
     int delta = 0;
-    for (int idx = gl; idx < deg; idx += stride) {
-        const int u = a.adj[s + idx];
-        const int du = a.dest[u];
-        if (du >= 0 && u < v) continue;
-        const int wt = a.ew ? a.ew[s + idx] : 1;
-        const int pu = a.P[u];
-        const int pun = du >= 0 ? du : pu;
-        delta += wt * ((int)(pn != pun) - (int)(ps != pu));
+    for (int base = gl; base < deg; base += stride * U) {
+        int u[U], wt[U], du[U], pu[U];
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            const int idx = base + j * stride;
+            u[j] = idx < deg ? a.adj[s + idx] : -1;
+            wt[j] = idx < deg ? (a.ew ? a.ew[s + idx] : 1) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            du[j] = u[j] >= 0 ? a.dest[u[j]] : -1;
+            pu[j] = u[j] >= 0 ? a.P[u[j]] : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            if (u[j] < 0 || (du[j] >= 0 && u[j] < v)) continue;
+            const int pun = du[j] >= 0 ? du[j] : pu[j];
+            delta += wt[j] * ((int)(pn != pun) - (int)(ps != pu[j]));
+        }
     }
     return delta;
 }
@@ -1188,7 +1235,7 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
                 return true;
             },
             [&](const Meta &t, int gl) {
-                int d = dcut_sum_row(a, t.v, t.s, t.deg, t.ps, t.aux, gl, 8);
+                int d = dcut_sum_row<1>(a, t.v, t.s, t.deg, t.ps, t.aux, gl, 8);
                 d = gsum<8>(d);
                 if (gl == 0) {
                     cacc.sel<B>(a, t.g);
@@ -1207,7 +1254,7 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
             const int ps = a.P[v];
             const int g = gof<B>(a, v);
             const int64_t s = a.xadj[v];
-            int d = dcut_sum_row(a, v, s, (int)(a.xadj[v + 1] - s), ps, pn, gl, 64);
+            int d = dcut_sum_row<4>(a, v, s, (int)(a.xadj[v + 1] - s), ps, pn, gl, 64);
             d = gsum<64>(d);
             if (gl == 0) {
                 pv.sel<B>(a, g);
@@ -1227,7 +1274,7 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
             const int ps = a.P[v];
             const int g = gof<B>(a, v);
             const int64_t s = a.xadj[v];
-            int d = dcut_sum_row(a, v, s, (int)(a.xadj[v + 1] - s), ps, pn, threadIdx.x, BLOCK);
+            int d = dcut_sum_row<UROW>(a, v, s, (int)(a.xadj[v + 1] - s), ps, pn, threadIdx.x, BLOCK);
             d = block_sum<BLOCK>(d, s_red32);
             if (threadIdx.x == 0) {
                 pv.sel<B>(a, g);
@@ -1278,7 +1325,7 @@ __global__ __launch_bounds__(BLOCK) void k_apply(KArgs a)
         pv.sel<B>(a, gof<B>(a, v));
         const int ps = a.P[v];
         const int vwv = a.vw ? a.vw[v] : 1;
-        a.P[v] = pn;
+        a.P[v] = (uint16_t)pn;
         a.dest[v] = -1;
         if (pv.kind == KIND_LP) a.lock[v] = pv.lp_id;
         if (single) {
@@ -1294,6 +1341,253 @@ __global__ __launch_bounds__(BLOCK) void k_apply(KArgs a)
         for (int p = threadIdx.x; p < a.k; p += BLOCK)
             if (s_dw[p]) atomicAdd((unsigned long long *)&a.w[p], (unsigned long long)(int64_t)s_dw[p]);
     }
+}
+
+// Candidate test without side effects (the chunked rows write the
+// "no candidate" outputs once, from the vertex's first chunk).
+__device__ __forceinline__ bool rb_is_candidate(const KArgs &a, int ps, int vwv, const GV &gv)
+{
+    const int gp = gv.poff + ps;
+    const int64_t k = gv.k;
+    return a.isA[gp] && 2 * k * vwv <= 3 * (k * a.w[gp] - gv.W);
+}
+
+// ------------------------------------------------------- chunked long rows --
+// Rows of the L class are cut into chunks of LCHUNK entries, one wave each,
+// spread over the whole grid instead of one block walking a hub's row alone.
+// A chunk adds its part connectivity (or its afterburner partial sum) into a
+// per-vertex global row with atomics; a second kernel (one wave per long-row
+// vertex) reads and clears that row and finishes the vertex exactly as the
+// block role would. The kernel boundary orders the two phases.
+constexpr int LCHUNK = 1024;  // 64 lanes x 16 entries
+
+struct LChunk {
+    int v, li, len;
+    int64_t s;
+};
+
+__device__ __forceinline__ LChunk lchunk(const KArgs &a, int i)
+{
+    const int2 e = a.lch[i];
+    LChunk ch;
+    ch.li = e.x;
+    ch.v = a.bins[a.binoff[CLS_L] + e.x];
+    const int64_t s = a.xadj[ch.v], deg = a.xadj[ch.v + 1] - s;
+    ch.s = s + (int64_t)e.y * LCHUNK;
+    const int64_t rest = deg - (int64_t)e.y * LCHUNK;
+    ch.len = (int)(rest < LCHUNK ? rest : LCHUNK);
+    return ch;
+}
+
+// Adds a wave's claimed connectivities into the vertex's global row.
+__device__ __forceinline__ void lchunk_flush(int32_t *row, const int (&pu)[16], const int (&cu)[16])
+{
+#pragma unroll
+    for (int r = 0; r < 16; r++)
+        if (cu[r] > 0) atomicAdd(&row[pu[r]], cu[r]);
+}
+
+// Phase 1 of Jetlp gain and of the rebalancing loss on long rows: every
+// chunk of a vertex that needs its connectivity adds it to the vertex's row.
+template <bool B, bool RB>
+__global__ __launch_bounds__(BLOCK) void k_lconn(KArgs a)
+{
+    if (RB ? !any_rb(a) : !any_kind(a, KIND_LP)) return;
+    extern __shared__ int32_t lds[];
+    const int stride = a.k + 1;
+    for (int i = threadIdx.x; i < (BLOCK / 64) * stride; i += BLOCK) lds[i] = 0;
+    __syncthreads();
+    int32_t *tab = lds + (threadIdx.x >> 6) * stride;
+    const int gl = threadIdx.x & 63;
+    GV pv;
+    if (!B) pv.at(a, 0);
+    const int nw = gridDim.x * (BLOCK / 64);
+    for (int i = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); i < a.nlch; i += nw) {
+        const LChunk ch = lchunk(a, i);
+        pv.sel<B>(a, gof<B>(a, ch.v));
+        const int ps = a.P[ch.v];
+        if (RB) {
+            if (!is_rb(pv.kind) || !rb_is_candidate(a, ps, a.vw ? a.vw[ch.v] : 1, pv)) continue;
+        } else {
+            if (pv.kind != KIND_LP || a.lock[ch.v] == pv.lp_id - 1) continue;
+        }
+        int pu[16], cu[16];
+        group_conn_row<64, 16>(a, ch.s, ch.len, gl, tab, pu, cu);
+        lchunk_flush(a.gconn + (int64_t)ch.li * a.lstride, pu, cu);
+    }
+}
+
+// Phase 2 of the Jetlp gain on long rows (one wave per vertex).
+template <bool B>
+__global__ __launch_bounds__(BLOCK) void k_lgain_fin(KArgs a)
+{
+    if (!any_kind(a, KIND_LP)) return;
+    const int gl = threadIdx.x & 63;
+    const int nL = a.binoff[CLS_L + 1] - a.binoff[CLS_L];
+    GV pv;
+    GainPre pacc;
+    CountX racc;
+    if (!B) {
+        pv.at(a, 0);
+        pacc.to(a, 0);
+        racc.to(a, 0);
+    }
+    const int nw = gridDim.x * (BLOCK / 64);
+    for (int li = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); li < nL; li += nw) {
+        const int v = a.bins[a.binoff[CLS_L] + li];
+        const int g = gof<B>(a, v);
+        pv.sel<B>(a, g);
+        if (pv.kind != KIND_LP) continue;
+        const int ps = a.P[v];
+        if (gl == 0) {
+            pacc.sel<B>(a, g);
+            pacc.c0++;
+        }
+        if (a.lock[v] == pv.lp_id - 1) {
+            if (gl == 0) gain_locked(a, v, ps);
+            continue;
+        }
+        int32_t *row = a.gconn + (int64_t)li * a.lstride;
+        uint64_t best = 0;
+        int cs = 0;
+        for (int p = gl; p < pv.k; p += 64) {
+            const int c = row[p];
+            if (c) {
+                row[p] = 0;
+                if (p == ps) cs = c;
+                else {
+                    const uint64_t k2 = conn_key(c, p);
+                    best = k2 > best ? k2 : best;
+                }
+            }
+        }
+        best = gmax_u64<64>(best);
+        cs = gsum<64>(cs);
+        if (gl == 0) {
+            pacc.c1++;
+            pacc.c2 += a.xadj[v + 1] - a.xadj[v];
+            racc.sel<B>(a, g);
+            racc.c0 += gain_finish(a, v, ps, best, cs, pv.cn, pv.cd);
+        }
+    }
+    acc_finish(a, pacc);
+    acc_finish(a, racc);
+}
+
+// Afterburner on long rows, phase 1: partial F2 of every chunk of a vertex in X.
+template <bool B>
+__global__ __launch_bounds__(BLOCK) void k_lafter(KArgs a)
+{
+    if (!any_kind(a, KIND_LP)) return;
+    const int gl = threadIdx.x & 63;
+    GV pv;
+    if (!B) pv.at(a, 0);
+    const int nw = gridDim.x * (BLOCK / 64);
+    for (int i = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); i < a.nlch; i += nw) {
+        const LChunk ch = lchunk(a, i);
+        pv.sel<B>(a, gof<B>(a, ch.v));
+        if (pv.kind != KIND_LP) continue;
+        const int2 r = a.rec[ch.v];
+        if ((r.x & 0xFFFF) == 0) continue;  // not in X
+        const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
+        int part = after_sum_row<4>(a, ch.v, ch.s, ch.len, ps, pd, r.y, gl, 64);
+        part = gsum<64>(part);
+        if (gl == 0 && part) atomicAdd(&a.gf2[ch.li], part);
+    }
+}
+
+// Afterburner on long rows, phase 2 (one lane per vertex).
+template <bool B>
+__global__ __launch_bounds__(BLOCK) void k_lafter_fin(KArgs a)
+{
+    if (!any_kind(a, KIND_LP)) return;
+    const int nL = a.binoff[CLS_L + 1] - a.binoff[CLS_L];
+    GV pv;
+    if (!B) pv.at(a, 0);
+    for (int li = blockIdx.x * BLOCK + threadIdx.x; li < nL; li += gridDim.x * BLOCK) {
+        const int v = a.bins[a.binoff[CLS_L] + li];
+        pv.sel<B>(a, gof<B>(a, v));
+        if (pv.kind != KIND_LP) continue;
+        const int2 r = a.rec[v];
+        if ((r.x & 0xFFFF) == 0) continue;
+        const int sum = a.gf2[li];
+        a.gf2[li] = 0;
+        after_store(a, v, (r.x & 0xFFFF) - 1, sum);
+    }
+}
+
+template <bool B>
+__global__ __launch_bounds__(BLOCK) void k_ldcut(KArgs a)
+{
+    if (!any_active(a)) return;
+    const int gl = threadIdx.x & 63;
+    GV pv;
+    MoveAcc macc;
+    CutAcc cacc;
+    if (!B) {
+        pv.at(a, 0);
+        macc.to(a, 0);
+        cacc.to(a, 0);
+    }
+    const int nw = gridDim.x * (BLOCK / 64);
+    for (int i = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); i < a.nlch; i += nw) {
+        const LChunk ch = lchunk(a, i);
+        const int pn = a.dest[ch.v];
+        if (pn < 0) continue;
+        const int ps = a.P[ch.v];
+        int d = dcut_sum_row<4>(a, ch.v, ch.s, ch.len, ps, pn, gl, 64);
+        d = gsum<64>(d);
+        if (gl == 0) {
+            const int g = gof<B>(a, ch.v);
+            cacc.sel<B>(a, g);
+            cacc.c0 += (uint64_t)(int64_t)d;
+            if (a.lch[i].y == 0) {
+                pv.sel<B>(a, g);
+                macc.sel<B>(a, g);
+                move_meta(a, ch.v, ch.v - pv.voff, ps, pn, macc);
+            }
+        }
+    }
+    acc_finish(a, macc);
+    acc_finish(a, cacc);
+}
+
+// Set-up of the chunk list: chunks per L vertex, their exclusive scan (total
+// in lmeta[0]) and the list itself. ctot holds the class totals.
+__global__ __launch_bounds__(BLOCK) void k_lchunk_count(const int64_t *xadj, const int32_t *bins, const int32_t *ctot,
+                                                        int32_t *lcnt)
+{
+    const int off = ctot[CLS_Z] + ctot[CLS_S] + ctot[CLS_M], nL = ctot[CLS_L];
+    for (int li = blockIdx.x * BLOCK + threadIdx.x; li < nL; li += gridDim.x * BLOCK) {
+        const int v = bins[off + li];
+        lcnt[li] = (int)((xadj[v + 1] - xadj[v] + LCHUNK - 1) / LCHUNK);
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_lchunk_scan(const int32_t *ctot, int32_t *lcnt, int32_t *lmeta)
+{
+    __shared__ int32_t s_scan[BLOCK / 64];
+    const int nL = ctot[CLS_L];
+    int32_t carry = 0;
+    for (int b0 = 0; b0 < nL; b0 += BLOCK) {
+        const int i = b0 + threadIdx.x;
+        const int32_t x = i < nL ? lcnt[i] : 0;
+        int32_t tot;
+        const int32_t ex = block_excl_scan<BLOCK>(x, s_scan, tot);
+        if (i < nL) lcnt[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        lcnt[nL] = carry;
+        lmeta[0] = carry;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_lchunk_fill(const int32_t *ctot, const int32_t *lcoff, int2 *lch)
+{
+    const int nL = ctot[CLS_L];
+    for (int li = blockIdx.x * BLOCK + threadIdx.x; li < nL; li += gridDim.x * BLOCK)
+        for (int c = 0; c < lcoff[li + 1] - lcoff[li]; c++) lch[lcoff[li] + c] = make_int2(li, c);
 }
 
 // -------------------------------------------------------------- rebalance --
@@ -1433,7 +1727,7 @@ __device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nb
     }
 }
 
-template <bool B, int ROLE, int GS = 8>
+template <bool B, int ROLE, int GS = 8, int RS = 32 / GS>
 __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
 {
     extern __shared__ int32_t lds[];
@@ -1447,7 +1741,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
         racc.to(a, 0);
     }
     if (ROLE == 1) {
-        constexpr int RS_ = 32 / GS;
+        constexpr int RS_ = RS;
         const int ng = BLOCK / GS;
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         __syncthreads();
@@ -1455,7 +1749,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
         int32_t *q = lds + ng * stride + (threadIdx.x >> 6) * 64;
         const int wid = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nblk * (BLOCK / 64);
         for (int c = 1; c < NCLS; c++) {
-            if (a.tmap[c] != 1) continue;
+            if (a.tmap[c] != ROLE) continue;
             wave_batched<GS>(
                 a.bins + a.binoff[c], walk<B>(a.binoff[c + 1] - a.binoff[c], wid, nwaves, 64), q,
                 [&](Meta &m) -> bool {
@@ -1524,6 +1818,60 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
             const int ps = a.P[v];
             if (!rb_candidate(a, v, ps, a.vw ? a.vw[v] : 1, pv)) continue;
             rb_finish(a, v, ps, pv, 0, 0, 0, 0);
+            racc.sel<B>(a, g);
+            racc.c0++;
+        }
+    }
+    acc_finish(a, racc);
+}
+
+// Rebalancing loss on long rows, phase 2 (one wave per vertex).
+template <bool B>
+__global__ __launch_bounds__(BLOCK) void k_lrb_fin(KArgs a)
+{
+    if (!any_rb(a)) return;
+    const int gl = threadIdx.x & 63;
+    const int nL = a.binoff[CLS_L + 1] - a.binoff[CLS_L];
+    GV pv;
+    CountX racc;
+    if (!B) {
+        pv.at(a, 0);
+        racc.to(a, 0);
+    }
+    const int nw = gridDim.x * (BLOCK / 64);
+    for (int li = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); li < nL; li += nw) {
+        const int v = a.bins[a.binoff[CLS_L] + li];
+        const int g = gof<B>(a, v);
+        pv.sel<B>(a, g);
+        if (!is_rb(pv.kind)) continue;
+        const int ps = a.P[v];
+        const int vwv = a.vw ? a.vw[v] : 1;
+        if (!rb_is_candidate(a, ps, vwv, pv)) {
+            if (gl == 0) rb_candidate(a, v, ps, vwv, pv);  // writes the "no candidate" outputs
+            continue;
+        }
+        int32_t *row = a.gconn + (int64_t)li * a.lstride;
+        uint64_t best = 0;
+        int cs = 0, sumB = 0, cntB = 0;
+        for (int p = gl; p < pv.k; p += 64) {
+            const int c = row[p];
+            if (c) {
+                row[p] = 0;
+                if (p == ps) cs = c;
+                else if (a.isB[pv.poff + p]) {
+                    const uint64_t k2 = conn_key(c, p);
+                    best = k2 > best ? k2 : best;
+                    sumB += c;
+                    cntB++;
+                }
+            }
+        }
+        best = gmax_u64<64>(best);
+        cs = gsum<64>(cs);
+        sumB = gsum<64>(sumB);
+        cntB = gsum<64>(cntB);
+        if (gl == 0) {
+            rb_finish(a, v, ps, pv, best, cs, sumB, cntB);
             racc.sel<B>(a, g);
             racc.c0++;
         }
@@ -1900,7 +2248,7 @@ __global__ __launch_bounds__(BLOCK) void k_union_edges(const UDesc *d, int G, in
 
 // Result of each graph back into the caller's array: P_best, or P_iter for
 // graphs that asked for it.
-__global__ __launch_bounds__(BLOCK) void k_union_scatter(const UDesc *d, int G, int N, const int32_t *P,
+__global__ __launch_bounds__(BLOCK) void k_union_scatter(const UDesc *d, int G, int N, const uint16_t *P,
                                                          const int32_t *best)
 {
     int lo, hi;
@@ -1985,6 +2333,8 @@ struct Plan {
     int grid_tab, grid_plain, grid_rbtab;
     size_t lds_tab;
     int grid_flat, grid_tile, grid_hist;
+    int grid_lch;  // chunk kernels (0: no chunked rows)
+    int grid_lfin, nL;
     bool hist_lds;
 };
 
@@ -1993,6 +2343,7 @@ static int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cnt, Plan &pl)
 {
     const int maxb = ctx->num_cu * 8;
+    const bool chunked = a.nlch > 0;  // L rows go to the chunk kernels
     // LDS-table kernels: the small-row role keeps 32 or 64 tables of k ints,
     // the wave role 4, the block role 1; larger k moves classes to roles with
     // fewer tables so a block stays within 64 KiB of LDS.
@@ -2002,6 +2353,7 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
     if (k <= 495) { t.tmap[1] = 1; t.tmap[2] = 2; t.tmap[3] = 3; }
     else if (k <= 4095) { t.tmap[1] = 2; t.tmap[2] = 2; t.tmap[3] = 3; }
     else { t.tmap[1] = 3; t.tmap[2] = 3; t.tmap[3] = 3; }
+    if (chunked) t.tmap[3] = 0;
     int64_t role_cnt[4] = {0, 0, 0, 0};
     for (int c = 1; c < NCLS; c++) role_cnt[t.tmap[c]] += cnt[c];
     t.gS = std::min(div_up(role_cnt[1], BLOCK / 8), maxb);
@@ -2020,7 +2372,7 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
     p.tmap[0] = 0; p.tmap[1] = 1; p.tmap[2] = 2; p.tmap[3] = 3;
     p.gS = std::min(div_up(cnt[1], BLOCK / 8), maxb);
     p.gM = std::min(div_up(cnt[2], BLOCK / 64), maxb);
-    p.gL = std::min(cnt[3], maxb);
+    p.gL = chunked ? 0 : std::min(cnt[3], maxb);
     p.gZ = std::min(div_up(cnt[0], BLOCK), maxb);
     pl.grid_plain = p.gS + p.gM + p.gL + p.gZ;
     pl.tab = t;
@@ -2029,6 +2381,9 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
     pl.grid_hist = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_flat = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_tile = std::max(1, std::min(a.ntile, ctx->num_cu * 8));
+    pl.grid_lch = chunked ? std::max(1, std::min(div_up(a.nlch, BLOCK / 64), maxb)) : 0;
+    pl.nL = cnt[CLS_L];
+    pl.grid_lfin = chunked ? std::max(1, std::min(div_up(pl.nL, BLOCK / 64), maxb)) : 0;
 }
 
 // Up to this k the small-row role runs with 4 lanes per vertex (64 tables of
@@ -2046,6 +2401,21 @@ static void launch_gain_t(const Plan &pl, hipStream_t s)
     }
     if (t.gM) k_gain<B, 2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM);
     if (t.gL) k_gain<B, 3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL);
+    if (pl.grid_lch) {
+        k_lconn<B, false><<<pl.grid_lch, BLOCK, (BLOCK / 64) * st, s>>>(t);
+        k_lgain_fin<B><<<pl.grid_lfin, BLOCK, 0, s>>>(t);
+    }
+}
+
+template <bool B>
+static void launch_after_t(const Plan &pl, hipStream_t s)
+{
+    const KArgs &p = pl.plain;
+    if (pl.grid_plain) k_afterburner<B><<<pl.grid_plain, BLOCK, 0, s>>>(p);
+    if (pl.grid_lch) {
+        k_lafter<B><<<pl.grid_lch, BLOCK, 0, s>>>(p);
+        k_lafter_fin<B><<<std::max(1, div_up(pl.nL, BLOCK)), BLOCK, 0, s>>>(p);
+    }
 }
 
 template <bool B>
@@ -2060,6 +2430,10 @@ static void launch_rb_loss_t(const Plan &pl, hipStream_t s)
     if (t.gM) k_rb_loss<B, 2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM);
     if (t.gL) k_rb_loss<B, 3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL);
     if (t.gZ) k_rb_loss<B, 4><<<t.gZ, BLOCK, 0, s>>>(t, t.gZ);
+    if (pl.grid_lch) {
+        k_lconn<B, true><<<pl.grid_lch, BLOCK, (BLOCK / 64) * st, s>>>(t);
+        k_lrb_fin<B><<<pl.grid_lfin, BLOCK, 0, s>>>(t);
+    }
 }
 
 // Histogram, cut-off slots, ordered selection and (Jetrs) the cookie-cutter.
@@ -2083,10 +2457,11 @@ static void launch_iteration_t(const Plan &pl, hipStream_t s, hipEvent_t ev_a, h
     if (ev_a) (void)hipEventRecord(ev_a, s);
     launch_gain_t<B>(pl, s);
     if (ev_b) (void)hipEventRecord(ev_b, s);
-    if (pl.grid_plain) k_afterburner<B><<<pl.grid_plain, BLOCK, 0, s>>>(p);
+    launch_after_t<B>(pl, s);
     launch_rb_loss_t<B>(pl, s);
     launch_rb_select_t<B>(pl, s);
     if (pl.grid_plain) k_dcut<B><<<pl.grid_plain, BLOCK, 0, s>>>(p);
+    if (pl.grid_lch) k_ldcut<B><<<pl.grid_lch, BLOCK, 0, s>>>(p);
     k_apply<B><<<pl.grid_flat, BLOCK, B ? 0 : (size_t)p.k * 4, s>>>(p);
     k_ctl_end<<<pl.G, BLOCK, 0, s>>>(p);
 }
@@ -2097,6 +2472,11 @@ static void launch_gain(const Plan &pl, hipStream_t s)
 {
     if (batched(pl)) launch_gain_t<true>(pl, s);
     else launch_gain_t<false>(pl, s);
+}
+static void launch_after(const Plan &pl, hipStream_t s)
+{
+    if (batched(pl)) launch_after_t<true>(pl, s);
+    else launch_after_t<false>(pl, s);
 }
 static void launch_rb_loss(const Plan &pl, hipStream_t s)
 {
@@ -2133,6 +2513,8 @@ static void set_lds_limits_t()
     (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_apply<B>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_hist<B>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_lconn<B, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_lconn<B, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
 }
 
 static void set_lds_limits()
@@ -2262,7 +2644,7 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     a.tg = L.tg;
     const size_t nn = (size_t)std::max(n, 1);
     const size_t kt = (size_t)L.ktot;
-    a.P = (int32_t *)ws_get(ctx, WS_P, nn * 4);
+    a.P = (uint16_t *)ws_get(ctx, WS_P, nn * 2);
     a.rec = (int2 *)ws_get(ctx, WS_REC, nn * 8);
     a.dest = (int32_t *)ws_get(ctx, WS_DEST, nn * 4);
     a.lock = (int32_t *)ws_get(ctx, WS_LOCK, nn * 4);
@@ -2272,7 +2654,7 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     int32_t *bins = (int32_t *)ws_get(ctx, WS_BIN, nn * 4);
     a.bins = bins;
     a.bstat = (int64_t *)ws_get(ctx, WS_BSTAT, sizeof(int64_t) * NSTAT * NSHARD * (size_t)G);
-    a.cnt = (int32_t *)ws_get(ctx, WS_CNT, sizeof(int32_t) * CNT_N);
+    a.cnt = (int32_t *)ws_get(ctx, WS_CNT, sizeof(int32_t) * (CNT_N + 2));
     a.ctl = (Ctl *)ws_get(ctx, WS_CTL, sizeof(Ctl) * (size_t)G);
     int64_t *p64 = (int64_t *)ws_get(ctx, WS_PART64, sizeof(int64_t) * (4 * kt + G + 8));
     int32_t *p32 = (int32_t *)ws_get(ctx, WS_PART32, sizeof(int32_t) * (3 * kt + 8));
@@ -2312,20 +2694,30 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     JET_TRY(hipMemcpyAsync(a.ctl, hcs, sizeof(Ctl) * G, hipMemcpyHostToDevice, s));
     JET_TRY(hipMemsetAsync(a.w, 0, sizeof(int64_t) * kt, s));
     JET_TRY(hipMemsetAsync(a.bstat, 0, sizeof(int64_t) * NSTAT * NSHARD * (size_t)G, s));
-    JET_TRY(hipMemsetAsync(a.cnt, 0, sizeof(int32_t) * CNT_N, s));
+    JET_TRY(hipMemsetAsync(a.cnt, 0, sizeof(int32_t) * (CNT_N + 2), s));
     if (n > 0) k_init_vertices<<<grid_v, BLOCK, a.vg ? 0 : (size_t)a.k * 4, s>>>(a, L.part_in, blkcnt);
     if (L.u.nnz > 0) {
         const int grid_e = std::max(1, std::min(div_up(div_up(L.u.nnz, 16), BLOCK), ctx->num_cu * 8));
         k_init_edges<<<grid_e, BLOCK, 0, s>>>(a, L.u.nnz);
     }
     k_bin_scan<<<1, BLOCK, 0, s>>>(blkcnt, grid_v);
+    const int32_t *ctot = blkcnt + (size_t)grid_v * NCLS;  // class totals on the device
+    if (n > 0) k_fill_bins<<<grid_v, BLOCK, 0, s>>>(a, blkcnt, bins);
+    // chunks of the long (L class) rows: count and scan now, list after the sync
+    int32_t *lcnt = (int32_t *)ws_get(ctx, WS_LCNT, sizeof(int32_t) * (nn + 1));
+    if (!lcnt) return JET_ENOMEM;
+    int32_t *lmeta = a.cnt + CNT_N;  // total chunk count
+    if (n > 0) {
+        k_lchunk_count<<<grid_v, BLOCK, 0, s>>>(a.xadj, bins, ctot, lcnt);
+        k_lchunk_scan<<<1, BLOCK, 0, s>>>(ctot, lcnt, lmeta);
+    }
     k_init_reduce<<<G, 64, 0, s>>>(a);
     JET_TRY(hipGetLastError());
     int32_t *hcnt = (int32_t *)pin;             // CNT_N counts
     int32_t *htot = (int32_t *)(pin + 64);      // class totals
     int64_t *xends = (int64_t *)(pin + 128);    // first and last row offset (one graph)
     JET_TRY(hipMemcpyAsync(hcs, a.ctl, sizeof(Ctl) * G, hipMemcpyDeviceToHost, s));
-    JET_TRY(hipMemcpyAsync(hcnt, a.cnt, sizeof(int32_t) * CNT_N, hipMemcpyDeviceToHost, s));
+    JET_TRY(hipMemcpyAsync(hcnt, a.cnt, sizeof(int32_t) * (CNT_N + 1), hipMemcpyDeviceToHost, s));
     JET_TRY(hipMemcpyAsync(htot, blkcnt + (size_t)grid_v * NCLS, sizeof(int32_t) * NCLS, hipMemcpyDeviceToHost, s));
     JET_TRY(hipMemcpyAsync(xends, L.u.xadj, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     JET_TRY(hipMemcpyAsync(xends + 1, L.u.xadj + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -2348,7 +2740,24 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
         tot[c] = htot[c];
         a.binoff[c + 1] = a.binoff[c] + tot[c];
     }
-    if (n > 0) k_fill_bins<<<grid_v, BLOCK, 0, s>>>(a, blkcnt, bins);
+    // chunked long rows when their per-vertex connectivity rows fit in 512 MiB
+    const int nL = tot[CLS_L];
+    const int nch = hcnt[CNT_N];
+    if (nL > 0 && nch > 0 && (size_t)nL * (size_t)L.kmax * 4 <= ((size_t)512 << 20)) {
+        int2 *lch = (int2 *)ws_get(ctx, WS_LCH, sizeof(int2) * (size_t)nch);
+        int32_t *gconn = (int32_t *)ws_get(ctx, WS_GCONN, sizeof(int32_t) * (size_t)nL * L.kmax);
+        int32_t *ldone = (int32_t *)ws_get(ctx, WS_LDONE, sizeof(int32_t) * 2 * (size_t)nL);
+        if (!lch || !gconn || !ldone) return JET_ENOMEM;
+        JET_TRY(hipMemsetAsync(gconn, 0, sizeof(int32_t) * (size_t)nL * L.kmax, s));
+        JET_TRY(hipMemsetAsync(ldone, 0, sizeof(int32_t) * 2 * (size_t)nL, s));
+        k_lchunk_fill<<<grid_v, BLOCK, 0, s>>>(ctot, lcnt, lch);
+        a.lch = lch;
+        a.nlch = nch;
+        a.lstride = L.kmax;
+        a.gconn = gconn;
+        a.ldone = ldone;
+        a.gf2 = ldone + nL;
+    }
     a.it = 0;
     k_ctl_setup<<<G, BLOCK, 0, s>>>(a);
     JET_TRY(hipGetLastError());
@@ -2504,7 +2913,7 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     k_copy_best<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain);
     JET_TRY(hipEventRecord(ctx->ev[2], s));
     if (prm->flags & JET_F_RETURN_ITER)
-        JET_TRY(hipMemcpyAsync(part, pl.plain.P, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        k_copy_iter<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, part);
     if (part_weights_out)
         JET_TRY(hipMemcpyAsync(part_weights_out, (prm->flags & JET_F_RETURN_ITER) ? pl.plain.w : pl.plain.wbest,
                                sizeof(int64_t) * k, hipMemcpyDeviceToDevice, s));
@@ -2863,7 +3272,7 @@ extern "C" int jet_lp_step(jet_context *ctx, const jet_csr *g, const jet_params 
     k_step_defaults<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, part);
     k_force_step<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, KIND_LP, 0, locked);
     launch_gain(pl, s);
-    if (pl.grid_plain) k_afterburner<false><<<pl.grid_plain, BLOCK, 0, s>>>(pl.plain);
+    launch_after(pl, s);
     k_lp_outputs<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, inX, move);
     JET_TRY(hipGetLastError());
     JET_TRY(hipStreamSynchronize(s));

@@ -42,6 +42,27 @@ def star(nleaves):
     return I.csr_from_edges(nleaves + 1, np.zeros(nleaves, np.int64), np.arange(1, nleaves + 1))
 
 
+def stars(sizes, seed=5):
+    """Disjoint stars (centre degrees = sizes) joined by a sparse random ring of
+    leaves, so long rows cross chunk boundaries at 1024-entry multiples."""
+    us, vs, base = [], [], 0
+    for m in sizes:
+        us.append(np.full(m, base, np.int64))
+        vs.append(np.arange(base + 1, base + m + 1, dtype=np.int64))
+        base += m + 1
+    n = base
+    leaves = np.array([v for v in range(n) if v not in set(np.cumsum([0] + [m + 1 for m in sizes[:-1]]))], np.int64)
+    order = leaves[np.argsort(I.stream(seed, np.arange(leaves.size, dtype=np.uint64)), kind="stable")]
+    a, b = order[::7], np.roll(order[::7], 1)
+    keep = a != b
+    us.append(np.minimum(a[keep], b[keep]))
+    vs.append(np.maximum(a[keep], b[keep]))
+    u = np.concatenate(us)
+    v = np.concatenate(vs)
+    key = np.unique(u * n + v)
+    return I.csr_from_edges(n, key // n, key % n)
+
+
 def cases():
     """(name, graph, k, level) covering every kernel role."""
     out = [
@@ -54,6 +75,7 @@ def cases():
         ("rmat12_k600", I.rmat(12, 8, 7), 600, 0),
         ("rmat12_k5000", I.rmat(12, 8, 8), 5000, 0),
         ("star3000_k3", star(3000), 3, 0),
+        ("stars_chunks_k4", stars([1024, 1025, 2048, 2049, 4100]), 4, 0),
         ("rgg3000_k16", I.rgg(3000, 9), 16, 0),
     ]
     for s in range(6):
