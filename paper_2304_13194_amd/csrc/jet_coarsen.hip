@@ -957,6 +957,7 @@ extern "C" int jet_partition(jet_context *ctx, const jet_csr *g, const jet_param
                 jet_params q = *params;
                 q.level = i;
                 q.flags &= ~(uint32_t)JET_F_VALIDATE;
+                if (i > 0) q.flags &= ~(uint32_t)JET_F_PROFILE;  // only the finest level is profiled
                 jet_stats ls;
                 int32_t cnt = 0, tot = 0;
                 jet_trace_rec *recs = nullptr;

@@ -91,7 +91,7 @@ struct KArgs {
     int32_t *Blist, *sstar, *vthr;
     uint8_t *isA, *isB;
     int32_t *tsum;         // per graph: [k][ntiles] cut-off-slot weight per (part, tile)
-    int64_t *esum;         // per tile: Jetrs evicted weight, then its exclusive prefix in the graph
+    int64_t *esum;         // per tile: Jetrs evicted weight
     int32_t ntile;         // tiles (each inside one graph)
     jet_trace_rec *trace;
     int8_t *kinds;         // kind of iteration t of graph 0 (t < KIND_LOG)
@@ -136,6 +136,8 @@ struct jet_context {
     size_t pinned_bytes = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> prof_ev;  // pairs around gain passes (JET_F_PROFILE)
+    hipStream_t cap = nullptr;        // side stream on which iteration sequences are captured
+    bool graphs = true;               // replay captured iteration pairs (JET_NO_GRAPH=1 turns it off)
 };
 
 namespace jet {

@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 #include <limits.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -521,7 +522,6 @@ __global__ __launch_bounds__(BLOCK) void k_ctl_setup(KArgs a)
 __global__ __launch_bounds__(BLOCK) void k_ctl_end(KArgs a)
 {
     __shared__ uint64_t s_red[BLOCK / 64];
-    __shared__ int64_t s_red64[BLOCK / 64];
     __shared__ int s_improved, s_next;
     // this launch's count row has been read by every kernel of the iteration:
     // clear it for the iteration after next
@@ -537,29 +537,22 @@ __global__ __launch_bounds__(BLOCK) void k_ctl_end(KArgs a)
         m = x > m ? x : m;
     }
     m = block_max_u64<BLOCK>(m, s_red);
+    // the NSHARD shards of each counter row: one lane of the first wave each
     int64_t px = 0, pm = 0, pdc = 0, pmw = 0, pe = 0, pr = 0, pv = 0;
     uint64_t pdg = 0;
     if (threadIdx.x < NSHARD) {
         const int64_t *b = a.bstat + (int64_t)g * NSTAT * NSHARD + threadIdx.x;
-        px = b[ST_X * NSHARD];
-        pm = b[ST_M * NSHARD];
-        pdc = b[ST_DCUT * NSHARD];
-        pmw = b[ST_MW * NSHARD];
-        pdg = (uint64_t)b[ST_DIG * NSHARD];
+        px = gsum<NSHARD>(b[ST_X * NSHARD]);
+        pm = gsum<NSHARD>(b[ST_M * NSHARD]);
+        pdc = gsum<NSHARD>(b[ST_DCUT * NSHARD]);
+        pmw = gsum<NSHARD>(b[ST_MW * NSHARD]);
+        pdg = gsum<NSHARD>((uint64_t)b[ST_DIG * NSHARD]);
         if (kind == KIND_LP) {
-            pe = b[ST_E * NSHARD];
-            pr = b[ST_R * NSHARD];
-            pv = b[ST_V * NSHARD];
+            pe = gsum<NSHARD>(b[ST_E * NSHARD]);
+            pr = gsum<NSHARD>(b[ST_R * NSHARD]);
+            pv = gsum<NSHARD>(b[ST_V * NSHARD]);
         }
     }
-    px = block_sum<BLOCK>(px, s_red64);
-    pm = block_sum<BLOCK>(pm, s_red64);
-    pdc = block_sum<BLOCK>(pdc, s_red64);
-    pmw = block_sum<BLOCK>(pmw, s_red64);
-    pe = block_sum<BLOCK>(pe, s_red64);
-    pr = block_sum<BLOCK>(pr, s_red64);
-    pv = block_sum<BLOCK>(pv, s_red64);
-    pdg = block_sum<BLOCK>(pdg, s_red);
     if (threadIdx.x == 0) {
         // one load of the whole state, one store: no dependent global round trips
         Ctl cc = *c;
@@ -1896,15 +1889,29 @@ __global__ __launch_bounds__(BLOCK) void k_rb_hist(KArgs a, int use_lds)
     if (!B) pv.at(a, 0);
     int lo, hi;
     block_chunk(a.n, blockIdx.x, gridDim.x, lo, hi);
-    for (int v = lo + threadIdx.x; v < hi; v += BLOCK) {
-        const int sl = a.slot[v];
-        if (sl == 255) continue;
-        pv.sel<B>(a, gof<B>(a, v));
-        if (!is_rb(pv.kind)) continue;  // a slot left from an earlier iteration
-        const int idx = (pv.poff + a.P[v]) * NSLOT + sl;
-        const int vwv = a.vw ? a.vw[v] : 1;
-        if (use_lds) atomicAdd(&h[idx], vwv);
-        else atomicAdd((unsigned long long *)&a.hist[idx], (unsigned long long)(int64_t)vwv);
+    constexpr int U = 4;
+    for (int base = lo + threadIdx.x; base < hi; base += BLOCK * U) {
+        int sl[U], pp[U], ww[U];
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            const int v = base + j * BLOCK;
+            sl[j] = v < hi ? a.slot[v] : 255;
+        }
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            const int v = base + j * BLOCK;
+            pp[j] = sl[j] != 255 ? a.P[v] : 0;
+            ww[j] = sl[j] != 255 ? (a.vw ? a.vw[v] : 1) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            if (sl[j] == 255) continue;
+            pv.sel<B>(a, gof<B>(a, base + j * BLOCK));
+            if (!is_rb(pv.kind)) continue;  // a slot left from an earlier iteration
+            const int idx = (pv.poff + pp[j]) * NSLOT + sl[j];
+            if (use_lds) atomicAdd(&h[idx], ww[j]);
+            else atomicAdd((unsigned long long *)&a.hist[idx], (unsigned long long)(int64_t)ww[j]);
+        }
     }
     if (use_lds) {
         __syncthreads();
@@ -1931,16 +1938,18 @@ __global__ __launch_bounds__(BLOCK) void k_rb_cutoff(KArgs a)
         int64_t res = 0;
         if (a.isA[gp]) {
             const int64_t need = a.w[gp] - o;
+            int64_t hv[NSLOT];
+#pragma unroll
+            for (int s = 0; s < NSLOT; s++) hv[s] = a.hist[(int64_t)gp * NSLOT + s];
             int64_t cum = 0;
             ss = NSLOT;
+#pragma unroll
             for (int s = 0; s < NSLOT; s++) {
-                const int64_t hv = a.hist[(int64_t)gp * NSLOT + s];
-                if (cum + hv >= need) {
+                if (ss == NSLOT && cum + hv[s] >= need) {
                     ss = s;
                     res = need - cum;
-                    break;
                 }
-                cum += hv;
+                cum += hv[s];
             }
         }
         a.sstar[gp] = ss;
@@ -1992,11 +2001,21 @@ __global__ __launch_bounds__(BLOCK) void k_rb_tilesum(KArgs a)
         const int k = c->k, poff = c->poff, ntl = c->ntiles;
         for (int p = threadIdx.x; p < k; p += BLOCK) acc[p] = 0;
         __syncthreads();
-        for (int v = v0 + threadIdx.x; v < v1; v += BLOCK) {
-            const int sl = a.slot[v];
-            if (sl == 255) continue;
-            const int p = a.P[v];
-            if (sl == a.sstar[poff + p]) atomicAdd(&acc[p], a.vw ? a.vw[v] : 1);
+        {
+            int sl[PER], pp[PER], ss[PER];
+#pragma unroll
+            for (int j = 0; j < PER; j++) {
+                const int v = v0 + threadIdx.x + j * BLOCK;
+                sl[j] = v < v1 ? a.slot[v] : 255;
+            }
+#pragma unroll
+            for (int j = 0; j < PER; j++) pp[j] = sl[j] != 255 ? a.P[v0 + threadIdx.x + j * BLOCK] : 0;
+#pragma unroll
+            for (int j = 0; j < PER; j++) ss[j] = sl[j] != 255 ? a.sstar[poff + pp[j]] : -1;
+#pragma unroll
+            for (int j = 0; j < PER; j++)
+                if (sl[j] != 255 && sl[j] == ss[j])
+                    atomicAdd(&acc[pp[j]], a.vw ? a.vw[v0 + threadIdx.x + j * BLOCK] : 1);
         }
         __syncthreads();
         int32_t *row = a.tsum + c->rowbase + lt;
@@ -2089,14 +2108,24 @@ __global__ __launch_bounds__(BLOCK) void k_rb_mark(KArgs a)
         if (!is_rb(kind)) continue;
         const int poff = c->poff;
         int64_t es = 0;
-        for (int v = v0 + threadIdx.x; v < v1; v += BLOCK) {
-            const int sl = a.slot[v];
-            bool ev = false;
-            if (sl != 255) {
-                const int gp = poff + a.P[v];
-                const int ss = a.sstar[gp];
-                ev = sl < ss || (sl == ss && v <= a.vthr[gp]);
-            }
+        int sl[PER], gp[PER], ss[PER], th[PER];
+#pragma unroll
+        for (int j = 0; j < PER; j++) {
+            const int v = v0 + threadIdx.x + j * BLOCK;
+            sl[j] = v < v1 ? a.slot[v] : 255;
+        }
+#pragma unroll
+        for (int j = 0; j < PER; j++) gp[j] = sl[j] != 255 ? poff + a.P[v0 + threadIdx.x + j * BLOCK] : -1;
+#pragma unroll
+        for (int j = 0; j < PER; j++) {
+            ss[j] = gp[j] >= 0 ? a.sstar[gp[j]] : -1;
+            th[j] = gp[j] >= 0 ? a.vthr[gp[j]] : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < PER; j++) {
+            const int v = v0 + threadIdx.x + j * BLOCK;
+            if (v >= v1) continue;
+            const bool ev = sl[j] != 255 && (sl[j] < ss[j] || (sl[j] == ss[j] && v <= th[j]));
             if (kind == KIND_RW) {
                 if (ev) a.dest[v] = a.rbd[v];
             } else {
@@ -2111,26 +2140,6 @@ __global__ __launch_bounds__(BLOCK) void k_rb_mark(KArgs a)
     }
 }
 
-// Jetrs, per graph (one block each): exclusive scan of the evicted weight
-// over the graph's tiles.
-__global__ __launch_bounds__(BLOCK) void k_rs_scan(KArgs a)
-{
-    __shared__ int64_t s_scan[BLOCK / 64];
-    const Ctl *c = a.ctl + blockIdx.x;
-    if (c->kind != KIND_RS) return;
-    int64_t *e = a.esum + c->t0;
-    const int ntl = c->ntiles;
-    int64_t carry = 0;
-    for (int base = 0; base < ntl; base += BLOCK) {
-        const int i = base + threadIdx.x;
-        const int64_t x = i < ntl ? e[i] : 0;
-        int64_t tot;
-        const int64_t ex = block_excl_scan<BLOCK>(x, s_scan, tot);
-        if (i < ntl) e[i] = carry + ex;
-        carry += tot;
-    }
-}
-
 // Jetrs cookie-cutter (one block per tile, PER consecutive vertices per
 // thread): evicted vertices in id order take consecutive positions (exclusive
 // prefix of their weights); position pos goes to the valid destination whose
@@ -2139,6 +2148,7 @@ __global__ __launch_bounds__(BLOCK) void k_rs_scan(KArgs a)
 __global__ __launch_bounds__(BLOCK) void k_rs_assign(KArgs a)
 {
     __shared__ int64_t s_scan[BLOCK / 64];
+    __shared__ int64_t s_red[BLOCK / 64];
     if (!any_kind(a, KIND_RS)) return;
     for (int tile = blockIdx.x; tile < a.ntile; tile += gridDim.x) {
         int lt, v0, v1;
@@ -2157,8 +2167,12 @@ __global__ __launch_bounds__(BLOCK) void k_rs_assign(KArgs a)
             wv[q] = (v < v1 && a.rsev[v]) ? (a.vw ? a.vw[v] : 1) : 0;
             mine += wv[q];
         }
+        // evicted weight of the graph's earlier tiles
+        int64_t before = 0;
+        for (int t = c->t0 + threadIdx.x; t < tile; t += BLOCK) before += a.esum[t];
+        before = block_sum<BLOCK>(before, s_red);
         int64_t tot;
-        int64_t pos = a.esum[tile] + block_excl_scan<BLOCK>(mine, s_scan, tot);
+        int64_t pos = before + block_excl_scan<BLOCK>(mine, s_scan, tot);
 #pragma unroll
         for (int q = 0; q < PER; q++) {
             if (wv[q] > 0 && pos < total) {
@@ -2446,7 +2460,6 @@ static void launch_rb_select_t(const Plan &pl, hipStream_t s)
     k_rb_tilesum<<<pl.grid_tile, BLOCK, (size_t)p.k * 4, s>>>(p);
     k_rb_split<<<std::min(p.ktot, 1024), BLOCK, 0, s>>>(p);
     k_rb_mark<<<pl.grid_tile, BLOCK, 0, s>>>(p);
-    k_rs_scan<<<pl.G, BLOCK, 0, s>>>(p);
     k_rs_assign<<<pl.grid_tile, BLOCK, 0, s>>>(p);
 }
 
@@ -2769,12 +2782,57 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
 }
 
 // Iterates until every graph is done: chunks of iterations, one sync each.
+// Two consecutive iterations (launch indices of both parities) captured once
+// as a HIP graph: kernels read only the parity of the launch index, so one
+// pair replays any number of times. Replaying costs the host far less than
+// enqueuing the ~15 kernels of every iteration one by one. The capture holds
+// kernel launches only (no memset or copy nodes).
+struct IterGraph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    ~IterGraph()
+    {
+        if (x) (void)hipGraphExecDestroy(x);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
+static int capture_pair(jet_context *ctx, Plan &pl, IterGraph &ig)
+{
+    JET_TRY(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < 2; i++) {
+        set_it(pl, i);
+        launch_iteration(pl, ctx->cap);
+    }
+    const hipError_t e = hipStreamEndCapture(ctx->cap, &ig.g);
+    if (e != hipSuccess) {
+        ig.g = nullptr;
+        return hip_status(ctx, e);
+    }
+    JET_TRY(hipGraphInstantiate(&ig.x, ig.g, nullptr, nullptr, 0));
+    return JET_OK;
+}
+
 static int run_loop(jet_context *ctx, Plan &pl, bool prof, hipStream_t s, int &launched)
 {
     int32_t *pin = (int32_t *)pinned_get(ctx, 4096);
     if (!pin) return JET_ENOMEM;
     int chunk = 4;
     launched = 0;
+    if (!prof && ctx->graphs && ctx->cap) {
+        IterGraph ig;
+        int st = capture_pair(ctx, pl, ig);
+        if (st) return st;
+        for (;;) {
+            for (int i = 0; i < chunk; i += 2) JET_TRY(hipGraphLaunch(ig.x, s));
+            launched += chunk;
+            JET_TRY(hipMemcpyAsync(pin, pl.plain.cnt + CNT_DONE, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            JET_TRY(hipStreamSynchronize(s));
+            if (pin[0] >= pl.G) break;
+            chunk = std::min(chunk * 2, 32);
+        }
+        return JET_OK;
+    }
     for (;;) {
         for (int i = 0; i < chunk; i++) {
             hipEvent_t ea = nullptr, eb = nullptr;
@@ -3161,6 +3219,14 @@ extern "C" int jet_context_create(jet_context **out, int device)
         delete ctx;
         return JET_ENOMEM;
     }
+    const char *ng = getenv("JET_NO_GRAPH");
+    ctx->graphs = !(ng && ng[0] == '1');
+    e = hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        int st = hip_status(ctx, e);
+        jet_context_destroy(ctx);
+        return st;
+    }
     for (auto &ev : ctx->ev) {
         e = hipEventCreate(&ev);
         if (e != hipSuccess) {
@@ -3183,6 +3249,7 @@ extern "C" void jet_context_destroy(jet_context *ctx)
     for (auto &ev : ctx->ev)
         if (ev) (void)hipEventDestroy(ev);
     for (auto ev : ctx->prof_ev) (void)hipEventDestroy(ev);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;
 }
 
