@@ -2774,8 +2774,8 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     a.it = 0;
     k_ctl_setup<<<G, BLOCK, 0, s>>>(a);
     JET_TRY(hipGetLastError());
-    // the host copy must outlive the upload: wait before the staging is reused
-    JET_TRY(hipStreamSynchronize(s));
+    // no wait here: the staging area of the upload is next written by the
+    // final state read-back, ordered after it on the same stream
     pl.G = G;
     plan_roles(ctx, a, tot, pl);
     return JET_OK;
@@ -2823,6 +2823,7 @@ static int run_loop(jet_context *ctx, Plan &pl, bool prof, hipStream_t s, int &l
         IterGraph ig;
         int st = capture_pair(ctx, pl, ig);
         if (st) return st;
+        chunk = 8;
         for (;;) {
             for (int i = 0; i < chunk; i += 2) JET_TRY(hipGraphLaunch(ig.x, s));
             launched += chunk;
@@ -2858,14 +2859,19 @@ static int run_loop(jet_context *ctx, Plan &pl, bool prof, hipStream_t s, int &l
     return JET_OK;
 }
 
-// Final controller states into L.hc (after the loop).
+// Final controller states: the read-back is enqueued here and lands in
+// L.hc at take_state, after the caller's one synchronisation.
 static int read_state(jet_context *ctx, Launch &L, const Plan &pl, hipStream_t s)
 {
     Ctl *hcs = (Ctl *)((char *)pinned_get(ctx, 4096 + sizeof(Ctl) * (size_t)L.G) + 4096);
     JET_TRY(hipMemcpyAsync(hcs, pl.plain.ctl, sizeof(Ctl) * L.G, hipMemcpyDeviceToHost, s));
-    JET_TRY(hipStreamSynchronize(s));
-    memcpy(L.hc.data(), hcs, sizeof(Ctl) * L.G);
     return JET_OK;
+}
+
+static void take_state(jet_context *ctx, Launch &L)
+{
+    const Ctl *hcs = (const Ctl *)((const char *)ctx->pinned + 4096);
+    memcpy(L.hc.data(), hcs, sizeof(Ctl) * L.G);
 }
 
 static void fill_stats(jet_stats *st, const Ctl &c, bool ret_iter)
@@ -2977,12 +2983,15 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
                                sizeof(int64_t) * k, hipMemcpyDeviceToDevice, s));
     st = read_state(ctx, L, pl, s);
     if (st) return st;
-    const Ctl &hc = L.hc[0];
-    const int ntr = std::min(hc.t, hc.trace_cap);
-    if (trace_dev && ntr > 0)
-        JET_TRY(hipMemcpyAsync(trace_host, trace_dev, sizeof(jet_trace_rec) * ntr, hipMemcpyDeviceToHost, s));
+    // records exist for the iterations run, at most one per launched iteration
+    const int ncopy = std::min(launched, L.hc[0].trace_cap);
+    if (trace_dev && ncopy > 0)
+        JET_TRY(hipMemcpyAsync(trace_host, trace_dev, sizeof(jet_trace_rec) * ncopy, hipMemcpyDeviceToHost, s));
     JET_TRY(hipEventRecord(ctx->ev[3], s));
     JET_TRY(hipStreamSynchronize(s));
+    take_state(ctx, L);
+    const Ctl &hc = L.hc[0];
+    const int ntr = std::min(hc.t, hc.trace_cap);
     if (trace_count) *trace_count = ntr;
     if (trace_total) *trace_total = hc.t;
     float ms_gain = 0.f;
@@ -3165,17 +3174,22 @@ int refine_batch(jet_context *ctx, int count, const jet_csr *graphs, const jet_p
     if (st) return st;
     if (traces)
         for (int j = 0; j < G; j++) {
-            jet_trace &tr = traces[act[j]];
-            const Ctl &c = L.hc[j];
-            const int ntr = std::min(c.t, c.trace_cap);
-            if (ntr > 0)
-                JET_TRY(hipMemcpyAsync(tr.recs, trace_dev + c.trace_off, sizeof(jet_trace_rec) * ntr,
+            const Ctl &c = L.hc[j];  // configuration: trace offset and capacity
+            const int ncopy = std::min(launched, c.trace_cap);
+            if (ncopy > 0)
+                JET_TRY(hipMemcpyAsync(traces[act[j]].recs, trace_dev + c.trace_off, sizeof(jet_trace_rec) * ncopy,
                                        hipMemcpyDeviceToHost, s));
-            tr.count = ntr;
-            tr.total = c.t;
         }
     JET_TRY(hipEventRecord(ctx->ev[3], s));
     JET_TRY(hipStreamSynchronize(s));
+    take_state(ctx, L);
+    if (traces)
+        for (int j = 0; j < G; j++) {
+            jet_trace &tr = traces[act[j]];
+            const Ctl &c = L.hc[j];
+            tr.count = std::min(c.t, c.trace_cap);
+            tr.total = c.t;
+        }
     if (stats) {
         float ms_total = 0, ms_refine = 0, ms_init = 0;
         (void)hipEventElapsedTime(&ms_total, ctx->ev[0], ctx->ev[3]);
