@@ -216,6 +216,20 @@ __device__ __forceinline__ void block_chunk(int cnt, int b, int nb, int &lo, int
     hi = (int)(l + chunk < cnt ? l + chunk : cnt);
 }
 
+// Range of the per-vertex passes: one graph walks its vertex ids; a batch
+// walks its class lists, which hold only the vertices of graphs still
+// running once they have been compacted.
+template <bool B>
+__device__ __forceinline__ void flat_range(const KArgs &a, int &lo, int &hi)
+{
+    block_chunk(B ? a.binoff[NCLS] : a.n, blockIdx.x, gridDim.x, lo, hi);
+}
+template <bool B>
+__device__ __forceinline__ int flat_vertex(const KArgs &a, int i)
+{
+    return B ? a.bins[i] : i;
+}
+
 __device__ __forceinline__ int degree_class(int64_t d)
 {
     return d == 0 ? CLS_Z : (d <= S_MAXDEG ? CLS_S : (d <= M_MAXDEG ? CLS_M : CLS_L));
@@ -375,6 +389,51 @@ __global__ __launch_bounds__(BLOCK) void k_fill_bins(KArgs a, const int32_t *blk
         const int v = base + threadIdx.x;
         int cls = -1;
         if (v < hi) cls = degree_class(a.xadj[v + 1] - a.xadj[v]);
+#pragma unroll
+        for (int c = 0; c < NCLS; c++) {
+            int32_t tot;
+            const int32_t pos = block_excl_scan<BLOCK>((int32_t)(cls == c), s_scan, tot);
+            if (cls == c) bins[run[c] + pos] = v;
+            run[c] += tot;
+        }
+    }
+}
+
+// Batch compaction: class counts and ordered class lists of the vertices of
+// graphs still running (same grid and ranges in both kernels).
+__global__ __launch_bounds__(BLOCK) void k_bin_count_active(KArgs a, int32_t *blkcnt)
+{
+    __shared__ int32_t s_cls[NCLS];
+    if (threadIdx.x < NCLS) s_cls[threadIdx.x] = 0;
+    __syncthreads();
+    GV gv;
+    int lo, hi;
+    block_chunk(a.n, blockIdx.x, gridDim.x, lo, hi);
+    for (int v = lo + threadIdx.x; v < hi; v += BLOCK) {
+        gv.at(a, graph_of(a, v));
+        if (gv.kind == KIND_DONE) continue;
+        atomicAdd(&s_cls[degree_class(a.xadj[v + 1] - a.xadj[v])], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < NCLS) blkcnt[blockIdx.x * NCLS + threadIdx.x] = s_cls[threadIdx.x];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fill_bins_active(KArgs a, const int32_t *blkoff, int32_t *bins)
+{
+    __shared__ int32_t s_scan[BLOCK / 64];
+    GV gv;
+    int lo, hi;
+    block_chunk(a.n, blockIdx.x, gridDim.x, lo, hi);
+    int32_t run[NCLS];
+#pragma unroll
+    for (int c = 0; c < NCLS; c++) run[c] = blkoff[blockIdx.x * NCLS + c];
+    for (int base = lo; base < hi; base += BLOCK) {
+        const int v = base + threadIdx.x;
+        int cls = -1;
+        if (v < hi) {
+            gv.at(a, graph_of(a, v));
+            if (gv.kind != KIND_DONE) cls = degree_class(a.xadj[v + 1] - a.xadj[v]);
+        }
 #pragma unroll
         for (int c = 0; c < NCLS; c++) {
             int32_t tot;
@@ -1194,8 +1253,9 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
         // graphs whose previous iteration improved the best partition: copy
         // P_iter before this iteration's moves are applied
         int lo, hi;
-        block_chunk(a.n, blockIdx.x, gridDim.x, lo, hi);
-        for (int v = lo + threadIdx.x; v < hi; v += BLOCK) {
+        flat_range<B>(a, lo, hi);
+        for (int i = lo + threadIdx.x; i < hi; i += BLOCK) {
+            const int v = flat_vertex<B>(a, i);
             pv.sel<B>(a, gof<B>(a, v));
             if (pv.copy && pv.kind != KIND_DONE) a.best[v] = a.P[v];
         }
@@ -1311,8 +1371,9 @@ __global__ __launch_bounds__(BLOCK) void k_apply(KArgs a)
     GV pv;
     if (!B) pv.at(a, 0);
     int lo, hi;
-    block_chunk(a.n, blockIdx.x, gridDim.x, lo, hi);
-    for (int v = lo + threadIdx.x; v < hi; v += BLOCK) {
+    flat_range<B>(a, lo, hi);
+    for (int i = lo + threadIdx.x; i < hi; i += BLOCK) {
+        const int v = flat_vertex<B>(a, i);
         const int pn = a.dest[v];
         if (pn < 0) continue;
         pv.sel<B>(a, gof<B>(a, v));
@@ -1888,25 +1949,26 @@ __global__ __launch_bounds__(BLOCK) void k_rb_hist(KArgs a, int use_lds)
     GV pv;
     if (!B) pv.at(a, 0);
     int lo, hi;
-    block_chunk(a.n, blockIdx.x, gridDim.x, lo, hi);
+    flat_range<B>(a, lo, hi);
     constexpr int U = 4;
     for (int base = lo + threadIdx.x; base < hi; base += BLOCK * U) {
-        int sl[U], pp[U], ww[U];
+        int vv[U], sl[U], pp[U], ww[U];
 #pragma unroll
         for (int j = 0; j < U; j++) {
-            const int v = base + j * BLOCK;
-            sl[j] = v < hi ? a.slot[v] : 255;
+            const int i = base + j * BLOCK;
+            vv[j] = i < hi ? flat_vertex<B>(a, i) : -1;
         }
 #pragma unroll
+        for (int j = 0; j < U; j++) sl[j] = vv[j] >= 0 ? a.slot[vv[j]] : 255;
+#pragma unroll
         for (int j = 0; j < U; j++) {
-            const int v = base + j * BLOCK;
-            pp[j] = sl[j] != 255 ? a.P[v] : 0;
-            ww[j] = sl[j] != 255 ? (a.vw ? a.vw[v] : 1) : 0;
+            pp[j] = sl[j] != 255 ? a.P[vv[j]] : 0;
+            ww[j] = sl[j] != 255 ? (a.vw ? a.vw[vv[j]] : 1) : 0;
         }
 #pragma unroll
         for (int j = 0; j < U; j++) {
             if (sl[j] == 255) continue;
-            pv.sel<B>(a, gof<B>(a, base + j * BLOCK));
+            pv.sel<B>(a, gof<B>(a, vv[j]));
             if (!is_rb(pv.kind)) continue;  // a slot left from an earlier iteration
             const int idx = (pv.poff + pp[j]) * NSLOT + sl[j];
             if (use_lds) atomicAdd(&h[idx], ww[j]);
@@ -2349,6 +2411,9 @@ struct Plan {
     int grid_flat, grid_tile, grid_hist;
     int grid_lch;  // chunk kernels (0: no chunked rows)
     int grid_lfin, nL;
+    int grid_v;              // grid of the list-building kernels
+    int32_t *blkcnt, *lcnt;  // their scratch
+    int32_t *bins;
     bool hist_lds;
 };
 
@@ -2778,6 +2843,54 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     // final state read-back, ordered after it on the same stream
     pl.G = G;
     plan_roles(ctx, a, tot, pl);
+    pl.grid_v = grid_v;
+    pl.blkcnt = blkcnt;
+    pl.lcnt = lcnt;
+    pl.bins = bins;
+    return JET_OK;
+}
+
+// Batch compaction: rebuilds the class lists (and the long-row chunk list)
+// from the vertices of graphs still running, then re-plans the roles. Called
+// between chunks of iterations, when nothing is in flight on the stream.
+static int compact_lists(jet_context *ctx, Plan &pl, hipStream_t s)
+{
+    KArgs a = pl.plain;
+    const int gv = pl.grid_v;
+    const int32_t *ctot = pl.blkcnt + (size_t)gv * NCLS;
+    k_bin_count_active<<<gv, BLOCK, 0, s>>>(a, pl.blkcnt);
+    k_bin_scan<<<1, BLOCK, 0, s>>>(pl.blkcnt, gv);
+    k_fill_bins_active<<<gv, BLOCK, 0, s>>>(a, pl.blkcnt, pl.bins);
+    int32_t *lmeta = a.cnt + CNT_N;
+    if (a.nlch > 0) {
+        k_lchunk_count<<<gv, BLOCK, 0, s>>>(a.xadj, pl.bins, ctot, pl.lcnt);
+        k_lchunk_scan<<<1, BLOCK, 0, s>>>(ctot, pl.lcnt, lmeta);
+    }
+    JET_TRY(hipGetLastError());
+    int32_t *pin = (int32_t *)pinned_get(ctx, 4096);
+    JET_TRY(hipMemcpyAsync(pin + 16, ctot, sizeof(int32_t) * NCLS, hipMemcpyDeviceToHost, s));
+    if (a.nlch > 0) JET_TRY(hipMemcpyAsync(pin + 24, lmeta, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    JET_TRY(hipStreamSynchronize(s));
+    int32_t tot[NCLS];
+    a.binoff[0] = 0;
+    for (int c = 0; c < NCLS; c++) {
+        tot[c] = pin[16 + c];
+        a.binoff[c + 1] = a.binoff[c] + tot[c];
+    }
+    if (a.nlch > 0) {
+        // never more chunks than at set-up, so the list and rows keep their room
+        a.nlch = pin[24];
+        if (a.nlch > 0) k_lchunk_fill<<<gv, BLOCK, 0, s>>>(ctot, pl.lcnt, (int2 *)a.lch);
+        else a.lch = nullptr;
+        JET_TRY(hipGetLastError());
+    }
+    const int grid_v = pl.grid_v;
+    int32_t *blkcnt = pl.blkcnt, *lcnt = pl.lcnt, *bins = pl.bins;
+    plan_roles(ctx, a, tot, pl);
+    pl.grid_v = grid_v;
+    pl.blkcnt = blkcnt;
+    pl.lcnt = lcnt;
+    pl.bins = bins;
     return JET_OK;
 }
 
@@ -2790,11 +2903,14 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
 struct IterGraph {
     hipGraph_t g = nullptr;
     hipGraphExec_t x = nullptr;
-    ~IterGraph()
+    void reset()
     {
         if (x) (void)hipGraphExecDestroy(x);
         if (g) (void)hipGraphDestroy(g);
+        x = nullptr;
+        g = nullptr;
     }
+    ~IterGraph() { reset(); }
 };
 
 static int capture_pair(jet_context *ctx, Plan &pl, IterGraph &ig)
@@ -2819,6 +2935,17 @@ static int run_loop(jet_context *ctx, Plan &pl, bool prof, hipStream_t s, int &l
     if (!pin) return JET_ENOMEM;
     int chunk = 4;
     launched = 0;
+    // a batch drops the vertices of finished graphs from its lists whenever
+    // the number of running graphs has halved since the last rebuild
+    int running_at_build = pl.G;
+    auto maybe_compact = [&](int done, bool &rebuilt) -> int {
+        rebuilt = false;
+        const int running = pl.G - done;
+        if (pl.G == 1 || running <= 0 || 2 * running > running_at_build) return JET_OK;
+        running_at_build = running;
+        rebuilt = true;
+        return compact_lists(ctx, pl, s);
+    };
     if (!prof && ctx->graphs && ctx->cap) {
         IterGraph ig;
         int st = capture_pair(ctx, pl, ig);
@@ -2830,6 +2957,14 @@ static int run_loop(jet_context *ctx, Plan &pl, bool prof, hipStream_t s, int &l
             JET_TRY(hipMemcpyAsync(pin, pl.plain.cnt + CNT_DONE, sizeof(int32_t), hipMemcpyDeviceToHost, s));
             JET_TRY(hipStreamSynchronize(s));
             if (pin[0] >= pl.G) break;
+            bool rebuilt = false;
+            st = maybe_compact(pin[0], rebuilt);
+            if (st) return st;
+            if (rebuilt) {
+                ig.reset();
+                st = capture_pair(ctx, pl, ig);
+                if (st) return st;
+            }
             chunk = std::min(chunk * 2, 32);
         }
         return JET_OK;
@@ -2854,6 +2989,9 @@ static int run_loop(jet_context *ctx, Plan &pl, bool prof, hipStream_t s, int &l
         JET_TRY(hipMemcpyAsync(pin, pl.plain.cnt + CNT_DONE, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         JET_TRY(hipStreamSynchronize(s));
         if (pin[0] >= pl.G) break;
+        bool rebuilt = false;
+        const int st = maybe_compact(pin[0], rebuilt);
+        if (st) return st;
         chunk = std::min(chunk * 2, 32);
     }
     return JET_OK;
