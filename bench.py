@@ -119,44 +119,7 @@ def _gen_rgg(args):
 
 def _gen_pool_graph(spec):
     from paper_2304_13194_amd import inputs as I
-    if spec[0] == "grid":
-        return I.grid2d(spec[1], spec[1])
-    return I.rmat(spec[1], spec[2], spec[3])
-
-
-def rgg_batch_spec(count=512, nmin=1000, nmax=200000, seed=77):
-    """n log-uniform on [nmin, nmax], k uniform in {2, 4, ..., 128}, seeds."""
-    import numpy as np
-    from paper_2304_13194_amd import inputs as I
-    u = I.stream(seed, np.arange(2 * count, dtype=np.uint64))
-    frac = (u[:count] >> np.uint64(11)).astype(np.float64) / float(1 << 53)
-    ns = np.exp(np.log(nmin) + (np.log(nmax) - np.log(nmin)) * frac).astype(np.int64)
-    ks = np.array([2, 4, 8, 16, 32, 64, 128])[I.uniform_below(u[count:], 7)]
-    return [(int(ns[i]), int(ks[i]), seed * 100003 + i) for i in range(count)]
-
-
-SERVE_POOL = [("grid", 64), ("grid", 128), ("grid", 256), ("grid", 512), ("grid", 1024),
-              ("rmat", 12, 8, 41), ("rmat", 14, 16, 42), ("rmat", 16, 8, 43), ("rmat", 18, 16, 44),
-              ("rmat", 20, 16, 45)]
-
-
-def serve_jobs(count, seed=99):
-    """(pool index, k uniform in [2, 256], seed) per job."""
-    import numpy as np
-    from paper_2304_13194_amd import inputs as I
-    u = I.stream(seed, np.arange(2 * count, dtype=np.uint64))
-    gi = I.uniform_below(u[:count], len(SERVE_POOL))
-    ks = 2 + I.uniform_below(u[count:], 255)
-    return [(int(gi[i]), int(ks[i]), 1000 + i) for i in range(count)]
-
-
-def arrivals(rate, count, seed):
-    """Poisson process: exponential gaps of mean 1/rate (seeded)."""
-    import numpy as np
-    from paper_2304_13194_amd import inputs as I
-    u = (I.stream(seed, np.arange(count, dtype=np.uint64)) >> np.uint64(11)).astype(np.float64) / float(1 << 53)
-    gaps = -np.log1p(-u) / rate
-    return np.cumsum(gaps) - gaps[0]
+    return I.serve_pool_graph(spec)
 
 
 # -------------------------------------------------------------- sub-benches --
@@ -215,7 +178,8 @@ def serve_bench(J, pool, jobs, rates=(50, 200, 1000, 2000)):
     """Poisson arrivals into jet_server vs the same jobs one at a time."""
     import numpy as np
     import torch
-    dgs = [J.to_device(g, unit_vwgt=(s[0] == "grid"), unit_adjwgt=(s[0] == "grid")) for g, s in zip(pool, SERVE_POOL)]
+    from paper_2304_13194_amd import inputs as I
+    dgs = [J.to_device(g, unit_vwgt=(s[0] == "grid"), unit_adjwgt=(s[0] == "grid")) for g, s in zip(pool, I.SERVE_POOL)]
     # one at a time (jet_partition): reference results and sequential throughput
     for gi, k, seed in jobs[:4]:
         J.partition(dgs[gi], k, seed=seed)
@@ -232,7 +196,7 @@ def serve_bench(J, pool, jobs, rates=(50, 200, 1000, 2000)):
            "graphs_per_s_one_at_a_time": len(jobs) / t_seq, "rates": []}
     identical = True
     for ri, rate in enumerate(rates):
-        arr = arrivals(rate, len(jobs), 500 + ri)
+        arr = I.arrivals(rate, len(jobs), 500 + ri)
         outs = [torch.empty(dgs[gi].n, dtype=torch.int32, device="cuda") for gi, _, _ in jobs]
         torch.cuda.synchronize()
         sv = J.Server(hbm_budget_bytes=128 << 30, max_slots=64)
@@ -293,6 +257,7 @@ def main():
 
     import numpy as np
     import torch
+    from paper_2304_13194_amd import inputs as I
     from paper_2304_13194_amd import jet as J
 
     w = WORKLOADS[args.workload]
@@ -312,10 +277,10 @@ def main():
     if not (args.no_batch and args.no_serve):
         pool_ex = ProcessPoolExecutor(max_workers=6)
         if not args.no_batch:
-            spec = rgg_batch_spec()
+            spec = I.rgg_batch_spec()
             fut_rgg = [pool_ex.submit(_gen_rgg, (n, s)) for n, _, s in spec]
         if not args.no_serve:
-            fut_pool = [pool_ex.submit(_gen_pool_graph, s) for s in SERVE_POOL]
+            fut_pool = [pool_ex.submit(_gen_pool_graph, s) for s in I.SERVE_POOL]
     t_gen = time.perf_counter()
     print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
     g = load_or_make_graph(w, args.workload, args.graph_cache)
@@ -410,7 +375,7 @@ def main():
     if fut_pool is not None:
         try:
             pool = [f.result() for f in fut_pool]
-            out["serving"] = serve_bench(J, pool, serve_jobs(40))
+            out["serving"] = serve_bench(J, pool, I.serve_jobs(40))
         except Exception as e:
             out["serving"] = {"error": repr(e)}
     if pool_ex is not None:

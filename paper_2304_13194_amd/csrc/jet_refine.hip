@@ -1126,14 +1126,13 @@ __device__ __forceinline__ void after_store(const KArgs &a, int v, int pd, int s
 }
 
 template <bool B>
-__global__ __launch_bounds__(BLOCK) void k_afterburner(KArgs a)
+__device__ void afterburner_body(const KArgs &a, int b)
 {
     __shared__ int32_t s_red[BLOCK / 64];
     __shared__ int32_t s_q[BLOCK];
     if (!any_kind(a, KIND_LP)) return;
     GV pv;
     if (!B) pv.at(a, 0);
-    int b = blockIdx.x;
     if (b < a.gS) {
         int32_t *q = s_q + (threadIdx.x >> 6) * 64;
         wave_batched<8>(
@@ -1650,8 +1649,14 @@ __global__ __launch_bounds__(BLOCK) void k_lchunk_fill(const int32_t *ctot, cons
 // minus that of the best connected valid destination, ties -> smaller id, or
 // a random valid destination when none is adjacent; Jetrs: own connectivity
 // minus the floor mean over adjacent valid destinations) and its slot.
+// Histogram of the candidates' (part, slot) weights, when the loss kernels
+// build it: HIST_LDS adds into the block's LDS copy (flushed once per block),
+// HIST_GLOBAL adds into the global histogram directly; HIST_NONE leaves it to
+// the separate histogram pass.
+enum HistMode { HIST_NONE = 0, HIST_LDS = 1, HIST_GLOBAL = 2 };
+
 __device__ __forceinline__ void rb_finish(const KArgs &a, int v, int ps, const GV &gv, uint64_t best, int cs, int sumB,
-                                          int cntB)
+                                          int cntB, int vwv, int hmode, int32_t *lh)
 {
     int loss, d = -1;
     if (gv.kind == KIND_RW) {
@@ -1672,6 +1677,9 @@ __device__ __forceinline__ void rb_finish(const KArgs &a, int v, int ps, const G
     }
     const int s = loss_slot(loss);
     a.slot[v] = (uint8_t)s;
+    if (hmode == HIST_LDS) atomicAdd(&lh[ps * NSLOT + s], vwv);
+    else if (hmode == HIST_GLOBAL)
+        atomicAdd((unsigned long long *)&a.hist[(int64_t)(gv.poff + ps) * NSLOT + s], (unsigned long long)(int64_t)vwv);
     if (a.dbg_loss) {
         a.dbg_loss[v] = loss;
         a.dbg_slot[v] = s;
@@ -1696,7 +1704,8 @@ __device__ __forceinline__ bool rb_candidate(const KArgs &a, int v, int ps, int 
 }
 
 template <bool B, int G, int R>
-__device__ void rb_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ngroups, GV &gv, CountX &racc)
+__device__ void rb_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ngroups, GV &gv, CountX &racc, int hmode,
+                          int32_t *lh)
 {
     const int gl = threadIdx.x & (G - 1);
     const int32_t *list = a.bins + a.binoff[cls];
@@ -1731,7 +1740,7 @@ __device__ void rb_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ng
         sumB = gsum<G>(sumB);
         cntB = gsum<G>(cntB);
         if (gl == 0) {
-            rb_finish(a, v, ps, gv, best, cs, sumB, cntB);
+            rb_finish(a, v, ps, gv, best, cs, sumB, cntB, vwv, hmode, lh);
             racc.sel<B>(a, g);
             racc.c0++;
         }
@@ -1739,7 +1748,8 @@ __device__ void rb_groups(const KArgs &a, int cls, int32_t *tab, int gid, int ng
 }
 
 template <bool B>
-__device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nblocks, GV &gv, CountX &racc)
+__device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nblocks, GV &gv, CountX &racc, int hmode,
+                          int32_t *lh)
 {
     __shared__ uint64_t s_red[BLOCK / 64];
     __shared__ int32_t s_red32[BLOCK / 64];
@@ -1774,7 +1784,7 @@ __device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nb
         sumB = block_sum<BLOCK>(sumB, s_red32);
         cntB = block_sum<BLOCK>(cntB, s_red32);
         if (threadIdx.x == 0) {
-            rb_finish(a, v, ps, gv, best, cs, sumB, cntB);
+            rb_finish(a, v, ps, gv, best, cs, sumB, cntB, vwv, hmode, lh);
             racc.sel<B>(a, g);
             racc.c0++;
         }
@@ -1782,7 +1792,7 @@ __device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nb
 }
 
 template <bool B, int ROLE, int GS = 8, int RS = 32 / GS>
-__global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
+__global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int hmode)
 {
     extern __shared__ int32_t lds[];
     if (!any_rb(a)) return;
@@ -1794,6 +1804,11 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
         rv.at(a, 0);
         racc.to(a, 0);
     }
+    // the block's histogram sits after the role's tables (HIST_LDS, one graph)
+    const int hoff = ROLE == 1 ? (BLOCK / GS) * stride + BLOCK : (ROLE == 2 ? (BLOCK / 64) * stride : (ROLE == 3 ? a.k : 0));
+    int32_t *lh = lds + hoff;
+    if (hmode == HIST_LDS)
+        for (int i = threadIdx.x; i < a.k * NSLOT; i += BLOCK) lh[i] = 0;
     if (ROLE == 1) {
         constexpr int RS_ = RS;
         const int ng = BLOCK / GS;
@@ -1840,7 +1855,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
                     sumB = gsum<GS>(sumB);
                     cntB = gsum<GS>(cntB);
                     if (gl == 0) {
-                        rb_finish(a, t.v, t.ps, rv, best, cs, sumB, cntB);
+                        rb_finish(a, t.v, t.ps, rv, best, cs, sumB, cntB, t.aux, hmode, lh);
                         racc.sel<B>(a, t.g);
                         racc.c0++;
                     }
@@ -1852,13 +1867,15 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
         __syncthreads();
         int32_t *tab = lds + (threadIdx.x >> 6) * stride;
         for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 2) rb_groups<B, 64, 16>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 6), nblk * ng, pv, racc);
+            if (a.tmap[c] == 2)
+                rb_groups<B, 64, 16>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 6), nblk * ng, pv, racc, hmode, lh);
     } else if (ROLE == 3) {
         for (int i = threadIdx.x; i < a.k; i += BLOCK) lds[i] = 0;
         __syncthreads();
         for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 3) rb_blocks<B>(a, c, lds, blockIdx.x, nblk, pv, racc);
+            if (a.tmap[c] == 3) rb_blocks<B>(a, c, lds, blockIdx.x, nblk, pv, racc, hmode, lh);
     } else {
+        __syncthreads();
         // isolated vertices: no connectivity, loss 0, random destination (Jetrw)
         const int32_t *list = a.bins + a.binoff[CLS_Z];
         const int cnt = a.binoff[CLS_Z + 1] - a.binoff[CLS_Z];
@@ -1870,18 +1887,24 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk)
             pv.sel<B>(a, g);
             if (!is_rb(pv.kind)) continue;
             const int ps = a.P[v];
-            if (!rb_candidate(a, v, ps, a.vw ? a.vw[v] : 1, pv)) continue;
-            rb_finish(a, v, ps, pv, 0, 0, 0, 0);
+            const int vwv = a.vw ? a.vw[v] : 1;
+            if (!rb_candidate(a, v, ps, vwv, pv)) continue;
+            rb_finish(a, v, ps, pv, 0, 0, 0, 0, vwv, hmode, lh);
             racc.sel<B>(a, g);
             racc.c0++;
         }
+    }
+    if (hmode == HIST_LDS) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < a.k * NSLOT; i += BLOCK)
+            if (lh[i]) atomicAdd((unsigned long long *)&a.hist[i], (unsigned long long)(int64_t)lh[i]);
     }
     acc_finish(a, racc);
 }
 
 // Rebalancing loss on long rows, phase 2 (one wave per vertex).
 template <bool B>
-__global__ __launch_bounds__(BLOCK) void k_lrb_fin(KArgs a)
+__global__ __launch_bounds__(BLOCK) void k_lrb_fin(KArgs a, int hmode)
 {
     if (!any_rb(a)) return;
     const int gl = threadIdx.x & 63;
@@ -1925,7 +1948,7 @@ __global__ __launch_bounds__(BLOCK) void k_lrb_fin(KArgs a)
         sumB = gsum<64>(sumB);
         cntB = gsum<64>(cntB);
         if (gl == 0) {
-            rb_finish(a, v, ps, pv, best, cs, sumB, cntB);
+            rb_finish(a, v, ps, pv, best, cs, sumB, cntB, vwv, hmode, nullptr);
             racc.sel<B>(a, g);
             racc.c0++;
         }
@@ -1985,6 +2008,49 @@ __global__ __launch_bounds__(BLOCK) void k_rb_hist(KArgs a, int use_lds)
 // Per graph (one block each): cut-off slot s* of every oversized part (slots
 // below it are evicted whole) and the residual weight still needed inside
 // s*; Jetrs capacities over B.
+__device__ __forceinline__ void part_cutoff(const KArgs &a, int gp, int64_t o, int &ss, int64_t &res)
+{
+    ss = -1;
+    res = 0;
+    if (!a.isA[gp]) return;
+    const int64_t need = a.w[gp] - o;
+    int64_t hv[NSLOT];
+#pragma unroll
+    for (int s = 0; s < NSLOT; s++) hv[s] = a.hist[(int64_t)gp * NSLOT + s];
+    int64_t cum = 0;
+    ss = NSLOT;
+#pragma unroll
+    for (int s = 0; s < NSLOT; s++) {
+        if (ss == NSLOT && cum + hv[s] >= need) {
+            ss = s;
+            res = need - cum;
+        }
+        cum += hv[s];
+    }
+}
+
+// Jetrs capacities of graph g: exclusive prefix of sigma - W(b) over its
+// list B (whole block).
+__device__ void rs_capacities(const KArgs &a, int g, Ctl *c, int64_t *s_scan64)
+{
+    const int nB = c->nB, poff = c->poff;
+    const int64_t sigma = c->sigma;
+    int64_t *cap = a.capstart + poff + g;
+    int64_t acc = 0;
+    for (int base = 0; base < nB; base += BLOCK) {
+        const int i = base + threadIdx.x;
+        const int64_t cv = i < nB ? sigma - a.w[poff + a.Blist[poff + i]] : 0;
+        int64_t tot;
+        const int64_t pos = block_excl_scan<BLOCK>(cv, s_scan64, tot);
+        if (i < nB) cap[i] = acc + pos;
+        acc += tot;
+    }
+    if (threadIdx.x == 0) {
+        cap[nB] = acc;
+        c->total_cap = acc;
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void k_rb_cutoff(KArgs a)
 {
     __shared__ int64_t s_scan64[BLOCK / 64];
@@ -1995,46 +2061,13 @@ __global__ __launch_bounds__(BLOCK) void k_rb_cutoff(KArgs a)
     const int64_t o = c->o;
     const int k = c->k, poff = c->poff;
     for (int p = threadIdx.x; p < k; p += BLOCK) {
-        const int gp = poff + p;
-        int ss = -1;
-        int64_t res = 0;
-        if (a.isA[gp]) {
-            const int64_t need = a.w[gp] - o;
-            int64_t hv[NSLOT];
-#pragma unroll
-            for (int s = 0; s < NSLOT; s++) hv[s] = a.hist[(int64_t)gp * NSLOT + s];
-            int64_t cum = 0;
-            ss = NSLOT;
-#pragma unroll
-            for (int s = 0; s < NSLOT; s++) {
-                if (ss == NSLOT && cum + hv[s] >= need) {
-                    ss = s;
-                    res = need - cum;
-                }
-                cum += hv[s];
-            }
-        }
-        a.sstar[gp] = ss;
-        a.resid[gp] = res;
+        int ss;
+        int64_t res;
+        part_cutoff(a, poff + p, o, ss, res);
+        a.sstar[poff + p] = ss;
+        a.resid[poff + p] = res;
     }
-    if (kind == KIND_RS) {
-        const int nB = c->nB;
-        const int64_t sigma = c->sigma;
-        int64_t *cap = a.capstart + poff + g;
-        int64_t acc = 0;
-        for (int base = 0; base < nB; base += BLOCK) {
-            const int i = base + threadIdx.x;
-            const int64_t cv = i < nB ? sigma - a.w[poff + a.Blist[poff + i]] : 0;
-            int64_t tot;
-            const int64_t pos = block_excl_scan<BLOCK>(cv, s_scan64, tot);
-            if (i < nB) cap[i] = acc + pos;
-            acc += tot;
-        }
-        if (threadIdx.x == 0) {
-            cap[nB] = acc;
-            c->total_cap = acc;
-        }
-    }
+    if (kind == KIND_RS) rs_capacities(a, g, c, s_scan64);
 }
 
 // Vertex range [v0, v1) of tile `tile` and its graph's controller.
@@ -2051,12 +2084,31 @@ __device__ __forceinline__ const Ctl *tile_range(const KArgs &a, int tile, int &
 
 // Per tile (one block) and part whose cut-off lies inside the histogram:
 // weight of the tile's candidates that sit in the part's cut-off slot,
-// stored at tsum[rowbase + part * ntiles + tile].
-__global__ __launch_bounds__(BLOCK) void k_rb_tilesum(KArgs a)
+// stored at tsum[rowbase + part * ntiles + tile]. Blocks bid, bid + nb, ...
+// take the tiles. With `sst` (one graph, k LDS entries) the blocks first
+// find the cut-off slots themselves; block 0 also stores them with the
+// residuals and the Jetrs capacities.
+__device__ void tilesum_body(const KArgs &a, int bid, int nb, int32_t *acc, int32_t *sst)
 {
-    extern __shared__ int32_t acc[];
+    __shared__ int64_t s_scan64[BLOCK / 64];
     if (!any_rb(a)) return;
-    for (int tile = blockIdx.x; tile < a.ntile; tile += gridDim.x) {
+    if (sst) {
+        Ctl *c = a.ctl;
+        if (!is_rb(c->kind)) return;
+        for (int p = threadIdx.x; p < c->k; p += BLOCK) {
+            int ss;
+            int64_t res;
+            part_cutoff(a, p, c->o, ss, res);
+            sst[p] = ss;
+            if (bid == 0) {
+                a.sstar[p] = ss;
+                a.resid[p] = res;
+            }
+        }
+        if (bid == 0 && c->kind == KIND_RS) rs_capacities(a, 0, c, s_scan64);
+        __syncthreads();
+    }
+    for (int tile = bid; tile < a.ntile; tile += nb) {
         int lt, v0, v1;
         const Ctl *c = tile_range(a, tile, lt, v0, v1);
         if (!is_rb(c->kind)) continue;
@@ -2073,7 +2125,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_tilesum(KArgs a)
 #pragma unroll
             for (int j = 0; j < PER; j++) pp[j] = sl[j] != 255 ? a.P[v0 + threadIdx.x + j * BLOCK] : 0;
 #pragma unroll
-            for (int j = 0; j < PER; j++) ss[j] = sl[j] != 255 ? a.sstar[poff + pp[j]] : -1;
+            for (int j = 0; j < PER; j++) ss[j] = sl[j] != 255 ? (sst ? sst[pp[j]] : a.sstar[poff + pp[j]]) : -1;
 #pragma unroll
             for (int j = 0; j < PER; j++)
                 if (sl[j] != 255 && sl[j] == ss[j])
@@ -2082,11 +2134,23 @@ __global__ __launch_bounds__(BLOCK) void k_rb_tilesum(KArgs a)
         __syncthreads();
         int32_t *row = a.tsum + c->rowbase + lt;
         for (int p = threadIdx.x; p < k; p += BLOCK) {
-            const int ss = a.sstar[poff + p];
+            const int ss = sst ? sst[p] : a.sstar[poff + p];
             if (ss >= 0 && ss < NSLOT) row[(int64_t)p * ntl] = acc[p];
         }
         __syncthreads();
     }
+}
+
+// One launch for two passes that never run in the same iteration of a
+// graph: blocks [0, nafter) run the afterburner (Jetlp), the rest the tile
+// sums of the rebalancing selection. Dynamic LDS: k ints, 2k when the
+// cut-off is found here (fuse_cut, one graph).
+template <bool B>
+__global__ __launch_bounds__(BLOCK) void k_after_tsum(KArgs a, int nafter, int fuse_cut)
+{
+    extern __shared__ int32_t lds[];
+    if ((int)blockIdx.x < nafter) afterburner_body<B>(a, blockIdx.x);
+    else tilesum_body(a, blockIdx.x - nafter, gridDim.x - nafter, lds, fuse_cut ? lds + a.k : nullptr);
 }
 
 // Per part whose cut-off lies inside the histogram (one block): an exclusive
@@ -2402,6 +2466,24 @@ static int64_t deadzone_sigma(int64_t W, int k, int64_t o, int div)
         if (e_ != hipSuccess) return hip_status(ctx, e_);  \
     } while (0)
 
+// Up to this k the small-row role runs with 4 lanes per vertex (64 tables of
+// k + 1 ints per block fit in 32 KiB): twice the vertices in flight per wave.
+constexpr int K_G4 = 120;
+
+// LDS of one compute unit (gfx950).
+constexpr size_t LDS_PER_CU = 160 * 1024;
+
+// Dynamic LDS of the loss kernel of a role (tables and queue), without the
+// block histogram.
+static size_t rb_role_lds(int role, int k)
+{
+    const size_t st = (size_t)(k + 1) * 4;
+    if (role == 1) return (BLOCK / (k <= K_G4 ? 4 : 8)) * st + BLOCK * 4;
+    if (role == 2) return (BLOCK / 64) * st;
+    if (role == 3) return (size_t)k * 4;
+    return 0;
+}
+
 struct Plan {
     KArgs tab;    // LDS-table kernels (gain, loss)
     KArgs plain;  // afterburner, cut delta and the flat kernels
@@ -2410,6 +2492,8 @@ struct Plan {
     size_t lds_tab;
     int grid_flat, grid_tile, grid_hist;
     int grid_lch;  // chunk kernels (0: no chunked rows)
+    bool hist_fused;  // the loss kernels build the histogram (one graph, LDS room)
+    bool cut_fused;   // the tile-sum blocks find the cut-off slots (one graph)
     int grid_lfin, nL;
     int grid_v;              // grid of the list-building kernels
     int32_t *blkcnt, *lcnt;  // their scratch
@@ -2457,6 +2541,15 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
     pl.tab = t;
     pl.plain = p;
     pl.hist_lds = a.vg == nullptr && (size_t)a.k * NSLOT * 4 <= 65536;
+    // The loss kernels keep a block histogram only where it costs no
+    // occupancy: every block of each role stays resident at once.
+    pl.hist_fused = a.vg == nullptr;
+    const int rgrid[5] = {0, t.gS, t.gM, t.gL, t.gZ};
+    for (int r = 1; r <= 4; r++) {
+        const size_t per = rb_role_lds(r, k) + (size_t)k * NSLOT * 4;
+        if (per > 65536 || (size_t)div_up(rgrid[r], ctx->num_cu) * per > LDS_PER_CU) pl.hist_fused = false;
+    }
+    pl.cut_fused = a.vg == nullptr && k <= 1024;
     pl.grid_hist = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_flat = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_tile = std::max(1, std::min(a.ntile, ctx->num_cu * 8));
@@ -2465,9 +2558,6 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
     pl.grid_lfin = chunked ? std::max(1, std::min(div_up(pl.nL, BLOCK / 64), maxb)) : 0;
 }
 
-// Up to this k the small-row role runs with 4 lanes per vertex (64 tables of
-// k + 1 ints per block fit in 32 KiB): twice the vertices in flight per wave.
-constexpr int K_G4 = 120;
 
 template <bool B>
 static void launch_gain_t(const Plan &pl, hipStream_t s)
@@ -2486,11 +2576,14 @@ static void launch_gain_t(const Plan &pl, hipStream_t s)
     }
 }
 
+// Afterburner and the rebalancing tile sums in one launch (each pass exits
+// at once in iterations of the other kind), then the long-row afterburner.
 template <bool B>
 static void launch_after_t(const Plan &pl, hipStream_t s)
 {
     const KArgs &p = pl.plain;
-    if (pl.grid_plain) k_afterburner<B><<<pl.grid_plain, BLOCK, 0, s>>>(p);
+    const size_t lds = (size_t)p.k * 4 * (pl.cut_fused ? 2 : 1);
+    k_after_tsum<B><<<pl.grid_plain + pl.grid_tile, BLOCK, lds, s>>>(p, pl.grid_plain, pl.cut_fused ? 1 : 0);
     if (pl.grid_lch) {
         k_lafter<B><<<pl.grid_lch, BLOCK, 0, s>>>(p);
         k_lafter_fin<B><<<std::max(1, div_up(pl.nL, BLOCK)), BLOCK, 0, s>>>(p);
@@ -2501,28 +2594,37 @@ template <bool B>
 static void launch_rb_loss_t(const Plan &pl, hipStream_t s)
 {
     const KArgs &t = pl.tab;
+    const int hm = pl.hist_fused ? HIST_LDS : HIST_NONE;
+    const size_t hb = pl.hist_fused ? (size_t)t.k * NSLOT * 4 : 0;
     const size_t st = (size_t)(t.k + 1) * 4;
     if (t.gS) {
-        if (t.k <= K_G4) k_rb_loss<B, 1, 4><<<t.gS, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, t.gS);
-        else k_rb_loss<B, 1, 8><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS);
+        if (t.k <= K_G4) k_rb_loss<B, 1, 4><<<t.gS, BLOCK, rb_role_lds(1, t.k) + hb, s>>>(t, t.gS, hm);
+        else k_rb_loss<B, 1, 8><<<t.gS, BLOCK, rb_role_lds(1, t.k) + hb, s>>>(t, t.gS, hm);
     }
-    if (t.gM) k_rb_loss<B, 2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM);
-    if (t.gL) k_rb_loss<B, 3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL);
-    if (t.gZ) k_rb_loss<B, 4><<<t.gZ, BLOCK, 0, s>>>(t, t.gZ);
+    if (t.gM) k_rb_loss<B, 2><<<t.gM, BLOCK, rb_role_lds(2, t.k) + hb, s>>>(t, t.gM, hm);
+    if (t.gL) k_rb_loss<B, 3><<<t.gL, BLOCK, rb_role_lds(3, t.k) + hb, s>>>(t, t.gL, hm);
+    if (t.gZ) k_rb_loss<B, 4><<<t.gZ, BLOCK, rb_role_lds(4, t.k) + hb, s>>>(t, t.gZ, hm);
     if (pl.grid_lch) {
         k_lconn<B, true><<<pl.grid_lch, BLOCK, (BLOCK / 64) * st, s>>>(t);
-        k_lrb_fin<B><<<pl.grid_lfin, BLOCK, 0, s>>>(t);
+        k_lrb_fin<B><<<pl.grid_lfin, BLOCK, 0, s>>>(t, pl.hist_fused ? HIST_GLOBAL : HIST_NONE);
     }
 }
 
-// Histogram, cut-off slots, ordered selection and (Jetrs) the cookie-cutter.
+// Histogram and cut-off slots where the loss and tile-sum passes do not
+// find them themselves.
+template <bool B>
+static void launch_rb_cutoff_t(const Plan &pl, hipStream_t s)
+{
+    const KArgs &p = pl.plain;
+    if (!pl.hist_fused) k_rb_hist<B><<<pl.grid_hist, BLOCK, pl.hist_lds ? (size_t)p.k * NSLOT * 4 : 0, s>>>(p, pl.hist_lds);
+    if (!pl.cut_fused) k_rb_cutoff<<<pl.G, BLOCK, 0, s>>>(p);
+}
+
+// Ordered selection (split, mark) and the Jetrs cookie-cutter.
 template <bool B>
 static void launch_rb_select_t(const Plan &pl, hipStream_t s)
 {
     const KArgs &p = pl.plain;
-    k_rb_hist<B><<<pl.grid_hist, BLOCK, pl.hist_lds ? (size_t)p.k * NSLOT * 4 : 0, s>>>(p, pl.hist_lds);
-    k_rb_cutoff<<<pl.G, BLOCK, 0, s>>>(p);
-    k_rb_tilesum<<<pl.grid_tile, BLOCK, (size_t)p.k * 4, s>>>(p);
     k_rb_split<<<std::min(p.ktot, 1024), BLOCK, 0, s>>>(p);
     k_rb_mark<<<pl.grid_tile, BLOCK, 0, s>>>(p);
     k_rs_assign<<<pl.grid_tile, BLOCK, 0, s>>>(p);
@@ -2535,8 +2637,9 @@ static void launch_iteration_t(const Plan &pl, hipStream_t s, hipEvent_t ev_a, h
     if (ev_a) (void)hipEventRecord(ev_a, s);
     launch_gain_t<B>(pl, s);
     if (ev_b) (void)hipEventRecord(ev_b, s);
-    launch_after_t<B>(pl, s);
     launch_rb_loss_t<B>(pl, s);
+    launch_rb_cutoff_t<B>(pl, s);
+    launch_after_t<B>(pl, s);
     launch_rb_select_t<B>(pl, s);
     if (pl.grid_plain) k_dcut<B><<<pl.grid_plain, BLOCK, 0, s>>>(p);
     if (pl.grid_lch) k_ldcut<B><<<pl.grid_lch, BLOCK, 0, s>>>(p);
@@ -2560,6 +2663,11 @@ static void launch_rb_loss(const Plan &pl, hipStream_t s)
 {
     if (batched(pl)) launch_rb_loss_t<true>(pl, s);
     else launch_rb_loss_t<false>(pl, s);
+}
+static void launch_rb_cutoff(const Plan &pl, hipStream_t s)
+{
+    if (batched(pl)) launch_rb_cutoff_t<true>(pl, s);
+    else launch_rb_cutoff_t<false>(pl, s);
 }
 static void launch_rb_select(const Plan &pl, hipStream_t s)
 {
@@ -2589,8 +2697,10 @@ static void set_lds_limits_t()
     (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_apply<B>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_hist<B>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_after_tsum<B>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_lconn<B, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_lconn<B, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
 }
@@ -2603,7 +2713,6 @@ static void set_lds_limits()
     set_lds_limits_t<false>();
     set_lds_limits_t<true>();
     (void)hipFuncSetAttribute((const void *)k_init_vertices, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-    (void)hipFuncSetAttribute((const void *)k_rb_tilesum, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
 }
 
 static int check_params(const jet_csr *g, const jet_params *prm)
@@ -3527,6 +3636,8 @@ extern "C" int jet_rebalance_step(jet_context *ctx, const jet_csr *g, const jet_
     k_step_defaults<<<pl.grid_flat, BLOCK, 0, s>>>(p, part);
     k_force_step<<<1, BLOCK, 0, s>>>(p, kind, t, nullptr);
     launch_rb_loss(pl, s);
+    launch_rb_cutoff(pl, s);
+    launch_after(pl, s);
     launch_rb_select(pl, s);
     JET_TRY(hipGetLastError());
     JET_TRY(hipMemcpyAsync(dest, p.dest, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));

@@ -331,3 +331,45 @@ def small_random_graph(n: int, p_edge: float, seed: int, wmax: int = 1, vwmax: i
          ).astype(np.int32) if u.shape[0] else np.zeros(0, np.int32)
     vw = (1 + uniform_below(stream(subseed(seed, 4), np.arange(n, dtype=np.uint64)), vwmax)).astype(np.int32)
     return csr_from_edges(n, u, v, w, vwgt=vw, name=f"er_{n}_{seed}")
+
+
+# ------------------------------------------------------------- workloads --
+# Recipes of the batched and serving workloads (sizes, k and seeds only).
+
+def rgg_batch_spec(count: int = 512, nmin: int = 1000, nmax: int = 200000, seed: int = 77):
+    """(n, k, seed) per graph: n log-uniform on [nmin, nmax], k uniform in
+    {2, 4, ..., 128}. Graph i is ``rgg(n, seed)`` with P_0 =
+    ``random_partition(n, k, seed)``."""
+    u = stream(seed, np.arange(2 * count, dtype=np.uint64))
+    frac = (u[:count] >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    ns = np.exp(np.log(nmin) + (np.log(nmax) - np.log(nmin)) * frac).astype(np.int64)
+    ks = np.array([2, 4, 8, 16, 32, 64, 128])[uniform_below(u[count:], 7)]
+    return [(int(ns[i]), int(ks[i]), seed * 100003 + i) for i in range(count)]
+
+
+# Graph pool of the serving workload: 2-D grids (unit weights) and R-MAT
+# graphs (scale, edge factor, seed; weights 1..16).
+SERVE_POOL = [("grid", 64), ("grid", 128), ("grid", 256), ("grid", 512), ("grid", 1024),
+              ("rmat", 12, 8, 41), ("rmat", 14, 16, 42), ("rmat", 16, 8, 43), ("rmat", 18, 16, 44),
+              ("rmat", 20, 16, 45)]
+
+
+def serve_pool_graph(spec) -> Graph:
+    if spec[0] == "grid":
+        return grid2d(spec[1], spec[1])
+    return rmat(spec[1], spec[2], spec[3])
+
+
+def serve_jobs(count: int, seed: int = 99):
+    """(pool index, k uniform in [2, 256], seed) per job."""
+    u = stream(seed, np.arange(2 * count, dtype=np.uint64))
+    gi = uniform_below(u[:count], len(SERVE_POOL))
+    ks = 2 + uniform_below(u[count:], 255)
+    return [(int(gi[i]), int(ks[i]), 1000 + i) for i in range(count)]
+
+
+def arrivals(rate: float, count: int, seed: int) -> np.ndarray:
+    """Poisson process: exponential gaps of mean 1/rate, first arrival at 0."""
+    u = (stream(seed, np.arange(count, dtype=np.uint64)) >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    gaps = -np.log1p(-u) / rate
+    return np.cumsum(gaps) - gaps[0]
