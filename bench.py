@@ -30,6 +30,7 @@ Prints one JSON line:
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -300,17 +301,25 @@ def main():
         lv_nnz.append(int(view.nnz))
     h.close()
 
+    # warm-up calls are the timed call itself (same flags and trace buffer)
     for _ in range(args.warmup):
-        J.partition(dg, k, seed=args.seed)
+        J.partition(dg, k, seed=args.seed, flags=J.JET_F_PROFILE, trace_cap=1 << 16)
     torch.cuda.synchronize()
 
+    # no Python garbage collection inside the timed region (a full collection
+    # of the interpreter's heap costs tens of milliseconds)
+    gc.collect()
+    gc.disable()
     steps = []
+    t_ret = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         part, st, tr = J.partition(dg, k, seed=args.seed, flags=J.JET_F_PROFILE, trace_cap=1 << 16)
         steps.append((st, tr))
+        t_ret.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    gc.enable()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
 
     st0, tr0 = steps[0]
@@ -348,6 +357,8 @@ def main():
             "rs_iters": st0["rs_iters"], "finest_iters": len(fin), "cut": st0["cut"],
             "balanced": bool(st0["balanced"]), "ms_coarsen": st0["ms_coarsen"],
             "ms_refine": refine_ms,
+            "ms_gpu_total": sum(s["ms_total"] for s, _ in steps) / args.steps,
+            "ms_wall_steps": [round((b - a) * 1e3, 2) for a, b in zip([t0] + t_ret[:-1], t_ret)],
             "refine_only_edges_per_s": edges_per_step / (refine_ms * 1e-3) if refine_ms else None,
             "gen_s": t_gen,
         },

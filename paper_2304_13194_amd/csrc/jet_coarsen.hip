@@ -669,7 +669,7 @@ int check_graph(jet_context *ctx, const jet_csr *g, uint32_t flags, hipStream_t 
     int64_t *ends = (int64_t *)((char *)ctx->pinned + 2048);
     JET_TRY(hipMemcpyAsync(ends, g->xadj, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     JET_TRY(hipMemcpyAsync(ends + 1, g->xadj + g->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     if (ends[0] != 0 || ends[1] != g->nnz) return JET_EGRAPH;
     k_chk_vertices<<<grid_for(ctx, g->n, CB, 4), CB, 0, s>>>(g->n, g->xadj, g->vwgt, st);
     if (g->nnz > 0)
@@ -677,14 +677,69 @@ int check_graph(jet_context *ctx, const jet_csr *g, uint32_t flags, hipStream_t 
     JET_TRY(hipGetLastError());
     CState *h = (CState *)((char *)ctx->pinned + 2304);
     JET_TRY(hipMemcpyAsync(h, st, sizeof(CState), hipMemcpyDeviceToHost, s));
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     if (h->bad) return JET_EGRAPH;
     if (h->wsum >= ((int64_t)1 << 31) || h->ewsum >= ((int64_t)1 << 31)) return JET_EOVERFLOW;
     return JET_OK;
 }
 
+void *jet::Arena::alloc(size_t bytes)
+{
+    bytes = (std::max<size_t>(bytes, 16) + 255) & ~(size_t)255;
+    while (cur < chunks.size()) {
+        if (used + bytes <= chunks[cur].bytes) {
+            void *p = (char *)chunks[cur].ptr + used;
+            used += bytes;
+            return p;
+        }
+        cur++;
+        used = 0;
+    }
+    size_t total = 0;
+    for (const Buffer &b : chunks) total += b.bytes;
+    Buffer b;
+    b.bytes = std::max<size_t>({bytes, total, (size_t)64 << 20});
+    if (hipMalloc(&b.ptr, b.bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    chunks.push_back(b);
+    cur = chunks.size() - 1;
+    used = bytes;
+    return b.ptr;
+}
+
+// Only between calls (nothing queued still uses the memory).
+void jet::Arena::reset()
+{
+    if (chunks.size() > 1) {
+        size_t total = 0;
+        for (const Buffer &b : chunks) total += b.bytes;
+        release();
+        Buffer b;
+        if (hipMalloc(&b.ptr, total) == hipSuccess) {
+            b.bytes = total;
+            chunks.push_back(b);
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    cur = 0;
+    used = 0;
+}
+
+void jet::Arena::release()
+{
+    for (Buffer &b : chunks)
+        if (b.ptr) (void)hipFree(b.ptr);
+    chunks.clear();
+    cur = 0;
+    used = 0;
+}
+
 static void *hier_alloc(jet_hierarchy *h, size_t bytes)
 {
+    if (h->arena) return h->arena->alloc(bytes);
     void *p = nullptr;
     if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) {
         (void)hipGetLastError();
@@ -696,6 +751,7 @@ static void *hier_alloc(jet_hierarchy *h, size_t bytes)
 
 static void hier_release(jet_hierarchy *h)
 {
+    if (h->arena) h->arena->reset();
     for (void *p : h->owned) (void)hipFree(p);
     h->owned.clear();
 }
@@ -721,7 +777,7 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     k_big_list<<<gv, CB, 0, s>>>(n, f->xadj, big, nbig);
     int32_t *hbig = (int32_t *)((char *)ctx->pinned + 2400);
     JET_TRY(hipMemcpyAsync(hbig, nbig, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     const int nb = *hbig;
     const uint64_t hseed = stream64(seed, (uint64_t)(uint32_t)level);
     const int gp = grid_for(ctx, n, CB / 8);
@@ -739,7 +795,7 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     scan_excl(flag, n, cid, tsum, s);
     int64_t *hn = (int64_t *)((char *)ctx->pinned + 2432);
     JET_TRY(hipMemcpyAsync(hn, cid + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     const int nc = (int)*hn;
     *nc_out = nc;
     if (nc == n) return JET_OK;
@@ -761,7 +817,7 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     k_cclass<<<grid_for(ctx, nc, CB, 4), CB, 0, s>>>(nc, bound, listM, listL, ccnt, ltot);
     int32_t *hc = (int32_t *)((char *)ctx->pinned + 2448);
     JET_TRY(hipMemcpyAsync(hc, ccnt, 24, hipMemcpyDeviceToHost, s));
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     const int nM = hc[0], nL = hc[1];
     const int64_t lslots = *(int64_t *)(hc + 4);
     int64_t *toffL = nullptr;
@@ -788,7 +844,7 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     scan_excl(ccount, nc, cxadj, tsum, s);
     JET_TRY(hipMemcpyAsync(hn, cxadj + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     JET_TRY(hipMemcpyAsync(hc, ccnt, 24, hipMemcpyDeviceToHost, s));
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     if (hc[2]) return JET_EHIP;  // a probe ran past its table: internal error
     const int64_t cnnz = *hn;
     int32_t *cadj = (int32_t *)hier_alloc(h, (size_t)std::max<int64_t>(cnnz, 1) * 4);
@@ -887,7 +943,7 @@ extern "C" int jet_coarsen(jet_context *ctx, const jet_csr *g, const jet_params 
     st = build_hierarchy(ctx, g, params, h, s);
     if (st) { hier_release(h); delete h; return st; }
     JET_TRY(hipEventRecord(ctx->ev[1], s));
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     (void)hipEventElapsedTime(&h->ms_coarsen, ctx->ev[0], ctx->ev[1]);
     *out = h;
     return JET_OK;
@@ -927,7 +983,9 @@ extern "C" int jet_partition(jet_context *ctx, const jet_csr *g, const jet_param
     JET_TRY(hipEventCreate(&e1));
     JET_TRY(hipEventCreate(&e2));
     JET_TRY(hipEventRecord(e0, s));
+    // the coarse levels live in the context's arena (kept between calls)
     jet_hierarchy h;
+    h.arena = &ctx->part_arena;
     st = build_hierarchy(ctx, g, params, &h, s);
     JET_TRY(hipEventRecord(e1, s));
     int levels = h.nlevels;
@@ -993,7 +1051,7 @@ extern "C" int jet_partition(jet_context *ctx, const jet_csr *g, const jet_param
     }
     if (st == JET_OK) {
         JET_TRY(hipEventRecord(e2, s));
-        JET_TRY(hipStreamSynchronize(s));
+        JET_TRY(stream_wait(ctx, s));
     }
     float ms_c = 0, ms_t = 0;
     if (st == JET_OK) {
@@ -1003,6 +1061,7 @@ extern "C" int jet_partition(jet_context *ctx, const jet_csr *g, const jet_param
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipEventDestroy(e2);
+    if (st) (void)hipStreamSynchronize(s);  // nothing queued may still use the arena
     hier_release(&h);
     if (st) return st;
     if (stats) {

@@ -118,12 +118,26 @@ struct Buffer {
 
 }  // namespace jet
 
+namespace jet {
+// Grow-only device arena: bump allocation from a list of chunks; reset()
+// keeps the memory (merging the chunks into one when a call needed several),
+// so repeated partitions of graphs of one size allocate nothing.
+struct Arena {
+    std::vector<Buffer> chunks;
+    size_t cur = 0, used = 0;
+    void *alloc(size_t bytes);
+    void reset();
+    void release();
+};
+}  // namespace jet
+
 struct jet_hierarchy {
     int device = 0;
     int nlevels = 0;
     std::vector<jet_csr> lv;        // level views (level 0 = caller's graph)
     std::vector<int32_t *> maps;    // maps[l]: level l -> level l+1 (owned)
-    std::vector<void *> owned;      // device buffers owned by the hierarchy
+    std::vector<void *> owned;      // device buffers owned by the hierarchy (no arena)
+    jet::Arena *arena = nullptr;    // when set, levels live in this arena instead
     float ms_coarsen = 0.f;
 };
 
@@ -138,6 +152,9 @@ struct jet_context {
     std::vector<hipEvent_t> prof_ev;  // pairs around gain passes (JET_F_PROFILE)
     hipStream_t cap = nullptr;        // side stream on which iteration sequences are captured
     bool graphs = true;               // replay captured iteration pairs (JET_NO_GRAPH=1 turns it off)
+    hipEvent_t wait_ev = nullptr;     // polled by stream_wait
+    jet::Arena part_arena;            // coarse levels of jet_partition calls
+    bool poll_wait = true;            // poll instead of sleeping in the runtime (JET_BLOCKING_WAIT=1 turns it off)
 };
 
 namespace jet {
@@ -156,6 +173,8 @@ enum WsSlot {
 void *ws_get(jet_context *ctx, int slot, size_t bytes);
 // Grow-only pinned host staging; returns nullptr on allocation failure.
 void *pinned_get(jet_context *ctx, size_t bytes);
+// Waits for everything queued on s (polling an event, see jet_context).
+hipError_t stream_wait(jet_context *ctx, hipStream_t s);
 
 // Refinement of one level; `part` holds P_0 on entry and P_best on exit.
 int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int32_t *part,

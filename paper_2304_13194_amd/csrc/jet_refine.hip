@@ -587,34 +587,50 @@ __global__ __launch_bounds__(BLOCK) void k_ctl_end(KArgs a)
     if (blockIdx.x == 0 && threadIdx.x < 4) a.cnt[CNT_ROW + (a.it & 1) * 4 + threadIdx.x] = 0;
     const int g = blockIdx.x;
     Ctl *c = a.ctl + g;
+    // thread 0 fetches the whole state while the block reads the part
+    // weights and counter shards: one round trip before the decision
+    Ctl cc;
+    if (threadIdx.x == 0) cc = *c;
     const int kind = c->kind;
     if (kind == KIND_DONE) return;
     const int k = c->k, poff = c->poff;
+    // the NSHARD shards of each counter row: one lane of the first wave each
+    int64_t sx = 0, sm = 0, sdc = 0, smw = 0, se = 0, sr = 0, sv = 0;
+    if (threadIdx.x < NSHARD) {
+        const int64_t *b = a.bstat + (int64_t)g * NSTAT * NSHARD + threadIdx.x;
+        sx = b[ST_X * NSHARD];
+        sm = b[ST_M * NSHARD];
+        sdc = b[ST_DCUT * NSHARD];
+        smw = b[ST_MW * NSHARD];
+        se = b[ST_DIG * NSHARD];
+        if (kind == KIND_LP) {
+            sr = b[ST_R * NSHARD];
+            sv = b[ST_V * NSHARD];
+        }
+    }
+    int64_t pe = 0;
+    if (threadIdx.x < NSHARD && kind == KIND_LP) pe = a.bstat[(int64_t)g * NSTAT * NSHARD + ST_E * NSHARD + threadIdx.x];
     uint64_t m = 0;
     for (int p = threadIdx.x; p < k; p += BLOCK) {
         const uint64_t x = (uint64_t)a.w[poff + p];
         m = x > m ? x : m;
     }
     m = block_max_u64<BLOCK>(m, s_red);
-    // the NSHARD shards of each counter row: one lane of the first wave each
-    int64_t px = 0, pm = 0, pdc = 0, pmw = 0, pe = 0, pr = 0, pv = 0;
+    int64_t px = 0, pm = 0, pdc = 0, pmw = 0, pr = 0, pv = 0;
     uint64_t pdg = 0;
     if (threadIdx.x < NSHARD) {
-        const int64_t *b = a.bstat + (int64_t)g * NSTAT * NSHARD + threadIdx.x;
-        px = gsum<NSHARD>(b[ST_X * NSHARD]);
-        pm = gsum<NSHARD>(b[ST_M * NSHARD]);
-        pdc = gsum<NSHARD>(b[ST_DCUT * NSHARD]);
-        pmw = gsum<NSHARD>(b[ST_MW * NSHARD]);
-        pdg = gsum<NSHARD>((uint64_t)b[ST_DIG * NSHARD]);
+        px = gsum<NSHARD>(sx);
+        pm = gsum<NSHARD>(sm);
+        pdc = gsum<NSHARD>(sdc);
+        pmw = gsum<NSHARD>(smw);
+        pdg = gsum<NSHARD>((uint64_t)se);
         if (kind == KIND_LP) {
-            pe = gsum<NSHARD>(b[ST_E * NSHARD]);
-            pr = gsum<NSHARD>(b[ST_R * NSHARD]);
-            pv = gsum<NSHARD>(b[ST_V * NSHARD]);
+            pe = gsum<NSHARD>(pe);
+            pr = gsum<NSHARD>(sr);
+            pv = gsum<NSHARD>(sv);
         }
     }
     if (threadIdx.x == 0) {
-        // one load of the whole state, one store: no dependent global round trips
-        Ctl cc = *c;
         const int64_t maxw = (int64_t)m;
         cc.nX = (int)px;
         cc.nM = (int)pm;
@@ -1030,15 +1046,18 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
                     m.g = gof<B>(a, m.v);
                     pv.sel<B>(a, m.g);
                     if (pv.kind != KIND_LP) return false;
+                    // part, lock stamp and row bounds in one round trip
                     m.ps = a.P[m.v];
+                    const int lk = a.lock[m.v];
+                    const int64_t x0 = a.xadj[m.v], x1 = a.xadj[m.v + 1];
                     pacc.sel<B>(a, m.g);
                     pacc.c0++;
-                    if (a.lock[m.v] == pv.lp_id - 1) {
+                    if (lk == pv.lp_id - 1) {
                         gain_locked(a, m.v, m.ps);
                         return false;
                     }
-                    m.s = a.xadj[m.v];
-                    m.deg = (int)(a.xadj[m.v + 1] - m.s);
+                    m.s = x0;
+                    m.deg = (int)(x1 - x0);
                     pacc.c1++;
                     pacc.c2 += m.deg;
                     return true;
@@ -1687,19 +1706,23 @@ __device__ __forceinline__ void rb_finish(const KArgs &a, int v, int ps, const G
     }
 }
 
-// Candidate test: the vertex's part is oversized and its weight is small
-// enough (2k * vw <= 3 (k * w(P_s) - W)). Writes the "no candidate" outputs.
-__device__ __forceinline__ bool rb_candidate(const KArgs &a, int v, int ps, int vwv, const GV &gv)
+// Outputs of a vertex that is no rebalancing candidate.
+__device__ __forceinline__ void rb_no_candidate(const KArgs &a, int v)
 {
-    const int gp = gv.poff + ps;
-    const int64_t k = gv.k;
-    if (a.isA[gp] && 2 * k * vwv <= 3 * (k * a.w[gp] - gv.W)) return true;
     a.slot[v] = 255;
     if (a.dbg_loss) {
         a.dbg_loss[v] = INT64_MIN;
         a.dbg_slot[v] = -1;
         a.dbg_pd[v] = -1;
     }
+}
+
+// Candidate test: the vertex's part is oversized and its weight is small
+// enough (2k * vw <= 3 (k * w(P_s) - W)). Writes the "no candidate" outputs.
+__device__ __forceinline__ bool rb_candidate(const KArgs &a, int v, int ps, int vwv, const GV &gv)
+{
+    if (rb_is_candidate(a, ps, vwv, gv)) return true;
+    rb_no_candidate(a, v);
     return false;
 }
 
@@ -1791,9 +1814,14 @@ __device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nb
     }
 }
 
-template <bool B, int ROLE, int GS = 8, int RS = 32 / GS>
+// Small-row role with PC (one graph): the per-part candidate bounds
+// 3 (k w(p) - W) (-1 outside A) and the B flags are copied to LDS first, so
+// a vertex's candidate test and its neighbours' B tests read LDS instead of
+// waiting on dependent global loads.
+template <bool B, int ROLE, int GS = 8, int RS = 32 / GS, bool PC = false>
 __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int hmode)
 {
+    constexpr bool pcache = PC && !B && ROLE == 1;
     extern __shared__ int32_t lds[];
     if (!any_rb(a)) return;
     const int stride = a.k + 1;
@@ -1813,6 +1841,16 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int hmode)
         constexpr int RS_ = RS;
         const int ng = BLOCK / GS;
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
+        const int coff = (hoff + (hmode == HIST_LDS ? a.k * NSLOT : 0) + 1) & ~1;
+        int64_t *cthr = reinterpret_cast<int64_t *>(lds + coff);
+        uint8_t *cB = reinterpret_cast<uint8_t *>(cthr + a.k);
+        if (pcache) {
+            const int64_t kk = pv.k;
+            for (int p = threadIdx.x; p < a.k; p += BLOCK) {
+                cthr[p] = a.isA[p] ? 3 * (kk * a.w[p] - pv.W) : -1;
+                cB[p] = a.isB[p];
+            }
+        }
         __syncthreads();
         int32_t *tab = lds + (threadIdx.x / GS) * stride;
         int32_t *q = lds + ng * stride + (threadIdx.x >> 6) * 64;
@@ -1827,6 +1865,16 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int hmode)
                     if (!is_rb(pv.kind)) return false;
                     m.ps = a.P[m.v];
                     m.aux = a.vw ? a.vw[m.v] : 1;
+                    if (pcache) {
+                        const int64_t x0 = a.xadj[m.v], x1 = a.xadj[m.v + 1];
+                        if (2 * (int64_t)pv.k * m.aux > cthr[m.ps]) {
+                            rb_no_candidate(a, m.v);
+                            return false;
+                        }
+                        m.s = x0;
+                        m.deg = (int)(x1 - x0);
+                        return true;
+                    }
                     if (!rb_candidate(a, m.v, m.ps, m.aux, pv)) return false;
                     m.s = a.xadj[m.v];
                     m.deg = (int)(a.xadj[m.v + 1] - m.s);
@@ -1842,7 +1890,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int hmode)
                     for (int r = 0; r < RS_; r++) {
                         if (cu[r] > 0) {
                             if (pu[r] == t.ps) cs += cu[r];
-                            else if (a.isB[rv.poff + pu[r]]) {
+                            else if (pcache ? cB[pu[r]] : a.isB[rv.poff + pu[r]]) {
                                 const uint64_t k2 = conn_key(cu[r], pu[r]);
                                 best = k2 > best ? k2 : best;
                                 sumB += cu[r];
@@ -2473,6 +2521,10 @@ constexpr int K_G4 = 120;
 // LDS of one compute unit (gfx950).
 constexpr size_t LDS_PER_CU = 160 * 1024;
 
+// Per-part candidate bounds (int64) and B flags of the small-row loss
+// kernel, plus 4 bytes of alignment slack.
+static size_t rb_cache_lds(int k) { return (size_t)k * 9 + 4; }
+
 // Dynamic LDS of the loss kernel of a role (tables and queue), without the
 // block histogram.
 static size_t rb_role_lds(int role, int k)
@@ -2494,6 +2546,7 @@ struct Plan {
     int grid_lch;  // chunk kernels (0: no chunked rows)
     bool hist_fused;  // the loss kernels build the histogram (one graph, LDS room)
     bool cut_fused;   // the tile-sum blocks find the cut-off slots (one graph)
+    bool loss_cache;  // the small-row loss kernel keeps per-part bounds in LDS (one graph)
     int grid_lfin, nL;
     int grid_v;              // grid of the list-building kernels
     int32_t *blkcnt, *lcnt;  // their scratch
@@ -2550,6 +2603,11 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
         if (per > 65536 || (size_t)div_up(rgrid[r], ctx->num_cu) * per > LDS_PER_CU) pl.hist_fused = false;
     }
     pl.cut_fused = a.vg == nullptr && k <= 1024;
+    {
+        const size_t per = rb_role_lds(1, k) + (pl.hist_fused ? (size_t)k * NSLOT * 4 : 0) + rb_cache_lds(k);
+        pl.loss_cache = a.vg == nullptr && k <= 1024 && per <= 65536 &&
+                        (size_t)div_up(t.gS, ctx->num_cu) * per <= LDS_PER_CU;
+    }
     pl.grid_hist = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_flat = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_tile = std::max(1, std::min(a.ntile, ctx->num_cu * 8));
@@ -2597,9 +2655,16 @@ static void launch_rb_loss_t(const Plan &pl, hipStream_t s)
     const int hm = pl.hist_fused ? HIST_LDS : HIST_NONE;
     const size_t hb = pl.hist_fused ? (size_t)t.k * NSLOT * 4 : 0;
     const size_t st = (size_t)(t.k + 1) * 4;
+    const size_t cb = pl.loss_cache ? rb_cache_lds(t.k) : 0;
     if (t.gS) {
-        if (t.k <= K_G4) k_rb_loss<B, 1, 4><<<t.gS, BLOCK, rb_role_lds(1, t.k) + hb, s>>>(t, t.gS, hm);
-        else k_rb_loss<B, 1, 8><<<t.gS, BLOCK, rb_role_lds(1, t.k) + hb, s>>>(t, t.gS, hm);
+        const size_t l1 = rb_role_lds(1, t.k) + hb + cb;
+        if (pl.loss_cache) {
+            if (t.k <= K_G4) k_rb_loss<B, 1, 4, 8, true><<<t.gS, BLOCK, l1, s>>>(t, t.gS, hm);
+            else k_rb_loss<B, 1, 8, 4, true><<<t.gS, BLOCK, l1, s>>>(t, t.gS, hm);
+        } else {
+            if (t.k <= K_G4) k_rb_loss<B, 1, 4><<<t.gS, BLOCK, l1, s>>>(t, t.gS, hm);
+            else k_rb_loss<B, 1, 8><<<t.gS, BLOCK, l1, s>>>(t, t.gS, hm);
+        }
     }
     if (t.gM) k_rb_loss<B, 2><<<t.gM, BLOCK, rb_role_lds(2, t.k) + hb, s>>>(t, t.gM, hm);
     if (t.gL) k_rb_loss<B, 3><<<t.gL, BLOCK, rb_role_lds(3, t.k) + hb, s>>>(t, t.gL, hm);
@@ -2695,6 +2760,10 @@ static void set_lds_limits_t()
     (void)hipFuncSetAttribute((const void *)k_gain<B, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 1, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 1, 4, 8, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 1, 8, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              65536);
     (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
@@ -2741,7 +2810,7 @@ int validate_full_csr(jet_context *ctx, const jet_csr *g, hipStream_t s)
     JET_TRY(hipMemcpyAsync(xadj.data(), g->xadj, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
     if (nnz) JET_TRY(hipMemcpyAsync(adj.data(), g->adjncy, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
     if (nnz && g->adjwgt) JET_TRY(hipMemcpyAsync(ew.data(), g->adjwgt, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     if (xadj[0] != 0 || xadj[n] != nnz) return JET_EGRAPH;
     std::vector<std::pair<uint64_t, int32_t>> kw(nnz), rkw(nnz);
     for (int v = 0; v < n; v++) {
@@ -2908,7 +2977,7 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     JET_TRY(hipMemcpyAsync(htot, blkcnt + (size_t)grid_v * NCLS, sizeof(int32_t) * NCLS, hipMemcpyDeviceToHost, s));
     JET_TRY(hipMemcpyAsync(xends, L.u.xadj, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     JET_TRY(hipMemcpyAsync(xends + 1, L.u.xadj + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     if (xends[0] != 0 || xends[1] != L.u.nnz || hcnt[1]) return JET_EGRAPH;
     for (int g = 0; g < G; g++)
         if (hcs[g].bad_part) return JET_EPART;
@@ -2979,7 +3048,7 @@ static int compact_lists(jet_context *ctx, Plan &pl, hipStream_t s)
     int32_t *pin = (int32_t *)pinned_get(ctx, 4096);
     JET_TRY(hipMemcpyAsync(pin + 16, ctot, sizeof(int32_t) * NCLS, hipMemcpyDeviceToHost, s));
     if (a.nlch > 0) JET_TRY(hipMemcpyAsync(pin + 24, lmeta, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     int32_t tot[NCLS];
     a.binoff[0] = 0;
     for (int c = 0; c < NCLS; c++) {
@@ -3038,11 +3107,31 @@ static int capture_pair(jet_context *ctx, Plan &pl, IterGraph &ig)
     return JET_OK;
 }
 
-static int run_loop(jet_context *ctx, Plan &pl, bool prof, hipStream_t s, int &launched)
+// Iterations launched between two looks at the loop state. One graph: the
+// loop cannot end before the stall counter reaches
+// stall_limit, so each chunk is what the counter still allows (at least 4,
+// rounded up to whole pairs, at most 64 and never past max_iters), the
+// first stall_limit + 1: few iterations run past the end and few waits are
+// spent. A batch starts at 8 (4 without graph replay) and doubles up to 32.
+static int single_chunk(const Ctl &c0, int left)
 {
+    if (c0.max_iters > 0) left = std::min(left, c0.max_iters - c0.t);
+    return (std::min(std::max(left, 4), 64) + 1) & ~1;
+}
+
+static int next_chunk(bool single, const Ctl &c0, int chunk)
+{
+    if (single) return single_chunk(c0, c0.stall_limit - c0.stall);
+    return std::min(chunk * 2, 32);
+}
+
+static int run_loop(jet_context *ctx, Plan &pl, bool prof, hipStream_t s, int &launched, const Ctl *single_ctl)
+{
+    static_assert(64 + sizeof(Ctl) <= 4096, "pinned scratch holds the done count and one controller");
     int32_t *pin = (int32_t *)pinned_get(ctx, 4096);
     if (!pin) return JET_ENOMEM;
-    int chunk = 4;
+    Ctl *pin_ctl = (Ctl *)((char *)pin + 64);
+    const bool single = single_ctl != nullptr;
     launched = 0;
     // a batch drops the vertices of finished graphs from its lists whenever
     // the number of running graphs has halved since the last rebuild
@@ -3055,16 +3144,24 @@ static int run_loop(jet_context *ctx, Plan &pl, bool prof, hipStream_t s, int &l
         rebuilt = true;
         return compact_lists(ctx, pl, s);
     };
-    if (!prof && ctx->graphs && ctx->cap) {
+    // loop state after a chunk: graphs done (and graph 0's controller)
+    auto look = [&]() -> int {
+        JET_TRY(hipMemcpyAsync(pin, pl.plain.cnt + CNT_DONE, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (single) JET_TRY(hipMemcpyAsync(pin_ctl, pl.plain.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        JET_TRY(stream_wait(ctx, s));
+        return JET_OK;
+    };
+    const bool graphs = !prof && ctx->graphs && ctx->cap;
+    int chunk = single ? single_chunk(*single_ctl, single_ctl->stall_limit + 1) : (graphs ? 8 : 4);
+    if (graphs) {
         IterGraph ig;
         int st = capture_pair(ctx, pl, ig);
         if (st) return st;
-        chunk = 8;
         for (;;) {
             for (int i = 0; i < chunk; i += 2) JET_TRY(hipGraphLaunch(ig.x, s));
             launched += chunk;
-            JET_TRY(hipMemcpyAsync(pin, pl.plain.cnt + CNT_DONE, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            JET_TRY(hipStreamSynchronize(s));
+            st = look();
+            if (st) return st;
             if (pin[0] >= pl.G) break;
             bool rebuilt = false;
             st = maybe_compact(pin[0], rebuilt);
@@ -3074,7 +3171,7 @@ static int run_loop(jet_context *ctx, Plan &pl, bool prof, hipStream_t s, int &l
                 st = capture_pair(ctx, pl, ig);
                 if (st) return st;
             }
-            chunk = std::min(chunk * 2, 32);
+            chunk = next_chunk(single, *pin_ctl, chunk);
         }
         return JET_OK;
     }
@@ -3095,13 +3192,13 @@ static int run_loop(jet_context *ctx, Plan &pl, bool prof, hipStream_t s, int &l
             launched++;
         }
         JET_TRY(hipGetLastError());
-        JET_TRY(hipMemcpyAsync(pin, pl.plain.cnt + CNT_DONE, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        JET_TRY(hipStreamSynchronize(s));
+        const int st = look();
+        if (st) return st;
         if (pin[0] >= pl.G) break;
         bool rebuilt = false;
-        const int st = maybe_compact(pin[0], rebuilt);
-        if (st) return st;
-        chunk = std::min(chunk * 2, 32);
+        const int st2 = maybe_compact(pin[0], rebuilt);
+        if (st2) return st2;
+        chunk = next_chunk(single, *pin_ctl, chunk);
     }
     return JET_OK;
 }
@@ -3147,7 +3244,7 @@ static int refine_trivial(jet_context *ctx, const jet_csr *g, const jet_params *
     if (n > 0 && g->vwgt) {
         std::vector<int32_t> vw(n);
         JET_TRY(hipMemcpyAsync(vw.data(), g->vwgt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-        JET_TRY(hipStreamSynchronize(s));
+        JET_TRY(stream_wait(ctx, s));
         W = 0;
         for (int32_t x : vw) W += x;
     }
@@ -3156,7 +3253,7 @@ static int refine_trivial(jet_context *ctx, const jet_csr *g, const jet_params *
         pw[0] = W;
         JET_TRY(hipMemcpyAsync(part_weights_out, pw.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, s));
     }
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     if (stats) {
         memset(stats, 0, sizeof(*stats));
         stats->max_part_weight = W;
@@ -3219,7 +3316,7 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     JET_TRY(hipEventRecord(ctx->ev[1], s));
     const bool prof = prm->flags & JET_F_PROFILE;
     int launched = 0;
-    st = run_loop(ctx, pl, prof, s, launched);
+    st = run_loop(ctx, pl, prof, s, launched, &L.hc[0]);
     if (st) return st;
     k_copy_best<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain);
     JET_TRY(hipEventRecord(ctx->ev[2], s));
@@ -3235,7 +3332,7 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     if (trace_dev && ncopy > 0)
         JET_TRY(hipMemcpyAsync(trace_host, trace_dev, sizeof(jet_trace_rec) * ncopy, hipMemcpyDeviceToHost, s));
     JET_TRY(hipEventRecord(ctx->ev[3], s));
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     take_state(ctx, L);
     const Ctl &hc = L.hc[0];
     const int ntr = std::min(hc.t, hc.trace_cap);
@@ -3248,7 +3345,7 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
         std::vector<int8_t> kinds(std::max(nk, 1));
         if (nk > 0) {
             JET_TRY(hipMemcpyAsync(kinds.data(), pl.plain.kinds, nk, hipMemcpyDeviceToHost, s));
-            JET_TRY(hipStreamSynchronize(s));
+            JET_TRY(stream_wait(ctx, s));
         }
         // launch i ran iteration i (the kind log is written before t advances)
         for (int i = 0; i < nk; i++) {
@@ -3392,7 +3489,7 @@ int refine_batch(jet_context *ctx, int count, const jet_csr *graphs, const jet_p
     int32_t *hbad = (int32_t *)pinned_get(ctx, 4096);
     if (!hbad) return JET_ENOMEM;
     JET_TRY(hipMemcpyAsync(hbad, ubad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     if (hbad[0]) return JET_EGRAPH;
     L.u.n = (int32_t)N;
     L.u.nnz = NNZ;
@@ -3411,7 +3508,7 @@ int refine_batch(jet_context *ctx, int count, const jet_csr *graphs, const jet_p
     if (st) return st;
     JET_TRY(hipEventRecord(ctx->ev[1], s));
     int launched = 0;
-    st = run_loop(ctx, pl, false, s, launched);
+    st = run_loop(ctx, pl, false, s, launched, nullptr);
     if (st) return st;
     k_copy_best<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain);
     JET_TRY(hipEventRecord(ctx->ev[2], s));
@@ -3428,7 +3525,7 @@ int refine_batch(jet_context *ctx, int count, const jet_csr *graphs, const jet_p
                                        hipMemcpyDeviceToHost, s));
         }
     JET_TRY(hipEventRecord(ctx->ev[3], s));
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     take_state(ctx, L);
     if (traces)
         for (int j = 0; j < G; j++) {
@@ -3459,6 +3556,21 @@ using namespace jet;
 
 // --------------------------------------------------------------- C ABI ------
 
+// The refinement loop reads its state back many times per partition; a
+// thread that sleeps in the runtime until the stream drains wakes up tens of
+// microseconds late each time, so the wait polls an event instead.
+hipError_t jet::stream_wait(jet_context *ctx, hipStream_t s)
+{
+    if (!ctx->poll_wait || !ctx->wait_ev) return hipStreamSynchronize(s);
+    hipError_t e = hipEventRecord(ctx->wait_ev, s);
+    if (e != hipSuccess) return e;
+    for (;;) {
+        e = hipEventQuery(ctx->wait_ev);
+        if (e != hipErrorNotReady) return e;
+        __builtin_ia32_pause();
+    }
+}
+
 extern "C" int jet_context_create(jet_context **out, int device)
 {
     if (!out) return JET_EINVAL;
@@ -3482,6 +3594,14 @@ extern "C" int jet_context_create(jet_context **out, int device)
     }
     const char *ng = getenv("JET_NO_GRAPH");
     ctx->graphs = !(ng && ng[0] == '1');
+    const char *bw = getenv("JET_BLOCKING_WAIT");
+    ctx->poll_wait = !(bw && bw[0] == '1');
+    e = hipEventCreateWithFlags(&ctx->wait_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        int st = hip_status(ctx, e);
+        jet_context_destroy(ctx);
+        return st;
+    }
     e = hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         int st = hip_status(ctx, e);
@@ -3510,6 +3630,8 @@ extern "C" void jet_context_destroy(jet_context *ctx)
     for (auto &ev : ctx->ev)
         if (ev) (void)hipEventDestroy(ev);
     for (auto ev : ctx->prof_ev) (void)hipEventDestroy(ev);
+    if (ctx->wait_ev) (void)hipEventDestroy(ctx->wait_ev);
+    ctx->part_arena.release();
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;
 }
@@ -3603,7 +3725,7 @@ extern "C" int jet_lp_step(jet_context *ctx, const jet_csr *g, const jet_params 
     launch_after(pl, s);
     k_lp_outputs<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain, inX, move);
     JET_TRY(hipGetLastError());
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     return JET_OK;
 }
 
@@ -3641,6 +3763,6 @@ extern "C" int jet_rebalance_step(jet_context *ctx, const jet_csr *g, const jet_
     launch_rb_select(pl, s);
     JET_TRY(hipGetLastError());
     JET_TRY(hipMemcpyAsync(dest, p.dest, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
-    JET_TRY(hipStreamSynchronize(s));
+    JET_TRY(stream_wait(ctx, s));
     return JET_OK;
 }
