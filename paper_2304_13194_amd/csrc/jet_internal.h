@@ -23,9 +23,11 @@ constexpr int NSHARD = 64;         // shards per counter row and graph
 constexpr int KIND_LOG = 1 << 16;  // iterations whose kind is logged (graph 0)
 
 enum Kind { KIND_DONE = 0, KIND_LP = 1, KIND_RW = 2, KIND_RS = 3 };
-// Degree classes: 0 isolated, 1 small (<= 32), 2 medium (<= 1024), 3 large.
-enum Cls { CLS_Z = 0, CLS_S = 1, CLS_M = 2, CLS_L = 3, NCLS = 4 };
+// Degree classes: 0 isolated, 1 small (<= 32), 2 small wide (<= 64), 3 medium
+// (<= 1024), 4 large.
+enum Cls { CLS_Z = 0, CLS_S = 1, CLS_S2 = 2, CLS_M = 3, CLS_L = 4, NCLS = 5 };
 constexpr int S_MAXDEG = 32;
+constexpr int S2_MAXDEG = 64;
 constexpr int M_MAXDEG = 1024;
 
 // Launch-wide counts: CNT_DONE graphs finished; then two rows (selected by

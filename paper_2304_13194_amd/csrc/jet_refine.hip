@@ -36,6 +36,7 @@
 
 #include <algorithm>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "jet_device.h"
@@ -232,7 +233,7 @@ __device__ __forceinline__ int flat_vertex(const KArgs &a, int i)
 
 __device__ __forceinline__ int degree_class(int64_t d)
 {
-    return d == 0 ? CLS_Z : (d <= S_MAXDEG ? CLS_S : (d <= M_MAXDEG ? CLS_M : CLS_L));
+    return d == 0 ? CLS_Z : (d <= S_MAXDEG ? CLS_S : (d <= S2_MAXDEG ? CLS_S2 : (d <= M_MAXDEG ? CLS_M : CLS_L)));
 }
 
 // ------------------------------------------------------------------ set-up --
@@ -1030,17 +1031,20 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
         racc.to(a, 0);
     }
     if (ROLE == 1) {
-        // groups of GS lanes (rows of up to GS * RS entries), wave-batched
-        constexpr int RS_ = RS;
+        // groups of G lanes (rows of up to G * R entries), wave-batched: the
+        // small class with the kernel's (GS, RS), the wide small class with
+        // groups of 8 lanes and 8 entries each (the first BLOCK / 8 tables)
         const int ng = BLOCK / GS;
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         __syncthreads();
-        int32_t *tab = lds + (threadIdx.x / GS) * stride;
         int32_t *q = lds + ng * stride + (threadIdx.x >> 6) * 64;
         const int wid = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nblk * (BLOCK / 64);
-        for (int c = 1; c < NCLS; c++) {
-            if (a.tmap[c] != ROLE) continue;
-            wave_batched<GS>(
+        auto run = [&](int c, auto g_c, auto r_c) {
+            constexpr int G = decltype(g_c)::value, R = decltype(r_c)::value;
+            // a wave keeps to its own tables whatever the group size (the
+            // waves of the block run the two classes unsynchronised)
+            int32_t *tab = lds + ((threadIdx.x >> 6) * (64 / GS) + (threadIdx.x & 63) / G) * stride;
+            wave_batched<G>(
                 a.bins + a.binoff[c], walk<B>(a.binoff[c + 1] - a.binoff[c], wid, nwaves, 64), q,
                 [&](Meta &m) -> bool {
                     m.g = gof<B>(a, m.v);
@@ -1063,12 +1067,12 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
                     return true;
                 },
                 [&](const Meta &t, int gl) {
-                    int pu[RS_], cu[RS_];
-                    group_conn_row<GS, RS_>(a, t.s, t.deg, gl, tab, pu, cu);
+                    int pu[R], cu[R];
+                    group_conn_row<G, R>(a, t.s, t.deg, gl, tab, pu, cu);
                     uint64_t best = 0;
                     int cs = 0;
 #pragma unroll
-                    for (int r = 0; r < RS_; r++) {
+                    for (int r = 0; r < R; r++) {
                         if (cu[r] > 0) {
                             if (pu[r] == t.ps) cs += cu[r];
                             else {
@@ -1077,15 +1081,17 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
                             }
                         }
                     }
-                    best = gmax_u64<GS>(best);
-                    cs = gsum<GS>(cs);
+                    best = gmax_u64<G>(best);
+                    cs = gsum<G>(cs);
                     if (gl == 0) {
                         rv.sel<B>(a, t.g);
                         racc.sel<B>(a, t.g);
                         racc.c0 += gain_finish(a, t.v, t.ps, best, cs, rv.cn, rv.cd);
                     }
                 });
-        }
+        };
+        if (a.tmap[CLS_S] == ROLE) run(CLS_S, std::integral_constant<int, GS>{}, std::integral_constant<int, RS>{});
+        if (a.tmap[CLS_S2] == ROLE) run(CLS_S2, std::integral_constant<int, 8>{}, std::integral_constant<int, 8>{});
     } else if (ROLE == 2) {
         // one wave per vertex, walking its list interleaved with the other waves
         const int ng = BLOCK / 64;
@@ -1156,7 +1162,7 @@ __device__ void afterburner_body(const KArgs &a, int b)
         int32_t *q = s_q + (threadIdx.x >> 6) * 64;
         wave_batched<8>(
             a.bins + a.binoff[CLS_S],
-            walk<B>(a.binoff[CLS_S + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6), a.gS * (BLOCK / 64),
+            walk<B>(a.binoff[CLS_S2 + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6), a.gS * (BLOCK / 64),
                  64),
             q,
             [&](Meta &m) -> bool {
@@ -1289,7 +1295,7 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
         int32_t *q = s_q + (threadIdx.x >> 6) * 64;
         wave_batched<8>(
             a.bins + a.binoff[CLS_S],
-            walk<B>(a.binoff[CLS_S + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6), a.gS * (BLOCK / 64),
+            walk<B>(a.binoff[CLS_S2 + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6), a.gS * (BLOCK / 64),
                  64),
             q,
             [&](Meta &m) -> bool {
@@ -1629,7 +1635,7 @@ __global__ __launch_bounds__(BLOCK) void k_ldcut(KArgs a)
 __global__ __launch_bounds__(BLOCK) void k_lchunk_count(const int64_t *xadj, const int32_t *bins, const int32_t *ctot,
                                                         int32_t *lcnt)
 {
-    const int off = ctot[CLS_Z] + ctot[CLS_S] + ctot[CLS_M], nL = ctot[CLS_L];
+    const int off = ctot[CLS_Z] + ctot[CLS_S] + ctot[CLS_S2] + ctot[CLS_M], nL = ctot[CLS_L];
     for (int li = blockIdx.x * BLOCK + threadIdx.x; li < nL; li += gridDim.x * BLOCK) {
         const int v = bins[off + li];
         lcnt[li] = (int)((xadj[v + 1] - xadj[v] + LCHUNK - 1) / LCHUNK);
@@ -1819,7 +1825,8 @@ __device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nb
 // a vertex's candidate test and its neighbours' B tests read LDS instead of
 // waiting on dependent global loads.
 template <bool B, int ROLE, int GS = 8, int RS = 32 / GS, bool PC = false>
-__global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int hmode)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ROLE == 1 && !B ? 8 : 1)))
+void k_rb_loss(KArgs a, int nblk, int hmode)
 {
     constexpr bool pcache = PC && !B && ROLE == 1;
     extern __shared__ int32_t lds[];
@@ -1838,7 +1845,6 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int hmode)
     if (hmode == HIST_LDS)
         for (int i = threadIdx.x; i < a.k * NSLOT; i += BLOCK) lh[i] = 0;
     if (ROLE == 1) {
-        constexpr int RS_ = RS;
         const int ng = BLOCK / GS;
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         const int coff = (hoff + (hmode == HIST_LDS ? a.k * NSLOT : 0) + 1) & ~1;
@@ -1852,12 +1858,16 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int hmode)
             }
         }
         __syncthreads();
-        int32_t *tab = lds + (threadIdx.x / GS) * stride;
         int32_t *q = lds + ng * stride + (threadIdx.x >> 6) * 64;
         const int wid = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nblk * (BLOCK / 64);
-        for (int c = 1; c < NCLS; c++) {
-            if (a.tmap[c] != ROLE) continue;
-            wave_batched<GS>(
+        // the small class with the kernel's (GS, RS), the wide small class
+        // with groups of 8 lanes and 8 entries each
+        auto run = [&](int c, auto g_c, auto r_c) {
+            constexpr int G = decltype(g_c)::value, R = decltype(r_c)::value;
+            // a wave keeps to its own tables whatever the group size (the
+            // waves of the block run the two classes unsynchronised)
+            int32_t *tab = lds + ((threadIdx.x >> 6) * (64 / GS) + (threadIdx.x & 63) / G) * stride;
+            wave_batched<G>(
                 a.bins + a.binoff[c], walk<B>(a.binoff[c + 1] - a.binoff[c], wid, nwaves, 64), q,
                 [&](Meta &m) -> bool {
                     m.g = gof<B>(a, m.v);
@@ -1882,12 +1892,12 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int hmode)
                 },
                 [&](const Meta &t, int gl) {
                     rv.sel<B>(a, t.g);
-                    int pu[RS_], cu[RS_];
-                    group_conn_row<GS, RS_>(a, t.s, t.deg, gl, tab, pu, cu);
+                    int pu[R], cu[R];
+                    group_conn_row<G, R>(a, t.s, t.deg, gl, tab, pu, cu);
                     uint64_t best = 0;
                     int cs = 0, sumB = 0, cntB = 0;
 #pragma unroll
-                    for (int r = 0; r < RS_; r++) {
+                    for (int r = 0; r < R; r++) {
                         if (cu[r] > 0) {
                             if (pu[r] == t.ps) cs += cu[r];
                             else if (pcache ? cB[pu[r]] : a.isB[rv.poff + pu[r]]) {
@@ -1898,17 +1908,19 @@ __global__ __launch_bounds__(BLOCK) void k_rb_loss(KArgs a, int nblk, int hmode)
                             }
                         }
                     }
-                    best = gmax_u64<GS>(best);
-                    cs = gsum<GS>(cs);
-                    sumB = gsum<GS>(sumB);
-                    cntB = gsum<GS>(cntB);
+                    best = gmax_u64<G>(best);
+                    cs = gsum<G>(cs);
+                    sumB = gsum<G>(sumB);
+                    cntB = gsum<G>(cntB);
                     if (gl == 0) {
                         rb_finish(a, t.v, t.ps, rv, best, cs, sumB, cntB, t.aux, hmode, lh);
                         racc.sel<B>(a, t.g);
                         racc.c0++;
                     }
                 });
-        }
+        };
+        if (a.tmap[CLS_S] == ROLE) run(CLS_S, std::integral_constant<int, GS>{}, std::integral_constant<int, RS>{});
+        if (a.tmap[CLS_S2] == ROLE) run(CLS_S2, std::integral_constant<int, 8>{}, std::integral_constant<int, 8>{});
     } else if (ROLE == 2) {
         const int ng = BLOCK / 64;
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
@@ -2566,10 +2578,10 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
     KArgs t = a;
     t.tmap[0] = 0;
     const int k = a.k;
-    if (k <= 495) { t.tmap[1] = 1; t.tmap[2] = 2; t.tmap[3] = 3; }
-    else if (k <= 4095) { t.tmap[1] = 2; t.tmap[2] = 2; t.tmap[3] = 3; }
-    else { t.tmap[1] = 3; t.tmap[2] = 3; t.tmap[3] = 3; }
-    if (chunked) t.tmap[3] = 0;
+    if (k <= 495) { t.tmap[CLS_S] = 1; t.tmap[CLS_S2] = 1; t.tmap[CLS_M] = 2; t.tmap[CLS_L] = 3; }
+    else if (k <= 4095) { t.tmap[CLS_S] = 2; t.tmap[CLS_S2] = 2; t.tmap[CLS_M] = 2; t.tmap[CLS_L] = 3; }
+    else { t.tmap[CLS_S] = 3; t.tmap[CLS_S2] = 3; t.tmap[CLS_M] = 3; t.tmap[CLS_L] = 3; }
+    if (chunked) t.tmap[CLS_L] = 0;
     int64_t role_cnt[4] = {0, 0, 0, 0};
     for (int c = 1; c < NCLS; c++) role_cnt[t.tmap[c]] += cnt[c];
     t.gS = std::min(div_up(role_cnt[1], BLOCK / 8), maxb);
@@ -2585,11 +2597,11 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
     pl.grid_rbtab = t.gS + t.gM + t.gL + t.gZ;
     // plain row kernels: roles follow the classes directly
     KArgs p = a;
-    p.tmap[0] = 0; p.tmap[1] = 1; p.tmap[2] = 2; p.tmap[3] = 3;
-    p.gS = std::min(div_up(cnt[1], BLOCK / 8), maxb);
-    p.gM = std::min(div_up(cnt[2], BLOCK / 64), maxb);
-    p.gL = chunked ? 0 : std::min(cnt[3], maxb);
-    p.gZ = std::min(div_up(cnt[0], BLOCK), maxb);
+    p.tmap[CLS_Z] = 0; p.tmap[CLS_S] = 1; p.tmap[CLS_S2] = 1; p.tmap[CLS_M] = 2; p.tmap[CLS_L] = 3;
+    p.gS = std::min(div_up(cnt[CLS_S] + cnt[CLS_S2], BLOCK / 8), maxb);
+    p.gM = std::min(div_up(cnt[CLS_M], BLOCK / 64), maxb);
+    p.gL = chunked ? 0 : std::min(cnt[CLS_L], maxb);
+    p.gZ = std::min(div_up(cnt[CLS_Z], BLOCK), maxb);
     pl.grid_plain = p.gS + p.gM + p.gL + p.gZ;
     pl.tab = t;
     pl.plain = p;
