@@ -1015,7 +1015,7 @@ __device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int 
 // groups, waves, blocks), so each keeps its own register budget; a.tmap says
 // which classes a role serves. Group tables are padded to k + 1 ints so the
 // tables of neighbouring groups start in different LDS banks.
-template <bool B, int ROLE, int GS = 8, int RS = 32 / GS>
+template <bool B, int ROLE, int GS = 8, int RS = 32 / GS, int CL = CLS_S>
 __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
 {
     if (!any_kind(a, KIND_LP)) return;
@@ -1031,21 +1031,20 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
         racc.to(a, 0);
     }
     if (ROLE == 1) {
-        // groups of G lanes (rows of up to G * R entries), wave-batched: the
-        // small class with the kernel's (GS, RS), the wide small class with
-        // groups of 8 lanes and 8 entries each (the first BLOCK / 8 tables)
+        // groups of G lanes (rows of up to G * R entries) over one small
+        // class, wave-batched. CL = NCLS: blocks [0, gS) take class S with
+        // (GS, RS), the next gS2 blocks class S2 with groups of 8 lanes.
         const int ng = BLOCK / GS;
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         __syncthreads();
         int32_t *q = lds + ng * stride + (threadIdx.x >> 6) * 64;
-        const int wid = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nblk * (BLOCK / 64);
-        auto run = [&](int c, auto g_c, auto r_c) {
+        auto body = [&](auto g_c, auto r_c, int cl, int bid, int nb) {
             constexpr int G = decltype(g_c)::value, R = decltype(r_c)::value;
-            // a wave keeps to its own tables whatever the group size (the
-            // waves of the block run the two classes unsynchronised)
-            int32_t *tab = lds + ((threadIdx.x >> 6) * (64 / GS) + (threadIdx.x & 63) / G) * stride;
+            if (a.tmap[cl] != ROLE) return;
+            int32_t *tab = lds + (threadIdx.x / G) * stride;
+            const int wid = bid * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nb * (BLOCK / 64);
             wave_batched<G>(
-                a.bins + a.binoff[c], walk<B>(a.binoff[c + 1] - a.binoff[c], wid, nwaves, 64), q,
+                a.bins + a.binoff[cl], walk<B>(a.binoff[cl + 1] - a.binoff[cl], wid, nwaves, 64), q,
                 [&](Meta &m) -> bool {
                     m.g = gof<B>(a, m.v);
                     pv.sel<B>(a, m.g);
@@ -1090,8 +1089,11 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
                     }
                 });
         };
-        if (a.tmap[CLS_S] == ROLE) run(CLS_S, std::integral_constant<int, GS>{}, std::integral_constant<int, RS>{});
-        if (a.tmap[CLS_S2] == ROLE) run(CLS_S2, std::integral_constant<int, 8>{}, std::integral_constant<int, 8>{});
+        if (CL != NCLS) body(std::integral_constant<int, GS>{}, std::integral_constant<int, RS>{}, CL, blockIdx.x, nblk);
+        else if ((int)blockIdx.x < a.gS)
+            body(std::integral_constant<int, GS>{}, std::integral_constant<int, RS>{}, CLS_S, blockIdx.x, a.gS);
+        else
+            body(std::integral_constant<int, 8>{}, std::integral_constant<int, 8>{}, CLS_S2, blockIdx.x - a.gS, a.gS2);
     } else if (ROLE == 2) {
         // one wave per vertex, walking its list interleaved with the other waves
         const int ng = BLOCK / 64;
@@ -1824,7 +1826,7 @@ __device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nb
 // 3 (k w(p) - W) (-1 outside A) and the B flags are copied to LDS first, so
 // a vertex's candidate test and its neighbours' B tests read LDS instead of
 // waiting on dependent global loads.
-template <bool B, int ROLE, int GS = 8, int RS = 32 / GS, bool PC = false>
+template <bool B, int ROLE, int GS = 8, int RS = 32 / GS, bool PC = false, int CL = CLS_S>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ROLE == 1 && !B ? 8 : 1)))
 void k_rb_loss(KArgs a, int nblk, int hmode)
 {
@@ -1859,16 +1861,14 @@ void k_rb_loss(KArgs a, int nblk, int hmode)
         }
         __syncthreads();
         int32_t *q = lds + ng * stride + (threadIdx.x >> 6) * 64;
-        const int wid = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nblk * (BLOCK / 64);
-        // the small class with the kernel's (GS, RS), the wide small class
-        // with groups of 8 lanes and 8 entries each
-        auto run = [&](int c, auto g_c, auto r_c) {
+        // one small class per block, as in the gain kernel
+        auto body = [&](auto g_c, auto r_c, int cl, int bid, int nb) {
             constexpr int G = decltype(g_c)::value, R = decltype(r_c)::value;
-            // a wave keeps to its own tables whatever the group size (the
-            // waves of the block run the two classes unsynchronised)
-            int32_t *tab = lds + ((threadIdx.x >> 6) * (64 / GS) + (threadIdx.x & 63) / G) * stride;
+            if (a.tmap[cl] != ROLE) return;
+            int32_t *tab = lds + (threadIdx.x / G) * stride;
+            const int wid = bid * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nb * (BLOCK / 64);
             wave_batched<G>(
-                a.bins + a.binoff[c], walk<B>(a.binoff[c + 1] - a.binoff[c], wid, nwaves, 64), q,
+                a.bins + a.binoff[cl], walk<B>(a.binoff[cl + 1] - a.binoff[cl], wid, nwaves, 64), q,
                 [&](Meta &m) -> bool {
                     m.g = gof<B>(a, m.v);
                     pv.sel<B>(a, m.g);
@@ -1919,8 +1919,11 @@ void k_rb_loss(KArgs a, int nblk, int hmode)
                     }
                 });
         };
-        if (a.tmap[CLS_S] == ROLE) run(CLS_S, std::integral_constant<int, GS>{}, std::integral_constant<int, RS>{});
-        if (a.tmap[CLS_S2] == ROLE) run(CLS_S2, std::integral_constant<int, 8>{}, std::integral_constant<int, 8>{});
+        if (CL != NCLS) body(std::integral_constant<int, GS>{}, std::integral_constant<int, RS>{}, CL, blockIdx.x, nblk);
+        else if ((int)blockIdx.x < a.gS)
+            body(std::integral_constant<int, GS>{}, std::integral_constant<int, RS>{}, CLS_S, blockIdx.x, a.gS);
+        else
+            body(std::integral_constant<int, 8>{}, std::integral_constant<int, 8>{}, CLS_S2, blockIdx.x - a.gS, a.gS2);
     } else if (ROLE == 2) {
         const int ng = BLOCK / 64;
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
@@ -2537,6 +2540,10 @@ constexpr size_t LDS_PER_CU = 160 * 1024;
 // kernel, plus 4 bytes of alignment slack.
 static size_t rb_cache_lds(int k) { return (size_t)k * 9 + 4; }
 
+// Dynamic LDS of the wide small-row kernels (groups of 8 lanes), without the
+// block histogram.
+static size_t rb_s2_lds(int k) { return (BLOCK / 8) * (size_t)(k + 1) * 4 + BLOCK * 4; }
+
 // Dynamic LDS of the loss kernel of a role (tables and queue), without the
 // block histogram.
 static size_t rb_role_lds(int role, int k)
@@ -2584,7 +2591,8 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
     if (chunked) t.tmap[CLS_L] = 0;
     int64_t role_cnt[4] = {0, 0, 0, 0};
     for (int c = 1; c < NCLS; c++) role_cnt[t.tmap[c]] += cnt[c];
-    t.gS = std::min(div_up(role_cnt[1], BLOCK / 8), maxb);
+    t.gS = t.tmap[CLS_S] == 1 ? std::min(div_up(cnt[CLS_S], BLOCK / 8), maxb) : 0;
+    t.gS2 = t.tmap[CLS_S2] == 1 ? std::min(div_up(cnt[CLS_S2], BLOCK / 8), maxb) : 0;
     t.gM = std::min(div_up(role_cnt[2], BLOCK / 64), maxb);
     t.gL = std::min((int)role_cnt[3], maxb);
     t.gZ = std::min(div_up(cnt[0], BLOCK), maxb);
@@ -2593,8 +2601,8 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
     if (t.gM) lds = std::max(lds, (size_t)(BLOCK / 64) * k * 4);
     if (t.gL) lds = std::max(lds, (size_t)k * 4);
     pl.lds_tab = lds;
-    pl.grid_tab = t.gS + t.gM + t.gL;
-    pl.grid_rbtab = t.gS + t.gM + t.gL + t.gZ;
+    pl.grid_tab = t.gS + t.gS2 + t.gM + t.gL;
+    pl.grid_rbtab = t.gS + t.gS2 + t.gM + t.gL + t.gZ;
     // plain row kernels: roles follow the classes directly
     KArgs p = a;
     p.tmap[CLS_Z] = 0; p.tmap[CLS_S] = 1; p.tmap[CLS_S2] = 1; p.tmap[CLS_M] = 2; p.tmap[CLS_L] = 3;
@@ -2609,16 +2617,19 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
     // The loss kernels keep a block histogram only where it costs no
     // occupancy: every block of each role stays resident at once.
     pl.hist_fused = a.vg == nullptr;
-    const int rgrid[5] = {0, t.gS, t.gM, t.gL, t.gZ};
+    // (the small-row role: one launch of gS + gS2 blocks when both classes have rows)
+    const int rgrid[5] = {0, t.gS + t.gS2, t.gM, t.gL, t.gZ};
     for (int r = 1; r <= 4; r++) {
-        const size_t per = rb_role_lds(r, k) + (size_t)k * NSLOT * 4;
+        const size_t base = (r == 1 && !t.gS) ? rb_s2_lds(k) : rb_role_lds(r, k);
+        const size_t per = base + (size_t)k * NSLOT * 4;
         if (per > 65536 || (size_t)div_up(rgrid[r], ctx->num_cu) * per > LDS_PER_CU) pl.hist_fused = false;
     }
     pl.cut_fused = a.vg == nullptr && k <= 1024;
     {
-        const size_t per = rb_role_lds(1, k) + (pl.hist_fused ? (size_t)k * NSLOT * 4 : 0) + rb_cache_lds(k);
+        const size_t extra = (pl.hist_fused ? (size_t)k * NSLOT * 4 : 0) + rb_cache_lds(k);
+        const size_t per = (t.gS ? rb_role_lds(1, k) : rb_s2_lds(k)) + extra;
         pl.loss_cache = a.vg == nullptr && k <= 1024 && per <= 65536 &&
-                        (size_t)div_up(t.gS, ctx->num_cu) * per <= LDS_PER_CU;
+                        (size_t)div_up(t.gS + t.gS2, ctx->num_cu) * per <= LDS_PER_CU;
     }
     pl.grid_hist = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_flat = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
@@ -2634,9 +2645,16 @@ static void launch_gain_t(const Plan &pl, hipStream_t s)
 {
     const KArgs &t = pl.tab;
     const size_t st = (size_t)(t.k + 1) * 4;
-    if (t.gS) {
+    // small rows: one launch for both small classes when both are present
+    if (t.gS && t.gS2) {
+        const int g = t.gS + t.gS2;
+        if (t.k <= K_G4) k_gain<B, 1, 4, 8, NCLS><<<g, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, g);
+        else k_gain<B, 1, 8, 4, NCLS><<<g, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, g);
+    } else if (t.gS) {
         if (t.k <= K_G4) k_gain<B, 1, 4><<<t.gS, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, t.gS);
         else k_gain<B, 1, 8><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS);
+    } else if (t.gS2) {
+        k_gain<B, 1, 8, 8, CLS_S2><<<t.gS2, BLOCK, rb_s2_lds(t.k), s>>>(t, t.gS2);
     }
     if (t.gM) k_gain<B, 2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM);
     if (t.gL) k_gain<B, 3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL);
@@ -2668,7 +2686,17 @@ static void launch_rb_loss_t(const Plan &pl, hipStream_t s)
     const size_t hb = pl.hist_fused ? (size_t)t.k * NSLOT * 4 : 0;
     const size_t st = (size_t)(t.k + 1) * 4;
     const size_t cb = pl.loss_cache ? rb_cache_lds(t.k) : 0;
-    if (t.gS) {
+    if (t.gS && t.gS2) {
+        const size_t l1 = rb_role_lds(1, t.k) + hb + cb;
+        const int g = t.gS + t.gS2;
+        if (pl.loss_cache) {
+            if (t.k <= K_G4) k_rb_loss<B, 1, 4, 8, true, NCLS><<<g, BLOCK, l1, s>>>(t, g, hm);
+            else k_rb_loss<B, 1, 8, 4, true, NCLS><<<g, BLOCK, l1, s>>>(t, g, hm);
+        } else {
+            if (t.k <= K_G4) k_rb_loss<B, 1, 4, 8, false, NCLS><<<g, BLOCK, l1, s>>>(t, g, hm);
+            else k_rb_loss<B, 1, 8, 4, false, NCLS><<<g, BLOCK, l1, s>>>(t, g, hm);
+        }
+    } else if (t.gS) {
         const size_t l1 = rb_role_lds(1, t.k) + hb + cb;
         if (pl.loss_cache) {
             if (t.k <= K_G4) k_rb_loss<B, 1, 4, 8, true><<<t.gS, BLOCK, l1, s>>>(t, t.gS, hm);
@@ -2677,6 +2705,10 @@ static void launch_rb_loss_t(const Plan &pl, hipStream_t s)
             if (t.k <= K_G4) k_rb_loss<B, 1, 4><<<t.gS, BLOCK, l1, s>>>(t, t.gS, hm);
             else k_rb_loss<B, 1, 8><<<t.gS, BLOCK, l1, s>>>(t, t.gS, hm);
         }
+    } else if (t.gS2) {
+        const size_t l2 = rb_s2_lds(t.k) + hb + cb;
+        if (pl.loss_cache) k_rb_loss<B, 1, 8, 8, true, CLS_S2><<<t.gS2, BLOCK, l2, s>>>(t, t.gS2, hm);
+        else k_rb_loss<B, 1, 8, 8, false, CLS_S2><<<t.gS2, BLOCK, l2, s>>>(t, t.gS2, hm);
     }
     if (t.gM) k_rb_loss<B, 2><<<t.gM, BLOCK, rb_role_lds(2, t.k) + hb, s>>>(t, t.gM, hm);
     if (t.gL) k_rb_loss<B, 3><<<t.gL, BLOCK, rb_role_lds(3, t.k) + hb, s>>>(t, t.gL, hm);
@@ -2779,6 +2811,24 @@ static void set_lds_limits_t()
     (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_gain<B, 1, 8, 8, CLS_S2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              65536);
+    (void)hipFuncSetAttribute((const void *)k_gain<B, 1, 4, 8, NCLS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              65536);
+    (void)hipFuncSetAttribute((const void *)k_gain<B, 1, 8, 4, NCLS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 1, 4, 8, true, NCLS>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 1, 8, 4, true, NCLS>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 1, 4, 8, false, NCLS>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 1, 8, 4, false, NCLS>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 1, 8, 8, true, CLS_S2>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rb_loss<B, 1, 8, 8, false, CLS_S2>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_apply<B>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_rb_hist<B>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     (void)hipFuncSetAttribute((const void *)k_after_tsum<B>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
