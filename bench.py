@@ -1,7 +1,7 @@
 """Benchmark: Jet refinement on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload stencil128|rmat22|grid64]
-                    [--no-cpu-baseline] [--no-batch] [--no-serve]
+                    [--no-cpu-baseline] [--no-batch] [--no-serve] [--no-ablations]
 
 A step is one full multilevel partition (Algorithm 1: heavy-edge coarsening,
 seeded random coarsest partition, Jet refinement of every level, i.e. every
@@ -26,6 +26,10 @@ Prints one JSON line:
   serving      Poisson arrivals of partition jobs (grids and R-MAT graphs)
                into jet_server: p50 / p99 latency and graphs/s per arrival
                rate, vs partitioning the same jobs one at a time
+  ablations    Jetlp variants (baseline synchronous LP, +locks, +weak or
+               full afterburner, full Jetlp) and phi 0.99 / 0.999 / 0.9999
+               on the main graph and the serving pool's largest R-MAT graph:
+               cut and partition time per variant
 """
 from __future__ import annotations
 
@@ -226,6 +230,31 @@ def serve_bench(J, pool, jobs, rates=(50, 200, 1000, 2000)):
     return out
 
 
+def ablation_bench(J, dg, k, seed, label):
+    """Jetlp ablations and the phi sweep (Section 5, Table lp_versions) on one
+    graph: cut and time of the full multilevel partition per variant."""
+    import torch
+    NL, NA = J.JET_F_LP_NO_LOCKS, J.JET_F_LP_NO_AFTERBURNER
+    variants = [("baseline sync LP", dict(c=(0, 1), flags=NL | NA)),
+                ("+locks", dict(c=(0, 1), flags=NA)),
+                ("+weak afterburner", dict(c=(0, 1), flags=NL)),
+                ("+full afterburner", dict(flags=NL)),
+                ("full Jetlp", dict()),
+                ("full Jetlp, phi 0.99", dict(phi=(99, 100))),
+                ("full Jetlp, phi 0.9999", dict(phi=(9999, 10000)))]
+    rows = []
+    for name, kw in variants:
+        J.partition(dg, k, seed=seed, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        part, st, _ = J.partition(dg, k, seed=seed, **kw)
+        torch.cuda.synchronize()
+        rows.append({"variant": name, "cut": st["cut"], "balanced": bool(st["balanced"]),
+                     "ms": round((time.perf_counter() - t0) * 1e3, 2), "ms_refine": round(st["ms_refine"], 2),
+                     "iters": st["iters"]})
+    return {"graph": label, "k": k, "rows": rows}
+
+
 def cpu_baseline(g, k, seed):
     """The oracle's multilevel partition of the same graph, single thread."""
     from oracle import oracle as O
@@ -245,6 +274,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-ablations", action="store_true")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--graph-cache", default=None,
                     help="directory: reuse the generated main graph across runs (.npz, no pickle)")
@@ -376,6 +406,8 @@ def main():
             "passes": passes,
         },
     }
+    if not args.no_ablations:
+        out["ablations"] = [ablation_bench(J, dg, k, args.seed, f"{args.workload} (n={g.n})")]
     if fut_rgg is not None:
         try:
             graphs = [f.result() for f in fut_rgg]
@@ -387,6 +419,11 @@ def main():
         try:
             pool = [f.result() for f in fut_pool]
             out["serving"] = serve_bench(J, pool, I.serve_jobs(40))
+            if not args.no_ablations:
+                spec = I.SERVE_POOL[-1]  # the largest R-MAT of the pool
+                dgr = J.to_device(pool[-1])
+                out.setdefault("ablations", []).append(
+                    ablation_bench(J, dgr, 64, args.seed, f"R-MAT scale {spec[1]}, edge factor {spec[2]} (n={pool[-1].n})"))
         except Exception as e:
             out["serving"] = {"error": repr(e)}
     if pool_ex is not None:

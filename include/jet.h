@@ -55,6 +55,13 @@ extern "C" {
 #define JET_F_VALIDATE    0x1u  /* full CSR check: range, self-loops, symmetry, duplicates */
 #define JET_F_RETURN_ITER 0x2u  /* return P_iter (state after the last iteration) instead of P_best */
 #define JET_F_PROFILE     0x4u  /* time the connectivity/gain passes (see jet_stats.ms_gain) */
+/* Jetlp ablations (Section 5, component effectiveness, Table lp_versions):
+ * without locks, a vertex moved by one Jetlp may move again in the next;
+ * without the afterburner, every vertex of X moves (F2 is reported as 0).
+ * The paper's "weak afterburner" admits only moves with F >= 0: set
+ * c_num = 0, c_den = 1. The baseline synchronous LP is all three. */
+#define JET_F_LP_NO_LOCKS       0x8u
+#define JET_F_LP_NO_AFTERBURNER 0x10u
 
 typedef struct jet_context jet_context;
 typedef struct jet_hierarchy jet_hierarchy;

@@ -44,9 +44,17 @@ typedef struct {
     int32_t deadzone_div;    /* sigma rule divisor: 10 */
     int32_t level;
     int32_t max_iters;       /* 0 = no cap */
-    int32_t pad;
+    int32_t flags;           /* OG_F_* (Jetlp ablations) */
     uint64_t seed;
 } og_params;
+
+/* Jetlp ablations of Section 5 (component effectiveness, Table lp_versions).
+ * Reading: "ignores the lock bit" = R stays empty; "omits the afterburner"
+ * = every vertex of X moves (F2 is left 0). The weak afterburner (moves with
+ * F >= 0 only) is the first filter with c = 0. Bit values follow the public
+ * flags of the library's interface. */
+#define OG_F_NO_LOCKS 0x8
+#define OG_F_NO_AFTERBURNER 0x10
 
 typedef struct {
     int32_t level, t, kind, nX, nM, stall, wcount, balanced;
@@ -203,6 +211,7 @@ int32_t og_jetlp(const og_graph *g, const og_params *prm, const int32_t *P,
     }
     for (int32_t v = 0; v < n; v++) {
         if (!inX[v]) continue;
+        if (prm->flags & OG_F_NO_AFTERBURNER) { move[v] = 1; nM++; continue; }
         int64_t f2 = 0;
         for (int64_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
             int32_t u = g->adjncy[e];
@@ -390,7 +399,7 @@ int32_t og_refine(const og_graph *g, const og_params *prm, int32_t *part, og_tra
             nM = og_jetlp(g, prm, P, locked, pd, F, cs, inX, F2, move, &nX);
             /* R <- vertices moved by this Jetlp; rebalancing leaves R alone */
             for (int32_t v = 0; v < n; v++) {
-                locked[v] = move[v];
+                locked[v] = (prm->flags & OG_F_NO_LOCKS) ? 0 : move[v];
                 dest[v] = move[v] ? pd[v] : -1;
             }
             wcount = 0;

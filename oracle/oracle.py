@@ -36,7 +36,7 @@ class OgParams(C.Structure):
     _fields_ = [("k", C.c_int32), ("lambda_ppm", C.c_int32), ("c_num", C.c_int32),
                 ("c_den", C.c_int32), ("phi_num", C.c_int32), ("phi_den", C.c_int32),
                 ("stall_limit", C.c_int32), ("bmax", C.c_int32), ("deadzone_div", C.c_int32),
-                ("level", C.c_int32), ("max_iters", C.c_int32), ("pad", C.c_int32),
+                ("level", C.c_int32), ("max_iters", C.c_int32), ("flags", C.c_int32),
                 ("seed", C.c_uint64)]
 
 
@@ -117,11 +117,16 @@ class _G:
                          self.vwgt.ctypes.data, self.adjwgt.ctypes.data)
 
 
+# Jetlp ablation flags (same bit values as the library's public interface)
+F_NO_LOCKS = 0x8
+F_NO_AFTERBURNER = 0x10
+
+
 def make_params(k, lambda_ppm=30000, c=None, phi=(999, 1000), stall_limit=12, bmax=2,
-                deadzone_div=10, level=0, max_iters=0, seed=0) -> OgParams:
+                deadzone_div=10, level=0, max_iters=0, seed=0, flags=0) -> OgParams:
     cn, cd = (0, 0) if c is None else c
     return OgParams(k, lambda_ppm, cn, cd, phi[0], phi[1], stall_limit, bmax, deadzone_div, level,
-                    max_iters, 0, seed & ((1 << 64) - 1))
+                    max_iters, flags, seed & ((1 << 64) - 1))
 
 
 def trace_to_dicts(arr, n):

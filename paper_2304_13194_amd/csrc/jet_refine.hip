@@ -185,6 +185,17 @@ __device__ void acc_finish(const KArgs &a, Acc &acc)
 struct Walk {
     int first, end, step;
 };
+
+// Blocks are dispatched to the 8 XCDs round robin (block b on XCD b mod 8).
+// Renumbered so that the blocks of one XCD form a contiguous range, its
+// waves walk neighbouring stretches of a list and its L2 holds their
+// neighbours' parts. Identity unless the grid is a multiple of 8.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    if (nb % NXCD) return b;
+    return (b % NXCD) * (nb / NXCD) + b / NXCD;
+}
 template <bool B>
 __device__ __forceinline__ Walk walk(int cnt, int worker, int nworkers, int unit)
 {
@@ -505,7 +516,9 @@ __device__ __forceinline__ int ctl_next(Ctl &cc)
         cc.stall++;
         if (cc.balanced) {
             kind = KIND_LP;
-            cc.lp_id++;
+            // without locks (ablation) Jetlp ids advance by 2, so no stamp
+            // ever equals the previous id and nothing is locked
+            cc.lp_id += (cc.flags & JET_F_LP_NO_LOCKS) ? 2 : 1;
             cc.wcount = 0;
             cc.n_lp++;
         } else if (cc.wcount < cc.bmax) {
@@ -1042,6 +1055,7 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
             constexpr int G = decltype(g_c)::value, R = decltype(r_c)::value;
             if (a.tmap[cl] != ROLE) return;
             int32_t *tab = lds + (threadIdx.x / G) * stride;
+            if (!B && CL != NCLS) bid = xcd_block(bid, nb);
             const int wid = bid * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nb * (BLOCK / 64);
             wave_batched<G>(
                 a.bins + a.binoff[cl], walk<B>(a.binoff[cl + 1] - a.binoff[cl], wid, nwaves, 64), q,
@@ -1152,6 +1166,12 @@ __device__ __forceinline__ void after_store(const KArgs &a, int v, int pd, int s
     if (sum >= 0) a.dest[v] = pd;
 }
 
+// Jetlp ablation without the afterburner: every vertex of X moves.
+__device__ __forceinline__ bool no_afterburner(const KArgs &a, int g)
+{
+    return a.ctl[g].flags & JET_F_LP_NO_AFTERBURNER;
+}
+
 template <bool B>
 __device__ void afterburner_body(const KArgs &a, int b)
 {
@@ -1168,10 +1188,15 @@ __device__ void afterburner_body(const KArgs &a, int b)
                  64),
             q,
             [&](Meta &m) -> bool {
-                pv.sel<B>(a, gof<B>(a, m.v));
+                const int g = gof<B>(a, m.v);
+                pv.sel<B>(a, g);
                 if (pv.kind != KIND_LP) return false;
                 const int2 r = a.rec[m.v];
                 if ((r.x & 0xFFFF) == 0) return false;  // not in X
+                if (no_afterburner(a, g)) {
+                    after_store(a, m.v, (r.x & 0xFFFF) - 1, 0);
+                    return false;
+                }
                 m.ps = r.x;
                 m.aux = r.y;
                 m.s = a.xadj[m.v];
@@ -1194,11 +1219,16 @@ __device__ void afterburner_body(const KArgs &a, int b)
                             a.gM * (BLOCK / 64), 1);
         for (int i = w.first; i < w.end; i += w.step) {
             const int v = list[i];
-            pv.sel<B>(a, gof<B>(a, v));
+            const int g = gof<B>(a, v);
+            pv.sel<B>(a, g);
             if (pv.kind != KIND_LP) continue;
             const int2 r = a.rec[v];
             if ((r.x & 0xFFFF) == 0) continue;
             const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
+            if (no_afterburner(a, g)) {
+                if (gl == 0) after_store(a, v, pd, 0);
+                continue;
+            }
             const int64_t s = a.xadj[v];
             int sum = after_sum_row<4>(a, v, s, (int)(a.xadj[v + 1] - s), ps, pd, r.y, gl, 64);
             sum = gsum<64>(sum);
@@ -1212,11 +1242,16 @@ __device__ void afterburner_body(const KArgs &a, int b)
     const Walk w = walk<B>(a.binoff[CLS_L + 1] - a.binoff[CLS_L], b, a.gL, 1);
     for (int i = w.first; i < w.end; i += w.step) {
         const int v = list[i];
-        pv.sel<B>(a, gof<B>(a, v));
+        const int g = gof<B>(a, v);
+        pv.sel<B>(a, g);
         if (pv.kind != KIND_LP) continue;
         const int2 r = a.rec[v];
         if ((r.x & 0xFFFF) == 0) continue;
         const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
+        if (no_afterburner(a, g)) {
+            if (threadIdx.x == 0) after_store(a, v, pd, 0);
+            continue;
+        }
         const int64_t s = a.xadj[v];
         int sum = after_sum_row<UROW>(a, v, s, (int)(a.xadj[v + 1] - s), ps, pd, r.y, threadIdx.x, BLOCK);
         sum = block_sum<BLOCK>(sum, s_red);
@@ -1565,8 +1600,9 @@ __global__ __launch_bounds__(BLOCK) void k_lafter(KArgs a)
     const int nw = gridDim.x * (BLOCK / 64);
     for (int i = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); i < a.nlch; i += nw) {
         const LChunk ch = lchunk(a, i);
-        pv.sel<B>(a, gof<B>(a, ch.v));
-        if (pv.kind != KIND_LP) continue;
+        const int g = gof<B>(a, ch.v);
+        pv.sel<B>(a, g);
+        if (pv.kind != KIND_LP || no_afterburner(a, g)) continue;
         const int2 r = a.rec[ch.v];
         if ((r.x & 0xFFFF) == 0) continue;  // not in X
         const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
@@ -1586,11 +1622,12 @@ __global__ __launch_bounds__(BLOCK) void k_lafter_fin(KArgs a)
     if (!B) pv.at(a, 0);
     for (int li = blockIdx.x * BLOCK + threadIdx.x; li < nL; li += gridDim.x * BLOCK) {
         const int v = a.bins[a.binoff[CLS_L] + li];
-        pv.sel<B>(a, gof<B>(a, v));
+        const int g = gof<B>(a, v);
+        pv.sel<B>(a, g);
         if (pv.kind != KIND_LP) continue;
         const int2 r = a.rec[v];
         if ((r.x & 0xFFFF) == 0) continue;
-        const int sum = a.gf2[li];
+        const int sum = no_afterburner(a, g) ? 0 : a.gf2[li];
         a.gf2[li] = 0;
         after_store(a, v, (r.x & 0xFFFF) - 1, sum);
     }

@@ -26,6 +26,8 @@ JET_OK, JET_EINVAL, JET_EGRAPH, JET_EPART, JET_EOVERFLOW, JET_ENOMEM, JET_EHIP, 
 JET_F_VALIDATE = 0x1
 JET_F_RETURN_ITER = 0x2
 JET_F_PROFILE = 0x4
+JET_F_LP_NO_LOCKS = 0x8
+JET_F_LP_NO_AFTERBURNER = 0x10
 KIND_LP, KIND_RW, KIND_RS = 1, 2, 3
 
 # Every function declared in include/jet.h.

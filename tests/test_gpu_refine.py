@@ -259,3 +259,42 @@ def test_refine_edge_cases(J, O):
     gi = I.csr_from_edges(50, np.zeros(0, np.int64), np.zeros(0, np.int64))
     P0 = np.zeros(50, np.int32)
     _compare_refine(J, O, gi, 4, P0, "isolated_only")
+
+
+# Jetlp ablations (Section 5, Table lp_versions): (name, c, flags)
+def _ablations(J):
+    NL, NA = J.JET_F_LP_NO_LOCKS, J.JET_F_LP_NO_AFTERBURNER
+    return [("baseline", (0, 1), NL | NA), ("locks", (0, 1), NA), ("weak_afterburner", (0, 1), NL),
+            ("full_afterburner", None, NL), ("full", None, 0)]
+
+
+ABL_CASES = [c for c in CASES if c[0] in ("grid64_k4", "rmat12_k32_w", "stencil12_k8_l2", "rmat14_k64_hubs",
+                                           "stars_chunks_k4", "er3")]
+
+
+@pytest.mark.parametrize("case", ABL_CASES, ids=[c[0] for c in ABL_CASES])
+def test_refine_ablation_parity(J, O, case):
+    name, g, k, level = case
+    for vname, c, flags in _ablations(J):
+        kw = dict(flags=flags)
+        if c is not None:
+            kw["c"] = c
+        _compare_refine(J, O, g, k, I.random_partition(g.n, k, 700), f"{name}_{vname}", level=level, seed=13, **kw)
+
+
+@pytest.mark.parametrize("case", ABL_CASES, ids=[c[0] for c in ABL_CASES])
+def test_lp_step_no_afterburner_parity(J, O, case):
+    import torch
+    name, g, k, level = case
+    dg = J.to_device(g)
+    P = I.random_partition(g.n, k, 101)
+    L = _locks(g.n, 201)
+    for c in ((0, 1), None):
+        kw = {} if c is None else dict(c=c)
+        exp = O.jetlp(g, P, L, k, level=level, flags=O.F_NO_AFTERBURNER, **kw)
+        got = J.lp_step(dg, torch.from_numpy(P).cuda(), torch.from_numpy(L).cuda(), k, level=level,
+                        flags=J.JET_F_LP_NO_AFTERBURNER, **kw)
+        for key in ("pd", "F", "conn_s", "F2"):
+            np.testing.assert_array_equal(got[key].cpu().numpy(), exp[key], err_msg=f"{name} {key}")
+        np.testing.assert_array_equal(got["move"].cpu().numpy().astype(bool), exp["move"], err_msg=name)
+

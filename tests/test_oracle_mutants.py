@@ -43,6 +43,8 @@ MUTANTS = [
      "bal_best = 1; cut_best = cut; maxw_best = maxw;"),
     ("contraction keeps self loops", "if (cu == c) continue;", ""),
     ("rebalance from B side", "if (!inB[p] || conn[p] <= 0) continue;", "if (conn[p] <= 0) continue;"),
+    ("ablation keeps locks", "locked[v] = (prm->flags & OG_F_NO_LOCKS) ? 0 : move[v];", "locked[v] = move[v];"),
+    ("ablation still filters by F2", "if (prm->flags & OG_F_NO_AFTERBURNER) { move[v] = 1; nM++; continue; }", ""),
 ]
 
 PIN_TESTS = [
@@ -62,6 +64,9 @@ PIN_TESTS = [
     pins.test_stall_counter_follows_algorithm3,
     pins.test_exhaustive_optimum_bounds_result,
     pins.test_hem_is_a_matching_and_contraction_preserves_cut,
+    pins.test_ablation_baseline_step_is_textbook_sync_lp,
+    lambda O: pins.test_ablation_loop_iterates_textbook_lp(O, False),
+    lambda O: pins.test_ablation_loop_iterates_textbook_lp(O, True),
 ]
 
 

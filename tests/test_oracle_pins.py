@@ -478,3 +478,65 @@ def test_partition_multilevel_sanity(oracle_lib):
     assert all(sizes[i + 1] < sizes[i] for i in range(len(sizes) - 1))
     assert brute_cut(g, res["part"]) == res["cut"]
     assert res["balanced"]
+
+
+# ---------------------------------------------------- Jetlp ablations ---
+# Section 5 (component effectiveness, Table lp_versions): the baseline is a
+# synchronous LP that moves vertices to their best connected part, with no
+# afterburner and no locks.
+
+def _textbook_sync_lp(g, P, k, frozen=None):
+    """One synchronous label-propagation step written from the textbook rule:
+    every vertex that is not frozen and has an adjacent other part moves to
+    its most connected other part (ties to the smallest id) when that does
+    not lose (F >= 0)."""
+    Cm = conn_matrix(g, P, k)
+    newP = np.array(P, dtype=np.int32, copy=True)
+    for v in range(g.n):
+        if frozen is not None and frozen[v]:
+            continue
+        row = Cm[v].copy()
+        own = row[P[v]]
+        row[P[v]] = -1
+        if row.max() <= 0:
+            continue
+        d = int(np.argmax(row))
+        if row[d] - own >= 0:
+            newP[v] = d
+    return newP
+
+
+def test_ablation_baseline_step_is_textbook_sync_lp(oracle_lib):
+    """No afterburner and c = 0: one Jetlp step is the textbook synchronous LP
+    step, every vertex of X moves and F2 stays 0."""
+    O = oracle_lib
+    for s, g, k, P in _cases(60):
+        lp = O.jetlp(g, P, np.zeros(g.n, np.uint8), k, c=(0, 1), flags=O.F_NO_AFTERBURNER)
+        got = np.where(lp["move"], lp["pd"], P)
+        np.testing.assert_array_equal(got, _textbook_sync_lp(g, P, k), err_msg=f"case {s}")
+        assert lp["nM"] == lp["nX"] and (lp["F2"] == 0).all()
+
+
+@pytest.mark.parametrize("locks", [False, True])
+def test_ablation_loop_iterates_textbook_lp(oracle_lib, locks):
+    """With a generous lambda every iteration is a Jetlp. Without locks each
+    iteration is the textbook step of the previous partition; with locks the
+    vertices moved by the previous iteration sit out (R of Algorithm 3)."""
+    O = oracle_lib
+    k = 4
+    for seed in range(4):
+        g = I.grid2d(10 + seed, 12)
+        P = I.random_partition(g.n, k, 40 + seed)
+        flags = O.F_NO_AFTERBURNER | (0 if locks else O.F_NO_LOCKS)
+        res = O.refine(g, P, k, lambda_ppm=3_000_000, c=(0, 1), flags=flags, max_iters=10, stall_limit=100)
+        cur = P.copy()
+        frozen = np.zeros(g.n, bool)
+        assert len(res.trace) == 10
+        for rec in res.trace:
+            assert rec["kind"] == 1
+            nxt = _textbook_sync_lp(g, cur, k, frozen if locks else None)
+            assert rec["nM"] == int((nxt != cur).sum())
+            assert rec["cut"] == brute_cut(g, nxt)
+            frozen = nxt != cur
+            cur = nxt
+        np.testing.assert_array_equal(res.iter_part, cur)
