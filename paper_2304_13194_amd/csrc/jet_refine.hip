@@ -820,14 +820,15 @@ struct Meta {
 };
 
 template <int G, class Pre, class Row>
-__device__ __forceinline__ void wave_batched(const int32_t *list, Walk w, int32_t *q, Pre pre, Row row)
+__device__ __forceinline__ void wave_batched(const int32_t *list, Walk w, int32_t *q, Pre pre, Row row,
+                                             int unit = 64)
 {
     const int lane = threadIdx.x & 63, grp = lane / G, gl = lane & (G - 1);
     for (int base = w.first; base < w.end; base += w.step) {
         const int i = base + lane;
         Meta m{0, 0, 0, 0, 0, 0};
         bool act = false;
-        if (i < w.end) {
+        if (lane < unit && i < w.end) {
             m.v = list[i];
             act = pre(m);
         }
@@ -850,6 +851,16 @@ __device__ __forceinline__ void wave_batched(const int32_t *list, Walk w, int32_
         }
         lds_fence_wave();
     }
+}
+
+// List entries a wave inspects per visit when every queued row takes the
+// whole wave (wave_batched<64>): 64, halved while the list would leave waves
+// idle, so short lists still spread over the grid.
+__device__ __forceinline__ int wave_unit(int cnt, int nwaves)
+{
+    int u = 64;
+    while (u > 1 && (int64_t)u * nwaves > cnt) u >>= 1;
+    return u;
 }
 
 // Rows longer than a group walk their entries in rounds of U per lane: all
@@ -1213,27 +1224,35 @@ __device__ void afterburner_body(const KArgs &a, int b)
     }
     b -= a.gS;
     if (b < a.gM) {
-        const int gl = threadIdx.x & 63;
-        const int32_t *list = a.bins + a.binoff[CLS_M];
-        const Walk w = walk<B>(a.binoff[CLS_M + 1] - a.binoff[CLS_M], b * (BLOCK / 64) + (threadIdx.x >> 6),
-                            a.gM * (BLOCK / 64), 1);
-        for (int i = w.first; i < w.end; i += w.step) {
-            const int v = list[i];
-            const int g = gof<B>(a, v);
-            pv.sel<B>(a, g);
-            if (pv.kind != KIND_LP) continue;
-            const int2 r = a.rec[v];
-            if ((r.x & 0xFFFF) == 0) continue;
-            const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
-            if (no_afterburner(a, g)) {
-                if (gl == 0) after_store(a, v, pd, 0);
-                continue;
-            }
-            const int64_t s = a.xadj[v];
-            int sum = after_sum_row<4>(a, v, s, (int)(a.xadj[v + 1] - s), ps, pd, r.y, gl, 64);
-            sum = gsum<64>(sum);
-            if (gl == 0) after_store(a, v, pd, sum);
-        }
+        // one wave per row of X; lanes first inspect a stretch of the list at once
+        int32_t *q = s_q + (threadIdx.x >> 6) * 64;
+        const int cnt = a.binoff[CLS_M + 1] - a.binoff[CLS_M], nw = a.gM * (BLOCK / 64);
+        const int unit = wave_unit(cnt, nw);
+        wave_batched<64>(
+            a.bins + a.binoff[CLS_M], walk<B>(cnt, b * (BLOCK / 64) + (threadIdx.x >> 6), nw, unit), q,
+            [&](Meta &m) -> bool {
+                const int g = gof<B>(a, m.v);
+                pv.sel<B>(a, g);
+                if (pv.kind != KIND_LP) return false;
+                const int2 r = a.rec[m.v];
+                if ((r.x & 0xFFFF) == 0) return false;  // not in X
+                if (no_afterburner(a, g)) {
+                    after_store(a, m.v, (r.x & 0xFFFF) - 1, 0);
+                    return false;
+                }
+                m.ps = r.x;
+                m.aux = r.y;
+                m.s = a.xadj[m.v];
+                m.deg = (int)(a.xadj[m.v + 1] - m.s);
+                return true;
+            },
+            [&](const Meta &t, int gl) {
+                const int ps = t.ps >> 16, pd = (t.ps & 0xFFFF) - 1;
+                int sum = after_sum_row<4>(a, t.v, t.s, t.deg, ps, pd, t.aux, gl, 64);
+                sum = gsum<64>(sum);
+                if (gl == 0) after_store(a, t.v, pd, sum);
+            },
+            unit);
         return;
     }
     b -= a.gM;
@@ -1357,27 +1376,34 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
                 }
             });
     } else if ((b -= a.gS) < a.gM) {
-        const int gl = threadIdx.x & 63;
-        const int32_t *list = a.bins + a.binoff[CLS_M];
-        const Walk w = walk<B>(a.binoff[CLS_M + 1] - a.binoff[CLS_M], b * (BLOCK / 64) + (threadIdx.x >> 6),
-                            a.gM * (BLOCK / 64), 1);
-        for (int i = w.first; i < w.end; i += w.step) {
-            const int v = list[i];
-            const int pn = a.dest[v];
-            if (pn < 0) continue;
-            const int ps = a.P[v];
-            const int g = gof<B>(a, v);
-            const int64_t s = a.xadj[v];
-            int d = dcut_sum_row<4>(a, v, s, (int)(a.xadj[v + 1] - s), ps, pn, gl, 64);
-            d = gsum<64>(d);
-            if (gl == 0) {
-                pv.sel<B>(a, g);
-                macc.sel<B>(a, g);
-                move_meta(a, v, v - pv.voff, ps, pn, macc);
-                cacc.sel<B>(a, g);
-                cacc.c0 += (uint64_t)(int64_t)d;
-            }
-        }
+        // one wave per moved row; lanes first inspect a stretch of the list at once
+        int32_t *q = s_q + (threadIdx.x >> 6) * 64;
+        const int cnt = a.binoff[CLS_M + 1] - a.binoff[CLS_M], nw = a.gM * (BLOCK / 64);
+        const int unit = wave_unit(cnt, nw);
+        wave_batched<64>(
+            a.bins + a.binoff[CLS_M], walk<B>(cnt, b * (BLOCK / 64) + (threadIdx.x >> 6), nw, unit), q,
+            [&](Meta &m) -> bool {
+                const int pn = a.dest[m.v];
+                if (pn < 0) return false;
+                m.aux = pn;
+                m.ps = a.P[m.v];
+                m.g = gof<B>(a, m.v);
+                pv.sel<B>(a, m.g);
+                macc.sel<B>(a, m.g);
+                move_meta(a, m.v, m.v - pv.voff, m.ps, pn, macc);
+                m.s = a.xadj[m.v];
+                m.deg = (int)(a.xadj[m.v + 1] - m.s);
+                return true;
+            },
+            [&](const Meta &t, int gl) {
+                int d = dcut_sum_row<4>(a, t.v, t.s, t.deg, t.ps, t.aux, gl, 64);
+                d = gsum<64>(d);
+                if (gl == 0) {
+                    cacc.sel<B>(a, t.g);
+                    cacc.c0 += (uint64_t)(int64_t)d;
+                }
+            },
+            unit);
     } else if ((b -= a.gM) < a.gL) {
         const int32_t *list = a.bins + a.binoff[CLS_L];
         const Walk w = walk<B>(a.binoff[CLS_L + 1] - a.binoff[CLS_L], b, a.gL, 1);
