@@ -27,9 +27,9 @@ Prints one JSON line:
                into jet_server: p50 / p99 latency and graphs/s per arrival
                rate, vs partitioning the same jobs one at a time
   ablations    Jetlp variants (baseline synchronous LP, +locks, +weak or
-               full afterburner, full Jetlp) and phi 0.99 / 0.999 / 0.9999
-               on the main graph and the serving pool's largest R-MAT graph:
-               cut and partition time per variant
+               full afterburner, full Jetlp), phi 0.99 / 0.999 / 0.9999 and
+               two-hop coarsening on the main graph and the serving pool's
+               largest R-MAT graph: cut and partition time per variant
 """
 from __future__ import annotations
 
@@ -241,7 +241,8 @@ def ablation_bench(J, dg, k, seed, label):
                 ("+full afterburner", dict(flags=NL)),
                 ("full Jetlp", dict()),
                 ("full Jetlp, phi 0.99", dict(phi=(99, 100))),
-                ("full Jetlp, phi 0.9999", dict(phi=(9999, 10000)))]
+                ("full Jetlp, phi 0.9999", dict(phi=(9999, 10000))),
+                ("full Jetlp, two-hop coarsening", dict(flags=J.JET_F_TWO_HOP))]
     rows = []
     for name, kw in variants:
         J.partition(dg, k, seed=seed, **kw)

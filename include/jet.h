@@ -62,6 +62,13 @@ extern "C" {
  * c_num = 0, c_den = 1. The baseline synchronous LP is all three. */
 #define JET_F_LP_NO_LOCKS       0x8u
 #define JET_F_LP_NO_AFTERBURNER 0x10u
+/* Coarsening (jet_coarsen, jet_partition, serving jobs): after heavy-edge
+ * matching, while more than a quarter of the vertices is unmatched, add
+ * two-hop matches (Section 3.1): leaves (one entry, same neighbour), twins
+ * (1 to 64 entries, same neighbourhood hash), relatives (1 to 64 entries,
+ * same matchmaker: the smallest-id matched neighbour of at most 1024
+ * entries); equal keys pair in ascending id order. */
+#define JET_F_TWO_HOP           0x20u
 
 typedef struct jet_context jet_context;
 typedef struct jet_hierarchy jet_hierarchy;

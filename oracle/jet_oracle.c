@@ -55,6 +55,8 @@ typedef struct {
  * flags of the library's interface. */
 #define OG_F_NO_LOCKS 0x8
 #define OG_F_NO_AFTERBURNER 0x10
+/* coarsening with two-hop matching (Section 3.1) after heavy-edge matching */
+#define OG_F_TWO_HOP 0x20
 
 typedef struct {
     int32_t level, t, kind, nX, nM, stall, wcount, balanced;
@@ -454,16 +456,104 @@ int32_t og_refine(const og_graph *g, const og_params *prm, int32_t *part, og_tra
     return t;
 }
 
+/* ---- two-hop matching (Section 3.1) --------------------------------------
+ * reading: after the heavy-edge rounds, while more than a quarter of the
+ * vertices is unmatched, three passes add matches between vertices two hops
+ * apart, each pass only if the previous one left more than n/4 unmatched:
+ *   leaves     unmatched vertices of degree 1, keyed by their neighbour;
+ *   twins      unmatched vertices of 1 to 64 entries keyed by their
+ *              neighbourhood: the hash mix64(h ^ mix64(deg)) >> 1 of
+ *              h = sum over neighbours u of mix64(u + 1) (mod 2^64)
+ *              (twins are relatives, two hops apart, so isolated vertices
+ *              never pair);
+ *   relatives  unmatched vertices of 1 to 64 entries keyed by their
+ *              matchmaker, the smallest-id neighbour that is already matched
+ *              and has at most 1024 entries (hubs never act as matchmakers).
+ * Vertices with equal keys are matched in ascending id order, first with
+ * second, third with fourth, and so on. */
+#define OG_TWO_HOP_MM_MAXDEG 1024
+#define OG_TWO_HOP_MAXDEG 64
+
+typedef struct { uint64_t key; int32_t v; } og_kv;
+static int og_kv_cmp(const void *a, const void *b)
+{
+    const og_kv *x = (const og_kv *)a, *y = (const og_kv *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->v < y->v ? -1 : (x->v > y->v);
+}
+
+static int32_t og_unmatched(const int32_t *match, int32_t n)
+{
+    int32_t c = 0;
+    for (int32_t v = 0; v < n; v++) c += match[v] < 0;
+    return c;
+}
+
+/* pairs vertices of equal key (candidates only) in ascending id order */
+static void og_pair_by_key(int32_t *match, og_kv *kv, int32_t m)
+{
+    qsort(kv, (size_t)m, sizeof(og_kv), og_kv_cmp);
+    int32_t i = 0;
+    while (i < m) {
+        int32_t j = i;
+        while (j < m && kv[j].key == kv[i].key) j++;
+        for (int32_t a = i; a + 1 < j; a += 2) {
+            match[kv[a].v] = kv[a + 1].v;
+            match[kv[a + 1].v] = kv[a].v;
+        }
+        i = j;
+    }
+}
+
+static void og_two_hop(const og_graph *g, int32_t *match)
+{
+    int32_t n = g->n;
+    if (n == 0) return;
+    og_kv *kv = (og_kv *)malloc(sizeof(og_kv) * (size_t)n);
+    for (int pass = 0; pass < 3; pass++) {
+        if (4 * (int64_t)og_unmatched(match, n) <= (int64_t)n) break;
+        int32_t m = 0;
+        for (int32_t v = 0; v < n; v++) {
+            if (match[v] >= 0) continue;
+            int64_t deg = g->xadj[v + 1] - g->xadj[v];
+            if (deg < 1 || deg > OG_TWO_HOP_MAXDEG) continue;
+            if (pass == 0) {
+                if (deg != 1) continue;
+                kv[m].key = (uint64_t)(uint32_t)g->adjncy[g->xadj[v]];
+            } else if (pass == 1) {
+                uint64_t h = 0;
+                for (int64_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) h += og_mix64((uint64_t)(uint32_t)g->adjncy[e] + 1);
+                kv[m].key = og_mix64(h ^ og_mix64((uint64_t)deg)) >> 1;
+            } else {
+                int32_t mm = -1;
+                for (int64_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+                    int32_t u = g->adjncy[e];
+                    if (match[u] < 0 || g->xadj[u + 1] - g->xadj[u] > OG_TWO_HOP_MM_MAXDEG) continue;
+                    if (mm < 0 || u < mm) mm = u;
+                }
+                if (mm < 0) continue;
+                kv[m].key = (uint64_t)(uint32_t)mm;
+            }
+            kv[m].v = v;
+            m++;
+        }
+        og_pair_by_key(match, kv, m);
+    }
+    free(kv);
+}
+
 /* ---- multilevel scaffold: heavy-edge matching + contraction ------------
  * reading (the paper names heavy-edge matching but not its tie rules):
  * rounds of mutual proposals. Each unmatched vertex proposes to the
  * unmatched neighbour across its heaviest edge; ties go to the smaller
  * edge hash mix64(hseed ^ (min << 32 | max)), then to the smaller id.
  * Mutual proposals match. Rounds stop after 16, or once a round matches
- * fewer than 1% of the vertices. hseed = stream(seed, level).
+ * fewer than 1% of the vertices. hseed = stream(seed, level). With
+ * two_hop, two-hop matching (above) then adds pairs when many vertices
+ * stay unmatched.
  * Coarse ids: vertices that are unmatched or the smaller end of their pair
  * are leaders, numbered in vertex order. Returns the coarse vertex count. */
-int32_t og_hem_map(const og_graph *g, int32_t level, uint64_t seed, int32_t *map)
+int32_t og_hem_map(const og_graph *g, int32_t level, uint64_t seed, int32_t two_hop, int32_t *map)
 {
     int32_t n = g->n;
     size_t nn = (size_t)(n > 0 ? n : 1);
@@ -495,6 +585,7 @@ int32_t og_hem_map(const og_graph *g, int32_t level, uint64_t seed, int32_t *map
         }
         if (newly == 0 || newly * 100 < (int64_t)n) break;
     }
+    if (two_hop) og_two_hop(g, match);
     int32_t nc = 0;
     for (int32_t v = 0; v < n; v++)
         if (match[v] < 0 || v < match[v]) map[v] = nc++;
@@ -578,7 +669,7 @@ int32_t og_partition(const og_graph *g, const og_params *prm, int32_t *part, og_
     while (nl < MAXL && G[nl - 1].n > 8 * (int64_t)k) {
         const og_graph *f = &G[nl - 1];
         int32_t *map = (int32_t *)malloc(sizeof(int32_t) * (size_t)(f->n > 0 ? f->n : 1));
-        int32_t nc = og_hem_map(f, nl - 1, prm->seed, map);
+        int32_t nc = og_hem_map(f, nl - 1, prm->seed, (prm->flags & OG_F_TWO_HOP) != 0, map);
         if (nc == f->n) { free(map); break; }
         int64_t *cx; int32_t *ca, *cv, *cw;
         og_contract(f, map, nc, &cx, &ca, &cv, &cw);

@@ -120,6 +120,7 @@ class _G:
 # Jetlp ablation flags (same bit values as the library's public interface)
 F_NO_LOCKS = 0x8
 F_NO_AFTERBURNER = 0x10
+F_TWO_HOP = 0x20
 
 
 def make_params(k, lambda_ppm=30000, c=None, phi=(999, 1000), stall_limit=12, bmax=2,
@@ -215,10 +216,11 @@ def partition(g, k, trace_cap=200000, **kw):
                 cut=int(st[0]), maxw=int(st[1]), balanced=bool(st[2]), o=int(st[3]))
 
 
-def hem_map(g, level, seed):
+def hem_map(g, level, seed, two_hop=False):
     G = _G(g)
     m = np.zeros(max(G.s.n, 1), np.int32)
-    nc = lib().og_hem_map(C.byref(G.s), C.c_int32(level), C.c_uint64(seed & ((1 << 64) - 1)), _ptr(m))
+    nc = lib().og_hem_map(C.byref(G.s), C.c_int32(level), C.c_uint64(seed & ((1 << 64) - 1)),
+                          C.c_int32(1 if two_hop else 0), _ptr(m))
     return nc, m[:G.s.n]
 
 

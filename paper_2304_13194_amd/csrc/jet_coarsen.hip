@@ -15,6 +15,8 @@
 // compaction of the occupied slots. Coarse rows come out unsorted; nothing
 // downstream depends on row order.
 #include <hip/hip_runtime.h>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 #include <stdint.h>
 #include <string.h>
 
@@ -268,6 +270,80 @@ __global__ __launch_bounds__(CB) void k_big_list(int n, const int64_t *xadj, int
         const int v = it * stride + blockIdx.x * CB + threadIdx.x;
         const bool heavy = v < n && xadj[v + 1] - xadj[v] > 64;
         wave_append(heavy, nbig, big, v);
+    }
+}
+
+// ------------------------------------------------------ two-hop matching ---
+// Section 3.1: when heavy-edge matching leaves more than a quarter of the
+// vertices unmatched, up to three passes match vertices two hops apart.
+// Each pass gives every candidate a key; candidates of equal key are matched
+// in ascending id order (first with second, third with fourth, ...):
+//   leaves    (pass 0) unmatched, one entry: the neighbour;
+//   twins     (pass 1) unmatched, 1 to 64 entries: a hash of the
+//             neighbourhood (twins are relatives, so isolated vertices
+//             never pair);
+//   relatives (pass 2) unmatched, 1 to 64 entries: the matchmaker, the
+//             smallest-id neighbour already matched with at most 1024
+//             entries (hubs are never matchmakers).
+// Non-candidates get TH_NONE and sort after every candidate (twin hashes
+// keep 63 bits).
+constexpr uint64_t TH_NONE = ~0ull;
+constexpr int TH_MAXDEG = 64, TH_MM_MAXDEG = 1024;
+
+__global__ __launch_bounds__(CB) void k_th_count(int n, const int32_t *match, int32_t *cnt)
+{
+    __shared__ int32_t s_red[CB / 64];
+    int c = 0;
+    for (int v = blockIdx.x * CB + threadIdx.x; v < n; v += gridDim.x * CB) c += match[v] < 0;
+    c = block_sum<CB>(c, s_red);
+    if (threadIdx.x == 0 && c) atomicAdd(cnt, c);
+}
+
+__global__ __launch_bounds__(CB) void k_th_keys(int n, int pass, const int64_t *xadj, const int32_t *adj,
+                                                const int32_t *match, uint64_t *key, int32_t *val)
+{
+    for (int v = blockIdx.x * CB + threadIdx.x; v < n; v += gridDim.x * CB) {
+        val[v] = v;
+        uint64_t k = TH_NONE;
+        const int64_t s = xadj[v];
+        const int deg = (int)(xadj[v + 1] - s);
+        if (match[v] < 0 && deg >= 1 && deg <= TH_MAXDEG) {
+            if (pass == 0) {
+                if (deg == 1) k = (uint64_t)(uint32_t)adj[s];
+            } else if (pass == 1) {
+                uint64_t h = 0;
+                for (int e = 0; e < deg; e++) h += mix64((uint64_t)(uint32_t)adj[s + e] + 1);
+                k = mix64(h ^ mix64((uint64_t)deg)) >> 1;
+            } else {
+                int mm = -1;
+                for (int e = 0; e < deg; e++) {
+                    const int u = adj[s + e];
+                    if (match[u] < 0 || xadj[u + 1] - xadj[u] > TH_MM_MAXDEG) continue;
+                    if (mm < 0 || u < mm) mm = u;
+                }
+                if (mm >= 0) k = (uint64_t)(uint32_t)mm;
+            }
+        }
+        key[v] = k;
+    }
+}
+
+// Start index of each sorted entry's run of equal keys (max-scanned next).
+__global__ __launch_bounds__(CB) void k_th_runflag(int n, const uint64_t *key, int32_t *flag)
+{
+    for (int i = blockIdx.x * CB + threadIdx.x; i < n; i += gridDim.x * CB)
+        flag[i] = (i == 0 || key[i] != key[i - 1]) ? i : 0;
+}
+
+__global__ __launch_bounds__(CB) void k_th_pair(int n, const uint64_t *key, const int32_t *val, const int32_t *run,
+                                                int32_t *match)
+{
+    for (int i = blockIdx.x * CB + threadIdx.x; i + 1 < n; i += gridDim.x * CB) {
+        const uint64_t k = key[i];
+        if (k == TH_NONE || key[i + 1] != k || ((i - run[i]) & 1)) continue;
+        const int a = val[i], b = val[i + 1];
+        match[a] = b;
+        match[b] = a;
     }
 }
 
@@ -756,9 +832,48 @@ static void hier_release(jet_hierarchy *h)
     h->owned.clear();
 }
 
+// Two-hop passes while more than n/4 vertices are unmatched (one count and
+// wait per pass).
+static int two_hop(jet_context *ctx, const jet_csr *f, int32_t *match, hipStream_t s)
+{
+    const int n = f->n;
+    if (n == 0) return JET_OK;
+    const size_t nn = (size_t)n;
+    int32_t *cnt = (int32_t *)ws_get(ctx, WS_TH_RUN, nn * 8 + 64);
+    int32_t *flag = cnt + 16, *run = flag + nn;
+    uint64_t *key = (uint64_t *)ws_get(ctx, WS_TH_KEY, nn * 16);
+    int32_t *val = (int32_t *)ws_get(ctx, WS_TH_VAL, nn * 8);
+    if (!cnt || !key || !val) return JET_ENOMEM;
+    uint64_t *key2 = key + nn;
+    int32_t *val2 = val + nn;
+    size_t sort_bytes = 0, scan_bytes = 0;
+    JET_TRY(rocprim::radix_sort_pairs(nullptr, sort_bytes, key, key2, val, val2, nn, 0, 64, s));
+    JET_TRY(rocprim::inclusive_scan(nullptr, scan_bytes, flag, run, nn, rocprim::maximum<int32_t>(), s));
+    void *tmp = ws_get(ctx, WS_TH_TMP, std::max(sort_bytes, scan_bytes) + 256);
+    if (!tmp) return JET_ENOMEM;
+    int32_t *hcnt = (int32_t *)((char *)ctx->pinned + 2560);
+    const int gv = grid_for(ctx, n, CB, 4);
+    for (int pass = 0; pass < 3; pass++) {
+        JET_TRY(hipMemsetAsync(cnt, 0, 4, s));
+        k_th_count<<<gv, CB, 0, s>>>(n, match, cnt);
+        JET_TRY(hipMemcpyAsync(hcnt, cnt, 4, hipMemcpyDeviceToHost, s));
+        JET_TRY(stream_wait(ctx, s));
+        if (4 * (int64_t)*hcnt <= (int64_t)n) break;
+        k_th_keys<<<gv, CB, 0, s>>>(n, pass, f->xadj, f->adjncy, match, key, val);
+        size_t b = sort_bytes;
+        JET_TRY(rocprim::radix_sort_pairs(tmp, b, key, key2, val, val2, nn, 0, 64, s));
+        k_th_runflag<<<gv, CB, 0, s>>>(n, key2, flag);
+        b = scan_bytes;
+        JET_TRY(rocprim::inclusive_scan(tmp, b, flag, run, nn, rocprim::maximum<int32_t>(), s));
+        k_th_pair<<<gv, CB, 0, s>>>(n, key2, val2, run, match);
+        JET_TRY(hipGetLastError());
+    }
+    return JET_OK;
+}
+
 // One coarsening step of level graph f into c (device buffers owned by h).
 // Returns the coarse vertex count in *nc_out (== f->n when nothing matched).
-static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, int level, uint64_t seed,
+static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, int level, uint64_t seed, bool th,
                          jet_csr *c, int32_t **map_out, int *nc_out, hipStream_t s)
 {
     const int n = f->n;
@@ -788,6 +903,10 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
                                                                            match, prop, hseed, st);
         k_hem_match<<<gv, CB, 0, s>>>(n, match, prop, st);
         k_hem_round_end<<<1, 1, 0, s>>>(n, st);
+    }
+    if (th) {
+        const int st2 = two_hop(ctx, f, match, s);
+        if (st2) return st2;
     }
     // coarse ids: leaders numbered in vertex order
     int32_t *flag = prop;  // proposals are no longer needed
@@ -891,7 +1010,8 @@ static int build_hierarchy(jet_context *ctx, const jet_csr *g, const jet_params 
         jet_csr c;
         int32_t *map = nullptr;
         int nc = 0;
-        int st = coarsen_level(ctx, h, &f, (int)h->lv.size() - 1, prm->seed, &c, &map, &nc, s);
+        int st = coarsen_level(ctx, h, &f, (int)h->lv.size() - 1, prm->seed, (prm->flags & JET_F_TWO_HOP) != 0, &c,
+                               &map, &nc, s);
         if (st) return st;
         if (nc == f.n) break;
         h->maps.push_back(map);

@@ -28,6 +28,7 @@ JET_F_RETURN_ITER = 0x2
 JET_F_PROFILE = 0x4
 JET_F_LP_NO_LOCKS = 0x8
 JET_F_LP_NO_AFTERBURNER = 0x10
+JET_F_TWO_HOP = 0x20
 KIND_LP, KIND_RW, KIND_RS = 1, 2, 3
 
 # Every function declared in include/jet.h.

@@ -53,11 +53,12 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("two_hop", [False, True], ids=["hem", "two_hop"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_hierarchy_matches_oracle(J, O, case):
+def test_hierarchy_matches_oracle(J, O, case, two_hop):
     name, g, k, seed = case
-    _say(f"coarsen {name} n={g.n} k={k}")
-    h = J.coarsen(J.to_device(g), k, seed=seed)
+    _say(f"coarsen {name} n={g.n} k={k} two_hop={two_hop}")
+    h = J.coarsen(J.to_device(g), k, seed=seed, flags=J.JET_F_TWO_HOP if two_hop else 0)
     cur = g
     for lvl in range(h.levels):
         L = h.level(lvl)
@@ -65,7 +66,7 @@ def test_hierarchy_matches_oracle(J, O, case):
         if lvl == h.levels - 1:
             assert L["map"] is None
             break
-        nc, cmap = O.hem_map(cur, lvl, seed)
+        nc, cmap = O.hem_map(cur, lvl, seed, two_hop=two_hop)
         np.testing.assert_array_equal(L["map"], cmap, err_msg=f"{name} map level {lvl}")
         nxt = O.contract(cur, cmap, nc)
         Ln = h.level(lvl + 1)
@@ -77,12 +78,14 @@ def test_hierarchy_matches_oracle(J, O, case):
     h.close()
 
 
+@pytest.mark.parametrize("two_hop", [False, True], ids=["hem", "two_hop"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_partition_matches_oracle(J, O, case):
+def test_partition_matches_oracle(J, O, case, two_hop):
     name, g, k, seed = case
-    _say(f"partition {name} n={g.n} k={k}")
-    exp = O.partition(g, k, seed=seed)
-    part, st, tr = J.partition(J.to_device(g), k, seed=seed, trace_cap=100000)
+    _say(f"partition {name} n={g.n} k={k} two_hop={two_hop}")
+    exp = O.partition(g, k, seed=seed, flags=O.F_TWO_HOP if two_hop else 0)
+    part, st, tr = J.partition(J.to_device(g), k, seed=seed, trace_cap=100000,
+                               flags=J.JET_F_TWO_HOP if two_hop else 0)
     assert st["levels"] == len(exp["level_sizes"])
     assert len(tr) == len(exp["trace"])
     for a, b in zip(tr, exp["trace"]):

@@ -45,6 +45,10 @@ MUTANTS = [
     ("rebalance from B side", "if (!inB[p] || conn[p] <= 0) continue;", "if (conn[p] <= 0) continue;"),
     ("ablation keeps locks", "locked[v] = (prm->flags & OG_F_NO_LOCKS) ? 0 : move[v];", "locked[v] = move[v];"),
     ("ablation still filters by F2", "if (prm->flags & OG_F_NO_AFTERBURNER) { move[v] = 1; nM++; continue; }", ""),
+    ("two-hop leaves keyed by self", "kv[m].key = (uint64_t)(uint32_t)g->adjncy[g->xadj[v]];",
+     "kv[m].key = (uint64_t)(uint32_t)v;"),
+    ("two-hop pairs overlap", "for (int32_t a = i; a + 1 < j; a += 2) {", "for (int32_t a = i; a + 1 < j; a += 1) {"),
+    ("two-hop never triggers", "if (4 * (int64_t)og_unmatched(match, n) <= (int64_t)n) break;", "break;"),
 ]
 
 PIN_TESTS = [
@@ -67,6 +71,10 @@ PIN_TESTS = [
     pins.test_ablation_baseline_step_is_textbook_sync_lp,
     lambda O: pins.test_ablation_loop_iterates_textbook_lp(O, False),
     lambda O: pins.test_ablation_loop_iterates_textbook_lp(O, True),
+    pins.test_two_hop_star_leaves_closed_form,
+    pins.test_two_hop_isolated_vertices_never_pair,
+    pins.test_two_hop_pairs_are_within_two_hops,
+    pins.test_two_hop_passes_stop_once_three_quarters_match,
 ]
 
 

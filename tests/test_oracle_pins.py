@@ -540,3 +540,85 @@ def test_ablation_loop_iterates_textbook_lp(oracle_lib, locks):
             frozen = nxt != cur
             cur = nxt
         np.testing.assert_array_equal(res.iter_part, cur)
+
+
+# ------------------------------------------------- two-hop matching -----
+# Section 3.1: leaves, twins and relatives when more than a quarter of the
+# vertices stays unmatched after heavy-edge matching.
+
+def _groups(cmap):
+    out = {}
+    for v, c in enumerate(cmap):
+        out.setdefault(int(c), []).append(v)
+    return list(out.values())
+
+
+def test_two_hop_star_leaves_closed_form(oracle_lib):
+    """A hub with L leaves: heavy-edge matching pairs the hub with one leaf,
+    the leaves pass pairs the other L - 1 leaves in id order."""
+    O = oracle_lib
+    for L in (2, 3, 8, 9, 100, 101):
+        g = I.csr_from_edges(L + 1, np.zeros(L, np.int64), np.arange(1, L + 1))
+        nc, cmap = O.hem_map(g, 0, 7, two_hop=True)
+        assert nc == 1 + (L - 1 + 1) // 2, L
+        hub_mate = [v for v in range(1, L + 1) if cmap[v] == cmap[0]]
+        assert len(hub_mate) == 1
+        rest = [v for v in range(1, L + 1) if v != hub_mate[0]]
+        for i in range(0, len(rest) - 1, 2):
+            assert cmap[rest[i]] == cmap[rest[i + 1]]
+        if len(rest) % 2:
+            assert sum(1 for v in range(L + 1) if cmap[v] == cmap[rest[-1]]) == 1
+
+
+def test_two_hop_isolated_vertices_never_pair(oracle_lib):
+    """Twins are relatives (two hops apart), so vertices without edges stay
+    single whatever their number."""
+    O = oracle_lib
+    for n in (1, 2, 7, 10):
+        g = I.csr_from_edges(n, np.zeros(0, np.int64), np.zeros(0, np.int64))
+        nc, cmap = O.hem_map(g, 0, 3, two_hop=True)
+        assert nc == n
+        np.testing.assert_array_equal(cmap, np.arange(n))
+
+
+def test_two_hop_pairs_are_within_two_hops(oracle_lib):
+    """Every coarse vertex holds one vertex or a pair that is adjacent, two
+    hops apart, or of identical neighbourhood (isolated vertices included);
+    on meshes, where heavy-edge matching leaves few vertices, all pairs are
+    adjacent."""
+    O = oracle_lib
+    graphs = [(I.rmat(10, 4, s), False) for s in range(3)] + [(I.grid2d(20, 20), True), (I.stencil27(6, 6, 6), True)]
+    for g, mesh in graphs:
+        A = sp.csr_matrix((np.ones(g.nnz), g.adjncy, g.xadj), shape=(g.n, g.n))
+        A2 = (A @ A).tocsr()
+        nc, cmap = O.hem_map(g, 0, 5, two_hop=True)
+        for grp in _groups(cmap):
+            assert len(grp) <= 2
+            if len(grp) < 2:
+                continue
+            a, b = grp
+            adj = A[a, b] != 0
+            if mesh:
+                assert adj
+                continue
+            same = set(g.adjncy[g.xadj[a]:g.xadj[a + 1]]) == set(g.adjncy[g.xadj[b]:g.xadj[b + 1]])
+            assert adj or A2[a, b] != 0 or same, (a, b)
+
+
+def test_two_hop_passes_stop_once_three_quarters_match(oracle_lib):
+    """A hub with L leaves next to K(2, m) (m twins of neighbourhood {p, q}):
+    the leaves pass brings the unmatched count to at most n/4, so no twin pass
+    runs: all leaves but at most one pair up, and no two of the m twins do."""
+    O = oracle_lib
+    for L, m in ((101, 12), (80, 9), (63, 14)):
+        n = 1 + L + 2 + m
+        p, q = L + 1, L + 2
+        cs = np.arange(L + 3, n)
+        us = np.concatenate([np.zeros(L, np.int64), np.full(m, p), np.full(m, q)])
+        vs = np.concatenate([np.arange(1, L + 1), cs, cs])
+        g = I.csr_from_edges(n, us, vs)
+        nc, cmap = O.hem_map(g, 0, 11, two_hop=True)
+        groups = _groups(cmap)
+        leaf_pairs = sum(1 for grp in groups if len(grp) == 2 and all(1 <= v <= L for v in grp))
+        assert leaf_pairs >= (L - 2) // 2
+        assert not any(len(grp) == 2 and all(v >= L + 3 for v in grp) for grp in groups)
