@@ -395,7 +395,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_gain (connectivity/gain pass, finest level, Jetlp iterations)",
+            "kernel": "k_rows<4, 8, false, 1> in Jetlp iterations (connectivity/gain pass of the small rows, finest level)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -1039,10 +1039,9 @@ __device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int 
 // groups, waves, blocks), so each keeps its own register budget; a.tmap says
 // which classes a role serves. Group tables are padded to k + 1 ints so the
 // tables of neighbouring groups start in different LDS banks.
-template <bool B, int ROLE, int GS = 8, int RS = 32 / GS, int CL = CLS_S>
-__global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
+template <bool B, int ROLE, int GS, int RS, int CL>
+__device__ __forceinline__ void gain_body(const KArgs &a, int nblk)
 {
-    if (!any_kind(a, KIND_LP)) return;
     extern __shared__ int32_t lds[];
     const int stride = a.k + 1;
     GV pv, rv;
@@ -1136,6 +1135,13 @@ __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
     }
     acc_finish(a, pacc);
     acc_finish(a, racc);
+}
+
+template <bool B, int ROLE, int GS = 8, int RS = 32 / GS, int CL = CLS_S>
+__global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
+{
+    if (!any_kind(a, KIND_LP)) return;
+    gain_body<B, ROLE, GS, RS, CL>(a, nblk);
 }
 
 // -------------------------------------------------------------- afterburner --
@@ -1889,13 +1895,11 @@ __device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nb
 // 3 (k w(p) - W) (-1 outside A) and the B flags are copied to LDS first, so
 // a vertex's candidate test and its neighbours' B tests read LDS instead of
 // waiting on dependent global loads.
-template <bool B, int ROLE, int GS = 8, int RS = 32 / GS, bool PC = false, int CL = CLS_S>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ROLE == 1 && !B ? 8 : 1)))
-void k_rb_loss(KArgs a, int nblk, int hmode)
+template <bool B, int ROLE, int GS, int RS, bool PC, int CL>
+__device__ __forceinline__ void loss_body(const KArgs &a, int nblk, int hmode)
 {
     constexpr bool pcache = PC && !B && ROLE == 1;
     extern __shared__ int32_t lds[];
-    if (!any_rb(a)) return;
     const int stride = a.k + 1;
     GV pv, rv;
     CountX racc;
@@ -2026,6 +2030,24 @@ void k_rb_loss(KArgs a, int nblk, int hmode)
             if (lh[i]) atomicAdd((unsigned long long *)&a.hist[i], (unsigned long long)(int64_t)lh[i]);
     }
     acc_finish(a, racc);
+}
+
+template <bool B, int ROLE, int GS = 8, int RS = 32 / GS, bool PC = false, int CL = CLS_S>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ROLE == 1 && !B ? 8 : 1)))
+void k_rb_loss(KArgs a, int nblk, int hmode)
+{
+    if (!any_rb(a)) return;
+    loss_body<B, ROLE, GS, RS, PC, CL>(a, nblk, hmode);
+}
+
+// One launch for the small-row gain and loss passes of one graph: each
+// iteration is Jetlp or rebalancing, so a launch runs one of the two and the
+// other kind's launch is not needed.
+template <int GS, int RS, bool PC, int CL>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_rows(KArgs a, int nblk, int hmode)
+{
+    if (any_kind(a, KIND_LP)) gain_body<false, 1, GS, RS, CL>(a, nblk);
+    else if (any_rb(a)) loss_body<false, 1, GS, RS, PC, CL>(a, nblk, hmode);
 }
 
 // Rebalancing loss on long rows, phase 2 (one wave per vertex).
@@ -2704,12 +2726,13 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
 
 
 template <bool B>
-static void launch_gain_t(const Plan &pl, hipStream_t s)
+static void launch_gain_t(const Plan &pl, hipStream_t s, bool small = true)
 {
     const KArgs &t = pl.tab;
     const size_t st = (size_t)(t.k + 1) * 4;
     // small rows: one launch for both small classes when both are present
-    if (t.gS && t.gS2) {
+    if (!small) {
+    } else if (t.gS && t.gS2) {
         const int g = t.gS + t.gS2;
         if (t.k <= K_G4) k_gain<B, 1, 4, 8, NCLS><<<g, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, g);
         else k_gain<B, 1, 8, 4, NCLS><<<g, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, g);
@@ -2742,14 +2765,15 @@ static void launch_after_t(const Plan &pl, hipStream_t s)
 }
 
 template <bool B>
-static void launch_rb_loss_t(const Plan &pl, hipStream_t s)
+static void launch_rb_loss_t(const Plan &pl, hipStream_t s, bool small = true)
 {
     const KArgs &t = pl.tab;
     const int hm = pl.hist_fused ? HIST_LDS : HIST_NONE;
     const size_t hb = pl.hist_fused ? (size_t)t.k * NSLOT * 4 : 0;
     const size_t st = (size_t)(t.k + 1) * 4;
     const size_t cb = pl.loss_cache ? rb_cache_lds(t.k) : 0;
-    if (t.gS && t.gS2) {
+    if (!small) {
+    } else if (t.gS && t.gS2) {
         const size_t l1 = rb_role_lds(1, t.k) + hb + cb;
         const int g = t.gS + t.gS2;
         if (pl.loss_cache) {
@@ -2802,14 +2826,37 @@ static void launch_rb_select_t(const Plan &pl, hipStream_t s)
     k_rs_assign<<<pl.grid_tile, BLOCK, 0, s>>>(p);
 }
 
+// One graph: the small-row gain and loss passes in one launch (k_rows).
+template <bool PC>
+static void launch_rows_t(const Plan &pl, hipStream_t s)
+{
+    const KArgs &t = pl.tab;
+    const int hm = pl.hist_fused ? HIST_LDS : HIST_NONE;
+    const size_t extra = (pl.hist_fused ? (size_t)t.k * NSLOT * 4 : 0) + (PC ? rb_cache_lds(t.k) : 0);
+    if (t.gS && t.gS2) {
+        const int g = t.gS + t.gS2;
+        if (t.k <= K_G4) k_rows<4, 8, PC, NCLS><<<g, BLOCK, rb_role_lds(1, t.k) + extra, s>>>(t, g, hm);
+        else k_rows<8, 4, PC, NCLS><<<g, BLOCK, rb_role_lds(1, t.k) + extra, s>>>(t, g, hm);
+    } else if (t.gS) {
+        if (t.k <= K_G4) k_rows<4, 8, PC, CLS_S><<<t.gS, BLOCK, rb_role_lds(1, t.k) + extra, s>>>(t, t.gS, hm);
+        else k_rows<8, 4, PC, CLS_S><<<t.gS, BLOCK, rb_role_lds(1, t.k) + extra, s>>>(t, t.gS, hm);
+    } else if (t.gS2) {
+        k_rows<8, 8, PC, CLS_S2><<<t.gS2, BLOCK, rb_s2_lds(t.k) + extra, s>>>(t, t.gS2, hm);
+    }
+}
+
 template <bool B>
 static void launch_iteration_t(const Plan &pl, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b)
 {
     const KArgs &p = pl.plain;
     if (ev_a) (void)hipEventRecord(ev_a, s);
-    launch_gain_t<B>(pl, s);
+    if (!B) {
+        if (pl.loss_cache) launch_rows_t<true>(pl, s);
+        else launch_rows_t<false>(pl, s);
+    }
+    launch_gain_t<B>(pl, s, B);
     if (ev_b) (void)hipEventRecord(ev_b, s);
-    launch_rb_loss_t<B>(pl, s);
+    launch_rb_loss_t<B>(pl, s, B);
     launch_rb_cutoff_t<B>(pl, s);
     launch_after_t<B>(pl, s);
     launch_rb_select_t<B>(pl, s);
@@ -2899,6 +2946,17 @@ static void set_lds_limits_t()
     (void)hipFuncSetAttribute((const void *)k_lconn<B, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
 }
 
+template <bool PC>
+static void set_lds_limits_rows()
+{
+    (void)hipFuncSetAttribute((const void *)k_rows<4, 8, PC, NCLS>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rows<8, 4, PC, NCLS>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rows<4, 8, PC, CLS_S>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rows<8, 4, PC, CLS_S>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    (void)hipFuncSetAttribute((const void *)k_rows<8, 8, PC, CLS_S2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              65536);
+}
+
 static void set_lds_limits()
 {
     static bool done = false;
@@ -2906,6 +2964,8 @@ static void set_lds_limits()
     done = true;
     set_lds_limits_t<false>();
     set_lds_limits_t<true>();
+    set_lds_limits_rows<false>();
+    set_lds_limits_rows<true>();
     (void)hipFuncSetAttribute((const void *)k_init_vertices, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
 }
 
