@@ -817,6 +817,14 @@ static void *hier_alloc(jet_hierarchy *h, size_t bytes)
 {
     if (h->arena) return h->arena->alloc(bytes);
     void *p = nullptr;
+    if (h->pool) {
+        if (hipMallocFromPoolAsync(&p, bytes ? bytes : 16, h->pool, h->pool_stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        h->owned.push_back(p);
+        return p;
+    }
     if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) {
         (void)hipGetLastError();
         return nullptr;
@@ -828,7 +836,10 @@ static void *hier_alloc(jet_hierarchy *h, size_t bytes)
 static void hier_release(jet_hierarchy *h)
 {
     if (h->arena) h->arena->reset();
-    for (void *p : h->owned) (void)hipFree(p);
+    for (void *p : h->owned) {
+        if (h->pool) (void)hipFreeAsync(p, h->pool_stream);
+        else (void)hipFree(p);
+    }
     h->owned.clear();
 }
 

@@ -141,6 +141,8 @@ struct jet_hierarchy {
     std::vector<int32_t *> maps;    // maps[l]: level l -> level l+1 (owned)
     std::vector<void *> owned;      // device buffers owned by the hierarchy (no arena)
     jet::Arena *arena = nullptr;    // when set, levels live in this arena instead
+    hipMemPool_t pool = nullptr;    // else, when set: stream-ordered allocations from this pool
+    hipStream_t pool_stream = nullptr;
     float ms_coarsen = 0.f;
 };
 

@@ -37,6 +37,8 @@ struct SJob {
     jet_hierarchy h;
     bool has_h = false;
     int32_t *buf = nullptr;  // two coarse partition buffers of n_1 ints each
+    hipMemPool_t pool = nullptr;  // where buf came from (nullptr: hipMalloc)
+    hipStream_t pool_stream = nullptr;
     int32_t *cur = nullptr;  // partition of the current level
     int level = 0;           // level refined by the next step
     jet_result res;
@@ -55,6 +57,7 @@ static size_t job_footprint(const jet_csr &g)
 struct jet_server {
     jet_context *ctx = nullptr;
     hipStream_t stream = nullptr;
+    hipMemPool_t pool = nullptr;  // stream-ordered job memory (hierarchies, partition buffers)
     size_t budget = 0;
     int max_slots = 1;
     std::chrono::steady_clock::time_point t0;
@@ -84,7 +87,8 @@ static void free_job(SJob *j)
         j->has_h = false;
     }
     if (j->buf) {
-        (void)hipFree(j->buf);
+        if (j->pool) (void)hipFreeAsync(j->buf, j->pool_stream);
+        else (void)hipFree(j->buf);
         j->buf = nullptr;
     }
 }
@@ -99,6 +103,10 @@ static int start_job(jet_server *sv, SJob *j)
     const jet_params &p = j->spec.params;
     int st = check_graph(ctx, &g, p.flags, s);
     if (st) return st;
+    j->h.pool = sv->pool;
+    j->h.pool_stream = s;
+    j->pool = sv->pool;
+    j->pool_stream = s;
     st = hierarchy_build(ctx, &g, &p, &j->h, s);
     j->has_h = true;
     if (st) return st;
@@ -109,7 +117,9 @@ static int start_job(jet_server *sv, SJob *j)
         j->cur = j->spec.part_out;
     } else {
         const size_t n1 = (size_t)std::max(j->h.lv[1].n, 1);
-        if (hipMalloc((void **)&j->buf, 2 * n1 * sizeof(int32_t)) != hipSuccess) {
+        const hipError_t e = sv->pool ? hipMallocFromPoolAsync((void **)&j->buf, 2 * n1 * sizeof(int32_t), sv->pool, s)
+                                      : hipMalloc((void **)&j->buf, 2 * n1 * sizeof(int32_t));
+        if (e != hipSuccess) {
             (void)hipGetLastError();
             j->buf = nullptr;
             return JET_ENOMEM;
@@ -256,9 +266,27 @@ extern "C" int jet_server_create(jet_server **out, jet_context *ctx, size_t hbm_
         delete sv;
         return st;
     }
+    // job memory comes from a private stream-ordered pool that keeps what it
+    // has (no device-wide wait per freed hierarchy); without one, plain
+    // allocations are used
+    {
+        hipMemPoolProps props;
+        memset(&props, 0, sizeof(props));
+        props.allocType = hipMemAllocationTypePinned;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = ctx->device;
+        if (hipMemPoolCreate(&sv->pool, &props) == hipSuccess) {
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(sv->pool, hipMemPoolAttrReleaseThreshold, &keep);
+        } else {
+            (void)hipGetLastError();
+            sv->pool = nullptr;
+        }
+    }
     try {
         sv->worker = std::thread(worker_main, sv);
     } catch (...) {
+        if (sv->pool) (void)hipMemPoolDestroy(sv->pool);
         (void)hipStreamDestroy(sv->stream);
         delete sv;
         return JET_ENOMEM;
@@ -343,6 +371,8 @@ extern "C" void jet_server_destroy(jet_server *sv)
     }
     if (sv->worker.joinable()) sv->worker.join();
     (void)hipSetDevice(sv->ctx->device);
+    (void)hipStreamSynchronize(sv->stream);
+    if (sv->pool) (void)hipMemPoolDestroy(sv->pool);
     (void)hipStreamDestroy(sv->stream);
     delete sv;
 }
