@@ -1222,7 +1222,7 @@ __device__ void afterburner_body(const KArgs &a, int b)
             },
             [&](const Meta &t, int gl) {
                 const int ps = t.ps >> 16, pd = (t.ps & 0xFFFF) - 1;
-                int sum = after_sum_row<1>(a, t.v, t.s, t.deg, ps, pd, t.aux, gl, 8);
+                int sum = after_sum_row<4>(a, t.v, t.s, t.deg, ps, pd, t.aux, gl, 8);
                 sum = gsum<8>(sum);
                 if (gl == 0) after_store(a, t.v, pd, sum);
             });
@@ -1374,7 +1374,7 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
                 return true;
             },
             [&](const Meta &t, int gl) {
-                int d = dcut_sum_row<1>(a, t.v, t.s, t.deg, t.ps, t.aux, gl, 8);
+                int d = dcut_sum_row<4>(a, t.v, t.s, t.deg, t.ps, t.aux, gl, 8);
                 d = gsum<8>(d);
                 if (gl == 0) {
                     cacc.sel<B>(a, t.g);
