@@ -50,8 +50,8 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE runs (each calibrated by a plain 2^28-byte copy), valid only for
 # the kernel source they were taken on (profiles/k_gain_stencil128_k64.md).
 TRAFFIC = {
-    "stencil128": dict(src_sha256="980bd13d9d2d4b63eade386913243a1dce6c12f501d0ba4f100b973d43e94144",
-                       fetch=258796259, write=18009466, fetch_factor=1.9997, write_factor=1.0),
+    "stencil128": dict(src_sha256="c3626fcdd19a6d41c49409e73247767da45e0ff6909c947b6d8caa03d28092a3",
+                       fetch=258780648, write=18009920, fetch_factor=1.9997, write_factor=1.0),
 }
 
 
