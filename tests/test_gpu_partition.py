@@ -117,3 +117,39 @@ def test_partition_errors(J):
     with pytest.raises(J.JetError) as e:
         J.partition(J.DeviceGraph(dg.xadj, dg.adjncy, None, big), 4)
     assert e.value.status == J.JET_EOVERFLOW
+
+
+@pytest.mark.parametrize("env", [{"JET_NO_GRAPH": "1"}, {"JET_BLOCKING_WAIT": "1"}],
+                         ids=["direct_launches", "blocking_wait"])
+def test_partition_host_loop_variants(J, O, env):
+    """A context created without graph replay (iterations launched one by one)
+    or with the runtime's blocking wait gives the same partitions, batch
+    included."""
+    import os
+    import torch
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        ctx = J.Context()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    try:
+        for name, g, k, seed in CASES[:4]:
+            exp = O.partition(g, k, seed=seed)
+            part, st, tr = J.partition(J.to_device(g), k, seed=seed, trace_cap=100000, ctx=ctx)
+            np.testing.assert_array_equal(part.cpu().numpy(), exp["part"], err_msg=name)
+            assert tr == exp["trace"], name
+        gs = [g for _, g, _, _ in CASES[:4]]
+        dgs = [J.to_device(g) for g in gs]
+        p0 = [I.random_partition(g.n, k, 5) for g, (_, _, k, _) in zip(gs, CASES[:4])]
+        parts = [torch.from_numpy(p.copy()).cuda() for p in p0]
+        J.refine_batch(dgs, parts, [dict(k=k, seed=1) for _, _, k, _ in CASES[:4]], ctx=ctx)
+        for (name, g, k, _), P0, p in zip(CASES[:4], p0, parts):
+            exp = O.refine(g, P0, k, seed=1)
+            np.testing.assert_array_equal(p.cpu().numpy(), exp.part, err_msg=name)
+    finally:
+        ctx.close()
