@@ -100,6 +100,7 @@ struct KArgs {
     // block counts per role of the row kernels
     int32_t gS, gM, gL, gZ;
     int32_t gS2;           // blocks of the wide small-row kernels (class S2 in the small-row role)
+    int32_t sident;        // one graph whose vertices all sit in the small class: its list is 0..n-1
     int32_t tmap[NCLS];    // which role (1 S, 2 M, 3 L) serves each class in the LDS-table kernels
     // long rows of the L class cut into chunks (see LCHUNK); nlch = 0: L rows use the block role
     const int2 *lch;       // (index in the L list, chunk index) per chunk

@@ -829,7 +829,7 @@ __device__ __forceinline__ void wave_batched(const int32_t *list, Walk w, int32_
         Meta m{0, 0, 0, 0, 0, 0};
         bool act = false;
         if (lane < unit && i < w.end) {
-            m.v = list[i];
+            m.v = list ? list[i] : i;  // no list: entry i is vertex i
             act = pre(m);
         }
         const uint64_t mask = __ballot(act);
@@ -1068,7 +1068,8 @@ __device__ __forceinline__ void gain_body(const KArgs &a, int nblk)
             if (!B && CL != NCLS) bid = xcd_block(bid, nb);
             const int wid = bid * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nb * (BLOCK / 64);
             wave_batched<G>(
-                a.bins + a.binoff[cl], walk<B>(a.binoff[cl + 1] - a.binoff[cl], wid, nwaves, 64), q,
+                (!B && cl == CLS_S && a.sident) ? nullptr : a.bins + a.binoff[cl],
+                walk<B>(a.binoff[cl + 1] - a.binoff[cl], wid, nwaves, 64), q,
                 [&](Meta &m) -> bool {
                     m.g = gof<B>(a, m.v);
                     pv.sel<B>(a, m.g);
@@ -1200,7 +1201,7 @@ __device__ void afterburner_body(const KArgs &a, int b)
     if (b < a.gS) {
         int32_t *q = s_q + (threadIdx.x >> 6) * 64;
         wave_batched<8>(
-            a.bins + a.binoff[CLS_S],
+            (!B && a.sident) ? nullptr : a.bins + a.binoff[CLS_S],
             walk<B>(a.binoff[CLS_S2 + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6), a.gS * (BLOCK / 64),
                  64),
             q,
@@ -1356,7 +1357,7 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
     if (b < a.gS) {
         int32_t *q = s_q + (threadIdx.x >> 6) * 64;
         wave_batched<8>(
-            a.bins + a.binoff[CLS_S],
+            (!B && a.sident) ? nullptr : a.bins + a.binoff[CLS_S],
             walk<B>(a.binoff[CLS_S2 + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6), a.gS * (BLOCK / 64),
                  64),
             q,
@@ -1935,7 +1936,8 @@ __device__ __forceinline__ void loss_body(const KArgs &a, int nblk, int hmode)
             int32_t *tab = lds + (threadIdx.x / G) * stride;
             const int wid = bid * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nb * (BLOCK / 64);
             wave_batched<G>(
-                a.bins + a.binoff[cl], walk<B>(a.binoff[cl + 1] - a.binoff[cl], wid, nwaves, 64), q,
+                (!B && cl == CLS_S && a.sident) ? nullptr : a.bins + a.binoff[cl],
+                walk<B>(a.binoff[cl + 1] - a.binoff[cl], wid, nwaves, 64), q,
                 [&](Meta &m) -> bool {
                     m.g = gof<B>(a, m.v);
                     pv.sel<B>(a, m.g);
@@ -2678,6 +2680,9 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
     for (int c = 1; c < NCLS; c++) role_cnt[t.tmap[c]] += cnt[c];
     t.gS = t.tmap[CLS_S] == 1 ? std::min(div_up(cnt[CLS_S], BLOCK / 8), maxb) : 0;
     t.gS2 = t.tmap[CLS_S2] == 1 ? std::min(div_up(cnt[CLS_S2], BLOCK / 8), maxb) : 0;
+    // one graph with every vertex in the small class (a mesh's finest levels):
+    // its class list is the identity and is not read
+    t.sident = a.vg == nullptr && cnt[CLS_S] == a.n ? 1 : 0;
     t.gM = std::min(div_up(role_cnt[2], BLOCK / 64), maxb);
     t.gL = std::min((int)role_cnt[3], maxb);
     t.gZ = std::min(div_up(cnt[0], BLOCK), maxb);
@@ -2692,6 +2697,7 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
     KArgs p = a;
     p.tmap[CLS_Z] = 0; p.tmap[CLS_S] = 1; p.tmap[CLS_S2] = 1; p.tmap[CLS_M] = 2; p.tmap[CLS_L] = 3;
     p.gS = std::min(div_up(cnt[CLS_S] + cnt[CLS_S2], BLOCK / 8), maxb);
+    p.sident = t.sident;
     p.gM = std::min(div_up(cnt[CLS_M], BLOCK / 64), maxb);
     p.gL = chunked ? 0 : std::min(cnt[CLS_L], maxb);
     p.gZ = std::min(div_up(cnt[CLS_Z], BLOCK), maxb);
