@@ -461,7 +461,11 @@ __global__ __launch_bounds__(BLOCK) void k_fill_bins_active(KArgs a, const int32
 // Oversized parts A = {w > o}, valid destinations B = {w <= sigma} listed in
 // ascending id, and a cleared (part, slot) histogram, for graph g. Whole
 // block calls.
-__device__ void rb_prepare(const KArgs &a, int g)
+// wreg: when not null, the caller's registers hold w(p) for p = threadIdx.x +
+// j * BLOCK, j < WREG (k <= WREG * BLOCK).
+constexpr int WREG = 4;
+
+__device__ void rb_prepare(const KArgs &a, int g, const int64_t *wreg = nullptr)
 {
     __shared__ int32_t s_scan[BLOCK / 64];
     Ctl *c = a.ctl + g;
@@ -472,7 +476,7 @@ __device__ void rb_prepare(const KArgs &a, int g)
         const int p = base + threadIdx.x;
         int inA = 0, inB = 0;
         if (p < k) {
-            const int64_t wp = a.w[poff + p];
+            const int64_t wp = wreg ? wreg[base / BLOCK] : a.w[poff + p];
             inA = wp > o;
             inB = wp <= sigma;
             a.isA[poff + p] = (uint8_t)inA;
@@ -538,10 +542,10 @@ __device__ __forceinline__ int ctl_next(Ctl &cc)
 
 // Whole-block part of starting graph g's next iteration: clear its counter
 // shards and, for rebalancing, build A, B and clear its histogram.
-__device__ __forceinline__ void begin_iteration(const KArgs &a, int g, int kind)
+__device__ __forceinline__ void begin_iteration(const KArgs &a, int g, int kind, const int64_t *wreg = nullptr)
 {
     for (int i = threadIdx.x; i < NSTAT * NSHARD; i += BLOCK) a.bstat[(int64_t)g * NSTAT * NSHARD + i] = 0;
-    if (is_rb(kind)) rb_prepare(a, g);
+    if (is_rb(kind)) rb_prepare(a, g, wreg);
 }
 
 // Adds graph g's next kind (and whether its best must be copied) to the
@@ -624,10 +628,23 @@ __global__ __launch_bounds__(BLOCK) void k_ctl_end(KArgs a)
     }
     int64_t pe = 0;
     if (threadIdx.x < NSHARD && kind == KIND_LP) pe = a.bstat[(int64_t)g * NSTAT * NSHARD + ST_E * NSHARD + threadIdx.x];
+    // part weights stay in registers for the best copy and the rebalancing set-up
+    const bool inreg = k <= WREG * BLOCK;
+    int64_t wreg[WREG];
+#pragma unroll
+    for (int j = 0; j < WREG; j++) {
+        const int p = threadIdx.x + j * BLOCK;
+        wreg[j] = (inreg && p < k) ? a.w[poff + p] : 0;
+    }
     uint64_t m = 0;
-    for (int p = threadIdx.x; p < k; p += BLOCK) {
-        const uint64_t x = (uint64_t)a.w[poff + p];
-        m = x > m ? x : m;
+    if (inreg) {
+#pragma unroll
+        for (int j = 0; j < WREG; j++) m = (uint64_t)wreg[j] > m ? (uint64_t)wreg[j] : m;
+    } else {
+        for (int p = threadIdx.x; p < k; p += BLOCK) {
+            const uint64_t x = (uint64_t)a.w[poff + p];
+            m = x > m ? x : m;
+        }
     }
     m = block_max_u64<BLOCK>(m, s_red);
     int64_t px = 0, pm = 0, pdc = 0, pmw = 0, pr = 0, pv = 0;
@@ -708,9 +725,18 @@ __global__ __launch_bounds__(BLOCK) void k_ctl_end(KArgs a)
         count_next(a, a.it + 1, next, improved);
     }
     __syncthreads();
-    if (s_improved)
-        for (int p = threadIdx.x; p < k; p += BLOCK) a.wbest[poff + p] = a.w[poff + p];
-    begin_iteration(a, g, s_next);
+    if (s_improved) {
+        if (inreg) {
+#pragma unroll
+            for (int j = 0; j < WREG; j++) {
+                const int p = threadIdx.x + j * BLOCK;
+                if (p < k) a.wbest[poff + p] = wreg[j];
+            }
+        } else {
+            for (int p = threadIdx.x; p < k; p += BLOCK) a.wbest[poff + p] = a.w[poff + p];
+        }
+    }
+    begin_iteration(a, g, s_next, inreg ? wreg : nullptr);
 }
 
 // After the loop: P_iter into P_best for graphs whose last iteration improved
