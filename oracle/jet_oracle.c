@@ -57,6 +57,9 @@ typedef struct {
 #define OG_F_NO_AFTERBURNER 0x10
 /* coarsening with two-hop matching (Section 3.1) after heavy-edge matching */
 #define OG_F_TWO_HOP 0x20
+/* graph-growing start of the coarsest graph (og_bfs_part) instead of the
+ * seeded random one */
+#define OG_F_BFS_START 0x40
 
 typedef struct {
     int32_t level, t, kind, nX, nM, stall, wcount, balanced;
@@ -650,10 +653,69 @@ void og_contract(const og_graph *g, const int32_t *map, int32_t nc, int64_t **cx
 
 void og_free(void *p) { free(p); }
 
+/* ---- graph-growing start of the coarsest graph ---------------------------
+ * Not from the paper, whose coarsest partition comes from Metis (Section 3):
+ * every connected component is searched breadth-first from its smallest
+ * vertex id; vertices are ordered by (that id, distance from it, own id) and
+ * the order is cut into k consecutive runs of equal vertex weight: a vertex
+ * whose predecessors in the order weigh b goes to part floor(b k / W), W the
+ * total vertex weight (W = 0: part 0). */
+typedef struct { int32_t root, dist, v; } og_bkey;
+
+static int og_bkey_cmp(const void *pa, const void *pb)
+{
+    const og_bkey *a = (const og_bkey *)pa, *b = (const og_bkey *)pb;
+    if (a->root != b->root) return a->root < b->root ? -1 : 1;
+    if (a->dist != b->dist) return a->dist < b->dist ? -1 : 1;
+    return (a->v > b->v) - (a->v < b->v);
+}
+
+void og_bfs_part(const og_graph *g, int32_t k, int32_t *part)
+{
+    const int32_t n = g->n;
+    if (n <= 0) return;
+    int32_t *dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    og_bkey *order = (og_bkey *)malloc(sizeof(og_bkey) * (size_t)n);
+    for (int32_t v = 0; v < n; v++) dist[v] = -1;
+    for (int32_t r = 0; r < n; r++) {
+        if (dist[r] >= 0) continue;
+        int32_t head = 0, tail = 0;
+        queue[tail++] = r;
+        dist[r] = 0;
+        while (head < tail) {
+            const int32_t v = queue[head++];
+            order[v].root = r;
+            order[v].dist = dist[v];
+            order[v].v = v;
+            for (int64_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+                const int32_t u = g->adjncy[e];
+                if (dist[u] < 0) {
+                    dist[u] = dist[v] + 1;
+                    queue[tail++] = u;
+                }
+            }
+        }
+    }
+    qsort(order, (size_t)n, sizeof(og_bkey), og_bkey_cmp);
+    int64_t W = 0;
+    for (int32_t v = 0; v < n; v++) W += g->vwgt ? g->vwgt[v] : 1;
+    int64_t b = 0;
+    for (int32_t i = 0; i < n; i++) {
+        const int32_t v = order[i].v;
+        part[v] = W > 0 ? (int32_t)(((unsigned __int128)(uint64_t)b * (uint64_t)k) / (uint64_t)W) : 0;
+        b += g->vwgt ? g->vwgt[v] : 1;
+    }
+    free(dist);
+    free(queue);
+    free(order);
+}
+
 /* ---- multilevel template (Algorithm 1) ---------------------------------
  * Coarsen until n <= 8k, or a level shrinks by less than 10%, or 64 levels;
  * seeded uniform random partition of the coarsest graph,
- * P[v] = floor(stream(mix64(seed ^ 1), v) * k / 2^64); refine it; then
+ * P[v] = floor(stream(mix64(seed ^ 1), v) * k / 2^64), or with
+ * OG_F_BFS_START the graph-growing start og_bfs_part; refine it; then
  * project (P_i[v] = P_{i+1}[map_i[v]]) and refine each finer level.
  * Level numbers: 0 = input graph. Returns the number of levels (>= 1).
  * level_sizes (optional, [64]) receives n of each level. */
@@ -681,8 +743,12 @@ int32_t og_partition(const og_graph *g, const og_params *prm, int32_t *part, og_
     if (level_sizes) for (int32_t i = 0; i < nl; i++) level_sizes[i] = G[i].n;
     int32_t l = nl - 1;
     int32_t *P = (int32_t *)malloc(sizeof(int32_t) * (size_t)(G[l].n > 0 ? G[l].n : 1));
-    uint64_t s_init = og_mix64(prm->seed ^ 1ULL);
-    for (int32_t v = 0; v < G[l].n; v++) P[v] = (int32_t)og_below(og_stream(s_init, (uint64_t)v), (uint64_t)k);
+    if (prm->flags & OG_F_BFS_START) {
+        og_bfs_part(&G[l], k, P);
+    } else {
+        uint64_t s_init = og_mix64(prm->seed ^ 1ULL);
+        for (int32_t v = 0; v < G[l].n; v++) P[v] = (int32_t)og_below(og_stream(s_init, (uint64_t)v), (uint64_t)k);
+    }
     int32_t tr = 0;
     for (int32_t i = l; i >= 0; i--) {
         if (i < l) {

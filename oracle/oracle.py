@@ -121,6 +121,7 @@ class _G:
 F_NO_LOCKS = 0x8
 F_NO_AFTERBURNER = 0x10
 F_TWO_HOP = 0x20
+F_BFS_START = 0x40
 
 
 def make_params(k, lambda_ppm=30000, c=None, phi=(999, 1000), stall_limit=12, bmax=2,
@@ -214,6 +215,16 @@ def partition(g, k, trace_cap=200000, **kw):
                             _ptr(sizes), _ptr(st))
     return dict(part=P, trace=trace_to_dicts(tr, ntr.value), level_sizes=sizes[:nl].copy(),
                 cut=int(st[0]), maxw=int(st[1]), balanced=bool(st[2]), o=int(st[3]))
+
+
+def bfs_part(g, k):
+    """Graph-growing start of a coarsest graph (og_bfs_part): components
+    searched breadth-first from their smallest id, vertices ordered by (that
+    id, distance, id), the order cut into k runs of equal vertex weight."""
+    G = _G(g)
+    P = np.zeros(max(G.s.n, 1), np.int32)
+    lib().og_bfs_part(C.byref(G.s), C.c_int32(k), _ptr(P))
+    return P[:G.s.n]
 
 
 def hem_map(g, level, seed, two_hop=False):

@@ -49,6 +49,11 @@ MUTANTS = [
      "kv[m].key = (uint64_t)(uint32_t)v;"),
     ("two-hop pairs overlap", "for (int32_t a = i; a + 1 < j; a += 2) {", "for (int32_t a = i; a + 1 < j; a += 1) {"),
     ("two-hop never triggers", "if (4 * (int64_t)og_unmatched(match, n) <= (int64_t)n) break;", "break;"),
+    ("start order ignores distance", "if (a->dist != b->dist) return a->dist < b->dist ? -1 : 1;\n", ""),
+    ("start grows from largest id", "for (int32_t r = 0; r < n; r++) {\n        if (dist[r] >= 0) continue;",
+     "for (int32_t r = n - 1; r >= 0; r--) {\n        if (dist[r] >= 0) continue;"),
+    ("start chunks by count", "        b += g->vwgt ? g->vwgt[v] : 1;\n    }\n    free(dist);",
+     "        b += 1;\n    }\n    free(dist);"),
 ]
 
 PIN_TESTS = [
@@ -75,6 +80,8 @@ PIN_TESTS = [
     pins.test_two_hop_isolated_vertices_never_pair,
     pins.test_two_hop_pairs_are_within_two_hops,
     pins.test_two_hop_passes_stop_once_three_quarters_match,
+    pins.test_bfs_start_closed_forms,
+    pins.test_bfs_start_against_library_bfs,
 ]
 
 

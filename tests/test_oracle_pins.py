@@ -622,3 +622,96 @@ def test_two_hop_passes_stop_once_three_quarters_match(oracle_lib):
         leaf_pairs = sum(1 for grp in groups if len(grp) == 2 and all(1 <= v <= L for v in grp))
         assert leaf_pairs >= (L - 2) // 2
         assert not any(len(grp) == 2 and all(v >= L + 3 for v in grp) for grp in groups)
+
+
+# ---- graph-growing start of the coarsest graph (og_bfs_part) ---------------
+
+def test_bfs_start_closed_forms(oracle_lib):
+    """Hand-worked orders: (component's smallest id, distance from it, id),
+    cut into k runs of equal weight (part = floor(b k / W))."""
+    O = oracle_lib
+    # path 0-1-...-9 in id order: the order is the id order
+    g = graph_from_edges(10, [(v, v + 1, 1) for v in range(9)])
+    assert O.bfs_part(g, 3).tolist() == [0, 0, 0, 0, 1, 1, 1, 2, 2, 2]
+    # path 3-1-0-2-4: distances from 0 are 2,1,0,1,2 -> order 0,1,2,3,4
+    g = graph_from_edges(5, [(3, 1, 1), (1, 0, 1), (0, 2, 1), (2, 4, 1)])
+    assert O.bfs_part(g, 5).tolist() == [0, 1, 2, 3, 4]
+    assert O.bfs_part(g, 2).tolist() == [0, 0, 0, 1, 1]
+    # components {0, 2}, {1, 3} and the single vertex 4: order 0, 2, 1, 3, 4
+    g = graph_from_edges(5, [(0, 2, 1), (1, 3, 1)])
+    assert O.bfs_part(g, 5).tolist() == [0, 2, 1, 3, 4]
+    # star whose centre is 5: leaf 0 first, the centre second, then the leaves
+    g = graph_from_edges(7, [(5, v, 1) for v in (0, 1, 2, 3, 4, 6)])
+    assert O.bfs_part(g, 7).tolist() == [0, 2, 3, 4, 5, 1, 6]
+    # vertex weights 3,1,4,1,2,1 (W = 12, k = 3): weights before each vertex
+    # 0,3,4,8,9,11 -> floor(3 b / 12) = 0,0,1,2,2,2
+    g = graph_from_edges(6, [(v, v + 1, 1) for v in range(5)], vwgt=[3, 1, 4, 1, 2, 1])
+    assert O.bfs_part(g, 3).tolist() == [0, 0, 1, 2, 2, 2]
+    # k = 1: one part
+    assert O.bfs_part(g, 1).tolist() == [0] * 6
+
+
+def test_bfs_start_grid_is_manhattan_layers(oracle_lib):
+    """On an r x c grid (id = y c + x) the distance from vertex 0 is x + y."""
+    O = oracle_lib
+    for r, c, k in ((7, 5, 4), (12, 12, 9), (3, 40, 6)):
+        g = I.grid2d(r, c)
+        n = g.n
+        ids = np.arange(n)
+        y, x = ids // c, ids % c
+        order = np.lexsort((ids, x + y))
+        part = O.bfs_part(g, k)
+        exp = np.empty(n, np.int64)
+        exp[order] = (np.arange(n) * k) // n
+        np.testing.assert_array_equal(part, exp)
+
+
+def test_bfs_start_against_library_bfs(oracle_lib):
+    """Random weighted graphs with several components: the order from
+    scipy's connected components and unweighted shortest paths."""
+    from scipy.sparse.csgraph import connected_components, shortest_path
+    O = oracle_lib
+    rng = np.random.default_rng(31)
+    for trial in range(6):
+        n = int(rng.integers(20, 90))
+        m = int(rng.integers(n // 2, 2 * n))
+        a = rng.integers(0, n, m)
+        b = rng.integers(0, n, m)
+        keep = a != b
+        edges = [(int(u), int(v), 1) for u, v in zip(a[keep], b[keep])]
+        vw = rng.integers(1, 9, n).tolist()
+        g = graph_from_edges(n, edges, vwgt=vw)
+        A = sp.csr_matrix((np.ones(g.nnz), g.adjncy, g.xadj), shape=(n, n))
+        ncomp, lab = connected_components(A, directed=False)
+        root = np.array([np.flatnonzero(lab == lab[v]).min() for v in range(n)])
+        D = shortest_path(A, unweighted=True, directed=False)
+        dist = D[root, np.arange(n)].astype(np.int64)
+        order = np.lexsort((np.arange(n), dist, root))
+        for k in (1, 2, 5, 16):
+            W = int(sum(vw))
+            exp = np.empty(n, np.int64)
+            b = 0
+            for v in order:
+                exp[v] = (b * k) // W
+                b += vw[v]
+            part = O.bfs_part(g, k)
+            np.testing.assert_array_equal(part, exp, err_msg=f"trial {trial} k {k}")
+            # runs are consecutive in the order and no part exceeds W/k by a vertex
+            assert np.all(np.diff(part[order]) >= 0)
+            pw = np.bincount(part, weights=vw, minlength=k)
+            assert pw.max() <= W / k + max(vw)
+
+
+def test_partition_with_bfs_start_is_valid(oracle_lib):
+    """The full multilevel partition from the graph-growing start: part ids
+    in range, balanced within lambda on a mesh, and a cut no larger than
+    from the random start on this instance."""
+    O = oracle_lib
+    g = I.grid2d(48, 48)
+    k = 8
+    r_bfs = O.partition(g, k, seed=3, flags=O.F_BFS_START)
+    r_rnd = O.partition(g, k, seed=3)
+    p = r_bfs["part"]
+    assert p.min() >= 0 and p.max() < k
+    assert r_bfs["balanced"]
+    assert r_bfs["cut"] <= r_rnd["cut"]
