@@ -244,7 +244,8 @@ def ablation_bench(J, dg, k, seed, label):
                 ("full Jetlp", dict()),
                 ("full Jetlp, phi 0.99", dict(phi=(99, 100))),
                 ("full Jetlp, phi 0.9999", dict(phi=(9999, 10000))),
-                ("full Jetlp, two-hop coarsening", dict(flags=J.JET_F_TWO_HOP))]
+                ("full Jetlp, two-hop coarsening", dict(flags=J.JET_F_TWO_HOP)),
+                ("full Jetlp, graph-growing start", dict(flags=J.JET_F_BFS_START))]
     rows = []
     for name, kw in variants:
         J.partition(dg, k, seed=seed, **kw)

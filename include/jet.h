@@ -69,6 +69,10 @@ extern "C" {
  * same matchmaker: the smallest-id matched neighbour of at most 1024
  * entries); equal keys pair in ascending id order. */
 #define JET_F_TWO_HOP           0x20u
+/* Multilevel partition (jet_partition, serving jobs): start the coarsest
+ * graph from jet_bfs_start's graph-growing partition instead of the seeded
+ * random one. */
+#define JET_F_BFS_START         0x40u
 
 typedef struct jet_context jet_context;
 typedef struct jet_hierarchy jet_hierarchy;
@@ -248,11 +252,24 @@ void jet_hierarchy_free(jet_hierarchy *h);
 
 /* Full multilevel partition (Algorithm 1): coarsen, seeded uniform random
  * partition of the coarsest graph P[v] = floor(stream(mix64(seed ^ 1), v) k
- * / 2^64), refine it, then project and refine every finer level (c = 3/4
+ * / 2^64) (with JET_F_BFS_START: jet_bfs_start's partition), refine it, then
+ * project and refine every finer level (c = 3/4
  * above level 0, 1/4 at level 0 unless params sets c). part_out: device
  * int32[n]. The trace, if given, concatenates the levels' records. */
 int jet_partition(jet_context *ctx, const jet_csr *g, const jet_params *params, int32_t *part_out,
                   jet_stats *stats, jet_trace *trace, void *stream);
+
+/* Graph-growing start (the paper takes its coarsest partition from Metis and
+ * leaves a GPU initial partitioner to future work, Section 3): every
+ * connected component is grown breadth-first from its smallest vertex id;
+ * vertices are ordered by (that id, BFS distance from it, own id), and the
+ * order is cut into k runs of equal vertex weight: the vertex whose
+ * predecessors in the order weigh b gets part floor(b k / W), W the total
+ * vertex weight. Deterministic (no seed). part: device int32[n], written.
+ * Returns JET_EINVAL (NULL pointers, k < 1), JET_ELIMIT (k > 16384),
+ * JET_EGRAPH (malformed CSR), JET_ENOMEM. Waits on `stream` a few times
+ * (one look per four relaxation passes). */
+int jet_bfs_start(jet_context *ctx, const jet_csr *g, int32_t k, int32_t *part, void *stream);
 
 /* ---- serving loop ---------------------------------------------------------
  * A server partitions submitted jobs (each one jet_partition call's worth of
@@ -261,7 +278,8 @@ int jet_partition(jet_context *ctx, const jet_csr *g, const jet_params *params, 
  *   1. admit queued jobs in submission order while fewer than max_slots are
  *      active and the job's HBM footprint fits in what the budget has left;
  *      an admitted job is checked, coarsened (its hierarchy stays in device
- *      memory until the job ends) and gets its seeded coarsest partition;
+ *      memory until the job ends) and gets its coarsest start (seeded random,
+ *      or graph-growing with JET_F_BFS_START);
  *   2. refine the current level of every active job in one jet_refine_batch
  *      launch sequence;
  *   3. project every job one level finer; a job whose finest level was

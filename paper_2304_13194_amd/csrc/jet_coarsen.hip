@@ -1039,6 +1039,159 @@ int hierarchy_build(jet_context *ctx, const jet_csr *g, const jet_params *prm, j
     return build_hierarchy(ctx, g, prm, h, s);
 }
 
+// ------------------------------------------------- graph-growing start --
+// Coarsest-graph start (not the paper's, which takes Metis): vertices ordered
+// by (smallest vertex id of their component, BFS distance from it, own id),
+// the order cut into k runs of equal vertex weight. Each vertex's key
+// (root << 32 | distance) starts at (v, 0) and is lowered to the smallest of
+// its neighbours' keys plus one hop until a pass changes nothing; the only
+// fixpoint of that rule is (component minimum, distance from it), so the
+// order of the relaxation does not matter. A stable radix sort of the keys
+// (values: vertex ids in id order) gives the order, a scan of the weights the
+// runs.
+
+__global__ __launch_bounds__(CB) void k_bfs_init(int n, uint64_t *key, int32_t *val)
+{
+    for (int v = blockIdx.x * CB + threadIdx.x; v < n; v += gridDim.x * CB) {
+        key[v] = (uint64_t)(uint32_t)v << 32;
+        val[v] = v;
+    }
+}
+
+// One relaxation pass over the CSR entries in runs of 16 per thread (hub rows
+// are spread over many threads): a run keeps the smallest neighbour key + 1
+// of its current row and lowers the row's key with a 64-bit atomic minimum.
+__device__ __forceinline__ void bfs_lower(uint64_t *key, int v, uint64_t m, bool &ch)
+{
+    if (m < key[v] && m < atomicMin((unsigned long long *)&key[v], (unsigned long long)m)) ch = true;
+}
+
+__global__ __launch_bounds__(CB) void k_bfs_relax(int n, int64_t nnz, const int64_t *xadj, const int32_t *adj,
+                                                  uint64_t *key, int32_t *changed)
+{
+    constexpr int RUN = 16;
+    bool ch = false;
+    const int64_t nruns = (nnz + RUN - 1) / RUN;
+    for (int64_t r = (int64_t)blockIdx.x * CB + threadIdx.x; r < nruns; r += (int64_t)gridDim.x * CB) {
+        const int64_t e0 = r * RUN, e1 = e0 + RUN < nnz ? e0 + RUN : nnz;
+        int lo = 0, hi = n;  // the row holding e0: largest v with xadj[v] <= e0
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (xadj[mid] <= e0) lo = mid;
+            else hi = mid;
+        }
+        int v = lo;
+        int64_t vend = xadj[v + 1];
+        uint64_t m = ~0ull;
+        for (int64_t e = e0; e < e1; e++) {
+            while (e >= vend) {  // next non-empty row (e < nnz = xadj[n] keeps v < n)
+                bfs_lower(key, v, m, ch);
+                v++;
+                vend = xadj[v + 1];
+                m = ~0ull;
+            }
+            const uint64_t c = key[adj[e]] + 1;  // same root, one hop further
+            m = c < m ? c : m;
+        }
+        bfs_lower(key, v, m, ch);
+    }
+    if (ch) changed[0] = 1;
+}
+
+__global__ __launch_bounds__(CB) void k_bfs_weights(int n, const int32_t *vw, const int32_t *order, int64_t *w)
+{
+    for (int i = blockIdx.x * CB + threadIdx.x; i < n; i += gridDim.x * CB) w[i] = vw ? vw[order[i]] : 1;
+}
+
+// a * b <= c * d for unsigned 64-bit operands (128-bit products)
+__device__ __forceinline__ bool mul_le(uint64_t a, uint64_t b, uint64_t c, uint64_t d)
+{
+    const uint64_t h1 = __umul64hi(a, b), h2 = __umul64hi(c, d);
+    return h1 < h2 || (h1 == h2 && a * b <= c * d);
+}
+
+// The vertex at position i, with weight b before it, goes to the largest part
+// p with p W <= b k, i.e. floor(b k / W) (W = 0: part 0).
+__global__ __launch_bounds__(CB) void k_bfs_assign(int n, int k, const int32_t *order, const int64_t *w,
+                                                   const int64_t *incl, int32_t *part)
+{
+    const uint64_t W = (uint64_t)incl[n - 1];
+    for (int i = blockIdx.x * CB + threadIdx.x; i < n; i += gridDim.x * CB) {
+        const uint64_t b = (uint64_t)(incl[i] - w[i]);
+        int lo = 0, hi = W ? k - 1 : 0;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (mul_le((uint64_t)mid, W, b, (uint64_t)k)) lo = mid;
+            else hi = mid - 1;
+        }
+        part[order[i]] = lo;
+    }
+}
+
+int bfs_start(jet_context *ctx, const jet_csr *g, int k, int32_t *part, hipStream_t s)
+{
+    const int n = g->n;
+    if (n == 0) return JET_OK;
+    const size_t nn = (size_t)n;
+    uint64_t *key = (uint64_t *)ws_get(ctx, WS_TH_KEY, nn * 16);
+    int32_t *val = (int32_t *)ws_get(ctx, WS_TH_VAL, nn * 8);
+    int64_t *w = (int64_t *)ws_get(ctx, WS_TH_RUN, nn * 16 + 64);
+    if (!key || !val || !w) return JET_ENOMEM;
+    uint64_t *key2 = key + nn;
+    int32_t *val2 = val + nn;
+    int64_t *incl = w + nn;
+    int32_t *changed = (int32_t *)(incl + nn);
+    size_t sort_bytes = 0, scan_bytes = 0;
+    JET_TRY(rocprim::radix_sort_pairs(nullptr, sort_bytes, key, key2, val, val2, nn, 0, 64, s));
+    JET_TRY(rocprim::inclusive_scan(nullptr, scan_bytes, w, incl, nn, rocprim::plus<int64_t>(), s));
+    void *tmp = ws_get(ctx, WS_TH_TMP, std::max(sort_bytes, scan_bytes) + 256);
+    if (!tmp) return JET_ENOMEM;
+    int32_t *hch = (int32_t *)((char *)ctx->pinned + 2560);
+    const int gv = grid_for(ctx, n, CB, 4);
+    const int ge = grid_for(ctx, (g->nnz + 15) / 16, CB);
+    k_bfs_init<<<gv, CB, 0, s>>>(n, key, val);
+    // every pass lowers at least one key until the fixpoint, and no key can
+    // fall more than n - 1 times (its distance only shrinks, then its root):
+    // chunks of 4 passes, one look each, at most n / 4 + 1 chunks
+    constexpr int CHUNK = 4;
+    bool done = false;
+    for (int64_t c = 0; c <= nn / CHUNK + 1 && !done; c++) {
+        JET_TRY(hipMemsetAsync(changed, 0, 4, s));
+        if (g->nnz > 0)
+            for (int i = 0; i < CHUNK; i++) k_bfs_relax<<<ge, CB, 0, s>>>(n, g->nnz, g->xadj, g->adjncy, key, changed);
+        JET_TRY(hipMemcpyAsync(hch, changed, 4, hipMemcpyDeviceToHost, s));
+        JET_TRY(stream_wait(ctx, s));
+        done = *hch == 0;
+    }
+    if (!done) return JET_EHIP;  // unreachable: the relaxation converges within n passes
+    size_t b = sort_bytes;
+    JET_TRY(rocprim::radix_sort_pairs(tmp, b, key, key2, val, val2, nn, 0, 64, s));
+    k_bfs_weights<<<gv, CB, 0, s>>>(n, g->vwgt, val2, w);
+    b = scan_bytes;
+    JET_TRY(rocprim::inclusive_scan(tmp, b, w, incl, nn, rocprim::plus<int64_t>(), s));
+    k_bfs_assign<<<gv, CB, 0, s>>>(n, k, val2, w, incl, part);
+    return hip_status(ctx, hipGetLastError());
+}
+
+// The start of the coarsest level: graph-growing with JET_F_BFS_START, else
+// the seeded uniform random partition.
+int coarsest_start(jet_context *ctx, const jet_csr *g, const jet_params *p, int32_t *part, hipStream_t s)
+{
+    if (p->flags & JET_F_BFS_START) return bfs_start(ctx, g, p->k, part, s);
+    return random_partition(ctx, g->n, p->k, p->seed, part, s);
+}
+
+extern "C" int jet_bfs_start(jet_context *ctx, const jet_csr *g, int32_t k, int32_t *part, void *stream)
+{
+    if (!ctx || !g || (!part && g->n > 0) || k < 1) return JET_EINVAL;
+    if (k > KMAX) return JET_ELIMIT;
+    hipStream_t s = (hipStream_t)stream;
+    JET_TRY(hipSetDevice(ctx->device));
+    const int st = check_graph(ctx, g, 0, s);
+    if (st) return st;
+    return bfs_start(ctx, g, k, part, s);
+}
+
 void hierarchy_release(jet_hierarchy *h) { hier_release(h); }
 
 int random_partition(jet_context *ctx, int n, int k, uint64_t seed, int32_t *part, hipStream_t s)
@@ -1123,15 +1276,16 @@ extern "C" int jet_partition(jet_context *ctx, const jet_csr *g, const jet_param
     jet_stats agg;
     memset(&agg, 0, sizeof(agg));
     if (st == JET_OK && g->n > 0) {
-        // seeded random partition of the coarsest graph, then refine upward
+        // start of the coarsest graph (seeded random or graph-growing), then refine upward
         const int l = levels - 1;
         const int nmax = g->n;
         int32_t *pa = (int32_t *)ws_get(ctx, WS_C10, (size_t)nmax * 4);
         int32_t *pb = (int32_t *)ws_get(ctx, WS_C11, (size_t)nmax * 4);
         if (!pa || !pb) st = JET_ENOMEM;
         if (st == JET_OK) {
-            k_random_part<<<grid_for(ctx, h.lv[l].n, CB, 4), CB, 0, s>>>(h.lv[l].n, params->k,
-                                                                         mix64(params->seed ^ 1ULL), pa);
+            st = coarsest_start(ctx, &h.lv[l], params, pa, s);
+        }
+        if (st == JET_OK) {
             int32_t *cur = pa, *other = pb;
             for (int i = l; i >= 0 && st == JET_OK; i--) {
                 if (i < l) {

@@ -203,6 +203,8 @@ int check_graph(jet_context *ctx, const jet_csr *g, uint32_t flags, hipStream_t 
 int hierarchy_build(jet_context *ctx, const jet_csr *g, const jet_params *prm, jet_hierarchy *h, hipStream_t s);
 void hierarchy_release(jet_hierarchy *h);
 int random_partition(jet_context *ctx, int n, int k, uint64_t seed, int32_t *part, hipStream_t s);
+int bfs_start(jet_context *ctx, const jet_csr *g, int k, int32_t *part, hipStream_t s);
+int coarsest_start(jet_context *ctx, const jet_csr *g, const jet_params *p, int32_t *part, hipStream_t s);
 int project_partition(jet_context *ctx, int n, const int32_t *map, const int32_t *coarse, int32_t *fine, hipStream_t s);
 
 }  // namespace jet

@@ -4,7 +4,7 @@
 //
 // A worker thread owns the context and its own stream. Each step admits
 // queued jobs (slots and HBM footprint permitting; an admitted job is
-// checked, coarsened, and given its seeded coarsest partition, and its
+// checked, coarsened, and given its coarsest start (seeded random or graph-growing), and its
 // hierarchy stays in device memory), refines the current level of every
 // active job in one batched launch sequence, then projects each job one
 // level finer or retires it. Because a batch refines each graph exactly as
@@ -127,7 +127,7 @@ static int start_job(jet_server *sv, SJob *j)
         // the coarsest level uses the half the next-finer level will not write to
         j->cur = (l % 2 == 1) ? j->buf : j->buf + n1;
     }
-    st = random_partition(ctx, j->h.lv[l].n, p.k, p.seed, j->cur, s);
+    st = coarsest_start(ctx, &j->h.lv[l], &p, j->cur, s);
     if (st) return st;
     j->res.levels = L;
     return JET_OK;

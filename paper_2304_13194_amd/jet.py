@@ -29,6 +29,7 @@ JET_F_PROFILE = 0x4
 JET_F_LP_NO_LOCKS = 0x8
 JET_F_LP_NO_AFTERBURNER = 0x10
 JET_F_TWO_HOP = 0x20
+JET_F_BFS_START = 0x40
 KIND_LP, KIND_RW, KIND_RS = 1, 2, 3
 
 # Every function declared in include/jet.h.
@@ -36,7 +37,7 @@ EXPORTS = [
     "jet_context_create", "jet_context_destroy", "jet_strerror", "jet_last_hip_error",
     "jet_refine", "jet_refine_batch", "jet_lp_step", "jet_rebalance_step", "jet_coarsen",
     "jet_hierarchy_levels", "jet_hierarchy_level", "jet_hierarchy_free", "jet_partition",
-    "jet_server_create", "jet_server_submit", "jet_server_poll", "jet_server_wait",
+    "jet_bfs_start", "jet_server_create", "jet_server_submit", "jet_server_poll", "jet_server_wait",
     "jet_server_info_get", "jet_server_destroy",
 ]
 
@@ -347,6 +348,17 @@ def partition(g: DeviceGraph, k: int, trace_cap=0, ctx=None, **kw):
     if tr is not None:
         out["trace_total"] = tr.total
     return part, out, _trace_list(arr, tr)
+
+
+def bfs_start(g: DeviceGraph, k: int, ctx=None):
+    """jet_bfs_start: graph-growing partition (components grown breadth-first
+    from their smallest id, cut into k runs of equal vertex weight)."""
+    ctx = ctx or default_context()
+    part = torch.empty(g.n, dtype=torch.int32, device=g.xadj.device)
+    csr = g.csr()
+    s = lib().jet_bfs_start(ctx.h, C.byref(csr), C.c_int32(k), _ptr(part), _stream())
+    _check(s, "jet_bfs_start")
+    return part
 
 
 class Hierarchy:
