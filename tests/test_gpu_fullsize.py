@@ -7,7 +7,8 @@
   cut, largest part weight, best cut, partition digest), the final partition
   element by element, cut and balance. The same call without the profiling
   flag, where every level replays its iteration pairs as HIP graphs, gives
-  the same partition.
+  the same partition. The partition from the graph-growing start of the
+  coarsest graph (JET_F_BFS_START) matches the oracle's the same way.
 * The 512-RGG batch (sum n = 18.0M, sum 2m = 180M): one jet_refine_batch
   call as timed. Sampled graphs match the oracle's refinement of each graph
   alone; for every graph the part ids lie in [0, k), and the cut and the
@@ -91,6 +92,23 @@ def test_stencil128_partition_matches_oracle(J, O):
     assert st2["cut"] == st["cut"] and st2["iters"] == st["iters"]
     cut, pw = _recount(g, part, k)
     assert cut == st["cut"] and int(pw.max()) == st["max_part_weight"] and int(pw.sum()) == g.n
+
+
+def test_stencil128_partition_from_bfs_start_matches_oracle(J, O):
+    """The same partition started from the graph-growing partition of the
+    coarsest graph (JET_F_BFS_START): every trace record and the result."""
+    g = I.stencil27(128, 128, 128)
+    k, seed = 64, 2
+    dg = J.to_device(g, unit_vwgt=True, unit_adjwgt=True)
+    part, st, tr = J.partition(dg, k, seed=seed, flags=J.JET_F_BFS_START, trace_cap=1 << 16)
+    part = part.cpu().numpy()
+    _say(f"gpu (graph-growing start): cut={st['cut']} iters={st['iters']}; oracle running")
+    exp = O.partition(g, k, seed=seed, flags=O.F_BFS_START, trace_cap=1 << 20)
+    assert len(tr) == len(exp["trace"])
+    for a, b in zip(tr, exp["trace"]):
+        assert a == b, f"gpu {a} != oracle {b}"
+    np.testing.assert_array_equal(part, exp["part"])
+    assert st["cut"] == exp["cut"] and bool(st["balanced"]) == exp["balanced"]
 
 
 def test_rgg512_batch_full_size(J, O):
