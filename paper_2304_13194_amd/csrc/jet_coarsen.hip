@@ -1150,9 +1150,10 @@ int bfs_start(jet_context *ctx, const jet_csr *g, int k, int32_t *part, hipStrea
     const int gv = grid_for(ctx, n, CB, 4);
     const int ge = grid_for(ctx, (g->nnz + 15) / 16, CB);
     k_bfs_init<<<gv, CB, 0, s>>>(n, key, val);
-    // every pass lowers at least one key until the fixpoint, and no key can
-    // fall more than n - 1 times (its distance only shrinks, then its root):
-    // chunks of 4 passes, one look each, at most n / 4 + 1 chunks
+    // after p passes every vertex within p hops of its component's smallest
+    // id (along a shortest path) holds its final key, and BFS distances are
+    // below n: at most n passes change anything. Chunks of 4 passes, one look
+    // each; n / 4 + 2 chunks cover n passes and the pass that finds no change.
     constexpr int CHUNK = 4;
     bool done = false;
     for (int64_t c = 0; c <= nn / CHUNK + 1 && !done; c++) {
@@ -1163,7 +1164,7 @@ int bfs_start(jet_context *ctx, const jet_csr *g, int k, int32_t *part, hipStrea
         JET_TRY(stream_wait(ctx, s));
         done = *hch == 0;
     }
-    if (!done) return JET_EHIP;  // unreachable: the relaxation converges within n passes
+    if (!done) return JET_EGRAPH;  // not reached for any CSR: the bound above holds for every adjacency
     size_t b = sort_bytes;
     JET_TRY(rocprim::radix_sort_pairs(tmp, b, key, key2, val, val2, nn, 0, 64, s));
     k_bfs_weights<<<gv, CB, 0, s>>>(n, g->vwgt, val2, w);
