@@ -401,7 +401,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_rows<4, 8, true, 1> in Jetlp iterations (connectivity/gain pass of the small rows, finest level)",
+            "kernel": "k_gain<false, 1, 4, 8, 1> in Jetlp iterations (connectivity/gain pass of the small rows, finest level)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

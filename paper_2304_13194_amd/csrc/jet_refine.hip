@@ -834,6 +834,35 @@ __device__ __forceinline__ void group_conn_row(const KArgs &a, int64_t s, int de
     lds_fence_wave();
 }
 
+// The two halves of group_conn_row for rows of unit edge weights, so that a
+// group can have two rows' loads in flight: conn_load gathers a row's
+// neighbour parts (slot r of lane gl is entry gl + r * G; -1 beyond the row),
+// conn_claim adds them into `tab` and reads every adjacent part's total back
+// exactly once (cu as in group_conn_row).
+template <int G, int R>
+__device__ __forceinline__ void conn_load(const KArgs &a, int64_t s, int deg, int gl, int (&pu)[R])
+{
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int idx = gl + r * G;
+        pu[r] = idx < deg ? a.adj[s + idx] : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) pu[r] = pu[r] >= 0 ? a.P[pu[r]] : -1;
+}
+
+template <int R>
+__device__ __forceinline__ void conn_claim(int32_t *tab, const int (&pu)[R], int (&cu)[R])
+{
+#pragma unroll
+    for (int r = 0; r < R; r++)
+        if (pu[r] >= 0) atomicAdd(&tab[pu[r]], 1);
+    lds_fence_wave();
+#pragma unroll
+    for (int r = 0; r < R; r++) cu[r] = pu[r] >= 0 ? atomicExch(&tab[pu[r]], 0) : 0;
+    lds_fence_wave();
+}
+
 // Wave-batched driver of the small-row role. Lanes first inspect 64 list
 // entries at once (coalesced loads of the id, row offsets and per-vertex
 // state); the entries that need row work are queued in LDS and handed to the
@@ -874,6 +903,52 @@ __device__ __forceinline__ void wave_batched(const int32_t *list, Walk w, int32_
             t.g = __shfl(m.g, src, 64);
             t.s = __shfl(m.s, src, 64);
             if (has) row(t, gl);
+        }
+        lds_fence_wave();
+    }
+}
+
+// wave_batched with two queued rows per group and round: the row callback
+// gets both, each with a flag saying whether it exists, and can issue the
+// loads of both before the LDS work of either. Every lane takes part in the
+// shuffles (a shuffle under a divergent mask could read an inactive lane).
+template <int G, class Pre, class Row2>
+__device__ __forceinline__ void wave_batched2(const int32_t *list, Walk w, int32_t *q, Pre pre, Row2 row2)
+{
+    constexpr int NG = 64 / G;
+    const int lane = threadIdx.x & 63, grp = lane / G, gl = lane & (G - 1);
+    for (int base = w.first; base < w.end; base += w.step) {
+        const int i = base + lane;
+        Meta m{0, 0, 0, 0, 0, 0};
+        bool act = false;
+        if (i < w.end) {
+            m.v = list ? list[i] : i;
+            act = pre(m);
+        }
+        const uint64_t mask = __ballot(act);
+        if (act) q[__popcll(mask & ((1ull << lane) - 1ull))] = lane;
+        lds_fence_wave();
+        const int nact = __popcll(mask);
+        for (int sb = 0; sb < nact; sb += 2 * NG) {
+            const int s0 = sb + grp, s1 = sb + NG + grp;
+            const bool h0 = s0 < nact, h1 = s1 < nact;
+            const int c0 = q[h0 ? s0 : 0], c1 = q[h1 ? s1 : 0];
+            Meta t0, t1;
+            t0.v = __shfl(m.v, c0, 64);
+            t0.ps = __shfl(m.ps, c0, 64);
+            t0.deg = __shfl(m.deg, c0, 64);
+            t0.aux = __shfl(m.aux, c0, 64);
+            t0.g = __shfl(m.g, c0, 64);
+            t0.s = __shfl(m.s, c0, 64);
+            t1.v = __shfl(m.v, c1, 64);
+            t1.ps = __shfl(m.ps, c1, 64);
+            t1.deg = __shfl(m.deg, c1, 64);
+            t1.aux = __shfl(m.aux, c1, 64);
+            t1.g = __shfl(m.g, c1, 64);
+            t1.s = __shfl(m.s, c1, 64);
+            if (!h0) t0.deg = 0;
+            if (!h1) t1.deg = 0;
+            row2(t0, h0, t1, h1, gl);
         }
         lds_fence_wave();
     }
@@ -1065,7 +1140,7 @@ __device__ void gain_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int 
 // groups, waves, blocks), so each keeps its own register budget; a.tmap says
 // which classes a role serves. Group tables are padded to k + 1 ints so the
 // tables of neighbouring groups start in different LDS banks.
-template <bool B, int ROLE, int GS, int RS, int CL>
+template <bool B, int ROLE, int GS, int RS, int CL, bool PAIR = false>
 __device__ __forceinline__ void gain_body(const KArgs &a, int nblk)
 {
     extern __shared__ int32_t lds[];
@@ -1093,10 +1168,9 @@ __device__ __forceinline__ void gain_body(const KArgs &a, int nblk)
             int32_t *tab = lds + (threadIdx.x / G) * stride;
             if (!B && CL != NCLS) bid = xcd_block(bid, nb);
             const int wid = bid * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nb * (BLOCK / 64);
-            wave_batched<G>(
-                (!B && cl == CLS_S && a.sident) ? nullptr : a.bins + a.binoff[cl],
-                walk<B>(a.binoff[cl + 1] - a.binoff[cl], wid, nwaves, 64), q,
-                [&](Meta &m) -> bool {
+            const int32_t *list = (!B && cl == CLS_S && a.sident) ? nullptr : a.bins + a.binoff[cl];
+            const Walk wk = walk<B>(a.binoff[cl + 1] - a.binoff[cl], wid, nwaves, 64);
+            auto pre = [&](Meta &m) -> bool {
                     m.g = gof<B>(a, m.v);
                     pv.sel<B>(a, m.g);
                     if (pv.kind != KIND_LP) return false;
@@ -1115,8 +1189,8 @@ __device__ __forceinline__ void gain_body(const KArgs &a, int nblk)
                     pacc.c1++;
                     pacc.c2 += m.deg;
                     return true;
-                },
-                [&](const Meta &t, int gl) {
+                };
+            auto row = [&](const Meta &t, int gl) {
                     int pu[R], cu[R];
                     group_conn_row<G, R>(a, t.s, t.deg, gl, tab, pu, cu);
                     uint64_t best = 0;
@@ -1138,7 +1212,42 @@ __device__ __forceinline__ void gain_body(const KArgs &a, int nblk)
                         racc.sel<B>(a, t.g);
                         racc.c0 += gain_finish(a, t.v, t.ps, best, cs, rv.cn, rv.cd);
                     }
-                });
+                };
+            if (PAIR && cl == CLS_S && !a.ew) {
+                // two rows per group and round, both rows' parts in flight at once
+                auto row2 = [&](const Meta &t0, bool h0, const Meta &t1, bool h1, int gl) {
+                    int p0[R], p1[R], cu[R];
+                    conn_load<G, R>(a, t0.s, t0.deg, gl, p0);
+                    conn_load<G, R>(a, t1.s, t1.deg, gl, p1);
+                    auto finish = [&](const Meta &t, const int (&pu)[R]) {
+                        conn_claim<R>(tab, pu, cu);
+                        uint64_t best = 0;
+                        int cs = 0;
+#pragma unroll
+                        for (int r = 0; r < R; r++) {
+                            if (cu[r] > 0) {
+                                if (pu[r] == t.ps) cs += cu[r];
+                                else {
+                                    const uint64_t k2 = conn_key(cu[r], pu[r]);
+                                    best = k2 > best ? k2 : best;
+                                }
+                            }
+                        }
+                        best = gmax_u64<G>(best);
+                        cs = gsum<G>(cs);
+                        if (gl == 0) {
+                            rv.sel<B>(a, t.g);
+                            racc.sel<B>(a, t.g);
+                            racc.c0 += gain_finish(a, t.v, t.ps, best, cs, rv.cn, rv.cd);
+                        }
+                    };
+                    if (h0) finish(t0, p0);
+                    if (h1) finish(t1, p1);
+                };
+                wave_batched2<G>(list, wk, q, pre, row2);
+            } else {
+                wave_batched<G>(list, wk, q, pre, row);
+            }
         };
         if (CL != NCLS) body(std::integral_constant<int, GS>{}, std::integral_constant<int, RS>{}, CL, blockIdx.x, nblk);
         else if ((int)blockIdx.x < a.gS)
@@ -1168,7 +1277,9 @@ template <bool B, int ROLE, int GS = 8, int RS = 32 / GS, int CL = CLS_S>
 __global__ __launch_bounds__(BLOCK) void k_gain(KArgs a, int nblk)
 {
     if (!any_kind(a, KIND_LP)) return;
-    gain_body<B, ROLE, GS, RS, CL>(a, nblk);
+    // one graph's small class alone (the finest levels of a mesh): its own
+    // launch, so the paired rows get their register budget
+    gain_body<B, ROLE, GS, RS, CL, !B && ROLE == 1 && CL == CLS_S>(a, nblk);
 }
 
 // -------------------------------------------------------------- afterburner --
@@ -2679,6 +2790,7 @@ struct Plan {
     bool hist_fused;  // the loss kernels build the histogram (one graph, LDS room)
     bool cut_fused;   // the tile-sum blocks find the cut-off slots (one graph)
     bool loss_cache;  // the small-row loss kernel keeps per-part bounds in LDS (one graph)
+    bool split_rows;  // one large graph, small class only: gain and loss in launches of their own
     int grid_lfin, nL;
     int grid_v;              // grid of the list-building kernels
     int32_t *blkcnt, *lcnt;  // their scratch
@@ -2748,6 +2860,10 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
         pl.loss_cache = a.vg == nullptr && k <= 1024 && per <= 65536 &&
                         (size_t)div_up(t.gS + t.gS2, ctx->num_cu) * per <= LDS_PER_CU;
     }
+    // A large graph whose rows are all in the small class (a mesh's finest
+    // levels): the gain pass is long enough that its own launch, with two
+    // rows in flight per group, pays for the extra launch per iteration.
+    pl.split_rows = a.vg == nullptr && t.gS && !t.gS2 && a.n >= (1 << 18);
     pl.grid_hist = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_flat = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_tile = std::max(1, std::min(a.ntile, ctx->num_cu * 8));
@@ -2882,13 +2998,14 @@ static void launch_iteration_t(const Plan &pl, hipStream_t s, hipEvent_t ev_a, h
 {
     const KArgs &p = pl.plain;
     if (ev_a) (void)hipEventRecord(ev_a, s);
-    if (!B) {
+    const bool split = !B && pl.split_rows;
+    if (!B && !split) {
         if (pl.loss_cache) launch_rows_t<true>(pl, s);
         else launch_rows_t<false>(pl, s);
     }
-    launch_gain_t<B>(pl, s, B);
+    launch_gain_t<B>(pl, s, B || split);
     if (ev_b) (void)hipEventRecord(ev_b, s);
-    launch_rb_loss_t<B>(pl, s, B);
+    launch_rb_loss_t<B>(pl, s, B || split);
     launch_rb_cutoff_t<B>(pl, s);
     launch_after_t<B>(pl, s);
     launch_rb_select_t<B>(pl, s);
