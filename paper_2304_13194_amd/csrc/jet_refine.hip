@@ -2033,7 +2033,7 @@ __device__ void rb_blocks(const KArgs &a, int cls, int32_t *tab, int bid, int nb
 // 3 (k w(p) - W) (-1 outside A) and the B flags are copied to LDS first, so
 // a vertex's candidate test and its neighbours' B tests read LDS instead of
 // waiting on dependent global loads.
-template <bool B, int ROLE, int GS, int RS, bool PC, int CL>
+template <bool B, int ROLE, int GS, int RS, bool PC, int CL, bool PAIR = false>
 __device__ __forceinline__ void loss_body(const KArgs &a, int nblk, int hmode)
 {
     constexpr bool pcache = PC && !B && ROLE == 1;
@@ -2072,10 +2072,9 @@ __device__ __forceinline__ void loss_body(const KArgs &a, int nblk, int hmode)
             if (a.tmap[cl] != ROLE) return;
             int32_t *tab = lds + (threadIdx.x / G) * stride;
             const int wid = bid * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nb * (BLOCK / 64);
-            wave_batched<G>(
-                (!B && cl == CLS_S && a.sident) ? nullptr : a.bins + a.binoff[cl],
-                walk<B>(a.binoff[cl + 1] - a.binoff[cl], wid, nwaves, 64), q,
-                [&](Meta &m) -> bool {
+            const int32_t *list = (!B && cl == CLS_S && a.sident) ? nullptr : a.bins + a.binoff[cl];
+            const Walk wk = walk<B>(a.binoff[cl + 1] - a.binoff[cl], wid, nwaves, 64);
+            auto pre = [&](Meta &m) -> bool {
                     m.g = gof<B>(a, m.v);
                     pv.sel<B>(a, m.g);
                     if (!is_rb(pv.kind)) return false;
@@ -2095,8 +2094,8 @@ __device__ __forceinline__ void loss_body(const KArgs &a, int nblk, int hmode)
                     m.s = a.xadj[m.v];
                     m.deg = (int)(a.xadj[m.v + 1] - m.s);
                     return true;
-                },
-                [&](const Meta &t, int gl) {
+                };
+            auto row = [&](const Meta &t, int gl) {
                     rv.sel<B>(a, t.g);
                     int pu[R], cu[R];
                     group_conn_row<G, R>(a, t.s, t.deg, gl, tab, pu, cu);
@@ -2123,7 +2122,47 @@ __device__ __forceinline__ void loss_body(const KArgs &a, int nblk, int hmode)
                         racc.sel<B>(a, t.g);
                         racc.c0++;
                     }
-                });
+                };
+            if (PAIR && cl == CLS_S && !a.ew) {
+                // two candidate rows per group and round, both rows' parts in flight at once
+                auto row2 = [&](const Meta &t0, bool h0, const Meta &t1, bool h1, int gl) {
+                    int p0[R], p1[R], cu[R];
+                    conn_load<G, R>(a, t0.s, t0.deg, gl, p0);
+                    conn_load<G, R>(a, t1.s, t1.deg, gl, p1);
+                    auto finish = [&](const Meta &t, const int (&pu)[R]) {
+                        rv.sel<B>(a, t.g);
+                        conn_claim<R>(tab, pu, cu);
+                        uint64_t best = 0;
+                        int cs = 0, sumB = 0, cntB = 0;
+#pragma unroll
+                        for (int r = 0; r < R; r++) {
+                            if (cu[r] > 0) {
+                                if (pu[r] == t.ps) cs += cu[r];
+                                else if (pcache ? cB[pu[r]] : a.isB[rv.poff + pu[r]]) {
+                                    const uint64_t k2 = conn_key(cu[r], pu[r]);
+                                    best = k2 > best ? k2 : best;
+                                    sumB += cu[r];
+                                    cntB++;
+                                }
+                            }
+                        }
+                        best = gmax_u64<G>(best);
+                        cs = gsum<G>(cs);
+                        sumB = gsum<G>(sumB);
+                        cntB = gsum<G>(cntB);
+                        if (gl == 0) {
+                            rb_finish(a, t.v, t.ps, rv, best, cs, sumB, cntB, t.aux, hmode, lh);
+                            racc.sel<B>(a, t.g);
+                            racc.c0++;
+                        }
+                    };
+                    if (h0) finish(t0, p0);
+                    if (h1) finish(t1, p1);
+                };
+                wave_batched2<G>(list, wk, q, pre, row2);
+            } else {
+                wave_batched<G>(list, wk, q, pre, row);
+            }
         };
         if (CL != NCLS) body(std::integral_constant<int, GS>{}, std::integral_constant<int, RS>{}, CL, blockIdx.x, nblk);
         else if ((int)blockIdx.x < a.gS)
@@ -2172,11 +2211,12 @@ __device__ __forceinline__ void loss_body(const KArgs &a, int nblk, int hmode)
 }
 
 template <bool B, int ROLE, int GS = 8, int RS = 32 / GS, bool PC = false, int CL = CLS_S>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ROLE == 1 && !B ? 8 : 1)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ROLE == 1 && !B ? (CL == CLS_S ? 6 : 8) : 1)))
 void k_rb_loss(KArgs a, int nblk, int hmode)
 {
     if (!any_rb(a)) return;
-    loss_body<B, ROLE, GS, RS, PC, CL>(a, nblk, hmode);
+    // one graph's small class alone (its own launch): two rows in flight per group
+    loss_body<B, ROLE, GS, RS, PC, CL, !B && ROLE == 1 && CL == CLS_S>(a, nblk, hmode);
 }
 
 // One launch for the small-row gain and loss passes of one graph: each
