@@ -50,8 +50,8 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE runs (each calibrated by a plain 2^28-byte copy), valid only for
 # the kernel source they were taken on (profiles/k_gain_stencil128_k64.md).
 TRAFFIC = {
-    "stencil128": dict(src_sha256="6192afb6c16e30c79868f39249058ba2561abb17a3c0bf61fabd7e50f4b40e13",
-                       fetch=249195231, write=17432442, fetch_factor=1.9997, write_factor=1.0),
+    "stencil128": dict(src_sha256="033629e58bb3ac3b35fbce81e7ab0b8ab8de40d2e94523d1bab68f49dcbc511b",
+                       fetch=249198497, write=17431882, fetch_factor=1.9997, write_factor=1.0),
 }
 
 
