@@ -298,3 +298,39 @@ def test_lp_step_no_afterburner_parity(J, O, case):
             np.testing.assert_array_equal(got[key].cpu().numpy(), exp[key], err_msg=f"{name} {key}")
         np.testing.assert_array_equal(got["move"].cpu().numpy().astype(bool), exp["move"], err_msg=name)
 
+
+
+@pytest.mark.parametrize("weights", ["null", "explicit_unit", "random"])
+def test_refine_large_mesh_split_launch(J, O, weights):
+    """A graph of 2^18 vertices whose rows all have at most 32 entries: the
+    gain and loss passes run in launches of their own, with two rows in
+    flight per lane group when edge weights are NULL (unit) and one row per
+    round otherwise. Start: z-slabs with the last part three slabs wide and
+    2% of the vertices reassigned at random (Jetlp, Jetrw and Jetrs all run);
+    k = 16, against the oracle."""
+    import torch
+    g = I.stencil27(64, 64, 64)
+    if weights == "random":
+        # symmetric weights 1..7 from a hash of the two endpoints
+        src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.xadj))
+        lo = np.minimum(src, g.adjncy).astype(np.uint64)
+        hi = np.maximum(src, g.adjncy).astype(np.uint64)
+        h = (lo * np.uint64(2654435761) + hi * np.uint64(40503)) % np.uint64(7)
+        g = I.Graph(g.xadj, g.adjncy, g.vwgt, (1 + h).astype(np.int32), "stencil64_weighted")
+    k = 16
+    rng = np.random.default_rng(3)
+    P0 = np.minimum((np.arange(g.n) * (k + 2)) // g.n, k - 1).astype(np.int32)
+    idx = rng.choice(g.n, g.n // 50, replace=False)
+    P0[idx] = rng.integers(0, k, idx.size)
+    exp = O.refine(g, P0, k, seed=5)
+    assert {t["kind"] for t in exp.trace} == {1, 2, 3}
+    unit = weights == "null"
+    dg = J.to_device(g, unit_vwgt=unit, unit_adjwgt=unit)
+    part = torch.from_numpy(P0.copy()).cuda()
+    st, tr, _ = J.refine(dg, part, k, trace_cap=10000, seed=5)
+    assert st["iters"] == exp.iters
+    assert len(tr) == len(exp.trace)
+    for a, b in zip(tr, exp.trace):
+        assert a == b, f"{weights}: gpu {a} != oracle {b}"
+    np.testing.assert_array_equal(part.cpu().numpy(), exp.part)
+    assert st["cut"] == exp.cut and st["max_part_weight"] == exp.maxw
