@@ -233,7 +233,7 @@ def serve_bench(J, pool, jobs, rates=(50, 200, 1000, 2000)):
 
 
 def ablation_bench(J, dg, k, seed, label):
-    """Jetlp ablations and the phi sweep (Section 5, Table lp_versions) on one
+    """Jetlp ablations and the phi sweep (Section 7.1, Component Effectiveness, Table lp_versions) on one
     graph: cut and time of the full multilevel partition per variant."""
     import torch
     NL, NA = J.JET_F_LP_NO_LOCKS, J.JET_F_LP_NO_AFTERBURNER

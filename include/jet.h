@@ -55,7 +55,7 @@ extern "C" {
 #define JET_F_VALIDATE    0x1u  /* full CSR check: range, self-loops, symmetry, duplicates */
 #define JET_F_RETURN_ITER 0x2u  /* return P_iter (state after the last iteration) instead of P_best */
 #define JET_F_PROFILE     0x4u  /* time the connectivity/gain passes (see jet_stats.ms_gain) */
-/* Jetlp ablations (Section 5, component effectiveness, Table lp_versions):
+/* Jetlp ablations (Section 7.1, Component Effectiveness, Table lp_versions):
  * without locks, a vertex moved by one Jetlp may move again in the next;
  * without the afterburner, every vertex of X moves (F2 is reported as 0).
  * The paper's "weak afterburner" admits only moves with F >= 0: set

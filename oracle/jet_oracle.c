@@ -48,7 +48,7 @@ typedef struct {
     uint64_t seed;
 } og_params;
 
-/* Jetlp ablations of Section 5 (component effectiveness, Table lp_versions).
+/* Jetlp ablations of Section 7.1 (Component Effectiveness, Table lp_versions).
  * Reading: "ignores the lock bit" = R stays empty; "omits the afterburner"
  * = every vertex of X moves (F2 is left 0). The weak afterburner (moves with
  * F >= 0 only) is the first filter with c = 0. Bit values follow the public

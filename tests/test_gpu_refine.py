@@ -261,7 +261,7 @@ def test_refine_edge_cases(J, O):
     _compare_refine(J, O, gi, 4, P0, "isolated_only")
 
 
-# Jetlp ablations (Section 5, Table lp_versions): (name, c, flags)
+# Jetlp ablations (Section 7.1, Component Effectiveness, Table lp_versions): (name, c, flags)
 def _ablations(J):
     NL, NA = J.JET_F_LP_NO_LOCKS, J.JET_F_LP_NO_AFTERBURNER
     return [("baseline", (0, 1), NL | NA), ("locks", (0, 1), NA), ("weak_afterburner", (0, 1), NL),

@@ -52,6 +52,17 @@ MUTANTS = [
     ("start order ignores distance", "if (a->dist != b->dist) return a->dist < b->dist ? -1 : 1;\n", ""),
     ("start grows from largest id", "for (int32_t r = 0; r < n; r++) {\n        if (dist[r] >= 0) continue;",
      "for (int32_t r = n - 1; r >= 0; r--) {\n        if (dist[r] >= 0) continue;"),
+    ("matching proposes the lightest edge", "if (bu < 0 || wt > bw ||", "if (bu < 0 || wt < bw ||"),
+    ("matching ignores the round cap", "for (int32_t round = 0; round < 16; round++) {",
+     "for (int32_t round = 0; round < 64; round++) {"),
+    ("matching ignores the 1% rule", "if (newly == 0 || newly * 100 < (int64_t)n) break;", "if (newly == 0) break;"),
+    ("coarse ids numbered by the larger member", "if (match[v] < 0 || v < match[v]) map[v] = nc++;",
+     "if (match[v] < 0 || v > match[v]) map[v] = nc++;"),
+    ("contraction overwrites edge weights", "acc[cu] += g->adjwgt[e];", "acc[cu] = g->adjwgt[e];"),
+    ("projection ignores the map", "Pf[v] = P[maps[i][v]];", "Pf[v] = P[v % G[i + 1].n];"),
+    ("coarsening target 4k", "G[nl - 1].n > 8 * (int64_t)k", "G[nl - 1].n > 4 * (int64_t)k"),
+    ("coarsening drops the 90% rule", "if (10 * (int64_t)nc > 9 * (int64_t)f->n) break;", ""),
+    ("random start with the wrong stream", "og_mix64(prm->seed ^ 1ULL)", "og_mix64(prm->seed ^ 2ULL)"),
     ("start chunks by count", "        b += g->vwgt ? g->vwgt[v] : 1;\n    }\n    free(dist);",
      "        b += 1;\n    }\n    free(dist);"),
 ]
@@ -73,6 +84,10 @@ PIN_TESTS = [
     pins.test_stall_counter_follows_algorithm3,
     pins.test_exhaustive_optimum_bounds_result,
     pins.test_hem_is_a_matching_and_contraction_preserves_cut,
+    pins.test_hem_path_closed_forms,
+    pins.test_hem_distinct_weights_is_greedy_matching,
+    pins.test_multilevel_is_algorithm1_composition,
+    pins.test_partition_multilevel_sanity,
     pins.test_ablation_baseline_step_is_textbook_sync_lp,
     lambda O: pins.test_ablation_loop_iterates_textbook_lp(O, False),
     lambda O: pins.test_ablation_loop_iterates_textbook_lp(O, True),

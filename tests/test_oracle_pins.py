@@ -469,19 +469,152 @@ def test_hem_is_a_matching_and_contraction_preserves_cut(oracle_lib):
             assert brute_cut(gc, Pc) == brute_cut(g, Pc[cmap])
 
 
+def _distinct_weight_graph(n, p_edge, seed):
+    """A random graph whose edge weights are a seeded permutation of 1..m,
+    so that no two edges weigh the same."""
+    g = I.small_random_graph(n, p_edge, seed)
+    src = np.repeat(np.arange(g.n), np.diff(g.xadj))
+    keep = src < g.adjncy
+    u, v = src[keep], g.adjncy[keep].astype(np.int64)
+    order = np.argsort(I.stream(I.subseed(seed, 11), np.arange(u.shape[0], dtype=np.uint64)), kind="stable")
+    w = np.empty(u.shape[0], np.int32)
+    w[order] = np.arange(1, u.shape[0] + 1, dtype=np.int32)
+    return I.csr_from_edges(n, u, v, w)
+
+
+def _greedy_matching(g):
+    """Textbook greedy matching: undirected edges in decreasing weight, each
+    taken when both ends are still free."""
+    edges = []
+    for v in range(g.n):
+        for e in range(g.xadj[v], g.xadj[v + 1]):
+            u = int(g.adjncy[e])
+            if u > v:
+                edges.append((int(g.adjwgt[e]), v, u))
+    mate = [-1] * g.n
+    for _, a, b in sorted(edges, reverse=True):
+        if mate[a] < 0 and mate[b] < 0:
+            mate[a], mate[b] = b, a
+    return mate
+
+
+def _mates_from_map(cmap):
+    mate = [-1] * len(cmap)
+    for ms in _groups(cmap):
+        if len(ms) == 2:
+            mate[ms[0]], mate[ms[1]] = ms[1], ms[0]
+    return mate
+
+
+def test_hem_path_closed_forms(oracle_lib):
+    """Heavy-edge matching (Section 3.1) on paths whose matchings follow by
+    hand. Rounds of mutual proposals along the heaviest edge to an unmatched
+    neighbour, at most 16 rounds, a round matching < 1% of the vertices ends
+    them (reading R26); coarse ids are numbered by the smaller member."""
+    O = oracle_lib
+    # 0 -1- 1 -5- 2 -2- 3: only {1, 2} propose to each other; 0 and 3 then
+    # have no unmatched neighbour.
+    g = graph_from_edges(4, [(0, 1, 1), (1, 2, 5), (2, 3, 2)])
+    nc, cmap = O.hem_map(g, 0, 1)
+    assert nc == 3 and list(cmap) == [0, 1, 1, 2]
+    # weights falling away from the middle edge: {2,3} first, then {0,1} and
+    # {4,5} in the second round
+    g = graph_from_edges(6, [(0, 1, 3), (1, 2, 4), (2, 3, 9), (3, 4, 5), (4, 5, 2)])
+    nc, cmap = O.hem_map(g, 0, 1)
+    assert nc == 3 and list(cmap) == [0, 0, 1, 1, 2, 2]
+    # a path whose weights rise along it matches one pair per round from the
+    # heavy end: 34 vertices need 17 rounds, the cap of 16 leaves 0 and 1 single
+    n = 34
+    g = graph_from_edges(n, [(i, i + 1, i + 1) for i in range(n - 1)])
+    nc, cmap = O.hem_map(g, 0, 1)
+    assert nc == 18
+    assert list(cmap[:2]) == [0, 1] and all(cmap[2 * j] == cmap[2 * j + 1] for j in range(1, 17))
+    # with 250 vertices the first round matches 2 < 1% of 250 and ends them
+    n = 250
+    g = graph_from_edges(n, [(i, i + 1, i + 1) for i in range(n - 1)])
+    nc, cmap = O.hem_map(g, 0, 1)
+    assert nc == n - 1 and cmap[n - 2] == cmap[n - 1]
+
+
+def test_hem_distinct_weights_is_greedy_matching(oracle_lib):
+    """With distinct edge weights, rounds of mutual heaviest-edge proposals
+    run to a fixpoint give the textbook greedy matching (the heaviest free
+    edge is always proposed from both ends). Graphs below 100 vertices stop
+    only when a round matches nothing, so the cases here reach the fixpoint."""
+    O = oracle_lib
+    for s in range(24):
+        g = _distinct_weight_graph(20 + 3 * s, 0.12, 8100 + s)
+        nc, cmap = O.hem_map(g, s % 4, 300 + s)
+        mate = _mates_from_map(cmap)
+        assert mate == _greedy_matching(g), f"case {s}"
+        assert nc == g.n - sum(1 for m in mate if m >= 0) // 2
+        # coarse ids follow the smaller member's vertex order
+        firsts = [int(np.flatnonzero(cmap == c)[0]) for c in range(nc)]
+        assert firsts == sorted(firsts)
+
+
+def test_multilevel_is_algorithm1_composition(oracle_lib):
+    """Algorithm 1 recomposed from the oracle's pinned steps: coarsen while
+    n > 8k (a level keeping over 90% of its vertices is the last; one that
+    matches nothing is dropped), seeded random start on the coarsest graph,
+    then refine, project P_i = P_{i+1}[map_i] and refine each finer level.
+    The projected start's cut equals the coarser result's cut (contraction
+    keeps the cut of every projected partition)."""
+    O = oracle_lib
+    cases = [(I.grid2d(40, 40), 4, 7), (I.grid2d(33, 29), 3, 2), (I.stencil27(9, 8, 7), 5, 11),
+             (I.small_random_graph(300, 0.03, 41, wmax=5, vwmax=3), 4, 5),
+             # a star matches one leaf per level: the first level keeps 200 of
+             # 201 vertices and is the last
+             (graph_from_edges(201, [(0, i, 1 + i % 3) for i in range(1, 201)]), 2, 3)]
+    for g, k, seed in cases:
+        res = O.partition(g, k, seed=seed)
+        levels, maps = [g], []
+        while len(levels) < 64 and levels[-1].n > 8 * k:
+            f = levels[-1]
+            nc, cmap = O.hem_map(f, len(levels) - 1, seed)
+            if nc == f.n:
+                break
+            levels.append(O.contract(f, cmap, nc))
+            maps.append(cmap)
+            if 10 * nc > 9 * f.n:
+                break
+        sizes = [lv.n for lv in levels]
+        assert list(res["level_sizes"]) == sizes, g.name
+        top = len(levels) - 1
+        P = I.uniform_below(I.stream(I.mix64_scalar(seed ^ 1), np.arange(levels[top].n, dtype=np.uint64)),
+                            k).astype(np.int32)
+        trace = []
+        for i in range(top, -1, -1):
+            if i < top:
+                Pc = P
+                P = Pc[maps[i]]
+                assert brute_cut(levels[i], P) == brute_cut(levels[i + 1], Pc)
+            r = O.refine(levels[i], P, k, level=i, seed=seed)
+            trace += r.trace
+            P = r.part
+        np.testing.assert_array_equal(res["part"], P, err_msg=g.name)
+        assert res["trace"] == trace, g.name
+
+
 def test_partition_multilevel_sanity(oracle_lib):
+    """Level sizes follow the stop rule: every level but the coarsest has
+    more than 8k vertices, each level shrinks, and the coarsest has at most
+    8k vertices or kept more than 90% of the level above it."""
     O = oracle_lib
     g = I.grid2d(40, 40)
     res = O.partition(g, 4, seed=7)
     sizes = res["level_sizes"]
-    assert sizes[0] == 1600 and sizes[-1] <= 32 or len(sizes) > 1
+    assert sizes[0] == 1600 and sizes[-1] <= 32 and len(sizes) > 1
+    for k, gg in ((4, g), (3, I.grid2d(33, 29)), (6, I.stencil27(9, 8, 7))):
+        sz = [int(x) for x in O.partition(gg, k, seed=3)["level_sizes"]]
+        assert all(x > 8 * k for x in sz[:-1]) and (sz[-1] <= 8 * k or 10 * sz[-1] > 9 * sz[-2]), sz
     assert all(sizes[i + 1] < sizes[i] for i in range(len(sizes) - 1))
     assert brute_cut(g, res["part"]) == res["cut"]
     assert res["balanced"]
 
 
 # ---------------------------------------------------- Jetlp ablations ---
-# Section 5 (component effectiveness, Table lp_versions): the baseline is a
+# Section 7.1 (Component Effectiveness, Table lp_versions): the baseline is a
 # synchronous LP that moves vertices to their best connected part, with no
 # afterburner and no locks.
 
