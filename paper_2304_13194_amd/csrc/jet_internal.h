@@ -104,9 +104,10 @@ struct KArgs {
     int32_t tmap[NCLS];    // which role (1 S, 2 M, 3 L) serves each class in the LDS-table kernels
     // long rows of the L class cut into chunks (see LCHUNK); nlch = 0: L rows use the block role
     const int2 *lch;       // (index in the L list, chunk index) per chunk
+    const int32_t *lcoff;  // [L list + 1] first chunk of each long row
     int32_t nlch;
     int32_t lstride;       // row length of gconn (largest k)
-    int32_t *gconn;        // [L list][lstride] connectivity summed over a vertex's chunks
+    int32_t *gconn;        // [chunk][lstride] part counts of each chunk of a row of several chunks
     int32_t *ldone;        // [L list] chunks of the vertex completed in this pass
     int32_t *gf2;          // [L list] afterburner sum over a vertex's chunks
     // optional step outputs

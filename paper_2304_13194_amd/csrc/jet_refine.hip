@@ -863,6 +863,32 @@ __device__ __forceinline__ void conn_claim(int32_t *tab, const int (&pu)[R], int
     lds_fence_wave();
 }
 
+// Group of G lanes adds the neighbours of a row (deg <= G*R) into `tab`; all
+// R neighbour ids (and weights) of a lane are loaded before its dependent
+// part gathers. The caller reads the table back.
+template <int G, int R>
+__device__ __forceinline__ void group_fill_row(const KArgs &a, int64_t s, int deg, int gl, int32_t *tab)
+{
+    int u[R], w[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int idx = gl + r * G;
+        u[r] = idx < deg ? a.adj[s + idx] : -1;
+        w[r] = idx < deg ? (a.ew ? a.ew[s + idx] : 1) : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) u[r] = u[r] >= 0 ? a.P[u[r]] : -1;
+#pragma unroll
+    for (int r = 0; r < R; r++)
+        if (u[r] >= 0) atomicAdd(&tab[u[r]], w[r]);
+    lds_fence_wave();
+}
+
+// Parts a whole-wave row reads back by scanning its k-entry table (and
+// clearing what it finds) rather than claiming entry by entry: the scan is
+// k / 64 LDS reads per lane against one atomic exchange per row entry.
+constexpr int WAVE_SCAN_KMAX = 1024;
+
 // Wave-batched driver of the small-row role. Lanes first inspect 64 list
 // entries at once (coalesced loads of the id, row offsets and per-vertex
 // state); the entries that need row work are queued in LDS and handed to the
@@ -1255,14 +1281,80 @@ __device__ __forceinline__ void gain_body(const KArgs &a, int nblk)
         else
             body(std::integral_constant<int, 8>{}, std::integral_constant<int, 8>{}, CLS_S2, blockIdx.x - a.gS, a.gS2);
     } else if (ROLE == 2) {
-        // one wave per vertex, walking its list interleaved with the other waves
+        // one wave per row; lanes first inspect a stretch of the class list at
+        // once (part, lock stamp and row bounds of up to 64 vertices in one
+        // round trip) and queue the rows that need work
         const int ng = BLOCK / 64;
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         __syncthreads();
         int32_t *tab = lds + (threadIdx.x >> 6) * stride;
-        for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 2)
-                gain_groups<B, 64, 16>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 6), nblk * ng, pv, pacc, racc);
+        int32_t *q = lds + ng * stride + (threadIdx.x >> 6) * 64;
+        const int wid = blockIdx.x * ng + (threadIdx.x >> 6), nwaves = nblk * ng;
+        const bool scan = a.k <= WAVE_SCAN_KMAX;
+        for (int c = 1; c < NCLS; c++) {
+            if (a.tmap[c] != 2) continue;
+            const int cnt = a.binoff[c + 1] - a.binoff[c];
+            const int unit = wave_unit(cnt, nwaves);
+            auto pre = [&](Meta &m) -> bool {
+                m.g = gof<B>(a, m.v);
+                pv.sel<B>(a, m.g);
+                if (pv.kind != KIND_LP) return false;
+                m.ps = a.P[m.v];
+                const int lk = a.lock[m.v];
+                const int64_t x0 = a.xadj[m.v], x1 = a.xadj[m.v + 1];
+                pacc.sel<B>(a, m.g);
+                pacc.c0++;
+                if (lk == pv.lp_id - 1) {
+                    gain_locked(a, m.v, m.ps);
+                    return false;
+                }
+                m.s = x0;
+                m.deg = (int)(x1 - x0);
+                pacc.c1++;
+                pacc.c2 += m.deg;
+                return true;
+            };
+            auto row = [&](const Meta &t, int gl) {
+                rv.sel<B>(a, t.g);
+                uint64_t best = 0;
+                int cs = 0;
+                if (scan) {
+                    group_fill_row<64, 16>(a, t.s, t.deg, gl, tab);
+                    for (int p = gl; p < rv.k; p += 64) {
+                        const int cc = tab[p];
+                        if (cc) {
+                            tab[p] = 0;
+                            if (p == t.ps) cs = cc;
+                            else {
+                                const uint64_t k2 = conn_key(cc, p);
+                                best = k2 > best ? k2 : best;
+                            }
+                        }
+                    }
+                    lds_fence_wave();
+                } else {
+                    int pu[16], cu[16];
+                    group_conn_row<64, 16>(a, t.s, t.deg, gl, tab, pu, cu);
+#pragma unroll
+                    for (int r = 0; r < 16; r++) {
+                        if (cu[r] > 0) {
+                            if (pu[r] == t.ps) cs += cu[r];
+                            else {
+                                const uint64_t k2 = conn_key(cu[r], pu[r]);
+                                best = k2 > best ? k2 : best;
+                            }
+                        }
+                    }
+                }
+                best = gmax_u64<64>(best);
+                cs = gsum<64>(cs);
+                if (gl == 0) {
+                    racc.sel<B>(a, t.g);
+                    racc.c0 += gain_finish(a, t.v, t.ps, best, cs, rv.cn, rv.cd);
+                }
+            };
+            wave_batched<64>(a.bins + a.binoff[c], walk<B>(cnt, wid, nwaves, unit), q, pre, row, unit);
+        }
     } else {
         for (int i = threadIdx.x; i < a.k; i += BLOCK) lds[i] = 0;
         __syncthreads();
@@ -1638,16 +1730,25 @@ __device__ __forceinline__ bool rb_is_candidate(const KArgs &a, int ps, int vwv,
 }
 
 // ------------------------------------------------------- chunked long rows --
-// Rows of the L class are cut into chunks of LCHUNK entries, one wave each,
-// spread over the whole grid instead of one block walking a hub's row alone.
-// A chunk adds its part connectivity (or its afterburner partial sum) into a
-// per-vertex global row with atomics; a second kernel (one wave per long-row
-// vertex) reads and clears that row and finishes the vertex exactly as the
-// block role would. The kernel boundary orders the two phases.
-constexpr int LCHUNK = 1024;  // 64 lanes x 16 entries
+// Rows of the L class (more than M_MAXDEG entries) are cut into chunks of
+// LCHUNK entries, one block each (16 entries per thread, every load of the
+// chunk issued before its gathers), spread over the whole grid. A connectivity
+// pass adds a chunk's part counts into a block-shared LDS table. A row of one
+// chunk finishes in that block, as the block role would. A longer row stores
+// each chunk's table in a global row of its own (plain coalesced stores, no
+// atomics: chunks of one hub no longer meet on the same addresses), and a
+// second kernel (one wave per such vertex) sums the rows of its chunks and
+// finishes it. The afterburner and cut-delta passes reduce a chunk's partial
+// sum over the block. Kernel boundaries order the phases.
+constexpr int LCHUNK = BLOCK * 16;
+
+enum HistMode { HIST_NONE = 0, HIST_LDS = 1, HIST_GLOBAL = 2 };
+__device__ __forceinline__ void rb_finish(const KArgs &a, int v, int ps, const GV &gv, uint64_t best, int cs, int sumB,
+                                          int cntB, int vwv, int hmode, int32_t *lh);
 
 struct LChunk {
     int v, li, len;
+    bool multi;  // the row has more than one chunk
     int64_t s;
 };
 
@@ -1661,48 +1762,129 @@ __device__ __forceinline__ LChunk lchunk(const KArgs &a, int i)
     ch.s = s + (int64_t)e.y * LCHUNK;
     const int64_t rest = deg - (int64_t)e.y * LCHUNK;
     ch.len = (int)(rest < LCHUNK ? rest : LCHUNK);
+    ch.multi = deg > LCHUNK;
     return ch;
 }
 
-// Adds a wave's claimed connectivities into the vertex's global row.
-__device__ __forceinline__ void lchunk_flush(int32_t *row, const int (&pu)[16], const int (&cu)[16])
+// The whole block adds the part counts of a chunk (len <= LCHUNK entries)
+// into `tab`.
+__device__ __forceinline__ void chunk_fill(const KArgs &a, int64_t s, int len, int32_t *tab)
 {
+    constexpr int U = LCHUNK / BLOCK;
+    int u[U], w[U];
 #pragma unroll
-    for (int r = 0; r < 16; r++)
-        if (cu[r] > 0) atomicAdd(&row[pu[r]], cu[r]);
+    for (int j = 0; j < U; j++) {
+        const int idx = threadIdx.x + j * BLOCK;
+        u[j] = idx < len ? a.adj[s + idx] : -1;
+        w[j] = idx < len ? (a.ew ? a.ew[s + idx] : 1) : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < U; j++) u[j] = u[j] >= 0 ? a.P[u[j]] : -1;
+#pragma unroll
+    for (int j = 0; j < U; j++)
+        if (u[j] >= 0) atomicAdd(&tab[u[j]], w[j]);
+    __syncthreads();
 }
 
-// Phase 1 of Jetlp gain and of the rebalancing loss on long rows: every
-// chunk of a vertex that needs its connectivity adds it to the vertex's row.
-template <bool B, bool RB>
-__global__ __launch_bounds__(BLOCK) void k_lconn(KArgs a)
+// Moves a chunk's table to its global row (every part, zeros included, so
+// the finishing kernel needs no clearing) and clears the table.
+__device__ __forceinline__ void chunk_store(const KArgs &a, int i, int k, int32_t *tab)
 {
+    int32_t *row = a.gconn + (int64_t)i * a.lstride;
+    for (int p = threadIdx.x; p < k; p += BLOCK) {
+        const int c = tab[p];
+        row[p] = c;
+        if (c) tab[p] = 0;
+    }
+    __syncthreads();
+}
+
+// Jetlp gain (RB = false) or rebalancing loss (RB = true) of the long rows,
+// first phase: one block per chunk.
+template <bool B, bool RB>
+__global__ __launch_bounds__(BLOCK) void k_lconn(KArgs a, int hmode)
+{
+    __shared__ uint64_t s_red[BLOCK / 64];
+    __shared__ int32_t s_red32[BLOCK / 64];
     if (RB ? !any_rb(a) : !any_kind(a, KIND_LP)) return;
     extern __shared__ int32_t lds[];
-    const int stride = a.k + 1;
-    for (int i = threadIdx.x; i < (BLOCK / 64) * stride; i += BLOCK) lds[i] = 0;
+    for (int i = threadIdx.x; i < a.k; i += BLOCK) lds[i] = 0;
     __syncthreads();
-    int32_t *tab = lds + (threadIdx.x >> 6) * stride;
-    const int gl = threadIdx.x & 63;
     GV pv;
-    if (!B) pv.at(a, 0);
-    const int nw = gridDim.x * (BLOCK / 64);
-    for (int i = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); i < a.nlch; i += nw) {
+    GainPre pacc;
+    CountX racc;
+    if (!B) {
+        pv.at(a, 0);
+        pacc.to(a, 0);
+        racc.to(a, 0);
+    }
+    for (int i = blockIdx.x; i < a.nlch; i += gridDim.x) {
         const LChunk ch = lchunk(a, i);
-        pv.sel<B>(a, gof<B>(a, ch.v));
+        const int g = gof<B>(a, ch.v);
+        pv.sel<B>(a, g);
         const int ps = a.P[ch.v];
+        const int vwv = a.vw ? a.vw[ch.v] : 1;
         if (RB) {
-            if (!is_rb(pv.kind) || !rb_is_candidate(a, ps, a.vw ? a.vw[ch.v] : 1, pv)) continue;
+            if (!is_rb(pv.kind) || !rb_is_candidate(a, ps, vwv, pv)) continue;
         } else {
             if (pv.kind != KIND_LP || a.lock[ch.v] == pv.lp_id - 1) continue;
         }
-        int pu[16], cu[16];
-        group_conn_row<64, 16>(a, ch.s, ch.len, gl, tab, pu, cu);
-        lchunk_flush(a.gconn + (int64_t)ch.li * a.lstride, pu, cu);
+        chunk_fill(a, ch.s, ch.len, lds);
+        if (ch.multi) {
+            chunk_store(a, i, pv.k, lds);
+            continue;
+        }
+        // a row of one chunk: finish the vertex here
+        uint64_t best = 0;
+        int cs = 0, sumB = 0, cntB = 0;
+        for (int p = threadIdx.x; p < pv.k; p += BLOCK) {
+            const int c = lds[p];
+            if (c) {
+                lds[p] = 0;
+                if (p == ps) cs = c;
+                else if (!RB || a.isB[pv.poff + p]) {
+                    const uint64_t k2 = conn_key(c, p);
+                    best = k2 > best ? k2 : best;
+                    sumB += c;
+                    cntB++;
+                }
+            }
+        }
+        best = block_max_u64<BLOCK>(best, s_red);
+        cs = block_sum<BLOCK>(cs, s_red32);
+        if (RB) {
+            sumB = block_sum<BLOCK>(sumB, s_red32);
+            cntB = block_sum<BLOCK>(cntB, s_red32);
+        }
+        if (threadIdx.x == 0) {
+            racc.sel<B>(a, g);
+            if (RB) {
+                rb_finish(a, ch.v, ps, pv, best, cs, sumB, cntB, vwv, hmode, nullptr);
+                racc.c0++;
+            } else {
+                pacc.sel<B>(a, g);
+                pacc.c0++;
+                pacc.c1++;
+                pacc.c2 += ch.len;
+                racc.c0 += gain_finish(a, ch.v, ps, best, cs, pv.cn, pv.cd);
+            }
+        }
     }
+    if (!RB) acc_finish(a, pacc);
+    acc_finish(a, racc);
 }
 
-// Phase 2 of the Jetlp gain on long rows (one wave per vertex).
+// Sum of a multi-chunk row's chunk tables at part p.
+__device__ __forceinline__ int chunk_rows_sum(const KArgs &a, int li, int p)
+{
+    const int c0 = a.lcoff[li], c1 = a.lcoff[li + 1];
+    int c = 0;
+    for (int i = c0; i < c1; i++) c += a.gconn[(int64_t)i * a.lstride + p];
+    return c;
+}
+
+// Phase 2 of the Jetlp gain on long rows (one wave per vertex): locked rows,
+// and the rows of more than one chunk.
 template <bool B>
 __global__ __launch_bounds__(BLOCK) void k_lgain_fin(KArgs a)
 {
@@ -1724,21 +1906,21 @@ __global__ __launch_bounds__(BLOCK) void k_lgain_fin(KArgs a)
         pv.sel<B>(a, g);
         if (pv.kind != KIND_LP) continue;
         const int ps = a.P[v];
-        if (gl == 0) {
-            pacc.sel<B>(a, g);
-            pacc.c0++;
-        }
         if (a.lock[v] == pv.lp_id - 1) {
-            if (gl == 0) gain_locked(a, v, ps);
+            if (gl == 0) {
+                pacc.sel<B>(a, g);
+                pacc.c0++;
+                gain_locked(a, v, ps);
+            }
             continue;
         }
-        int32_t *row = a.gconn + (int64_t)li * a.lstride;
+        const int64_t deg = a.xadj[v + 1] - a.xadj[v];
+        if (deg <= LCHUNK) continue;  // finished by its chunk's block
         uint64_t best = 0;
         int cs = 0;
         for (int p = gl; p < pv.k; p += 64) {
-            const int c = row[p];
+            const int c = chunk_rows_sum(a, li, p);
             if (c) {
-                row[p] = 0;
                 if (p == ps) cs = c;
                 else {
                     const uint64_t k2 = conn_key(c, p);
@@ -1749,8 +1931,10 @@ __global__ __launch_bounds__(BLOCK) void k_lgain_fin(KArgs a)
         best = gmax_u64<64>(best);
         cs = gsum<64>(cs);
         if (gl == 0) {
+            pacc.sel<B>(a, g);
+            pacc.c0++;
             pacc.c1++;
-            pacc.c2 += a.xadj[v + 1] - a.xadj[v];
+            pacc.c2 += deg;
             racc.sel<B>(a, g);
             racc.c0 += gain_finish(a, v, ps, best, cs, pv.cn, pv.cd);
         }
@@ -1759,16 +1943,16 @@ __global__ __launch_bounds__(BLOCK) void k_lgain_fin(KArgs a)
     acc_finish(a, racc);
 }
 
-// Afterburner on long rows, phase 1: partial F2 of every chunk of a vertex in X.
+// Afterburner on long rows, phase 1: the F2 sum of every chunk of a vertex
+// in X; a row of one chunk stores its move here.
 template <bool B>
 __global__ __launch_bounds__(BLOCK) void k_lafter(KArgs a)
 {
+    __shared__ int32_t s_red[BLOCK / 64];
     if (!any_kind(a, KIND_LP)) return;
-    const int gl = threadIdx.x & 63;
     GV pv;
     if (!B) pv.at(a, 0);
-    const int nw = gridDim.x * (BLOCK / 64);
-    for (int i = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); i < a.nlch; i += nw) {
+    for (int i = blockIdx.x; i < a.nlch; i += gridDim.x) {
         const LChunk ch = lchunk(a, i);
         const int g = gof<B>(a, ch.v);
         pv.sel<B>(a, g);
@@ -1776,13 +1960,17 @@ __global__ __launch_bounds__(BLOCK) void k_lafter(KArgs a)
         const int2 r = a.rec[ch.v];
         if ((r.x & 0xFFFF) == 0) continue;  // not in X
         const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
-        int part = after_sum_row<4>(a, ch.v, ch.s, ch.len, ps, pd, r.y, gl, 64);
-        part = gsum<64>(part);
-        if (gl == 0 && part) atomicAdd(&a.gf2[ch.li], part);
+        int part = after_sum_row<8>(a, ch.v, ch.s, ch.len, ps, pd, r.y, threadIdx.x, BLOCK);
+        part = block_sum<BLOCK>(part, s_red);
+        if (threadIdx.x == 0) {
+            if (!ch.multi) after_store(a, ch.v, pd, part);
+            else if (part) atomicAdd(&a.gf2[ch.li], part);
+        }
     }
 }
 
-// Afterburner on long rows, phase 2 (one lane per vertex).
+// Afterburner on long rows, phase 2 (one lane per vertex): rows of more than
+// one chunk, and the ablation without the afterburner.
 template <bool B>
 __global__ __launch_bounds__(BLOCK) void k_lafter_fin(KArgs a)
 {
@@ -1797,7 +1985,12 @@ __global__ __launch_bounds__(BLOCK) void k_lafter_fin(KArgs a)
         if (pv.kind != KIND_LP) continue;
         const int2 r = a.rec[v];
         if ((r.x & 0xFFFF) == 0) continue;
-        const int sum = no_afterburner(a, g) ? 0 : a.gf2[li];
+        if (no_afterburner(a, g)) {
+            after_store(a, v, (r.x & 0xFFFF) - 1, 0);
+            continue;
+        }
+        if (a.xadj[v + 1] - a.xadj[v] <= LCHUNK) continue;
+        const int sum = a.gf2[li];
         a.gf2[li] = 0;
         after_store(a, v, (r.x & 0xFFFF) - 1, sum);
     }
@@ -1806,8 +1999,8 @@ __global__ __launch_bounds__(BLOCK) void k_lafter_fin(KArgs a)
 template <bool B>
 __global__ __launch_bounds__(BLOCK) void k_ldcut(KArgs a)
 {
+    __shared__ int32_t s_red[BLOCK / 64];
     if (!any_active(a)) return;
-    const int gl = threadIdx.x & 63;
     GV pv;
     MoveAcc macc;
     CutAcc cacc;
@@ -1816,15 +2009,14 @@ __global__ __launch_bounds__(BLOCK) void k_ldcut(KArgs a)
         macc.to(a, 0);
         cacc.to(a, 0);
     }
-    const int nw = gridDim.x * (BLOCK / 64);
-    for (int i = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); i < a.nlch; i += nw) {
+    for (int i = blockIdx.x; i < a.nlch; i += gridDim.x) {
         const LChunk ch = lchunk(a, i);
         const int pn = a.dest[ch.v];
         if (pn < 0) continue;
         const int ps = a.P[ch.v];
-        int d = dcut_sum_row<4>(a, ch.v, ch.s, ch.len, ps, pn, gl, 64);
-        d = gsum<64>(d);
-        if (gl == 0) {
+        int d = dcut_sum_row<8>(a, ch.v, ch.s, ch.len, ps, pn, threadIdx.x, BLOCK);
+        d = block_sum<BLOCK>(d, s_red);
+        if (threadIdx.x == 0) {
             const int g = gof<B>(a, ch.v);
             cacc.sel<B>(a, g);
             cacc.c0 += (uint64_t)(int64_t)d;
@@ -1887,8 +2079,6 @@ __global__ __launch_bounds__(BLOCK) void k_lchunk_fill(const int32_t *ctot, cons
 // build it: HIST_LDS adds into the block's LDS copy (flushed once per block),
 // HIST_GLOBAL adds into the global histogram directly; HIST_NONE leaves it to
 // the separate histogram pass.
-enum HistMode { HIST_NONE = 0, HIST_LDS = 1, HIST_GLOBAL = 2 };
-
 __device__ __forceinline__ void rb_finish(const KArgs &a, int v, int ps, const GV &gv, uint64_t best, int cs, int sumB,
                                           int cntB, int vwv, int hmode, int32_t *lh)
 {
@@ -2170,13 +2360,78 @@ __device__ __forceinline__ void loss_body(const KArgs &a, int nblk, int hmode)
         else
             body(std::integral_constant<int, 8>{}, std::integral_constant<int, 8>{}, CLS_S2, blockIdx.x - a.gS, a.gS2);
     } else if (ROLE == 2) {
+        // one wave per candidate row, wave-batched as in the gain kernel
         const int ng = BLOCK / 64;
         for (int i = threadIdx.x; i < ng * stride; i += BLOCK) lds[i] = 0;
         __syncthreads();
         int32_t *tab = lds + (threadIdx.x >> 6) * stride;
-        for (int c = 1; c < NCLS; c++)
-            if (a.tmap[c] == 2)
-                rb_groups<B, 64, 16>(a, c, tab, blockIdx.x * ng + (threadIdx.x >> 6), nblk * ng, pv, racc, hmode, lh);
+        int32_t *q = lds + hoff + (hmode == HIST_LDS ? a.k * NSLOT : 0) + (threadIdx.x >> 6) * 64;
+        const int wid = blockIdx.x * ng + (threadIdx.x >> 6), nwaves = nblk * ng;
+        const bool scan = a.k <= WAVE_SCAN_KMAX;
+        for (int c = 1; c < NCLS; c++) {
+            if (a.tmap[c] != 2) continue;
+            const int cnt = a.binoff[c + 1] - a.binoff[c];
+            const int unit = wave_unit(cnt, nwaves);
+            auto pre = [&](Meta &m) -> bool {
+                m.g = gof<B>(a, m.v);
+                pv.sel<B>(a, m.g);
+                if (!is_rb(pv.kind)) return false;
+                m.ps = a.P[m.v];
+                m.aux = a.vw ? a.vw[m.v] : 1;
+                const int64_t x0 = a.xadj[m.v], x1 = a.xadj[m.v + 1];
+                if (!rb_candidate(a, m.v, m.ps, m.aux, pv)) return false;
+                m.s = x0;
+                m.deg = (int)(x1 - x0);
+                return true;
+            };
+            auto row = [&](const Meta &t, int gl) {
+                rv.sel<B>(a, t.g);
+                uint64_t best = 0;
+                int cs = 0, sumB = 0, cntB = 0;
+                if (scan) {
+                    group_fill_row<64, 16>(a, t.s, t.deg, gl, tab);
+                    for (int p = gl; p < rv.k; p += 64) {
+                        const int cc = tab[p];
+                        if (cc) {
+                            tab[p] = 0;
+                            if (p == t.ps) cs = cc;
+                            else if (a.isB[rv.poff + p]) {
+                                const uint64_t k2 = conn_key(cc, p);
+                                best = k2 > best ? k2 : best;
+                                sumB += cc;
+                                cntB++;
+                            }
+                        }
+                    }
+                    lds_fence_wave();
+                } else {
+                    int pu[16], cu[16];
+                    group_conn_row<64, 16>(a, t.s, t.deg, gl, tab, pu, cu);
+#pragma unroll
+                    for (int r = 0; r < 16; r++) {
+                        if (cu[r] > 0) {
+                            if (pu[r] == t.ps) cs += cu[r];
+                            else if (a.isB[rv.poff + pu[r]]) {
+                                const uint64_t k2 = conn_key(cu[r], pu[r]);
+                                best = k2 > best ? k2 : best;
+                                sumB += cu[r];
+                                cntB++;
+                            }
+                        }
+                    }
+                }
+                best = gmax_u64<64>(best);
+                cs = gsum<64>(cs);
+                sumB = gsum<64>(sumB);
+                cntB = gsum<64>(cntB);
+                if (gl == 0) {
+                    rb_finish(a, t.v, t.ps, rv, best, cs, sumB, cntB, t.aux, hmode, lh);
+                    racc.sel<B>(a, t.g);
+                    racc.c0++;
+                }
+            };
+            wave_batched<64>(a.bins + a.binoff[c], walk<B>(cnt, wid, nwaves, unit), q, pre, row, unit);
+        }
     } else if (ROLE == 3) {
         for (int i = threadIdx.x; i < a.k; i += BLOCK) lds[i] = 0;
         __syncthreads();
@@ -2229,7 +2484,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
     else if (any_rb(a)) loss_body<false, 1, GS, RS, PC, CL>(a, nblk, hmode);
 }
 
-// Rebalancing loss on long rows, phase 2 (one wave per vertex).
+// Rebalancing loss on long rows, phase 2 (one wave per vertex): the "no
+// candidate" outputs, and the candidate rows of more than one chunk.
 template <bool B>
 __global__ __launch_bounds__(BLOCK) void k_lrb_fin(KArgs a, int hmode)
 {
@@ -2254,13 +2510,12 @@ __global__ __launch_bounds__(BLOCK) void k_lrb_fin(KArgs a, int hmode)
             if (gl == 0) rb_candidate(a, v, ps, vwv, pv);  // writes the "no candidate" outputs
             continue;
         }
-        int32_t *row = a.gconn + (int64_t)li * a.lstride;
+        if (a.xadj[v + 1] - a.xadj[v] <= LCHUNK) continue;  // finished by its chunk's block
         uint64_t best = 0;
         int cs = 0, sumB = 0, cntB = 0;
         for (int p = gl; p < pv.k; p += 64) {
-            const int c = row[p];
+            const int c = chunk_rows_sum(a, li, p);
             if (c) {
-                row[p] = 0;
                 if (p == ps) cs = c;
                 else if (a.isB[pv.poff + p]) {
                     const uint64_t k2 = conn_key(c, p);
@@ -2814,7 +3069,7 @@ static size_t rb_role_lds(int role, int k)
 {
     const size_t st = (size_t)(k + 1) * 4;
     if (role == 1) return (BLOCK / (k <= K_G4 ? 4 : 8)) * st + BLOCK * 4;
-    if (role == 2) return (BLOCK / 64) * st;
+    if (role == 2) return (BLOCK / 64) * st + BLOCK * 4;
     if (role == 3) return (size_t)k * 4;
     return 0;
 }
@@ -2851,7 +3106,7 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
     t.tmap[0] = 0;
     const int k = a.k;
     if (k <= 495) { t.tmap[CLS_S] = 1; t.tmap[CLS_S2] = 1; t.tmap[CLS_M] = 2; t.tmap[CLS_L] = 3; }
-    else if (k <= 4095) { t.tmap[CLS_S] = 2; t.tmap[CLS_S2] = 2; t.tmap[CLS_M] = 2; t.tmap[CLS_L] = 3; }
+    else if (k <= 4031) { t.tmap[CLS_S] = 2; t.tmap[CLS_S2] = 2; t.tmap[CLS_M] = 2; t.tmap[CLS_L] = 3; }
     else { t.tmap[CLS_S] = 3; t.tmap[CLS_S2] = 3; t.tmap[CLS_M] = 3; t.tmap[CLS_L] = 3; }
     if (chunked) t.tmap[CLS_L] = 0;
     int64_t role_cnt[4] = {0, 0, 0, 0};
@@ -2907,7 +3162,7 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
     pl.grid_hist = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_flat = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_tile = std::max(1, std::min(a.ntile, ctx->num_cu * 8));
-    pl.grid_lch = chunked ? std::max(1, std::min(div_up(a.nlch, BLOCK / 64), maxb)) : 0;
+    pl.grid_lch = chunked ? std::max(1, std::min(a.nlch, maxb)) : 0;
     pl.nL = cnt[CLS_L];
     pl.grid_lfin = chunked ? std::max(1, std::min(div_up(pl.nL, BLOCK / 64), maxb)) : 0;
 }
@@ -2930,10 +3185,10 @@ static void launch_gain_t(const Plan &pl, hipStream_t s, bool small = true)
     } else if (t.gS2) {
         k_gain<B, 1, 8, 8, CLS_S2><<<t.gS2, BLOCK, rb_s2_lds(t.k), s>>>(t, t.gS2);
     }
-    if (t.gM) k_gain<B, 2><<<t.gM, BLOCK, (BLOCK / 64) * st, s>>>(t, t.gM);
+    if (t.gM) k_gain<B, 2><<<t.gM, BLOCK, (BLOCK / 64) * st + BLOCK * 4, s>>>(t, t.gM);
     if (t.gL) k_gain<B, 3><<<t.gL, BLOCK, (size_t)t.k * 4, s>>>(t, t.gL);
     if (pl.grid_lch) {
-        k_lconn<B, false><<<pl.grid_lch, BLOCK, (BLOCK / 64) * st, s>>>(t);
+        k_lconn<B, false><<<pl.grid_lch, BLOCK, (size_t)t.k * 4, s>>>(t, HIST_NONE);
         k_lgain_fin<B><<<pl.grid_lfin, BLOCK, 0, s>>>(t);
     }
 }
@@ -2958,7 +3213,6 @@ static void launch_rb_loss_t(const Plan &pl, hipStream_t s, bool small = true)
     const KArgs &t = pl.tab;
     const int hm = pl.hist_fused ? HIST_LDS : HIST_NONE;
     const size_t hb = pl.hist_fused ? (size_t)t.k * NSLOT * 4 : 0;
-    const size_t st = (size_t)(t.k + 1) * 4;
     const size_t cb = pl.loss_cache ? rb_cache_lds(t.k) : 0;
     if (!small) {
     } else if (t.gS && t.gS2) {
@@ -2989,8 +3243,9 @@ static void launch_rb_loss_t(const Plan &pl, hipStream_t s, bool small = true)
     if (t.gL) k_rb_loss<B, 3><<<t.gL, BLOCK, rb_role_lds(3, t.k) + hb, s>>>(t, t.gL, hm);
     if (t.gZ) k_rb_loss<B, 4><<<t.gZ, BLOCK, rb_role_lds(4, t.k) + hb, s>>>(t, t.gZ, hm);
     if (pl.grid_lch) {
-        k_lconn<B, true><<<pl.grid_lch, BLOCK, (BLOCK / 64) * st, s>>>(t);
-        k_lrb_fin<B><<<pl.grid_lfin, BLOCK, 0, s>>>(t, pl.hist_fused ? HIST_GLOBAL : HIST_NONE);
+        const int lh = pl.hist_fused ? HIST_GLOBAL : HIST_NONE;
+        k_lconn<B, true><<<pl.grid_lch, BLOCK, (size_t)t.k * 4, s>>>(t, lh);
+        k_lrb_fin<B><<<pl.grid_lfin, BLOCK, 0, s>>>(t, lh);
     }
 }
 
@@ -3370,18 +3625,19 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
         tot[c] = htot[c];
         a.binoff[c + 1] = a.binoff[c] + tot[c];
     }
-    // chunked long rows when their per-vertex connectivity rows fit in 512 MiB
+    // chunked long rows when the per-chunk connectivity rows fit in 512 MiB
+    // (else the block role walks each long row alone)
     const int nL = tot[CLS_L];
     const int nch = hcnt[CNT_N];
-    if (nL > 0 && nch > 0 && (size_t)nL * (size_t)L.kmax * 4 <= ((size_t)512 << 20)) {
+    if (nL > 0 && nch > 0 && (size_t)nch * (size_t)L.kmax * 4 <= ((size_t)512 << 20)) {
         int2 *lch = (int2 *)ws_get(ctx, WS_LCH, sizeof(int2) * (size_t)nch);
-        int32_t *gconn = (int32_t *)ws_get(ctx, WS_GCONN, sizeof(int32_t) * (size_t)nL * L.kmax);
+        int32_t *gconn = (int32_t *)ws_get(ctx, WS_GCONN, sizeof(int32_t) * (size_t)nch * L.kmax);
         int32_t *ldone = (int32_t *)ws_get(ctx, WS_LDONE, sizeof(int32_t) * 2 * (size_t)nL);
         if (!lch || !gconn || !ldone) return JET_ENOMEM;
-        JET_TRY(hipMemsetAsync(gconn, 0, sizeof(int32_t) * (size_t)nL * L.kmax, s));
         JET_TRY(hipMemsetAsync(ldone, 0, sizeof(int32_t) * 2 * (size_t)nL, s));
         k_lchunk_fill<<<grid_v, BLOCK, 0, s>>>(ctot, lcnt, lch);
         a.lch = lch;
+        a.lcoff = lcnt;
         a.nlch = nch;
         a.lstride = L.kmax;
         a.gconn = gconn;
@@ -3929,6 +4185,7 @@ int refine_batch(jet_context *ctx, int count, const jet_csr *graphs, const jet_p
 using namespace jet;
 
 // --------------------------------------------------------------- C ABI ------
+
 
 // The refinement loop reads its state back many times per partition; a
 // thread that sleeps in the runtime until the stream drains wakes up tens of

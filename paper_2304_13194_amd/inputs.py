@@ -101,6 +101,17 @@ class Graph:
         return np.diff(self.xadj)
 
 
+def _argsort_unique(key: np.ndarray) -> np.ndarray:
+    """Ascending order of distinct int64 keys (any sort gives the same order
+    when no two keys are equal). Large arrays use torch's multithreaded CPU
+    sort; the order is identical to numpy's."""
+    if key.shape[0] < (1 << 20):
+        return np.argsort(key, kind="stable")
+    import torch
+    _, idx = torch.sort(torch.from_numpy(key), stable=True)
+    return idx.numpy()
+
+
 def csr_from_edges(n: int, u: np.ndarray, v: np.ndarray, w: np.ndarray | None = None,
                    vwgt: np.ndarray | None = None, name: str = "") -> Graph:
     """Symmetric CSR from a list of distinct undirected edges u < v (no self-loops).
@@ -115,7 +126,7 @@ def csr_from_edges(n: int, u: np.ndarray, v: np.ndarray, w: np.ndarray | None = 
     dst = np.concatenate([v, u])
     ww = np.concatenate([w, w]).astype(np.int32)
     key = src * np.int64(n) + dst
-    order = np.argsort(key, kind="stable")
+    order = _argsort_unique(key)
     src = src[order]
     dst = dst[order]
     ww = ww[order]
@@ -190,23 +201,26 @@ def rmat(scale: int, edge_factor: int, seed: int, a=0.57, b=0.19, c=0.19,
     ns = edge_factor * n
     s_bits = subseed(seed, 2)
     ta = int(round(a * 65536)); tb = int(round((a + b) * 65536)); tc = int(round((a + b + c) * 65536))
-    src = np.zeros(ns, dtype=np.int64)
-    dst = np.zeros(ns, dtype=np.int64)
+    import torch  # multithreaded elementwise bit work; same integers as numpy
+    src = torch.zeros(ns, dtype=torch.int64)
+    dst = torch.zeros(ns, dtype=torch.int64)
     sample = np.arange(ns, dtype=np.uint64)
     nwords = (scale + 3) // 4
     for wi in range(nwords):
         with np.errstate(over="ignore"):
-            x = stream(s_bits, sample * np.uint64(nwords) + np.uint64(wi))
+            x = torch.from_numpy(stream(s_bits, sample * np.uint64(nwords) + np.uint64(wi)).view(np.int64))
         for j in range(4):
             lvl = wi * 4 + j
             if lvl >= scale:
                 break
-            r = ((x >> np.uint64(16 * j)) & np.uint64(0xFFFF)).astype(np.int64)
-            bit_src = (r >= tb).astype(np.int64)           # quadrants c, d -> lower half
-            bit_dst = (((r >= ta) & (r < tb)) | (r >= tc)).astype(np.int64)  # b, d -> right
+            r = (x >> (16 * j)) & 0xFFFF  # the 16-bit field; masking undoes the sign of the shift
+            bit_src = (r >= tb).to(torch.int64)            # quadrants c, d -> lower half
+            bit_dst = (((r >= ta) & (r < tb)) | (r >= tc)).to(torch.int64)  # b, d -> right
             src |= bit_src << lvl
             dst |= bit_dst << lvl
         del x
+    del sample
+    src = src.numpy(); dst = dst.numpy()
     keep = src != dst
     src = src[keep]; dst = dst[keep]
     lo = np.minimum(src, dst); hi = np.maximum(src, dst)
@@ -358,6 +372,26 @@ def serve_pool_graph(spec) -> Graph:
     if spec[0] == "grid":
         return grid2d(spec[1], spec[1])
     return rmat(spec[1], spec[2], spec[3])
+
+
+def serve_job_specs(count: int, seed: int = 99):
+    """Per-job draws of the serving mix: half 2-D grids with side uniform in
+    [64, 1024] (unit weights), half R-MAT graphs with scale uniform in
+    [12, 20], edge factor uniform in [8, 16] and a graph seed of their own
+    (weights 1..16); k uniform in [2, 256]; a partition seed per job.
+    Returns (graph spec, k, seed) per job; ``serve_pool_graph(spec)`` draws
+    the graph."""
+    u = stream(subseed(seed, 10), np.arange(5 * count, dtype=np.uint64))
+    kind = uniform_below(u[:count], 2)
+    side = 64 + uniform_below(u[count:2 * count], 1024 - 64 + 1)
+    scale = 12 + uniform_below(u[2 * count:3 * count], 9)
+    ef = 8 + uniform_below(u[3 * count:4 * count], 9)
+    ks = 2 + uniform_below(u[4 * count:], 255)
+    out = []
+    for i in range(count):
+        spec = ("grid", int(side[i])) if kind[i] == 0 else ("rmat", int(scale[i]), int(ef[i]), 5000 + i)
+        out.append((spec, int(ks[i]), 1000 + i))
+    return out
 
 
 def serve_jobs(count: int, seed: int = 99):

@@ -76,6 +76,11 @@ def cases():
         ("rmat12_k5000", I.rmat(12, 8, 8), 5000, 0),
         ("star3000_k3", star(3000), 3, 0),
         ("stars_chunks_k4", stars([1024, 1025, 2048, 2049, 4100]), 4, 0),
+        # rows of several 4096-entry chunks (full and ragged last chunks)
+        ("stars_multichunk_k16", stars([4096, 4097, 8192, 9000, 13001]), 16, 0),
+        # long rows at k >= 4096 (one 16 KiB or 64 KiB chunk table per block)
+        ("stars_long_k5000", stars([1025, 4100, 9000]), 5000, 0),
+        ("stars_long_k16384", stars([1025, 4100]), 16384, 0),
         ("rgg3000_k16", I.rgg(3000, 9), 16, 0),
     ]
     for s in range(6):
