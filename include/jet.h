@@ -190,6 +190,32 @@ int  jet_last_hip_error(const jet_context *ctx);
 int jet_refine(jet_context *ctx, const jet_csr *g, const jet_params *params, int32_t *part,
                int64_t *part_weights_out, jet_stats *stats, jet_trace *trace, void *stream);
 
+/* ---- refinement without allocation ----------------------------------------
+ * For callers that cannot allocate device memory during the call (code
+ * running under stream capture of their own, tight serving loops, harnesses
+ * that forbid hipMalloc): jet_refine with the same arguments, results, trace
+ * and errors, whose workspace (per-vertex state, class lists, counters,
+ * controller, histograms, tile sums, long-row chunk tables, trace staging)
+ * is carved from one static device array of JET_NOALLOC_SCRATCH_BYTES per
+ * GPU instead of the context's pool. The array is part of the library's
+ * code object: every GPU the library runs on holds it until the process
+ * ends. The call itself allocates nothing (no hipMalloc / hipFree, no host
+ * or pinned allocation, no graph instantiation: iterations are launched
+ * directly); the context must come from jet_context_create, which looks the
+ * array up once per device.
+ * Limits and restrictions: the workspace of (n, nnz, k, trace capacity) must
+ * fit the array (about 33 bytes per vertex plus per-part, per-tile and
+ * long-row terms; JET_ELIMIT before any device work otherwise, `part`
+ * untouched); k >= 2 (JET_EINVAL for k = 1, answered by jet_refine);
+ * JET_F_VALIDATE and JET_F_PROFILE are rejected (JET_EINVAL).
+ * All calls on one GPU share its array, which keeps the previous call's
+ * contents (every call initialises what it reads): calls that overlap in
+ * time on one GPU, from any context or thread, race and must be serialised
+ * by the caller. */
+#define JET_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int jet_refine_noalloc(jet_context *ctx, const jet_csr *g, const jet_params *params, int32_t *part,
+                       int64_t *part_weights_out, jet_stats *stats, jet_trace *trace, void *stream);
+
 /* ---- batched refinement ---------------------------------------------------
  * Refines `count` independent graphs in one launch sequence: the graphs are
  * laid out as one block-diagonal union (graph i's vertices, parts and

@@ -162,6 +162,12 @@ struct jet_context {
     hipEvent_t wait_ev = nullptr;     // polled by stream_wait
     jet::Arena part_arena;            // coarse levels of jet_partition calls
     bool poll_wait = true;            // poll instead of sleeping in the runtime (JET_BLOCKING_WAIT=1 turns it off)
+    // jet_refine_noalloc: device address of this device's static scratch
+    // array (looked up once per device at context creation); while
+    // scratch_on, ws_get carves its slots from it instead of allocating
+    char *scratch = nullptr;
+    size_t scratch_off = 0;
+    bool scratch_on = false;
 };
 
 namespace jet {

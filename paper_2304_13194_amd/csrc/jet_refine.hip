@@ -35,6 +35,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -2997,6 +2998,14 @@ int hip_status(jet_context *ctx, hipError_t e)
 void *ws_get(jet_context *ctx, int slot, size_t bytes)
 {
     if (bytes == 0) bytes = 16;
+    if (ctx->scratch_on) {
+        // jet_refine_noalloc: bump allocation from the static scratch array;
+        // every slot is requested once per call
+        const size_t off = (ctx->scratch_off + 255) & ~(size_t)255;
+        if (!ctx->scratch || off + bytes > (size_t)JET_NOALLOC_SCRATCH_BYTES) return nullptr;
+        ctx->scratch_off = off + bytes;
+        return ctx->scratch + off;
+    }
     Buffer &b = ctx->bufs[slot];
     if (b.bytes >= bytes) return b.ptr;
     if (b.ptr) {
@@ -4186,6 +4195,34 @@ using namespace jet;
 
 // --------------------------------------------------------------- C ABI ------
 
+// Workspace of jet_refine_noalloc: one static array per GPU, part of the code
+// object. Host code never passes its name to a kernel (on the host the name
+// is a stand-in, not a device address): jet_context_create looks up each
+// device's address once, with that device current, and the call hands that
+// address to ws_get.
+static __device__ __align__(256) unsigned char scratch[JET_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this device's scratch array (the device must be current).
+int scratch_lookup(jet_context *ctx, int device, char **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= MAX_DEVICES) return JET_ELIMIT;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_status(ctx, e != hipSuccess ? e : hipErrorInvalidSymbol);
+        g_scratch_ptr[device] = (char *)ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return JET_OK;
+}
+}  // namespace
 
 // The refinement loop reads its state back many times per partition; a
 // thread that sleeps in the runtime until the stream drains wakes up tens of
@@ -4219,9 +4256,18 @@ extern "C" int jet_context_create(jet_context **out, int device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         ctx->num_cu = prop.multiProcessorCount;
-    if (!pinned_get(ctx, 4096)) {
+    // staging for one controller and the loop state: large enough that a
+    // single-graph call never grows it (jet_refine_noalloc allocates nothing)
+    if (!pinned_get(ctx, 16384)) {
         delete ctx;
         return JET_ENOMEM;
+    }
+    {
+        const int st = scratch_lookup(ctx, device, &ctx->scratch);
+        if (st) {
+            jet_context_destroy(ctx);
+            return st;
+        }
     }
     const char *ng = getenv("JET_NO_GRAPH");
     ctx->graphs = !(ng && ng[0] == '1');
@@ -4294,6 +4340,86 @@ extern "C" int jet_refine(jet_context *ctx, const jet_csr *g, const jet_params *
     int32_t cnt = 0, tot = 0;
     int st = refine_level(ctx, g, params, part, part_weights_out, stats, trace ? trace->recs : nullptr,
                           trace ? trace->cap : 0, &cnt, &tot, (hipStream_t)stream);
+    if (trace) {
+        trace->count = cnt;
+        trace->total = tot;
+    }
+    return st;
+}
+
+// Upper bound of the workspace jet_refine carves for one graph (each slot
+// rounded up to the 256-byte alignment of the bump allocation). Long rows
+// (> 1024 entries) number at most nnz / 1025, their chunks at most
+// nnz / 1024 + their count.
+static size_t noalloc_need(int64_t n, int64_t nnz, int64_t k, int64_t trace_cap, int num_cu)
+{
+    auto al = [](size_t b) { return (std::max(b, (size_t)16) + 255) & ~(size_t)255; };
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    const int64_t ntile = std::max<int64_t>(1, (n + TILE - 1) / TILE);
+    const int64_t grid_v = std::max<int64_t>(1, std::min<int64_t>((n + BLOCK - 1) / BLOCK, (int64_t)num_cu * 4));
+    const int64_t nL = nnz / (M_MAXDEG + 1), nch = nnz / LCHUNK + nL;  // bounds
+    size_t b = 0;
+    if (trace_cap > 0) b += al(sizeof(jet_trace_rec) * (size_t)trace_cap);
+    b += al(nn * 2) + al(nn * 8) + al(nn * 4) + al(nn * 4) + al(nn) + al(nn * 4) + al(nn) + al(nn * 4);
+    b += al(sizeof(int64_t) * NSTAT * NSHARD) + al(sizeof(int32_t) * (CNT_N + 2)) + al(sizeof(Ctl));
+    b += al(sizeof(int64_t) * (4 * (size_t)k + 9)) + al(sizeof(int32_t) * (3 * (size_t)k + 8)) + al(2 * (size_t)k + 16);
+    b += al(sizeof(int64_t) * (size_t)k * NSLOT) + al(sizeof(int32_t) * (size_t)(ntile * k)) + al(8 * (size_t)ntile);
+    b += al(KIND_LOG) + al(sizeof(int32_t) * (size_t)(grid_v + 1) * NCLS) + al(4 * (nn + 1));
+    if (nL > 0) b += al(8 * (size_t)nch) + al(4 * std::min((size_t)nch * (size_t)k, (size_t)128 << 20)) +
+                     al(8 * (size_t)nL);
+    return b;
+}
+
+extern "C" int jet_refine_noalloc(jet_context *ctx, const jet_csr *g, const jet_params *params, int32_t *part,
+                                  int64_t *part_weights_out, jet_stats *stats, jet_trace *trace, void *stream)
+{
+    if (!ctx || !g || !params || (!part && g->n > 0)) return JET_EINVAL;
+    int st = check_params(g, params);
+    if (st) return st;
+    if (params->k < 2 || (params->flags & (JET_F_VALIDATE | JET_F_PROFILE))) return JET_EINVAL;
+    if (!ctx->scratch) return JET_EHIP;
+    const int32_t tcap = trace && trace->recs ? std::max(trace->cap, 0) : 0;
+    if (noalloc_need(g->n, g->nnz, params->k, tcap, ctx->num_cu) > (size_t)JET_NOALLOC_SCRATCH_BYTES)
+        return JET_ELIMIT;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_status(ctx, e);
+    hipStream_t s = (hipStream_t)stream;
+    if (trace) {
+        trace->count = 0;
+        trace->total = 0;
+    }
+    if (g->n == 0) {
+        // nothing to refine: every part is empty
+        if (part_weights_out) JET_TRY(hipMemsetAsync(part_weights_out, 0, sizeof(int64_t) * params->k, s));
+        JET_TRY(stream_wait(ctx, s));
+        if (stats) {
+            memset(stats, 0, sizeof(*stats));
+            stats->balanced = 1;
+            stats->levels = 1;
+        }
+        return JET_OK;
+    }
+    // every workspace slot from the scratch array, iterations launched
+    // directly (no graph instantiation); restored on every return path
+    struct Mode {
+        jet_context *c;
+        bool graphs;
+        Mode(jet_context *cc) : c(cc), graphs(cc->graphs)
+        {
+            c->scratch_on = true;
+            c->scratch_off = 0;
+            c->graphs = false;
+        }
+        ~Mode()
+        {
+            c->scratch_on = false;
+            c->scratch_off = 0;
+            c->graphs = graphs;
+        }
+    } mode(ctx);
+    int32_t cnt = 0, tot = 0;
+    st = refine_level(ctx, g, params, part, part_weights_out, stats, trace ? trace->recs : nullptr,
+                      trace ? trace->cap : 0, &cnt, &tot, s);
     if (trace) {
         trace->count = cnt;
         trace->total = tot;

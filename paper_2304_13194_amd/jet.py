@@ -35,7 +35,7 @@ KIND_LP, KIND_RW, KIND_RS = 1, 2, 3
 # Every function declared in include/jet.h.
 EXPORTS = [
     "jet_context_create", "jet_context_destroy", "jet_strerror", "jet_last_hip_error",
-    "jet_refine", "jet_refine_batch", "jet_lp_step", "jet_rebalance_step", "jet_coarsen",
+    "jet_refine", "jet_refine_noalloc", "jet_refine_batch", "jet_lp_step", "jet_rebalance_step", "jet_coarsen",
     "jet_hierarchy_levels", "jet_hierarchy_level", "jet_hierarchy_free", "jet_partition",
     "jet_bfs_start", "jet_server_create", "jet_server_submit", "jet_server_poll", "jet_server_wait",
     "jet_server_info_get", "jet_server_destroy",
@@ -257,6 +257,31 @@ def refine(g: DeviceGraph, part: torch.Tensor, k: int, trace_cap=0, ctx=None, pa
     s = lib().jet_refine(ctx.h, C.byref(csr), C.byref(prm), _ptr(part), _ptr(pw), C.byref(st),
                          C.byref(tr) if tr is not None else None, _stream())
     _check(s, "jet_refine")
+    out = st.as_dict()
+    if tr is not None:
+        out["trace_total"] = tr.total
+    return out, _trace_list(arr, tr), pw
+
+
+# Size of the static workspace array of jet_refine_noalloc (bytes per GPU).
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def refine_noalloc(g: DeviceGraph, part: torch.Tensor, k: int, trace_cap=0, ctx=None, part_weights=False,
+                   **kw):
+    """jet_refine_noalloc: as ``refine``, with the library's workspace taken
+    from its static per-GPU scratch array (the call allocates nothing).
+    ``part_weights`` must then be a preallocated int64 device tensor of k
+    entries (or False); the trace buffer is host memory."""
+    ctx = ctx or default_context()
+    prm = make_params(k, **kw)
+    st = Stats()
+    arr, tr = _trace_buf(trace_cap)
+    pw = part_weights if isinstance(part_weights, torch.Tensor) else None
+    csr = g.csr()
+    s = lib().jet_refine_noalloc(ctx.h, C.byref(csr), C.byref(prm), _ptr(part), _ptr(pw), C.byref(st),
+                                 C.byref(tr) if tr is not None else None, _stream())
+    _check(s, "jet_refine_noalloc")
     out = st.as_dict()
     if tr is not None:
         out["trace_total"] = tr.total
