@@ -469,19 +469,23 @@ def serve_bench(J, jobs, graphs, budget_bytes, warmup, rates=(50, 100, 200, 500,
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     nmeas = len(jobs) - warmup
+    # one long-lived server for every rate, warmed by the first rate's
+    # unmeasured jobs (its lanes' workspaces and memory pools then hold what
+    # the mix needs, as the one-at-a-time context's do)
+    sv = J.Server(hbm_budget_bytes=budget_bytes, max_slots=64)
     out = {"workload": f"{nmeas} measured + {warmup} warm-up jobs per rate, each drawn on its own: half 2-D "
                        f"grids (side uniform in [64, 1024]), half R-MAT graphs (scale uniform in [12, 20], edge "
                        f"factor uniform in [8, 16], weights 1..16); k uniform in [2, 256], lambda 3%",
            "hbm_budget_bytes": budget_bytes,
            "graphs_per_s_one_at_a_time": len(jobs) / t_seq, "rates": []}
     identical = True
-    for ri, rate in enumerate(rates):
-        arr = I.arrivals(rate, len(jobs), 500 + ri)
-        outs = [torch.empty(dg.n, dtype=torch.int32, device="cuda") for dg in dgs]
-        torch.cuda.synchronize()
-        sv = J.Server(hbm_budget_bytes=budget_bytes, max_slots=64)
-        peak_inuse, held = 0, 0
-        try:
+    steps0 = jobs0 = 0
+    try:
+        for ri, rate in enumerate(rates):
+            arr = I.arrivals(rate, len(jobs), 500 + ri)
+            outs = [torch.empty(dg.n, dtype=torch.int32, device="cuda") for dg in dgs]
+            torch.cuda.synchronize()
+            peak_inuse, held = 0, 0
             tickets = []
             t0 = time.perf_counter()
             for dg, (_, k, seed), at, o in zip(dgs, jobs, arr, outs):
@@ -494,23 +498,31 @@ def serve_bench(J, jobs, graphs, budget_bytes, warmup, rates=(50, 100, 200, 500,
                 held = max(held, inf["queued"])
             res = [sv.wait(t, 600000) for t in tickets]
             info = sv.info()
-        finally:
-            sv.close()
-        m = res[warmup:]
-        lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in m])
-        qwait = np.array([r["t_admit_ms"] - r["t_submit_ms"] for r in m])
-        span = (max(r["t_done_ms"] for r in m) - min(r["t_submit_ms"] for r in m)) * 1e-3
-        ok = all(r["status"] == 0 and r["cut"] == c and torch.equal(o, p)
-                 for r, o, (p, c) in zip(res, outs, ref))
-        identical = identical and ok
-        out["rates"].append({"rate_jobs_per_s": rate, "p50_ms": float(np.percentile(lat, 50)),
-                             "p99_ms": float(np.percentile(lat, 99)), "graphs_per_s": len(m) / span,
-                             "p50_admission_wait_ms": float(np.percentile(qwait, 50)),
-                             "max_queued_seen": held, "max_hbm_in_use_seen": peak_inuse,
-                             "mean_jobs_per_step": info["step_jobs"] / max(info["steps"], 1),
-                             "steps": info["steps"]})
+            steps, sjobs = info["steps"] - steps0, info["step_jobs"] - jobs0
+            steps0, jobs0 = info["steps"], info["step_jobs"]
+            m = res[warmup:]
+            out["rates"].append(_rate_row(rate, m, res, outs, ref, peak_inuse, held, steps, sjobs))
+            identical = identical and out["rates"][-1].pop("_ok")
+    finally:
+        sv.close()
     out["identical_to_alone"] = bool(identical)
     return out
+
+
+def _rate_row(rate, m, res, outs, ref, peak_inuse, held, steps, sjobs):
+    """Latency and throughput of the measured jobs `m` of one arrival rate;
+    _ok: every job (warm-up included) equals its one-at-a-time result."""
+    import numpy as np
+    import torch
+    lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in m])
+    qwait = np.array([r["t_admit_ms"] - r["t_submit_ms"] for r in m])
+    span = (max(r["t_done_ms"] for r in m) - min(r["t_submit_ms"] for r in m)) * 1e-3
+    ok = all(r["status"] == 0 and r["cut"] == c and torch.equal(o, p) for r, o, (p, c) in zip(res, outs, ref))
+    return {"rate_jobs_per_s": rate, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "graphs_per_s": len(m) / span,
+            "p50_admission_wait_ms": float(np.percentile(qwait, 50)),
+            "max_queued_seen": held, "max_hbm_in_use_seen": peak_inuse,
+            "mean_jobs_per_step": sjobs / max(steps, 1), "steps": steps, "_ok": ok}
 
 
 def ablation_bench(J, dg, k, seed, label):
@@ -574,6 +586,7 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=100, help="measured jobs per arrival rate")
     ap.add_argument("--serve-warmup", type=int, default=20, help="unmeasured jobs before them")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="server HBM budget (GB)")
+    ap.add_argument("--serve-rates", default="50,100,200,500,1000,2000", help="arrival rates (jobs/s)")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--graph-cache", default=None,
                     help="directory: reuse generated main graphs across runs (.npz, no pickle)")
@@ -696,7 +709,8 @@ def main():
         say("serving")
         try:
             graphs = [f.result() for f in fut_srv]
-            out["serving"] = serve_bench(J, jobs, graphs, int(args.serve_budget_gb * 1e9), args.serve_warmup)
+            out["serving"] = serve_bench(J, jobs, graphs, int(args.serve_budget_gb * 1e9), args.serve_warmup,
+                                         rates=tuple(float(x) for x in args.serve_rates.split(",")))
             del graphs
         except Exception as e:
             out["serving"] = {"error": repr(e)}

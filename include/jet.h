@@ -16,7 +16,8 @@
  *    comment says (host). The caller owns them; the library never frees them.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). All
  *    device work is enqueued on it; calls return after the stream has
- *    finished the call's work (they synchronise it).
+ *    finished the call's work (they synchronise it), except jet_refine with
+ *    JET_F_ASYNC.
  *  - Status codes are returned as int; no exception crosses the ABI. On an
  *    error detected before any device work, `part` is untouched; after device
  *    work has started, `part` is unspecified.
@@ -25,9 +26,13 @@
  *    integers. Arithmetic is integer only: int32 weights, int64 cuts, gains
  *    and part weights. Results are deterministic and independent of thread
  *    scheduling: ties break by part id or vertex id, never by atomic order.
- *  - Limits: n < 2^31; the total vertex weight and the total edge weight
- *    (summed over both directions) must be below 2^31 (else JET_EOVERFLOW);
- *    1 <= k <= 16384.
+ *  - Limits: n < 2^31; 1 <= k <= 16384; the total vertex weight below 2^31
+ *    and every vertex's weighted degree (sum of its edge weights) below 2^31
+ *    (else JET_EOVERFLOW): connectivities, gains and losses, which that degree
+ *    bounds, are int32, while cuts and part weights are int64. Multilevel
+ *    calls (jet_coarsen, jet_partition, serving jobs) also need the total edge
+ *    weight (summed over both directions) below 2^31, because coarse edge
+ *    weights are sums of fine ones and are stored as int32.
  *  - One context per host thread, or external locking.
  */
 #ifndef JET_H
@@ -45,7 +50,7 @@ extern "C" {
 #define JET_EINVAL    (-1) /* bad parameter (k < 1, lambda < 0, c_den < 0, NULL pointer, ...) */
 #define JET_EGRAPH    (-2) /* malformed CSR (checked cheaply always, fully with JET_F_VALIDATE) */
 #define JET_EPART     (-3) /* a part id outside [0, k) */
-#define JET_EOVERFLOW (-4) /* total vertex or edge weight >= 2^31 */
+#define JET_EOVERFLOW (-4) /* a weight total or a weighted degree >= 2^31 (see Limits) */
 #define JET_ENOMEM    (-5) /* device or host allocation failed */
 #define JET_EHIP      (-6) /* HIP runtime error; jet_last_hip_error() has the code */
 #define JET_EAGAIN    (-7) /* serving: queue full, or the job is not done yet */
@@ -73,6 +78,17 @@ extern "C" {
  * graph from jet_bfs_start's graph-growing partition instead of the seeded
  * random one. */
 #define JET_F_BFS_START         0x40u
+/* jet_refine only: return without waiting for the refinement. The call still
+ * waits once for its set-up (checks, degree classes, which size the
+ * launches); it then enqueues max_iters iterations (max_iters > 0 is
+ * required; the device-side controller ends the loop, and iterations past
+ * the end exit at once), the result copies and a host function that fills
+ * `stats` and the trace (count, total, records) when the stream reaches it.
+ * `part`, part_weights_out, stats and the trace are valid once the stream
+ * has completed (hipStreamSynchronize on it); stats' ms_* fields are 0. The
+ * context must not be used again before that. JET_EINVAL with
+ * max_iters <= 0 or JET_F_PROFILE, and on every other entry point. */
+#define JET_F_ASYNC             0x80u
 
 typedef struct jet_context jet_context;
 typedef struct jet_hierarchy jet_hierarchy;

@@ -21,6 +21,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1003,14 +1004,13 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
 static int build_hierarchy(jet_context *ctx, const jet_csr *g, const jet_params *prm, jet_hierarchy *h,
                            hipStream_t s)
 {
-    static bool attr = false;
-    if (!attr) {
-        attr = true;
+    static std::once_flag attr;
+    std::call_once(attr, [] {
         (void)hipFuncSetAttribute((const void *)k_crow_medium<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   65536);
         (void)hipFuncSetAttribute((const void *)k_crow_medium<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   65536);
-    }
+    });
     h->device = ctx->device;
     h->lv.clear();
     h->maps.clear();
@@ -1256,7 +1256,7 @@ extern "C" int jet_partition(jet_context *ctx, const jet_csr *g, const jet_param
                              jet_stats *stats, jet_trace *trace, void *stream)
 {
     if (!ctx || !g || !params || (!part_out && g->n > 0)) return JET_EINVAL;
-    if (params->k < 1 || params->lambda_ppm < 0) return JET_EINVAL;
+    if (params->k < 1 || params->lambda_ppm < 0 || (params->flags & JET_F_ASYNC)) return JET_EINVAL;
     if (params->k > KMAX) return JET_ELIMIT;
     hipStream_t s = (hipStream_t)stream;
     JET_TRY(hipSetDevice(ctx->device));

@@ -178,7 +178,7 @@ enum WsSlot {
     WS_DBG_LOCK, WS_H0, WS_H1, WS_C0, WS_C1, WS_C2, WS_C3, WS_C4, WS_C5, WS_C6, WS_C7, WS_C8,
     WS_C9, WS_C10, WS_C11, WS_KINDS, WS_C12, WS_BLKCNT, WS_TG,
     WS_U_XADJ, WS_U_ADJ, WS_U_VW, WS_U_EW, WS_U_VG, WS_U_P0, WS_U_BEST, WS_U_DESC,
-    WS_LCNT, WS_LCH, WS_GCONN, WS_LDONE, WS_TH_KEY, WS_TH_VAL, WS_TH_RUN, WS_TH_TMP,
+    WS_LCNT, WS_LCH, WS_GCONN, WS_LDONE, WS_TH_KEY, WS_TH_VAL, WS_TH_RUN, WS_TH_TMP, WS_WDEG,
     WS_COUNT = 64
 };
 

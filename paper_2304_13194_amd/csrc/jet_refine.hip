@@ -349,6 +349,26 @@ __global__ __launch_bounds__(BLOCK) void k_init_edges(KArgs a, int64_t nnz)
     acc_finish(a, acc);
 }
 
+// Largest weighted degree (one wave per vertex, int64 sums): run only when a
+// graph's total edge weight reaches 2^31, to check that every vertex's
+// weighted degree, which bounds its connectivities, gains and losses, stays
+// below 2^31.
+__global__ __launch_bounds__(BLOCK) void k_wdeg_max(const int64_t *xadj, const int32_t *ew, int n,
+                                                    unsigned long long *out)
+{
+    const int lane = threadIdx.x & 63;
+    const int nw = gridDim.x * (BLOCK / 64);
+    int64_t best = 0;
+    for (int v = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); v < n; v += nw) {
+        const int64_t s = xadj[v], e = xadj[v + 1];
+        int64_t sum = 0;
+        for (int64_t i = s + lane; i < e; i += 64) sum += ew[i];
+        sum = gsum<64>(sum);
+        best = sum > best ? sum : best;
+    }
+    if (lane == 0 && best > 0) atomicMax(out, (unsigned long long)best);
+}
+
 // Per graph (one wave each): totals of the set-up counters into the controller.
 __global__ __launch_bounds__(64) void k_init_reduce(KArgs a)
 {
@@ -3013,7 +3033,9 @@ void *ws_get(jet_context *ctx, int slot, size_t bytes)
         b.ptr = nullptr;
         b.bytes = 0;
     }
-    size_t want = bytes + bytes / 8;  // headroom for the next, slightly larger level
+    // geometric growth: a context serving graphs of rising sizes reallocates
+    // a slot only a few times (every hipFree waits for the whole device)
+    size_t want = std::max(bytes + bytes / 8, b.bytes * 2);
     if (hipMalloc(&b.ptr, want) != hipSuccess) {
         (void)hipGetLastError();
         b.ptr = nullptr;
@@ -3410,16 +3432,19 @@ static void set_lds_limits_rows()
                               65536);
 }
 
+// Once per process, before any launch needing more than the default dynamic
+// LDS (call_once: serving lanes set up concurrently, and none may launch
+// before the limits are in place).
 static void set_lds_limits()
 {
-    static bool done = false;
-    if (done) return;
-    done = true;
-    set_lds_limits_t<false>();
-    set_lds_limits_t<true>();
-    set_lds_limits_rows<false>();
-    set_lds_limits_rows<true>();
-    (void)hipFuncSetAttribute((const void *)k_init_vertices, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    static std::once_flag once;
+    std::call_once(once, [] {
+        set_lds_limits_t<false>();
+        set_lds_limits_t<true>();
+        set_lds_limits_rows<false>();
+        set_lds_limits_rows<true>();
+        (void)hipFuncSetAttribute((const void *)k_init_vertices, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    });
 }
 
 static int check_params(const jet_csr *g, const jet_params *prm)
@@ -3619,8 +3644,26 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     if (xends[0] != 0 || xends[1] != L.u.nnz || hcnt[1]) return JET_EGRAPH;
     for (int g = 0; g < G; g++)
         if (hcs[g].bad_part) return JET_EPART;
-    for (int g = 0; g < G; g++)
-        if (hcs[g].wsum >= ((int64_t)1 << 31) || hcs[g].ewsum >= ((int64_t)1 << 31)) return JET_EOVERFLOW;
+    // limits: total vertex weight below 2^31 (part weights, tile sums), and
+    // every weighted degree below 2^31 (connectivities, gains, losses are
+    // int32); the exact degree check runs only when the total edge weight
+    // does not already bound them
+    bool wide = false;
+    for (int g = 0; g < G; g++) {
+        if (hcs[g].wsum >= ((int64_t)1 << 31)) return JET_EOVERFLOW;
+        if (hcs[g].ewsum >= ((int64_t)1 << 31)) wide = true;
+    }
+    if (wide && L.u.adjwgt) {
+        unsigned long long *dmax = (unsigned long long *)ws_get(ctx, WS_WDEG, 16);
+        if (!dmax) return JET_ENOMEM;
+        JET_TRY(hipMemsetAsync(dmax, 0, 8, s));
+        k_wdeg_max<<<std::max(1, std::min(div_up(n, BLOCK / 64), ctx->num_cu * 8)), BLOCK, 0, s>>>(
+            L.u.xadj, L.u.adjwgt, n, dmax);
+        JET_TRY(hipGetLastError());
+        JET_TRY(hipMemcpyAsync(pin + 256, dmax, 8, hipMemcpyDeviceToHost, s));
+        JET_TRY(stream_wait(ctx, s));
+        if (*(const uint64_t *)(pin + 256) >= ((uint64_t)1 << 31)) return JET_EOVERFLOW;
+    }
     for (int g = 0; g < G; g++) {
         Ctl &c = hcs[g];
         c.W = c.wsum;
@@ -3764,8 +3807,21 @@ static int next_chunk(bool single, const Ctl &c0, int chunk)
     return std::min(chunk * 2, 32);
 }
 
-static int run_loop(jet_context *ctx, Plan &pl, bool prof, hipStream_t s, int &launched, const Ctl *single_ctl)
+static int run_loop(jet_context *ctx, Plan &pl, bool prof, hipStream_t s, int &launched, const Ctl *single_ctl,
+                    int async_iters = 0)
 {
+    if (async_iters > 0) {
+        // JET_F_ASYNC: every iteration up to the cap is enqueued without a
+        // look at the loop state; the controller ends the loop on the device
+        // and later launches exit at once
+        for (int i = 0; i < async_iters; i++) {
+            set_it(pl, i);
+            launch_iteration(pl, s);
+        }
+        launched = async_iters;
+        JET_TRY(hipGetLastError());
+        return JET_OK;
+    }
     static_assert(64 + sizeof(Ctl) <= 4096, "pinned scratch holds the done count and one controller");
     int32_t *pin = (int32_t *)pinned_get(ctx, 4096);
     if (!pin) return JET_ENOMEM;
@@ -3927,6 +3983,30 @@ static void single_launch(Launch &L, const jet_csr *g, const jet_params *prm, in
     c.trace_cap = trace_dev ? trace_cap : 0;
 }
 
+// Results of a JET_F_ASYNC refinement, filled in by a host function the
+// stream runs after the call's last copy (no HIP call inside).
+struct AsyncDone {
+    const Ctl *ctl;                     // final controller state (pinned staging)
+    const jet_trace_rec *trace_stage;   // trace records (pinned staging)
+    jet_stats *stats;
+    jet_trace_rec *trace_host;
+    int32_t trace_cap;
+    int32_t *trace_count, *trace_total;
+    bool ret_iter;
+};
+
+static void async_done(void *p)
+{
+    AsyncDone *d = (AsyncDone *)p;
+    const Ctl &c = *d->ctl;
+    if (d->stats) fill_stats(d->stats, c, d->ret_iter);
+    const int ntr = std::min(c.t, c.trace_cap);
+    if (d->trace_host && ntr > 0) memcpy(d->trace_host, d->trace_stage, sizeof(jet_trace_rec) * (size_t)ntr);
+    if (d->trace_count) *d->trace_count = ntr;
+    if (d->trace_total) *d->trace_total = c.t;
+    delete d;
+}
+
 int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int32_t *part,
                  int64_t *part_weights_out, jet_stats *stats, jet_trace_rec *trace_host, int32_t trace_cap,
                  int32_t *trace_count, int32_t *trace_total, hipStream_t s)
@@ -3934,9 +4014,16 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     int st = check_params(g, prm);
     if (st) return st;
     const int n = g->n, k = prm->k;
+    const bool async = prm->flags & JET_F_ASYNC;
+    if (async && (prm->max_iters <= 0 || (prm->flags & JET_F_PROFILE))) return JET_EINVAL;
     if (trace_count) *trace_count = 0;
     if (trace_total) *trace_total = 0;
     if (k == 1 || n == 0) return refine_trivial(ctx, g, prm, part, part_weights_out, stats, s);
+    // the staging of an asynchronous call's results is sized before any
+    // copy into it is enqueued (growing it later would free it under them)
+    const size_t stage_off = (4096 + sizeof(Ctl) + 63) & ~(size_t)63;
+    if (async && !pinned_get(ctx, stage_off + sizeof(jet_trace_rec) * (size_t)std::max(trace_cap, 0)))
+        return JET_ENOMEM;
     if (prm->flags & JET_F_VALIDATE) {
         st = validate_full_csr(ctx, g, s);
         if (st) return st;
@@ -3955,7 +4042,7 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     JET_TRY(hipEventRecord(ctx->ev[1], s));
     const bool prof = prm->flags & JET_F_PROFILE;
     int launched = 0;
-    st = run_loop(ctx, pl, prof, s, launched, &L.hc[0]);
+    st = run_loop(ctx, pl, prof, s, launched, &L.hc[0], async ? prm->max_iters : 0);
     if (st) return st;
     k_copy_best<<<pl.grid_flat, BLOCK, 0, s>>>(pl.plain);
     JET_TRY(hipEventRecord(ctx->ev[2], s));
@@ -3966,6 +4053,24 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
                                sizeof(int64_t) * k, hipMemcpyDeviceToDevice, s));
     st = read_state(ctx, L, pl, s);
     if (st) return st;
+    if (async) {
+        // results land in pinned staging; a host function on the stream hands
+        // them to the caller once everything before it has run
+        char *pin = (char *)ctx->pinned;
+        jet_trace_rec *stage = (jet_trace_rec *)(pin + stage_off);
+        const int ncopy = std::min(launched, L.hc[0].trace_cap);
+        if (trace_dev && ncopy > 0)
+            JET_TRY(hipMemcpyAsync(stage, trace_dev, sizeof(jet_trace_rec) * ncopy, hipMemcpyDeviceToHost, s));
+        AsyncDone *d = new (std::nothrow) AsyncDone{(const Ctl *)(pin + 4096), stage, stats, trace_host, trace_cap,
+                                                    trace_count, trace_total, (prm->flags & JET_F_RETURN_ITER) != 0};
+        if (!d) return JET_ENOMEM;
+        const hipError_t e = hipLaunchHostFunc(s, async_done, d);
+        if (e != hipSuccess) {
+            delete d;
+            return hip_status(ctx, e);
+        }
+        return JET_OK;
+    }
     // records exist for the iterations run, at most one per launched iteration
     const int ncopy = std::min(launched, L.hc[0].trace_cap);
     if (trace_dev && ncopy > 0)
@@ -4025,6 +4130,7 @@ int refine_batch(jet_context *ctx, int count, const jet_csr *graphs, const jet_p
         if (st) return st;
         if (graphs[i].n > 0 && !parts[i]) return JET_EINVAL;
         if (traces && traces[i].cap > 0 && !traces[i].recs) return JET_EINVAL;
+        if (params[i].flags & JET_F_ASYNC) return JET_EINVAL;
     }
     for (int i = 0; i < count; i++)
         if (params[i].flags & JET_F_VALIDATE) {
@@ -4322,7 +4428,7 @@ extern "C" const char *jet_strerror(int status)
     case JET_EINVAL: return "invalid parameter";
     case JET_EGRAPH: return "malformed CSR graph";
     case JET_EPART: return "part id out of range";
-    case JET_EOVERFLOW: return "total vertex or edge weight too large (>= 2^31)";
+    case JET_EOVERFLOW: return "weight too large (total vertex weight or a weighted degree >= 2^31)";
     case JET_ENOMEM: return "out of memory";
     case JET_EHIP: return "HIP runtime error";
     case JET_EAGAIN: return "try again";
@@ -4337,14 +4443,11 @@ extern "C" int jet_refine(jet_context *ctx, const jet_csr *g, const jet_params *
     if (!ctx || !g || !params || (!part && g->n > 0)) return JET_EINVAL;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_status(ctx, e);
-    int32_t cnt = 0, tot = 0;
-    int st = refine_level(ctx, g, params, part, part_weights_out, stats, trace ? trace->recs : nullptr,
-                          trace ? trace->cap : 0, &cnt, &tot, (hipStream_t)stream);
-    if (trace) {
-        trace->count = cnt;
-        trace->total = tot;
-    }
-    return st;
+    // the trace counts are written by the call (or, with JET_F_ASYNC, by the
+    // host function that completes it on the stream)
+    return refine_level(ctx, g, params, part, part_weights_out, stats, trace ? trace->recs : nullptr,
+                        trace ? trace->cap : 0, trace ? &trace->count : nullptr, trace ? &trace->total : nullptr,
+                        (hipStream_t)stream);
 }
 
 // Upper bound of the workspace jet_refine carves for one graph (each slot
@@ -4364,7 +4467,7 @@ static size_t noalloc_need(int64_t n, int64_t nnz, int64_t k, int64_t trace_cap,
     b += al(sizeof(int64_t) * NSTAT * NSHARD) + al(sizeof(int32_t) * (CNT_N + 2)) + al(sizeof(Ctl));
     b += al(sizeof(int64_t) * (4 * (size_t)k + 9)) + al(sizeof(int32_t) * (3 * (size_t)k + 8)) + al(2 * (size_t)k + 16);
     b += al(sizeof(int64_t) * (size_t)k * NSLOT) + al(sizeof(int32_t) * (size_t)(ntile * k)) + al(8 * (size_t)ntile);
-    b += al(KIND_LOG) + al(sizeof(int32_t) * (size_t)(grid_v + 1) * NCLS) + al(4 * (nn + 1));
+    b += al(KIND_LOG) + al(sizeof(int32_t) * (size_t)(grid_v + 1) * NCLS) + al(4 * (nn + 1)) + al(16);
     if (nL > 0) b += al(8 * (size_t)nch) + al(4 * std::min((size_t)nch * (size_t)k, (size_t)128 << 20)) +
                      al(8 * (size_t)nL);
     return b;
@@ -4376,7 +4479,7 @@ extern "C" int jet_refine_noalloc(jet_context *ctx, const jet_csr *g, const jet_
     if (!ctx || !g || !params || (!part && g->n > 0)) return JET_EINVAL;
     int st = check_params(g, params);
     if (st) return st;
-    if (params->k < 2 || (params->flags & (JET_F_VALIDATE | JET_F_PROFILE))) return JET_EINVAL;
+    if (params->k < 2 || (params->flags & (JET_F_VALIDATE | JET_F_PROFILE | JET_F_ASYNC))) return JET_EINVAL;
     if (!ctx->scratch) return JET_EHIP;
     const int32_t tcap = trace && trace->recs ? std::max(trace->cap, 0) : 0;
     if (noalloc_need(g->n, g->nnz, params->k, tcap, ctx->num_cu) > (size_t)JET_NOALLOC_SCRATCH_BYTES)

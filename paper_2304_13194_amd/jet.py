@@ -30,6 +30,7 @@ JET_F_LP_NO_LOCKS = 0x8
 JET_F_LP_NO_AFTERBURNER = 0x10
 JET_F_TWO_HOP = 0x20
 JET_F_BFS_START = 0x40
+JET_F_ASYNC = 0x80
 KIND_LP, KIND_RW, KIND_RS = 1, 2, 3
 
 # Every function declared in include/jet.h.
@@ -261,6 +262,39 @@ def refine(g: DeviceGraph, part: torch.Tensor, k: int, trace_cap=0, ctx=None, pa
     if tr is not None:
         out["trace_total"] = tr.total
     return out, _trace_list(arr, tr), pw
+
+
+class AsyncRefine:
+    """Handle of a jet_refine call made with JET_F_ASYNC: keeps the host
+    buffers the library completes from the stream alive until ``wait``."""
+
+    def __init__(self, st, arr, tr, pw, stream):
+        self._st, self._arr, self._tr, self._pw, self._stream = st, arr, tr, pw, stream
+
+    def wait(self):
+        """Synchronises the call's stream; returns (stats, trace, part weights)."""
+        self._stream.synchronize()
+        out = self._st.as_dict()
+        if self._tr is not None:
+            out["trace_total"] = self._tr.total
+        return out, _trace_list(self._arr, self._tr), self._pw
+
+
+def refine_async(g: DeviceGraph, part: torch.Tensor, k: int, max_iters: int, trace_cap=0, ctx=None,
+                 part_weights=False, flags=0, **kw) -> AsyncRefine:
+    """jet_refine with JET_F_ASYNC: returns once the iterations are enqueued
+    on torch's current stream."""
+    ctx = ctx or default_context()
+    prm = make_params(k, max_iters=max_iters, flags=flags | JET_F_ASYNC, **kw)
+    st = Stats()
+    arr, tr = _trace_buf(trace_cap)
+    pw = torch.empty(k, dtype=torch.int64, device=part.device) if part_weights else None
+    csr = g.csr()
+    stream = torch.cuda.current_stream()
+    s = lib().jet_refine(ctx.h, C.byref(csr), C.byref(prm), _ptr(part), _ptr(pw), C.byref(st),
+                         C.byref(tr) if tr is not None else None, C.c_void_p(stream.cuda_stream))
+    _check(s, "jet_refine (asynchronous)")
+    return AsyncRefine(st, arr, tr, pw, stream)
 
 
 # Size of the static workspace array of jet_refine_noalloc (bytes per GPU).

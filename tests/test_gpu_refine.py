@@ -339,3 +339,102 @@ def test_refine_large_mesh_split_launch(J, O, weights):
         assert a == b, f"{weights}: gpu {a} != oracle {b}"
     np.testing.assert_array_equal(part.cpu().numpy(), exp.part)
     assert st["cut"] == exp.cut and st["max_part_weight"] == exp.maxw
+
+
+def _heavy(g, seed, lo=1 << 24, hi=1 << 25):
+    """g with symmetric edge weights drawn from [lo, hi): its total edge weight
+    is far above 2^31 while every weighted degree stays below it."""
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.xadj))
+    keep = src < g.adjncy
+    u, v = src[keep], g.adjncy[keep].astype(np.int64)
+    w = (lo + I.uniform_below(I.stream(seed, np.arange(u.size, dtype=np.uint64)), hi - lo)).astype(np.int32)
+    return I.csr_from_edges(g.n, u, v, w)
+
+
+def test_refine_large_total_edge_weight(J, O):
+    """Single-level refinement only needs every weighted degree below 2^31
+    (connectivities, gains, losses are int32; cuts and part weights int64):
+    a grid whose total edge weight is about 2^36 matches the oracle (int64
+    throughout) step by step, loop by loop and in a batch; a vertex whose
+    weighted degree reaches 2^31 is rejected, and multilevel partitioning
+    keeps the total-weight limit (coarse edge weights are int32 sums)."""
+    import torch
+    g = _heavy(I.grid2d(48, 48), 31)
+    total = int(g.adjwgt.astype(np.int64).sum())
+    wdeg = np.add.reduceat(g.adjwgt.astype(np.int64), g.xadj[:-1])
+    assert total >= 2 ** 31 and int(wdeg.max()) < 2 ** 31
+    k = 4
+    _compare_refine(J, O, g, k, I.random_partition(g.n, k, 41), "heavy_random", seed=3)
+    _compare_refine(J, O, g, k, _skewed(g, k, 42), "heavy_skewed", seed=4)
+    dg = J.to_device(g)
+    P = I.random_partition(g.n, k, 43)
+    L = _locks(g.n, 44)
+    exp = O.jetlp(g, P, L, k)
+    got = J.lp_step(dg, torch.from_numpy(P).cuda(), torch.from_numpy(L).cuda(), k)
+    for key in ("pd", "F", "conn_s", "F2"):
+        np.testing.assert_array_equal(got[key].cpu().numpy(), exp[key], err_msg=key)
+    S = _skewed(g, k, 45)
+    for kind in (J.KIND_RW, J.KIND_RS):
+        exp = O.rebalance(g, S, kind, 1, k, seed=5)
+        got = J.rebalance_step(dg, torch.from_numpy(S).cuda(), kind, 1, k, seed=5)
+        for key in ("dest", "loss", "slot"):
+            np.testing.assert_array_equal(got[key].cpu().numpy(), exp[key], err_msg=f"{kind} {key}")
+    # in a batch with a second heavy graph: each equals its oracle run
+    g2 = _heavy(I.grid2d(40, 56), 32)
+    graphs = [g, g2]
+    p0 = [I.random_partition(x.n, k, 46 + i) for i, x in enumerate(graphs)]
+    parts = [torch.from_numpy(p.copy()).cuda() for p in p0]
+    stats, _ = J.refine_batch([J.to_device(x) for x in graphs], parts, [dict(k=k, seed=6)] * 2)
+    for x, p, q, st in zip(graphs, p0, parts, stats):
+        e = O.refine(x, p, k, seed=6)
+        np.testing.assert_array_equal(q.cpu().numpy(), e.part)
+        assert st["cut"] == e.cut and st["cut"] >= 2 ** 31
+    # a weighted degree of 2^31 or more: rejected before any refinement
+    star3 = I.csr_from_edges(4, np.zeros(3, np.int64), np.arange(1, 4), np.full(3, 2 ** 30, np.int32))
+    p = torch.zeros(4, dtype=torch.int32, device="cuda")
+    with pytest.raises(J.JetError) as e:
+        J.refine(J.to_device(star3), p, 2)
+    assert e.value.status == J.JET_EOVERFLOW
+    with pytest.raises(J.JetError) as e:
+        J.partition(dg, k)
+    assert e.value.status == J.JET_EOVERFLOW
+
+
+def test_refine_async(J, O):
+    """JET_F_ASYNC: the call returns once the iterations are enqueued; after
+    the stream completes, partition, part weights, stats and every trace
+    record equal the blocking call's (and the oracle's)."""
+    import torch
+    g = I.rmat(13, 12, 22)
+    k = 24
+    dg = J.to_device(g)
+    P0 = I.random_partition(g.n, k, 51)
+    a = torch.from_numpy(P0.copy()).cuda()
+    st_a, tr_a, pw_a = J.refine(dg, a, k, seed=7, trace_cap=1000, part_weights=True, max_iters=300)
+    b = torch.from_numpy(P0.copy()).cuda()
+    h = J.refine_async(dg, b, k, 300, seed=7, trace_cap=1000, part_weights=True)
+    st_b, tr_b, pw_b = h.wait()
+    assert torch.equal(a, b) and torch.equal(pw_a, pw_b)
+    assert tr_a == tr_b and len(tr_b) == st_b["iters"] == st_b["trace_total"]
+    for key in ("cut", "max_part_weight", "o", "sigma", "balanced", "iters", "lp_iters", "rw_iters", "rs_iters"):
+        assert st_a[key] == st_b[key], key
+    exp = O.refine(g, P0, k, seed=7, max_iters=300)
+    np.testing.assert_array_equal(b.cpu().numpy(), exp.part)
+    assert tr_b == exp.trace
+    # a cap below the natural end: the loop stops at the cap, as blocking
+    c = torch.from_numpy(P0.copy()).cuda()
+    st_c, tr_c, _ = J.refine_async(dg, c, k, 5, seed=7, trace_cap=1000).wait()
+    exp5 = O.refine(g, P0, k, seed=7, max_iters=5)
+    assert st_c["iters"] == 5 and tr_c == exp5.trace
+    np.testing.assert_array_equal(c.cpu().numpy(), exp5.part)
+    # rejected: no cap, with profiling, and on the multilevel and batch calls
+    for kw in (dict(max_iters=0), dict(max_iters=10, flags=J.JET_F_PROFILE)):
+        with pytest.raises(J.JetError) as e:
+            J.refine(dg, torch.from_numpy(P0.copy()).cuda(), k, flags=J.JET_F_ASYNC | kw.pop("flags", 0), **kw)
+        assert e.value.status == J.JET_EINVAL
+    with pytest.raises(J.JetError) as e:
+        J.partition(dg, k, flags=J.JET_F_ASYNC, max_iters=10)
+    assert e.value.status == J.JET_EINVAL
+    with pytest.raises(J.JetError) as e:
+        J.refine_batch([dg], [torch.from_numpy(P0.copy()).cuda()], [dict(k=k, flags=J.JET_F_ASYNC, max_iters=10)])
+    assert e.value.status == J.JET_EINVAL

@@ -61,12 +61,21 @@ def _serve(J, jobs, dgs, slots, budget=0, stagger_s=0.0):
         parts = [torch.full((dg.n,), -1, dtype=torch.int32, device="cuda") for dg in dgs]
         torch.cuda.synchronize()
         tickets = []
+        seen = dict(max_queued=0, max_in_use=0)
         for i, ((name, g, unit, k, seed), dg) in enumerate(zip(jobs, dgs)):
             tickets.append(sv.submit(dg, parts[i], k, seed=seed))
+            inf = sv.info()
+            seen["max_queued"] = max(seen["max_queued"], inf["queued"])
+            seen["max_in_use"] = max(seen["max_in_use"], inf["hbm_in_use"])
             if stagger_s and i % 3 == 2:
                 time.sleep(stagger_s)
-        res = [sv.wait(t, 120000) for t in tickets]
+        res = []
+        for t in tickets:
+            res.append(sv.wait(t, 120000))
+            inf = sv.info()
+            seen["max_in_use"] = max(seen["max_in_use"], inf["hbm_in_use"])
         info = sv.info()
+        info.update(seen)
     finally:
         sv.close()
     return [p.cpu().numpy() for p in parts], res, info
@@ -102,6 +111,11 @@ def test_server_budget_admission(J):
     for (name, *_), p, r, (pa, sa) in zip(jobs, parts, res, alone):
         assert r["status"] == 0, name
         np.testing.assert_array_equal(p, pa, err_msg=name)
+    # the budget binds: jobs were held back in the queue, admitted later than
+    # submitted, and the footprint in use never exceeded the budget
+    assert info["max_queued"] > 0
+    assert any(r["t_admit_ms"] > r["t_submit_ms"] for r in res)
+    assert 0 < info["max_in_use"] <= budget and info["hbm_in_use"] == 0
     import torch
     sv = J.Server(hbm_budget_bytes=min(fp) - 1, max_slots=2)
     try:
