@@ -538,7 +538,9 @@ def ablation_bench(J, dg, k, seed, label):
                 ("full Jetlp, phi 0.99", dict(phi=(99, 100))),
                 ("full Jetlp, phi 0.9999", dict(phi=(9999, 10000))),
                 ("full Jetlp, two-hop coarsening", dict(flags=J.JET_F_TWO_HOP)),
-                ("full Jetlp, graph-growing start", dict(flags=J.JET_F_BFS_START))]
+                ("full Jetlp, graph-growing start", dict(flags=J.JET_F_BFS_START)),
+                ("full Jetlp, persistent connectivity table (Section 4.3, Algorithm 6)",
+                 dict(flags=J.JET_F_CONN_TABLE))]
     rows = []
     for name, kw in variants:
         J.partition(dg, k, seed=seed, **kw)

@@ -89,6 +89,19 @@ extern "C" {
  * context must not be used again before that. JET_EINVAL with
  * max_iters <= 0 or JET_F_PROFILE, and on every other entry point. */
 #define JET_F_ASYNC             0x80u
+/* Single-graph refinement (jet_refine, jet_partition, steps, serving jobs on
+ * their own lane; batches ignore it): keep Section 4.3's persistent
+ * vertex-part connectivity structure instead of rebuilding connectivity
+ * in LDS on every pass. Row v owns min(k, deg v) slots of (part, count),
+ * hashed by part and sized a little above the parts v touches; after each
+ * iteration the moves update the rows of their neighbours (Algorithm 6:
+ * decrement the source part, then increment the destination part,
+ * inserting it; a row without a free slot is rebuilt larger), or, when more
+ * than a tenth of the vertices moved, every row is rebuilt. Gains and
+ * losses then scan rows. Results are identical to the default (maxima are
+ * taken on (count, part) keys); only speed and memory differ:
+ * 8 (n + 1) + 8 sum_v min(k, deg v) + 12 n bytes. */
+#define JET_F_CONN_TABLE        0x100u
 
 typedef struct jet_context jet_context;
 typedef struct jet_hierarchy jet_hierarchy;
@@ -145,6 +158,10 @@ typedef struct {
     float ms_gain;
     int32_t gain_passes;
     int64_t gain_entries, gain_rows, gain_vertices;
+    /* jet_refine_batch: the autotuner's choice for the batch (how waves walk
+     * the vertex lists: 0 = static stretches, else work-queue tiles of that
+     * many visits of a wave; small-row group width, 4 or 8 lanes). */
+    int32_t batch_tile, batch_group;
 } jet_stats;
 
 /* One record per refinement iteration (written when a trace is passed). */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
 #include <vector>
 
 #include "../../include/jet.h"
@@ -33,7 +34,7 @@ constexpr int M_MAXDEG = 1024;
 // Launch-wide counts: CNT_DONE graphs finished; then two rows (selected by
 // the parity of the iteration's launch index) of [graphs whose previous
 // iteration improved the best and that go on, graphs in Jetlp, Jetrw, Jetrs].
-enum Cnt { CNT_DONE = 0, CNT_ROW = 2, CNT_N = 10 };
+enum Cnt { CNT_DONE = 0, CNT_ROW = 2, CNT_N = 10, CNT_TFAIL = 11 };
 
 // Device-resident state of one graph's refinement (one per graph of a batch).
 struct Ctl {
@@ -110,6 +111,16 @@ struct KArgs {
     int32_t *gconn;        // [chunk][lstride] part counts of each chunk of a row of several chunks
     int32_t *ldone;        // [L list] chunks of the vertex completed in this pass
     int32_t *gf2;          // [L list] afterburner sum over a vertex's chunks
+    // persistent connectivity table (one graph; toff NULL when off)
+    const int64_t *toff;   // [n+1] first slot of each vertex's row; row v has min(k, deg v) slots
+    unsigned long long *tab;  // slots: (count << 32) | part, or TAB_EMPTY
+    int32_t *tsize;        // [n] slots of row v in use (its hash modulus)
+    int32_t *tfail;        // [n] 1 while row v waits for its rebuild
+    int32_t *tlist;        // rows to rebuild after this iteration's moves (count at cnt[CNT_TFAIL])
+    // batch work queue: counters [2][NQ] (bank = launch parity); wtile visits
+    // of a wave per tile (0: static walks)
+    int32_t *wq;
+    int32_t wtile;
     // optional step outputs
     int64_t *dbg_F, *dbg_cs, *dbg_F2, *dbg_loss;
     int32_t *dbg_pd;
@@ -168,6 +179,8 @@ struct jet_context {
     char *scratch = nullptr;
     size_t scratch_off = 0;
     bool scratch_on = false;
+    // batch autotuner: chosen walk (tile | group-of-8 << 16) per batch shape
+    std::vector<std::pair<uint64_t, int>> tune_cache;
 };
 
 namespace jet {
@@ -179,8 +192,11 @@ enum WsSlot {
     WS_C9, WS_C10, WS_C11, WS_KINDS, WS_C12, WS_BLKCNT, WS_TG,
     WS_U_XADJ, WS_U_ADJ, WS_U_VW, WS_U_EW, WS_U_VG, WS_U_P0, WS_U_BEST, WS_U_DESC,
     WS_LCNT, WS_LCH, WS_GCONN, WS_LDONE, WS_TH_KEY, WS_TH_VAL, WS_TH_RUN, WS_TH_TMP, WS_WDEG,
-    WS_COUNT = 64
+    WS_TOFF, WS_TAB, WS_TSIZE, WS_TFAIL, WS_TLIST, WS_TBLK, WS_WQ, WS_TUNE_CTL, WS_TUNE_CNT, WS_TUNE_REC,
+    WS_TUNE_STAT,
+    WS_COUNT = 80
 };
+static_assert(WS_TUNE_STAT < WS_COUNT, "workspace slots");
 
 // Grow-only workspace slot; returns nullptr on allocation failure.
 void *ws_get(jet_context *ctx, int slot, size_t bytes);

@@ -185,7 +185,24 @@ __device__ void acc_finish(const KArgs &a, Acc &acc)
 // one contiguous stretch, so its vertices fall in few graphs.
 struct Walk {
     int first, end, step;
+    int32_t *wq = nullptr;  // batch work queue counter (NULL: static walk)
+    int tile = 0;           // entries per tile
 };
+
+// Work-queue slots of the batch row kernels (one queue per kernel and
+// class, two banks selected by the iteration's launch parity; the controller
+// clears the next iteration's bank). (Per-XCD sub-queues over contiguous
+// eighths of a list, with stealing, measured slower than one counter.)
+enum WqSlot {
+    WQ_GAIN = 0,     // + small class (1, 2)
+    WQ_GAIN2 = 3,    // + class of the wave role (1..4)
+    WQ_LOSS = 8,     // + small class
+    WQ_LOSS2 = 11,   // + class of the wave role
+    WQ_AFTER_S = 16, WQ_AFTER_M = 17, WQ_DCUT_S = 18, WQ_DCUT_M = 19,
+    NQ = 20
+};
+constexpr int NQC = NQ;  // counters per bank
+static_assert(NQC <= BLOCK, "the controller's block clears a bank in one pass");
 
 // Blocks are dispatched to the 8 XCDs round robin (block b on XCD b mod 8).
 // Renumbered so that the blocks of one XCD form a contiguous range, its
@@ -216,6 +233,25 @@ __device__ __forceinline__ Walk walk(int cnt, int worker, int nworkers, int unit
         w.step = unit;
     }
     return w;
+}
+
+// Walk of a batch row kernel: with a work queue, waves take tiles of
+// wtile * unit list entries from the slot's counter until the list is
+// exhausted (load balance across graphs and degree mixes); otherwise the
+// static walk.
+template <bool B>
+__device__ __forceinline__ Walk walk_q(const KArgs &a, int cnt, int worker, int nworkers, int unit, int slot)
+{
+    if (B && a.wq && a.wtile > 0) {
+        Walk w;
+        w.first = 0;
+        w.end = cnt;
+        w.step = unit;
+        w.wq = a.wq + (a.it & 1) * NQC + slot;
+        w.tile = a.wtile * unit;
+        return w;
+    }
+    return walk<B>(cnt, worker, nworkers, unit);
 }
 
 // Contiguous range [lo, hi) of `cnt` items for block `b` of `nb`.
@@ -624,6 +660,11 @@ __global__ __launch_bounds__(BLOCK) void k_ctl_end(KArgs a)
     // this launch's count row has been read by every kernel of the iteration:
     // clear it for the iteration after next
     if (blockIdx.x == 0 && threadIdx.x < 4) a.cnt[CNT_ROW + (a.it & 1) * 4 + threadIdx.x] = 0;
+    // the connectivity rows listed for rebuilding were rebuilt by now
+    if (blockIdx.x == 0 && threadIdx.x == 4) a.cnt[CNT_TFAIL] = 0;
+    // the next iteration's work-queue counters (its bank was last used two
+    // iterations ago)
+    if (a.wq && blockIdx.x == 0 && threadIdx.x < NQC) a.wq[((a.it + 1) & 1) * NQC + threadIdx.x] = 0;
     const int g = blockIdx.x;
     Ctl *c = a.ctl + g;
     // thread 0 fetches the whole state while the block reads the part
@@ -921,16 +962,31 @@ struct Meta {
     int64_t s;
 };
 
+// Next tile [lo, hi) of a queued walk: lane 0 takes it, the wave shares it
+// (lo >= hi once the list is exhausted).
+__device__ __forceinline__ void walk_grab(const Walk &w, int &lo, int &hi)
+{
+    int b = 0;
+    if ((threadIdx.x & 63) == 0) b = atomicAdd(w.wq, w.tile);
+    b = __shfl(b, 0, 64);
+    lo = b < w.end ? b : w.end;
+    hi = b + w.tile < w.end ? b + w.tile : w.end;
+}
+
 template <int G, class Pre, class Row>
 __device__ __forceinline__ void wave_batched(const int32_t *list, Walk w, int32_t *q, Pre pre, Row row,
                                              int unit = 64)
 {
     const int lane = threadIdx.x & 63, grp = lane / G, gl = lane & (G - 1);
-    for (int base = w.first; base < w.end; base += w.step) {
+    int lo = w.first, hi = w.end;
+    if (w.wq) walk_grab(w, lo, hi);
+    for (;;) {
+    if (lo >= hi) break;
+    for (int base = lo; base < hi; base += w.step) {
         const int i = base + lane;
         Meta m{0, 0, 0, 0, 0, 0};
         bool act = false;
-        if (lane < unit && i < w.end) {
+        if (lane < unit && i < hi) {
             m.v = list ? list[i] : i;  // no list: entry i is vertex i
             act = pre(m);
         }
@@ -952,6 +1008,10 @@ __device__ __forceinline__ void wave_batched(const int32_t *list, Walk w, int32_
             if (has) row(t, gl);
         }
         lds_fence_wave();
+    }
+    if (!w.wq) break;
+    walk_grab(w, lo, hi);
+    if (lo >= hi) break;
     }
 }
 
@@ -1216,7 +1276,7 @@ __device__ __forceinline__ void gain_body(const KArgs &a, int nblk)
             if (!B && CL != NCLS) bid = xcd_block(bid, nb);
             const int wid = bid * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nb * (BLOCK / 64);
             const int32_t *list = (!B && cl == CLS_S && a.sident) ? nullptr : a.bins + a.binoff[cl];
-            const Walk wk = walk<B>(a.binoff[cl + 1] - a.binoff[cl], wid, nwaves, 64);
+            const Walk wk = walk_q<B>(a, a.binoff[cl + 1] - a.binoff[cl], wid, nwaves, 64, WQ_GAIN + cl);
             auto pre = [&](Meta &m) -> bool {
                     m.g = gof<B>(a, m.v);
                     pv.sel<B>(a, m.g);
@@ -1374,7 +1434,8 @@ __device__ __forceinline__ void gain_body(const KArgs &a, int nblk)
                     racc.c0 += gain_finish(a, t.v, t.ps, best, cs, rv.cn, rv.cd);
                 }
             };
-            wave_batched<64>(a.bins + a.binoff[c], walk<B>(cnt, wid, nwaves, unit), q, pre, row, unit);
+            wave_batched<64>(a.bins + a.binoff[c], walk_q<B>(a, cnt, wid, nwaves, unit, WQ_GAIN2 + c), q, pre, row,
+                             unit);
         }
     } else {
         for (int i = threadIdx.x; i < a.k; i += BLOCK) lds[i] = 0;
@@ -1452,8 +1513,8 @@ __device__ void afterburner_body(const KArgs &a, int b)
         int32_t *q = s_q + (threadIdx.x >> 6) * 64;
         wave_batched<8>(
             (!B && a.sident) ? nullptr : a.bins + a.binoff[CLS_S],
-            walk<B>(a.binoff[CLS_S2 + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6), a.gS * (BLOCK / 64),
-                 64),
+            walk_q<B>(a, a.binoff[CLS_S2 + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6),
+                      a.gS * (BLOCK / 64), 64, WQ_AFTER_S),
             q,
             [&](Meta &m) -> bool {
                 const int g = gof<B>(a, m.v);
@@ -1486,7 +1547,7 @@ __device__ void afterburner_body(const KArgs &a, int b)
         const int cnt = a.binoff[CLS_M + 1] - a.binoff[CLS_M], nw = a.gM * (BLOCK / 64);
         const int unit = wave_unit(cnt, nw);
         wave_batched<64>(
-            a.bins + a.binoff[CLS_M], walk<B>(cnt, b * (BLOCK / 64) + (threadIdx.x >> 6), nw, unit), q,
+            a.bins + a.binoff[CLS_M], walk_q<B>(a, cnt, b * (BLOCK / 64) + (threadIdx.x >> 6), nw, unit, WQ_AFTER_M), q,
             [&](Meta &m) -> bool {
                 const int g = gof<B>(a, m.v);
                 pv.sel<B>(a, g);
@@ -1608,8 +1669,8 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
         int32_t *q = s_q + (threadIdx.x >> 6) * 64;
         wave_batched<8>(
             (!B && a.sident) ? nullptr : a.bins + a.binoff[CLS_S],
-            walk<B>(a.binoff[CLS_S2 + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6), a.gS * (BLOCK / 64),
-                 64),
+            walk_q<B>(a, a.binoff[CLS_S2 + 1] - a.binoff[CLS_S], b * (BLOCK / 64) + (threadIdx.x >> 6),
+                      a.gS * (BLOCK / 64), 64, WQ_DCUT_S),
             q,
             [&](Meta &m) -> bool {
                 const int pn = a.dest[m.v];
@@ -1638,7 +1699,7 @@ __global__ __launch_bounds__(BLOCK) void k_dcut(KArgs a)
         const int cnt = a.binoff[CLS_M + 1] - a.binoff[CLS_M], nw = a.gM * (BLOCK / 64);
         const int unit = wave_unit(cnt, nw);
         wave_batched<64>(
-            a.bins + a.binoff[CLS_M], walk<B>(cnt, b * (BLOCK / 64) + (threadIdx.x >> 6), nw, unit), q,
+            a.bins + a.binoff[CLS_M], walk_q<B>(a, cnt, b * (BLOCK / 64) + (threadIdx.x >> 6), nw, unit, WQ_DCUT_M), q,
             [&](Meta &m) -> bool {
                 const int pn = a.dest[m.v];
                 if (pn < 0) return false;
@@ -2284,7 +2345,7 @@ __device__ __forceinline__ void loss_body(const KArgs &a, int nblk, int hmode)
             int32_t *tab = lds + (threadIdx.x / G) * stride;
             const int wid = bid * (BLOCK / 64) + (threadIdx.x >> 6), nwaves = nb * (BLOCK / 64);
             const int32_t *list = (!B && cl == CLS_S && a.sident) ? nullptr : a.bins + a.binoff[cl];
-            const Walk wk = walk<B>(a.binoff[cl + 1] - a.binoff[cl], wid, nwaves, 64);
+            const Walk wk = walk_q<B>(a, a.binoff[cl + 1] - a.binoff[cl], wid, nwaves, 64, WQ_LOSS + cl);
             auto pre = [&](Meta &m) -> bool {
                     m.g = gof<B>(a, m.v);
                     pv.sel<B>(a, m.g);
@@ -2451,7 +2512,8 @@ __device__ __forceinline__ void loss_body(const KArgs &a, int nblk, int hmode)
                     racc.c0++;
                 }
             };
-            wave_batched<64>(a.bins + a.binoff[c], walk<B>(cnt, wid, nwaves, unit), q, pre, row, unit);
+            wave_batched<64>(a.bins + a.binoff[c], walk_q<B>(a, cnt, wid, nwaves, unit, WQ_LOSS2 + c), q, pre, row,
+                             unit);
         }
     } else if (ROLE == 3) {
         for (int i = threadIdx.x; i < a.k; i += BLOCK) lds[i] = 0;
@@ -2918,6 +2980,430 @@ __global__ __launch_bounds__(BLOCK) void k_rs_assign(KArgs a)
     }
 }
 
+// ------------------------------------------- persistent connectivity table --
+// Section 4.3's vertex-part connectivity structure, kept across iterations
+// (JET_F_CONN_TABLE, one graph). Row v owns min(k, deg v) slots (the
+// paper's space bound); its first tsize[v] slots form an open-addressed hash
+// table keyed by part (linear probing), sized a little above the number of
+// parts v touched when the row was last built. A slot holds
+// (count << 32) | part, or TAB_EMPTY. A part whose count falls to zero keeps
+// its slot until the row is rebuilt.
+//  * Build (set-up; after an iteration that moved more than a tenth of the
+//    vertices; for flagged rows otherwise): the row's part counts in LDS,
+//    then its nonzero parts inserted by CAS into the cleared row.
+//  * Update (Algorithm 6), after the cut delta of an iteration that moved at
+//    most a tenth: every moved vertex's edge weights leave its source part
+//    and join its destination part in its neighbours' rows, inserting the
+//    part where missing; a row with no free slot for an insert is listed and
+//    rebuilt after the moves, with more slots (the paper's failed-insert
+//    rehash).
+//  * Gains and losses scan rows instead of gathering neighbour parts. The
+//    maximum is taken on (count, ~part) keys, so slot order (and the races
+//    that decide it) never changes a result.
+constexpr unsigned long long TAB_EMPTY = 0xFFFFFFFFull;
+
+__device__ __forceinline__ int tab_part(unsigned long long x) { return (int)(uint32_t)x; }  // -1: empty
+__device__ __forceinline__ int tab_cnt(unsigned long long x) { return (int)(x >> 32); }
+__device__ __forceinline__ int tab_home(int p, int size) { return (int)(((uint32_t)p * 2654435761u) % (uint32_t)size); }
+
+// Slots a row is built with for nz nonzero parts (at most its allocation).
+__device__ __forceinline__ int tab_size(int nz, int alloc)
+{
+    const int want = nz + (nz / 4 > 2 ? nz / 4 : 2);
+    return want < alloc ? want : alloc;
+}
+
+// Adds w to part p of a row of `size` slots, inserting p in a free slot if
+// absent; false when no slot is free.
+__device__ __forceinline__ bool tab_add(unsigned long long *row, int size, int p, int w)
+{
+    const unsigned long long inc = (unsigned long long)(uint32_t)w << 32;
+    int i = tab_home(p, size);
+    for (int n = 0; n < size; n++) {
+        const unsigned long long x = row[i];
+        if (tab_part(x) == p) {
+            atomicAdd(&row[i], inc);
+            return true;
+        }
+        if (x == TAB_EMPTY) {
+            const unsigned long long old = atomicCAS(&row[i], TAB_EMPTY, inc | (uint32_t)p);
+            if (old == TAB_EMPTY) return true;
+            if (tab_part(old) == p) {
+                atomicAdd(&row[i], inc);
+                return true;
+            }
+        }
+        i = i + 1 == size ? 0 : i + 1;
+    }
+    return false;
+}
+
+// Subtracts w from part p of a row (p is present: a moved neighbour was in p).
+__device__ __forceinline__ void tab_sub(unsigned long long *row, int size, int p, int w)
+{
+    const unsigned long long dec = (unsigned long long)(-(int64_t)((uint64_t)(uint32_t)w << 32));
+    int i = tab_home(p, size);
+    for (int n = 0; n < size; n++) {
+        if (tab_part(row[i]) == p) {
+            atomicAdd(&row[i], dec);
+            return;
+        }
+        i = i + 1 == size ? 0 : i + 1;
+    }
+}
+
+// Writes the counts a group of G lanes holds (pu / cu as from
+// group_conn_row: each nonzero part once, with its connectivity) into row v:
+// sizes the row, clears it, inserts.
+template <int G, int R>
+__device__ __forceinline__ void tab_store_row(const KArgs &a, int v, int gl, const int (&pu)[R], const int (&cu)[R])
+{
+    int nz = 0;
+#pragma unroll
+    for (int r = 0; r < R; r++) nz += cu[r] > 0;
+    nz = gsum<G>(nz);
+    const int64_t s = a.toff[v];
+    const int alloc = (int)(a.toff[v + 1] - s);
+    const int size = tab_size(nz, alloc);
+    unsigned long long *row = a.tab + s;
+    for (int i = gl; i < size; i += G) row[i] = TAB_EMPTY;
+    if (gl == 0) a.tsize[v] = size;
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < R; r++)
+        if (cu[r] > 0) tab_add(row, size, pu[r], cu[r]);
+}
+
+// Role of a class in the table build: that of the gain pass (a.tmap: 1
+// groups of 8 lanes, 2 one wave, 3 one block per row, chosen by k so the
+// LDS tables fit), long rows always one block.
+__device__ __forceinline__ int tab_role(const KArgs &a, int cls) { return cls == CLS_L || a.tmap[cls] == 0 ? 3 : a.tmap[cls]; }
+
+// Builds rows: every row (at set-up, or after an iteration that moved more
+// than a tenth of the vertices) or the listed ones (after smaller move
+// sets); nothing after an iteration without moves. One graph.
+template <int ROLE>
+__global__ __launch_bounds__(BLOCK) void k_tab_build(KArgs a, int setup)
+{
+    extern __shared__ int32_t lds[];
+    __shared__ int32_t s_red32[BLOCK / 64];
+    bool full = setup != 0;
+    if (!full) {
+        if (!any_active(a)) return;
+        int64_t moved = 0;
+        for (int i = 0; i < NSHARD; i++) moved += a.bstat[ST_M * NSHARD + i];
+        if (moved == 0) return;
+        full = 10 * moved > (int64_t)a.n;
+        if (!full && a.cnt[CNT_TFAIL] == 0) return;
+    }
+    constexpr int G = ROLE == 1 ? 8 : 64, R = ROLE == 1 ? 8 : 16;
+    const int stride = a.k + 1;
+    const int ntab = ROLE == 1 ? BLOCK / 8 : (ROLE == 2 ? BLOCK / 64 : 1);
+    for (int i = threadIdx.x; i < ntab * (ROLE == 3 ? a.k : stride); i += BLOCK) lds[i] = 0;
+    __syncthreads();
+    // one row: counts in LDS, then the row written
+    auto group_row = [&](int v, int gl, int32_t *tab) {
+        const int64_t s = a.xadj[v];
+        int pu[R], cu[R];
+        group_conn_row<G, R>(a, s, (int)(a.xadj[v + 1] - s), gl, tab, pu, cu);
+        tab_store_row<G, R>(a, v, gl, pu, cu);
+        if (gl == 0) a.tfail[v] = 0;
+    };
+    auto block_row = [&](int v) {
+        block_fill(a, v, lds);
+        int nz = 0;
+        for (int p = threadIdx.x; p < a.k; p += BLOCK) nz += lds[p] > 0;
+        nz = block_sum<BLOCK>(nz, s_red32);
+        const int64_t s = a.toff[v];
+        const int size = tab_size(nz, (int)(a.toff[v + 1] - s));
+        unsigned long long *row = a.tab + s;
+        for (int j = threadIdx.x; j < size; j += BLOCK) row[j] = TAB_EMPTY;
+        if (threadIdx.x == 0) {
+            a.tsize[v] = size;
+            a.tfail[v] = 0;
+        }
+        __syncthreads();
+        for (int p = threadIdx.x; p < a.k; p += BLOCK) {
+            const int c = lds[p];
+            if (c) {
+                lds[p] = 0;
+                tab_add(row, size, p, c);
+            }
+        }
+        __syncthreads();
+    };
+    if (ROLE == 3) {
+        if (full) {
+            for (int c = CLS_S; c <= CLS_L; c++) {
+                if (tab_role(a, c) != 3) continue;
+                const int32_t *list = a.bins + a.binoff[c];
+                const int cnt = a.binoff[c + 1] - a.binoff[c];
+                for (int i = blockIdx.x; i < cnt; i += gridDim.x) block_row(list[i]);
+            }
+        } else {
+            const int cnt = a.cnt[CNT_TFAIL];
+            for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+                const int v = a.tlist[i];
+                if (tab_role(a, degree_class(a.xadj[v + 1] - a.xadj[v])) == 3) block_row(v);
+            }
+        }
+        return;
+    }
+    int32_t *tab = lds + (threadIdx.x / G) * stride;
+    const int gl = threadIdx.x & (G - 1);
+    const int gid = blockIdx.x * (BLOCK / G) + threadIdx.x / G, ngr = gridDim.x * (BLOCK / G);
+    if (full) {
+        for (int c = CLS_S; c <= CLS_M; c++) {
+            if (tab_role(a, c) != ROLE) continue;
+            const int32_t *list = a.bins + a.binoff[c];
+            const int cnt = a.binoff[c + 1] - a.binoff[c];
+            for (int i = gid; i < cnt; i += ngr) group_row(list[i], gl, tab);
+        }
+    } else {
+        const int cnt = a.cnt[CNT_TFAIL];
+        for (int i = gid; i < cnt; i += ngr) {
+            const int v = a.tlist[i];
+            if (tab_role(a, degree_class(a.xadj[v + 1] - a.xadj[v])) == ROLE) group_row(v, gl, tab);
+        }
+    }
+}
+
+// Jetlp gain (RB = false) or rebalancing loss (RB = true) from the rows:
+// rows of up to 64 slots in groups of 8 lanes, longer rows one wave each;
+// lanes first inspect 64 list entries at once (wave-batched).
+template <bool RB, int G>
+__device__ __forceinline__ void tab_scan_class(const KArgs &a, int cls, int wid, int nwaves, int32_t *q, GV &pv,
+                                               GainPre &pacc, CountX &racc, int hmode)
+{
+    const int cnt = a.binoff[cls + 1] - a.binoff[cls];
+    const int unit = G == 64 ? wave_unit(cnt, nwaves) : 64;
+    auto pre = [&](Meta &m) -> bool {
+        if (RB) {
+            if (!is_rb(pv.kind)) return false;
+            m.ps = a.P[m.v];
+            m.aux = a.vw ? a.vw[m.v] : 1;
+            const int64_t t0 = a.toff[m.v];
+            const int sz = a.tsize[m.v];
+            if (!rb_candidate(a, m.v, m.ps, m.aux, pv)) return false;
+            m.s = t0;
+            m.deg = sz;
+            return true;
+        }
+        if (pv.kind != KIND_LP) return false;
+        m.ps = a.P[m.v];
+        const int lk = a.lock[m.v];
+        const int64_t t0 = a.toff[m.v];
+        const int sz = a.tsize[m.v];
+        pacc.c0++;
+        if (lk == pv.lp_id - 1) {
+            gain_locked(a, m.v, m.ps);
+            return false;
+        }
+        m.s = t0;
+        m.deg = sz;
+        pacc.c1++;
+        pacc.c2 += sz;
+        return true;
+    };
+    auto row = [&](const Meta &t, int gl) {
+        uint64_t best = 0;
+        int cs = 0, sumB = 0, cntB = 0;
+        for (int i = gl; i < t.deg; i += G) {
+            const unsigned long long x = a.tab[t.s + i];
+            const int c = tab_cnt(x), p = tab_part(x);
+            if (x == TAB_EMPTY || c == 0) continue;
+            if (p == t.ps) cs = c;
+            else if (!RB || a.isB[p]) {
+                const uint64_t k2 = conn_key(c, p);
+                best = k2 > best ? k2 : best;
+                sumB += c;
+                cntB++;
+            }
+        }
+        best = gmax_u64<G>(best);
+        cs = gsum<G>(cs);
+        if (RB) {
+            sumB = gsum<G>(sumB);
+            cntB = gsum<G>(cntB);
+        }
+        if (gl == 0) {
+            if (RB) {
+                rb_finish(a, t.v, t.ps, pv, best, cs, sumB, cntB, t.aux, hmode, nullptr);
+                racc.c0++;
+            } else {
+                racc.c0 += gain_finish(a, t.v, t.ps, best, cs, pv.cn, pv.cd);
+            }
+        }
+    };
+    wave_batched<G>(a.bins + a.binoff[cls], walk<false>(cnt, wid, nwaves, unit), q, pre, row, unit);
+}
+
+template <bool RB>
+__global__ __launch_bounds__(BLOCK) void k_tab_scan(KArgs a, int gS)
+{
+    __shared__ int32_t s_q[BLOCK];
+    if (RB ? !any_rb(a) : !any_kind(a, KIND_LP)) return;
+    GV pv;
+    GainPre pacc;
+    CountX racc;
+    pv.at(a, 0);
+    pacc.to(a, 0);
+    racc.to(a, 0);
+    int32_t *q = s_q + (threadIdx.x >> 6) * 64;
+    // blocks [0, gS): the small classes (groups of 8 lanes); the rest: medium and long rows
+    if ((int)blockIdx.x < gS) {
+        const int wid = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6), nw = gS * (BLOCK / 64);
+        tab_scan_class<RB, 8>(a, CLS_S, wid, nw, q, pv, pacc, racc, HIST_NONE);
+        tab_scan_class<RB, 8>(a, CLS_S2, wid, nw, q, pv, pacc, racc, HIST_NONE);
+        if (RB && is_rb(pv.kind)) {
+            // isolated candidates: no connectivity, loss 0, random destination (Jetrw)
+            const int32_t *list = a.bins + a.binoff[CLS_Z];
+            const int cnt = a.binoff[CLS_Z + 1] - a.binoff[CLS_Z];
+            for (int i = blockIdx.x * BLOCK + threadIdx.x; i < cnt; i += gS * BLOCK) {
+                const int v = list[i];
+                const int ps = a.P[v];
+                const int vwv = a.vw ? a.vw[v] : 1;
+                if (!rb_candidate(a, v, ps, vwv, pv)) continue;
+                rb_finish(a, v, ps, pv, 0, 0, 0, 0, vwv, HIST_NONE, nullptr);
+                racc.c0++;
+            }
+        }
+    } else {
+        const int nb = gridDim.x - gS;
+        const int wid = (blockIdx.x - gS) * (BLOCK / 64) + (threadIdx.x >> 6), nw = nb * (BLOCK / 64);
+        tab_scan_class<RB, 64>(a, CLS_M, wid, nw, q, pv, pacc, racc, HIST_NONE);
+        tab_scan_class<RB, 64>(a, CLS_L, wid, nw, q, pv, pacc, racc, HIST_NONE);
+    }
+    if (!RB) acc_finish(a, pacc);
+    acc_finish(a, racc);
+}
+
+// Algorithm 6 on one moved row: every neighbour's row loses w in the source
+// part and gains it in the destination part. The paper runs the two halves
+// as separate passes so that the first can open slots the second reuses;
+// here a slot whose count reached zero keeps its part until the row is
+// rebuilt, so the decrements and increments of all moves commute (a count
+// never goes below zero: the source part held at least w) and one pass
+// does both.
+__device__ __forceinline__ void tab_update_row(const KArgs &a, int64_t s, int deg, int ps, int pn, int gl, int stride)
+{
+    for (int i = gl; i < deg; i += stride) {
+        const int u = a.adj[s + i];
+        const int w = a.ew ? a.ew[s + i] : 1;
+        unsigned long long *row = a.tab + a.toff[u];
+        const int size = a.tsize[u];
+        tab_sub(row, size, ps, w);
+        if (!tab_add(row, size, pn, w)) {
+            // no slot left: the row is rebuilt after the moves
+            if (atomicExch(&a.tfail[u], 1) == 0) a.tlist[atomicAdd(&a.cnt[CNT_TFAIL], 1)] = u;
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_tab_update(KArgs a, int gS)
+{
+    __shared__ int32_t s_q[BLOCK];
+    if (!any_active(a)) return;
+    // more than a tenth of the vertices moved: the whole table is rebuilt instead
+    int64_t moved = 0;
+    for (int i = 0; i < NSHARD; i++) moved += a.bstat[ST_M * NSHARD + i];
+    if (moved == 0 || 10 * moved > (int64_t)a.n) return;
+    int32_t *q = s_q + (threadIdx.x >> 6) * 64;
+    auto pre = [&](Meta &m) -> bool {
+        const int pn = a.dest[m.v];
+        if (pn < 0) return false;
+        m.aux = pn;
+        m.ps = a.P[m.v];
+        m.s = a.xadj[m.v];
+        m.deg = (int)(a.xadj[m.v + 1] - m.s);
+        return true;
+    };
+    if ((int)blockIdx.x < gS) {
+        const int wid = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6), nw = gS * (BLOCK / 64);
+        wave_batched<8>(a.bins + a.binoff[CLS_S], walk<false>(a.binoff[CLS_S2 + 1] - a.binoff[CLS_S], wid, nw, 64), q,
+                        pre, [&](const Meta &t, int gl) { tab_update_row(a, t.s, t.deg, t.ps, t.aux, gl, 8); });
+    } else {
+        const int nb = gridDim.x - gS;
+        const int wid = (blockIdx.x - gS) * (BLOCK / 64) + (threadIdx.x >> 6), nw = nb * (BLOCK / 64);
+        const int cnt = a.binoff[CLS_L + 1] - a.binoff[CLS_M];
+        const int unit = wave_unit(cnt, nw);
+        wave_batched<64>(a.bins + a.binoff[CLS_M], walk<false>(cnt, wid, nw, unit), q, pre,
+                         [&](const Meta &t, int gl) { tab_update_row(a, t.s, t.deg, t.ps, t.aux, gl, 64); },
+                         unit);
+    }
+}
+
+// Row offsets of the table: prefix sums of min(k, deg v), in three passes
+// (block sums, their scan, the fill). Blocks own contiguous vertex ranges.
+__global__ __launch_bounds__(BLOCK) void k_toff_count(const int64_t *xadj, int n, int k, int64_t *blk)
+{
+    __shared__ int64_t s_red[BLOCK / 64];
+    int lo, hi;
+    block_chunk(n, blockIdx.x, gridDim.x, lo, hi);
+    int64_t sum = 0;
+    for (int v = lo + threadIdx.x; v < hi; v += BLOCK) {
+        const int64_t d = xadj[v + 1] - xadj[v];
+        sum += d < k ? d : k;
+    }
+    sum = block_sum<BLOCK>(sum, s_red);
+    if (threadIdx.x == 0) blk[blockIdx.x] = sum;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_toff_scan(int64_t *blk, int nblk)
+{
+    __shared__ int64_t s_scan[BLOCK / 64];
+    int64_t carry = 0;
+    for (int b0 = 0; b0 < nblk; b0 += BLOCK) {
+        const int i = b0 + threadIdx.x;
+        const int64_t x = i < nblk ? blk[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan<BLOCK>(x, s_scan, tot);
+        if (i < nblk) blk[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) blk[nblk] = carry;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_toff_fill(const int64_t *xadj, int n, int k, const int64_t *blk, int64_t *toff)
+{
+    __shared__ int64_t s_scan[BLOCK / 64];
+    int lo, hi;
+    block_chunk(n, blockIdx.x, gridDim.x, lo, hi);
+    int64_t carry = blk[blockIdx.x];
+    for (int b0 = lo; b0 < hi; b0 += BLOCK) {
+        const int v = b0 + threadIdx.x;
+        int64_t x = 0;
+        if (v < hi) {
+            const int64_t d = xadj[v + 1] - xadj[v];
+            x = d < k ? d : k;
+        }
+        int64_t tot;
+        const int64_t ex = block_excl_scan<BLOCK>(x, s_scan, tot);
+        if (v < hi) toff[v] = carry + ex;
+        carry += tot;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) toff[n] = blk[gridDim.x];
+}
+
+// --------------------------------------------------------- batch autotuner --
+// A dry-run copy of the batch's state for timing the gain pass: every graph
+// in a Jetlp iteration with nothing locked (its lock stamps are all -1 at
+// set-up), a count row saying so. The tuner's passes write their records and
+// counters into scratch; the real state is untouched.
+__global__ __launch_bounds__(BLOCK) void k_tune_prep(KArgs a, Ctl *ctl2, int32_t *cnt2)
+{
+    const int g = blockIdx.x;
+    if (threadIdx.x == 0) {
+        Ctl c = a.ctl[g];
+        c.kind = KIND_LP;
+        if (c.lp_id < 1) c.lp_id = 1;
+        ctl2[g] = c;
+    }
+    if (g == 0)
+        for (int i = threadIdx.x; i < CNT_N + 2; i += BLOCK) cnt2[i] = i == CNT_ROW + KIND_LP ? a.ngraph : 0;
+}
+
 // ------------------------------------------------------- batch union graph --
 
 // One graph of a batch as the union sees it.
@@ -3122,6 +3608,12 @@ struct Plan {
     int32_t *blkcnt, *lcnt;  // their scratch
     int32_t *bins;
     bool hist_lds;
+    // persistent connectivity table (one graph, JET_F_CONN_TABLE)
+    bool table;
+    int grid_tsmall, grid_tlarge;  // row scans and updates: small classes / medium and long rows
+    int grid_tb[4];                // table build, per role (1, 2, 3)
+    size_t lds_tb[4];
+    bool small_g8 = false;         // batch: groups of 8 lanes for small rows even where k allows 4
 };
 
 static int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -3190,6 +3682,22 @@ static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cn
     // levels): the gain pass is long enough that its own launch, with two
     // rows in flight per group, pays for the extra launch per iteration.
     pl.split_rows = a.vg == nullptr && t.gS && !t.gS2 && a.n >= (1 << 18);
+    pl.table = a.toff != nullptr;
+    if (pl.table) {
+        // row scans build no block histogram; no split small-row launches
+        pl.hist_fused = false;
+        pl.split_rows = false;
+        pl.grid_tsmall = std::min(std::max(div_up(cnt[CLS_S] + cnt[CLS_S2], BLOCK / 8), div_up(cnt[CLS_Z], BLOCK)), maxb);
+        pl.grid_tlarge = std::min(div_up(cnt[CLS_M] + cnt[CLS_L], BLOCK / 64), maxb);
+        int64_t rows[4] = {0, 0, 0, 0};
+        for (int c = CLS_S; c <= CLS_L; c++) rows[(c == CLS_L || t.tmap[c] == 0) ? 3 : t.tmap[c]] += cnt[c];
+        pl.grid_tb[1] = rows[1] ? std::min(div_up(rows[1], BLOCK / 8), maxb) : 0;
+        pl.grid_tb[2] = rows[2] ? std::min(div_up(rows[2], BLOCK / 64), maxb) : 0;
+        pl.grid_tb[3] = rows[3] ? (int)std::min<int64_t>(rows[3], maxb) : 0;
+        pl.lds_tb[1] = (size_t)(BLOCK / 8) * (k + 1) * 4;
+        pl.lds_tb[2] = (size_t)(BLOCK / 64) * (k + 1) * 4;
+        pl.lds_tb[3] = (size_t)k * 4;
+    }
     pl.grid_hist = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_flat = std::max(1, std::min(div_up(a.n, BLOCK), ctx->num_cu * 2));
     pl.grid_tile = std::max(1, std::min(a.ntile, ctx->num_cu * 8));
@@ -3208,10 +3716,10 @@ static void launch_gain_t(const Plan &pl, hipStream_t s, bool small = true)
     if (!small) {
     } else if (t.gS && t.gS2) {
         const int g = t.gS + t.gS2;
-        if (t.k <= K_G4) k_gain<B, 1, 4, 8, NCLS><<<g, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, g);
+        if (t.k <= K_G4 && !pl.small_g8) k_gain<B, 1, 4, 8, NCLS><<<g, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, g);
         else k_gain<B, 1, 8, 4, NCLS><<<g, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, g);
     } else if (t.gS) {
-        if (t.k <= K_G4) k_gain<B, 1, 4><<<t.gS, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, t.gS);
+        if (t.k <= K_G4 && !pl.small_g8) k_gain<B, 1, 4><<<t.gS, BLOCK, (BLOCK / 4) * st + BLOCK * 4, s>>>(t, t.gS);
         else k_gain<B, 1, 8><<<t.gS, BLOCK, (BLOCK / 8) * st + BLOCK * 4, s>>>(t, t.gS);
     } else if (t.gS2) {
         k_gain<B, 1, 8, 8, CLS_S2><<<t.gS2, BLOCK, rb_s2_lds(t.k), s>>>(t, t.gS2);
@@ -3249,20 +3757,22 @@ static void launch_rb_loss_t(const Plan &pl, hipStream_t s, bool small = true)
     } else if (t.gS && t.gS2) {
         const size_t l1 = rb_role_lds(1, t.k) + hb + cb;
         const int g = t.gS + t.gS2;
+        const bool g4 = t.k <= K_G4 && !pl.small_g8;
         if (pl.loss_cache) {
-            if (t.k <= K_G4) k_rb_loss<B, 1, 4, 8, true, NCLS><<<g, BLOCK, l1, s>>>(t, g, hm);
+            if (g4) k_rb_loss<B, 1, 4, 8, true, NCLS><<<g, BLOCK, l1, s>>>(t, g, hm);
             else k_rb_loss<B, 1, 8, 4, true, NCLS><<<g, BLOCK, l1, s>>>(t, g, hm);
         } else {
-            if (t.k <= K_G4) k_rb_loss<B, 1, 4, 8, false, NCLS><<<g, BLOCK, l1, s>>>(t, g, hm);
+            if (g4) k_rb_loss<B, 1, 4, 8, false, NCLS><<<g, BLOCK, l1, s>>>(t, g, hm);
             else k_rb_loss<B, 1, 8, 4, false, NCLS><<<g, BLOCK, l1, s>>>(t, g, hm);
         }
     } else if (t.gS) {
         const size_t l1 = rb_role_lds(1, t.k) + hb + cb;
+        const bool g4 = t.k <= K_G4 && !pl.small_g8;
         if (pl.loss_cache) {
-            if (t.k <= K_G4) k_rb_loss<B, 1, 4, 8, true><<<t.gS, BLOCK, l1, s>>>(t, t.gS, hm);
+            if (g4) k_rb_loss<B, 1, 4, 8, true><<<t.gS, BLOCK, l1, s>>>(t, t.gS, hm);
             else k_rb_loss<B, 1, 8, 4, true><<<t.gS, BLOCK, l1, s>>>(t, t.gS, hm);
         } else {
-            if (t.k <= K_G4) k_rb_loss<B, 1, 4><<<t.gS, BLOCK, l1, s>>>(t, t.gS, hm);
+            if (g4) k_rb_loss<B, 1, 4><<<t.gS, BLOCK, l1, s>>>(t, t.gS, hm);
             else k_rb_loss<B, 1, 8><<<t.gS, BLOCK, l1, s>>>(t, t.gS, hm);
         }
     } else if (t.gS2) {
@@ -3319,9 +3829,48 @@ static void launch_rows_t(const Plan &pl, hipStream_t s)
     }
 }
 
+// Table mode: the row scans (gain, loss), the update passes, the builds.
+static void launch_tab_scan(const Plan &pl, hipStream_t s, bool rb)
+{
+    const int g = pl.grid_tsmall + pl.grid_tlarge;
+    if (!g) return;
+    if (rb) k_tab_scan<true><<<g, BLOCK, 0, s>>>(pl.tab, pl.grid_tsmall);
+    else k_tab_scan<false><<<g, BLOCK, 0, s>>>(pl.tab, pl.grid_tsmall);
+}
+
+static void launch_tab_build(const Plan &pl, hipStream_t s, int setup)
+{
+    if (pl.grid_tb[1]) k_tab_build<1><<<pl.grid_tb[1], BLOCK, pl.lds_tb[1], s>>>(pl.tab, setup);
+    if (pl.grid_tb[2]) k_tab_build<2><<<pl.grid_tb[2], BLOCK, pl.lds_tb[2], s>>>(pl.tab, setup);
+    if (pl.grid_tb[3]) k_tab_build<3><<<pl.grid_tb[3], BLOCK, pl.lds_tb[3], s>>>(pl.tab, setup);
+}
+
+static void launch_iteration_table(const Plan &pl, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b)
+{
+    const KArgs &p = pl.plain;
+    if (ev_a) (void)hipEventRecord(ev_a, s);
+    launch_tab_scan(pl, s, false);
+    if (ev_b) (void)hipEventRecord(ev_b, s);
+    launch_tab_scan(pl, s, true);
+    launch_rb_cutoff_t<false>(pl, s);
+    launch_after_t<false>(pl, s);
+    launch_rb_select_t<false>(pl, s);
+    if (pl.grid_plain) k_dcut<false><<<pl.grid_plain, BLOCK, 0, s>>>(p);
+    if (pl.grid_lch) k_ldcut<false><<<pl.grid_lch, BLOCK, 0, s>>>(p);
+    const int gu = pl.grid_tsmall + pl.grid_tlarge;
+    if (gu) k_tab_update<<<gu, BLOCK, 0, s>>>(p, pl.grid_tsmall);
+    k_apply<false><<<pl.grid_flat, BLOCK, (size_t)p.k * 4, s>>>(p);
+    launch_tab_build(pl, s, 0);
+    k_ctl_end<<<pl.G, BLOCK, 0, s>>>(p);
+}
+
 template <bool B>
 static void launch_iteration_t(const Plan &pl, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b)
 {
+    if (!B && pl.table) {
+        launch_iteration_table(pl, s, ev_a, ev_b);
+        return;
+    }
     const KArgs &p = pl.plain;
     if (ev_a) (void)hipEventRecord(ev_a, s);
     const bool split = !B && pl.split_rows;
@@ -3346,6 +3895,7 @@ static bool batched(const Plan &pl) { return pl.plain.vg != nullptr; }
 static void launch_gain(const Plan &pl, hipStream_t s)
 {
     if (batched(pl)) launch_gain_t<true>(pl, s);
+    else if (pl.table) launch_tab_scan(pl, s, false);
     else launch_gain_t<false>(pl, s);
 }
 static void launch_after(const Plan &pl, hipStream_t s)
@@ -3356,6 +3906,7 @@ static void launch_after(const Plan &pl, hipStream_t s)
 static void launch_rb_loss(const Plan &pl, hipStream_t s)
 {
     if (batched(pl)) launch_rb_loss_t<true>(pl, s);
+    else if (pl.table) launch_tab_scan(pl, s, true);
     else launch_rb_loss_t<false>(pl, s);
 }
 static void launch_rb_cutoff(const Plan &pl, hipStream_t s)
@@ -3444,6 +3995,9 @@ static void set_lds_limits()
         set_lds_limits_rows<false>();
         set_lds_limits_rows<true>();
         (void)hipFuncSetAttribute((const void *)k_init_vertices, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+        (void)hipFuncSetAttribute((const void *)k_tab_build<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+        (void)hipFuncSetAttribute((const void *)k_tab_build<2>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+        (void)hipFuncSetAttribute((const void *)k_tab_build<3>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     });
 }
 
@@ -3696,6 +4250,38 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
         a.ldone = ldone;
         a.gf2 = ldone + nL;
     }
+    // batch: work-queue counters of the row kernels (both banks clear)
+    if (a.vg != nullptr) {
+        a.wq = (int32_t *)ws_get(ctx, WS_WQ, sizeof(int32_t) * 2 * NQC);
+        if (!a.wq) return JET_ENOMEM;
+        JET_TRY(hipMemsetAsync(a.wq, 0, sizeof(int32_t) * 2 * NQC, s));
+        a.wtile = 0;
+    }
+    // persistent connectivity table (one graph, JET_F_CONN_TABLE): row
+    // offsets, then the rows built from P_0 once the roles are planned
+    int64_t tslots = 0;
+    if (a.vg == nullptr && (L.hc[0].flags & JET_F_CONN_TABLE) && n > 0) {
+        int64_t *toff = (int64_t *)ws_get(ctx, WS_TOFF, sizeof(int64_t) * (nn + 1));
+        int64_t *tblk = (int64_t *)ws_get(ctx, WS_TBLK, sizeof(int64_t) * ((size_t)grid_v + 1));
+        if (!toff || !tblk) return JET_ENOMEM;
+        k_toff_count<<<grid_v, BLOCK, 0, s>>>(a.xadj, n, a.k, tblk);
+        k_toff_scan<<<1, BLOCK, 0, s>>>(tblk, grid_v);
+        k_toff_fill<<<grid_v, BLOCK, 0, s>>>(a.xadj, n, a.k, tblk, toff);
+        JET_TRY(hipMemcpyAsync(pin + 264, tblk + grid_v, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        JET_TRY(stream_wait(ctx, s));
+        tslots = *(const int64_t *)(pin + 264);
+        unsigned long long *tab = (unsigned long long *)ws_get(ctx, WS_TAB, sizeof(unsigned long long) * (size_t)std::max<int64_t>(tslots, 1));
+        int32_t *tsize = (int32_t *)ws_get(ctx, WS_TSIZE, sizeof(int32_t) * nn);
+        int32_t *tfail = (int32_t *)ws_get(ctx, WS_TFAIL, sizeof(int32_t) * nn);
+        int32_t *tlist = (int32_t *)ws_get(ctx, WS_TLIST, sizeof(int32_t) * nn);
+        if (!tab || !tsize || !tfail || !tlist) return JET_ENOMEM;
+        JET_TRY(hipMemsetAsync(tfail, 0, sizeof(int32_t) * nn, s));
+        a.toff = toff;
+        a.tab = tab;
+        a.tsize = tsize;
+        a.tfail = tfail;
+        a.tlist = tlist;
+    }
     a.it = 0;
     k_ctl_setup<<<G, BLOCK, 0, s>>>(a);
     JET_TRY(hipGetLastError());
@@ -3703,6 +4289,10 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     // final state read-back, ordered after it on the same stream
     pl.G = G;
     plan_roles(ctx, a, tot, pl);
+    if (pl.table) {
+        launch_tab_build(pl, s, 1);
+        JET_TRY(hipGetLastError());
+    }
     pl.grid_v = grid_v;
     pl.blkcnt = blkcnt;
     pl.lcnt = lcnt;
@@ -4121,6 +4711,102 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     return JET_OK;
 }
 
+// Autotuner of a batch's launch sequence: picks how waves walk the class
+// lists (static stretches, or work-queue tiles of 16 or 64 visits of their
+// role) and, where k allows both, 4- or 8-lane groups for the small rows, by
+// timing one dry gain pass of each choice over the batch itself
+// (k_tune_prep). Every choice gives the same results; only the time
+// differs. The choice is recorded in the context per batch shape (graph
+// count, size and CSR-entry scales, largest k), so repeated calls on batches
+// of that shape reuse it; small batches take static walks.
+// JET_BATCH_TILE (0 = static) / JET_BATCH_GROUP force a choice.
+static uint64_t batch_signature(const Plan &pl, int64_t nnz)
+{
+    auto lg = [](int64_t x) { return (uint64_t)(64 - __builtin_clzll((unsigned long long)(x | 1))); };
+    return ((uint64_t)pl.G << 32) ^ (lg(pl.tab.n) << 24) ^ (lg(nnz) << 16) ^ (uint64_t)pl.tab.k;
+}
+
+static int tune_batch(jet_context *ctx, Plan &pl, int64_t nnz, hipStream_t s)
+{
+    const char *et = getenv("JET_BATCH_TILE"), *eg = getenv("JET_BATCH_GROUP");
+    int tile = 0;
+    bool g8 = pl.tab.k > K_G4;
+    const uint64_t sig = batch_signature(pl, nnz);
+    bool cached = false;
+    for (const auto &e : ctx->tune_cache)
+        if (e.first == sig) {
+            tile = e.second & 0xFFFF;
+            g8 = (e.second >> 16) != 0;
+            cached = true;
+        }
+    if (et || eg || (!cached && nnz < ((int64_t)1 << 20))) {
+        if (et && atoi(et) >= 0) tile = atoi(et);
+        if (eg) g8 = atoi(eg) == 8 || pl.tab.k > K_G4;
+    } else if (!cached) {
+        const int G = pl.G, n = pl.tab.n;
+        Ctl *ctl2 = (Ctl *)ws_get(ctx, WS_TUNE_CTL, sizeof(Ctl) * (size_t)G);
+        int32_t *cnt2 = (int32_t *)ws_get(ctx, WS_TUNE_CNT, sizeof(int32_t) * (CNT_N + 2 + 2 * NQC));
+        int2 *rec2 = (int2 *)ws_get(ctx, WS_TUNE_REC, sizeof(int2) * (size_t)std::max(n, 1));
+        int64_t *st2 = (int64_t *)ws_get(ctx, WS_TUNE_STAT, sizeof(int64_t) * NSTAT * NSHARD * (size_t)G);
+        if (!ctl2 || !cnt2 || !rec2 || !st2) return JET_ENOMEM;
+        int32_t *wq2 = cnt2 + CNT_N + 2;
+        k_tune_prep<<<G, BLOCK, 0, s>>>(pl.plain, ctl2, cnt2);
+        constexpr int NT = 3;
+        const int tiles[NT] = {0, 16, 64};
+        const int ng = pl.tab.k <= K_G4 ? 2 : 1;
+        hipEvent_t ev[2 * NT * 2];
+        int ne = 0;
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < 2 * NT * ng; i++) {
+            e = hipEventCreate(&ev[i]);
+            if (e != hipSuccess) break;
+            ne++;
+        }
+        if (e != hipSuccess) {
+            for (int i = 0; i < ne; i++) (void)hipEventDestroy(ev[i]);
+            return hip_status(ctx, e);
+        }
+        int c = 0;
+        for (int gi = 0; gi < ng; gi++)
+            for (int ti = 0; ti < NT; ti++, c++) {
+                Plan dp = pl;
+                for (KArgs *k : {&dp.tab, &dp.plain}) {
+                    k->ctl = ctl2;
+                    k->cnt = cnt2;
+                    k->rec = rec2;
+                    k->bstat = st2;
+                    k->wq = wq2;
+                    k->wtile = tiles[ti];
+                    k->it = 0;
+                }
+                dp.small_g8 = gi == 1;
+                JET_TRY(hipMemsetAsync(st2, 0, sizeof(int64_t) * NSTAT * NSHARD * (size_t)G, s));
+                JET_TRY(hipMemsetAsync(wq2, 0, sizeof(int32_t) * 2 * NQC, s));
+                JET_TRY(hipEventRecord(ev[2 * c], s));
+                launch_gain_t<true>(dp, s);
+                JET_TRY(hipEventRecord(ev[2 * c + 1], s));
+            }
+        JET_TRY(hipGetLastError());
+        JET_TRY(stream_wait(ctx, s));
+        float best = 1e30f;
+        c = 0;
+        for (int gi = 0; gi < ng; gi++)
+            for (int ti = 0; ti < NT; ti++, c++) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, ev[2 * c], ev[2 * c + 1]) == hipSuccess && ms < best) {
+                    best = ms;
+                    tile = tiles[ti];
+                    g8 = gi == 1 || pl.tab.k > K_G4;
+                }
+            }
+        for (int i = 0; i < ne; i++) (void)hipEventDestroy(ev[i]);
+        ctx->tune_cache.emplace_back(sig, tile | ((g8 ? 1 : 0) << 16));
+    }
+    pl.tab.wtile = pl.plain.wtile = tile;
+    pl.small_g8 = g8 && pl.tab.k <= K_G4;
+    return JET_OK;
+}
+
 int refine_batch(jet_context *ctx, int count, const jet_csr *graphs, const jet_params *params, int32_t *const *parts,
                  jet_stats *stats, jet_trace *traces, hipStream_t s)
 {
@@ -4251,6 +4937,8 @@ int refine_batch(jet_context *ctx, int count, const jet_csr *graphs, const jet_p
     Plan pl;
     int st = setup(ctx, L, pl, s, nullptr);
     if (st) return st;
+    st = tune_batch(ctx, pl, NNZ, s);
+    if (st) return st;
     JET_TRY(hipEventRecord(ctx->ev[1], s));
     int launched = 0;
     st = run_loop(ctx, pl, false, s, launched, nullptr);
@@ -4290,6 +4978,8 @@ int refine_batch(jet_context *ctx, int count, const jet_csr *graphs, const jet_p
             sj.ms_total = ms_total;
             sj.ms_refine = ms_refine;
             sj.ms_init = ms_init;
+            sj.batch_tile = pl.tab.wtile;
+            sj.batch_group = (pl.tab.k <= K_G4 && !pl.small_g8) ? 4 : 8;
         }
     }
     return JET_OK;
@@ -4479,7 +5169,8 @@ extern "C" int jet_refine_noalloc(jet_context *ctx, const jet_csr *g, const jet_
     if (!ctx || !g || !params || (!part && g->n > 0)) return JET_EINVAL;
     int st = check_params(g, params);
     if (st) return st;
-    if (params->k < 2 || (params->flags & (JET_F_VALIDATE | JET_F_PROFILE | JET_F_ASYNC))) return JET_EINVAL;
+    if (params->k < 2 || (params->flags & (JET_F_VALIDATE | JET_F_PROFILE | JET_F_ASYNC | JET_F_CONN_TABLE)))
+        return JET_EINVAL;
     if (!ctx->scratch) return JET_EHIP;
     const int32_t tcap = trace && trace->recs ? std::max(trace->cap, 0) : 0;
     if (noalloc_need(g->n, g->nnz, params->k, tcap, ctx->num_cu) > (size_t)JET_NOALLOC_SCRATCH_BYTES)

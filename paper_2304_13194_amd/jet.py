@@ -31,6 +31,7 @@ JET_F_LP_NO_AFTERBURNER = 0x10
 JET_F_TWO_HOP = 0x20
 JET_F_BFS_START = 0x40
 JET_F_ASYNC = 0x80
+JET_F_CONN_TABLE = 0x100
 KIND_LP, KIND_RW, KIND_RS = 1, 2, 3
 
 # Every function declared in include/jet.h.
@@ -70,7 +71,8 @@ class Stats(C.Structure):
                 ("rs_iters", C.c_int32), ("levels", C.c_int32), ("ms_total", C.c_float),
                 ("ms_refine", C.c_float), ("ms_coarsen", C.c_float), ("ms_init", C.c_float),
                 ("ms_gain", C.c_float), ("gain_passes", C.c_int32), ("gain_entries", C.c_int64),
-                ("gain_rows", C.c_int64), ("gain_vertices", C.c_int64)]
+                ("gain_rows", C.c_int64), ("gain_vertices", C.c_int64), ("batch_tile", C.c_int32),
+                ("batch_group", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

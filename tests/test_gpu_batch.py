@@ -181,3 +181,48 @@ def test_batch_errors(J):
     assert e.value.status == J.JET_EINVAL
     stats, traces = J.refine_batch([], [], [])
     assert stats == [] and traces is None
+
+
+def _alone(J, jobs):
+    import torch
+    out = []
+    for name, g, unit, k, level, seed, P0 in jobs:
+        p = torch.from_numpy(P0.copy()).cuda()
+        st, tr, _ = J.refine(_device(J, g, unit), p, k, trace_cap=4096, level=level, seed=seed)
+        out.append((p.cpu().numpy(), st, tr))
+    return out
+
+
+@pytest.mark.parametrize("tile,group", [(0, 8), (1, 4), (64, 4)], ids=["static_g8", "tile1_g4", "tile64_g4"])
+def test_batch_work_queue_choices_identical(J, monkeypatch, tile, group):
+    """Forced autotuner choices (static walks, or work-queue tiles of 1 or 64
+    visits per wave taken from per-XCD sub-queues; 4- or 8-lane groups for
+    small rows) and a reversed batch order all give every graph its result
+    alone, trace included."""
+    jobs = [j for j in rgg_batch(30, 1000, 30000, 6) if j[3] <= 64] + mixed_jobs()[:4]
+    jobs = [j for j in jobs if j[3] <= 64]
+    alone = _alone(J, jobs)
+    monkeypatch.setenv("JET_BATCH_TILE", str(tile))
+    monkeypatch.setenv("JET_BATCH_GROUP", str(group))
+    for order in (list(range(len(jobs))), list(reversed(range(len(jobs))))):
+        batch = [jobs[i] for i in order]
+        parts, stats, traces = _run_batch(J, batch)
+        assert all(s["batch_tile"] == tile and s["batch_group"] == group for s in stats)
+        for j, i in enumerate(order):
+            p, st, tr = alone[i]
+            np.testing.assert_array_equal(parts[j], p, err_msg=jobs[i][0])
+            assert traces[j] == tr and stats[j]["cut"] == st["cut"], jobs[i][0]
+
+
+def test_batch_autotuned_equals_alone(J):
+    """A batch large enough for the autotuner (over 2^20 CSR entries): its
+    measured choice is recorded, and every graph equals its alone run."""
+    jobs = rgg_batch(40, 10000, 100000, 7)
+    assert sum(j[1].nnz for j in jobs) >= 1 << 20
+    alone = _alone(J, jobs)
+    parts, stats, traces = _run_batch(J, jobs)
+    _say(f"autotuned: tile {stats[0]['batch_tile']} visits, groups of {stats[0]['batch_group']} lanes")
+    assert stats[0]["batch_tile"] in (0, 16, 64) and stats[0]["batch_group"] in (4, 8)
+    for (name, *_), part, st, tr, (p, s1, t1) in zip(jobs, parts, stats, traces, alone):
+        np.testing.assert_array_equal(part, p, err_msg=name)
+        assert tr == t1 and st["cut"] == s1["cut"], name

@@ -10,10 +10,11 @@
   the same partition. The partition from the graph-growing start of the
   coarsest graph (JET_F_BFS_START) matches the oracle's the same way.
 * The 512-RGG batch (sum n = 18.0M, sum 2m = 180M): one jet_refine_batch
-  call as timed. Sampled graphs match the oracle's refinement of each graph
-  alone; for every graph the part ids lie in [0, k), and the cut and the
-  largest part weight recomputed from the returned partition equal the
-  reported ones.
+  call as timed (autotuned work-queue tile and group width). Every graph
+  equals jet_refine of that graph alone; sampled graphs match the oracle's
+  refinement of each graph alone; for every graph the part ids lie in
+  [0, k), and the cut and the largest part weight recomputed from the
+  returned partition equal the reported ones.
 * Serving: the first 40 jobs of the serving mix (grids up to 1024^2, R-MAT up
   to scale 20) submitted at once; every result equals jet_partition of the
   same job alone, and sampled jobs equal the oracle's partition.
@@ -132,6 +133,15 @@ def test_rgg512_batch_full_size(J, O):
         assert cut == st["cut"], f"graph {i}: recomputed cut {cut} != {st['cut']}"
         assert int(pw.max()) == st["max_part_weight"] and int(pw.sum()) == g.n, i
         assert bool(st["balanced"]) == (st["max_part_weight"] <= st["o"]), i
+    # every graph equals its refinement alone (jet_refine, one launch sequence each)
+    single = [torch.from_numpy(p.copy()).cuda() for p in p0]
+    for dg, p, prm in zip(dgs, single, params):
+        J.refine(dg, p, **prm)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(host, single)):
+        np.testing.assert_array_equal(a, b.cpu().numpy(), err_msg=f"graph {i}: batch vs alone")
+    _say(f"all {len(spec)} graphs equal their alone runs (tile {stats[0]['batch_tile']}, "
+         f"groups of {stats[0]['batch_group']})")
     # sampled graphs against the oracle: seeded picks plus the largest graph
     u = I.stream(4242, np.arange(9, dtype=np.uint64))
     pick = sorted(set(I.uniform_below(u, len(spec)).tolist()) | {int(np.argmax([n for n, _, _ in spec]))})

@@ -438,3 +438,44 @@ def test_refine_async(J, O):
     with pytest.raises(J.JetError) as e:
         J.refine_batch([dg], [torch.from_numpy(P0.copy()).cuda()], [dict(k=k, flags=J.JET_F_ASYNC, max_iters=10)])
     assert e.value.status == J.JET_EINVAL
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_conn_table_parity(J, O, case):
+    """Section 4.3's persistent connectivity table (JET_F_CONN_TABLE): the
+    Jetlp and rebalancing step outputs from rows built once, and the whole
+    refinement loop with rows kept up to date by Algorithm 6 (decrement,
+    increment with inserts, rebuilds of full rows, whole rebuilds after large
+    move sets), equal the oracle's, which recomputes connectivity from
+    scratch."""
+    import torch
+    name, g, k, level = case
+    TF = J.JET_F_CONN_TABLE
+    dg = J.to_device(g)
+    P = I.random_partition(g.n, k, 100)
+    L = _locks(g.n, 201)
+    exp = O.jetlp(g, P, L, k, level=level)
+    got = J.lp_step(dg, torch.from_numpy(P).cuda(), torch.from_numpy(L).cuda(), k, level=level, flags=TF)
+    for key in ("pd", "F", "conn_s", "F2"):
+        np.testing.assert_array_equal(got[key].cpu().numpy(), exp[key], err_msg=f"{name} {key}")
+    S = _skewed(g, k, 300)
+    for kind in (J.KIND_RW, J.KIND_RS):
+        exp = O.rebalance(g, S, kind, 3, k, level=level, seed=77)
+        got = J.rebalance_step(dg, torch.from_numpy(S).cuda(), kind, 3, k, level=level, seed=77, flags=TF)
+        for key in ("dest", "loss", "slot"):
+            np.testing.assert_array_equal(got[key].cpu().numpy(), exp[key], err_msg=f"{name} {kind} {key}")
+    _compare_refine(J, O, g, k, I.random_partition(g.n, k, 400), name + "_table", level=level, seed=11, flags=TF)
+    _compare_refine(J, O, g, k, _skewed(g, k, 500), name + "_table_skew", level=level, seed=12, flags=TF)
+
+
+def test_conn_table_partition_parity(J, O):
+    """Multilevel partitions with the table on every level equal the oracle's."""
+    import torch
+    for name, g, k, unit in (("stencil16_k8", I.stencil27(16, 16, 16), 8, True),
+                             ("rmat14_k64", I.rmat(14, 16, 6), 64, False),
+                             ("grid96_k5", I.grid2d(96, 96), 5, True)):
+        dg = J.to_device(g, unit_vwgt=unit, unit_adjwgt=unit)
+        part, st, tr = J.partition(dg, k, seed=3, flags=J.JET_F_CONN_TABLE, trace_cap=1 << 14)
+        exp = O.partition(g, k, seed=3, trace_cap=1 << 14)
+        assert tr == exp["trace"], name
+        np.testing.assert_array_equal(part.cpu().numpy(), exp["part"], err_msg=name)
