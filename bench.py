@@ -268,6 +268,13 @@ def measure_workload(J, name, g, w, seed, steps, warmup, ceiling):
     refine_ms = sum(s["ms_refine"] for s, _ in res) / steps
     fin = [r for r in tr0 if r["level"] == 0]
     traffic, tdetail = measured_traffic(name)
+    # second ceiling: one pass that only streams the CSR and gathers the
+    # neighbours' parts (the floor of any pass over every entry)
+    gms = J.gather_ceiling(dg, part, reps=10)
+    gbytes_ceiling = g.nnz * (4 if w["unit"] else 8) + 2 * g.n
+    gather = {"ms": gms, "GBs": gbytes_ceiling / (gms * 1e-3) / 1e9,
+              "kernel": "k_gather_ceiling: every CSR entry (id, weight) read and its neighbour's 16-bit part "
+                        "gathered, 16 entries per thread; algorithmic bytes 4 or 8 per entry + 2 per vertex"}
     return {
         "part": part, "dg": dg, "value": edges_per_step / (ms_per_step * 1e-3), "ms_per_step": ms_per_step,
         "config": {
@@ -295,6 +302,8 @@ def measure_workload(J, name, g, w, seed, steps, warmup, ceiling):
             "traffic_detail": tdetail,
             "copy_ceiling_GBs": ceiling["GBs"] if ceiling else None,
             "frac_of_copy_ceiling": achieved / ceiling["GBs"] if ceiling else None,
+            "gather_ceiling": gather,
+            "frac_of_gather_ceiling": achieved / gather["GBs"] if gather["GBs"] else None,
             "bytes_per_pass": gbytes / passes if passes else None,
             "ms_per_pass": ms_gain / passes if passes else None,
             "passes": passes,

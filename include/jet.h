@@ -330,6 +330,17 @@ int jet_partition(jet_context *ctx, const jet_csr *g, const jet_params *params, 
  * (one look per four relaxation passes). */
 int jet_bfs_start(jet_context *ctx, const jet_csr *g, int32_t k, int32_t *part, void *stream);
 
+/* ---- measurement ------------------------------------------------------------
+ * The floor of a pass that reads every CSR entry of g (neighbour id, edge
+ * weight when given) and gathers the neighbour's part: times one kernel that
+ * does only that (the partition held as 16-bit parts, as refinement holds
+ * it), reps times after one warm-up, and writes the average milliseconds to
+ * *ms (host). `part`: device int32[n] with every entry in [0, 65535]. The
+ * graph's ids are checked first (JET_EGRAPH). Its algorithmic traffic is
+ * 4 nnz (8 nnz with edge weights) + 2 n bytes. */
+int jet_gather_ceiling(jet_context *ctx, const jet_csr *g, const int32_t *part, int32_t reps, float *ms,
+                       void *stream);
+
 /* ---- serving loop ---------------------------------------------------------
  * A server partitions submitted jobs (each one jet_partition call's worth of
  * work) with continuous batching at level granularity. A worker thread owns

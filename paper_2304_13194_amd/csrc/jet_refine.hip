@@ -3386,6 +3386,37 @@ __global__ __launch_bounds__(BLOCK) void k_toff_fill(const int64_t *xadj, int n,
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) toff[n] = blk[gridDim.x];
 }
 
+// ------------------------------------------------------ gather ceiling ----
+// The floor of any pass that reads every CSR entry (neighbour id, edge
+// weight) and gathers its neighbour's part: one pass with nothing else, 16
+// entries per thread (all loads before the gathers), the partition as 16-bit
+// parts (as P_iter is held). Timed by jet_gather_ceiling.
+__global__ __launch_bounds__(BLOCK) void k_gather_ceiling(const int32_t *adj, const int32_t *ew, const uint16_t *P,
+                                                          int64_t nnz, unsigned long long *out)
+{
+    constexpr int U = 16;
+    uint32_t acc = 0;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK * U;
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK * U + threadIdx.x; base < nnz; base += stride) {
+        int u[U], w[U];
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            const int64_t i = base + (int64_t)j * BLOCK;
+            u[j] = i < nnz ? adj[i] : -1;
+            w[j] = i < nnz ? (ew ? ew[i] : 1) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < U; j++) acc += u[j] >= 0 ? (uint32_t)P[u[j]] * (uint32_t)w[j] : 0u;
+    }
+    acc = gsum<64>(acc);
+    if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, (unsigned long long)acc);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_part16(const int32_t *part, int n, uint16_t *P)
+{
+    for (int v = blockIdx.x * BLOCK + threadIdx.x; v < n; v += gridDim.x * BLOCK) P[v] = (uint16_t)part[v];
+}
+
 // --------------------------------------------------------- batch autotuner --
 // A dry-run copy of the batch's state for timing the gain pass: every graph
 // in a Jetlp iteration with nothing locked (its lock stamps are all -1 at
@@ -5219,6 +5250,34 @@ extern "C" int jet_refine_noalloc(jet_context *ctx, const jet_csr *g, const jet_
         trace->total = tot;
     }
     return st;
+}
+
+extern "C" int jet_gather_ceiling(jet_context *ctx, const jet_csr *g, const int32_t *part, int32_t reps, float *ms,
+                                  void *stream)
+{
+    if (!ctx || !g || !part || !ms || reps < 1 || g->n < 1 || g->nnz < 1 || !g->xadj || !g->adjncy) return JET_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    JET_TRY(hipSetDevice(ctx->device));
+    // ids are checked against n (cheap O(nnz) pass) before any gather; the
+    // weight limits guard arithmetic this pass does not do
+    int st = check_graph(ctx, g, 0, s);
+    if (st && st != JET_EOVERFLOW) return st;
+    uint16_t *P = (uint16_t *)ws_get(ctx, WS_P, sizeof(uint16_t) * (size_t)g->n);
+    unsigned long long *out = (unsigned long long *)ws_get(ctx, WS_WDEG, 16);
+    if (!P || !out) return JET_ENOMEM;
+    const int grid_v = std::max(1, std::min(div_up(g->n, BLOCK), ctx->num_cu * 4));
+    k_part16<<<grid_v, BLOCK, 0, s>>>(part, g->n, P);
+    const int grid = ctx->num_cu * 8;
+    k_gather_ceiling<<<grid, BLOCK, 0, s>>>(g->adjncy, g->adjwgt, P, g->nnz, out);  // warm-up
+    JET_TRY(hipEventRecord(ctx->ev[0], s));
+    for (int r = 0; r < reps; r++) k_gather_ceiling<<<grid, BLOCK, 0, s>>>(g->adjncy, g->adjwgt, P, g->nnz, out);
+    JET_TRY(hipEventRecord(ctx->ev[1], s));
+    JET_TRY(hipGetLastError());
+    JET_TRY(stream_wait(ctx, s));
+    float t = 0.f;
+    JET_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]));
+    *ms = t / reps;
+    return JET_OK;
 }
 
 extern "C" int jet_refine_batch(jet_context *ctx, int32_t count, const jet_csr *graphs, const jet_params *params,

@@ -39,7 +39,7 @@ EXPORTS = [
     "jet_context_create", "jet_context_destroy", "jet_strerror", "jet_last_hip_error",
     "jet_refine", "jet_refine_noalloc", "jet_refine_batch", "jet_lp_step", "jet_rebalance_step", "jet_coarsen",
     "jet_hierarchy_levels", "jet_hierarchy_level", "jet_hierarchy_free", "jet_partition",
-    "jet_bfs_start", "jet_server_create", "jet_server_submit", "jet_server_poll", "jet_server_wait",
+    "jet_bfs_start", "jet_gather_ceiling", "jet_server_create", "jet_server_submit", "jet_server_poll", "jet_server_wait",
     "jet_server_info_get", "jet_server_destroy",
 ]
 
@@ -420,6 +420,17 @@ def bfs_start(g: DeviceGraph, k: int, ctx=None):
     s = lib().jet_bfs_start(ctx.h, C.byref(csr), C.c_int32(k), _ptr(part), _stream())
     _check(s, "jet_bfs_start")
     return part
+
+
+def gather_ceiling(g: DeviceGraph, part: torch.Tensor, reps=10, ctx=None) -> float:
+    """jet_gather_ceiling: milliseconds of one pass that only streams the CSR
+    entries of g and gathers their neighbours' parts."""
+    ctx = ctx or default_context()
+    ms = C.c_float()
+    csr = g.csr()
+    _check(lib().jet_gather_ceiling(ctx.h, C.byref(csr), _ptr(part), C.c_int32(reps), C.byref(ms), _stream()),
+           "jet_gather_ceiling")
+    return ms.value
 
 
 class Hierarchy:
