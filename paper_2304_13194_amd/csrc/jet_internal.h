@@ -75,6 +75,11 @@ struct KArgs {
     const int32_t *pg;     // graph of each global part (NULL: one graph)
     const int32_t *tg;     // graph of each tile (NULL: one graph)
     uint16_t *P;           // P_iter (local part ids; k <= KMAX fits 16 bits, halving the gathered bytes)
+    uint8_t *P8;           // P_iter again as bytes when every part id fits one (k <= 256; else NULL):
+                           // the neighbour gathers of the row passes read it (half the footprint)
+    void *mq;              // per vertex (P_iter, P_next) packed: bytes in a uint16 when k <= 256, else
+                           // halves of a uint32; P_next = the selected destination, else P_iter.
+                           // The cut-delta pass reads a neighbour's old and new part in one gather.
     int32_t *best;         // P_best
     int2 *rec;             // Jetlp record: x = (P_s << 16) | (in X ? P_d + 1 : 0), y = F
     int32_t *dest;         // move destination or -1 (kept -1 outside moves)
@@ -173,6 +178,7 @@ struct jet_context {
     hipEvent_t wait_ev = nullptr;     // polled by stream_wait
     jet::Arena part_arena;            // coarse levels of jet_partition calls
     bool poll_wait = true;            // poll instead of sleeping in the runtime (JET_BLOCKING_WAIT=1 turns it off)
+    bool part8 = true;                // byte copy of P_iter for the gathers when k <= 256 (JET_NO_PART8=1 turns it off)
     // jet_refine_noalloc: device address of this device's static scratch
     // array (looked up once per device at context creation); while
     // scratch_on, ws_get carves its slots from it instead of allocating
@@ -193,10 +199,10 @@ enum WsSlot {
     WS_U_XADJ, WS_U_ADJ, WS_U_VW, WS_U_EW, WS_U_VG, WS_U_P0, WS_U_BEST, WS_U_DESC,
     WS_LCNT, WS_LCH, WS_GCONN, WS_LDONE, WS_TH_KEY, WS_TH_VAL, WS_TH_RUN, WS_TH_TMP, WS_WDEG,
     WS_TOFF, WS_TAB, WS_TSIZE, WS_TFAIL, WS_TLIST, WS_TBLK, WS_WQ, WS_TUNE_CTL, WS_TUNE_CNT, WS_TUNE_REC,
-    WS_TUNE_STAT,
+    WS_TUNE_STAT, WS_P8, WS_MQ,
     WS_COUNT = 80
 };
-static_assert(WS_TUNE_STAT < WS_COUNT, "workspace slots");
+static_assert(WS_MQ < WS_COUNT, "workspace slots");
 
 // Grow-only workspace slot; returns nullptr on allocation failure.
 void *ws_get(jet_context *ctx, int slot, size_t bytes);

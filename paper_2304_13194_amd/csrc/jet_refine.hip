@@ -279,6 +279,21 @@ __device__ __forceinline__ int flat_vertex(const KArgs &a, int i)
     return B ? a.bins[i] : i;
 }
 
+// Part of neighbour u for a gather: the byte copy when it exists.
+__device__ __forceinline__ int gpart(const KArgs &a, int u) { return a.P8 ? (int)a.P8[u] : (int)a.P[u]; }
+
+// Packed (old, new) part of a vertex: set when a move is selected (new =
+// destination) and when P_iter changes (old = new = P_iter).
+__device__ __forceinline__ void mq_set(const KArgs &a, int v, int oldp, int newp)
+{
+    if (a.P8) ((uint16_t *)a.mq)[v] = (uint16_t)((oldp << 8) | newp);
+    else ((uint32_t *)a.mq)[v] = ((uint32_t)oldp << 16) | (uint32_t)newp;
+}
+__device__ __forceinline__ uint32_t mq_load(const KArgs &a, int u)
+{
+    return a.P8 ? (uint32_t)((const uint16_t *)a.mq)[u] : ((const uint32_t *)a.mq)[u];
+}
+
 __device__ __forceinline__ int degree_class(int64_t d)
 {
     return d == 0 ? CLS_Z : (d <= S_MAXDEG ? CLS_S : (d <= S2_MAXDEG ? CLS_S2 : (d <= M_MAXDEG ? CLS_M : CLS_L)));
@@ -316,6 +331,8 @@ __global__ __launch_bounds__(BLOCK) void k_init_vertices(KArgs a, const int32_t 
             a.best[v] = p;
         }
         a.P[v] = (uint16_t)p;
+        if (a.P8) a.P8[v] = (uint8_t)p;
+        mq_set(a, v, p, p);
         a.dest[v] = -1;
         a.lock[v] = -1;
         a.slot[v] = 255;
@@ -886,7 +903,7 @@ __device__ __forceinline__ void group_conn_row(const KArgs &a, int64_t s, int de
         if (idx < deg) {
             const int u = a.adj[s + idx];
             const int wt = a.ew ? a.ew[s + idx] : 1;
-            pu[r] = a.P[u];
+            pu[r] = gpart(a, u);
             atomicAdd(&tab[pu[r]], wt);
         }
     }
@@ -910,7 +927,7 @@ __device__ __forceinline__ void conn_load(const KArgs &a, int64_t s, int deg, in
         pu[r] = idx < deg ? a.adj[s + idx] : -1;
     }
 #pragma unroll
-    for (int r = 0; r < R; r++) pu[r] = pu[r] >= 0 ? a.P[pu[r]] : -1;
+    for (int r = 0; r < R; r++) pu[r] = pu[r] >= 0 ? gpart(a, pu[r]) : -1;
 }
 
 template <int R>
@@ -939,7 +956,7 @@ __device__ __forceinline__ void group_fill_row(const KArgs &a, int64_t s, int de
         w[r] = idx < deg ? (a.ew ? a.ew[s + idx] : 1) : 0;
     }
 #pragma unroll
-    for (int r = 0; r < R; r++) u[r] = u[r] >= 0 ? a.P[u[r]] : -1;
+    for (int r = 0; r < R; r++) u[r] = u[r] >= 0 ? gpart(a, u[r]) : -1;
 #pragma unroll
     for (int r = 0; r < R; r++)
         if (u[r] >= 0) atomicAdd(&tab[u[r]], w[r]);
@@ -1089,7 +1106,7 @@ __device__ __forceinline__ void block_fill(const KArgs &a, int v, int32_t *tab)
             w[j] = i < e ? (a.ew ? a.ew[i] : 1) : 0;
         }
 #pragma unroll
-        for (int j = 0; j < UROW; j++) p[j] = u[j] >= 0 ? a.P[u[j]] : -1;
+        for (int j = 0; j < UROW; j++) p[j] = u[j] >= 0 ? gpart(a, u[j]) : -1;
 #pragma unroll
         for (int j = 0; j < UROW; j++)
             if (p[j] >= 0) atomicAdd(&tab[p[j]], w[j]);
@@ -1489,10 +1506,15 @@ __device__ __forceinline__ int after_sum_row(const KArgs &a, int v, int64_t s, i
     return sum;
 }
 
-__device__ __forceinline__ void after_store(const KArgs &a, int v, int pd, int sum)
+// rx: the vertex's record word (P_s << 16 | P_d + 1).
+__device__ __forceinline__ void after_store(const KArgs &a, int v, int rx, int sum)
 {
     if (a.dbg_F2) a.dbg_F2[v] = sum;
-    if (sum >= 0) a.dest[v] = pd;
+    if (sum >= 0) {
+        const int pd = (rx & 0xFFFF) - 1;
+        a.dest[v] = pd;
+        mq_set(a, v, rx >> 16, pd);
+    }
 }
 
 // Jetlp ablation without the afterburner: every vertex of X moves.
@@ -1523,7 +1545,7 @@ __device__ void afterburner_body(const KArgs &a, int b)
                 const int2 r = a.rec[m.v];
                 if ((r.x & 0xFFFF) == 0) return false;  // not in X
                 if (no_afterburner(a, g)) {
-                    after_store(a, m.v, (r.x & 0xFFFF) - 1, 0);
+                    after_store(a, m.v, r.x, 0);
                     return false;
                 }
                 m.ps = r.x;
@@ -1536,7 +1558,7 @@ __device__ void afterburner_body(const KArgs &a, int b)
                 const int ps = t.ps >> 16, pd = (t.ps & 0xFFFF) - 1;
                 int sum = after_sum_row<4>(a, t.v, t.s, t.deg, ps, pd, t.aux, gl, 8);
                 sum = gsum<8>(sum);
-                if (gl == 0) after_store(a, t.v, pd, sum);
+                if (gl == 0) after_store(a, t.v, t.ps, sum);
             });
         return;
     }
@@ -1555,7 +1577,7 @@ __device__ void afterburner_body(const KArgs &a, int b)
                 const int2 r = a.rec[m.v];
                 if ((r.x & 0xFFFF) == 0) return false;  // not in X
                 if (no_afterburner(a, g)) {
-                    after_store(a, m.v, (r.x & 0xFFFF) - 1, 0);
+                    after_store(a, m.v, r.x, 0);
                     return false;
                 }
                 m.ps = r.x;
@@ -1568,7 +1590,7 @@ __device__ void afterburner_body(const KArgs &a, int b)
                 const int ps = t.ps >> 16, pd = (t.ps & 0xFFFF) - 1;
                 int sum = after_sum_row<4>(a, t.v, t.s, t.deg, ps, pd, t.aux, gl, 64);
                 sum = gsum<64>(sum);
-                if (gl == 0) after_store(a, t.v, pd, sum);
+                if (gl == 0) after_store(a, t.v, t.ps, sum);
             },
             unit);
         return;
@@ -1586,13 +1608,13 @@ __device__ void afterburner_body(const KArgs &a, int b)
         if ((r.x & 0xFFFF) == 0) continue;
         const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
         if (no_afterburner(a, g)) {
-            if (threadIdx.x == 0) after_store(a, v, pd, 0);
+            if (threadIdx.x == 0) after_store(a, v, r.x, 0);
             continue;
         }
         const int64_t s = a.xadj[v];
         int sum = after_sum_row<UROW>(a, v, s, (int)(a.xadj[v + 1] - s), ps, pd, r.y, threadIdx.x, BLOCK);
         sum = block_sum<BLOCK>(sum, s_red);
-        if (threadIdx.x == 0) after_store(a, v, pd, sum);
+        if (threadIdx.x == 0) after_store(a, v, r.x, sum);
     }
 }
 
@@ -1606,8 +1628,11 @@ __device__ __forceinline__ int dcut_sum_row(const KArgs &a, int v, int64_t s, in
                                             int stride)
 {
     int delta = 0;
+    const int sh = a.P8 ? 8 : 16;
+    const uint32_t lo = a.P8 ? 0xFFu : 0xFFFFu;
     for (int base = gl; base < deg; base += stride * U) {
-        int u[U], wt[U], du[U], pu[U];
+        int u[U], wt[U];
+        uint32_t q[U];
 #pragma unroll
         for (int j = 0; j < U; j++) {
             const int idx = base + j * stride;
@@ -1615,15 +1640,14 @@ __device__ __forceinline__ int dcut_sum_row(const KArgs &a, int v, int64_t s, in
             wt[j] = idx < deg ? (a.ew ? a.ew[s + idx] : 1) : 0;
         }
 #pragma unroll
-        for (int j = 0; j < U; j++) {
-            du[j] = u[j] >= 0 ? a.dest[u[j]] : -1;
-            pu[j] = u[j] >= 0 ? a.P[u[j]] : -1;
-        }
+        for (int j = 0; j < U; j++) q[j] = u[j] >= 0 ? mq_load(a, u[j]) : 0u;
 #pragma unroll
         for (int j = 0; j < U; j++) {
-            if (u[j] < 0 || (du[j] >= 0 && u[j] < v)) continue;
-            const int pun = du[j] >= 0 ? du[j] : pu[j];
-            delta += wt[j] * ((int)(pn != pun) - (int)(ps != pu[j]));
+            // a neighbour that moves too (new part != old part) and has the
+            // smaller id counts the edge from its own row
+            const int pu = (int)(q[j] >> sh), pun = (int)(q[j] & lo);
+            if (u[j] < 0 || (pun != pu && u[j] < v)) continue;
+            delta += wt[j] * ((int)(pn != pun) - (int)(ps != pu));
         }
     }
     return delta;
@@ -1785,6 +1809,8 @@ __global__ __launch_bounds__(BLOCK) void k_apply(KArgs a)
         const int ps = a.P[v];
         const int vwv = a.vw ? a.vw[v] : 1;
         a.P[v] = (uint16_t)pn;
+        if (a.P8) a.P8[v] = (uint8_t)pn;
+        mq_set(a, v, pn, pn);
         a.dest[v] = -1;
         if (pv.kind == KIND_LP) a.lock[v] = pv.lp_id;
         if (single) {
@@ -1861,7 +1887,7 @@ __device__ __forceinline__ void chunk_fill(const KArgs &a, int64_t s, int len, i
         w[j] = idx < len ? (a.ew ? a.ew[s + idx] : 1) : 0;
     }
 #pragma unroll
-    for (int j = 0; j < U; j++) u[j] = u[j] >= 0 ? a.P[u[j]] : -1;
+    for (int j = 0; j < U; j++) u[j] = u[j] >= 0 ? gpart(a, u[j]) : -1;
 #pragma unroll
     for (int j = 0; j < U; j++)
         if (u[j] >= 0) atomicAdd(&tab[u[j]], w[j]);
@@ -2045,7 +2071,7 @@ __global__ __launch_bounds__(BLOCK) void k_lafter(KArgs a)
         int part = after_sum_row<8>(a, ch.v, ch.s, ch.len, ps, pd, r.y, threadIdx.x, BLOCK);
         part = block_sum<BLOCK>(part, s_red);
         if (threadIdx.x == 0) {
-            if (!ch.multi) after_store(a, ch.v, pd, part);
+            if (!ch.multi) after_store(a, ch.v, r.x, part);
             else if (part) atomicAdd(&a.gf2[ch.li], part);
         }
     }
@@ -2068,13 +2094,13 @@ __global__ __launch_bounds__(BLOCK) void k_lafter_fin(KArgs a)
         const int2 r = a.rec[v];
         if ((r.x & 0xFFFF) == 0) continue;
         if (no_afterburner(a, g)) {
-            after_store(a, v, (r.x & 0xFFFF) - 1, 0);
+            after_store(a, v, r.x, 0);
             continue;
         }
         if (a.xadj[v + 1] - a.xadj[v] <= LCHUNK) continue;
         const int sum = a.gf2[li];
         a.gf2[li] = 0;
-        after_store(a, v, (r.x & 0xFFFF) - 1, sum);
+        after_store(a, v, r.x, sum);
     }
 }
 
@@ -2918,7 +2944,11 @@ __global__ __launch_bounds__(BLOCK) void k_rb_mark(KArgs a)
             if (v >= v1) continue;
             const bool ev = sl[j] != 255 && (sl[j] < ss[j] || (sl[j] == ss[j] && v <= th[j]));
             if (kind == KIND_RW) {
-                if (ev) a.dest[v] = a.rbd[v];
+                if (ev) {
+                    const int d = a.rbd[v];
+                    a.dest[v] = d;
+                    mq_set(a, v, gp[j] - poff, d);
+                }
             } else {
                 a.rsev[v] = ev;
                 if (ev) es += a.vw ? a.vw[v] : 1;
@@ -2973,7 +3003,9 @@ __global__ __launch_bounds__(BLOCK) void k_rs_assign(KArgs a)
                     if (cap[mid] <= pos) lo = mid;
                     else hi = mid;
                 }
-                a.dest[vb + q] = a.Blist[poff + lo];
+                const int d = a.Blist[poff + lo];
+                a.dest[vb + q] = d;
+                mq_set(a, vb + q, a.P[vb + q], d);
             }
             pos += wv[q];
         }
@@ -4149,6 +4181,10 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     const size_t nn = (size_t)std::max(n, 1);
     const size_t kt = (size_t)L.ktot;
     a.P = (uint16_t *)ws_get(ctx, WS_P, nn * 2);
+    const bool part8 = ctx->part8 && L.kmax <= 256;
+    a.P8 = part8 ? (uint8_t *)ws_get(ctx, WS_P8, nn) : nullptr;
+    a.mq = ws_get(ctx, WS_MQ, nn * (part8 ? 2 : 4));
+    if ((part8 && !a.P8) || !a.mq) return JET_ENOMEM;
     a.rec = (int2 *)ws_get(ctx, WS_REC, nn * 8);
     a.dest = (int32_t *)ws_get(ctx, WS_DEST, nn * 4);
     a.lock = (int32_t *)ws_get(ctx, WS_LOCK, nn * 4);
@@ -5100,6 +5136,8 @@ extern "C" int jet_context_create(jet_context **out, int device)
     ctx->graphs = !(ng && ng[0] == '1');
     const char *bw = getenv("JET_BLOCKING_WAIT");
     ctx->poll_wait = !(bw && bw[0] == '1');
+    const char *p8 = getenv("JET_NO_PART8");
+    ctx->part8 = !(p8 && p8[0] == '1');
     e = hipEventCreateWithFlags(&ctx->wait_ev, hipEventDisableTiming);
     if (e != hipSuccess) {
         int st = hip_status(ctx, e);
@@ -5185,6 +5223,7 @@ static size_t noalloc_need(int64_t n, int64_t nnz, int64_t k, int64_t trace_cap,
     size_t b = 0;
     if (trace_cap > 0) b += al(sizeof(jet_trace_rec) * (size_t)trace_cap);
     b += al(nn * 2) + al(nn * 8) + al(nn * 4) + al(nn * 4) + al(nn) + al(nn * 4) + al(nn) + al(nn * 4);
+    b += al(nn) + al(nn * 4);  // byte parts and the packed (old, new) parts, at their largest
     b += al(sizeof(int64_t) * NSTAT * NSHARD) + al(sizeof(int32_t) * (CNT_N + 2)) + al(sizeof(Ctl));
     b += al(sizeof(int64_t) * (4 * (size_t)k + 9)) + al(sizeof(int32_t) * (3 * (size_t)k + 8)) + al(2 * (size_t)k + 16);
     b += al(sizeof(int64_t) * (size_t)k * NSLOT) + al(sizeof(int32_t) * (size_t)(ntile * k)) + al(8 * (size_t)ntile);
