@@ -270,11 +270,13 @@ def measure_workload(J, name, g, w, seed, steps, warmup, ceiling):
     traffic, tdetail = measured_traffic(name)
     # second ceiling: one pass that only streams the CSR and gathers the
     # neighbours' parts (the floor of any pass over every entry)
-    gms = J.gather_ceiling(dg, part, reps=10)
-    gbytes_ceiling = g.nnz * (4 if w["unit"] else 8) + 2 * g.n
+    gms = J.gather_ceiling(dg, part, k, reps=10)
+    pbytes = 1 if k <= 256 else 2
+    gbytes_ceiling = g.nnz * (4 if w["unit"] else 8) + pbytes * g.n
     gather = {"ms": gms, "GBs": gbytes_ceiling / (gms * 1e-3) / 1e9,
-              "kernel": "k_gather_ceiling: every CSR entry (id, weight) read and its neighbour's 16-bit part "
-                        "gathered, 16 entries per thread; algorithmic bytes 4 or 8 per entry + 2 per vertex"}
+              "kernel": f"k_gather_ceiling: every CSR entry (id, weight) read and its neighbour's {8 * pbytes}-bit "
+                        f"part gathered, 16 entries per thread; algorithmic bytes 4 or 8 per entry + {pbytes} per "
+                        f"vertex"}
     return {
         "part": part, "dg": dg, "value": edges_per_step / (ms_per_step * 1e-3), "ms_per_step": ms_per_step,
         "config": {

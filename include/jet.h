@@ -333,12 +333,14 @@ int jet_bfs_start(jet_context *ctx, const jet_csr *g, int32_t k, int32_t *part, 
 /* ---- measurement ------------------------------------------------------------
  * The floor of a pass that reads every CSR entry of g (neighbour id, edge
  * weight when given) and gathers the neighbour's part: times one kernel that
- * does only that (the partition held as 16-bit parts, as refinement holds
- * it), reps times after one warm-up, and writes the average milliseconds to
- * *ms (host). `part`: device int32[n] with every entry in [0, 65535]. The
- * graph's ids are checked first (JET_EGRAPH). Its algorithmic traffic is
- * 4 nnz (8 nnz with edge weights) + 2 n bytes. */
-int jet_gather_ceiling(jet_context *ctx, const jet_csr *g, const int32_t *part, int32_t reps, float *ms,
+ * does only that, with the partition held as refinement holds it for k parts
+ * (one byte per vertex when k <= 256, else 16 bits), reps times after one
+ * warm-up, and writes the average milliseconds to *ms (host). `part`: device
+ * int32[n] with every entry in [0, k). Returns JET_EINVAL (NULL pointers,
+ * reps < 1, k < 1), JET_ELIMIT (k > 16384); the graph's ids are checked
+ * first (JET_EGRAPH). Its algorithmic traffic is 4 nnz (8 nnz with edge
+ * weights) + n (k <= 256) or 2 n bytes. */
+int jet_gather_ceiling(jet_context *ctx, const jet_csr *g, const int32_t *part, int32_t k, int32_t reps, float *ms,
                        void *stream);
 
 /* ---- serving loop ---------------------------------------------------------

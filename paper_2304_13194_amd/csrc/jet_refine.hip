@@ -294,6 +294,17 @@ __device__ __forceinline__ uint32_t mq_load(const KArgs &a, int u)
     return a.P8 ? (uint32_t)((const uint16_t *)a.mq)[u] : ((const uint32_t *)a.mq)[u];
 }
 
+// Compact Jetlp record of a vertex for the afterburner's gathers, when
+// every part id fits a byte (k <= 256): P_s in bits 31..24, P_d (in X) or
+// P_s (not in X; P_d != P_s in X) in bits 23..16, F saturated to int16 in
+// bits 15..0. A saturated F still orders exactly against any F that is not
+// beyond the same bound; the full F is read only in that rare case.
+__device__ __forceinline__ void rq_set(const KArgs &a, int v, int ps, int pq, int F)
+{
+    const int fs = F > 32767 ? 32767 : (F < -32768 ? -32768 : F);
+    ((uint32_t *)a.rq)[v] = ((uint32_t)ps << 24) | ((uint32_t)pq << 16) | ((uint32_t)fs & 0xFFFFu);
+}
+
 __device__ __forceinline__ int degree_class(int64_t d)
 {
     return d == 0 ? CLS_Z : (d <= S_MAXDEG ? CLS_S : (d <= S2_MAXDEG ? CLS_S2 : (d <= M_MAXDEG ? CLS_M : CLS_L)));
@@ -1140,6 +1151,7 @@ __device__ __forceinline__ bool gain_finish(const KArgs &a, int v, int ps, uint6
         if (inx) r.x |= pd + 1;
     }
     a.rec[v] = r;
+    if (a.rq) rq_set(a, v, ps, inx ? pd : ps, r.y);
     if (a.dbg_F) {
         a.dbg_F[v] = F;
         a.dbg_cs[v] = cs;
@@ -1151,6 +1163,7 @@ __device__ __forceinline__ bool gain_finish(const KArgs &a, int v, int ps, uint6
 __device__ __forceinline__ void gain_locked(const KArgs &a, int v, int ps)
 {
     a.rec[v] = make_int2(ps << 16, 0);
+    if (a.rq) rq_set(a, v, ps, ps, 0);
     if (a.dbg_F) {
         a.dbg_F[v] = INT64_MIN;
         a.dbg_cs[v] = 0;
@@ -1483,6 +1496,35 @@ __device__ __forceinline__ int after_sum_row(const KArgs &a, int v, int64_t s, i
                                              int stride)
 {
     int sum = 0;
+    if (a.rq) {
+        // one 4-byte gather per neighbour (parts and saturated F)
+        const int *Fs = (const int *)a.rec + 1;  // full F of vertex u at Fs[2 u]
+        for (int base = gl; base < deg; base += stride * U) {
+            int u[U], wt[U];
+            uint32_t q[U];
+#pragma unroll
+            for (int j = 0; j < U; j++) {
+                const int idx = base + j * stride;
+                u[j] = idx < deg ? a.adj[s + idx] : -1;
+                wt[j] = idx < deg ? (a.ew ? a.ew[s + idx] : 1) : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < U; j++) q[j] = u[j] >= 0 ? ((const uint32_t *)a.rq)[u[j]] : 0u;
+#pragma unroll
+            for (int j = 0; j < U; j++) {
+                if (u[j] < 0) continue;
+                int qp = (int)(q[j] >> 24);
+                const int pqu = (int)((q[j] >> 16) & 0xFFu);
+                if (pqu != qp) {
+                    int Fu = (int)(int16_t)(q[j] & 0xFFFFu);
+                    if ((Fu == 32767 && Fv >= 32767) || (Fu == -32768 && Fv <= -32768)) Fu = Fs[2 * (int64_t)u[j]];
+                    if (Fu > Fv || (Fu == Fv && u[j] < v)) qp = pqu;
+                }
+                sum += qp == pd ? wt[j] : (qp == ps ? -wt[j] : 0);
+            }
+        }
+        return sum;
+    }
     for (int base = gl; base < deg; base += stride * U) {
         int u[U], wt[U];
         int2 ru[U];
@@ -3421,9 +3463,11 @@ __global__ __launch_bounds__(BLOCK) void k_toff_fill(const int64_t *xadj, int n,
 // ------------------------------------------------------ gather ceiling ----
 // The floor of any pass that reads every CSR entry (neighbour id, edge
 // weight) and gathers its neighbour's part: one pass with nothing else, 16
-// entries per thread (all loads before the gathers), the partition as 16-bit
-// parts (as P_iter is held). Timed by jet_gather_ceiling.
-__global__ __launch_bounds__(BLOCK) void k_gather_ceiling(const int32_t *adj, const int32_t *ew, const uint16_t *P,
+// entries per thread (all loads before the gathers), the partition as
+// refinement holds it (T = uint8_t for k <= 256, else uint16_t). Timed by
+// jet_gather_ceiling.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_gather_ceiling(const int32_t *adj, const int32_t *ew, const T *P,
                                                           int64_t nnz, unsigned long long *out)
 {
     constexpr int U = 16;
@@ -3444,9 +3488,10 @@ __global__ __launch_bounds__(BLOCK) void k_gather_ceiling(const int32_t *adj, co
     if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, (unsigned long long)acc);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_part16(const int32_t *part, int n, uint16_t *P)
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_part_narrow(const int32_t *part, int n, T *P)
 {
-    for (int v = blockIdx.x * BLOCK + threadIdx.x; v < n; v += gridDim.x * BLOCK) P[v] = (uint16_t)part[v];
+    for (int v = blockIdx.x * BLOCK + threadIdx.x; v < n; v += gridDim.x * BLOCK) P[v] = (T)part[v];
 }
 
 // --------------------------------------------------------- batch autotuner --
@@ -4184,7 +4229,8 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     const bool part8 = ctx->part8 && L.kmax <= 256;
     a.P8 = part8 ? (uint8_t *)ws_get(ctx, WS_P8, nn) : nullptr;
     a.mq = ws_get(ctx, WS_MQ, nn * (part8 ? 2 : 4));
-    if ((part8 && !a.P8) || !a.mq) return JET_ENOMEM;
+    a.rq = part8 ? (uint32_t *)ws_get(ctx, WS_RQ, nn * 4) : nullptr;
+    if ((part8 && (!a.P8 || !a.rq)) || !a.mq) return JET_ENOMEM;
     a.rec = (int2 *)ws_get(ctx, WS_REC, nn * 8);
     a.dest = (int32_t *)ws_get(ctx, WS_DEST, nn * 4);
     a.lock = (int32_t *)ws_get(ctx, WS_LOCK, nn * 4);
@@ -5223,7 +5269,7 @@ static size_t noalloc_need(int64_t n, int64_t nnz, int64_t k, int64_t trace_cap,
     size_t b = 0;
     if (trace_cap > 0) b += al(sizeof(jet_trace_rec) * (size_t)trace_cap);
     b += al(nn * 2) + al(nn * 8) + al(nn * 4) + al(nn * 4) + al(nn) + al(nn * 4) + al(nn) + al(nn * 4);
-    b += al(nn) + al(nn * 4);  // byte parts and the packed (old, new) parts, at their largest
+    b += al(nn) + al(nn * 4) + al(nn * 4);  // byte parts, packed (old, new) parts and records, at their largest
     b += al(sizeof(int64_t) * NSTAT * NSHARD) + al(sizeof(int32_t) * (CNT_N + 2)) + al(sizeof(Ctl));
     b += al(sizeof(int64_t) * (4 * (size_t)k + 9)) + al(sizeof(int32_t) * (3 * (size_t)k + 8)) + al(2 * (size_t)k + 16);
     b += al(sizeof(int64_t) * (size_t)k * NSLOT) + al(sizeof(int32_t) * (size_t)(ntile * k)) + al(8 * (size_t)ntile);
@@ -5291,25 +5337,33 @@ extern "C" int jet_refine_noalloc(jet_context *ctx, const jet_csr *g, const jet_
     return st;
 }
 
-extern "C" int jet_gather_ceiling(jet_context *ctx, const jet_csr *g, const int32_t *part, int32_t reps, float *ms,
-                                  void *stream)
+extern "C" int jet_gather_ceiling(jet_context *ctx, const jet_csr *g, const int32_t *part, int32_t k, int32_t reps,
+                                  float *ms, void *stream)
 {
-    if (!ctx || !g || !part || !ms || reps < 1 || g->n < 1 || g->nnz < 1 || !g->xadj || !g->adjncy) return JET_EINVAL;
+    if (!ctx || !g || !part || !ms || reps < 1 || k < 1 || g->n < 1 || g->nnz < 1 || !g->xadj || !g->adjncy)
+        return JET_EINVAL;
+    if (k > KMAX) return JET_ELIMIT;
     hipStream_t s = (hipStream_t)stream;
     JET_TRY(hipSetDevice(ctx->device));
     // ids are checked against n (cheap O(nnz) pass) before any gather; the
     // weight limits guard arithmetic this pass does not do
     int st = check_graph(ctx, g, 0, s);
     if (st && st != JET_EOVERFLOW) return st;
-    uint16_t *P = (uint16_t *)ws_get(ctx, WS_P, sizeof(uint16_t) * (size_t)g->n);
+    void *P = ws_get(ctx, WS_P, sizeof(uint16_t) * (size_t)g->n);
     unsigned long long *out = (unsigned long long *)ws_get(ctx, WS_WDEG, 16);
     if (!P || !out) return JET_ENOMEM;
     const int grid_v = std::max(1, std::min(div_up(g->n, BLOCK), ctx->num_cu * 4));
-    k_part16<<<grid_v, BLOCK, 0, s>>>(part, g->n, P);
     const int grid = ctx->num_cu * 8;
-    k_gather_ceiling<<<grid, BLOCK, 0, s>>>(g->adjncy, g->adjwgt, P, g->nnz, out);  // warm-up
+    const bool bytes = k <= 256;
+    auto pass = [&]() {
+        if (bytes) k_gather_ceiling<uint8_t><<<grid, BLOCK, 0, s>>>(g->adjncy, g->adjwgt, (const uint8_t *)P, g->nnz, out);
+        else k_gather_ceiling<uint16_t><<<grid, BLOCK, 0, s>>>(g->adjncy, g->adjwgt, (const uint16_t *)P, g->nnz, out);
+    };
+    if (bytes) k_part_narrow<uint8_t><<<grid_v, BLOCK, 0, s>>>(part, g->n, (uint8_t *)P);
+    else k_part_narrow<uint16_t><<<grid_v, BLOCK, 0, s>>>(part, g->n, (uint16_t *)P);
+    pass();  // warm-up
     JET_TRY(hipEventRecord(ctx->ev[0], s));
-    for (int r = 0; r < reps; r++) k_gather_ceiling<<<grid, BLOCK, 0, s>>>(g->adjncy, g->adjwgt, P, g->nnz, out);
+    for (int r = 0; r < reps; r++) pass();
     JET_TRY(hipEventRecord(ctx->ev[1], s));
     JET_TRY(hipGetLastError());
     JET_TRY(stream_wait(ctx, s));

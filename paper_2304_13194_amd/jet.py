@@ -422,13 +422,15 @@ def bfs_start(g: DeviceGraph, k: int, ctx=None):
     return part
 
 
-def gather_ceiling(g: DeviceGraph, part: torch.Tensor, reps=10, ctx=None) -> float:
+def gather_ceiling(g: DeviceGraph, part: torch.Tensor, k: int, reps=10, ctx=None) -> float:
     """jet_gather_ceiling: milliseconds of one pass that only streams the CSR
-    entries of g and gathers their neighbours' parts."""
+    entries of g and gathers their neighbours' parts (held as refinement holds
+    them for k parts)."""
     ctx = ctx or default_context()
     ms = C.c_float()
     csr = g.csr()
-    _check(lib().jet_gather_ceiling(ctx.h, C.byref(csr), _ptr(part), C.c_int32(reps), C.byref(ms), _stream()),
+    _check(lib().jet_gather_ceiling(ctx.h, C.byref(csr), _ptr(part), C.c_int32(k), C.c_int32(reps), C.byref(ms),
+                                    _stream()),
            "jet_gather_ceiling")
     return ms.value
 

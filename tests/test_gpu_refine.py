@@ -63,6 +63,15 @@ def stars(sizes, seed=5):
     return I.csr_from_edges(n, key // n, key % n)
 
 
+def _reweight(g, lo, hi, seed):
+    """g with symmetric edge weights drawn from [lo, hi)."""
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.xadj))
+    keep = src < g.adjncy
+    u, v = src[keep], g.adjncy[keep].astype(np.int64)
+    w = (lo + I.uniform_below(I.stream(seed, np.arange(u.size, dtype=np.uint64)), hi - lo)).astype(np.int32)
+    return I.csr_from_edges(g.n, u, v, w)
+
+
 def cases():
     """(name, graph, k, level) covering every kernel role."""
     out = [
@@ -82,6 +91,12 @@ def cases():
         ("stars_long_k5000", stars([1025, 4100, 9000]), 5000, 0),
         ("stars_long_k16384", stars([1025, 4100]), 16384, 0),
         ("rgg3000_k16", I.rgg(3000, 9), 16, 0),
+        # gains beyond the afterburner's 16-bit packed F: equal weights make
+        # many equal F above the bound (the full F breaks those ties), and
+        # large random weights spread F on both sides of it
+        ("grid48_w40000_k4", _reweight(I.grid2d(48, 48), 40000, 40001, 1), 4, 0),
+        ("rmat12_w20k_70k_k200_l1", _reweight(I.rmat(12, 8, 9), 20000, 70000, 2), 200, 1),
+        ("rmat12_w20k_70k_k300", _reweight(I.rmat(12, 8, 9), 20000, 70000, 3), 300, 0),
     ]
     for s in range(6):
         g = I.small_random_graph(30 + 11 * s, 0.15, 600 + s, wmax=1 + s % 5, vwmax=1 + s % 3)
@@ -479,3 +494,22 @@ def test_conn_table_partition_parity(J, O):
         exp = O.partition(g, k, seed=3, trace_cap=1 << 14)
         assert tr == exp["trace"], name
         np.testing.assert_array_equal(part.cpu().numpy(), exp["part"], err_msg=name)
+
+
+@pytest.mark.parametrize("k", [64, 256, 257, 5000])
+def test_gather_ceiling_runs_and_rejects(J, k):
+    """jet_gather_ceiling (byte parts for k <= 256, else 16-bit) times a pass
+    and rejects bad arguments before any device work."""
+    import torch
+    g = I.rmat(12, 8, 3)
+    _say(f"gather ceiling rmat12 k={k}")
+    dg = J.to_device(g)
+    part = torch.from_numpy(I.random_partition(g.n, k, 1)).cuda()
+    ms = J.gather_ceiling(dg, part, k, reps=2)
+    assert ms > 0
+    with pytest.raises(J.JetError) as e:
+        J.gather_ceiling(dg, part, 0, reps=2)
+    assert e.value.status == J.JET_EINVAL
+    with pytest.raises(J.JetError) as e:
+        J.gather_ceiling(dg, part, 16385, reps=2)
+    assert e.value.status == J.JET_ELIMIT
