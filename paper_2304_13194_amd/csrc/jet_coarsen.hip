@@ -481,15 +481,17 @@ __device__ __forceinline__ int64_t member_entry(int64_t s0, int d0, int64_t s1, 
 __global__ __launch_bounds__(CB) void k_cclass(int nc, const int32_t *bound, int32_t *listM, int32_t *listL,
                                                int32_t *cnt, int64_t *ltot)
 {
+    __shared__ int32_t s_cnt[CB / 64 + 1];
     const int stride = gridDim.x * CB;
     const int nloop = (nc + stride - 1) / stride;
     for (int it = 0; it < nloop; it++) {
         const int c = it * stride + blockIdx.x * CB + threadIdx.x;
         const int b = c < nc ? bound[c] : 0;
-        wave_append(c < nc && b > CS_MAX && b <= CM_MAX, &cnt[0], listM, c);
+        block_append<CB>(c < nc && b > CS_MAX && b <= CM_MAX, &cnt[0], listM, c, s_cnt);
         const bool isL = c < nc && b > CM_MAX;
-        wave_append(isL, &cnt[1], listL, c);
-        if (isL) atomicAdd((unsigned long long *)ltot, (unsigned long long)(2 * (int64_t)b));
+        block_append<CB>(isL, &cnt[1], listL, c, s_cnt);
+        const int64_t lw = gsum<64>(isL ? 2 * (int64_t)b : (int64_t)0);  // one atomic per wave
+        if ((threadIdx.x & 63) == 0 && lw) atomicAdd((unsigned long long *)ltot, (unsigned long long)lw);
     }
 }
 
@@ -619,32 +621,80 @@ __global__ __launch_bounds__(CB) void k_crow_medium(const int32_t *list, int cnt
     }
 }
 
-// Exclusive scan of 2 * bound over the large rows (single block).
-__global__ __launch_bounds__(CB) void k_cl_offsets(const int32_t *listL, int cntL, const int32_t *bound, int64_t *toffL)
+// Large coarse rows (more than CM_MAX member entries) are spread over the
+// grid: the member entries in chunks of LCC per block for the insertion, the
+// row's table in chunks of LTC slots per block for the extraction, so a hub
+// no longer waits on one block. A table slot holds (key << 32) | weight sum,
+// or LEMPTY; insertions race only on slot placement, and rows are compared
+// and used as sets (every consumer is independent of the order of a row's
+// entries).
+constexpr int LCC = 4096;
+constexpr int LTC = 4096;
+constexpr uint64_t LEMPTY = ~0ull;
+
+// Exclusive scans over the large rows (single block): table offsets (2 *
+// bound slots each), insertion chunks and extraction chunks; also zeroes the
+// rows' distinct-key counts and output cursors.
+__global__ __launch_bounds__(CB) void k_cl_offsets(const int32_t *listL, int cntL, const int32_t *bound, int64_t *toffL,
+                                                   int32_t *ich, int32_t *ech, int32_t *ccount, int32_t *cur)
 {
     __shared__ int64_t s_scan[CB / 64];
+    __shared__ int32_t s_scan32[CB / 64];
     int64_t carry = 0;
+    int32_t ci = 0, ce = 0;
     for (int base = 0; base < cntL; base += CB) {
         const int i = base + threadIdx.x;
-        const int64_t x = i < cntL ? 2 * (int64_t)bound[listL[i]] : 0;
+        const int b = i < cntL ? bound[listL[i]] : 0;
+        const int64_t x = 2 * (int64_t)b;
         int64_t tot;
         const int64_t ex = block_excl_scan<CB>(x, s_scan, tot);
-        if (i < cntL) toffL[i] = carry + ex;
+        int32_t ti, te;
+        const int32_t exi = block_excl_scan<CB>((int32_t)((b + LCC - 1) / LCC), s_scan32, ti);
+        const int32_t exe = block_excl_scan<CB>((int32_t)((x + LTC - 1) / LTC), s_scan32, te);
+        if (i < cntL) {
+            toffL[i] = carry + ex;
+            ich[i] = ci + exi;
+            ech[i] = ce + exe;
+            ccount[listL[i]] = 0;
+            cur[i] = 0;
+        }
         carry += tot;
+        ci += ti;
+        ce += te;
     }
-    if (threadIdx.x == 0) toffL[cntL] = carry;
+    if (threadIdx.x == 0) {
+        toffL[cntL] = carry;
+        ich[cntL] = ci;
+        ech[cntL] = ce;
+    }
 }
 
-// Large rows: one block per row inserts into a global open-addressed table of
-// 2 * bound slots and counts the distinct keys.
+// Largest r in [0, cnt) with off[r] <= x (off[0] = 0 <= x).
+__device__ __forceinline__ int chunk_row(const int32_t *off, int cnt, int x)
+{
+    int lo = 0, hi = cnt;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Insertion: one block per chunk of LCC member entries of a large row, into
+// the row's global open-addressed table of 2 * bound slots; the distinct
+// keys a block claims are added to the row's count.
 __global__ __launch_bounds__(CB) void k_crow_large_insert(const int32_t *listL, int cntL, const int64_t *toffL,
-                                                          const int32_t *mem0, const int32_t *mem1,
+                                                          const int32_t *ich, const int32_t *mem0, const int32_t *mem1,
                                                           const int64_t *xadj, const int32_t *adj, const int32_t *ew,
-                                                          const int32_t *map, int32_t *tkey, int32_t *tval,
+                                                          const int32_t *map, unsigned long long *tab,
                                                           int32_t *ccount, int32_t *overflow)
 {
     __shared__ int32_t s_red[CB / 64];
-    for (int r = blockIdx.x; r < cntL; r += gridDim.x) {
+    constexpr int U = LCC / CB;
+    const int nch = ich[cntL];
+    for (int ci = blockIdx.x; ci < nch; ci += gridDim.x) {
+        const int r = chunk_row(ich, cntL, ci);
         const int c = listL[r];
         const int m0 = mem0[c], m1 = mem1[c];
         const int64_t base = toffL[r];
@@ -654,46 +704,75 @@ __global__ __launch_bounds__(CB) void k_crow_large_insert(const int32_t *listL, 
         int64_t s1 = 0;
         int d1 = 0;
         if (m1 >= 0) { s1 = xadj[m1]; d1 = (int)(xadj[m1 + 1] - s1); }
-        int claimed = 0;
-        for (int idx = threadIdx.x; idx < d0 + d1; idx += CB) {
+        const int lo = (ci - ich[r]) * LCC, hi = min(lo + LCC, d0 + d1);
+        int cu[U], w[U];
+#pragma unroll
+        for (int q = 0; q < U; q++) {
+            const int idx = lo + q * CB + threadIdx.x;
             const int64_t e = member_entry(s0, d0, s1, idx);
-            const int cu = map[adj[e]];
-            if (cu == c) continue;
-            const int w = ew ? ew[e] : 1;
-            if (T == 0) { *overflow = 1; break; }
-            uint32_t h = ((uint32_t)cu * 2654435761u) % T;
+            cu[q] = idx < hi ? adj[e] : -1;
+            w[q] = idx < hi ? (ew ? ew[e] : 1) : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < U; q++) cu[q] = cu[q] >= 0 ? map[cu[q]] : -1;
+        int claimed = 0;
+        for (int q = 0; q < U; q++) {
+            if (cu[q] < 0 || cu[q] == c) continue;
+            const unsigned long long want = ((unsigned long long)(uint32_t)cu[q] << 32) | (uint32_t)w[q];
+            uint32_t h = ((uint32_t)cu[q] * 2654435761u) % T;
             for (uint32_t probe = 0;; probe++) {
                 if (probe == T) { *overflow = 1; break; }  // cannot happen: <= bound keys in 2 * bound slots
-                const int32_t old = atomicCAS(&tkey[base + h], -1, cu);
-                if (old == -1) { claimed++; atomicAdd(&tval[base + h], w); break; }
-                if (old == cu) { atomicAdd(&tval[base + h], w); break; }
+                const unsigned long long old = atomicCAS(&tab[base + h], (unsigned long long)LEMPTY, want);
+                if (old == LEMPTY) { claimed++; break; }
+                // coarse edge weights stay below 2^31 (multilevel limit): no carry into the key
+                if ((uint32_t)(old >> 32) == (uint32_t)cu[q]) { atomicAdd(&tab[base + h], (unsigned long long)(uint32_t)w[q]); break; }
                 h = h + 1 == T ? 0 : h + 1;
             }
         }
         const int tot = block_sum<CB>(claimed, s_red);
-        if (threadIdx.x == 0) ccount[c] = tot;
+        if (threadIdx.x == 0 && tot) atomicAdd(&ccount[c], tot);
     }
 }
 
+// Extraction: one block per chunk of LTC table slots of a large row; each
+// wave appends its occupied slots at the row's cursor.
 __global__ __launch_bounds__(CB) void k_crow_large_extract(const int32_t *listL, int cntL, const int64_t *toffL,
-                                                           const int32_t *tkey, const int32_t *tval,
-                                                           const int64_t *cxadj, int32_t *cadj, int32_t *cew)
+                                                           const int32_t *ech, const unsigned long long *tab,
+                                                           int32_t *cur, const int64_t *cxadj, int32_t *cadj,
+                                                           int32_t *cew)
 {
-    __shared__ int64_t s_scan[CB / 64];
-    for (int r = blockIdx.x; r < cntL; r += gridDim.x) {
+    constexpr int U = LTC / CB;
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int nch = ech[cntL];
+    for (int ci = blockIdx.x; ci < nch; ci += gridDim.x) {
+        const int r = chunk_row(ech, cntL, ci);
         const int c = listL[r];
         const int64_t base = toffL[r], T = toffL[r + 1] - base;
-        int64_t out = cxadj[c];
-        for (int64_t j0 = 0; j0 < T; j0 += CB) {
-            const int64_t j = j0 + threadIdx.x;
-            const int occ = j < T && tkey[base + j] >= 0;
-            int64_t tot;
-            const int64_t pos = block_excl_scan<CB>((int64_t)occ, s_scan, tot);
+        const int64_t j0 = (int64_t)(ci - ech[r]) * LTC;
+        unsigned long long v[U];
+        int cnt = 0;
+#pragma unroll
+        for (int q = 0; q < U; q++) {
+            const int64_t j = j0 + q * CB + threadIdx.x;
+            v[q] = j < T ? tab[base + j] : LEMPTY;
+            cnt += __popcll(__ballot(v[q] != LEMPTY));
+        }
+        int wbase = 0;
+        if (lane == 0 && cnt) wbase = atomicAdd(&cur[r], cnt);
+        wbase = __shfl(wbase, 0, 64);
+        const int64_t out = cxadj[c] + wbase;
+        int pos = 0;
+#pragma unroll
+        for (int q = 0; q < U; q++) {
+            const bool occ = v[q] != LEMPTY;
+            const uint64_t m = __ballot(occ);
             if (occ) {
-                cadj[out + pos] = tkey[base + j];
-                cew[out + pos] = tval[base + j];
+                const int64_t o = out + pos + __popcll(m & below);
+                cadj[o] = (int32_t)(v[q] >> 32);
+                cew[o] = (int32_t)(uint32_t)v[q];
             }
-            out += tot;
+            pos += __popcll(m);
         }
     }
 }
@@ -952,18 +1031,19 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     const int nM = hc[0], nL = hc[1];
     const int64_t lslots = *(int64_t *)(hc + 4);
     int64_t *toffL = nullptr;
-    int32_t *tkey = nullptr, *tval = nullptr;
+    unsigned long long *ltab = nullptr;
+    int32_t *ich = nullptr, *ech = nullptr, *lcur = nullptr;
     if (nL > 0) {
         toffL = (int64_t *)ws_get(ctx, WS_C6, ((size_t)nL + 1) * 8);
-        tkey = (int32_t *)ws_get(ctx, WS_C10, (size_t)lslots * 4);
-        tval = (int32_t *)ws_get(ctx, WS_C11, (size_t)lslots * 4);
-        if (!toffL || !tkey || !tval) return JET_ENOMEM;
-        JET_TRY(hipMemsetAsync(tkey, 0xFF, (size_t)lslots * 4, s));
-        JET_TRY(hipMemsetAsync(tval, 0, (size_t)lslots * 4, s));
-        k_cl_offsets<<<1, CB, 0, s>>>(listL, nL, bound, toffL);
-        k_crow_large_insert<<<std::min(nL, ctx->num_cu * 4), CB, 0, s>>>(listL, nL, toffL, mem0, mem1, f->xadj,
-                                                                         f->adjncy, f->adjwgt, map, tkey, tval, ccount,
-                                                                         ccnt + 2);
+        ltab = (unsigned long long *)ws_get(ctx, WS_C10, (size_t)lslots * 8);
+        ich = (int32_t *)ws_get(ctx, WS_C11, ((size_t)nL + 1) * 4 * 3);
+        if (!toffL || !ltab || !ich) return JET_ENOMEM;
+        ech = ich + nL + 1;
+        lcur = ech + nL + 1;
+        JET_TRY(hipMemsetAsync(ltab, 0xFF, (size_t)lslots * 8, s));
+        k_cl_offsets<<<1, CB, 0, s>>>(listL, nL, bound, toffL, ich, ech, ccount, lcur);
+        k_crow_large_insert<<<ctx->num_cu * 8, CB, 0, s>>>(listL, nL, toffL, ich, mem0, mem1, f->xadj, f->adjncy,
+                                                            f->adjwgt, map, ltab, ccount, ccnt + 2);
     }
     const int gsmall = grid_for(ctx, nc, CB / 8);
     const size_t lds_m = 2 * CM_T * sizeof(int32_t);
@@ -987,8 +1067,7 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
         k_crow_medium<true><<<std::min(nM, ctx->num_cu * 4), CB, lds_m, s>>>(
             listM, nM, mem0, mem1, f->xadj, f->adjncy, f->adjwgt, map, ccount, cxadj, cadj, cew, ccnt + 2);
     if (nL > 0)
-        k_crow_large_extract<<<std::min(nL, ctx->num_cu * 4), CB, 0, s>>>(listL, nL, toffL, tkey, tval, cxadj, cadj,
-                                                                          cew);
+        k_crow_large_extract<<<ctx->num_cu * 8, CB, 0, s>>>(listL, nL, toffL, ech, ltab, lcur, cxadj, cadj, cew);
     JET_TRY(hipGetLastError());
     c->n = nc;
     c->reserved = 0;

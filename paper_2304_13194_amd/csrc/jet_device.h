@@ -76,6 +76,30 @@ __device__ __forceinline__ void wave_append(bool pred, int32_t *counter, int32_t
     if (pred) list[base + __popcll(m & ((1ull << l) - 1ull))] = value;
 }
 
+// Block-wide append: like wave_append with one atomic per block. Every
+// thread of the block (blockDim.x == NT) must call; s_cnt holds NT/64 + 1
+// ints.
+template <int NT>
+__device__ __forceinline__ void block_append(bool pred, int32_t *counter, int32_t *list, int32_t value, int32_t *s_cnt)
+{
+    const uint64_t m = __ballot(pred);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) s_cnt[w] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int i = 0; i < NT / 64; i++) {
+            const int c = s_cnt[i];
+            s_cnt[i] = t;
+            t += c;
+        }
+        s_cnt[NT / 64] = t ? atomicAdd(counter, t) : 0;
+    }
+    __syncthreads();
+    if (pred) list[s_cnt[NT / 64] + s_cnt[w] + __popcll(m & ((1ull << l) - 1ull))] = value;
+    __syncthreads();
+}
+
 // Block-wide (blockDim.x == NT) reductions / exclusive scan. `scratch` must
 // hold NT/64 elements; every thread of the block must call.
 template <int NT, typename T>

@@ -369,12 +369,33 @@ __global__ __launch_bounds__(BLOCK) void k_init_vertices(KArgs a, const int32_t 
             if (s_w[p]) atomicAdd((unsigned long long *)&a.w[p], (unsigned long long)(int64_t)s_w[p]);
 }
 
+// Row marks for the edge pass: mark[i] = the row holding CSR entry i * MARK
+// (the largest v with xadj[v] <= i * MARK), for i < nmark = nnz / MARK + 1,
+// so a run's row search starts within a few rows instead of over all n.
+constexpr int MARK = 4096;
+__global__ __launch_bounds__(BLOCK) void k_row_marks(const int64_t *xadj, int n, int64_t nmark, int32_t *mark)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nmark; i += (int64_t)gridDim.x * BLOCK) {
+        const int64_t e = i * MARK;
+        int lo = 0, hi = n + 1;  // largest lo with xadj[lo] <= e (xadj[0] = 0 <= e)
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (xadj[mid] <= e) lo = mid;
+            else hi = mid;
+        }
+        mark[i] = lo;
+    }
+}
+
 // Edge pass: cut of P_0 and total edge weight (counter rows 2 and 3),
-// neighbour-range / self-loop / weight checks. Blocks own contiguous ranges
-// of runs of 16 consecutive CSR entries.
-__global__ __launch_bounds__(BLOCK) void k_init_edges(KArgs a, int64_t nnz)
+// neighbour-range / self-loop / weight checks. Each thread takes runs of 16
+// consecutive CSR entries (blocks own contiguous ranges of runs): it finds
+// the run's first row between two row marks, loads the 16 entries and
+// gathers their parts at once, then walks the rows.
+__global__ __launch_bounds__(BLOCK) void k_init_edges(KArgs a, int64_t nnz, const int32_t *mark, int64_t nmark)
 {
     constexpr int RUN = 16;
+    if (a.n < 1) return;  // callers refine no empty graph
     const int64_t nruns = (nnz + RUN - 1) / RUN;
     const int64_t per = (nruns + gridDim.x - 1) / gridDim.x;
     const int64_t r0 = (int64_t)blockIdx.x * per, r1 = r0 + per < nruns ? r0 + per : nruns;
@@ -382,31 +403,47 @@ __global__ __launch_bounds__(BLOCK) void k_init_edges(KArgs a, int64_t nnz)
     int bad = 0;
     for (int64_t r = r0 + threadIdx.x; r < r1; r += BLOCK) {
         const int64_t e0 = r * RUN, e1 = e0 + RUN < nnz ? e0 + RUN : nnz;
-        int lo = 0, hi = a.n;  // invariant xadj[lo] <= e0 < xadj[hi] (xadj[n] = nnz > e0)
+        // invariant xadj[lo] <= e0 < xadj[hi] (mark[i + 1] + 1 <= n holds
+        // such an offset; xadj[n] = nnz > e0)
+        const int64_t mi = e0 / MARK;
+        int lo = mark[mi];
+        int hi = mi + 1 < nmark ? mark[mi + 1] + 1 : a.n;
+        if (hi > a.n) hi = a.n;
+        if (lo >= hi) lo = hi - 1;  // only for malformed offsets; the checks below flag them
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (a.xadj[mid] <= e0) lo = mid;
             else hi = mid;
         }
+        int u[RUN], wt[RUN], pu[RUN];
+#pragma unroll
+        for (int j = 0; j < RUN; j++) {
+            const int64_t e = e0 + j;
+            u[j] = e < e1 ? a.adj[e] : -1;
+            wt[j] = e < e1 ? (a.ew ? a.ew[e] : 1) : 1;
+        }
+#pragma unroll
+        for (int j = 0; j < RUN; j++) pu[j] = (u[j] >= 0 && u[j] < a.n) ? gpart(a, u[j]) : -1;
         int v = lo;
         int64_t vend = a.xadj[v + 1];
         int pv = a.P[v];
         acc.to(a, graph_of(a, v));
-        for (int64_t e = e0; e < e1; e++) {
+#pragma unroll
+        for (int j = 0; j < RUN; j++) {
+            const int64_t e = e0 + j;
+            if (e >= e1) break;
             while (e >= vend && v < a.n - 1) {
                 v++;
                 vend = a.xadj[v + 1];
                 pv = a.P[v];
                 acc.to(a, graph_of(a, v));
             }
-            const int u = a.adj[e];
-            const int wt = a.ew ? a.ew[e] : 1;
-            if (u < 0 || u >= a.n || u == v || wt < 1) {
+            if (u[j] < 0 || u[j] >= a.n || u[j] == v || wt[j] < 1) {
                 bad = 1;
                 continue;
             }
-            acc.c1 += wt;
-            if (u > v && a.P[u] != pv) acc.c0 += wt;
+            acc.c1 += wt[j];
+            if (u[j] > v && pu[j] != pv) acc.c0 += wt[j];
         }
     }
     if (bad) a.cnt[1] = 1;
@@ -4284,7 +4321,11 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     if (n > 0) k_init_vertices<<<grid_v, BLOCK, a.vg ? 0 : (size_t)a.k * 4, s>>>(a, L.part_in, blkcnt);
     if (L.u.nnz > 0) {
         const int grid_e = std::max(1, std::min(div_up(div_up(L.u.nnz, 16), BLOCK), ctx->num_cu * 8));
-        k_init_edges<<<grid_e, BLOCK, 0, s>>>(a, L.u.nnz);
+        const int64_t nmark = L.u.nnz / MARK + 1;
+        int32_t *mark = (int32_t *)ws_get(ctx, WS_RMARK, sizeof(int32_t) * (size_t)nmark);
+        if (!mark) return JET_ENOMEM;
+        k_row_marks<<<std::max(1, std::min(div_up(nmark, BLOCK), ctx->num_cu)), BLOCK, 0, s>>>(L.u.xadj, n, nmark, mark);
+        k_init_edges<<<grid_e, BLOCK, 0, s>>>(a, L.u.nnz, mark, nmark);
     }
     k_bin_scan<<<1, BLOCK, 0, s>>>(blkcnt, grid_v);
     const int32_t *ctot = blkcnt + (size_t)grid_v * NCLS;  // class totals on the device
@@ -5270,6 +5311,7 @@ static size_t noalloc_need(int64_t n, int64_t nnz, int64_t k, int64_t trace_cap,
     if (trace_cap > 0) b += al(sizeof(jet_trace_rec) * (size_t)trace_cap);
     b += al(nn * 2) + al(nn * 8) + al(nn * 4) + al(nn * 4) + al(nn) + al(nn * 4) + al(nn) + al(nn * 4);
     b += al(nn) + al(nn * 4) + al(nn * 4);  // byte parts, packed (old, new) parts and records, at their largest
+    b += al(4 * (size_t)(nnz / 4096 + 1));   // row marks of the edge pass
     b += al(sizeof(int64_t) * NSTAT * NSHARD) + al(sizeof(int32_t) * (CNT_N + 2)) + al(sizeof(Ctl));
     b += al(sizeof(int64_t) * (4 * (size_t)k + 9)) + al(sizeof(int32_t) * (3 * (size_t)k + 8)) + al(2 * (size_t)k + 16);
     b += al(sizeof(int64_t) * (size_t)k * NSLOT) + al(sizeof(int32_t) * (size_t)(ntile * k)) + al(8 * (size_t)ntile);
