@@ -174,13 +174,27 @@ __device__ __forceinline__ Prop prop_shfl_xor(const Prop &p, int o, int width)
 __device__ __forceinline__ Prop prop_scan_row(int v, int64_t s, int64_t e, int lane, int stride, const int32_t *adj,
                                                const int32_t *ew, const int32_t *match, uint64_t hseed)
 {
+    // U entries per lane per round: their ids and weights, then their match
+    // states, are loaded before any is examined
+    constexpr int U = 8;
     Prop best{0, -1, 0};
-    for (int64_t i = s + lane; i < e; i += stride) {
-        const int u = adj[i];
-        if (match[u] >= 0) continue;
-        const uint32_t lo = (uint32_t)(u < v ? u : v), hi = (uint32_t)(u < v ? v : u);
-        Prop c{ew ? ew[i] : 1, u, mix64(hseed ^ (((uint64_t)lo << 32) | hi))};
-        if (prop_better(c, best)) best = c;
+    for (int64_t i0 = s + lane; i0 < e; i0 += (int64_t)stride * U) {
+        int u[U], w[U], mu[U];
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            const int64_t i = i0 + (int64_t)j * stride;
+            u[j] = i < e ? adj[i] : -1;
+            w[j] = i < e ? (ew ? ew[i] : 1) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < U; j++) mu[j] = u[j] >= 0 ? match[u[j]] : 0;
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            if (u[j] < 0 || mu[j] >= 0) continue;
+            const uint32_t lo = (uint32_t)(u[j] < v ? u[j] : v), hi = (uint32_t)(u[j] < v ? v : u[j]);
+            Prop c{w[j], u[j], mix64(hseed ^ (((uint64_t)lo << 32) | hi))};
+            if (prop_better(c, best)) best = c;
+        }
     }
     return best;
 }
@@ -519,11 +533,21 @@ __global__ __launch_bounds__(CB) void k_crow_small(int nc, const int32_t *bound,
         int64_t s1 = 0;
         int d1 = 0;
         if (m1 >= 0) { s1 = xadj[m1]; d1 = (int)(xadj[m1 + 1] - s1); }
-        for (int idx = gl; idx < d0 + d1; idx += 8) {
+        // at most CS_MAX = 64 member entries: 8 per lane, all loaded first
+        int cuv[8], wv[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const int idx = gl + q * 8;
             const int64_t e = member_entry(s0, d0, s1, idx);
-            const int cu = map[adj[e]];
-            if (cu == c) continue;
-            const int w = ew ? ew[e] : 1;
+            cuv[q] = idx < d0 + d1 ? adj[e] : -1;
+            wv[q] = idx < d0 + d1 ? (ew ? ew[e] : 1) : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; q++) cuv[q] = cuv[q] >= 0 ? map[cuv[q]] : -1;
+        for (int q = 0; q < 8; q++) {
+            const int cu = cuv[q];
+            if (cu < 0 || cu == c) continue;
+            const int w = wv[q];
             uint32_t h = chash(cu, 7);
             for (int probe = 0;; probe++) {
                 if (probe == CS_T) { *overflow = 1; break; }  // cannot happen: <= 64 keys in 128 slots
@@ -582,11 +606,22 @@ __global__ __launch_bounds__(CB) void k_crow_medium(const int32_t *list, int cnt
         int64_t s1 = 0;
         int d1 = 0;
         if (m1 >= 0) { s1 = xadj[m1]; d1 = (int)(xadj[m1 + 1] - s1); }
-        for (int idx = threadIdx.x; idx < d0 + d1; idx += CB) {
+        // at most CM_MAX = 2048 member entries: CM_MAX / CB per thread, all loaded first
+        constexpr int UM = CM_MAX / CB;
+        int cuv[UM], wv[UM];
+#pragma unroll
+        for (int q = 0; q < UM; q++) {
+            const int idx = threadIdx.x + q * CB;
             const int64_t e = member_entry(s0, d0, s1, idx);
-            const int cu = map[adj[e]];
-            if (cu == c) continue;
-            const int w = ew ? ew[e] : 1;
+            cuv[q] = idx < d0 + d1 ? adj[e] : -1;
+            wv[q] = idx < d0 + d1 ? (ew ? ew[e] : 1) : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < UM; q++) cuv[q] = cuv[q] >= 0 ? map[cuv[q]] : -1;
+        for (int q = 0; q < UM; q++) {
+            const int cu = cuv[q];
+            if (cu < 0 || cu == c) continue;
+            const int w = wv[q];
             uint32_t h = chash(cu, 12);
             for (int probe = 0;; probe++) {
                 if (probe == CM_T) { *overflow = 1; break; }  // cannot happen: <= 2048 keys in 4096 slots

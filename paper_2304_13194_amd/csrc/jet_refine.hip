@@ -1166,6 +1166,44 @@ __device__ __forceinline__ void block_fill(const KArgs &a, int v, int32_t *tab)
 // word, so ties go to the smaller part id.
 __device__ __forceinline__ uint64_t conn_key(int c, int p) { return ((uint64_t)(uint32_t)c << 32) | (uint32_t)(~p); }
 
+// Rows of at most TINY entries are taken one per lane, by the lane that
+// inspects them in the wave-batched drivers: the row's neighbour parts sit in
+// registers and are compared pairwise, so no lane group, LDS table or
+// reduction is spent on a row of a few entries (most rows of a power-law
+// graph).
+constexpr int TINY = 8;
+
+// Connectivity of such a row (deg <= T): calls f(p, conn(v, p)) once for
+// every adjacent part p != ps and returns conn(v, ps).
+template <int T, class F>
+__device__ __forceinline__ int tiny_conn(const KArgs &a, int64_t s, int deg, int ps, F f)
+{
+    int p[T], w[T];
+#pragma unroll
+    for (int j = 0; j < T; j++) {
+        p[j] = j < deg ? a.adj[s + j] : -1;
+        w[j] = j < deg ? (a.ew ? a.ew[s + j] : 1) : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < T; j++) p[j] = p[j] >= 0 ? gpart(a, p[j]) : -1;
+    int cs = 0;
+#pragma unroll
+    for (int j = 0; j < T; j++) cs += p[j] == ps ? w[j] : 0;
+#pragma unroll
+    for (int j = 0; j < T; j++) {
+        if (p[j] < 0 || p[j] == ps) continue;
+        bool first = true;
+        int c = w[j];
+#pragma unroll
+        for (int i = 0; i < T; i++) {
+            if (i < j) first = first && p[i] != p[j];
+            else if (i > j) c += p[i] == p[j] ? w[i] : 0;
+        }
+        if (first) f(p[j], c);  // the first slot of a part reports its whole sum
+    }
+    return cs;
+}
+
 // -------------------------------------------------------------- Jetlp gain --
 
 // Writes rec[v]; returns whether v passes the first filter (a destination
@@ -1362,6 +1400,16 @@ __device__ __forceinline__ void gain_body(const KArgs &a, int nblk)
                     m.deg = (int)(x1 - x0);
                     pacc.c1++;
                     pacc.c2 += m.deg;
+                    if (!PAIR && m.deg <= TINY) {
+                        uint64_t best = 0;
+                        const int cs = tiny_conn<TINY>(a, m.s, m.deg, m.ps, [&](int p, int c) {
+                            const uint64_t k2 = conn_key(c, p);
+                            best = k2 > best ? k2 : best;
+                        });
+                        racc.sel<B>(a, m.g);
+                        racc.c0 += gain_finish(a, m.v, m.ps, best, cs, pv.cn, pv.cd);
+                        return false;
+                    }
                     return true;
                 };
             auto row = [&](const Meta &t, int gl) {
@@ -2465,11 +2513,27 @@ __device__ __forceinline__ void loss_body(const KArgs &a, int nblk, int hmode)
                         }
                         m.s = x0;
                         m.deg = (int)(x1 - x0);
-                        return true;
+                    } else {
+                        if (!rb_candidate(a, m.v, m.ps, m.aux, pv)) return false;
+                        m.s = a.xadj[m.v];
+                        m.deg = (int)(a.xadj[m.v + 1] - m.s);
                     }
-                    if (!rb_candidate(a, m.v, m.ps, m.aux, pv)) return false;
-                    m.s = a.xadj[m.v];
-                    m.deg = (int)(a.xadj[m.v + 1] - m.s);
+                    if (!PAIR && m.deg <= TINY) {
+                        uint64_t best = 0;
+                        int sumB = 0, cntB = 0;
+                        const int cs = tiny_conn<TINY>(a, m.s, m.deg, m.ps, [&](int p, int c) {
+                            if (pcache ? cB[p] : a.isB[pv.poff + p]) {
+                                const uint64_t k2 = conn_key(c, p);
+                                best = k2 > best ? k2 : best;
+                                sumB += c;
+                                cntB++;
+                            }
+                        });
+                        rb_finish(a, m.v, m.ps, pv, best, cs, sumB, cntB, m.aux, hmode, lh);
+                        racc.sel<B>(a, m.g);
+                        racc.c0++;
+                        return false;
+                    }
                     return true;
                 };
             auto row = [&](const Meta &t, int gl) {
