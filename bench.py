@@ -58,10 +58,13 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per finest-level Jetlp gain pass from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs (each calibrated by a plain 2^28-byte copy), valid only for
-# the kernel source they were taken on (profiles/k_gain_stencil128_k64.md).
+# the kernel source they were taken on (profiles/gain_pass_rmat22_k256.md,
+# profiles/k_gain_stencil128_k64.md).
 TRAFFIC = {
-    "stencil128": dict(src_sha256="033629e58bb3ac3b35fbce81e7ab0b8ab8de40d2e94523d1bab68f49dcbc511b",
-                       fetch=249198497, write=17431882, fetch_factor=1.9997, write_factor=1.0),
+    "rmat22": dict(src_sha256="762ea4d256058fedcd29bc6473dd70ac4ca4ed4fd4e1e9ca1ce63c10b3e448b5",
+                   fetch=1894108013, write=98680256, fetch_factor=1.9997, write_factor=1.0),
+    "stencil128": dict(src_sha256="762ea4d256058fedcd29bc6473dd70ac4ca4ed4fd4e1e9ca1ce63c10b3e448b5",
+                       fetch=249298235, write=26258760, fetch_factor=1.9997, write_factor=1.0),
 }
 
 
@@ -82,8 +85,10 @@ WORKLOADS = {
     # R-MAT scale 22, edge factor 16, weights in [1, 16], k = 256
     "rmat22": dict(kind="rmat", scale=22, ef=16, k=256, unit=False,
                    label="R-MAT scale 22 (edge factor 16, a,b,c,d = 0.57,0.19,0.19,0.05)",
-                   gain_kernels="rows of up to 64 entries in lane groups, 65..1024 one wave each, longer rows "
-                                "in 1024-entry chunks plus a finishing launch"),
+                   gain_kernels="k_rows<8, 4, false, 5>: rows of at most 8 entries one per lane, up to 64 in "
+                                "groups of 8 lanes; k_gain<false, 2, 8, 4, 1>: 65..1024 one wave each; "
+                                "k_lconn<false, false> + k_lgain_fin<false>: longer rows in 4096-entry chunks, one "
+                                "block each, then a finishing launch"),
     # full multilevel partition of the 128^3 27-point mesh, k = 64
     "stencil128": dict(kind="stencil", side=128, k=64, unit=True,
                        label="27-point stencil 128^3",
@@ -307,6 +312,11 @@ def measure_workload(J, name, g, w, seed, steps, warmup, ceiling):
             "gather_ceiling": gather,
             "frac_of_gather_ceiling": achieved / gather["GBs"] if gather["GBs"] else None,
             "bytes_per_pass": gbytes / passes if passes else None,
+            # the scope table's all-rows formula (every row's entries, 30 B per
+            # vertex), beside the method's bytes above (locked rows skipped)
+            "all_rows_formula_bytes": g.nnz * (4 if w["unit"] else 8) + 30 * g.n,
+            "frac_all_rows_formula": ((g.nnz * (4 if w["unit"] else 8) + 30 * g.n) / ((ms_gain / passes) * 1e-3) / 1e9
+                                      / HBM_PEAK_GBS) if passes else None,
             "ms_per_pass": ms_gain / passes if passes else None,
             "passes": passes,
         },
