@@ -3,6 +3,7 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat22|stencil128|grid64]
                     [--secondary stencil128|none] [--no-cpu-baseline] [--no-batch] [--no-serve]
                     [--no-ablations] [--serve-jobs N] [--serve-warmup N] [--serve-budget-gb G]
+                    [--serve-slots S]
 
 A step is one full multilevel partition (Algorithm 1: heavy-edge coarsening,
 seeded random coarsest partition, Jet refinement of every level, i.e. every
@@ -469,7 +470,7 @@ def batch_oracle(spec, budget_s=10.0):
     }
 
 
-def serve_bench(J, jobs, graphs, budget_bytes, warmup, rates=(50, 100, 200, 500, 1000, 2000)):
+def serve_bench(J, jobs, graphs, budget_bytes, warmup, rates=(50, 100, 200, 500, 1000, 2000), slots=256):
     """Poisson arrivals into jet_server vs the same jobs one at a time. Every
     job is drawn on its own (grid side, or R-MAT scale, edge factor and graph
     seed; k; seed); the first `warmup` jobs of each rate are not measured."""
@@ -493,11 +494,11 @@ def serve_bench(J, jobs, graphs, budget_bytes, warmup, rates=(50, 100, 200, 500,
     # one long-lived server for every rate, warmed by the first rate's
     # unmeasured jobs (its lanes' workspaces and memory pools then hold what
     # the mix needs, as the one-at-a-time context's do)
-    sv = J.Server(hbm_budget_bytes=budget_bytes, max_slots=64)
+    sv = J.Server(hbm_budget_bytes=budget_bytes, max_slots=slots)
     out = {"workload": f"{nmeas} measured + {warmup} warm-up jobs per rate, each drawn on its own: half 2-D "
                        f"grids (side uniform in [64, 1024]), half R-MAT graphs (scale uniform in [12, 20], edge "
                        f"factor uniform in [8, 16], weights 1..16); k uniform in [2, 256], lambda 3%",
-           "hbm_budget_bytes": budget_bytes,
+           "hbm_budget_bytes": budget_bytes, "max_slots": slots,
            "graphs_per_s_one_at_a_time": len(jobs) / t_seq, "rates": []}
     identical = True
     steps0 = jobs0 = 0
@@ -606,9 +607,10 @@ def main():
     ap.add_argument("--no-copy-ceiling", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8,
                     help="iterations of the oracle's sampled refinement (R-MAT workload)")
-    ap.add_argument("--serve-jobs", type=int, default=100, help="measured jobs per arrival rate")
+    ap.add_argument("--serve-jobs", type=int, default=200, help="measured jobs per arrival rate")
     ap.add_argument("--serve-warmup", type=int, default=20, help="unmeasured jobs before them")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="server HBM budget (GB)")
+    ap.add_argument("--serve-slots", type=int, default=256, help="server slots (jobs admitted at once)")
     ap.add_argument("--serve-rates", default="50,100,200,500,1000,2000", help="arrival rates (jobs/s)")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--graph-cache", default=None,
@@ -733,7 +735,8 @@ def main():
         try:
             graphs = [f.result() for f in fut_srv]
             out["serving"] = serve_bench(J, jobs, graphs, int(args.serve_budget_gb * 1e9), args.serve_warmup,
-                                         rates=tuple(float(x) for x in args.serve_rates.split(",")))
+                                         rates=tuple(float(x) for x in args.serve_rates.split(",")),
+                                         slots=args.serve_slots)
             del graphs
         except Exception as e:
             out["serving"] = {"error": repr(e)}
