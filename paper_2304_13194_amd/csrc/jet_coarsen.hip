@@ -171,8 +171,10 @@ __device__ __forceinline__ Prop prop_shfl_xor(const Prop &p, int o, int width)
     return q;
 }
 
+// taken[u] != 0: u is matched (a byte per vertex, so the gathers of the
+// proposal rounds read a quarter of the bytes of the partner array)
 __device__ __forceinline__ Prop prop_scan_row(int v, int64_t s, int64_t e, int lane, int stride, const int32_t *adj,
-                                               const int32_t *ew, const int32_t *match, uint64_t hseed)
+                                               const int32_t *ew, const uint8_t *taken, uint64_t hseed)
 {
     // U entries per lane per round: their ids and weights, then their match
     // states, are loaded before any is examined
@@ -187,10 +189,10 @@ __device__ __forceinline__ Prop prop_scan_row(int v, int64_t s, int64_t e, int l
             w[j] = i < e ? (ew ? ew[i] : 1) : 0;
         }
 #pragma unroll
-        for (int j = 0; j < U; j++) mu[j] = u[j] >= 0 ? match[u[j]] : 0;
+        for (int j = 0; j < U; j++) mu[j] = u[j] >= 0 ? taken[u[j]] : 1;
 #pragma unroll
         for (int j = 0; j < U; j++) {
-            if (u[j] < 0 || mu[j] >= 0) continue;
+            if (u[j] < 0 || mu[j]) continue;
             const uint32_t lo = (uint32_t)(u[j] < v ? u[j] : v), hi = (uint32_t)(u[j] < v ? v : u[j]);
             Prop c{w[j], u[j], mix64(hseed ^ (((uint64_t)lo << 32) | hi))};
             if (prop_better(c, best)) best = c;
@@ -202,8 +204,8 @@ __device__ __forceinline__ Prop prop_scan_row(int v, int64_t s, int64_t e, int l
 // Proposals. Vertices of degree <= 64 use 8-lane groups; heavier rows are
 // left to k_hem_propose_big (one block per row) through the `big` list.
 __global__ __launch_bounds__(CB) void k_hem_propose(int n, const int64_t *xadj, const int32_t *adj, const int32_t *ew,
-                                                    const int32_t *match, int32_t *prop, uint64_t hseed,
-                                                    const CState *st)
+                                                    const int32_t *match, const uint8_t *taken, int32_t *prop,
+                                                    uint64_t hseed, const CState *st)
 {
     if (st->stop) return;
     constexpr int G = 8;
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(CB) void k_hem_propose(int n, const int64_t *xadj, 
         const int64_t s = xadj[v], e = xadj[v + 1];
         if (e - s > 64) continue;  // heavy row: handled by the block kernel
         if (match[v] >= 0) { if (gl == 0) prop[v] = -1; continue; }
-        Prop b = prop_scan_row(v, s, e, gl, G, adj, ew, match, hseed);
+        Prop b = prop_scan_row(v, s, e, gl, G, adj, ew, taken, hseed);
 #pragma unroll
         for (int o = G / 2; o > 0; o >>= 1) {
             Prop q = prop_shfl_xor(b, o, G);
@@ -225,14 +227,15 @@ __global__ __launch_bounds__(CB) void k_hem_propose(int n, const int64_t *xadj, 
 
 __global__ __launch_bounds__(CB) void k_hem_propose_big(const int32_t *big, int nbig, const int64_t *xadj,
                                                         const int32_t *adj, const int32_t *ew, const int32_t *match,
-                                                        int32_t *prop, uint64_t hseed, const CState *st)
+                                                        const uint8_t *taken, int32_t *prop, uint64_t hseed,
+                                                        const CState *st)
 {
     __shared__ Prop s_p[CB / 64];
     if (st->stop) return;
     for (int i = blockIdx.x; i < nbig; i += gridDim.x) {
         const int v = big[i];
         if (match[v] >= 0) { if (threadIdx.x == 0) prop[v] = -1; continue; }
-        Prop b = prop_scan_row(v, xadj[v], xadj[v + 1], threadIdx.x, CB, adj, ew, match, hseed);
+        Prop b = prop_scan_row(v, xadj[v], xadj[v + 1], threadIdx.x, CB, adj, ew, taken, hseed);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             Prop q = prop_shfl_xor(b, o, 64);
@@ -251,7 +254,7 @@ __global__ __launch_bounds__(CB) void k_hem_propose_big(const int32_t *big, int 
 }
 
 // Mutual proposals match; the smaller id of each pair writes both entries.
-__global__ __launch_bounds__(CB) void k_hem_match(int n, int32_t *match, const int32_t *prop, CState *st)
+__global__ __launch_bounds__(CB) void k_hem_match(int n, int32_t *match, uint8_t *taken, const int32_t *prop, CState *st)
 {
     __shared__ int32_t s_red[CB / 64];
     if (st->stop) return;
@@ -262,6 +265,8 @@ __global__ __launch_bounds__(CB) void k_hem_match(int n, int32_t *match, const i
         if (u > v && prop[u] == v) {
             match[v] = u;
             match[u] = v;
+            taken[v] = 1;
+            taken[u] = 1;
             cnt += 2;
         }
     }
@@ -1011,8 +1016,10 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     int64_t *tsum = (int64_t *)ws_get(ctx, WS_C4, ((nn + SCAN_TILE - 1) / SCAN_TILE + 2) * 8);
     CState *st = (CState *)ws_get(ctx, WS_H1, sizeof(CState) + 16);
     int32_t *nbig = (int32_t *)(st + 1);
-    if (!match || !prop || !big || !cid || !tsum || !st) return JET_ENOMEM;
+    uint8_t *taken = (uint8_t *)ws_get(ctx, WS_C13, nn);
+    if (!match || !prop || !big || !cid || !tsum || !st || !taken) return JET_ENOMEM;
     JET_TRY(hipMemsetAsync(match, 0xFF, nn * 4, s));
+    JET_TRY(hipMemsetAsync(taken, 0, nn, s));
     JET_TRY(hipMemsetAsync(st, 0, sizeof(CState) + 16, s));
     const int gv = grid_for(ctx, n, CB, 4);
     k_big_list<<<gv, CB, 0, s>>>(n, f->xadj, big, nbig);
@@ -1023,11 +1030,11 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     const uint64_t hseed = stream64(seed, (uint64_t)(uint32_t)level);
     const int gp = grid_for(ctx, n, CB / 8);
     for (int round = 0; round < 16; round++) {
-        k_hem_propose<<<gp, CB, 0, s>>>(n, f->xadj, f->adjncy, f->adjwgt, match, prop, hseed, st);
+        k_hem_propose<<<gp, CB, 0, s>>>(n, f->xadj, f->adjncy, f->adjwgt, match, taken, prop, hseed, st);
         if (nb > 0)
             k_hem_propose_big<<<std::min(nb, ctx->num_cu * 8), CB, 0, s>>>(big, nb, f->xadj, f->adjncy, f->adjwgt,
-                                                                           match, prop, hseed, st);
-        k_hem_match<<<gv, CB, 0, s>>>(n, match, prop, st);
+                                                                           match, taken, prop, hseed, st);
+        k_hem_match<<<gv, CB, 0, s>>>(n, match, taken, prop, st);
         k_hem_round_end<<<1, 1, 0, s>>>(n, st);
     }
     if (th) {

@@ -202,10 +202,10 @@ enum WsSlot {
     WS_U_XADJ, WS_U_ADJ, WS_U_VW, WS_U_EW, WS_U_VG, WS_U_P0, WS_U_BEST, WS_U_DESC,
     WS_LCNT, WS_LCH, WS_GCONN, WS_LDONE, WS_TH_KEY, WS_TH_VAL, WS_TH_RUN, WS_TH_TMP, WS_WDEG,
     WS_TOFF, WS_TAB, WS_TSIZE, WS_TFAIL, WS_TLIST, WS_TBLK, WS_WQ, WS_TUNE_CTL, WS_TUNE_CNT, WS_TUNE_REC,
-    WS_TUNE_STAT, WS_P8, WS_MQ, WS_RQ, WS_RMARK,
+    WS_TUNE_STAT, WS_P8, WS_MQ, WS_RQ, WS_RMARK, WS_C13,
     WS_COUNT = 80
 };
-static_assert(WS_RMARK < WS_COUNT, "workspace slots");
+static_assert(WS_C13 < WS_COUNT, "workspace slots");
 
 // Grow-only workspace slot; returns nullptr on allocation failure.
 void *ws_get(jet_context *ctx, int slot, size_t bytes);
