@@ -297,8 +297,9 @@ int jet_rebalance_step(jet_context *ctx, const jet_csr *g, const jet_params *par
  * smaller id; at most 16 rounds, stopping when a round matches < 1% of the
  * vertices) and contraction (coarse ids = matched pairs and singletons
  * numbered by their smaller member; coarse edge weights summed; no
- * self-loops). Coarsening stops when n <= 8k, when a level keeps more than
- * 90% of its vertices, or at 64 levels. The hierarchy lives in device memory
+ * self-loops). Coarsening stops when n <= 8k, at 64 levels, or when a
+ * matching would keep more than 90% of the vertices (that matching makes no
+ * level; the current one is the coarsest). The hierarchy lives in device memory
  * owned by the library until jet_hierarchy_free. Rows of coarse graphs are
  * not sorted. */
 int jet_coarsen(jet_context *ctx, const jet_csr *g, const jet_params *params, jet_hierarchy **h,

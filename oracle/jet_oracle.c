@@ -712,7 +712,9 @@ void og_bfs_part(const og_graph *g, int32_t k, int32_t *part)
 }
 
 /* ---- multilevel template (Algorithm 1) ---------------------------------
- * Coarsen until n <= 8k, or a level shrinks by less than 10%, or 64 levels;
+ * Coarsen until n <= 8k (Section 3's target), or 64 levels. A matching that
+ * would keep more than 90% of the vertices (or matches nothing) makes no
+ * level: the current level is the coarsest;
  * seeded uniform random partition of the coarsest graph,
  * P[v] = floor(stream(mix64(seed ^ 1), v) * k / 2^64), or with
  * OG_F_BFS_START the graph-growing start og_bfs_part; refine it; then
@@ -732,13 +734,12 @@ int32_t og_partition(const og_graph *g, const og_params *prm, int32_t *part, og_
         const og_graph *f = &G[nl - 1];
         int32_t *map = (int32_t *)malloc(sizeof(int32_t) * (size_t)(f->n > 0 ? f->n : 1));
         int32_t nc = og_hem_map(f, nl - 1, prm->seed, (prm->flags & OG_F_TWO_HOP) != 0, map);
-        if (nc == f->n) { free(map); break; }
+        if (nc == f->n || 10 * (int64_t)nc > 9 * (int64_t)f->n) { free(map); break; }
         int64_t *cx; int32_t *ca, *cv, *cw;
         og_contract(f, map, nc, &cx, &ca, &cv, &cw);
         maps[nl - 1] = map;
         G[nl].n = nc; G[nl].xadj = cx; G[nl].adjncy = ca; G[nl].vwgt = cv; G[nl].adjwgt = cw;
         nl++;
-        if (10 * (int64_t)nc > 9 * (int64_t)f->n) break;
     }
     if (level_sizes) for (int32_t i = 0; i < nl; i++) level_sizes[i] = G[i].n;
     int32_t l = nl - 1;

@@ -1050,7 +1050,8 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     JET_TRY(stream_wait(ctx, s));
     const int nc = (int)*hn;
     *nc_out = nc;
-    if (nc == n) return JET_OK;
+    // a matching that keeps more than 90% of the vertices makes no level
+    if (nc == n || 10 * (int64_t)nc > 9 * (int64_t)n) return JET_OK;
     const size_t ncc = (size_t)std::max(nc, 1);
     int32_t *map = (int32_t *)hier_alloc(h, nn * 4);
     int32_t *cvw = (int32_t *)hier_alloc(h, ncc * 4);
@@ -1145,10 +1146,11 @@ static int build_hierarchy(jet_context *ctx, const jet_csr *g, const jet_params 
         int st = coarsen_level(ctx, h, &f, (int)h->lv.size() - 1, prm->seed, (prm->flags & JET_F_TWO_HOP) != 0, &c,
                                &map, &nc, s);
         if (st) return st;
-        if (nc == f.n) break;
+        // stall: the matching keeps more than 90% of the vertices (or matches
+        // nothing), so the current level is the coarsest
+        if (nc == f.n || 10 * (int64_t)nc > 9 * (int64_t)f.n) break;
         h->maps.push_back(map);
         h->lv.push_back(c);
-        if (10 * (int64_t)nc > 9 * (int64_t)f.n) break;
     }
     h->maps.push_back(nullptr);
     h->nlevels = (int)h->lv.size();

@@ -61,7 +61,10 @@ MUTANTS = [
     ("contraction overwrites edge weights", "acc[cu] += g->adjwgt[e];", "acc[cu] = g->adjwgt[e];"),
     ("projection ignores the map", "Pf[v] = P[maps[i][v]];", "Pf[v] = P[v % G[i + 1].n];"),
     ("coarsening target 4k", "G[nl - 1].n > 8 * (int64_t)k", "G[nl - 1].n > 4 * (int64_t)k"),
-    ("coarsening drops the 90% rule", "if (10 * (int64_t)nc > 9 * (int64_t)f->n) break;", ""),
+    ("coarsening drops the 90% rule", "if (nc == f->n || 10 * (int64_t)nc > 9 * (int64_t)f->n) { free(map); break; }",
+     "if (nc == f->n) { free(map); break; }"),
+    ("coarsening stops at 80%", "if (nc == f->n || 10 * (int64_t)nc > 9 * (int64_t)f->n) { free(map); break; }",
+     "if (nc == f->n || 10 * (int64_t)nc > 8 * (int64_t)f->n) { free(map); break; }"),
     ("random start with the wrong stream", "og_mix64(prm->seed ^ 1ULL)", "og_mix64(prm->seed ^ 2ULL)"),
     ("start chunks by count", "        b += g->vwgt ? g->vwgt[v] : 1;\n    }\n    free(dist);",
      "        b += 1;\n    }\n    free(dist);"),

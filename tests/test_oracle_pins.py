@@ -555,29 +555,31 @@ def test_hem_distinct_weights_is_greedy_matching(oracle_lib):
 
 def test_multilevel_is_algorithm1_composition(oracle_lib):
     """Algorithm 1 recomposed from the oracle's pinned steps: coarsen while
-    n > 8k (a level keeping over 90% of its vertices is the last; one that
-    matches nothing is dropped), seeded random start on the coarsest graph,
+    n > 8k (a matching that would keep over 90% of the vertices, or matches
+    nothing, makes no level), seeded random start on the coarsest graph,
     then refine, project P_i = P_{i+1}[map_i] and refine each finer level.
     The projected start's cut equals the coarser result's cut (contraction
     keeps the cut of every projected partition)."""
     O = oracle_lib
     cases = [(I.grid2d(40, 40), 4, 7), (I.grid2d(33, 29), 3, 2), (I.stencil27(9, 8, 7), 5, 11),
              (I.small_random_graph(300, 0.03, 41, wmax=5, vwmax=3), 4, 5),
-             # a star matches one leaf per level: the first level keeps 200 of
-             # 201 vertices and is the last
-             (graph_from_edges(201, [(0, i, 1 + i % 3) for i in range(1, 201)]), 2, 3)]
+             # a star matches one leaf per level: its first matching would keep
+             # 200 of 201 vertices, so the star is the only level
+             (graph_from_edges(201, [(0, i, 1 + i % 3) for i in range(1, 201)]), 2, 3),
+             # 100 isolated vertices beside a 40-vertex path: the first
+             # matching keeps 120 of 140 (a level), the next would keep 110 of
+             # 120 (none)
+             (graph_from_edges(140, [(i, i + 1, 1) for i in range(100, 139)]), 2, 5)]
     for g, k, seed in cases:
         res = O.partition(g, k, seed=seed)
         levels, maps = [g], []
         while len(levels) < 64 and levels[-1].n > 8 * k:
             f = levels[-1]
             nc, cmap = O.hem_map(f, len(levels) - 1, seed)
-            if nc == f.n:
+            if nc == f.n or 10 * nc > 9 * f.n:
                 break
             levels.append(O.contract(f, cmap, nc))
             maps.append(cmap)
-            if 10 * nc > 9 * f.n:
-                break
         sizes = [lv.n for lv in levels]
         assert list(res["level_sizes"]) == sizes, g.name
         top = len(levels) - 1
@@ -598,16 +600,24 @@ def test_multilevel_is_algorithm1_composition(oracle_lib):
 
 def test_partition_multilevel_sanity(oracle_lib):
     """Level sizes follow the stop rule: every level but the coarsest has
-    more than 8k vertices, each level shrinks, and the coarsest has at most
-    8k vertices or kept more than 90% of the level above it."""
+    more than 8k vertices, each level keeps at most 90% of the level above
+    it, and the coarsest has at most 8k vertices or its next matching would
+    keep more than 90% of them."""
     O = oracle_lib
     g = I.grid2d(40, 40)
     res = O.partition(g, 4, seed=7)
     sizes = res["level_sizes"]
     assert sizes[0] == 1600 and sizes[-1] <= 32 and len(sizes) > 1
-    for k, gg in ((4, g), (3, I.grid2d(33, 29)), (6, I.stencil27(9, 8, 7))):
+    for k, gg in ((4, g), (3, I.grid2d(33, 29)), (6, I.stencil27(9, 8, 7)), (2, I.rmat(10, 8, 4))):
         sz = [int(x) for x in O.partition(gg, k, seed=3)["level_sizes"]]
-        assert all(x > 8 * k for x in sz[:-1]) and (sz[-1] <= 8 * k or 10 * sz[-1] > 9 * sz[-2]), sz
+        assert all(x > 8 * k for x in sz[:-1]) and all(10 * b <= 9 * a for a, b in zip(sz, sz[1:])), sz
+        if sz[-1] > 8 * k:
+            cur = gg
+            for lvl in range(len(sz) - 1):
+                nc, cmap = O.hem_map(cur, lvl, 3)
+                cur = O.contract(cur, cmap, nc)
+            nc, _ = O.hem_map(cur, len(sz) - 1, 3)
+            assert 10 * nc > 9 * cur.n, sz
     assert all(sizes[i + 1] < sizes[i] for i in range(len(sizes) - 1))
     assert brute_cut(g, res["part"]) == res["cut"]
     assert res["balanced"]
