@@ -63,9 +63,9 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_gain_stencil128_k64.md).
 TRAFFIC = {
     "rmat22": dict(src_sha256="762ea4d256058fedcd29bc6473dd70ac4ca4ed4fd4e1e9ca1ce63c10b3e448b5",
-                   fetch=1894108013, write=98680256, fetch_factor=1.9997, write_factor=1.0),
+                   fetch=1899410603, write=98564523, fetch_factor=1.9997, write_factor=1.0),
     "stencil128": dict(src_sha256="762ea4d256058fedcd29bc6473dd70ac4ca4ed4fd4e1e9ca1ce63c10b3e448b5",
-                       fetch=249298235, write=26258760, fetch_factor=1.9997, write_factor=1.0),
+                       fetch=249267323, write=26228473, fetch_factor=1.9997, write_factor=1.0),
 }
 
 
