@@ -201,11 +201,22 @@ __device__ __forceinline__ Prop prop_scan_row(int v, int64_t s, int64_t e, int l
     return best;
 }
 
+// After the first round a vertex rescans its row only when last round's
+// proposal has been matched since: the unmatched neighbours only shrink from
+// round to round, so a proposal that is still unmatched is still the best,
+// and a vertex that had no unmatched neighbour (-1) has none now.
+__device__ __forceinline__ bool prop_stands(int round, const int32_t *prop, const uint8_t *taken, int v)
+{
+    if (round == 0) return false;
+    const int pu = prop[v];
+    return pu < 0 || !taken[pu];
+}
+
 // Proposals. Vertices of degree <= 64 use 8-lane groups; heavier rows are
 // left to k_hem_propose_big (one block per row) through the `big` list.
 __global__ __launch_bounds__(CB) void k_hem_propose(int n, const int64_t *xadj, const int32_t *adj, const int32_t *ew,
                                                     const int32_t *match, const uint8_t *taken, int32_t *prop,
-                                                    uint64_t hseed, const CState *st)
+                                                    uint64_t hseed, const CState *st, int round)
 {
     if (st->stop) return;
     constexpr int G = 8;
@@ -215,6 +226,7 @@ __global__ __launch_bounds__(CB) void k_hem_propose(int n, const int64_t *xadj, 
         const int64_t s = xadj[v], e = xadj[v + 1];
         if (e - s > 64) continue;  // heavy row: handled by the block kernel
         if (match[v] >= 0) { if (gl == 0) prop[v] = -1; continue; }
+        if (prop_stands(round, prop, taken, v)) continue;
         Prop b = prop_scan_row(v, s, e, gl, G, adj, ew, taken, hseed);
 #pragma unroll
         for (int o = G / 2; o > 0; o >>= 1) {
@@ -228,13 +240,14 @@ __global__ __launch_bounds__(CB) void k_hem_propose(int n, const int64_t *xadj, 
 __global__ __launch_bounds__(CB) void k_hem_propose_big(const int32_t *big, int nbig, const int64_t *xadj,
                                                         const int32_t *adj, const int32_t *ew, const int32_t *match,
                                                         const uint8_t *taken, int32_t *prop, uint64_t hseed,
-                                                        const CState *st)
+                                                        const CState *st, int round)
 {
     __shared__ Prop s_p[CB / 64];
     if (st->stop) return;
     for (int i = blockIdx.x; i < nbig; i += gridDim.x) {
         const int v = big[i];
         if (match[v] >= 0) { if (threadIdx.x == 0) prop[v] = -1; continue; }
+        if (prop_stands(round, prop, taken, v)) continue;  // uniform over the block
         Prop b = prop_scan_row(v, xadj[v], xadj[v + 1], threadIdx.x, CB, adj, ew, taken, hseed);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -1030,10 +1043,10 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     const uint64_t hseed = stream64(seed, (uint64_t)(uint32_t)level);
     const int gp = grid_for(ctx, n, CB / 8);
     for (int round = 0; round < 16; round++) {
-        k_hem_propose<<<gp, CB, 0, s>>>(n, f->xadj, f->adjncy, f->adjwgt, match, taken, prop, hseed, st);
+        k_hem_propose<<<gp, CB, 0, s>>>(n, f->xadj, f->adjncy, f->adjwgt, match, taken, prop, hseed, st, round);
         if (nb > 0)
             k_hem_propose_big<<<std::min(nb, ctx->num_cu * 8), CB, 0, s>>>(big, nb, f->xadj, f->adjncy, f->adjwgt,
-                                                                           match, taken, prop, hseed, st);
+                                                                           match, taken, prop, hseed, st, round);
         k_hem_match<<<gv, CB, 0, s>>>(n, match, taken, prop, st);
         k_hem_round_end<<<1, 1, 0, s>>>(n, st);
     }
