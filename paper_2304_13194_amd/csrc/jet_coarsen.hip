@@ -60,8 +60,12 @@ __global__ __launch_bounds__(CB) void k_chk_vertices(int n, const int64_t *xadj,
     if (threadIdx.x == 0) atomicAdd((unsigned long long *)&st->wsum, (unsigned long long)ws);
 }
 
+// Neighbour-range, self-loop and weight checks and the total edge weight.
+// Each thread takes runs of 16 consecutive entries: the run's first row is
+// searched between two row marks, and the 16 entries are loaded at once
+// before the rows are walked.
 __global__ __launch_bounds__(CB) void k_chk_edges(int n, int64_t nnz, const int64_t *xadj, const int32_t *adj,
-                                                  const int32_t *ew, CState *st)
+                                                  const int32_t *ew, const int32_t *mark, int64_t nmark, CState *st)
 {
     __shared__ int64_t s_red[CB / 64];
     constexpr int RUN = 16;
@@ -70,19 +74,40 @@ __global__ __launch_bounds__(CB) void k_chk_edges(int n, int64_t nnz, const int6
     const int64_t nruns = (nnz + RUN - 1) / RUN;
     for (int64_t r = (int64_t)blockIdx.x * CB + threadIdx.x; r < nruns; r += (int64_t)gridDim.x * CB) {
         const int64_t e0 = r * RUN, e1 = e0 + RUN < nnz ? e0 + RUN : nnz;
-        int lo = 0, hi = n;
+        // xadj[lo] <= e0 < xadj[hi] on well-formed offsets; the guards keep
+        // lo and hi inside [0, n) on malformed ones (k_chk_vertices flags them)
+        const int64_t mi = e0 / MARK;
+        int lo = mark[mi];
+        int hi = mi + 1 < nmark ? mark[mi + 1] + 1 : n;
+        if (hi > n) hi = n;
+        if (lo >= hi) lo = hi - 1;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (xadj[mid] <= e0) lo = mid; else hi = mid;
+            if (xadj[mid] <= e0) lo = mid;
+            else hi = mid;
+        }
+        int u[RUN], w[RUN];
+#pragma unroll
+        for (int j = 0; j < RUN; j++) {
+            const int64_t e = e0 + j;
+            u[j] = e < e1 ? adj[e] : -1;
+            w[j] = e < e1 ? (ew ? ew[e] : 1) : 1;
         }
         int v = lo;
         int64_t vend = xadj[v + 1];
-        for (int64_t e = e0; e < e1; e++) {
-            while (e >= vend && v < n - 1) { v++; vend = xadj[v + 1]; }
-            const int u = adj[e];
-            const int w = ew ? ew[e] : 1;
-            if (u < 0 || u >= n || u == v || w < 1) { bad = 1; continue; }
-            ews += w;
+#pragma unroll
+        for (int j = 0; j < RUN; j++) {
+            const int64_t e = e0 + j;
+            if (e >= e1) break;
+            while (e >= vend && v < n - 1) {
+                v++;
+                vend = xadj[v + 1];
+            }
+            if (u[j] < 0 || u[j] >= n || u[j] == v || w[j] < 1) {
+                bad = 1;
+                continue;
+            }
+            ews += w[j];
         }
     }
     ews = block_sum<CB>(ews, s_red);
@@ -237,6 +262,30 @@ __global__ __launch_bounds__(CB) void k_hem_propose(int n, const int64_t *xadj, 
     }
 }
 
+// Rows of 65 to HEM_MID entries: one wave per row.
+__global__ __launch_bounds__(CB) void k_hem_propose_mid(const int32_t *list, int cnt, const int64_t *xadj,
+                                                        const int32_t *adj, const int32_t *ew, const int32_t *match,
+                                                        const uint8_t *taken, int32_t *prop, uint64_t hseed,
+                                                        const CState *st, int round)
+{
+    if (st->stop) return;
+    const int lane = threadIdx.x & 63;
+    const int nw = gridDim.x * (CB / 64);
+    for (int i = blockIdx.x * (CB / 64) + (threadIdx.x >> 6); i < cnt; i += nw) {
+        const int v = list[i];
+        if (match[v] >= 0) { if (lane == 0) prop[v] = -1; continue; }
+        if (prop_stands(round, prop, taken, v)) continue;  // uniform over the wave
+        Prop b = prop_scan_row(v, xadj[v], xadj[v + 1], lane, 64, adj, ew, taken, hseed);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            Prop q = prop_shfl_xor(b, o, 64);
+            if (prop_better(q, b)) b = q;
+        }
+        if (lane == 0) prop[v] = b.u;
+    }
+}
+
+// Rows of more than HEM_MID entries: one block per row.
 __global__ __launch_bounds__(CB) void k_hem_propose_big(const int32_t *big, int nbig, const int64_t *xadj,
                                                         const int32_t *adj, const int32_t *ew, const int32_t *match,
                                                         const uint8_t *taken, int32_t *prop, uint64_t hseed,
@@ -295,14 +344,39 @@ __global__ void k_hem_round_end(int n, CState *st)
     st->newly = 0;
 }
 
+// Rows of more than 64 entries: those of at most HEM_MID entries (one wave
+// each) from the front of `big`, the longer ones (one block each) from its
+// back; counts in nbig[0] and nbig[1]. Each block counts its contiguous range
+// first and takes its places with one atomic per list: a list counter is one
+// address that every XCD reaches through memory, so one atomic per wave
+// serialised into most of the kernel's time.
+constexpr int HEM_MID = 1024;
 __global__ __launch_bounds__(CB) void k_big_list(int n, const int64_t *xadj, int32_t *big, int32_t *nbig)
 {
-    const int stride = gridDim.x * CB;
-    const int nloop = (n + stride - 1) / stride;
-    for (int it = 0; it < nloop; it++) {
-        const int v = it * stride + blockIdx.x * CB + threadIdx.x;
-        const bool heavy = v < n && xadj[v + 1] - xadj[v] > 64;
-        wave_append(heavy, nbig, big, v);
+    __shared__ int32_t s_scan[CB / 64];
+    __shared__ int32_t s_base[2];
+    const int per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t l0 = (int64_t)blockIdx.x * per, h0 = l0 + per;
+    const int lo = (int)(l0 < n ? l0 : n), hi = (int)(h0 < n ? h0 : n);
+    int cm = 0, cl = 0;
+    for (int v = lo + threadIdx.x; v < hi; v += CB) {
+        const int64_t d = xadj[v + 1] - xadj[v];
+        cm += d > 64 && d <= HEM_MID;
+        cl += d > HEM_MID;
+    }
+    int totm, totl;
+    const int offm = block_excl_scan<CB>(cm, s_scan, totm);
+    const int offl = block_excl_scan<CB>(cl, s_scan, totl);
+    if (threadIdx.x == 0) {
+        s_base[0] = totm > 0 ? atomicAdd(&nbig[0], totm) : 0;
+        s_base[1] = totl > 0 ? atomicAdd(&nbig[1], totl) : 0;
+    }
+    __syncthreads();
+    int pm = s_base[0] + offm, pl = s_base[1] + offl;
+    for (int v = lo + threadIdx.x; v < hi; v += CB) {
+        const int64_t d = xadj[v + 1] - xadj[v];
+        if (d > HEM_MID) big[n - 1 - pl++] = v;
+        else if (d > 64) big[pm++] = v;
     }
 }
 
@@ -881,8 +955,14 @@ int check_graph(jet_context *ctx, const jet_csr *g, uint32_t flags, hipStream_t 
     JET_TRY(stream_wait(ctx, s));
     if (ends[0] != 0 || ends[1] != g->nnz) return JET_EGRAPH;
     k_chk_vertices<<<grid_for(ctx, g->n, CB, 4), CB, 0, s>>>(g->n, g->xadj, g->vwgt, st);
-    if (g->nnz > 0)
-        k_chk_edges<<<grid_for(ctx, (g->nnz + 15) / 16, CB), CB, 0, s>>>(g->n, g->nnz, g->xadj, g->adjncy, g->adjwgt, st);
+    if (g->nnz > 0) {
+        int32_t *mark = nullptr;
+        int64_t nmark = 0;
+        const int rs = row_marks(ctx, g->xadj, g->n, g->nnz, &mark, &nmark, s);
+        if (rs) return rs;
+        k_chk_edges<<<grid_for(ctx, (g->nnz + 15) / 16, CB), CB, 0, s>>>(g->n, g->nnz, g->xadj, g->adjncy, g->adjwgt,
+                                                                        mark, nmark, st);
+    }
     JET_TRY(hipGetLastError());
     CState *h = (CState *)((char *)ctx->pinned + 2304);
     JET_TRY(hipMemcpyAsync(h, st, sizeof(CState), hipMemcpyDeviceToHost, s));
@@ -1037,16 +1117,19 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     const int gv = grid_for(ctx, n, CB, 4);
     k_big_list<<<gv, CB, 0, s>>>(n, f->xadj, big, nbig);
     int32_t *hbig = (int32_t *)((char *)ctx->pinned + 2400);
-    JET_TRY(hipMemcpyAsync(hbig, nbig, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    JET_TRY(hipMemcpyAsync(hbig, nbig, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     JET_TRY(stream_wait(ctx, s));
-    const int nb = *hbig;
+    const int nmid = hbig[0], nhuge = hbig[1];
     const uint64_t hseed = stream64(seed, (uint64_t)(uint32_t)level);
     const int gp = grid_for(ctx, n, CB / 8);
     for (int round = 0; round < 16; round++) {
         k_hem_propose<<<gp, CB, 0, s>>>(n, f->xadj, f->adjncy, f->adjwgt, match, taken, prop, hseed, st, round);
-        if (nb > 0)
-            k_hem_propose_big<<<std::min(nb, ctx->num_cu * 8), CB, 0, s>>>(big, nb, f->xadj, f->adjncy, f->adjwgt,
-                                                                           match, taken, prop, hseed, st, round);
+        if (nmid > 0)
+            k_hem_propose_mid<<<std::min((nmid + CB / 64 - 1) / (CB / 64), ctx->num_cu * 8), CB, 0, s>>>(
+                big, nmid, f->xadj, f->adjncy, f->adjwgt, match, taken, prop, hseed, st, round);
+        if (nhuge > 0)
+            k_hem_propose_big<<<std::min(nhuge, ctx->num_cu * 8), CB, 0, s>>>(
+                big + (n - nhuge), nhuge, f->xadj, f->adjncy, f->adjwgt, match, taken, prop, hseed, st, round);
         k_hem_match<<<gv, CB, 0, s>>>(n, match, taken, prop, st);
         k_hem_round_end<<<1, 1, 0, s>>>(n, st);
     }

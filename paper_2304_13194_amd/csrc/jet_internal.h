@@ -225,6 +225,13 @@ int refine_batch(jet_context *ctx, int count, const jet_csr *graphs, const jet_p
                  int32_t *const *parts, jet_stats *stats, jet_trace *traces, hipStream_t s);
 
 int hip_status(jet_context *ctx, hipError_t e);
+// Row marks of a CSR, for the passes that take runs of entries: mark[i] = the
+// row holding entry i * MARK (the largest v with xadj[v] <= i * MARK), for
+// i < nmark = nnz / MARK + 1, so that a run's row search starts within a few
+// rows. Launched on s into workspace slot WS_RMARK.
+constexpr int MARK = 4096;
+int row_marks(jet_context *ctx, const int64_t *xadj, int n, int64_t nnz, int32_t **mark, int64_t *nmark,
+              hipStream_t s);
 int validate_full_csr(jet_context *ctx, const jet_csr *g, hipStream_t s);
 // Cheap O(n + m) input checks (and the full check under JET_F_VALIDATE).
 int check_graph(jet_context *ctx, const jet_csr *g, uint32_t flags, hipStream_t s);

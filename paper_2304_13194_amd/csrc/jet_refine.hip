@@ -386,10 +386,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_vertices(KArgs a, const int32_t 
             if (s_w[p]) atomicAdd((unsigned long long *)&a.w[p], (unsigned long long)(int64_t)s_w[p]);
 }
 
-// Row marks for the edge pass: mark[i] = the row holding CSR entry i * MARK
-// (the largest v with xadj[v] <= i * MARK), for i < nmark = nnz / MARK + 1,
-// so a run's row search starts within a few rows instead of over all n.
-constexpr int MARK = 4096;
+// Row marks (see row_marks) for the edge passes.
 __global__ __launch_bounds__(BLOCK) void k_row_marks(const int64_t *xadj, int n, int64_t nmark, int32_t *mark)
 {
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nmark; i += (int64_t)gridDim.x * BLOCK) {
@@ -3845,6 +3842,18 @@ struct Plan {
 
 static int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+int row_marks(jet_context *ctx, const int64_t *xadj, int n, int64_t nnz, int32_t **mark, int64_t *nmark,
+              hipStream_t s)
+{
+    const int64_t nm = nnz / MARK + 1;
+    int32_t *m = (int32_t *)ws_get(ctx, WS_RMARK, sizeof(int32_t) * (size_t)nm);
+    if (!m) return JET_ENOMEM;
+    k_row_marks<<<std::max(1, std::min(div_up(nm, BLOCK), ctx->num_cu)), BLOCK, 0, s>>>(xadj, n, nm, m);
+    *mark = m;
+    *nmark = nm;
+    return JET_OK;
+}
+
 static void plan_roles(const jet_context *ctx, const KArgs &a, const int32_t *cnt, Plan &pl)
 {
     const int maxb = ctx->num_cu * 8;
@@ -4403,10 +4412,10 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     if (n > 0) k_init_vertices<<<grid_v, BLOCK, a.vg ? 0 : (size_t)a.k * 4, s>>>(a, L.part_in, blkcnt);
     if (L.u.nnz > 0) {
         const int grid_e = std::max(1, std::min(div_up(div_up(L.u.nnz, 16), BLOCK), ctx->num_cu * 8));
-        const int64_t nmark = L.u.nnz / MARK + 1;
-        int32_t *mark = (int32_t *)ws_get(ctx, WS_RMARK, sizeof(int32_t) * (size_t)nmark);
-        if (!mark) return JET_ENOMEM;
-        k_row_marks<<<std::max(1, std::min(div_up(nmark, BLOCK), ctx->num_cu)), BLOCK, 0, s>>>(L.u.xadj, n, nmark, mark);
+        int32_t *mark = nullptr;
+        int64_t nmark = 0;
+        const int rs = row_marks(ctx, L.u.xadj, n, L.u.nnz, &mark, &nmark, s);
+        if (rs) return rs;
         k_init_edges<<<grid_e, BLOCK, 0, s>>>(a, L.u.nnz, mark, nmark);
     }
     k_bin_scan<<<1, BLOCK, 0, s>>>(blkcnt, grid_v);
