@@ -569,8 +569,10 @@ __global__ __launch_bounds__(CB) void k_contract_extract(int nc, const int64_t *
 // neighbour, value = summed edge weight) built from its members' fine rows.
 // A count pass sizes the rows, an exclusive scan places them, a fill pass
 // writes them. Rows of bound <= 64 use 8-lane groups with 128 slots; rows of
-// bound <= 2048 one block with 4096 slots; larger rows a global table.
+// bound <= 512 one wave with 1024 slots; rows of bound <= 2048 one block with
+// 4096 slots; larger rows a global table.
 constexpr int CS_MAX = 64, CS_T = 128;
+constexpr int CW_MAX = 512, CW_T = 1024;
 constexpr int CM_MAX = 2048, CM_T = 4096;
 
 __device__ __forceinline__ uint32_t chash(int key, int bits)
@@ -584,20 +586,48 @@ __device__ __forceinline__ int64_t member_entry(int64_t s0, int d0, int64_t s1, 
     return idx < d0 ? s0 + idx : s1 + (idx - d0);
 }
 
-__global__ __launch_bounds__(CB) void k_cclass(int nc, const int32_t *bound, int32_t *listM, int32_t *listL,
-                                               int32_t *cnt, int64_t *ltot)
+// Lists of the wave rows (count in cnt[3]), block rows (cnt[0]) and large
+// rows (cnt[1]; their table slots, 2 * bound each, summed into ltot). Each
+// block counts its contiguous stretch first and takes its places with one
+// atomic per list (a list counter is one address for the whole device).
+__global__ __launch_bounds__(CB) void k_cclass(int nc, const int32_t *bound, int32_t *listW, int32_t *listM,
+                                               int32_t *listL, int32_t *cnt, int64_t *ltot)
 {
-    __shared__ int32_t s_cnt[CB / 64 + 1];
-    const int stride = gridDim.x * CB;
-    const int nloop = (nc + stride - 1) / stride;
-    for (int it = 0; it < nloop; it++) {
-        const int c = it * stride + blockIdx.x * CB + threadIdx.x;
-        const int b = c < nc ? bound[c] : 0;
-        block_append<CB>(c < nc && b > CS_MAX && b <= CM_MAX, &cnt[0], listM, c, s_cnt);
-        const bool isL = c < nc && b > CM_MAX;
-        block_append<CB>(isL, &cnt[1], listL, c, s_cnt);
-        const int64_t lw = gsum<64>(isL ? 2 * (int64_t)b : (int64_t)0);  // one atomic per wave
-        if ((threadIdx.x & 63) == 0 && lw) atomicAdd((unsigned long long *)ltot, (unsigned long long)lw);
+    __shared__ int32_t s_scan[CB / 64];
+    __shared__ int64_t s_red[CB / 64];
+    __shared__ int32_t s_base[3];
+    const int per = (nc + gridDim.x - 1) / gridDim.x;
+    const int64_t l0 = (int64_t)blockIdx.x * per, h0 = l0 + per;
+    const int lo = (int)(l0 < nc ? l0 : nc), hi = (int)(h0 < nc ? h0 : nc);
+    int cw = 0, cm = 0, cl = 0;
+    int64_t lw = 0;
+    for (int c = lo + threadIdx.x; c < hi; c += CB) {
+        const int b = bound[c];
+        cw += b > CS_MAX && b <= CW_MAX;
+        cm += b > CW_MAX && b <= CM_MAX;
+        if (b > CM_MAX) {
+            cl++;
+            lw += 2 * (int64_t)b;
+        }
+    }
+    int tw, tm, tl;
+    const int ow = block_excl_scan<CB>(cw, s_scan, tw);
+    const int om = block_excl_scan<CB>(cm, s_scan, tm);
+    const int ol = block_excl_scan<CB>(cl, s_scan, tl);
+    lw = block_sum<CB>(lw, s_red);
+    if (threadIdx.x == 0) {
+        s_base[0] = tw > 0 ? atomicAdd(&cnt[3], tw) : 0;
+        s_base[1] = tm > 0 ? atomicAdd(&cnt[0], tm) : 0;
+        s_base[2] = tl > 0 ? atomicAdd(&cnt[1], tl) : 0;
+        if (lw) atomicAdd((unsigned long long *)ltot, (unsigned long long)lw);
+    }
+    __syncthreads();
+    int pw = s_base[0] + ow, pm = s_base[1] + om, pl = s_base[2] + ol;
+    for (int c = lo + threadIdx.x; c < hi; c += CB) {
+        const int b = bound[c];
+        if (b > CM_MAX) listL[pl++] = c;
+        else if (b > CW_MAX) listM[pm++] = c;
+        else if (b > CS_MAX) listW[pw++] = c;
     }
 }
 
@@ -671,6 +701,79 @@ __global__ __launch_bounds__(CB) void k_crow_small(int nc, const int32_t *bound,
                     V[j] = 0;
                 }
                 out += __popc(gm);
+            }
+        }
+        lds_fence_wave();
+    }
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(CB) void k_crow_wave(const int32_t *list, int cntW, const int32_t *mem0,
+                                                  const int32_t *mem1, const int64_t *xadj, const int32_t *adj,
+                                                  const int32_t *ew, const int32_t *map, int32_t *ccount,
+                                                  const int64_t *cxadj, int32_t *cadj, int32_t *cew,
+                                                  int32_t *overflow)
+{
+    __shared__ int32_t keys[(CB / 64) * CW_T];
+    __shared__ int32_t vals[(CB / 64) * CW_T];
+    for (int i = threadIdx.x; i < (CB / 64) * CW_T; i += CB) { keys[i] = -1; vals[i] = 0; }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    int32_t *K = keys + (threadIdx.x >> 6) * CW_T;
+    int32_t *V = vals + (threadIdx.x >> 6) * CW_T;
+    constexpr int PER = CW_T / 64;
+    const int nw = gridDim.x * (CB / 64);
+    for (int r = blockIdx.x * (CB / 64) + (threadIdx.x >> 6); r < cntW; r += nw) {
+        const int c = list[r];
+        const int m0 = mem0[c], m1 = mem1[c];
+        const int64_t s0 = xadj[m0];
+        const int d0 = (int)(xadj[m0 + 1] - s0);
+        int64_t s1 = 0;
+        int d1 = 0;
+        if (m1 >= 0) { s1 = xadj[m1]; d1 = (int)(xadj[m1 + 1] - s1); }
+        // at most CW_MAX = 512 member entries: 8 per lane, all loaded first
+        constexpr int UW = CW_MAX / 64;
+        int cuv[UW], wv[UW];
+#pragma unroll
+        for (int q = 0; q < UW; q++) {
+            const int idx = lane + q * 64;
+            const int64_t e = member_entry(s0, d0, s1, idx);
+            cuv[q] = idx < d0 + d1 ? adj[e] : -1;
+            wv[q] = idx < d0 + d1 ? (ew ? ew[e] : 1) : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < UW; q++) cuv[q] = cuv[q] >= 0 ? map[cuv[q]] : -1;
+        for (int q = 0; q < UW; q++) {
+            const int cu = cuv[q];
+            if (cu < 0 || cu == c) continue;
+            const int w = wv[q];
+            uint32_t h = chash(cu, 10);
+            for (int probe = 0;; probe++) {
+                if (probe == CW_T) { *overflow = 1; break; }  // cannot happen: <= 512 keys in 1024 slots
+                const int old = atomicCAS(&K[h], -1, cu);
+                if (old == -1 || old == cu) { if (FILL) atomicAdd(&V[h], w); break; }
+                h = (h + 1) & (CW_T - 1);
+            }
+        }
+        lds_fence_wave();
+        int mine = 0;
+        const int j0 = lane * PER;
+        for (int q = 0; q < PER; q++) mine += K[j0 + q] >= 0;
+        if (!FILL) {
+            const int tot = gsum<64>(mine);
+            if (lane == 0) ccount[c] = tot;
+            for (int q = 0; q < PER; q++) K[j0 + q] = -1;
+        } else {
+            int64_t out = cxadj[c] + (wave_incl_scan(mine) - mine);
+            for (int q = 0; q < PER; q++) {
+                const int key = K[j0 + q];
+                if (key >= 0) {
+                    cadj[out] = key;
+                    cew[out] = V[j0 + q];
+                    out++;
+                    K[j0 + q] = -1;
+                    V[j0 + q] = 0;
+                }
             }
         }
         lds_fence_wave();
@@ -1155,19 +1258,20 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     int32_t *ccount = (int32_t *)ws_get(ctx, WS_C7, ncc * 4);
     int32_t *mem0 = (int32_t *)ws_get(ctx, WS_C8, ncc * 4);
     int32_t *mem1 = (int32_t *)ws_get(ctx, WS_C9, ncc * 4);
-    int32_t *lists = (int32_t *)ws_get(ctx, WS_C12, 2 * ncc * 4 + 64);
+    const size_t nce = (ncc + 1) & ~(size_t)1;  // even, so that the counters after the lists are 8-byte aligned
+    int32_t *lists = (int32_t *)ws_get(ctx, WS_C12, 3 * nce * 4 + 64);
     int64_t *cxadj = (int64_t *)hier_alloc(h, (ncc + 1) * 8);
     if (!map || !cvw || !bound || !ccount || !mem0 || !mem1 || !lists || !cxadj) return JET_ENOMEM;
-    int32_t *listM = lists, *listL = lists + ncc;
-    int32_t *ccnt = lists + 2 * ncc;          // [0] medium rows, [1] large rows, [2] probe overflow
+    int32_t *listM = lists, *listL = lists + nce, *listW = lists + 2 * nce;
+    int32_t *ccnt = lists + 3 * nce;          // [0] block rows, [1] large rows, [2] probe overflow, [3] wave rows
     int64_t *ltot = (int64_t *)(ccnt + 4);    // table slots of the large rows (bytes 16..23)
     k_coarse_map<<<gv, CB, 0, s>>>(n, match, cid, f->xadj, f->vwgt, map, cvw, bound, mem0, mem1);
     JET_TRY(hipMemsetAsync(ccnt, 0, 64, s));
-    k_cclass<<<grid_for(ctx, nc, CB, 4), CB, 0, s>>>(nc, bound, listM, listL, ccnt, ltot);
+    k_cclass<<<grid_for(ctx, nc, CB, 4), CB, 0, s>>>(nc, bound, listW, listM, listL, ccnt, ltot);
     int32_t *hc = (int32_t *)((char *)ctx->pinned + 2448);
     JET_TRY(hipMemcpyAsync(hc, ccnt, 24, hipMemcpyDeviceToHost, s));
     JET_TRY(stream_wait(ctx, s));
-    const int nM = hc[0], nL = hc[1];
+    const int nM = hc[0], nL = hc[1], nW = hc[3];
     const int64_t lslots = *(int64_t *)(hc + 4);
     int64_t *toffL = nullptr;
     unsigned long long *ltab = nullptr;
@@ -1188,6 +1292,10 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     const size_t lds_m = 2 * CM_T * sizeof(int32_t);
     k_crow_small<false><<<gsmall, CB, 0, s>>>(nc, bound, mem0, mem1, f->xadj, f->adjncy, f->adjwgt, map, ccount,
                                                nullptr, nullptr, nullptr, ccnt + 2);
+    const int gwave = std::max(1, std::min((nW + CB / 64 - 1) / (CB / 64), ctx->num_cu * 8));
+    if (nW > 0)
+        k_crow_wave<false><<<gwave, CB, 0, s>>>(listW, nW, mem0, mem1, f->xadj, f->adjncy, f->adjwgt, map, ccount,
+                                                 nullptr, nullptr, nullptr, ccnt + 2);
     if (nM > 0)
         k_crow_medium<false><<<std::min(nM, ctx->num_cu * 4), CB, lds_m, s>>>(
             listM, nM, mem0, mem1, f->xadj, f->adjncy, f->adjwgt, map, ccount, nullptr, nullptr, nullptr, ccnt + 2);
@@ -1202,6 +1310,9 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     if (!cadj || !cew) return JET_ENOMEM;
     k_crow_small<true><<<gsmall, CB, 0, s>>>(nc, bound, mem0, mem1, f->xadj, f->adjncy, f->adjwgt, map, ccount,
                                               cxadj, cadj, cew, ccnt + 2);
+    if (nW > 0)
+        k_crow_wave<true><<<gwave, CB, 0, s>>>(listW, nW, mem0, mem1, f->xadj, f->adjncy, f->adjwgt, map, ccount,
+                                                cxadj, cadj, cew, ccnt + 2);
     if (nM > 0)
         k_crow_medium<true><<<std::min(nM, ctx->num_cu * 4), CB, lds_m, s>>>(
             listM, nM, mem0, mem1, f->xadj, f->adjncy, f->adjwgt, map, ccount, cxadj, cadj, cew, ccnt + 2);
