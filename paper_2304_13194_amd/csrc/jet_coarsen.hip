@@ -1618,6 +1618,7 @@ extern "C" int jet_partition(jet_context *ctx, const jet_csr *g, const jet_param
         }
         if (st == JET_OK) {
             int32_t *cur = pa, *other = pb;
+            int64_t cut_prev = -1;  // cut of the coarser level's result, which the projection keeps
             for (int i = l; i >= 0 && st == JET_OK; i--) {
                 if (i < l) {
                     int32_t *dst = i == 0 ? part_out : other;
@@ -1640,8 +1641,10 @@ extern "C" int jet_partition(jet_context *ctx, const jet_csr *g, const jet_param
                     recs = trace->recs + trace->count;
                     cap = trace->cap - trace->count;
                 }
-                st = refine_level(ctx, &h.lv[i], &q, cur, nullptr, &ls, recs, cap, &cnt, &tot, s);
+                st = refine_level(ctx, &h.lv[i], &q, cur, nullptr, &ls, recs, cap, &cnt, &tot, s,
+                                  i < l ? cut_prev : -1);
                 if (st) break;
+                cut_prev = ls.cut;
                 if (trace) { trace->count += cnt; trace->total += tot; }
                 agg.iters += ls.iters;
                 agg.lp_iters += ls.lp_iters;

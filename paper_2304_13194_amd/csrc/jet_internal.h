@@ -215,9 +215,14 @@ void *pinned_get(jet_context *ctx, size_t bytes);
 hipError_t stream_wait(jet_context *ctx, hipStream_t s);
 
 // Refinement of one level; `part` holds P_0 on entry and P_best on exit.
+// cut0 >= 0: P_0 is the projection of a coarser level's result whose cut was
+// cut0 (projection keeps the cut), and the graph is one the library built or
+// checked, so the set-up skips its edge pass (cut, total edge weight and
+// entry checks).
 int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int32_t *part,
                  int64_t *part_weights_out, jet_stats *stats, jet_trace_rec *trace_host,
-                 int32_t trace_cap, int32_t *trace_count, int32_t *trace_total, hipStream_t s);
+                 int32_t trace_cap, int32_t *trace_count, int32_t *trace_total, hipStream_t s,
+                 int64_t cut0 = -1);
 
 // Refinement of `count` independent graphs in one launch sequence; parts[i]
 // holds graph i's P_0 on entry and its P_best on exit.

@@ -4328,6 +4328,9 @@ struct Launch {
     int ktot = 0, kmax = 0, ntile = 0;
     int64_t tsum_cap = 0;
     jet_trace_rec *trace_dev = nullptr;
+    // one graph whose P_0 is a projection: its cut, known from the coarser
+    // level (>= 0), replaces the set-up edge pass
+    int64_t cut0 = -1;
 };
 
 // Fills the workspace and the controllers, runs the set-up passes and
@@ -4410,7 +4413,8 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     JET_TRY(hipMemsetAsync(a.bstat, 0, sizeof(int64_t) * NSTAT * NSHARD * (size_t)G, s));
     JET_TRY(hipMemsetAsync(a.cnt, 0, sizeof(int32_t) * (CNT_N + 2), s));
     if (n > 0) k_init_vertices<<<grid_v, BLOCK, a.vg ? 0 : (size_t)a.k * 4, s>>>(a, L.part_in, blkcnt);
-    if (L.u.nnz > 0) {
+    const bool known_cut = L.G == 1 && L.cut0 >= 0;
+    if (L.u.nnz > 0 && !known_cut) {
         const int grid_e = std::max(1, std::min(div_up(div_up(L.u.nnz, 16), BLOCK), ctx->num_cu * 8));
         int32_t *mark = nullptr;
         int64_t nmark = 0;
@@ -4443,6 +4447,7 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     if (xends[0] != 0 || xends[1] != L.u.nnz || hcnt[1]) return JET_EGRAPH;
     for (int g = 0; g < G; g++)
         if (hcs[g].bad_part) return JET_EPART;
+    if (known_cut) hcs[0].cut = L.cut0;
     // limits: total vertex weight below 2^31 (part weights, tile sums), and
     // every weighted degree below 2^31 (connectivities, gains, losses are
     // int32); the exact degree check runs only when the total edge weight
@@ -4844,7 +4849,7 @@ static void async_done(void *p)
 
 int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int32_t *part,
                  int64_t *part_weights_out, jet_stats *stats, jet_trace_rec *trace_host, int32_t trace_cap,
-                 int32_t *trace_count, int32_t *trace_total, hipStream_t s)
+                 int32_t *trace_count, int32_t *trace_total, hipStream_t s, int64_t cut0)
 {
     int st = check_params(g, prm);
     if (st) return st;
@@ -4871,6 +4876,7 @@ int refine_level(jet_context *ctx, const jet_csr *g, const jet_params *prm, int3
     }
     Launch L;
     single_launch(L, g, prm, part, trace_dev, trace_cap);
+    L.cut0 = cut0;
     Plan pl;
     st = setup(ctx, L, pl, s, nullptr);
     if (st) return st;
