@@ -237,28 +237,47 @@ __device__ __forceinline__ bool prop_stands(int round, const int32_t *prop, cons
     return pu < 0 || !taken[pu];
 }
 
-// Proposals. Vertices of degree <= 64 use 8-lane groups; heavier rows are
-// left to k_hem_propose_big (one block per row) through the `big` list.
+// Proposals of the vertices of degree <= 64 (heavier rows are left to the
+// wave and block kernels through the `big` lists). Each lane of a wave first
+// inspects one vertex with coalesced loads; only unmatched vertices whose
+// proposal no longer stands are queued in LDS and scanned by the wave's
+// groups of 8 lanes. Matched vertices cost no group time (k_hem_match clears
+// their proposals once, when they match).
 __global__ __launch_bounds__(CB) void k_hem_propose(int n, const int64_t *xadj, const int32_t *adj, const int32_t *ew,
                                                     const int32_t *match, const uint8_t *taken, int32_t *prop,
                                                     uint64_t hseed, const CState *st, int round)
 {
+    __shared__ int32_t s_q[CB];
     if (st->stop) return;
     constexpr int G = 8;
-    const int gl = threadIdx.x & (G - 1);
-    const int ngroups = gridDim.x * (CB / G);
-    for (int v = blockIdx.x * (CB / G) + (threadIdx.x >> 3); v < n; v += ngroups) {
-        const int64_t s = xadj[v], e = xadj[v + 1];
-        if (e - s > 64) continue;  // heavy row: handled by the block kernel
-        if (match[v] >= 0) { if (gl == 0) prop[v] = -1; continue; }
-        if (prop_stands(round, prop, taken, v)) continue;
-        Prop b = prop_scan_row(v, s, e, gl, G, adj, ew, taken, hseed);
-#pragma unroll
-        for (int o = G / 2; o > 0; o >>= 1) {
-            Prop q = prop_shfl_xor(b, o, G);
-            if (prop_better(q, b)) b = q;
+    const int lane = threadIdx.x & 63, gl = lane & (G - 1), grp = lane >> 3;
+    int32_t *q = s_q + (threadIdx.x >> 6) * 64;
+    const int nw = gridDim.x * (CB / 64);
+    for (int64_t base = (int64_t)(blockIdx.x * (CB / 64) + (threadIdx.x >> 6)) * 64; base < n; base += (int64_t)nw * 64) {
+        const int v = (int)base + lane;
+        bool need = false;
+        if (v < n) {
+            const int64_t d = xadj[v + 1] - xadj[v];
+            if (d <= 64 && match[v] < 0 && !prop_stands(round, prop, taken, v)) {
+                if (d == 0) prop[v] = -1;  // no neighbour: nothing to scan
+                else need = true;
+            }
         }
-        if (gl == 0) prop[v] = b.u;
+        const uint64_t m = __ballot(need);
+        if (need) q[__popcll(m & ((1ull << lane) - 1ull))] = v;
+        lds_fence_wave();
+        const int cnt = __popcll(m);
+        for (int i = grp; i < cnt; i += 64 / G) {
+            const int u = q[i];
+            Prop b = prop_scan_row(u, xadj[u], xadj[u + 1], gl, G, adj, ew, taken, hseed);
+#pragma unroll
+            for (int o = G / 2; o > 0; o >>= 1) {
+                Prop t = prop_shfl_xor(b, o, G);
+                if (prop_better(t, b)) b = t;
+            }
+            if (gl == 0) prop[u] = b.u;
+        }
+        lds_fence_wave();
     }
 }
 
@@ -273,7 +292,7 @@ __global__ __launch_bounds__(CB) void k_hem_propose_mid(const int32_t *list, int
     const int nw = gridDim.x * (CB / 64);
     for (int i = blockIdx.x * (CB / 64) + (threadIdx.x >> 6); i < cnt; i += nw) {
         const int v = list[i];
-        if (match[v] >= 0) { if (lane == 0) prop[v] = -1; continue; }
+        if (match[v] >= 0) continue;
         if (prop_stands(round, prop, taken, v)) continue;  // uniform over the wave
         Prop b = prop_scan_row(v, xadj[v], xadj[v + 1], lane, 64, adj, ew, taken, hseed);
 #pragma unroll
@@ -295,7 +314,7 @@ __global__ __launch_bounds__(CB) void k_hem_propose_big(const int32_t *big, int 
     if (st->stop) return;
     for (int i = blockIdx.x; i < nbig; i += gridDim.x) {
         const int v = big[i];
-        if (match[v] >= 0) { if (threadIdx.x == 0) prop[v] = -1; continue; }
+        if (match[v] >= 0) continue;
         if (prop_stands(round, prop, taken, v)) continue;  // uniform over the block
         Prop b = prop_scan_row(v, xadj[v], xadj[v + 1], threadIdx.x, CB, adj, ew, taken, hseed);
 #pragma unroll
@@ -315,8 +334,10 @@ __global__ __launch_bounds__(CB) void k_hem_propose_big(const int32_t *big, int 
     }
 }
 
-// Mutual proposals match; the smaller id of each pair writes both entries.
-__global__ __launch_bounds__(CB) void k_hem_match(int n, int32_t *match, uint8_t *taken, const int32_t *prop, CState *st)
+// Mutual proposals match; the smaller id of each pair writes both entries
+// and clears both proposals, so that no later round sees a stale proposal
+// of a matched vertex (the propose kernels skip matched vertices).
+__global__ __launch_bounds__(CB) void k_hem_match(int n, int32_t *match, uint8_t *taken, int32_t *prop, CState *st)
 {
     __shared__ int32_t s_red[CB / 64];
     if (st->stop) return;
@@ -329,6 +350,8 @@ __global__ __launch_bounds__(CB) void k_hem_match(int n, int32_t *match, uint8_t
             match[u] = v;
             taken[v] = 1;
             taken[u] = 1;
+            prop[v] = -1;
+            prop[u] = -1;
             cnt += 2;
         }
     }
