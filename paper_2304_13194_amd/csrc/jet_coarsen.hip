@@ -281,26 +281,41 @@ __global__ __launch_bounds__(CB) void k_hem_propose(int n, const int64_t *xadj, 
     }
 }
 
-// Rows of 65 to HEM_MID entries: one wave per row.
+// Rows of 65 to HEM_MID entries: one wave per row. The wave first inspects
+// 64 list entries at once and queues the rows that need a scan.
 __global__ __launch_bounds__(CB) void k_hem_propose_mid(const int32_t *list, int cnt, const int64_t *xadj,
                                                         const int32_t *adj, const int32_t *ew, const int32_t *match,
                                                         const uint8_t *taken, int32_t *prop, uint64_t hseed,
                                                         const CState *st, int round)
 {
+    __shared__ int32_t s_q[CB];
     if (st->stop) return;
     const int lane = threadIdx.x & 63;
+    int32_t *q = s_q + (threadIdx.x >> 6) * 64;
     const int nw = gridDim.x * (CB / 64);
-    for (int i = blockIdx.x * (CB / 64) + (threadIdx.x >> 6); i < cnt; i += nw) {
-        const int v = list[i];
-        if (match[v] >= 0) continue;
-        if (prop_stands(round, prop, taken, v)) continue;  // uniform over the wave
-        Prop b = prop_scan_row(v, xadj[v], xadj[v + 1], lane, 64, adj, ew, taken, hseed);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            Prop q = prop_shfl_xor(b, o, 64);
-            if (prop_better(q, b)) b = q;
+    for (int64_t base = (int64_t)(blockIdx.x * (CB / 64) + (threadIdx.x >> 6)) * 64; base < cnt; base += (int64_t)nw * 64) {
+        const int i = (int)base + lane;
+        int v = -1;
+        bool need = false;
+        if (i < cnt) {
+            v = list[i];
+            need = match[v] < 0 && !prop_stands(round, prop, taken, v);
         }
-        if (lane == 0) prop[v] = b.u;
+        const uint64_t m = __ballot(need);
+        if (need) q[__popcll(m & ((1ull << lane) - 1ull))] = v;
+        lds_fence_wave();
+        const int nq = __popcll(m);
+        for (int j = 0; j < nq; j++) {
+            const int u = q[j];
+            Prop b = prop_scan_row(u, xadj[u], xadj[u + 1], lane, 64, adj, ew, taken, hseed);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                Prop t = prop_shfl_xor(b, o, 64);
+                if (prop_better(t, b)) b = t;
+            }
+            if (lane == 0) prop[u] = b.u;
+        }
+        lds_fence_wave();
     }
 }
 
@@ -1251,7 +1266,7 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     for (int round = 0; round < 16; round++) {
         k_hem_propose<<<gp, CB, 0, s>>>(n, f->xadj, f->adjncy, f->adjwgt, match, taken, prop, hseed, st, round);
         if (nmid > 0)
-            k_hem_propose_mid<<<std::min((nmid + CB / 64 - 1) / (CB / 64), ctx->num_cu * 8), CB, 0, s>>>(
+            k_hem_propose_mid<<<std::min((nmid + CB - 1) / CB, ctx->num_cu * 8), CB, 0, s>>>(
                 big, nmid, f->xadj, f->adjncy, f->adjwgt, match, taken, prop, hseed, st, round);
         if (nhuge > 0)
             k_hem_propose_big<<<std::min(nhuge, ctx->num_cu * 8), CB, 0, s>>>(
