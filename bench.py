@@ -62,10 +62,10 @@ HBM_PEAK_GBS = 8000.0
 # the kernel source they were taken on (profiles/gain_pass_rmat22_k256.md,
 # profiles/k_gain_stencil128_k64.md).
 TRAFFIC = {
-    "rmat22": dict(src_sha256="762ea4d256058fedcd29bc6473dd70ac4ca4ed4fd4e1e9ca1ce63c10b3e448b5",
-                   fetch=1899410603, write=98564523, fetch_factor=1.9997, write_factor=1.0),
-    "stencil128": dict(src_sha256="762ea4d256058fedcd29bc6473dd70ac4ca4ed4fd4e1e9ca1ce63c10b3e448b5",
-                       fetch=249267323, write=26228473, fetch_factor=1.9997, write_factor=1.0),
+    "rmat22": dict(src_sha256="96733c57d5be7edc30186b0140dcd69dc1553ccf63746ff30a8c958dd500908e",
+                   fetch=1899464956, write=98554469, fetch_factor=1.9998, write_factor=1.0),
+    "stencil128": dict(src_sha256="96733c57d5be7edc30186b0140dcd69dc1553ccf63746ff30a8c958dd500908e",
+                       fetch=249265552, write=26226649, fetch_factor=1.9997, write_factor=1.0),
 }
 
 
