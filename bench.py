@@ -636,20 +636,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     # inputs of the batch and serving runs are generated in worker processes
-    # while the main workload runs (none of it inside a timed region)
+    # once the partition timings and the CPU baselines are done: generation
+    # running beside a timed partition slows the host thread that drives it
     pool_ex = None
     fut_rgg = fut_srv = None
     spec = None
     jobs = I.serve_job_specs(args.serve_jobs + args.serve_warmup)
-    if not (args.no_batch and args.no_serve):
-        import multiprocessing as mp
-        pool_ex = ProcessPoolExecutor(max_workers=max(1, min(6, pool_workers() - 2)), mp_context=mp.get_context("spawn"),
-                                      initializer=_worker_init)
-        if not args.no_batch:
-            spec = I.rgg_batch_spec()
-            fut_rgg = [pool_ex.submit(_gen_rgg, (n, s)) for n, _, s in spec]
-        if not args.no_serve:
-            fut_srv = [pool_ex.submit(_gen_pool_graph, sp) for sp, _, _ in jobs]
     ceiling = None if args.no_copy_ceiling else copy_ceiling()
     if ceiling:
         say(f"copy ceiling {ceiling['GBs']:.0f} GB/s")
@@ -720,6 +712,19 @@ def main():
         del sec, g2
         gc.collect()
         torch.cuda.empty_cache()
+    if not (args.no_batch and args.no_serve):
+        import multiprocessing as mp
+        say("generating batch and serving inputs")
+        pool_ex = ProcessPoolExecutor(max_workers=max(1, pool_workers() - 2), mp_context=mp.get_context("spawn"),
+                                      initializer=_worker_init)
+        if not args.no_batch:
+            spec = I.rgg_batch_spec()
+            fut_rgg = [pool_ex.submit(_gen_rgg, (n, s)) for n, _, s in spec]
+        if not args.no_serve:
+            fut_srv = [pool_ex.submit(_gen_pool_graph, sp) for sp, _, _ in jobs]
+        # every input is ready before the first timed batch or serving run
+        for f in (fut_rgg or []) + (fut_srv or []):
+            f.exception()
     if fut_rgg is not None:
         say("batch")
         try:
