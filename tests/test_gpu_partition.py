@@ -47,7 +47,8 @@ CASES = [
     ("rmat13_k16", I.rmat(13, 8, 4), 16, 6),
     ("rgg20000_k32", I.rgg(20000, 3), 32, 7),
     ("er200_k2", I.small_random_graph(200, 0.05, 9, wmax=5, vwmax=3), 2, 8),
-    # hubs: coarse rows above 64 and above 2048 entries take the wave/block and global-table paths
+    # hubs: coarse rows above 64, 512 and 2048 member entries take the wave, block and global-table
+    # contraction paths; rows above 64 and 1024 entries the wave and block matching proposals
     ("rmat14_k64_hubs", I.rmat(14, 16, 6), 64, 9),
     ("star3000_k2", I.csr_from_edges(3001, np.zeros(3000, np.int64), np.arange(1, 3001)), 2, 10),
 ]
