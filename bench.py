@@ -124,17 +124,19 @@ def load_or_make_graph(w, name, cache_dir):
     return g
 
 
-def gain_bytes(entries, rows, vertices, weighted, listed=True):
+def gain_bytes(entries, rows, vertices, weighted, listed=True, compact=False, in_x=0):
     """Algorithmic bytes of a connectivity/gain pass.
 
     Per CSR entry of an unlocked row: 4 B neighbour id (+4 B edge weight when
     weights are passed). Per unlocked row: 8 B row offsets, 4 B for its part
     id gathered by neighbours (counted once). Per visited vertex: 4 B list
     entry (none when every vertex is in the small-row class, whose list is
-    then the identity and is not read), 4 B own part, 4 B lock stamp, 8 B
-    record written.
+    then the identity and is not read), 4 B own part, 4 B lock stamp, and the
+    record written: 8 B, or, when every part id fits a byte (compact), the
+    4 B compact record plus the 4 B full F of each of the in_x vertices of X.
     """
-    return entries * (8 if weighted else 4) + rows * 12 + vertices * (20 if listed else 16)
+    per_vertex = (4 if listed else 0) + 8 + (4 if compact else 8)
+    return entries * (8 if weighted else 4) + rows * 12 + vertices * per_vertex + (4 * in_x if compact else 0)
 
 
 # ------------------------------------------------------------ input makers --
@@ -268,8 +270,11 @@ def measure_workload(J, name, g, w, seed, steps, warmup, ceiling):
     # finest level: one graph whose degrees all lie in [1, 32] has no class list
     deg = np.diff(g.xadj)
     listed = not (g.n > 0 and int(deg.min()) >= 1 and int(deg.max()) <= 32)
-    gbytes = sum(gain_bytes(s["gain_entries"], s["gain_rows"], s["gain_vertices"], not w["unit"], listed)
-                 for s, _ in res)
+    # |X| of each finest-level Jetlp pass, from the trace (one record per iteration)
+    gbytes = sum(gain_bytes(s["gain_entries"], s["gain_rows"], s["gain_vertices"], not w["unit"], listed,
+                            compact=k <= 256,
+                            in_x=sum(r["nX"] for r in tr if r["level"] == 0 and r["kind"] == 1))
+                 for s, tr in res)
     achieved = (gbytes / passes) / ((ms_gain / passes) * 1e-3) / 1e9 if passes else 0.0
     refine_ms = sum(s["ms_refine"] for s, _ in res) / steps
     fin = [r for r in tr0 if r["level"] == 0]

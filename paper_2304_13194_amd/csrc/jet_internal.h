@@ -81,8 +81,10 @@ struct KArgs {
                            // halves of a uint32; P_next = the selected destination, else P_iter.
                            // The cut-delta pass reads a neighbour's old and new part in one gather.
     uint32_t *rq;          // when P8: per vertex (P_s, in X ? P_d : P_s, F saturated to int16) in 4 bytes,
-                           // the afterburner's neighbour gather (rec's full F only where saturation hides
-                           // the order); NULL: the afterburner gathers rec
+                           // the afterburner's neighbour gather (Fx only where saturation hides the
+                           // order); it replaces rec, which is then neither written nor read.
+                           // NULL: the afterburner gathers rec
+    int32_t *Fx;           // with rq: the full F of the vertices of X (other entries stale)
     int32_t *best;         // P_best
     int2 *rec;             // Jetlp record: x = (P_s << 16) | (in X ? P_d + 1 : 0), y = F
     int32_t *dest;         // move destination or -1 (kept -1 outside moves)
@@ -202,10 +204,10 @@ enum WsSlot {
     WS_U_XADJ, WS_U_ADJ, WS_U_VW, WS_U_EW, WS_U_VG, WS_U_P0, WS_U_BEST, WS_U_DESC,
     WS_LCNT, WS_LCH, WS_GCONN, WS_LDONE, WS_TH_KEY, WS_TH_VAL, WS_TH_RUN, WS_TH_TMP, WS_WDEG,
     WS_TOFF, WS_TAB, WS_TSIZE, WS_TFAIL, WS_TLIST, WS_TBLK, WS_WQ, WS_TUNE_CTL, WS_TUNE_CNT, WS_TUNE_REC,
-    WS_TUNE_STAT, WS_P8, WS_MQ, WS_RQ, WS_RMARK, WS_C13,
+    WS_TUNE_STAT, WS_P8, WS_MQ, WS_RQ, WS_RMARK, WS_C13, WS_FX,
     WS_COUNT = 80
 };
-static_assert(WS_C13 < WS_COUNT, "workspace slots");
+static_assert(WS_FX < WS_COUNT, "workspace slots");
 
 // Grow-only workspace slot; returns nullptr on allocation failure.
 void *ws_get(jet_context *ctx, int slot, size_t bytes);

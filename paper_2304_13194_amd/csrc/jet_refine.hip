@@ -322,6 +322,17 @@ __device__ __forceinline__ void rq_set(const KArgs &a, int v, int ps, int pq, in
     ((uint32_t *)a.rq)[v] = ((uint32_t)ps << 24) | ((uint32_t)pq << 16) | ((uint32_t)fs & 0xFFFFu);
 }
 
+// Jetlp record of vertex v in rec's layout (x = P_s << 16 | (in X ? P_d + 1 :
+// 0), y = F for a vertex of X), from rq and Fx when those replace rec.
+__device__ __forceinline__ int2 own_rec(const KArgs &a, int v)
+{
+    if (!a.rq) return a.rec[v];
+    const uint32_t q = a.rq[v];
+    const int ps = (int)(q >> 24), pq = (int)((q >> 16) & 0xFFu);
+    if (pq == ps) return make_int2(ps << 16, 0);
+    return make_int2((ps << 16) | (pq + 1), a.Fx[v]);
+}
+
 __device__ __forceinline__ int degree_class(int64_t d)
 {
     return d == 0 ? CLS_Z : (d <= S_MAXDEG ? CLS_S : (d <= S2_MAXDEG ? CLS_S2 : (d <= M_MAXDEG ? CLS_M : CLS_L)));
@@ -942,7 +953,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_outputs(KArgs a, uint8_t *inX, uin
 {
     for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) {
         const bool iso = a.xadj[v + 1] == a.xadj[v];
-        inX[v] = iso ? 0 : (uint8_t)((a.rec[v].x & 0xFFFF) != 0);
+        inX[v] = iso ? 0 : (uint8_t)((own_rec(a, v).x & 0xFFFF) != 0);
         move[v] = a.dest[v] >= 0;
     }
 }
@@ -1239,8 +1250,12 @@ __device__ __forceinline__ bool gain_finish(const KArgs &a, int v, int ps, uint6
         F = f;
         if (inx) r.x |= pd + 1;
     }
-    a.rec[v] = r;
-    if (a.rq) rq_set(a, v, ps, inx ? pd : ps, r.y);
+    if (a.rq) {
+        rq_set(a, v, ps, inx ? pd : ps, r.y);
+        if (inx) a.Fx[v] = r.y;
+    } else {
+        a.rec[v] = r;
+    }
     if (a.dbg_F) {
         a.dbg_F[v] = F;
         a.dbg_cs[v] = cs;
@@ -1251,8 +1266,8 @@ __device__ __forceinline__ bool gain_finish(const KArgs &a, int v, int ps, uint6
 
 __device__ __forceinline__ void gain_locked(const KArgs &a, int v, int ps)
 {
-    a.rec[v] = make_int2(ps << 16, 0);
     if (a.rq) rq_set(a, v, ps, ps, 0);
+    else a.rec[v] = make_int2(ps << 16, 0);
     if (a.dbg_F) {
         a.dbg_F[v] = INT64_MIN;
         a.dbg_cs[v] = 0;
@@ -1597,7 +1612,6 @@ __device__ __forceinline__ int after_sum_row(const KArgs &a, int v, int64_t s, i
     int sum = 0;
     if (a.rq) {
         // one 4-byte gather per neighbour (parts and saturated F)
-        const int *Fs = (const int *)a.rec + 1;  // full F of vertex u at Fs[2 u]
         for (int base = gl; base < deg; base += stride * U) {
             int u[U], wt[U];
             uint32_t q[U];
@@ -1616,7 +1630,7 @@ __device__ __forceinline__ int after_sum_row(const KArgs &a, int v, int64_t s, i
                 const int pqu = (int)((q[j] >> 16) & 0xFFu);
                 if (pqu != qp) {
                     int Fu = (int)(int16_t)(q[j] & 0xFFFFu);
-                    if ((Fu == 32767 && Fv >= 32767) || (Fu == -32768 && Fv <= -32768)) Fu = Fs[2 * (int64_t)u[j]];
+                    if ((Fu == 32767 && Fv >= 32767) || (Fu == -32768 && Fv <= -32768)) Fu = a.Fx[u[j]];
                     if (Fu > Fv || (Fu == Fv && u[j] < v)) qp = pqu;
                 }
                 sum += qp == pd ? wt[j] : (qp == ps ? -wt[j] : 0);
@@ -1683,7 +1697,7 @@ __device__ void afterburner_body(const KArgs &a, int b)
                 const int g = gof<B>(a, m.v);
                 pv.sel<B>(a, g);
                 if (pv.kind != KIND_LP) return false;
-                const int2 r = a.rec[m.v];
+                const int2 r = own_rec(a, m.v);
                 if ((r.x & 0xFFFF) == 0) return false;  // not in X
                 if (no_afterburner(a, g)) {
                     after_store(a, m.v, r.x, 0);
@@ -1715,7 +1729,7 @@ __device__ void afterburner_body(const KArgs &a, int b)
                 const int g = gof<B>(a, m.v);
                 pv.sel<B>(a, g);
                 if (pv.kind != KIND_LP) return false;
-                const int2 r = a.rec[m.v];
+                const int2 r = own_rec(a, m.v);
                 if ((r.x & 0xFFFF) == 0) return false;  // not in X
                 if (no_afterburner(a, g)) {
                     after_store(a, m.v, r.x, 0);
@@ -1745,7 +1759,7 @@ __device__ void afterburner_body(const KArgs &a, int b)
         const int g = gof<B>(a, v);
         pv.sel<B>(a, g);
         if (pv.kind != KIND_LP) continue;
-        const int2 r = a.rec[v];
+        const int2 r = own_rec(a, v);
         if ((r.x & 0xFFFF) == 0) continue;
         const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
         if (no_afterburner(a, g)) {
@@ -2206,7 +2220,7 @@ __global__ __launch_bounds__(BLOCK) void k_lafter(KArgs a)
         const int g = gof<B>(a, ch.v);
         pv.sel<B>(a, g);
         if (pv.kind != KIND_LP || no_afterburner(a, g)) continue;
-        const int2 r = a.rec[ch.v];
+        const int2 r = own_rec(a, ch.v);
         if ((r.x & 0xFFFF) == 0) continue;  // not in X
         const int ps = r.x >> 16, pd = (r.x & 0xFFFF) - 1;
         int part = after_sum_row<8, true>(a, ch.v, ch.s, ch.len, ps, pd, r.y, threadIdx.x, BLOCK);
@@ -2232,7 +2246,7 @@ __global__ __launch_bounds__(BLOCK) void k_lafter_fin(KArgs a)
         const int g = gof<B>(a, v);
         pv.sel<B>(a, g);
         if (pv.kind != KIND_LP) continue;
-        const int2 r = a.rec[v];
+        const int2 r = own_rec(a, v);
         if ((r.x & 0xFFFF) == 0) continue;
         if (no_afterburner(a, g)) {
             after_store(a, v, r.x, 0);
@@ -4361,7 +4375,8 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     a.P8 = part8 ? (uint8_t *)ws_get(ctx, WS_P8, nn) : nullptr;
     a.mq = ws_get(ctx, WS_MQ, nn * (part8 ? 2 : 4));
     a.rq = part8 ? (uint32_t *)ws_get(ctx, WS_RQ, nn * 4) : nullptr;
-    if ((part8 && (!a.P8 || !a.rq)) || !a.mq) return JET_ENOMEM;
+    a.Fx = part8 ? (int32_t *)ws_get(ctx, WS_FX, nn * 4) : nullptr;
+    if ((part8 && (!a.P8 || !a.rq || !a.Fx)) || !a.mq) return JET_ENOMEM;
     a.rec = (int2 *)ws_get(ctx, WS_REC, nn * 8);
     a.dest = (int32_t *)ws_get(ctx, WS_DEST, nn * 4);
     a.lock = (int32_t *)ws_get(ctx, WS_LOCK, nn * 4);
@@ -5407,7 +5422,7 @@ static size_t noalloc_need(int64_t n, int64_t nnz, int64_t k, int64_t trace_cap,
     size_t b = 0;
     if (trace_cap > 0) b += al(sizeof(jet_trace_rec) * (size_t)trace_cap);
     b += al(nn * 2) + al(nn * 8) + al(nn * 4) + al(nn * 4) + al(nn) + al(nn * 4) + al(nn) + al(nn * 4);
-    b += al(nn) + al(nn * 4) + al(nn * 4);  // byte parts, packed (old, new) parts and records, at their largest
+    b += al(nn) + al(nn * 4) + al(nn * 4) + al(nn * 4);  // byte parts, packed (old, new) parts, records and F, at their largest
     b += al(4 * (size_t)(nnz / 4096 + 1));   // row marks of the edge pass
     b += al(sizeof(int64_t) * NSTAT * NSHARD) + al(sizeof(int32_t) * (CNT_N + 2)) + al(sizeof(Ctl));
     b += al(sizeof(int64_t) * (4 * (size_t)k + 9)) + al(sizeof(int32_t) * (3 * (size_t)k + 8)) + al(2 * (size_t)k + 16);
