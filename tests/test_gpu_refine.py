@@ -97,6 +97,10 @@ def cases():
         ("grid48_w40000_k4", _reweight(I.grid2d(48, 48), 40000, 40001, 1), 4, 0),
         ("rmat12_w20k_70k_k200_l1", _reweight(I.rmat(12, 8, 9), 20000, 70000, 2), 200, 1),
         ("rmat12_w20k_70k_k300", _reweight(I.rmat(12, 8, 9), 20000, 70000, 3), 300, 0),
+        # the last k whose part ids fit a byte (compact Jetlp records, part id 255
+        # in use) and the first that takes the full records
+        ("rmat12_w20k_70k_k256", _reweight(I.rmat(12, 8, 9), 20000, 70000, 4), 256, 0),
+        ("rmat12_w20k_70k_k257", _reweight(I.rmat(12, 8, 9), 20000, 70000, 4), 257, 0),
     ]
     for s in range(6):
         g = I.small_random_graph(30 + 11 * s, 0.15, 600 + s, wmax=1 + s % 5, vwmax=1 + s % 3)
