@@ -237,23 +237,20 @@ __device__ __forceinline__ bool prop_stands(int round, const int32_t *prop, cons
     return pu < 0 || !taken[pu];
 }
 
-// Proposals of the vertices of degree <= 64 (heavier rows are left to the
-// wave and block kernels through the `big` lists). Each lane of a wave first
+// Proposals of the vertices of degree <= 64. Each lane of a wave first
 // inspects one vertex with coalesced loads; only unmatched vertices whose
 // proposal no longer stands are queued in LDS and scanned by the wave's
 // groups of 8 lanes. Matched vertices cost no group time (k_hem_match clears
-// their proposals once, when they match).
-__global__ __launch_bounds__(CB) void k_hem_propose(int n, const int64_t *xadj, const int32_t *adj, const int32_t *ew,
-                                                    const int32_t *match, const uint8_t *taken, int32_t *prop,
-                                                    uint64_t hseed, const CState *st, int round)
+// their proposals once, when they match). Blocks b of nb.
+__device__ __forceinline__ void propose_small(int b, int nb, int n, const int64_t *xadj, const int32_t *adj,
+                                              const int32_t *ew, const int32_t *match, const uint8_t *taken,
+                                              int32_t *prop, uint64_t hseed, int round, int32_t *s_q)
 {
-    __shared__ int32_t s_q[CB];
-    if (st->stop) return;
     constexpr int G = 8;
     const int lane = threadIdx.x & 63, gl = lane & (G - 1), grp = lane >> 3;
     int32_t *q = s_q + (threadIdx.x >> 6) * 64;
-    const int nw = gridDim.x * (CB / 64);
-    for (int64_t base = (int64_t)(blockIdx.x * (CB / 64) + (threadIdx.x >> 6)) * 64; base < n; base += (int64_t)nw * 64) {
+    const int nw = nb * (CB / 64);
+    for (int64_t base = (int64_t)(b * (CB / 64) + (threadIdx.x >> 6)) * 64; base < n; base += (int64_t)nw * 64) {
         const int v = (int)base + lane;
         bool need = false;
         if (v < n) {
@@ -269,13 +266,13 @@ __global__ __launch_bounds__(CB) void k_hem_propose(int n, const int64_t *xadj, 
         const int cnt = __popcll(m);
         for (int i = grp; i < cnt; i += 64 / G) {
             const int u = q[i];
-            Prop b = prop_scan_row(u, xadj[u], xadj[u + 1], gl, G, adj, ew, taken, hseed);
+            Prop r = prop_scan_row(u, xadj[u], xadj[u + 1], gl, G, adj, ew, taken, hseed);
 #pragma unroll
             for (int o = G / 2; o > 0; o >>= 1) {
-                Prop t = prop_shfl_xor(b, o, G);
-                if (prop_better(t, b)) b = t;
+                Prop t = prop_shfl_xor(r, o, G);
+                if (prop_better(t, r)) r = t;
             }
-            if (gl == 0) prop[u] = b.u;
+            if (gl == 0) prop[u] = r.u;
         }
         lds_fence_wave();
     }
@@ -283,17 +280,15 @@ __global__ __launch_bounds__(CB) void k_hem_propose(int n, const int64_t *xadj, 
 
 // Rows of 65 to HEM_MID entries: one wave per row. The wave first inspects
 // 64 list entries at once and queues the rows that need a scan.
-__global__ __launch_bounds__(CB) void k_hem_propose_mid(const int32_t *list, int cnt, const int64_t *xadj,
-                                                        const int32_t *adj, const int32_t *ew, const int32_t *match,
-                                                        const uint8_t *taken, int32_t *prop, uint64_t hseed,
-                                                        const CState *st, int round)
+__device__ __forceinline__ void propose_mid(int b, int nb, const int32_t *list, int cnt, const int64_t *xadj,
+                                            const int32_t *adj, const int32_t *ew, const int32_t *match,
+                                            const uint8_t *taken, int32_t *prop, uint64_t hseed, int round,
+                                            int32_t *s_q)
 {
-    __shared__ int32_t s_q[CB];
-    if (st->stop) return;
     const int lane = threadIdx.x & 63;
     int32_t *q = s_q + (threadIdx.x >> 6) * 64;
-    const int nw = gridDim.x * (CB / 64);
-    for (int64_t base = (int64_t)(blockIdx.x * (CB / 64) + (threadIdx.x >> 6)) * 64; base < cnt; base += (int64_t)nw * 64) {
+    const int nw = nb * (CB / 64);
+    for (int64_t base = (int64_t)(b * (CB / 64) + (threadIdx.x >> 6)) * 64; base < cnt; base += (int64_t)nw * 64) {
         const int i = (int)base + lane;
         int v = -1;
         bool need = false;
@@ -307,46 +302,72 @@ __global__ __launch_bounds__(CB) void k_hem_propose_mid(const int32_t *list, int
         const int nq = __popcll(m);
         for (int j = 0; j < nq; j++) {
             const int u = q[j];
-            Prop b = prop_scan_row(u, xadj[u], xadj[u + 1], lane, 64, adj, ew, taken, hseed);
+            Prop r = prop_scan_row(u, xadj[u], xadj[u + 1], lane, 64, adj, ew, taken, hseed);
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) {
-                Prop t = prop_shfl_xor(b, o, 64);
-                if (prop_better(t, b)) b = t;
+                Prop t = prop_shfl_xor(r, o, 64);
+                if (prop_better(t, r)) r = t;
             }
-            if (lane == 0) prop[u] = b.u;
+            if (lane == 0) prop[u] = r.u;
         }
         lds_fence_wave();
     }
 }
 
 // Rows of more than HEM_MID entries: one block per row.
-__global__ __launch_bounds__(CB) void k_hem_propose_big(const int32_t *big, int nbig, const int64_t *xadj,
-                                                        const int32_t *adj, const int32_t *ew, const int32_t *match,
-                                                        const uint8_t *taken, int32_t *prop, uint64_t hseed,
-                                                        const CState *st, int round)
+__device__ __forceinline__ void propose_huge(int b, int nb, const int32_t *list, int cnt, const int64_t *xadj,
+                                             const int32_t *adj, const int32_t *ew, const int32_t *match,
+                                             const uint8_t *taken, int32_t *prop, uint64_t hseed, int round,
+                                             Prop *s_p)
 {
-    __shared__ Prop s_p[CB / 64];
-    if (st->stop) return;
-    for (int i = blockIdx.x; i < nbig; i += gridDim.x) {
-        const int v = big[i];
+    for (int i = b; i < cnt; i += nb) {
+        const int v = list[i];
         if (match[v] >= 0) continue;
         if (prop_stands(round, prop, taken, v)) continue;  // uniform over the block
-        Prop b = prop_scan_row(v, xadj[v], xadj[v + 1], threadIdx.x, CB, adj, ew, taken, hseed);
+        Prop r = prop_scan_row(v, xadj[v], xadj[v + 1], threadIdx.x, CB, adj, ew, taken, hseed);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
-            Prop q = prop_shfl_xor(b, o, 64);
-            if (prop_better(q, b)) b = q;
+            Prop t = prop_shfl_xor(r, o, 64);
+            if (prop_better(t, r)) r = t;
         }
-        if ((threadIdx.x & 63) == 0) s_p[threadIdx.x >> 6] = b;
+        if ((threadIdx.x & 63) == 0) s_p[threadIdx.x >> 6] = r;
         __syncthreads();
         if (threadIdx.x == 0) {
-            Prop r = s_p[0];
-            for (int w = 1; w < CB / 64; w++)
-                if (prop_better(s_p[w], r)) r = s_p[w];
-            prop[v] = r.u;
+            Prop w = s_p[0];
+            for (int k = 1; k < CB / 64; k++)
+                if (prop_better(s_p[k], w)) w = s_p[k];
+            prop[v] = w.u;
         }
         __syncthreads();
     }
+}
+
+// One launch per round for the three proposal roles, by block range: the
+// rows of more than HEM_MID entries first (gh blocks, from the back of
+// `big`), then those of 65 to HEM_MID (gm blocks, from its front), then every
+// vertex of degree <= 64 (the remaining blocks). The roles touch disjoint
+// vertices, and in one launch their tails overlap.
+__global__ __launch_bounds__(CB) void k_hem_propose(int n, const int64_t *xadj, const int32_t *adj, const int32_t *ew,
+                                                    const int32_t *match, const uint8_t *taken, int32_t *prop,
+                                                    uint64_t hseed, const CState *st, int round,
+                                                    const int32_t *mid, int nmid, const int32_t *huge, int nhuge,
+                                                    int gh, int gm)
+{
+    __shared__ int32_t s_q[CB];
+    __shared__ Prop s_p[CB / 64];
+    if (st->stop) return;
+    int b = blockIdx.x;
+    if (b < gh) {
+        propose_huge(b, gh, huge, nhuge, xadj, adj, ew, match, taken, prop, hseed, round, s_p);
+        return;
+    }
+    b -= gh;
+    if (b < gm) {
+        propose_mid(b, gm, mid, nmid, xadj, adj, ew, match, taken, prop, hseed, round, s_q);
+        return;
+    }
+    b -= gm;
+    propose_small(b, (int)gridDim.x - gh - gm, n, xadj, adj, ew, match, taken, prop, hseed, round, s_q);
 }
 
 // Mutual proposals match; the smaller id of each pair writes both entries
@@ -1262,15 +1283,12 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     JET_TRY(stream_wait(ctx, s));
     const int nmid = hbig[0], nhuge = hbig[1];
     const uint64_t hseed = stream64(seed, (uint64_t)(uint32_t)level);
-    const int gp = grid_for(ctx, n, CB / 8);
+    const int gs = grid_for(ctx, n, CB / 8);
+    const int gh = nhuge > 0 ? std::min(nhuge, ctx->num_cu * 8) : 0;
+    const int gm = nmid > 0 ? std::min((nmid + CB - 1) / CB, ctx->num_cu * 8) : 0;
     for (int round = 0; round < 16; round++) {
-        k_hem_propose<<<gp, CB, 0, s>>>(n, f->xadj, f->adjncy, f->adjwgt, match, taken, prop, hseed, st, round);
-        if (nmid > 0)
-            k_hem_propose_mid<<<std::min((nmid + CB - 1) / CB, ctx->num_cu * 8), CB, 0, s>>>(
-                big, nmid, f->xadj, f->adjncy, f->adjwgt, match, taken, prop, hseed, st, round);
-        if (nhuge > 0)
-            k_hem_propose_big<<<std::min(nhuge, ctx->num_cu * 8), CB, 0, s>>>(
-                big + (n - nhuge), nhuge, f->xadj, f->adjncy, f->adjwgt, match, taken, prop, hseed, st, round);
+        k_hem_propose<<<gh + gm + gs, CB, 0, s>>>(n, f->xadj, f->adjncy, f->adjwgt, match, taken, prop, hseed, st,
+                                                  round, big, nmid, big + (n - nhuge), nhuge, gh, gm);
         k_hem_match<<<gv, CB, 0, s>>>(n, match, taken, prop, st);
         k_hem_round_end<<<1, 1, 0, s>>>(n, st);
     }
