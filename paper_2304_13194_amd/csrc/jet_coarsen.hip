@@ -1341,8 +1341,13 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
         lcur = ech + nL + 1;
         JET_TRY(hipMemsetAsync(ltab, 0xFF, (size_t)lslots * 8, s));
         k_cl_offsets<<<1, CB, 0, s>>>(listL, nL, bound, toffL, ich, ech, ccount, lcur);
-        k_crow_large_insert<<<ctx->num_cu * 8, CB, 0, s>>>(listL, nL, toffL, ich, mem0, mem1, f->xadj, f->adjncy,
-                                                            f->adjwgt, map, ltab, ccount, ccnt + 2);
+        // the hub rows' insertion (bound by device-scope atomics) runs on the
+        // second stream beside the LDS-table rows (bound by gathers); the two
+        // touch disjoint coarse rows, and the scan below waits for both
+        JET_TRY(hipEventRecord(ctx->fork_ev, s));
+        JET_TRY(hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0));
+        k_crow_large_insert<<<ctx->num_cu * 4, CB, 0, ctx->aux>>>(listL, nL, toffL, ich, mem0, mem1, f->xadj,
+                                                                   f->adjncy, f->adjwgt, map, ltab, ccount, ccnt + 2);
     }
     const int gsmall = grid_for(ctx, nc, CB / 8);
     const size_t lds_m = 2 * CM_T * sizeof(int32_t);
@@ -1355,6 +1360,10 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     if (nM > 0)
         k_crow_medium<false><<<std::min(nM, ctx->num_cu * 4), CB, lds_m, s>>>(
             listM, nM, mem0, mem1, f->xadj, f->adjncy, f->adjwgt, map, ccount, nullptr, nullptr, nullptr, ccnt + 2);
+    if (nL > 0) {
+        JET_TRY(hipEventRecord(ctx->join_ev, ctx->aux));
+        JET_TRY(hipStreamWaitEvent(s, ctx->join_ev, 0));
+    }
     scan_excl(ccount, nc, cxadj, tsum, s);
     JET_TRY(hipMemcpyAsync(hn, cxadj + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     JET_TRY(hipMemcpyAsync(hc, ccnt, 24, hipMemcpyDeviceToHost, s));
@@ -1364,6 +1373,13 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     int32_t *cadj = (int32_t *)hier_alloc(h, (size_t)std::max<int64_t>(cnnz, 1) * 4);
     int32_t *cew = (int32_t *)hier_alloc(h, (size_t)std::max<int64_t>(cnnz, 1) * 4);
     if (!cadj || !cew) return JET_ENOMEM;
+    if (nL > 0) {
+        // the hub rows' extraction beside the other rows' fill, as in the count pass
+        JET_TRY(hipEventRecord(ctx->fork_ev, s));
+        JET_TRY(hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0));
+        k_crow_large_extract<<<ctx->num_cu * 4, CB, 0, ctx->aux>>>(listL, nL, toffL, ech, ltab, lcur, cxadj, cadj,
+                                                                    cew);
+    }
     k_crow_small<true><<<gsmall, CB, 0, s>>>(nc, bound, mem0, mem1, f->xadj, f->adjncy, f->adjwgt, map, ccount,
                                               cxadj, cadj, cew, ccnt + 2);
     if (nW > 0)
@@ -1372,8 +1388,10 @@ static int coarsen_level(jet_context *ctx, jet_hierarchy *h, const jet_csr *f, i
     if (nM > 0)
         k_crow_medium<true><<<std::min(nM, ctx->num_cu * 4), CB, lds_m, s>>>(
             listM, nM, mem0, mem1, f->xadj, f->adjncy, f->adjwgt, map, ccount, cxadj, cadj, cew, ccnt + 2);
-    if (nL > 0)
-        k_crow_large_extract<<<ctx->num_cu * 8, CB, 0, s>>>(listL, nL, toffL, ech, ltab, lcur, cxadj, cadj, cew);
+    if (nL > 0) {
+        JET_TRY(hipEventRecord(ctx->join_ev, ctx->aux));
+        JET_TRY(hipStreamWaitEvent(s, ctx->join_ev, 0));
+    }
     JET_TRY(hipGetLastError());
     c->n = nc;
     c->reserved = 0;

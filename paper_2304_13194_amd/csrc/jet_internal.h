@@ -179,6 +179,8 @@ struct jet_context {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> prof_ev;  // pairs around gain passes (JET_F_PROFILE)
     hipStream_t cap = nullptr;        // side stream on which iteration sequences are captured
+    hipStream_t aux = nullptr;        // second stream of the contraction (hub rows beside the other rows)
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;  // fork to and join from aux
     bool graphs = true;               // replay captured iteration pairs (JET_NO_GRAPH=1 turns it off)
     hipEvent_t wait_ev = nullptr;     // polled by stream_wait
     jet::Arena part_arena;            // coarse levels of jet_partition calls

@@ -5344,6 +5344,9 @@ extern "C" int jet_context_create(jet_context **out, int device)
         return st;
     }
     e = hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
     if (e != hipSuccess) {
         int st = hip_status(ctx, e);
         jet_context_destroy(ctx);
@@ -5374,6 +5377,9 @@ extern "C" void jet_context_destroy(jet_context *ctx)
     if (ctx->wait_ev) (void)hipEventDestroy(ctx->wait_ev);
     ctx->part_arena.release();
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
     delete ctx;
 }
 
