@@ -62,10 +62,10 @@ HBM_PEAK_GBS = 8000.0
 # the kernel source they were taken on (profiles/gain_pass_rmat22_k256.md,
 # profiles/k_gain_stencil128_k64.md).
 TRAFFIC = {
-    "rmat22": dict(src_sha256="5ba63d6f311ee444f8e1c4f3a6c8e3e9d5d0ce5a0aa04bdc7c770e907e1c2742",
-                   fetch=1876982661, write=68810667, fetch_factor=1.9997, write_factor=1.0),
-    "stencil128": dict(src_sha256="5ba63d6f311ee444f8e1c4f3a6c8e3e9d5d0ce5a0aa04bdc7c770e907e1c2742",
-                       fetch=249034824, write=9861324, fetch_factor=1.9998, write_factor=1.0),
+    "rmat22": dict(src_sha256="551f83c172e5536b95a861e93e41c755f1fa36284aaffa3fcd2b364e98639d00",
+                   fetch=1876923407, write=68815792, fetch_factor=1.9997, write_factor=1.0),
+    "stencil128": dict(src_sha256="551f83c172e5536b95a861e93e41c755f1fa36284aaffa3fcd2b364e98639d00",
+                       fetch=249044221, write=9872350, fetch_factor=1.9997, write_factor=1.0),
 }
 
 
