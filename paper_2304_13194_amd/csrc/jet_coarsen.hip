@@ -61,53 +61,79 @@ __global__ __launch_bounds__(CB) void k_chk_vertices(int n, const int64_t *xadj,
 }
 
 // Neighbour-range, self-loop and weight checks and the total edge weight.
-// Each thread takes runs of 16 consecutive entries: the run's first row is
-// searched between two row marks, and the 16 entries are loaded at once
-// before the rows are walked.
+// Block b takes the entries of row-mark interval b, [b * MARK, (b + 1) *
+// MARK). When the interval's rows fit in LDS, their offsets are staged there
+// and the entries are read coalesced, each finding its row by a binary search
+// in LDS; otherwise each thread takes runs of 16 entries and searches their
+// first row between the two marks.
+constexpr int CHK_ROWS = 2048;
 __global__ __launch_bounds__(CB) void k_chk_edges(int n, int64_t nnz, const int64_t *xadj, const int32_t *adj,
                                                   const int32_t *ew, const int32_t *mark, int64_t nmark, CState *st)
 {
     __shared__ int64_t s_red[CB / 64];
-    constexpr int RUN = 16;
+    __shared__ int64_t s_x[CHK_ROWS + 1];
     int64_t ews = 0;
     int bad = 0;
-    const int64_t nruns = (nnz + RUN - 1) / RUN;
-    for (int64_t r = (int64_t)blockIdx.x * CB + threadIdx.x; r < nruns; r += (int64_t)gridDim.x * CB) {
-        const int64_t e0 = r * RUN, e1 = e0 + RUN < nnz ? e0 + RUN : nnz;
-        // xadj[lo] <= e0 < xadj[hi] on well-formed offsets; the guards keep
-        // lo and hi inside [0, n) on malformed ones (k_chk_vertices flags them)
-        const int64_t mi = e0 / MARK;
-        int lo = mark[mi];
-        int hi = mi + 1 < nmark ? mark[mi + 1] + 1 : n;
-        if (hi > n) hi = n;
-        if (lo >= hi) lo = hi - 1;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (xadj[mid] <= e0) lo = mid;
-            else hi = mid;
-        }
-        int u[RUN], w[RUN];
-#pragma unroll
-        for (int j = 0; j < RUN; j++) {
-            const int64_t e = e0 + j;
-            u[j] = e < e1 ? adj[e] : -1;
-            w[j] = e < e1 ? (ew ? ew[e] : 1) : 1;
-        }
-        int v = lo;
-        int64_t vend = xadj[v + 1];
-#pragma unroll
-        for (int j = 0; j < RUN; j++) {
-            const int64_t e = e0 + j;
-            if (e >= e1) break;
-            while (e >= vend && v < n - 1) {
-                v++;
-                vend = xadj[v + 1];
+    for (int64_t blk = blockIdx.x; blk * MARK < nnz; blk += gridDim.x) {
+        const int64_t e_lo = blk * MARK, e_hi = e_lo + MARK < nnz ? e_lo + MARK : nnz;
+        // rows r_lo..r_hi hold the interval on well-formed offsets; both stay
+        // in [0, n) on malformed ones (k_chk_vertices flags those)
+        int r_lo = mark[blk];
+        int r_hi = blk + 1 < nmark ? mark[blk + 1] : n - 1;
+        if (r_hi > n - 1) r_hi = n - 1;
+        if (r_lo > r_hi) r_lo = r_hi;
+        const int nr = r_hi - r_lo + 1;
+        if (nr <= CHK_ROWS) {
+            for (int i = threadIdx.x; i <= nr; i += CB) s_x[i] = xadj[r_lo + i];
+            __syncthreads();
+            for (int64_t e = e_lo + threadIdx.x; e < e_hi; e += CB) {
+                int lo = 0, hi = nr;  // largest lo with s_x[lo] <= e
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_x[mid] <= e) lo = mid;
+                    else hi = mid;
+                }
+                const int v = r_lo + lo;
+                const int u = adj[e];
+                const int w = ew ? ew[e] : 1;
+                if (u < 0 || u >= n || u == v || w < 1) bad = 1;
+                else ews += w;
             }
-            if (u[j] < 0 || u[j] >= n || u[j] == v || w[j] < 1) {
-                bad = 1;
-                continue;
+            __syncthreads();
+            continue;
+        }
+        constexpr int RUN = 16;
+        for (int64_t e0 = e_lo + (int64_t)threadIdx.x * RUN; e0 < e_hi; e0 += (int64_t)CB * RUN) {
+            const int64_t e1 = e0 + RUN < e_hi ? e0 + RUN : e_hi;
+            int lo = r_lo, hi = r_hi + 1;  // largest lo with xadj[lo] <= e0
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (xadj[mid] <= e0) lo = mid;
+                else hi = mid;
             }
-            ews += w[j];
+            int u[RUN], w[RUN];
+#pragma unroll
+            for (int j = 0; j < RUN; j++) {
+                const int64_t e = e0 + j;
+                u[j] = e < e1 ? adj[e] : -1;
+                w[j] = e < e1 ? (ew ? ew[e] : 1) : 1;
+            }
+            int v = lo;
+            int64_t vend = xadj[v + 1];
+#pragma unroll
+            for (int j = 0; j < RUN; j++) {
+                const int64_t e = e0 + j;
+                if (e >= e1) break;
+                while (e >= vend && v < n - 1) {
+                    v++;
+                    vend = xadj[v + 1];
+                }
+                if (u[j] < 0 || u[j] >= n || u[j] == v || w[j] < 1) {
+                    bad = 1;
+                    continue;
+                }
+                ews += w[j];
+            }
         }
     }
     ews = block_sum<CB>(ews, s_red);
@@ -1122,8 +1148,8 @@ int check_graph(jet_context *ctx, const jet_csr *g, uint32_t flags, hipStream_t 
         int64_t nmark = 0;
         const int rs = row_marks(ctx, g->xadj, g->n, g->nnz, &mark, &nmark, s);
         if (rs) return rs;
-        k_chk_edges<<<grid_for(ctx, (g->nnz + 15) / 16, CB), CB, 0, s>>>(g->n, g->nnz, g->xadj, g->adjncy, g->adjwgt,
-                                                                        mark, nmark, st);
+        k_chk_edges<<<grid_for(ctx, (g->nnz + MARK - 1) / MARK, 1), CB, 0, s>>>(g->n, g->nnz, g->xadj, g->adjncy,
+                                                                              g->adjwgt, mark, nmark, st);
     }
     JET_TRY(hipGetLastError());
     CState *h = (CState *)((char *)ctx->pinned + 2304);
