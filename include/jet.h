@@ -15,9 +15,11 @@
  *  - Every pointer inside jet_csr, and `part`, are DEVICE pointers unless a
  *    comment says (host). The caller owns them; the library never frees them.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). All
- *    device work is enqueued on it; calls return after the stream has
- *    finished the call's work (they synchronise it), except jet_refine with
- *    JET_F_ASYNC.
+ *    device work is ordered on it: the coarsening forks the hub rows'
+ *    contraction onto a second stream of the context, which waits on
+ *    `stream` and is joined back to it within the call. Calls return after
+ *    the stream has finished the call's work (they synchronise it), except
+ *    jet_refine with JET_F_ASYNC.
  *  - Status codes are returned as int; no exception crosses the ABI. On an
  *    error detected before any device work, `part` is untouched; after device
  *    work has started, `part` is unspecified.
