@@ -413,62 +413,116 @@ __global__ __launch_bounds__(BLOCK) void k_row_marks(const int64_t *xadj, int n,
 }
 
 // Edge pass: cut of P_0 and total edge weight (counter rows 2 and 3),
-// neighbour-range / self-loop / weight checks. Each thread takes runs of 16
-// consecutive CSR entries (blocks own contiguous ranges of runs): it finds
-// the run's first row between two row marks, loads the 16 entries and
-// gathers their parts at once, then walks the rows.
+// neighbour-range / self-loop / weight checks. Block b takes the entries of
+// row-mark interval b, [b * MARK, (b + 1) * MARK). When the interval's rows
+// fit in LDS, their offsets, parts (and graphs) are staged there and the
+// entries are read coalesced, four per thread in flight, each finding its row
+// by a binary search in LDS. Otherwise each thread takes runs of 16
+// consecutive entries: it finds the run's first row between the interval's
+// rows, loads the 16 entries and gathers their parts at once, then walks the
+// rows.
+constexpr int EDGE_ROWS = 1024;
 __global__ __launch_bounds__(BLOCK) void k_init_edges(KArgs a, int64_t nnz, const int32_t *mark, int64_t nmark)
 {
-    constexpr int RUN = 16;
-    if (a.n < 1) return;  // callers refine no empty graph
-    const int64_t nruns = (nnz + RUN - 1) / RUN;
-    const int64_t per = (nruns + gridDim.x - 1) / gridDim.x;
-    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = r0 + per < nruns ? r0 + per : nruns;
+    __shared__ int64_t s_x[EDGE_ROWS + 1];
+    __shared__ int32_t s_p[EDGE_ROWS];
+    __shared__ int32_t s_g[EDGE_ROWS];
+    const int n = a.n;
+    if (n < 1) return;  // callers refine no empty graph
     GAcc<2, 3> acc;
     int bad = 0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += BLOCK) {
-        const int64_t e0 = r * RUN, e1 = e0 + RUN < nnz ? e0 + RUN : nnz;
-        // invariant xadj[lo] <= e0 < xadj[hi] (mark[i + 1] + 1 <= n holds
-        // such an offset; xadj[n] = nnz > e0)
-        const int64_t mi = e0 / MARK;
-        int lo = mark[mi];
-        int hi = mi + 1 < nmark ? mark[mi + 1] + 1 : a.n;
-        if (hi > a.n) hi = a.n;
-        if (lo >= hi) lo = hi - 1;  // only for malformed offsets; the checks below flag them
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (a.xadj[mid] <= e0) lo = mid;
-            else hi = mid;
-        }
-        int u[RUN], wt[RUN], pu[RUN];
-#pragma unroll
-        for (int j = 0; j < RUN; j++) {
-            const int64_t e = e0 + j;
-            u[j] = e < e1 ? ld_adj(a, e) : -1;
-            wt[j] = e < e1 ? ld_ew(a, e) : 1;
-        }
-#pragma unroll
-        for (int j = 0; j < RUN; j++) pu[j] = (u[j] >= 0 && u[j] < a.n) ? gpart(a, u[j]) : -1;
-        int v = lo;
-        int64_t vend = a.xadj[v + 1];
-        int pv = a.P[v];
-        acc.to(a, graph_of(a, v));
-#pragma unroll
-        for (int j = 0; j < RUN; j++) {
-            const int64_t e = e0 + j;
-            if (e >= e1) break;
-            while (e >= vend && v < a.n - 1) {
-                v++;
-                vend = a.xadj[v + 1];
-                pv = a.P[v];
-                acc.to(a, graph_of(a, v));
+    for (int64_t blk = blockIdx.x; blk * MARK < nnz; blk += gridDim.x) {
+        const int64_t e_lo = blk * MARK, e_hi = e_lo + MARK < nnz ? e_lo + MARK : nnz;
+        // rows r_lo..r_hi hold the interval on well-formed offsets; both stay
+        // in [0, n) on malformed ones (the checks below and the vertex pass
+        // flag those)
+        int r_lo = mark[blk];
+        int r_hi = blk + 1 < nmark ? mark[blk + 1] : n - 1;
+        if (r_hi > n - 1) r_hi = n - 1;
+        if (r_lo > r_hi) r_lo = r_hi;
+        const int nr = r_hi - r_lo + 1;
+        if (nr <= EDGE_ROWS) {
+            for (int i = threadIdx.x; i <= nr; i += BLOCK) {
+                s_x[i] = a.xadj[r_lo + i];
+                if (i < nr) {
+                    s_p[i] = a.P[r_lo + i];
+                    s_g[i] = graph_of(a, r_lo + i);
+                }
             }
-            if (u[j] < 0 || u[j] >= a.n || u[j] == v || wt[j] < 1) {
-                bad = 1;
-                continue;
+            __syncthreads();
+            constexpr int U = 4;
+            for (int64_t e0 = e_lo + threadIdx.x; e0 < e_hi; e0 += (int64_t)BLOCK * U) {
+                int u[U], wt[U], pu[U];
+#pragma unroll
+                for (int j = 0; j < U; j++) {
+                    const int64_t e = e0 + (int64_t)j * BLOCK;
+                    u[j] = e < e_hi ? ld_adj(a, e) : -1;
+                    wt[j] = e < e_hi ? ld_ew(a, e) : 1;
+                }
+#pragma unroll
+                for (int j = 0; j < U; j++) pu[j] = (u[j] >= 0 && u[j] < n) ? gpart(a, u[j]) : -1;
+#pragma unroll
+                for (int j = 0; j < U; j++) {
+                    const int64_t e = e0 + (int64_t)j * BLOCK;
+                    if (e >= e_hi) continue;
+                    int lo = 0, hi = nr;  // largest lo with s_x[lo] <= e
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_x[mid] <= e) lo = mid;
+                        else hi = mid;
+                    }
+                    const int v = r_lo + lo;
+                    if (u[j] < 0 || u[j] >= n || u[j] == v || wt[j] < 1) {
+                        bad = 1;
+                        continue;
+                    }
+                    acc.to(a, s_g[lo]);
+                    acc.c1 += wt[j];
+                    if (u[j] > v && pu[j] != s_p[lo]) acc.c0 += wt[j];
+                }
             }
-            acc.c1 += wt[j];
-            if (u[j] > v && pu[j] != pv) acc.c0 += wt[j];
+            __syncthreads();
+            continue;
+        }
+        constexpr int RUN = 16;
+        for (int64_t e0 = e_lo + (int64_t)threadIdx.x * RUN; e0 < e_hi; e0 += (int64_t)BLOCK * RUN) {
+            const int64_t e1 = e0 + RUN < e_hi ? e0 + RUN : e_hi;
+            int lo = r_lo, hi = r_hi + 1;  // largest lo with xadj[lo] <= e0
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (a.xadj[mid] <= e0) lo = mid;
+                else hi = mid;
+            }
+            int u[RUN], wt[RUN], pu[RUN];
+#pragma unroll
+            for (int j = 0; j < RUN; j++) {
+                const int64_t e = e0 + j;
+                u[j] = e < e1 ? ld_adj(a, e) : -1;
+                wt[j] = e < e1 ? ld_ew(a, e) : 1;
+            }
+#pragma unroll
+            for (int j = 0; j < RUN; j++) pu[j] = (u[j] >= 0 && u[j] < n) ? gpart(a, u[j]) : -1;
+            int v = lo;
+            int64_t vend = a.xadj[v + 1];
+            int pv = a.P[v];
+            acc.to(a, graph_of(a, v));
+#pragma unroll
+            for (int j = 0; j < RUN; j++) {
+                const int64_t e = e0 + j;
+                if (e >= e1) break;
+                while (e >= vend && v < n - 1) {
+                    v++;
+                    vend = a.xadj[v + 1];
+                    pv = a.P[v];
+                    acc.to(a, graph_of(a, v));
+                }
+                if (u[j] < 0 || u[j] >= n || u[j] == v || wt[j] < 1) {
+                    bad = 1;
+                    continue;
+                }
+                acc.c1 += wt[j];
+                if (u[j] > v && pu[j] != pv) acc.c0 += wt[j];
+            }
         }
     }
     if (bad) a.cnt[1] = 1;
@@ -4430,7 +4484,7 @@ static int setup(jet_context *ctx, Launch &L, Plan &pl, hipStream_t s, const Deb
     if (n > 0) k_init_vertices<<<grid_v, BLOCK, a.vg ? 0 : (size_t)a.k * 4, s>>>(a, L.part_in, blkcnt);
     const bool known_cut = L.G == 1 && L.cut0 >= 0;
     if (L.u.nnz > 0 && !known_cut) {
-        const int grid_e = std::max(1, std::min(div_up(div_up(L.u.nnz, 16), BLOCK), ctx->num_cu * 8));
+        const int grid_e = std::max(1, std::min(div_up(L.u.nnz, MARK), ctx->num_cu * 8));
         int32_t *mark = nullptr;
         int64_t nmark = 0;
         const int rs = row_marks(ctx, L.u.xadj, n, L.u.nnz, &mark, &nmark, s);
