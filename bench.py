@@ -62,10 +62,10 @@ HBM_PEAK_GBS = 8000.0
 # the kernel source they were taken on (profiles/gain_pass_rmat22_k256.md,
 # profiles/k_gain_stencil128_k64.md).
 TRAFFIC = {
-    "rmat22": dict(src_sha256="551f83c172e5536b95a861e93e41c755f1fa36284aaffa3fcd2b364e98639d00",
-                   fetch=1876923407, write=68815792, fetch_factor=1.9997, write_factor=1.0),
-    "stencil128": dict(src_sha256="551f83c172e5536b95a861e93e41c755f1fa36284aaffa3fcd2b364e98639d00",
-                       fetch=249044221, write=9872350, fetch_factor=1.9997, write_factor=1.0),
+    "rmat22": dict(src_sha256="25615504a2741f898dd681d4171dc5fb801f475f458a2c1094e1296eff410c05",
+                   fetch=1876883518, write=68820405, fetch_factor=1.9997, write_factor=1.0),
+    "stencil128": dict(src_sha256="25615504a2741f898dd681d4171dc5fb801f475f458a2c1094e1296eff410c05",
+                       fetch=249036138, write=9872254, fetch_factor=1.9997, write_factor=1.0),
 }
 
 
